@@ -1,0 +1,200 @@
+"""Pins of the oracle's QP solution (Sec. 2.1.3, eq. non-negative; Sec. 2.2.2)
+against brute force, library solves of special cases, the KKT definition, a
+manufactured solution's convergence rate and limits of the transient step."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+from oracle import brute
+from paper_1506_08435_amd import workloads as W
+
+
+def _system_from_dense(oracle_mod, K, F):
+    A = sp.csr_matrix(K)
+    A.sort_indices()
+    return oracle_mod.System(n=K.shape[0], rowptr=A.indptr.astype(np.int64),
+                             col=A.indices.astype(np.int32), K=A.data.astype(np.float64), M=None,
+                             F=np.asarray(F, dtype=np.float64), dof=np.arange(K.shape[0]))
+
+
+@pytest.mark.parametrize("maker", [W.tiny2d, W.tiny3d])
+def test_tiny_meshes_match_brute_force(oracle_mod, maker):
+    S = oracle_mod.assemble(maker())
+    assert S.n <= 12
+    K = S.to_scipy().toarray()
+    gal = np.linalg.solve(K, S.F)
+    assert gal.min() < 0.0                    # the constraint matters here
+    c_bf, sets = brute.brute_force(K, S.F)
+    r = oracle_mod.solve(S, tol=1e-13)
+    assert r.certified and r.status == 0
+    np.testing.assert_allclose(r.c, c_bf, rtol=0, atol=1e-13 * np.abs(c_bf).max())
+    assert (r.c >= 0).all()
+    assert len(sets) == 1                    # non-degenerate: one KKT face
+
+
+def test_random_dense_qps_match_brute_force(oracle_mod):
+    rng = np.random.default_rng(1506)
+    for trial in range(40):
+        n = int(rng.integers(1, 11))
+        A = rng.standard_normal((n, n))
+        K = A @ A.T + 0.3 * np.eye(n)
+        F = rng.standard_normal(n)
+        c_bf, _ = brute.brute_force(K, F)
+        S = _system_from_dense(oracle_mod, K, F)
+        r = oracle_mod.solve(S, tol=1e-13)
+        scale = max(np.abs(c_bf).max(), 1e-300)
+        np.testing.assert_allclose(r.c, c_bf, rtol=0, atol=1e-11 * scale, err_msg=f"trial {trial}")
+        assert (r.c >= 0).all()
+
+
+def _isotropic(p):
+    p.D = np.eye(p.dim)[None].copy()
+    return p
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: _isotropic(W.square2d(32)),               # isotropic: 5-point M-matrix
+    lambda: W.square2d(32, theta=0.0, ratio=1e-3),    # axis-aligned anisotropy: D12 = 0
+    lambda: _isotropic(W.cube3d(10)),                 # isotropic Kuhn: 7-point M-matrix
+])
+def test_m_matrix_cases_equal_direct_solve(oracle_mod, maker):
+    """K is a Stieltjes matrix and F >= 0, so K^-1 F >= 0 solves the QP."""
+    S = oracle_mod.assemble(maker())
+    A = S.to_scipy().tocsc()
+    off = (A - sp.diags(A.diagonal())).tocoo()
+    assert off.data.max() <= 0.0
+    ref = spl.spsolve(A, S.F)
+    assert ref.min() > 0.0
+    r = oracle_mod.solve(S, tol=1e-13)
+    np.testing.assert_allclose(r.c, ref, rtol=0, atol=1e-12 * ref.max())
+    assert (r.c > 0).all()                    # active set empty
+
+
+def test_nonnegative_galerkin_is_the_minimiser(oracle_mod):
+    # mild anisotropy + a broad source: the Galerkin solution is already >= 0
+    p = W.square2d(24, theta=math.pi / 6, ratio=0.5)
+    p.f_elem = np.ones(p.n_elems)
+    S = oracle_mod.assemble(p)
+    ref = spl.spsolve(S.to_scipy().tocsc(), S.F)
+    assert ref.min() > 0.0
+    r = oracle_mod.solve(S, tol=1e-13)
+    np.testing.assert_allclose(r.c, ref, rtol=0, atol=1e-12 * ref.max())
+
+
+def test_config_small_certificate(oracle_mod):
+    S = oracle_mod.assemble(W.config_small())
+    r = oracle_mod.solve(S, tol=1e-12)
+    k = oracle_mod.kkt(S, r.c)
+    assert r.certified and k.r <= 1e-12 and k.min_c >= 0.0 and k.nonfinite == 0
+    assert k.nat_inf <= 1e-11 * np.abs(S.F).max()
+    assert k.min_g_active >= -1e-11 * np.abs(S.F).max()
+    assert abs(r.c.max() - 0.0739059) < 1e-6
+    # the Galerkin solution violates non-negativity on ~32% of the nodes
+    gal = spl.spsolve(S.to_scipy().tocsc(), S.F)
+    assert 0.25 < (gal < 0).mean() < 0.40
+    # first-order optimality differs: the QP solution is not the Galerkin one
+    assert np.abs(r.c - gal).max() > 1e-5
+
+
+def test_oracle_deterministic(oracle_mod):
+    S = oracle_mod.assemble(W.square2d(40))
+    oracle_mod.set_num_threads(1)
+    a = oracle_mod.solve(S, tol=1e-12).c
+    oracle_mod.set_num_threads(max(2, oracle_mod.num_threads()))
+    b = oracle_mod.solve(S, tol=1e-12).c
+    assert np.array_equal(a, b)
+
+
+def test_nonpositive_source_gives_zero(oracle_mod):
+    p = W.square2d(16)
+    p.f_elem = -p.f_elem
+    S = oracle_mod.assemble(p)
+    r = oracle_mod.solve(S, c0=np.full(S.n, 0.3))
+    assert r.certified and np.array_equal(r.c, np.zeros(S.n))
+
+
+def test_mms_rate_2d(oracle_mod):
+    errs = []
+    for n in (16, 32, 64):
+        p = W.mms_problem(2, n)
+        S = oracle_mod.assemble(p)
+        r = oracle_mod.solve(S, tol=1e-13)
+        free = W.free_node_ids(p)
+        errs.append(np.abs(r.c - p.exact(p.coords[free])).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(1.8 <= q <= 2.25 for q in rates), rates
+
+
+def test_mms_rate_3d(oracle_mod):
+    errs = []
+    for n in (8, 16, 32):
+        p = W.mms_problem(3, n)
+        S = oracle_mod.assemble(p)
+        r = oracle_mod.solve(S, tol=1e-13)
+        free = W.free_node_ids(p)
+        errs.append(np.abs(r.c - p.exact(p.coords[free])).max())
+    rate = math.log2(errs[-2] / errs[-1])
+    assert 1.8 <= rate <= 2.3, errs
+
+
+def test_transient_huge_dt_is_steady(oracle_mod):
+    p = W.square2d(24)
+    S = oracle_mod.assemble(p, with_mass=True)
+    steady = oracle_mod.solve(S, tol=1e-13).c
+    r = oracle_mod.transient_step(S, 1e12, np.zeros(S.n), tol=1e-13)
+    assert r.certified
+    np.testing.assert_allclose(r.c, steady, rtol=0, atol=1e-9 * steady.max())
+
+
+def test_transient_steps_certified_and_warm_equals_cold(oracle_mod):
+    p = W.cube3d(8)
+    S = oracle_mod.assemble(p, with_mass=True)
+    dt = 1e-3
+    c = np.zeros(S.n)
+    for step in range(3):
+        Kt, ft = oracle_mod.transient_system(S, dt, c)
+        warm = oracle_mod.transient_step(S, dt, c, tol=1e-13)
+        cold = oracle_mod.solve(S, tol=1e-13, F=ft, vals=Kt)
+        assert warm.certified and cold.certified
+        k = oracle_mod.kkt(S, warm.c, F=ft, vals=Kt)
+        assert k.r <= 1e-13 and k.min_c >= 0.0
+        np.testing.assert_allclose(warm.c, cold.c, rtol=0, atol=1e-11 * max(cold.c.max(), 1e-30))
+        c = warm.c
+    assert c.max() > 0
+
+
+def test_transient_system_definition(oracle_mod):
+    """K~ = M/dt + K and f~ = F + M c^n / dt, checked through scipy products."""
+    p = W.square2d(12)
+    S = oracle_mod.assemble(p, with_mass=True)
+    rng = np.random.default_rng(3)
+    cn = rng.random(S.n)
+    Kt, ft = oracle_mod.transient_system(S, 0.01, cn)
+    A = S.to_scipy()
+    Mm = S.to_scipy("M")
+    np.testing.assert_allclose(Kt, Mm.data / 0.01 + A.data, rtol=1e-15)
+    np.testing.assert_allclose(ft, S.F + (Mm @ cn) / 0.01, rtol=1e-13)
+
+
+def test_kkt_report_special_points(oracle_mod):
+    """At c = 0 with F >= 0 the projected gradient is -F, so r = 1 exactly; at
+    the brute-force minimiser every KKT measure vanishes to rounding; a point
+    with a negative entry is reported by min_c."""
+    S = oracle_mod.assemble(W.tiny2d())
+    k0 = oracle_mod.kkt(S, np.zeros(S.n))
+    assert k0.r == 1.0 and k0.min_c == 0.0 and k0.n_zero == S.n
+    # min(c, g) at c = 0 is min(0, -F): its largest magnitude is max(F)
+    assert k0.nat_inf == S.F.max()
+    c_bf, _ = brute.brute_force(S.to_scipy().toarray(), S.F)
+    k1 = oracle_mod.kkt(S, c_bf)
+    assert k1.r <= 1e-13 and k1.comp_inf <= 1e-15 and k1.min_c >= 0.0
+    bad = c_bf.copy()
+    bad[np.argmax(bad)] *= -1.0
+    k2 = oracle_mod.kkt(S, bad)
+    assert k2.min_c < 0.0 and k2.r > 1e-3
+    nanc = c_bf.copy()
+    nanc[0] = np.nan
+    assert oracle_mod.kkt(S, nanc).nonfinite >= 1
