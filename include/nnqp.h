@@ -1,0 +1,217 @@
+/*
+ * nnqp.h - C ABI of the MI355X (gfx950) non-negative diffusion QP library.
+ *
+ * The library assembles the P1 Galerkin stiffness matrix K of anisotropic
+ * diffusion on a simplicial mesh and solves the bound-constrained quadratic
+ * program
+ *
+ *     minimise 1/2 <c; K c> - <c; f>   subject to   0 <= c          (*)
+ *
+ * of Chang, Karra & Nakshatrala, arXiv:1506.08435, Sec. 2.1.3
+ * (eq. non-negative), with an active-set projected-Newton / trust-region
+ * method in the style of TRON (Lin & More, SIAM J. Optim. 9(4), 1999), the
+ * solver the paper uses through TAO (Sec. 3.1).  Every step of the solve runs
+ * in hand-written HIP kernels; the host only sequences launches and reads
+ * back a few scalars.
+ *
+ * Conventions (apply to every entry point):
+ *  - Every function returns nn_status; NN_OK (0) on success.  No C++
+ *    exception crosses this boundary.  On error, nn_last_error(ctx) returns a
+ *    message describing the last failure on that context.
+ *  - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *    pointers are HIP device memory on the context's device, owned by the
+ *    caller unless stated otherwise.  Nothing keeps a caller pointer after
+ *    the call returns.
+ *  - Vectors over the free degrees of freedom (DOFs) are dense float64
+ *    arrays of length n (nn_matrix_info), in DOF order: the non-Dirichlet
+ *    nodes in increasing node id.
+ *  - All device work is enqueued on the context's stream.  Entry points that
+ *    fill an nn_stats or return sizes synchronise that stream before
+ *    returning; nn_matvec does not (it is stream-ordered).
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef NNQP_H
+#define NNQP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NN_OK = 0,
+    NN_EINVAL = 1,      /* bad argument: null pointer, size, dimension, option value */
+    NN_ENONFINITE = 2,  /* NaN/Inf met in the input or during the iteration */
+    NN_ENOTSPD = 3,     /* non-positive diagonal or curvature: K is not SPD on the free set */
+    NN_EMAXIT = 4,      /* iteration cap reached; c holds the last feasible iterate */
+    NN_EOOM = 5,        /* device or host allocation failed */
+    NN_EHIP = 6,        /* a HIP runtime call failed */
+    NN_EBUDGET = 7      /* request exceeds the byte budget given by the caller */
+} nn_status;
+
+typedef enum {
+    NN_FP64 = 0,        /* all values, vectors and reductions in float64 */
+    NN_MIXED = 1        /* float32 K values and CG vectors, float64 reductions,
+                           float64 outer iterative-refinement residual f - K c */
+} nn_precision;
+
+typedef struct nn_ctx nn_ctx;        /* opaque; one device + one stream */
+typedef struct nn_matrix nn_matrix;  /* opaque; device CSR owned by the library */
+
+/* Simplicial mesh (host arrays, row-major).  P1 elements: triangles for
+ * dim = 2, tetrahedra for dim = 3 (Sec. 2.1.3, P^k spaces with k = 1). */
+typedef struct {
+    int32_t dim;             /* 2 or 3 */
+    int64_t n_nodes;
+    int64_t n_elems;
+    const double *coords;    /* host [n_nodes * dim] */
+    const int32_t *elems;    /* host [n_elems * (dim + 1)], node ids in [0, n_nodes) */
+} nn_mesh;
+
+/* Solver options; fill with nn_default_opts() and override. */
+typedef struct {
+    double tol;           /* stop when ||pg(c)||_2 <= tol * ||f||_2, pg the projected
+                             gradient (g_i if c_i > 0, else min(g_i, 0)), g = K c - f.
+                             Default 1e-8.  Must be > 0. */
+    double inner_rtol;    /* relative residual tolerance of each inner CG solve
+                             (the paper's TRON1/2/3 use 1e-1/1e-2/1e-3). Default 1e-1. */
+    int32_t max_outer;    /* outer (Newton) iteration cap; default 500 */
+    int32_t max_cg;       /* CG iterations per inner solve; default 5000 */
+    int32_t precision;    /* nn_precision; default NN_FP64 */
+    int32_t c0_mode;      /* 0: start from c = c0_value everywhere (Algorithm 1 of the
+                             paper starts from 1e-8); 1: start from the caller's c,
+                             projected onto c >= 0 (warm start).  Default 0. */
+    double c0_value;      /* default 1e-8 */
+    double delta0;        /* initial trust-region radius; <= 0 means unbounded
+                             (default).  The model is the objective itself, so the
+                             radius only ever grows. */
+    int32_t cg_chunk;     /* CG iterations enqueued between convergence reads; default 16 */
+    int32_t reserved;
+} nn_opts;
+
+/* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */
+typedef struct {
+    double kkt_rel;       /* ||pg||_2 / ||f||_2 at the returned c (f the solve's rhs) */
+    double kkt_nat_inf;   /* ||min(c, g)||_inf */
+    double min_c;         /* min_i c_i (>= 0 on every path) */
+    double norm_f;        /* ||f||_2 */
+    int32_t outer_its;
+    int32_t cg_its;
+    int32_t spmvs;        /* sparse matrix-vector products of every kind */
+    int32_t n_active;     /* #{i : c_i == 0} */
+    int32_t cauchy_trials;
+    int32_t search_trials;
+    int32_t refinements;  /* outer FP64 refinement steps (NN_MIXED) */
+    int32_t reserved;
+    double bytes_moved;   /* algorithmic HBM bytes of the solve (perfect-cache model) */
+    double seconds;       /* device time of the solve (HIP events on the stream) */
+} nn_stats;
+
+/* Create a context on HIP device `device` using `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  The stream must outlive the context. */
+nn_status nn_create(nn_ctx **ctx, int device, void *hip_stream);
+void nn_destroy(nn_ctx *ctx);
+/* Message for the last non-OK status on ctx (never NULL; "" if none). */
+const char *nn_last_error(const nn_ctx *ctx);
+nn_status nn_default_opts(nn_opts *opts);
+
+/*
+ * Assemble the stiffness matrix K (and the capacity matrix M if with_mass)
+ * over the free DOFs, and the load vector F.
+ *
+ *   K_ij = sum_e |e| grad(phi_i) . D_e grad(phi_j)   (bilinear form B, Sec. 2.1.2,
+ *                                                     eq. functionals_B_L; F_{1,1} = D
+ *                                                     in the point-wise Jacobian, Sec. 3.2)
+ *   M_ij = sum_e |e| (1 + delta_ij) / ((d+1)(d+2))    (consistent capacity matrix,
+ *                                                     Sec. 2.2.2; F_{0,0} = 1/dt, Sec. 3.2)
+ *   F_i  = sum_e |e| f_e / (d+1)                      (functional L with element-constant f)
+ *
+ * Homogeneous Dirichlet nodes (dirichlet[v] != 0) are eliminated: their rows
+ * and columns are dropped (c = 0 there).
+ *   D        host [nD * dim * dim]; nD = 1 (one tensor) or n_elems (one per element);
+ *            each tensor symmetric positive definite (Sec. 2.1, eq. symmetry and
+ *            positive definiteness of D).
+ *   kscale   host [n_elems] or NULL: element e uses kscale[e] * D_e.
+ *   f_elem   host [n_elems]: source value on each element.
+ *   dirichlet host [n_nodes]: 1 = Dirichlet node.
+ *   K_out    receives a library-owned matrix (free with nn_matrix_free).
+ *   F_dev    device [n] or NULL: receives F.  n = number of free nodes, known
+ *            beforehand by the caller (count of dirichlet == 0).
+ *   dof_of_node host [n_nodes] or NULL: receives the DOF index of each node, -1
+ *            for Dirichlet nodes.
+ * Errors: NN_EINVAL (sizes, ids out of range, degenerate element, nnz >= 2^31),
+ *         NN_ENONFINITE (NaN/Inf in coords, D, kscale or f), NN_ENOTSPD (a
+ *         non-positive diagonal entry of K), NN_EOOM, NN_EHIP.
+ */
+nn_status nn_assemble(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64_t nD,
+                      const double *kscale, const double *f_elem, const uint8_t *dirichlet,
+                      int with_mass, nn_matrix **K_out, double *F_dev, int64_t *dof_of_node);
+
+/* Wrap a caller CSR matrix (host arrays, copied to the device): rowptr [n+1]
+ * (int64, rowptr[0] = 0), col [nnz] (int32, ascending within each row,
+ * diagonal present), val [nnz], mval [nnz] or NULL (capacity values).  The
+ * matrix must be symmetric positive definite for the solver. */
+nn_status nn_matrix_from_csr(nn_ctx *ctx, int64_t n, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const double *mval, nn_matrix **out);
+
+nn_status nn_matrix_info(const nn_matrix *A, int64_t *n, int64_t *nnz, int *has_mass);
+/* Copy the CSR back to host arrays (rowptr [n+1], col/val/mval [nnz]; any may be NULL). */
+nn_status nn_matrix_export(nn_ctx *ctx, const nn_matrix *A, int64_t *rowptr, int32_t *col,
+                           double *val, double *mval);
+/* Device bytes the matrix and one solve's work vectors occupy for a precision
+ * (used to admit requests against an HBM budget). */
+nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes);
+void nn_matrix_free(nn_ctx *ctx, nn_matrix *A);
+
+/* y = A x on the stream (device vectors of length n); which = 0: K, 1: M. */
+nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_dev,
+                    double *y_dev);
+
+/*
+ * Solve (*) for c (Sec. 2.1.3, eq. non-negative).  The minimiser is unique
+ * because K is positive definite; it is the c with c >= 0, g = K c - f >= 0
+ * and c_i g_i = 0.
+ *   f_dev     device [n]
+ *   c_dev     device [n]; in: warm start when opts->c0_mode == 1; out: solution
+ *             with c_i >= 0 exactly (projection writes +0.0).
+ *   active_dev device [n] uint8 or NULL; out: 1 where c_i == 0.
+ *   stats     host or NULL.
+ * Returns NN_EMAXIT (c feasible, stats filled) if max_outer is reached before
+ * ||pg|| <= tol ||f||; NN_ENONFINITE if a non-finite value appears.
+ */
+nn_status nn_solve_nonneg(nn_ctx *ctx, const nn_matrix *K, const double *f_dev,
+                          const nn_opts *opts, double *c_dev, uint8_t *active_dev,
+                          nn_stats *stats);
+
+/*
+ * One backward-Euler step of the transient problem (Sec. 2.2.2,
+ * eq. Eq:non-negative with lower bound 0):
+ *     K~ = M/dt + K,  f~ = f + M c^(n) / dt,  c^(n+1) = argmin_{c >= 0} 1/2 c.K~c - c.f~.
+ * K must carry capacity values (with_mass).  K~ is formed on the device on
+ * the first call for a given dt and kept with the matrix.
+ *   c_dev  device [n]; in: c^(n) (>= 0), also the warm start; out: c^(n+1).
+ */
+nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *f_dev,
+                            const nn_opts *opts, double *c_dev, uint8_t *active_dev,
+                            nn_stats *stats);
+
+/* Device time per launch of the library's kernel classes, accumulated while
+ * profiling is on (nn_set_profiling).  For class k: counts[k] launches and
+ * total_ms[k] milliseconds measured with HIP events on the context stream.
+ * Classes: 0 CG SpMV (fused direction update), 1 CG vector update,
+ * 2 gradient SpMV, 3 projected-step SpMV, 4 other. */
+#define NN_KCLASSES 5
+nn_status nn_set_profiling(nn_ctx *ctx, int on);
+/* counts/total_ms/total_bytes: host arrays of NN_KCLASSES entries or NULL.
+ * total_bytes is the algorithmic (perfect-cache) byte count of the timed
+ * launches.  Launches that found their work already finished (CG iterations
+ * enqueued past convergence) are not counted.  reset != 0 clears the totals. */
+nn_status nn_kernel_times(nn_ctx *ctx, int64_t *counts, double *total_ms, double *total_bytes,
+                          int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNQP_H */

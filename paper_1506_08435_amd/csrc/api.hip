@@ -1,0 +1,414 @@
+// C ABI entry points (include/nnqp.h): argument checks, object lifetime,
+// workspace, profiling, and dispatch to the assembly and solver code.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "nnqp_internal.hpp"
+
+namespace nnqp {
+
+nn_status fail(nn_ctx *ctx, nn_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+nn_status ensure_workspace(nn_ctx *ctx, int64_t n)
+{
+    Workspace &W = ctx->ws;
+    if (W.cap >= n && W.g) return NN_OK;
+    double **vecs[] = {&W.g, &W.w, &W.r, &W.z, &W.q, &W.p0, &W.p1, &W.ks0, &W.ks1, &W.dm, &W.ft};
+    for (double **v : vecs)
+        if (*v) {
+            (void)hipFree(*v);
+            *v = nullptr;
+        }
+    if (W.mask) (void)hipFree(W.mask);
+    W.mask = nullptr;
+    W.cap = 0;
+    const int64_t cap = std::max<int64_t>(n, 1);
+    for (double **v : vecs) {
+        hipError_t e = hipMalloc(v, sizeof(double) * cap);
+        if (e != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
+    }
+    if (hipMalloc(&W.mask, cap) != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
+    W.cap = cap;
+    return NN_OK;
+}
+
+nn_status read_scalars(nn_ctx *ctx)
+{
+    NN_HIP_TRY(ctx, hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    NN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return NN_OK;
+}
+
+static hipEvent_t pool_event(nn_ctx *ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void prof_begin(nn_ctx *ctx, int cls, double bytes)
+{
+    if (!ctx->prof) return;
+    ProfEntry p;
+    p.cls = cls;
+    p.a = pool_event(ctx);
+    p.b = pool_event(ctx);
+    p.bytes = bytes;
+    p.valid = 1;
+    (void)hipEventRecord(p.a, ctx->stream);
+    ctx->prof_live.push_back(p);
+}
+
+void prof_end(nn_ctx *ctx)
+{
+    if (!ctx->prof || ctx->prof_live.empty()) return;
+    (void)hipEventRecord(ctx->prof_live.back().b, ctx->stream);
+}
+
+void prof_collect(nn_ctx *ctx)
+{
+    if (ctx->prof_live.empty()) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (ProfEntry &p : ctx->prof_live) {
+        if (p.valid) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                ctx->prof_count[p.cls]++;
+                ctx->prof_ms[p.cls] += ms;
+                ctx->prof_bytes[p.cls] += p.bytes > 0 ? p.bytes : 0.0;
+            }
+        }
+        ctx->ev_pool.push_back(p.a);
+        ctx->ev_pool.push_back(p.b);
+    }
+    ctx->prof_live.clear();
+}
+
+}  // namespace nnqp
+
+using namespace nnqp;
+
+#define NN_CHECK_CTX(ctx)                               \
+    do {                                                \
+        if (!(ctx)) return NN_EINVAL;                   \
+        if (hipSetDevice((ctx)->device) != hipSuccess)  \
+            return fail((ctx), NN_EHIP, "hipSetDevice"); \
+    } while (0)
+
+extern "C" {
+
+nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return NN_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NN_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return NN_EHIP;
+    nn_ctx *ctx = new (std::nothrow) nn_ctx();
+    if (!ctx) return NN_EOOM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    bool ok = hipMalloc(&ctx->partials, sizeof(double) * kMaxBlocks * kMaxRed) == hipSuccess &&
+              hipMalloc(&ctx->ticket, sizeof(unsigned) * 4) == hipSuccess &&
+              hipMalloc(&ctx->scal, sizeof(DevScalars)) == hipSuccess &&
+              hipHostMalloc(&ctx->h_scal, sizeof(DevScalars), hipHostMallocDefault) == hipSuccess &&
+              hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
+    if (ok) {
+        ok = hipMemsetAsync(ctx->ticket, 0, sizeof(unsigned) * 4, ctx->stream) == hipSuccess &&
+             hipMemsetAsync(ctx->scal, 0, sizeof(DevScalars), ctx->stream) == hipSuccess &&
+             hipStreamSynchronize(ctx->stream) == hipSuccess;
+    }
+    if (!ok) {
+        nn_destroy(ctx);
+        return NN_EOOM;
+    }
+    *out = ctx;
+    return NN_OK;
+}
+
+void nn_destroy(nn_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    Workspace &W = ctx->ws;
+    double *vecs[] = {W.g, W.w, W.r, W.z, W.q, W.p0, W.p1, W.ks0, W.ks1, W.dm, W.ft};
+    for (double *v : vecs)
+        if (v) (void)hipFree(v);
+    if (W.mask) (void)hipFree(W.mask);
+    if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->ticket) (void)hipFree(ctx->ticket);
+    if (ctx->scal) (void)hipFree(ctx->scal);
+    if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (ProfEntry &p : ctx->prof_live) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *nn_last_error(const nn_ctx *ctx)
+{
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+nn_status nn_default_opts(nn_opts *o)
+{
+    if (!o) return NN_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->inner_rtol = 1e-1;
+    o->max_outer = 500;
+    o->max_cg = 5000;
+    o->precision = NN_FP64;
+    o->c0_mode = 0;
+    o->c0_value = 1e-8;
+    o->delta0 = 0.0;
+    o->cg_chunk = 16;
+    return NN_OK;
+}
+
+nn_status nn_assemble(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64_t nD,
+                      const double *kscale, const double *f_elem, const uint8_t *dirichlet,
+                      int with_mass, nn_matrix **K_out, double *F_dev, int64_t *dof_of_node)
+{
+    NN_CHECK_CTX(ctx);
+    if (K_out) *K_out = nullptr;
+    return assemble_impl(ctx, mesh, D, nD, kscale, f_elem, dirichlet, with_mass, K_out, F_dev,
+                         dof_of_node);
+}
+
+nn_status nn_matrix_from_csr(nn_ctx *ctx, int64_t n, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const double *mval, nn_matrix **out)
+{
+    NN_CHECK_CTX(ctx);
+    if (!out || n < 0 || !rowptr || (n > 0 && (!col || !val)))
+        return fail(ctx, NN_EINVAL, "null argument to nn_matrix_from_csr");
+    *out = nullptr;
+    if (n >= ((int64_t)1 << 31)) return fail(ctx, NN_EINVAL, "n too large");
+    if (rowptr[0] != 0) return fail(ctx, NN_EINVAL, "rowptr[0] must be 0");
+    const int64_t nnz = rowptr[n];
+    if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return fail(ctx, NN_EINVAL, "nnz out of range");
+    std::vector<int> rp32(n + 1);
+    for (int64_t i = 0; i < n; i++) {
+        if (rowptr[i + 1] < rowptr[i]) return fail(ctx, NN_EINVAL, "rowptr not monotone");
+        bool has_diag = false;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; k++) {
+            if (col[k] < 0 || col[k] >= n) return fail(ctx, NN_EINVAL, "column index out of range");
+            if (k > rowptr[i] && col[k] <= col[k - 1])
+                return fail(ctx, NN_EINVAL, "columns must be strictly ascending within a row");
+            if (!std::isfinite(val[k]) || (mval && !std::isfinite(mval[k])))
+                return fail(ctx, NN_ENONFINITE, "non-finite matrix value");
+            if (col[k] == i) has_diag = true;
+        }
+        if (!has_diag) return fail(ctx, NN_EINVAL, "missing diagonal entry");
+        rp32[i] = (int)rowptr[i];
+    }
+    rp32[n] = (int)nnz;
+    nn_matrix *M = new (std::nothrow) nn_matrix();
+    if (!M) return fail(ctx, NN_EOOM, "host allocation");
+    M->n = n;
+    M->nnz = nnz;
+    const size_t nz = (size_t)std::max<int64_t>(nnz, 1);
+    bool ok = hipMalloc(&M->rowptr, sizeof(int) * (n + 1)) == hipSuccess &&
+              hipMalloc(&M->col, sizeof(int) * nz) == hipSuccess &&
+              hipMalloc(&M->val, sizeof(double) * nz) == hipSuccess &&
+              (!mval || hipMalloc(&M->mval, sizeof(double) * nz) == hipSuccess);
+    if (!ok) {
+        nn_matrix_free(ctx, M);
+        return fail(ctx, NN_EOOM, "matrix allocation failed");
+    }
+    hipStream_t s = ctx->stream;
+    ok = hipMemcpyAsync(M->rowptr, rp32.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (ok && nnz > 0) {
+        ok = hipMemcpyAsync(M->col, col, sizeof(int) * nnz, hipMemcpyHostToDevice, s) == hipSuccess &&
+             hipMemcpyAsync(M->val, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s) == hipSuccess &&
+             (!mval || hipMemcpyAsync(M->mval, mval, sizeof(double) * nnz, hipMemcpyHostToDevice, s) == hipSuccess);
+    }
+    if (!ok || hipStreamSynchronize(s) != hipSuccess) {
+        nn_matrix_free(ctx, M);
+        return fail(ctx, NN_EHIP, "matrix upload failed");
+    }
+    int mr = 0;
+    for (int64_t i = 0; i < n; i++) mr = std::max<int>(mr, (int)(rowptr[i + 1] - rowptr[i]));
+    M->max_row = mr;
+    nn_status st = finish_matrix(ctx, M);
+    if (st != NN_OK) {
+        nn_matrix_free(ctx, M);
+        return st;
+    }
+    *out = M;
+    return NN_OK;
+}
+
+nn_status nn_matrix_info(const nn_matrix *A, int64_t *n, int64_t *nnz, int *has_mass)
+{
+    if (!A) return NN_EINVAL;
+    if (n) *n = A->n;
+    if (nnz) *nnz = A->nnz;
+    if (has_mass) *has_mass = A->mval != nullptr;
+    return NN_OK;
+}
+
+nn_status nn_matrix_export(nn_ctx *ctx, const nn_matrix *A, int64_t *rowptr, int32_t *col,
+                           double *val, double *mval)
+{
+    NN_CHECK_CTX(ctx);
+    if (!A) return fail(ctx, NN_EINVAL, "null matrix");
+    hipStream_t s = ctx->stream;
+    if (rowptr) {
+        std::vector<int> rp(A->n + 1);
+        NN_HIP_TRY(ctx, hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int) * (A->n + 1),
+                                       hipMemcpyDeviceToHost, s));
+        NN_HIP_TRY(ctx, hipStreamSynchronize(s));
+        for (int64_t i = 0; i <= A->n; i++) rowptr[i] = rp[i];
+    }
+    if (A->nnz > 0) {
+        if (col) NN_HIP_TRY(ctx, hipMemcpyAsync(col, A->col, sizeof(int) * A->nnz, hipMemcpyDeviceToHost, s));
+        if (val) NN_HIP_TRY(ctx, hipMemcpyAsync(val, A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, s));
+        if (mval) {
+            if (!A->mval) return fail(ctx, NN_EINVAL, "matrix has no capacity values");
+            NN_HIP_TRY(ctx, hipMemcpyAsync(mval, A->mval, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, s));
+        }
+    }
+    NN_HIP_TRY(ctx, hipStreamSynchronize(s));
+    return NN_OK;
+}
+
+nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes)
+{
+    if (!A || !bytes) return NN_EINVAL;
+    const double n = (double)A->n, nnz = (double)A->nnz;
+    double b = 4.0 * (n + 1) + 12.0 * nnz + 8.0 * n;       // rowptr, col, values, diag
+    if (A->mval) b += 16.0 * nnz + 8.0 * n;                 // capacity + transient values, diag
+    b += 11.0 * 8.0 * n + n;                                // solver work vectors + mask
+    if (precision == NN_MIXED) b += 4.0 * nnz + 40.0 * n;   // float32 values and vectors
+    *bytes = (size_t)b;
+    return NN_OK;
+}
+
+void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
+{
+    if (!A) return;
+    if (ctx) (void)hipSetDevice(ctx->device);
+    int *iv[] = {A->rowptr, A->col};
+    for (int *p : iv)
+        if (p) (void)hipFree(p);
+    double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
+    for (double *p : dv)
+        if (p) (void)hipFree(p);
+    delete A;
+}
+
+nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_dev, double *y_dev)
+{
+    NN_CHECK_CTX(ctx);
+    if (!A || (A->n > 0 && (!x_dev || !y_dev)) || (which != 0 && which != 1))
+        return fail(ctx, NN_EINVAL, "bad argument to nn_matvec");
+    if (which == 1 && !A->mval) return fail(ctx, NN_EINVAL, "matrix has no capacity values");
+    launch_matvec(ctx, A, which == 0 ? A->val : A->mval, x_dev, y_dev);
+    NN_HIP_TRY(ctx, hipGetLastError());
+    return NN_OK;
+}
+
+static nn_status check_opts(nn_ctx *ctx, const nn_opts *o)
+{
+    if (!o) return fail(ctx, NN_EINVAL, "null options");
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(ctx, NN_EINVAL, "tol must be > 0");
+    if (!(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
+        return fail(ctx, NN_EINVAL, "inner_rtol must be in (0, 1)");
+    if (o->max_outer < 0 || o->max_cg < 1) return fail(ctx, NN_EINVAL, "bad iteration caps");
+    if (o->precision != NN_FP64 && o->precision != NN_MIXED)
+        return fail(ctx, NN_EINVAL, "unknown precision");
+    if (o->c0_mode != 0 && o->c0_mode != 1) return fail(ctx, NN_EINVAL, "unknown c0_mode");
+    if (o->c0_mode == 0 && !(o->c0_value >= 0.0 && std::isfinite(o->c0_value)))
+        return fail(ctx, NN_EINVAL, "c0_value must be finite and >= 0");
+    return NN_OK;
+}
+
+nn_status nn_solve_nonneg(nn_ctx *ctx, const nn_matrix *K, const double *f_dev,
+                          const nn_opts *opts, double *c_dev, uint8_t *active_dev, nn_stats *stats)
+{
+    NN_CHECK_CTX(ctx);
+    if (!K || (K->n > 0 && (!f_dev || !c_dev))) return fail(ctx, NN_EINVAL, "null argument");
+    nn_status st = check_opts(ctx, opts);
+    if (st != NN_OK) return st;
+    if (opts->precision != NN_FP64) return fail(ctx, NN_EINVAL, "precision not available");
+    return solve_impl(ctx, K, K->val, K->diag, f_dev, opts, c_dev, active_dev, stats);
+}
+
+nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *f_dev,
+                            const nn_opts *opts, double *c_dev, uint8_t *active_dev,
+                            nn_stats *stats)
+{
+    NN_CHECK_CTX(ctx);
+    if (!K || (K->n > 0 && (!f_dev || !c_dev))) return fail(ctx, NN_EINVAL, "null argument");
+    if (!K->mval) return fail(ctx, NN_EINVAL, "matrix has no capacity values (assemble with_mass)");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NN_EINVAL, "dt must be > 0");
+    nn_status st = check_opts(ctx, opts);
+    if (st != NN_OK) return st;
+    if (opts->precision != NN_FP64) return fail(ctx, NN_EINVAL, "precision not available");
+    const int64_t n = K->n;
+    if (n == 0) return solve_impl(ctx, K, K->val, K->diag, f_dev, opts, c_dev, active_dev, stats);
+    if (!K->kt || K->kt_dt != dt) {
+        if (!K->kt) {
+            if (hipMalloc(&K->kt, sizeof(double) * std::max<int64_t>(K->nnz, 1)) != hipSuccess ||
+                hipMalloc(&K->kt_diag, sizeof(double) * n) != hipSuccess)
+                return fail(ctx, NN_EOOM, "transient matrix allocation");
+        }
+        launch_axpby_vals(ctx, K->nnz, K->mval, dt, K->val, K->kt);
+        launch_diag(ctx, K, K->kt, K->kt_diag);
+        NN_HIP_TRY(ctx, hipGetLastError());
+        K->kt_dt = dt;
+    }
+    if ((st = ensure_workspace(ctx, n)) != NN_OK) return st;
+    launch_transient_rhs(ctx, K, c_dev, f_dev, dt, ctx->ws.ft);
+    nn_opts o = *opts;
+    o.c0_mode = 1;   // warm start from c^(n)
+    return solve_impl(ctx, K, K->kt, K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev, stats);
+}
+
+nn_status nn_set_profiling(nn_ctx *ctx, int on)
+{
+    NN_CHECK_CTX(ctx);
+    ctx->prof = on != 0;
+    return NN_OK;
+}
+
+nn_status nn_kernel_times(nn_ctx *ctx, int64_t *counts, double *total_ms, double *total_bytes,
+                          int reset)
+{
+    NN_CHECK_CTX(ctx);
+    prof_collect(ctx);
+    for (int k = 0; k < NN_KCLASSES; k++) {
+        if (counts) counts[k] = ctx->prof_count[k];
+        if (total_ms) total_ms[k] = ctx->prof_ms[k];
+        if (total_bytes) total_bytes[k] = ctx->prof_bytes[k];
+        if (reset) {
+            ctx->prof_count[k] = 0;
+            ctx->prof_ms[k] = 0.0;
+            ctx->prof_bytes[k] = 0.0;
+        }
+    }
+    return NN_OK;
+}
+
+}  // extern "C"

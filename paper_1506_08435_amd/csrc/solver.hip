@@ -1,0 +1,258 @@
+// Active-set projected-Newton / trust-region solver for
+//     min 1/2 c.Kc - c.f  subject to  c >= 0
+// (arXiv:1506.08435 Sec. 2.1.3, eq. non-negative), in the manner of TRON
+// (Lin & More 1999), which the paper uses through TAO (Sec. 3.1, Sec. 5.1).
+//
+// Outer iteration k (all vector work in kernels.hip; the host only sequences
+// launches and reads a few scalars):
+//   1. g = K c - f and the projected-gradient norm; stop at ||pg|| <= tol ||f||.
+//   2. Cauchy point: projected search c(t) = P(c - t g) with the sufficient
+//      decrease test q(c(t)) - q(c) <= mu0 g.(c(t) - c); t starts from the
+//      previous iteration's value and is extrapolated (x10) while the test
+//      holds, or interpolated (x0.1) until it holds.  Each trial is one
+//      project-on-gather SpMV that returns g.s and s.Ks.
+//   3. Free face at the Cauchy point: every variable except those with c = 0
+//      and g >= 0 (a zero gradient counts as binding).  Jacobi-PCG on
+//      K_FF w = -g_F from w = 0 until ||r|| <= inner_rtol ||g_F|| (TRON's
+//      inner tolerance, Sec. 5.1 TRON1/2/3), all scalars kept on the device.
+//   4. Projected search along w from the Cauchy point: if no free variable
+//      crosses zero for a unit step the step is taken without a matrix pass
+//      (CG from zero guarantees sufficient decrease along its own iterate);
+//      otherwise P(c + t w) is tried for t = 1, 1/2, ... down to the first
+//      breakpoint, where the step is again safe.
+//   5. Trust region: the quadratic model is the objective, so the ratio of
+//      actual to predicted reduction is one; the radius (unbounded unless the
+//      caller gives one) grows by 4x whenever a step reaches it.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "nnqp_internal.hpp"
+
+namespace nnqp {
+
+namespace {
+constexpr double kMu0 = 0.01;       // sufficient-decrease constant
+constexpr double kExtrap = 10.0;    // Cauchy extrapolation factor
+constexpr double kInterp = 0.1;     // Cauchy interpolation factor
+constexpr double kBack = 0.5;       // projected-search backtracking factor
+constexpr int kMaxTrials = 60;
+
+struct Bytes {
+    double n, nnz;
+    double spmv() const { return 4.0 * (n + 1) + 12.0 * nnz + 16.0 * n; }
+};
+}  // namespace
+
+nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag,
+                     const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st)
+{
+    const int64_t n = A->n;
+    nn_stats S;
+    std::memset(&S, 0, sizeof(S));
+    NN_HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    auto finish = [&](nn_status rc) -> nn_status {
+        if (active && n > 0) launch_active(ctx, n, c, active);
+        (void)hipEventRecord(ctx->ev1, ctx->stream);
+        hipError_t e = hipEventSynchronize(ctx->ev1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        S.seconds = ms * 1e-3;
+        prof_collect(ctx);
+        if (st) *st = S;
+        if (e != hipSuccess) return fail(ctx, NN_EHIP, hipGetErrorString(e));
+        return rc;
+    };
+    if (n == 0) return finish(NN_OK);
+    nn_status rc = ensure_workspace(ctx, n);
+    if (rc != NN_OK) return rc;
+    Workspace &W = ctx->ws;
+    DevScalars &H = *ctx->h_scal;
+    const Bytes B{(double)n, (double)A->nnz};
+    const double tol = o->tol;
+
+    // ---- start point and load statistics
+    prof_begin(ctx, KC_OTHER, 16.0 * n);
+    launch_init(ctx, n, c, f, o->c0_mode == 1 ? 1 : 0, o->c0_value);
+    prof_end(ctx);
+    if ((rc = read_scalars(ctx)) != NN_OK) return rc;
+    S.bytes_moved += 16.0 * n;
+    const double normf = std::sqrt(H.red[0]), fmax = H.red[1];
+    S.norm_f = normf;
+    if (H.red[2] != 0.0 || H.red[3] != 0.0)
+        return finish(fail(ctx, NN_ENONFINITE, "non-finite value in f or the initial c"));
+    if (!(fmax > 0.0)) {
+        // f <= 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0.
+        NN_HIP_TRY(ctx, hipMemsetAsync(c, 0, sizeof(double) * n, ctx->stream));
+        S.n_active = (int32_t)n;
+        S.kkt_rel = 0.0;
+        return finish(NN_OK);
+    }
+
+    double t_cauchy = 1.0;
+    double delta = o->delta0 > 0.0 ? o->delta0 : INFINITY;
+    const int chunk = o->cg_chunk > 0 ? o->cg_chunk : 16;
+    nn_status result = NN_EMAXIT;
+
+    for (int outer = 0;; outer++) {
+        // ---- 1. gradient and convergence test
+        prof_begin(ctx, KC_GRAD, B.spmv() + 16.0 * n);
+        launch_grad(ctx, A, vals, c, f, W.g);
+        prof_end(ctx);
+        S.spmvs++;
+        S.bytes_moved += B.spmv() + 16.0 * n;
+        if ((rc = read_scalars(ctx)) != NN_OK) return rc;
+        if (H.red[1] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite gradient"));
+        S.kkt_rel = std::sqrt(H.red[0]) / normf;
+        S.kkt_nat_inf = H.red[2];
+        S.min_c = H.red[3];
+        S.n_active = (int32_t)H.red[4];
+        S.outer_its = outer;
+        if (S.kkt_rel <= tol) {
+            result = NN_OK;
+            break;
+        }
+        if (outer >= o->max_outer) {
+            fail(ctx, NN_EMAXIT, "outer iteration cap reached");
+            break;
+        }
+
+        // ---- 2. Cauchy point along the projected steepest-descent path
+        double *ksbuf[2] = {W.ks0, W.ks1};
+        int cur = 0;
+        auto trial_cauchy = [&](double t, int buf, double &gs, double &sks, double &ss) -> nn_status {
+            prof_begin(ctx, KC_TRIAL, B.spmv() + 16.0 * n);
+            launch_trial(ctx, A, vals, c, W.g, -t, W.g, nullptr, ksbuf[buf]);
+            prof_end(ctx);
+            S.spmvs++;
+            S.cauchy_trials++;
+            S.bytes_moved += B.spmv() + 16.0 * n;
+            nn_status r2 = read_scalars(ctx);
+            gs = H.red[0];
+            sks = H.red[1];
+            ss = H.red[2];
+            return r2;
+        };
+        auto ok_decrease = [&](double gs, double sks, double ss) {
+            return gs < 0.0 && gs + 0.5 * sks <= kMu0 * gs && std::sqrt(ss) <= delta;
+        };
+        double gs, sks, ss;
+        double t = t_cauchy;
+        if ((rc = trial_cauchy(t, cur, gs, sks, ss)) != NN_OK) return rc;
+        if (ok_decrease(gs, sks, ss)) {
+            for (int k = 0; k < 20; k++) {
+                double gs2, sks2, ss2;
+                if ((rc = trial_cauchy(t * kExtrap, cur ^ 1, gs2, sks2, ss2)) != NN_OK) return rc;
+                if (!ok_decrease(gs2, sks2, ss2)) break;
+                const bool same = gs2 == gs && sks2 == sks;
+                t *= kExtrap;
+                cur ^= 1;
+                gs = gs2;
+                sks = sks2;
+                ss = ss2;
+                if (same) break;   // every moving variable has reached its bound
+            }
+        } else {
+            int k = 0;
+            do {
+                t *= kInterp;
+                if ((rc = trial_cauchy(t, cur, gs, sks, ss)) != NN_OK) return rc;
+            } while (!ok_decrease(gs, sks, ss) && ++k < kMaxTrials && gs < 0.0);
+            if (!ok_decrease(gs, sks, ss)) {
+                // no decrease possible along -g at this precision: stationary up to rounding
+                fail(ctx, NN_EMAXIT, "Cauchy search found no decrease (rounding floor)");
+                break;
+            }
+        }
+        t_cauchy = t;
+        prof_begin(ctx, KC_OTHER, 24.0 * n);
+        launch_apply(ctx, n, c, W.g, -t);
+        prof_end(ctx);
+        S.bytes_moved += 24.0 * n;
+        double step_norm = std::sqrt(ss);
+
+        // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point
+        prof_begin(ctx, KC_OTHER, 40.0 * n);
+        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], o->inner_rtol, o->max_cg);
+        prof_end(ctx);
+        S.bytes_moved += 88.0 * n;
+        double *pa = W.p0, *pb = W.p1;
+        int it_seen = 0;
+        for (;;) {
+            const size_t mark = ctx->prof_live.size();
+            for (int j = 0; j < chunk; j++) {
+                prof_begin(ctx, KC_CG_SPMV, -1.0);
+                launch_cg_spmv(ctx, A, vals, pa, pb);
+                prof_end(ctx);
+                prof_begin(ctx, KC_CG_UPDATE, -1.0);
+                launch_cg_update(ctx, n, pb);
+                prof_end(ctx);
+                std::swap(pa, pb);
+            }
+            if ((rc = read_scalars(ctx)) != NN_OK) return rc;
+            const int ran = H.it - it_seen;
+            // byte model of the launches that did work; the rest exited at once
+            const double nf = H.n_free, nzf = H.nnz_free;
+            const double b_spmv = 4.0 * (n + 1) + n + 12.0 * nzf + 32.0 * nf;
+            const double b_upd = n + 64.0 * nf;
+            for (size_t e = mark; e < ctx->prof_live.size(); e++) {
+                ProfEntry &P = ctx->prof_live[e];
+                const int idx = (int)(e - mark) / 2;
+                P.valid = idx < ran;
+                P.bytes = P.cls == KC_CG_SPMV ? b_spmv : b_upd;
+            }
+            S.bytes_moved += ran * (b_spmv + b_upd);
+            S.spmvs += ran;
+            it_seen = H.it;
+            if (H.done) break;
+        }
+        S.cg_its += it_seen;
+        if (H.done == 4) return finish(fail(ctx, NN_ENONFINITE, "non-finite value in CG"));
+        if (H.done == 3) return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature in CG"));
+        // After an even number of iterations the last direction is in pa's twin;
+        // the solution w does not depend on it.
+
+        // ---- 4. projected search along w
+        prof_begin(ctx, KC_OTHER, 24.0 * n);
+        launch_breakpoint(ctx, n, c, W.w, W.g);
+        prof_end(ctx);
+        S.bytes_moved += 24.0 * n;
+        if ((rc = read_scalars(ctx)) != NN_OK) return rc;
+        const double bmin = H.red[0], gw = H.red[1], wn = std::sqrt(H.red[2]);
+        if (it_seen > 0 && gw < 0.0 && wn > 0.0) {
+            double tmax = std::min(1.0, delta / wn);
+            double ts = tmax;
+            if (bmin < tmax) {
+                for (int k = 0; k < kMaxTrials; k++) {
+                    prof_begin(ctx, KC_TRIAL, B.spmv() + 16.0 * n);
+                    launch_trial(ctx, A, vals, c, W.w, ts, W.g, W.mask, nullptr);
+                    prof_end(ctx);
+                    S.spmvs++;
+                    S.search_trials++;
+                    S.bytes_moved += B.spmv() + 16.0 * n;
+                    if ((rc = read_scalars(ctx)) != NN_OK) return rc;
+                    const double g2 = H.red[0], s2 = H.red[1];
+                    if (g2 < 0.0 && g2 + 0.5 * s2 <= kMu0 * g2) break;
+                    ts *= kBack;
+                    if (ts <= bmin) {
+                        ts = bmin;   // no bound is crossed: decrease is guaranteed
+                        break;
+                    }
+                }
+            }
+            if (ts > 0.0) {
+                prof_begin(ctx, KC_OTHER, 24.0 * n);
+                launch_apply(ctx, n, c, W.w, ts);
+                prof_end(ctx);
+                S.bytes_moved += 24.0 * n;
+                step_norm += ts * wn;
+            }
+        }
+        // ---- 5. radius update (exact model: ratio one)
+        if (std::isfinite(delta) && step_norm >= 0.99 * delta) delta *= 4.0;
+    }
+    if (result == NN_OK) ctx->err.clear();
+    return finish(result);
+}
+
+}  // namespace nnqp

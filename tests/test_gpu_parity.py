@@ -1,0 +1,302 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Tolerances: assembly and SpMV values to a few units of FP64 roundoff
+(different summation orders); QP solutions ||c - c_ref||_inf / ||c_ref||_inf
+<= 1e-8 with the active set identical on the nodes the oracle decides
+unambiguously (free: c_ref > 1e-8 ||c_ref||_inf; strictly active: c_ref == 0
+and g_ref > 1e-8 ||F||_inf); min c >= 0 exactly on every path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_1506_08435_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PARITY_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1506_08435_amd import nnqp
+    c = nnqp.Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _check_solution(S, c, active, ref_c, tol=PARITY_TOL):
+    assert c.min() >= 0.0, c.min()
+    assert np.array_equal(active.astype(bool), c == 0.0)
+    scale = np.abs(ref_c).max()
+    err = np.abs(c - ref_c).max() / scale
+    assert err <= tol, err
+    g_ref = oracle.spmv(S, ref_c) - S.F
+    free, strict = oracle.nondegenerate_masks(ref_c, g_ref, S.F)
+    assert np.all(c[free] > 0.0), "a free node came out active"
+    assert np.all(c[strict] == 0.0), "a strictly active node came out free"
+    return err
+
+
+# ---------------------------------------------------------------- assembly
+ASM_CASES = {
+    "square2d_64": lambda: W.config_small(),
+    "square2d_37_ragged": lambda: W.square2d(37, theta=1.1, ratio=3e-3),
+    "cube3d_9": lambda: W.cube3d(9),
+    "transient_13x11x7": lambda: W.config_transient3d(13, 11, 7, ell=2.0),
+    "batch_member_3": lambda: W.batch_problem(3, n_range=(20, 40)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ASM_CASES))
+def test_assembly_matches_oracle(ctx, name):
+    p = ASM_CASES[name]()
+    K, F, dof = ctx.assemble(p, with_mass=True)
+    S = oracle.assemble(p, with_mass=True)
+    rowptr, col, val, mval = ctx.matrix_export(K)
+    assert K.n == S.n and K.nnz == S.nnz
+    assert np.array_equal(rowptr, S.rowptr) and np.array_equal(col, S.col)
+    assert np.array_equal(dof, S.dof)
+    scale = np.abs(S.K).max()
+    assert np.abs(val - S.K).max() <= 1e-14 * scale
+    assert np.abs(mval - S.M).max() <= 1e-14 * np.abs(S.M).max()
+    assert np.abs(_np(F) - S.F).max() <= 1e-14 * max(np.abs(S.F).max(), 1e-300)
+    import scipy.sparse as sp
+    A = sp.csr_matrix((val, col, rowptr), shape=(K.n, K.n))
+    assert (A - A.T).count_nonzero() == 0          # bitwise symmetric
+
+
+def test_matvec_matches_oracle(ctx):
+    import torch
+    p = W.cube3d(12)
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    S = oracle.assemble(p, with_mass=True)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(S.n)
+    xd = torch.from_numpy(x).to(ctx.device)
+    y = _np(ctx.matvec(K, xd))
+    ctx.torch.cuda.synchronize()
+    ref = oracle.spmv(S, x)
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(S.K).max() * np.abs(x).max() * 15
+    ym = _np(ctx.matvec(K, xd, which=1))
+    refm = oracle.spmv(S, x, vals=S.M)
+    assert np.abs(ym - refm).max() <= 1e-14 * np.abs(S.M).max() * np.abs(x).max() * 15
+
+
+# ---------------------------------------------------------------- QP solves
+SOLVE_CASES = {
+    "square2d_64": lambda: W.config_small(),
+    "square2d_45_theta1": lambda: W.square2d(45, theta=1.0, ratio=1e-3),
+    "cube3d_16": lambda: W.cube3d(16),
+    "cube3d_21_ragged": lambda: W.cube3d(21),
+    "transient_field_20x18x9": lambda: W.config_transient3d(20, 18, 9, ell=3.0),
+    "batch_member_0": lambda: W.batch_problem(0, n_range=(40, 60)),
+    "batch_member_5": lambda: W.batch_problem(5, n_range=(40, 60)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SOLVE_CASES))
+def test_solve_matches_oracle(ctx, name):
+    p = SOLVE_CASES[name]()
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, inner_rtol=0.1)
+    c, active = _np(c), _np(active)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    assert ref.certified
+    err = _check_solution(S, c, active, ref.c)
+    k = oracle.kkt(S, c)
+    assert k.r <= 1.01e-12 + 4 * ref.floor
+    print(f"{name}: n={S.n} err={err:.2e} kkt={k.r:.2e} outer={st['outer_its']} "
+          f"cg={st['cg_its']} {st['seconds'] * 1e3:.1f} ms")
+
+
+@pytest.mark.parametrize("rtol", [1e-1, 1e-2, 1e-3])
+def test_inner_tolerances_same_minimiser(ctx, rtol):
+    """TRON1/2/3 inner tolerances reach the same minimiser (Sec. 5.1)."""
+    p = W.square2d(48)
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, inner_rtol=rtol)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    _check_solution(S, _np(c), _np(active), ref.c)
+
+
+def test_metric_tolerance_certificate(ctx):
+    """At the metric tolerance the oracle's own KKT evaluation agrees."""
+    p = W.cube3d(20)
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-8)
+    c = _np(c)
+    S = oracle.assemble(p)
+    k = oracle.kkt(S, c)
+    assert st["kkt_rel"] <= 1e-8
+    assert abs(k.r - st["kkt_rel"]) <= 1e-6 * st["kkt_rel"] + 1e-14
+    assert k.min_c >= 0.0 and c.min() >= 0.0
+    ref = oracle.solve(S, tol=1e-13)
+    # error at the metric tolerance is bounded by the conditioning, kept loose here
+    assert np.abs(c - ref.c).max() / ref.c.max() <= 1e-4
+
+
+def test_random_spd_from_csr_matches_brute_force(ctx):
+    import scipy.sparse as sp
+    import torch
+    rng = np.random.default_rng(2015)
+    for trial in range(12):
+        n = int(rng.integers(1, 11))
+        A = rng.standard_normal((n, n))
+        Kd = A @ A.T + 0.5 * np.eye(n)
+        Fv = rng.standard_normal(n)
+        c_bf, _ = brute.brute_force(Kd, Fv)
+        M = sp.csr_matrix(Kd)
+        M.sort_indices()
+        K = ctx.matrix_from_csr(M.indptr, M.indices, M.data)
+        f = torch.from_numpy(Fv).to(ctx.device)
+        c, active, st = ctx.solve_nonneg(K, f, tol=1e-13)
+        c = _np(c)
+        assert c.min() >= 0.0
+        scale = max(np.abs(c_bf).max(), 1e-300)
+        assert np.abs(c - c_bf).max() <= 1e-9 * scale, (trial, c, c_bf)
+
+
+# ---------------------------------------------------------------- edge cases
+def test_all_dirichlet_is_empty(ctx):
+    p = W.square2d(1)
+    K, F, dof = ctx.assemble(p)
+    assert K.n == 0 and (dof == -1).all()
+    c, active, st = ctx.solve_nonneg(K, F)
+    assert st["status"] == 0
+
+
+def test_single_dof(ctx):
+    p = W.square2d(2)
+    K, F, _ = ctx.assemble(p)
+    assert K.n == 1
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-14)
+    S = oracle.assemble(p)
+    assert abs(_np(c)[0] - S.F[0] / S.K[0]) <= 1e-15 * S.F[0] / S.K[0]
+
+
+def test_nonpositive_source_gives_exact_zero(ctx):
+    p = W.square2d(20)
+    p.f_elem = -p.f_elem
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F)
+    assert np.array_equal(_np(c), np.zeros(K.n)) and _np(active).all()
+    p.f_elem = np.zeros_like(p.f_elem)
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F)
+    assert np.array_equal(_np(c), np.zeros(K.n))
+
+
+def test_warm_start_and_paper_start_agree(ctx):
+    import torch
+    p = W.square2d(40)
+    K, F, _ = ctx.assemble(p)
+    c1, _, _ = ctx.solve_nonneg(K, F, tol=1e-12)
+    c1 = _np(c1).copy()
+    rng = np.random.default_rng(11)
+    warm = torch.from_numpy(rng.random(K.n) - 0.3).to(ctx.device)
+    c2, _, st = ctx.solve_nonneg(K, F, tol=1e-12, c0_mode=1, c=warm)
+    c2 = _np(c2)
+    assert c2.min() >= 0.0
+    assert np.abs(c1 - c2).max() <= 1e-9 * c1.max()
+    # a warm start at the solution converges at once
+    c3, _, st3 = ctx.solve_nonneg(K, F, tol=1e-10, c0_mode=1, c=torch.from_numpy(c1).to(ctx.device))
+    assert st3["outer_its"] <= 1
+
+
+def test_deterministic_bitwise(ctx):
+    p = W.cube3d(14)
+    K, F, _ = ctx.assemble(p)
+    a = _np(ctx.solve_nonneg(K, F, tol=1e-10)[0]).copy()
+    b = _np(ctx.solve_nonneg(K, F, tol=1e-10)[0]).copy()
+    assert np.array_equal(a, b)
+
+
+def test_nonfinite_source_is_reported(ctx):
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.square2d(10)
+    K, F, _ = ctx.assemble(p)
+    bad = F.clone()
+    bad[3] = float("nan")
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_nonneg(K, bad)
+    assert ei.value.status == nnqp.NN_ENONFINITE
+    p.f_elem = p.f_elem.copy()
+    p.f_elem[0] = np.inf
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.assemble(p)
+    assert ei.value.status == nnqp.NN_ENONFINITE
+
+
+def test_bad_options_rejected(ctx):
+    from paper_1506_08435_amd import nnqp
+    p = W.square2d(6)
+    K, F, _ = ctx.assemble(p)
+    for kw in ({"tol": 0.0}, {"inner_rtol": 1.5}, {"c0_mode": 7}, {"max_cg": 0}):
+        with pytest.raises(nnqp.NnError) as ei:
+            ctx.solve_nonneg(K, F, **kw)
+        assert ei.value.status == nnqp.NN_EINVAL
+
+
+def test_iteration_cap_returns_feasible_iterate(ctx):
+    from paper_1506_08435_amd import nnqp
+    p = W.cube3d(16)
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, max_outer=1, allow_maxit=True)
+    assert st["status"] == nnqp.NN_EMAXIT
+    assert _np(c).min() >= 0.0 and st["outer_its"] == 1
+
+
+# ---------------------------------------------------------------- transient
+def test_transient_steps_match_oracle(ctx):
+    import torch
+    p = W.cube3d(10)
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    S = oracle.assemble(p, with_mass=True)
+    dt = 1e-3
+    c_ref = np.zeros(S.n)
+    c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    for step in range(4):
+        r = oracle.transient_step(S, dt, c_ref, tol=1e-13)
+        assert r.certified
+        c, active, st = ctx.step_transient(K, dt, F, c, tol=1e-12)
+        Kt, ft = oracle.transient_system(S, dt, c_ref)
+        S_t = oracle.System(n=S.n, rowptr=S.rowptr, col=S.col, K=Kt, M=None, F=ft, dof=S.dof)
+        _check_solution(S_t, _np(c), _np(active), r.c)
+        c_ref = r.c
+
+
+# ---------------------------------------------------------------- full size (bench configuration)
+def test_full_size_cube128_certificate(ctx):
+    """The 128^3 workload at the metric tolerance, in the launch configuration
+    the benchmark times: the oracle re-evaluates the KKT conditions of the GPU
+    solution with its own assembly, and sampled rows of K match."""
+    p = W.config_cube128()
+    K, F, dof = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-8)
+    c = _np(c)
+    assert c.min() >= 0.0 and np.array_equal(_np(active).astype(bool), c == 0.0)
+    S = oracle.assemble(p)
+    assert S.n == K.n == 2048383
+    k = oracle.kkt(S, c)
+    assert k.r <= 1e-8 * (1 + 1e-6), k.r
+    assert k.min_c >= 0.0 and k.nonfinite == 0
+    rowptr, col, val, _ = ctx.matrix_export(K)
+    rng = np.random.default_rng(128)
+    rows = rng.choice(S.n, 2000, replace=False)
+    for r in rows:
+        a, b = S.rowptr[r], S.rowptr[r + 1]
+        assert np.array_equal(col[a:b], S.col[a:b])
+        assert np.abs(val[a:b] - S.K[a:b]).max() <= 1e-14 * np.abs(S.K[a:b]).max()
+    print(f"cube128: kkt {k.r:.3e} outer {st['outer_its']} cg {st['cg_its']} "
+          f"{st['seconds']:.3f} s -> {S.n / st['seconds'] / 1e6:.2f} M DOF/s")
