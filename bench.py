@@ -1,0 +1,157 @@
+"""Benchmark: solved DOF/s of the non-negative diffusion QP at KKT tol 1e-8.
+
+One step = one full solve of the 128^3-cell anisotropic Kuhn-tet problem
+(2,048,383 free DOF, 30,340,171 nonzeros; D = R diag(1, 1e-2, 1e-4) R^T,
+f = 1 on the central cube of side 1/4, c = 0 on the boundary) from the
+paper's start value c = 1e-8, FP64, until ||pg||_2 <= 1e-8 ||f||_2.  K and f
+are assembled on the device before the timed region.
+
+Prints one JSON line.  `roofline` is for the dominant kernel (the CG matrix
+pass): algorithmic bytes of its launches (perfect-cache model) over their
+average duration, both measured with HIP events on the solve stream inside
+the timed region.  `cpu_baseline` times the CPU oracle on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_spmv_cube128_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1506_08435_amd", "csrc", "kernels.hip")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the CG matrix pass from the committed rocprofv3
+    counter summary, or None if absent or taken on different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(n_side: int, threads: int):
+    import numpy as np  # noqa: F401
+    import oracle
+    from paper_1506_08435_amd import workloads as W
+    if threads > 0:
+        oracle.set_num_threads(threads)
+    p = W.cube3d(n_side)
+    S = oracle.assemble(p)
+    r = oracle.solve(S, tol=1e-8)
+    return {"value": S.n / r.seconds, "unit": "DOF/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"oracle GPCG + face solve, tol 1e-8, on the same workload at {n_side}^3 cells "
+                       f"({S.n} free DOF) instead of 128^3: {r.seconds:.2f} s"),
+            "seconds": r.seconds}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128, help="cells per side of the cube workload")
+    ap.add_argument("--inner-rtol", type=float, default=0.1)
+    ap.add_argument("--cpu-n", type=int, default=64, help="cube side of the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1506_08435_amd import nnqp, workloads as W
+
+    p = W.cube3d(args.n)
+    ctx = nnqp.Context(0)
+    K, F, _ = ctx.assemble(p)
+    n = K.n
+    opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol)
+    c = torch.empty(n, dtype=torch.float64, device=ctx.device)
+    for _ in range(args.warmup):
+        ctx.solve_nonneg(K, F, opts=opts, c=c)
+    ctx.set_profiling(not args.no_kernel_timing)
+    ctx.kernel_times(reset=True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, st = ctx.solve_nonneg(K, F, opts=opts, c=c)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_profiling(False)
+    wall = t1 - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = n * args.steps / wall
+
+    dom = kt["cg_spmv"]
+    avg_ms = dom["ms"] / max(dom["count"], 1)
+    bytes_per_launch = dom["bytes"] / max(dom["count"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if dom["count"] else 0.0
+    traffic = read_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": "k_cg_spmv (CG matrix pass with fused direction update)",
+                "launches": dom["count"], "avg_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+
+    out = {
+        "metric": "solved DOF/s at KKT tol 1e-8",
+        "value": round(value, 1),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cube3d_{args.n}: {args.n}^3 cells x 6 P1 tets, {n} free DOF, "
+                               f"{K.nnz} nnz, D = R diag(1,1e-2,1e-4) R^T, f = 1 on central cube, "
+                               "FP64 plain solve from c0 = 1e-8 to KKT tol 1e-8",
+                   "inner_rtol": args.inner_rtol, "solver": "TRON-style active-set Newton-CG"},
+        "roofline": roofline,
+        "solve": {"outer_its": stats[-1]["outer_its"], "cg_its": stats[-1]["cg_its"],
+                  "spmvs": stats[-1]["spmvs"], "kkt_rel": stats[-1]["kkt_rel"],
+                  "device_s": round(stats[-1]["seconds"], 4),
+                  "algorithmic_GBps_whole_solve": round(stats[-1]["bytes_moved"] / stats[-1]["seconds"] / 1e9, 1),
+                  "kernel_classes": {k: {"count": v["count"],
+                                         "avg_us": round(v["ms"] / max(v["count"], 1) * 1e3, 2)}
+                                     for k, v in kt.items()}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

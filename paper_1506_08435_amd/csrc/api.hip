@@ -39,6 +39,25 @@ nn_status ensure_workspace(nn_ctx *ctx, int64_t n)
     return NN_OK;
 }
 
+nn_status host_reduce(nn_ctx *ctx, int64_t n, int nv, const int *ops, double *out)
+{
+    const Part P = make_part(n);
+    // partials are laid out [value][block]: copy the first nv rows
+    const size_t count = (size_t)(nv - 1) * kMaxBlocks + P.nb;
+    NN_HIP_TRY(ctx, hipMemcpyAsync(ctx->h_part, ctx->partials, sizeof(double) * count,
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    NN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < nv; k++) {
+        double a = ops[k] == OP_SUM ? 0.0 : (ops[k] == OP_MIN ? INFINITY : -INFINITY);
+        for (int b = 0; b < P.nb; b++) {
+            const double v = ctx->h_part[(size_t)k * kMaxBlocks + b];
+            a = ops[k] == OP_SUM ? a + v : (ops[k] == OP_MIN ? std::fmin(a, v) : std::fmax(a, v));
+        }
+        out[k] = a;
+    }
+    return NN_OK;
+}
+
 nn_status read_scalars(nn_ctx *ctx)
 {
     NN_HIP_TRY(ctx, hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(DevScalars), hipMemcpyDeviceToHost,
@@ -121,13 +140,15 @@ nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
     if (!ctx) return NN_EOOM;
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
-    bool ok = hipMalloc(&ctx->partials, sizeof(double) * kMaxBlocks * kMaxRed) == hipSuccess &&
-              hipMalloc(&ctx->ticket, sizeof(unsigned) * 4) == hipSuccess &&
+    const size_t part_bytes = sizeof(double) * kSlots * kMaxBlocks * kMaxRed;
+    bool ok = hipMalloc(&ctx->partials, part_bytes) == hipSuccess &&
+              hipHostMalloc(&ctx->h_part, sizeof(double) * kMaxBlocks * kMaxRed,
+                            hipHostMallocDefault) == hipSuccess &&
               hipMalloc(&ctx->scal, sizeof(DevScalars)) == hipSuccess &&
               hipHostMalloc(&ctx->h_scal, sizeof(DevScalars), hipHostMallocDefault) == hipSuccess &&
               hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
     if (ok) {
-        ok = hipMemsetAsync(ctx->ticket, 0, sizeof(unsigned) * 4, ctx->stream) == hipSuccess &&
+        ok = hipMemsetAsync(ctx->partials, 0, part_bytes, ctx->stream) == hipSuccess &&
              hipMemsetAsync(ctx->scal, 0, sizeof(DevScalars), ctx->stream) == hipSuccess &&
              hipStreamSynchronize(ctx->stream) == hipSuccess;
     }
@@ -151,7 +172,7 @@ void nn_destroy(nn_ctx *ctx)
         if (v) (void)hipFree(v);
     if (W.mask) (void)hipFree(W.mask);
     if (ctx->partials) (void)hipFree(ctx->partials);
-    if (ctx->ticket) (void)hipFree(ctx->ticket);
+    if (ctx->h_part) (void)hipHostFree(ctx->h_part);
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -228,11 +249,17 @@ nn_status nn_matrix_from_csr(nn_ctx *ctx, int64_t n, const int64_t *rowptr, cons
     M->n = n;
     M->nnz = nnz;
     const size_t nz = (size_t)std::max<int64_t>(nnz, 1);
+    double *d_val = nullptr, *d_mval = nullptr;
+    auto release = [&]() {
+        if (d_val) (void)hipFree(d_val);
+        if (d_mval) (void)hipFree(d_mval);
+    };
     bool ok = hipMalloc(&M->rowptr, sizeof(int) * (n + 1)) == hipSuccess &&
               hipMalloc(&M->col, sizeof(int) * nz) == hipSuccess &&
-              hipMalloc(&M->val, sizeof(double) * nz) == hipSuccess &&
-              (!mval || hipMalloc(&M->mval, sizeof(double) * nz) == hipSuccess);
+              hipMalloc(&d_val, sizeof(double) * nz) == hipSuccess &&
+              (!mval || hipMalloc(&d_mval, sizeof(double) * nz) == hipSuccess);
     if (!ok) {
+        release();
         nn_matrix_free(ctx, M);
         return fail(ctx, NN_EOOM, "matrix allocation failed");
     }
@@ -240,17 +267,20 @@ nn_status nn_matrix_from_csr(nn_ctx *ctx, int64_t n, const int64_t *rowptr, cons
     ok = hipMemcpyAsync(M->rowptr, rp32.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, s) == hipSuccess;
     if (ok && nnz > 0) {
         ok = hipMemcpyAsync(M->col, col, sizeof(int) * nnz, hipMemcpyHostToDevice, s) == hipSuccess &&
-             hipMemcpyAsync(M->val, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s) == hipSuccess &&
-             (!mval || hipMemcpyAsync(M->mval, mval, sizeof(double) * nnz, hipMemcpyHostToDevice, s) == hipSuccess);
+             hipMemcpyAsync(d_val, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s) == hipSuccess &&
+             (!mval || hipMemcpyAsync(d_mval, mval, sizeof(double) * nnz, hipMemcpyHostToDevice, s) == hipSuccess);
     }
     if (!ok || hipStreamSynchronize(s) != hipSuccess) {
+        release();
         nn_matrix_free(ctx, M);
         return fail(ctx, NN_EHIP, "matrix upload failed");
     }
     int mr = 0;
     for (int64_t i = 0; i < n; i++) mr = std::max<int>(mr, (int)(rowptr[i + 1] - rowptr[i]));
     M->max_row = mr;
-    nn_status st = finish_matrix(ctx, M);
+    nn_status st = sell_build(ctx, M, rowptr, d_val, d_mval);
+    release();
+    if (st == NN_OK) st = finish_matrix(ctx, M);
     if (st != NN_OK) {
         nn_matrix_free(ctx, M);
         return st;
@@ -273,20 +303,32 @@ nn_status nn_matrix_export(nn_ctx *ctx, const nn_matrix *A, int64_t *rowptr, int
 {
     NN_CHECK_CTX(ctx);
     if (!A) return fail(ctx, NN_EINVAL, "null matrix");
+    if (mval && !A->mval) return fail(ctx, NN_EINVAL, "matrix has no capacity values");
     hipStream_t s = ctx->stream;
-    if (rowptr) {
-        std::vector<int> rp(A->n + 1);
-        NN_HIP_TRY(ctx, hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int) * (A->n + 1),
-                                       hipMemcpyDeviceToHost, s));
-        NN_HIP_TRY(ctx, hipStreamSynchronize(s));
-        for (int64_t i = 0; i <= A->n; i++) rowptr[i] = rp[i];
-    }
+    std::vector<int> rp(A->n + 1);
+    NN_HIP_TRY(ctx, hipMemcpyAsync(rp.data(), A->rowptr, sizeof(int) * (A->n + 1),
+                                   hipMemcpyDeviceToHost, s));
+    NN_HIP_TRY(ctx, hipStreamSynchronize(s));
+    std::vector<int64_t> rp64(rp.begin(), rp.end());
+    if (rowptr)
+        for (int64_t i = 0; i <= A->n; i++) rowptr[i] = rp64[i];
     if (A->nnz > 0) {
         if (col) NN_HIP_TRY(ctx, hipMemcpyAsync(col, A->col, sizeof(int) * A->nnz, hipMemcpyDeviceToHost, s));
-        if (val) NN_HIP_TRY(ctx, hipMemcpyAsync(val, A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, s));
-        if (mval) {
-            if (!A->mval) return fail(ctx, NN_EINVAL, "matrix has no capacity values");
-            NN_HIP_TRY(ctx, hipMemcpyAsync(mval, A->mval, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, s));
+        // values live in sliced-ELL order: entry k of row i sits at off[i/64] + 64 k + i%64
+        std::vector<int64_t> off;
+        int wmax = 0;
+        sell_offsets(rp64.data(), A->n, off, wmax);
+        std::vector<double> buf(A->nsell);
+        const double *srcs[2] = {A->val, A->mval};
+        double *dsts[2] = {val, mval};
+        for (int t = 0; t < 2; t++) {
+            if (!dsts[t]) continue;
+            NN_HIP_TRY(ctx, hipMemcpyAsync(buf.data(), srcs[t], sizeof(double) * A->nsell,
+                                           hipMemcpyDeviceToHost, s));
+            NN_HIP_TRY(ctx, hipStreamSynchronize(s));
+            for (int64_t i = 0; i < A->n; i++)
+                for (int64_t k = 0; k < rp64[i + 1] - rp64[i]; k++)
+                    dsts[t][rp64[i] + k] = buf[off[i / kSlice] + k * kSlice + i % kSlice];
         }
     }
     NN_HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -296,11 +338,12 @@ nn_status nn_matrix_export(nn_ctx *ctx, const nn_matrix *A, int64_t *rowptr, int
 nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes)
 {
     if (!A || !bytes) return NN_EINVAL;
-    const double n = (double)A->n, nnz = (double)A->nnz;
-    double b = 4.0 * (n + 1) + 12.0 * nnz + 8.0 * n;       // rowptr, col, values, diag
-    if (A->mval) b += 16.0 * nnz + 8.0 * n;                 // capacity + transient values, diag
+    const double n = (double)A->n, nnz = (double)A->nnz, ns = (double)A->nsell;
+    double b = 4.0 * (n + 1) + 4.0 * nnz;                   // CSR pattern
+    b += 4.0 * (A->nslices + 1) + 12.0 * ns + 8.0 * n;      // sliced-ELL columns, values, diag
+    if (A->mval) b += 16.0 * ns + 8.0 * n;                  // capacity + transient values, diag
     b += 11.0 * 8.0 * n + n;                                // solver work vectors + mask
-    if (precision == NN_MIXED) b += 4.0 * nnz + 40.0 * n;   // float32 values and vectors
+    if (precision == NN_MIXED) b += 4.0 * ns + 40.0 * n;    // float32 values and vectors
     *bytes = (size_t)b;
     return NN_OK;
 }
@@ -309,7 +352,7 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
 {
     if (!A) return;
     if (ctx) (void)hipSetDevice(ctx->device);
-    int *iv[] = {A->rowptr, A->col};
+    int *iv[] = {A->rowptr, A->col, A->sl_off, A->sl_col};
     for (int *p : iv)
         if (p) (void)hipFree(p);
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
@@ -370,11 +413,11 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     if (n == 0) return solve_impl(ctx, K, K->val, K->diag, f_dev, opts, c_dev, active_dev, stats);
     if (!K->kt || K->kt_dt != dt) {
         if (!K->kt) {
-            if (hipMalloc(&K->kt, sizeof(double) * std::max<int64_t>(K->nnz, 1)) != hipSuccess ||
+            if (hipMalloc(&K->kt, sizeof(double) * std::max<int64_t>(K->nsell, 1)) != hipSuccess ||
                 hipMalloc(&K->kt_diag, sizeof(double) * n) != hipSuccess)
                 return fail(ctx, NN_EOOM, "transient matrix allocation");
         }
-        launch_axpby_vals(ctx, K->nnz, K->mval, dt, K->val, K->kt);
+        launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
         launch_diag(ctx, K, K->kt, K->kt_diag);
         NN_HIP_TRY(ctx, hipGetLastError());
         K->kt_dt = dt;

@@ -164,6 +164,47 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs A)
 }
 
 // ---------------------------------------------------------------- host side
+void sell_offsets(const int64_t *rowptr, int64_t n, std::vector<int64_t> &off, int &wmax)
+{
+    const int64_t ns = (n + kSlice - 1) / kSlice;
+    off.assign(ns + 1, 0);
+    wmax = 0;
+    for (int64_t s = 0; s < ns; s++) {
+        int w = 0;
+        for (int64_t i = s * kSlice; i < std::min<int64_t>(n, (s + 1) * kSlice); i++)
+            w = std::max<int>(w, (int)(rowptr[i + 1] - rowptr[i]));
+        off[s + 1] = off[s] + (int64_t)w * kSlice;
+        wmax = std::max(wmax, w);
+    }
+}
+
+nn_status sell_build(nn_ctx *ctx, nn_matrix *A, const int64_t *rowptr_host, const double *csr_val,
+                     const double *csr_mval)
+{
+    std::vector<int64_t> off;
+    int wmax = 0;
+    sell_offsets(rowptr_host, A->n, off, wmax);
+    const int64_t ns = (int64_t)off.size() - 1;
+    const int64_t nsell = off.back();
+    if (nsell >= ((int64_t)1 << 31)) return fail(ctx, NN_EINVAL, "sliced-ELL size exceeds 32-bit offsets");
+    A->nslices = ns;
+    A->nsell = nsell;
+    A->wmax = wmax;
+    std::vector<int> off32(off.begin(), off.end());
+    const size_t ne = (size_t)std::max<int64_t>(nsell, 1);
+    hipError_t e = hipMalloc(&A->sl_off, sizeof(int) * (ns + 1));
+    if (e == hipSuccess) e = hipMalloc(&A->sl_col, sizeof(int) * ne);
+    if (e == hipSuccess) e = hipMalloc(&A->val, sizeof(double) * ne);
+    if (e == hipSuccess && csr_mval) e = hipMalloc(&A->mval, sizeof(double) * ne);
+    if (e != hipSuccess) return fail(ctx, NN_EOOM, "sliced-ELL allocation failed");
+    NN_HIP_TRY(ctx, hipMemcpyAsync(A->sl_off, off32.data(), sizeof(int) * (ns + 1),
+                                   hipMemcpyHostToDevice, ctx->stream));
+    if (A->n > 0) launch_csr_to_sell(ctx, A, csr_val, csr_mval);
+    NN_HIP_TRY(ctx, hipGetLastError());
+    NN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return NN_OK;
+}
+
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A)
 {
     if (A->n > 0) {
@@ -179,7 +220,6 @@ nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A)
                 return fail(ctx, NN_ENOTSPD, "non-positive diagonal entry at row " + std::to_string(i));
         }
     }
-    A->lanes = choose_lanes(A->n > 0 ? (double)A->nnz / (double)A->n : 1.0);
     return NN_OK;
 }
 
@@ -285,7 +325,7 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
         nn_matrix_free(ctx, M);
         return st;
     };
-    DevBuf d_free, d_incp, d_ince, d_elems, d_coords, d_D, d_ks, d_f, d_dof, d_F;
+    DevBuf d_free, d_incp, d_ince, d_elems, d_coords, d_D, d_ks, d_f, d_dof, d_F, d_val, d_mval;
     auto up = [&](DevBuf &b, const void *src, size_t bytes) -> hipError_t {
         hipError_t e = hipMalloc(&b.p, bytes > 0 ? bytes : 8);
         if (e != hipSuccess) return e;
@@ -313,9 +353,9 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
     {
         hipError_t e = hipMalloc(&M->rowptr, sizeof(int) * (n + 1));
         if (e == hipSuccess) e = hipMalloc(&M->col, sizeof(int) * std::max<int64_t>(nnz, 1));
-        if (e == hipSuccess) e = hipMalloc(&M->val, sizeof(double) * std::max<int64_t>(nnz, 1));
+        if (e == hipSuccess) e = hipMalloc(&d_val.p, sizeof(double) * std::max<int64_t>(nnz, 1));
         if (e == hipSuccess && with_mass)
-            e = hipMalloc(&M->mval, sizeof(double) * std::max<int64_t>(nnz, 1));
+            e = hipMalloc(&d_mval.p, sizeof(double) * std::max<int64_t>(nnz, 1));
         if (e == hipSuccess && !F_dev) e = hipMalloc(&d_F.p, sizeof(double) * std::max<int64_t>(n, 1));
         if (e != hipSuccess) {
             fail(ctx, NN_EOOM, std::string("matrix allocation: ") + hipGetErrorString(e));
@@ -327,8 +367,8 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
     if (nnz > 0) {
         NN_HIP_TRY(ctx, hipMemcpyAsync(M->col, col.data(), sizeof(int) * nnz, hipMemcpyHostToDevice,
                                        ctx->stream));
-        NN_HIP_TRY(ctx, hipMemsetAsync(M->val, 0, sizeof(double) * nnz, ctx->stream));
-        if (M->mval) NN_HIP_TRY(ctx, hipMemsetAsync(M->mval, 0, sizeof(double) * nnz, ctx->stream));
+        NN_HIP_TRY(ctx, hipMemsetAsync(d_val.p, 0, sizeof(double) * nnz, ctx->stream));
+        if (d_mval.p) NN_HIP_TRY(ctx, hipMemsetAsync(d_mval.p, 0, sizeof(double) * nnz, ctx->stream));
     }
     AsmArgs args;
     args.dim = dim;
@@ -345,8 +385,8 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
     args.dof = (const int *)d_dof.p;
     args.rowptr = M->rowptr;
     args.col = M->col;
-    args.val = M->val;
-    args.mval = M->mval;
+    args.val = (double *)d_val.p;
+    args.mval = (double *)d_mval.p;
     args.F = F_dev ? F_dev : (double *)d_F.p;
     if (n > 0) {
         const int64_t nb = (n + kBlock - 1) / kBlock;
@@ -354,7 +394,8 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
         NN_HIP_TRY(ctx, hipGetLastError());
     }
     NN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    nn_status st = finish_matrix(ctx, M);
+    nn_status st = sell_build(ctx, M, rp64.data(), (const double *)d_val.p, (const double *)d_mval.p);
+    if (st == NN_OK) st = finish_matrix(ctx, M);
     if (st != NN_OK) return cleanup(st);
     int mr = 0;
     for (int64_t r = 0; r < n; r++) mr = std::max(mr, rowlen[r]);

@@ -12,44 +12,47 @@
 namespace nnqp {
 
 // ---------------------------------------------------------------- launch geometry
-// Every row-parallel kernel of a solve uses the same partition of the rows:
-// `nb` blocks of 256 threads, block b owning rows [lb*chunk, (lb+1)*chunk) where
-// lb = xcd_block(b).  The hardware deals workgroups round-robin to the 8 XCDs,
-// so lb maps the blocks of one XCD onto one contiguous eighth of the rows: each
-// XCD's L2 then sees one slab of the vectors instead of all of them, and a row
-// is touched by the same XCD in every kernel of the solve.
-constexpr int kBlock = 256;
-constexpr int kXcds = 8;
-constexpr int kMaxBlocks = 2048;   // 8 workgroups per CU on 256 CUs
+// The solver stores K in sliced-ELL form: rows are grouped in slices of 64
+// (one wavefront), each slice padded to the longest row in it and stored
+// column-major, so lane l of the wavefront owns row 64 s + l and every
+// value/index load of the wavefront is one contiguous 512/256-byte segment.
+// Every row-parallel kernel walks the slices grid-stride, one slice per
+// wavefront at a time, with the same slice -> wavefront assignment, so the
+// vectors a kernel writes are read back by the same wavefront (and XCD) in
+// the next kernel.  Two 1024-thread blocks per CU fill its 32 wave slots.
+constexpr int kBlock = 1024;
+constexpr int kWaves = kBlock / 64;
+constexpr int kSlice = 64;
+constexpr int kMaxBlocks = 512;    // 2 workgroups per CU on 256 CUs
 constexpr int kMaxRed = 8;         // values per reduction
 
 struct Part {
-    int n = 0;       // rows
-    int nb = 0;      // blocks (multiple of kXcds)
-    int chunk = 0;   // rows per block (multiple of kBlock)
+    int n = 0;        // rows
+    int nslices = 0;  // ceil(n / 64)
+    int nb = 0;       // blocks
 };
 
 Part make_part(int64_t n, int max_blocks = kMaxBlocks);
 
-__device__ __forceinline__ int xcd_block(int b, int nb)
-{
-    return (b % kXcds) * (nb / kXcds) + (b / kXcds);
-}
+// ---------------------------------------------------------------- reductions
+// A reduction kernel leaves one partial per block and value in a slot of
+// ctx->partials ([slot][value][block]); nothing is combined with atomics.
+// Results the host needs are combined on the host in block order; results the
+// next kernel needs (CG scalars) are combined by every block of that kernel in
+// the same fixed order, so all blocks hold bitwise identical values.
+enum { SLOT_HOST = 0, SLOT_U0 = 1, SLOT_U1 = 2, SLOT_Q = 3, kSlots = 4 };
+enum : int { OP_SUM = 0, OP_MIN = 1, OP_MAX = 2 };
 
 // ---------------------------------------------------------------- device scalars
-// Scalars the kernels hand to each other without a host round trip.
+// Scalars the CG kernels hand to each other without a host round trip.  Only
+// block 0 of a kernel writes them; the next kernel on the stream reads them.
 struct DevScalars {
-    double red[kMaxRed];   // output of the last reduction kernel
-    double rz;             // CG: r.z
-    double rr;             // CG: r.r
-    double rr_stop;        // CG: stop when r.r <= rr_stop
-    double alpha, beta, pq;
+    double rzh[2];         // r.z of CG iteration j, stored at j % 2
+    double rr_stop;        // stop when r.r <= rr_stop
+    double n_free;         // free rows of the current face
     double nnz_free;       // nonzeros in the free rows (byte model)
-    double n_free;
     int done;              // CG: 0 running, 1 converged/capped, 3 breakdown, 4 non-finite
     int it;                // CG iterations done
-    int max_it;
-    int pad;
 };
 
 // ---------------------------------------------------------------- objects
@@ -72,15 +75,18 @@ struct ProfEntry {
 
 struct nn_matrix {
     int64_t n = 0, nnz = 0;
-    int *rowptr = nullptr;     // [n+1]
+    int *rowptr = nullptr;     // CSR pattern [n+1] (boundary format, export)
     int *col = nullptr;        // [nnz]
-    double *val = nullptr;     // K values
-    double *mval = nullptr;    // M values (or null)
+    int64_t nslices = 0, nsell = 0;
+    int *sl_off = nullptr;     // [nslices+1] first entry of each 64-row slice
+    int *sl_col = nullptr;     // [nsell] column of each sliced-ELL entry (padding: own row)
+    double *val = nullptr;     // K values, sliced-ELL order [nsell]
+    double *mval = nullptr;    // M values, sliced-ELL order (or null)
     double *diag = nullptr;    // diag(K)
     double *kt = nullptr;      // M/dt + K values (transient), lazily formed
     double *kt_diag = nullptr;
     double kt_dt = 0.0;
-    int lanes = 16;            // lanes per row of the SpMV kernels
+    int wmax = 0;              // widest slice
     int max_row = 0;
 };
 
@@ -88,8 +94,8 @@ struct nn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    double *partials = nullptr;      // [kMaxBlocks * kMaxRed]
-    unsigned *ticket = nullptr;
+    double *partials = nullptr;      // [kSlots][kMaxBlocks][kMaxRed]
+    double *h_part = nullptr;        // pinned host copy of one slot
     nnqp::DevScalars *scal = nullptr;
     nnqp::DevScalars *h_scal = nullptr;  // pinned mirror
     nnqp::Workspace ws;
@@ -115,7 +121,15 @@ nn_status fail(nn_ctx *ctx, nn_status st, const std::string &msg);
     } while (0)
 
 nn_status ensure_workspace(nn_ctx *ctx, int64_t n);
+// Sliced-ELL offsets of a CSR pattern: off[s] for s = 0..nslices, widest slice.
+void sell_offsets(const int64_t *rowptr, int64_t n, std::vector<int64_t> &off, int &wmax);
+// Device CSR values (ordered by rowptr) -> sliced-ELL arrays of A (col, vals, diag).
+nn_status sell_build(nn_ctx *ctx, nn_matrix *A, const int64_t *rowptr_host, const double *csr_val,
+                     const double *csr_mval);
 nn_status read_scalars(nn_ctx *ctx);
+// Combine the host-slot partials of the last reduction kernel over n rows;
+// ops[k] is OP_SUM / OP_MIN / OP_MAX for value k.
+nn_status host_reduce(nn_ctx *ctx, int64_t n, int nv, const int *ops, double *out);
 
 // profiling around launches of a kernel class
 void prof_begin(nn_ctx *ctx, int cls, double bytes);
@@ -123,27 +137,32 @@ void prof_end(nn_ctx *ctx);
 void prof_collect(nn_ctx *ctx);
 
 // ---------------------------------------------------------------- kernel launchers
-// (kernels.hip).  All launch on ctx->stream with the partition of the matrix.
+// (kernels.hip).  All launch on ctx->stream with the partition of the rows.
+// Kernels marked [host] leave partials for host_reduce; their value lists
+// are given in order.
 enum { KC_CG_SPMV = 0, KC_CG_UPDATE = 1, KC_GRAD = 2, KC_TRIAL = 3, KC_OTHER = 4 };
 
 void launch_matvec(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *x, double *y);
-// c: init (mode 0: c = c0v; mode 1: c = P(c)); reduce over f: |f|^2, max f, #nonfinite(f), #nonfinite(c)
+// [host] c = c0v (mode 0) or P(c) (mode 1); |f|^2 sum, max f, #nonfinite f sum, #nonfinite c sum
 void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v);
-// g = A c - f; reduce |pg|^2, #nonfinite, ||min(c,g)||_inf, min c, #zero
+// [host] g = A c - f; |pg|^2 sum, #nonfinite sum, ||min(c,g)||_inf max, min c min, #(c==0) sum
 void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
                  const double *f, double *g);
-// s = P(c + t d) - c gathered; ks = A s; reduce g.s, s.As, s.s (rows with mask == 0 skipped if mask)
+// [host] s = P(c + t d) - c gathered, ks = A s; g.s, s.As, s.s (sums); rows with mask == 0 skipped
 void launch_trial(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
                   const double *d, double t, const double *g, const uint8_t *mask, double *ks);
 // c = P(c + t d)
 void launch_apply(nn_ctx *ctx, int64_t n, double *c, const double *d, double t);
-// CG set-up on the free set of (c, g + ks): see kernels.hip
+// CG set-up on the face of (c, g + ks); partials of r.z, r.r, #free, nnz(free) in SLOT_U0
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, double rtol, int max_it);
-void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *p_old,
-                    double *p_new);
-void launch_cg_update(nn_ctx *ctx, int64_t n, const double *p);
-// reduce over free rows: min_{w<0} c/(-w), g.w, w.w
+                     double *g, const double *ks);
+// CG iteration j: direction update + matrix pass (prologue: scalars from the
+// previous kernel's partials)
+void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const double *vals, int j, int max_it,
+                    double rtol);
+// CG iteration j: vector update
+void launch_cg_update(nn_ctx *ctx, int64_t n, int j);
+// [host] min over w<0 of c/(-w) min, g.w sum, w.w sum
 void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, const double *w, const double *g);
 // active = (c == 0)
 void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active);
@@ -151,6 +170,8 @@ void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active);
 void launch_axpby_vals(nn_ctx *ctx, int64_t nnz, const double *m, double dt, const double *k,
                        double *out);
 void launch_diag(nn_ctx *ctx, const nn_matrix *A, const double *vals, double *diag);
+// csr -> sliced-ELL: col, values (and capacity values), diag
+void launch_csr_to_sell(nn_ctx *ctx, nn_matrix *A, const double *csr_val, const double *csr_mval);
 // ft = f + (M c)/dt, fused SpMV
 void launch_transient_rhs(nn_ctx *ctx, const nn_matrix *A, const double *c, const double *f,
                           double dt, double *ft);
@@ -164,7 +185,6 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag,
                      const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st);
 
-int choose_lanes(double avg_row);
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);
 
 }  // namespace nnqp

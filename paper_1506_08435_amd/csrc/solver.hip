@@ -71,15 +71,21 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     const Bytes B{(double)n, (double)A->nnz};
     const double tol = o->tol;
 
+    static const int kInitOps[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
+    static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
+    static const int kTrialOps[3] = {OP_SUM, OP_SUM, OP_SUM};
+    static const int kBrkOps[3] = {OP_MIN, OP_SUM, OP_SUM};
+    double red[kMaxRed];
+
     // ---- start point and load statistics
     prof_begin(ctx, KC_OTHER, 16.0 * n);
     launch_init(ctx, n, c, f, o->c0_mode == 1 ? 1 : 0, o->c0_value);
     prof_end(ctx);
-    if ((rc = read_scalars(ctx)) != NN_OK) return rc;
+    if ((rc = host_reduce(ctx, n, 4, kInitOps, red)) != NN_OK) return rc;
     S.bytes_moved += 16.0 * n;
-    const double normf = std::sqrt(H.red[0]), fmax = H.red[1];
+    const double normf = std::sqrt(red[0]), fmax = red[1];
     S.norm_f = normf;
-    if (H.red[2] != 0.0 || H.red[3] != 0.0)
+    if (red[2] != 0.0 || red[3] != 0.0)
         return finish(fail(ctx, NN_ENONFINITE, "non-finite value in f or the initial c"));
     if (!(fmax > 0.0)) {
         // f <= 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0.
@@ -101,12 +107,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         prof_end(ctx);
         S.spmvs++;
         S.bytes_moved += B.spmv() + 16.0 * n;
-        if ((rc = read_scalars(ctx)) != NN_OK) return rc;
-        if (H.red[1] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite gradient"));
-        S.kkt_rel = std::sqrt(H.red[0]) / normf;
-        S.kkt_nat_inf = H.red[2];
-        S.min_c = H.red[3];
-        S.n_active = (int32_t)H.red[4];
+        if ((rc = host_reduce(ctx, n, 5, kGradOps, red)) != NN_OK) return rc;
+        if (red[1] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite gradient"));
+        S.kkt_rel = std::sqrt(red[0]) / normf;
+        S.kkt_nat_inf = red[2];
+        S.min_c = red[3];
+        S.n_active = (int32_t)red[4];
         S.outer_its = outer;
         if (S.kkt_rel <= tol) {
             result = NN_OK;
@@ -127,10 +133,10 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             S.spmvs++;
             S.cauchy_trials++;
             S.bytes_moved += B.spmv() + 16.0 * n;
-            nn_status r2 = read_scalars(ctx);
-            gs = H.red[0];
-            sks = H.red[1];
-            ss = H.red[2];
+            nn_status r2 = host_reduce(ctx, n, 3, kTrialOps, red);
+            gs = red[0];
+            sks = red[1];
+            ss = red[2];
             return r2;
         };
         auto ok_decrease = [&](double gs, double sks, double ss) {
@@ -173,27 +179,25 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
 
         // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], o->inner_rtol, o->max_cg);
+        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur]);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
-        double *pa = W.p0, *pb = W.p1;
-        int it_seen = 0;
+        int it_seen = 0, j_next = 0;
         for (;;) {
             const size_t mark = ctx->prof_live.size();
-            for (int j = 0; j < chunk; j++) {
+            for (int k = 0; k < chunk; k++, j_next++) {
                 prof_begin(ctx, KC_CG_SPMV, -1.0);
-                launch_cg_spmv(ctx, A, vals, pa, pb);
+                launch_cg_spmv(ctx, A, vals, j_next, o->max_cg, o->inner_rtol);
                 prof_end(ctx);
                 prof_begin(ctx, KC_CG_UPDATE, -1.0);
-                launch_cg_update(ctx, n, pb);
+                launch_cg_update(ctx, n, j_next);
                 prof_end(ctx);
-                std::swap(pa, pb);
             }
             if ((rc = read_scalars(ctx)) != NN_OK) return rc;
             const int ran = H.it - it_seen;
             // byte model of the launches that did work; the rest exited at once
             const double nf = H.n_free, nzf = H.nnz_free;
-            const double b_spmv = 4.0 * (n + 1) + n + 12.0 * nzf + 32.0 * nf;
+            const double b_spmv = n + 12.0 * nzf + 44.0 * nf;
             const double b_upd = n + 64.0 * nf;
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
@@ -209,16 +213,14 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         S.cg_its += it_seen;
         if (H.done == 4) return finish(fail(ctx, NN_ENONFINITE, "non-finite value in CG"));
         if (H.done == 3) return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature in CG"));
-        // After an even number of iterations the last direction is in pa's twin;
-        // the solution w does not depend on it.
 
         // ---- 4. projected search along w
         prof_begin(ctx, KC_OTHER, 24.0 * n);
         launch_breakpoint(ctx, n, c, W.w, W.g);
         prof_end(ctx);
         S.bytes_moved += 24.0 * n;
-        if ((rc = read_scalars(ctx)) != NN_OK) return rc;
-        const double bmin = H.red[0], gw = H.red[1], wn = std::sqrt(H.red[2]);
+        if ((rc = host_reduce(ctx, n, 3, kBrkOps, red)) != NN_OK) return rc;
+        const double bmin = red[0], gw = red[1], wn = std::sqrt(red[2]);
         if (it_seen > 0 && gw < 0.0 && wn > 0.0) {
             double tmax = std::min(1.0, delta / wn);
             double ts = tmax;
@@ -230,8 +232,8 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                     S.spmvs++;
                     S.search_trials++;
                     S.bytes_moved += B.spmv() + 16.0 * n;
-                    if ((rc = read_scalars(ctx)) != NN_OK) return rc;
-                    const double g2 = H.red[0], s2 = H.red[1];
+                    if ((rc = host_reduce(ctx, n, 3, kTrialOps, red)) != NN_OK) return rc;
+                    const double g2 = red[0], s2 = red[1];
                     if (g2 < 0.0 && g2 + 0.5 * s2 <= kMu0 * g2) break;
                     ts *= kBack;
                     if (ts <= bmin) {

@@ -72,6 +72,10 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime under the same soname as /opt/rocm's; it
+    # must be loaded first so that this library binds to the runtime that owns
+    # torch's device memory and streams (one runtime per process).
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run __graft_entry__.build() or paper_1506_08435_amd/build.py)")
