@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=64, help="cube side of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--verbose", action="store_true", help="per-outer-iteration trace on stderr")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -91,7 +92,7 @@ def main():
     ctx = nnqp.Context(0)
     K, F, _ = ctx.assemble(p)
     n = K.n
-    opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol)
+    opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, verbose=int(args.verbose))
     c = torch.empty(n, dtype=torch.float64, device=ctx.device)
     for _ in range(args.warmup):
         ctx.solve_nonneg(K, F, opts=opts, c=c)

@@ -88,7 +88,7 @@ typedef struct {
                              (default).  The model is the objective itself, so the
                              radius only ever grows. */
     int32_t cg_chunk;     /* CG iterations enqueued between convergence reads; default 16 */
-    int32_t reserved;
+    int32_t verbose;      /* 1: one line per outer iteration on stderr; default 0 */
 } nn_opts;
 
 /* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */

@@ -25,6 +25,7 @@
 //      caller gives one) grows by 4x whenever a step reaches it.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "nnqp_internal.hpp"
@@ -250,6 +251,11 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                 step_norm += ts * wn;
             }
         }
+        if (o->verbose)
+            std::fprintf(stderr,
+                         "nnqp outer %3d kkt %.3e active %d free %.0f cauchy t %.3g cg %d "
+                         "breakpoint %.3g step %.3e\n",
+                         outer, S.kkt_rel, S.n_active, H.n_free, t_cauchy, it_seen, bmin, step_norm);
         // ---- 5. radius update (exact model: ratio one)
         if (std::isfinite(delta) && step_norm >= 0.99 * delta) delta *= 4.0;
     }

@@ -48,7 +48,7 @@ class Opts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("max_cg", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("c0_mode", ctypes.c_int32),
                 ("c0_value", ctypes.c_double), ("delta0", ctypes.c_double),
-                ("cg_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cg_chunk", ctypes.c_int32), ("verbose", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
