@@ -178,10 +178,14 @@ nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_
  *             with c_i >= 0 exactly (projection writes +0.0).
  *   active_dev device [n] uint8 or NULL; out: 1 where c_i == 0.
  *   stats     host or NULL.
+ * With opts->precision == NN_MIXED the Cauchy and projected searches and the
+ * inner CG run on float32 copies of the values with float32 CG vectors, while
+ * every outer iteration re-evaluates the float64 residual g = K c - f that
+ * decides convergence; the first mixed solve attaches the float32 copy to K.
  * Returns NN_EMAXIT (c feasible, stats filled) if max_outer is reached before
  * ||pg|| <= tol ||f||; NN_ENONFINITE if a non-finite value appears.
  */
-nn_status nn_solve_nonneg(nn_ctx *ctx, const nn_matrix *K, const double *f_dev,
+nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
                           const nn_opts *opts, double *c_dev, uint8_t *active_dev,
                           nn_stats *stats);
 

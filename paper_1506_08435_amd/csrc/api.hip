@@ -26,6 +26,12 @@ nn_status ensure_workspace(nn_ctx *ctx, int64_t n)
             (void)hipFree(*v);
             *v = nullptr;
         }
+    float **fv[] = {&W.w32, &W.r32, &W.z32, &W.q32, &W.p32, &W.dm32};
+    for (float **v : fv)
+        if (*v) {
+            (void)hipFree(*v);
+            *v = nullptr;
+        }
     if (W.mask) (void)hipFree(W.mask);
     W.mask = nullptr;
     W.cap = 0;
@@ -35,6 +41,11 @@ nn_status ensure_workspace(nn_ctx *ctx, int64_t n)
         if (e != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
     }
     if (hipMalloc(&W.mask, cap) != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
+    float **fvecs[] = {&W.w32, &W.r32, &W.z32, &W.q32, &W.p32, &W.dm32};
+    for (float **v : fvecs) {
+        hipError_t e = hipMalloc(v, sizeof(float) * cap);
+        if (e != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
+    }
     W.cap = cap;
     return NN_OK;
 }
@@ -169,6 +180,9 @@ void nn_destroy(nn_ctx *ctx)
     Workspace &W = ctx->ws;
     double *vecs[] = {W.g, W.w, W.r, W.z, W.q, W.p0, W.p1, W.ks0, W.ks1, W.dm, W.ft};
     for (double *v : vecs)
+        if (v) (void)hipFree(v);
+    float *fvecs[] = {W.w32, W.r32, W.z32, W.q32, W.p32, W.dm32};
+    for (float *v : fvecs)
         if (v) (void)hipFree(v);
     if (W.mask) (void)hipFree(W.mask);
     if (ctx->partials) (void)hipFree(ctx->partials);
@@ -358,6 +372,9 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
     for (double *p : dv)
         if (p) (void)hipFree(p);
+    float *fv[] = {A->val32, A->kt32};
+    for (float *p : fv)
+        if (p) (void)hipFree(p);
     delete A;
 }
 
@@ -387,15 +404,24 @@ static nn_status check_opts(nn_ctx *ctx, const nn_opts *o)
     return NN_OK;
 }
 
-nn_status nn_solve_nonneg(nn_ctx *ctx, const nn_matrix *K, const double *f_dev,
+nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
                           const nn_opts *opts, double *c_dev, uint8_t *active_dev, nn_stats *stats)
 {
     NN_CHECK_CTX(ctx);
     if (!K || (K->n > 0 && (!f_dev || !c_dev))) return fail(ctx, NN_EINVAL, "null argument");
     nn_status st = check_opts(ctx, opts);
     if (st != NN_OK) return st;
-    if (opts->precision != NN_FP64) return fail(ctx, NN_EINVAL, "precision not available");
-    return solve_impl(ctx, K, K->val, K->diag, f_dev, opts, c_dev, active_dev, stats);
+    const float *v32 = nullptr;
+    if (opts->precision == NN_MIXED && K->n > 0) {
+        if (!K->val32) {
+            if (hipMalloc(&K->val32, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
+                return fail(ctx, NN_EOOM, "float32 value allocation");
+            launch_to_f32(ctx, K->nsell, K->val, K->val32);
+            NN_HIP_TRY(ctx, hipGetLastError());
+        }
+        v32 = K->val32;
+    }
+    return solve_impl(ctx, K, K->val, v32, K->diag, f_dev, opts, c_dev, active_dev, stats);
 }
 
 nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *f_dev,
@@ -408,17 +434,21 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NN_EINVAL, "dt must be > 0");
     nn_status st = check_opts(ctx, opts);
     if (st != NN_OK) return st;
-    if (opts->precision != NN_FP64) return fail(ctx, NN_EINVAL, "precision not available");
     const int64_t n = K->n;
-    if (n == 0) return solve_impl(ctx, K, K->val, K->diag, f_dev, opts, c_dev, active_dev, stats);
-    if (!K->kt || K->kt_dt != dt) {
+    const bool mixed = opts->precision == NN_MIXED;
+    if (n == 0) return solve_impl(ctx, K, K->val, nullptr, K->diag, f_dev, opts, c_dev, active_dev, stats);
+    if (!K->kt || K->kt_dt != dt || (mixed && !K->kt32)) {
         if (!K->kt) {
             if (hipMalloc(&K->kt, sizeof(double) * std::max<int64_t>(K->nsell, 1)) != hipSuccess ||
                 hipMalloc(&K->kt_diag, sizeof(double) * n) != hipSuccess)
                 return fail(ctx, NN_EOOM, "transient matrix allocation");
         }
+        if (mixed && !K->kt32 &&
+            hipMalloc(&K->kt32, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
+            return fail(ctx, NN_EOOM, "transient float32 allocation");
         launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
         launch_diag(ctx, K, K->kt, K->kt_diag);
+        if (K->kt32) launch_to_f32(ctx, K->nsell, K->kt, K->kt32);
         NN_HIP_TRY(ctx, hipGetLastError());
         K->kt_dt = dt;
     }
@@ -426,7 +456,8 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     launch_transient_rhs(ctx, K, c_dev, f_dev, dt, ctx->ws.ft);
     nn_opts o = *opts;
     o.c0_mode = 1;   // warm start from c^(n)
-    return solve_impl(ctx, K, K->kt, K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev, stats);
+    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, K->kt_diag, ctx->ws.ft, &o, c_dev,
+                      active_dev, stats);
 }
 
 nn_status nn_set_profiling(nn_ctx *ctx, int on)

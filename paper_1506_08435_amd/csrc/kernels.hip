@@ -140,47 +140,98 @@ __device__ __forceinline__ void for_rows(const Part &P, Body body)
 
 // Sliced-ELL product row by row: for each owned row i with active(i), the sum
 // over the row's entries k = 0..w-1 (column order) of val * x(col), then
-// epi(i, sum).  Padding entries have value 0 and column i.  Entries are
-// loaded eight at a time, all eight before their gathers (enough loads in
-// flight per lane while staying under 64 VGPRs, i.e. 8 waves per SIMD);
-// slices wider than WMAX finish in a plain loop.
-template <int WMAX, class Act, class X, class Epi>
+// epi(i, sum, pre(i)).  Padding entries have value 0 and column i.
+// The SpMV passes are latency-bound (each slice is a chain: offsets ->
+// indices/values -> gathers -> own-row data -> stores), so a wavefront keeps
+// NS slices in flight at once, issues the slice offsets and the own-row loads
+// of pre() before any gather, and loads entries eight at a time (all eight
+// before their gathers, which keeps the kernels under 64 VGPRs).  Slices wider
+// than WMAX finish in a plain loop.
+#ifndef NNQP_SLICES_IN_FLIGHT
+#define NNQP_SLICES_IN_FLIGHT 1
+#endif
+#ifndef NNQP_LOAD_PHASE
+#define NNQP_LOAD_PHASE 8
+#endif
+template <int WMAX, class VT, class Act, class Pre, class X, class Epi>
 __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__ so,
                                           const int *__restrict__ sc,
-                                          const double *__restrict__ sv, Act active, X x, Epi epi)
+                                          const VT *__restrict__ sv, Act active, Pre pre, X x,
+                                          Epi epi)
 {
+    constexpr int NS = NNQP_SLICES_IN_FLIGHT;
+    using PV = decltype(pre(0));
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = P.nb * kWaves;
-    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += nw) {
-        const int i = s * kSlice + lane;
-        const bool act = i < P.n && active(i);
-        if (__ballot(act) == 0) continue;
-        const int off = so[s];
-        const int w = (so[s + 1] - off) / kSlice;
-        double acc = 0.0;
-        constexpr int H = WMAX < 8 ? WMAX : 8;
+    for (int s0 = blockIdx.x * kWaves + wid; s0 < P.nslices; s0 += NS * nw) {
+        int off[NS], w[NS], row[NS];
+        bool act[NS];
+        PV pv[NS];
+#pragma unroll
+        for (int t = 0; t < NS; t++) {
+            const int s = s0 + t * nw;
+            const bool has = s < P.nslices;
+            off[t] = has ? so[s] : 0;
+            w[t] = has ? (so[s + 1] - off[t]) >> 6 : 0;   // slice width (uniform in the wave)
+            row[t] = s * kSlice + lane;
+            act[t] = has && row[t] < P.n && active(row[t]);
+            pv[t] = act[t] ? pre(row[t]) : PV();
+        }
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < NS; t++) any = any || (__ballot(act[t]) != 0);
+        if (!any) continue;
+        // Every lane of a live slice loads and gathers under the wave-uniform
+        // test k < w: padding and inactive rows hold valid columns, so this
+        // stays in bounds, and their sums are discarded below.  Per-lane
+        // predication here would cost more issue slots than the bytes saved.
+        double acc[NS];
+#pragma unroll
+        for (int t = 0; t < NS; t++) acc[t] = 0.0;
+        constexpr int H = WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE;
 #pragma unroll
         for (int h0 = 0; h0 < WMAX; h0 += H) {
-            int cc[H];
-            double vv[H];
+            int cc[NS][H];
+            VT vv[NS][H];
 #pragma unroll
-            for (int k = 0; k < H; k++) {
-                const bool h = act && h0 + k < w;
-                cc[k] = h ? sc[off + (h0 + k) * kSlice + lane] : 0;
-                vv[k] = h ? sv[off + (h0 + k) * kSlice + lane] : 0.0;
-            }
+            for (int t = 0; t < NS; t++)
 #pragma unroll
-            for (int k = 0; k < H; k++)
-                if (act && h0 + k < w) acc += vv[k] * x(cc[k]);
+                for (int k = 0; k < H; k++) {
+                    if (h0 + k < w[t]) {
+                        cc[t][k] = sc[off[t] + (h0 + k) * kSlice + lane];
+                        vv[t][k] = sv[off[t] + (h0 + k) * kSlice + lane];
+                    } else {
+                        cc[t][k] = 0;
+                        vv[t][k] = VT(0);
+                    }
+                }
+#pragma unroll
+            for (int t = 0; t < NS; t++)
+#pragma unroll
+                for (int k = 0; k < H; k++)
+                    if (h0 + k < w[t]) acc[t] += (double)vv[t][k] * x(cc[t][k]);
         }
-        if (act)
-            for (int k = WMAX; k < w; k++) {
-                const int e = off + k * kSlice + lane;
-                acc += sv[e] * x(sc[e]);
+#pragma unroll
+        for (int t = 0; t < NS; t++) {
+            for (int k = WMAX; k < w[t]; k++) {
+                const int e = off[t] + k * kSlice + lane;
+                acc[t] += (double)sv[e] * x(sc[e]);
             }
-        if (act) epi(i, acc);
+            if (act[t]) epi(row[t], acc[t], pv[t]);
+        }
     }
 }
+
+struct NoPre {
+    __device__ __forceinline__ int operator()(int) const { return 0; }
+};
+
+struct Two {
+    double a, b;
+};
+struct Three {
+    double a, b, c;
+};
 
 struct AllRows {
     __device__ __forceinline__ bool operator()(int) const { return true; }
@@ -195,8 +246,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec(Part P, const int *__restrict
                                                    const double *__restrict__ v,
                                                    const double *__restrict__ x, double *__restrict__ y)
 {
-    sell_rows<WMAX>(P, so, sc, v, AllRows(), [&](int j) { return x[j]; },
-                    [&](int i, double s) { y[i] = s; });
+    sell_rows<WMAX>(P, so, sc, v, AllRows(), NoPre(), [&](int j) { return x[j]; },
+                    [&](int i, double s, int) { y[i] = s; });
 }
 
 // ft = f + (M c) / dt
@@ -208,8 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_transient_rhs(Part P, const int *__r
                                                           const double *__restrict__ f, double dt,
                                                           double *__restrict__ ft)
 {
-    sell_rows<WMAX>(P, so, sc, m, AllRows(), [&](int j) { return c[j]; },
-                    [&](int i, double s) { ft[i] = f[i] + s / dt; });
+    sell_rows<WMAX>(P, so, sc, m, AllRows(), [&](int i) { return f[i]; },
+                    [&](int j) { return c[j]; },
+                    [&](int i, double s, double fi) { ft[i] = fi + s / dt; });
 }
 
 // g = K c - f with the projected-gradient report:
@@ -226,9 +278,10 @@ __global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__
 {
     double a[5];
     red_init<kOpsGrad, 5>(a);
-    sell_rows<WMAX>(P, so, sc, v, AllRows(), [&](int j) { return c[j]; }, [&](int i, double s) {
-        const double gi = s - f[i];
-        const double cv = c[i];
+    sell_rows<WMAX>(P, so, sc, v, AllRows(), [&](int i) { return Two{c[i], f[i]}; },
+                    [&](int j) { return c[j]; }, [&](int i, double s, Two cf) {
+        const double gi = s - cf.b;
+        const double cv = cf.a;
         g[i] = gi;
         const double pg = cv > 0.0 ? gi : (gi < 0.0 ? gi : 0.0);
         a[0] += pg * pg;
@@ -245,27 +298,27 @@ __global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__
 // skipped when a mask is given (there d = 0, so s = 0 and they add nothing).
 constexpr uint32_t kOpsTrial = OPS3(OP_SUM, OP_SUM, OP_SUM);
 
-template <int WMAX>
+template <int WMAX, class VT, class VD>
 __global__ __launch_bounds__(kBlock) void k_trial(Part P, const int *__restrict__ so,
                                                   const int *__restrict__ sc,
-                                                  const double *__restrict__ v,
+                                                  const VT *__restrict__ v,
                                                   const double *__restrict__ c,
-                                                  const double *__restrict__ d, double t,
+                                                  const VD *__restrict__ d, double t,
                                                   const double *__restrict__ g,
                                                   const uint8_t *__restrict__ mask,
                                                   double *__restrict__ ks, double *partials)
 {
     auto sv = [&](int j) {
         const double cj = c[j];
-        return proj0(cj + t * d[j]) - cj;
+        return proj0(cj + t * (double)d[j]) - cj;
     };
     double a[3];
     red_init<kOpsTrial, 3>(a);
-    sell_rows<WMAX>(P, so, sc, v, [&](int i) { return mask == nullptr || mask[i] != 0; }, sv,
-                    [&](int i, double s) {
+    sell_rows<WMAX>(P, so, sc, v, [&](int i) { return mask == nullptr || mask[i] != 0; },
+                    [&](int i) { return Two{sv(i), g[i]}; }, sv, [&](int i, double s, Two sg) {
                         if (ks) ks[i] = s;
-                        const double si = sv(i);
-                        a[0] += g[i] * si;
+                        const double si = sg.a;
+                        a[0] += sg.b * si;
                         a[1] += si * s;
                         a[2] += si * si;
                     });
@@ -273,11 +326,12 @@ __global__ __launch_bounds__(kBlock) void k_trial(Part P, const int *__restrict_
 }
 
 // c = P(c + t d)
+template <class VD>
 __global__ __launch_bounds__(kBlock) void k_apply(Part P, double *__restrict__ c,
-                                                  const double *__restrict__ d, double t)
+                                                  const VD *__restrict__ d, double t)
 {
     for_rows(P, [&](int i, bool act) {
-        if (act) c[i] = proj0(c[i] + t * d[i]);
+        if (act) c[i] = proj0(c[i] + t * (double)d[i]);
     });
 }
 
@@ -315,12 +369,12 @@ __global__ __launch_bounds__(kBlock) void k_init(Part P, double *__restrict__ c,
 // Partials (SLOT_U0): r.z, r.r, #free, nnz of free rows.
 constexpr uint32_t kOpsU = OPS4(OP_SUM, OP_SUM, OP_SUM, OP_SUM);
 
+template <class VV>
 __global__ __launch_bounds__(kBlock) void k_cg_setup(
     Part P, const int *__restrict__ rp, const double *__restrict__ diag,
     const double *__restrict__ c, double *__restrict__ g, const double *__restrict__ ks,
-    uint8_t *__restrict__ mask, double *__restrict__ dm, double *__restrict__ r,
-    double *__restrict__ z, double *__restrict__ p, double *__restrict__ q,
-    double *__restrict__ w, double *partials, DevScalars *S)
+    uint8_t *__restrict__ mask, VV *__restrict__ dm, VV *__restrict__ r, VV *__restrict__ z,
+    VV *__restrict__ p, VV *__restrict__ q, VV *__restrict__ w, double *partials, DevScalars *S)
 {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for_rows(P, [&](int i, bool act) {
@@ -329,18 +383,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
         if (ks) g[i] = gi;
         const double cv = c[i];
         const bool fr = !(cv == 0.0 && gi >= 0.0);
-        const double dmi = fr ? 1.0 / diag[i] : 0.0;
-        const double ri = fr ? -gi : 0.0;
-        const double zi = dmi * ri;
+        const VV dmi = fr ? (VV)(1.0 / diag[i]) : VV(0);
+        const VV ri = fr ? (VV)(-gi) : VV(0);
+        const VV zi = dmi * ri;
         mask[i] = fr ? 1 : 0;
         dm[i] = dmi;
         r[i] = ri;
         z[i] = zi;
-        p[i] = 0.0;
-        q[i] = 0.0;
-        w[i] = 0.0;
-        a[0] += ri * zi;
-        a[1] += ri * ri;
+        p[i] = VV(0);
+        q[i] = VV(0);
+        w[i] = VV(0);
+        a[0] += (double)ri * (double)zi;
+        a[1] += (double)ri * (double)ri;
         a[2] += fr ? 1.0 : 0.0;
         a[3] += fr ? (double)(rp[i + 1] - rp[i]) : 0.0;
     });
@@ -359,13 +413,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
 // formed together, using K p = K z + beta (K p_old): only z is gathered, and
 // p, q are updated in place on the free rows; partials of p.q into SLOT_Q.
 // Columns outside the free set contribute 0 because z vanishes there.
-template <int WMAX>
+template <int WMAX, class VT, class VV>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restrict__ so,
                                                     const int *__restrict__ sc,
-                                                    const double *__restrict__ v,
+                                                    const VT *__restrict__ v,
                                                     const uint8_t *__restrict__ mask,
-                                                    const double *__restrict__ z,
-                                                    double *__restrict__ p, double *__restrict__ q,
+                                                    const VV *__restrict__ z,
+                                                    VV *__restrict__ p, VV *__restrict__ q,
                                                     double *partials, DevScalars *S, int j,
                                                     int max_it, double rtol2)
 {
@@ -395,12 +449,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restric
     if (done) return;
     double a[1] = {0.0};
     sell_rows<WMAX>(P, so, sc, v, [&](int i) { return mask[i] != 0; },
-                    [&](int jj) { return z[jj]; }, [&](int i, double kz) {
-                        const double pi = fma(beta, p[i], z[i]);
-                        const double qi = fma(beta, q[i], kz);
+                    [&](int i) { return Three{(double)p[i], (double)q[i], (double)z[i]}; },
+                    [&](int jj) { return (double)z[jj]; }, [&](int i, double kz, Three pqz) {
+                        const VV pi = (VV)fma(beta, pqz.a, pqz.c);
+                        const VV qi = (VV)fma(beta, pqz.b, kz);
                         p[i] = pi;
                         q[i] = qi;
-                        a[0] += pi * qi;
+                        a[0] += (double)pi * (double)qi;
                     });
     block_partial<OP_SUM, 1>(a, slot_ptr(partials, SLOT_Q));
 }
@@ -409,12 +464,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restric
 // Prologue: p.q_j from SLOT_Q, alpha_j = r.z_j / p.q_j (r.z_j stored by the
 // matrix pass).  Body: w += alpha p, r -= alpha q, z = dm r; partials of
 // r.z_{j+1}, r.r_{j+1} into slot U[(j+1)%2].
+template <class VV>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__restrict__ mask,
-                                                      const double *__restrict__ p,
-                                                      const double *__restrict__ q,
-                                                      const double *__restrict__ dm,
-                                                      double *__restrict__ w, double *__restrict__ r,
-                                                      double *__restrict__ z, double *partials,
+                                                      const VV *__restrict__ p,
+                                                      const VV *__restrict__ q,
+                                                      const VV *__restrict__ dm,
+                                                      VV *__restrict__ w, VV *__restrict__ r,
+                                                      VV *__restrict__ z, double *partials,
                                                       DevScalars *S, int j)
 {
     if (S->done) return;
@@ -432,13 +488,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__r
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for_rows(P, [&](int i, bool act) {
         if (!act || !mask[i]) return;
-        const double ri = r[i] - alpha * q[i];
-        const double zi = dm[i] * ri;
-        w[i] += alpha * p[i];
+        const VV ri = (VV)((double)r[i] - alpha * (double)q[i]);
+        const VV zi = dm[i] * ri;
+        w[i] = (VV)((double)w[i] + alpha * (double)p[i]);
         r[i] = ri;
         z[i] = zi;
-        a[0] += ri * zi;
-        a[1] += ri * ri;
+        a[0] += (double)ri * (double)zi;
+        a[1] += (double)ri * (double)ri;
     });
     block_partial<kOpsU, 4>(a, slot_ptr(partials, ((j + 1) & 1) ? SLOT_U1 : SLOT_U0));
     if (blockIdx.x == 0 && threadIdx.x == 0) S->it = j + 1;
@@ -448,8 +504,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__r
 // min over w_i < 0 of c_i / (-w_i), g.w, w.w
 constexpr uint32_t kOpsBrk = OPS3(OP_MIN, OP_SUM, OP_SUM);
 
+template <class VV>
 __global__ __launch_bounds__(kBlock) void k_breakpoint(Part P, const double *__restrict__ c,
-                                                       const double *__restrict__ w,
+                                                       const VV *__restrict__ w,
                                                        const double *__restrict__ g,
                                                        double *partials)
 {
@@ -457,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_breakpoint(Part P, const double *__r
     red_init<kOpsBrk, 3>(a);
     for_rows(P, [&](int i, bool act) {
         if (!act) return;
-        const double wi = w[i];
+        const double wi = (double)w[i];
         if (wi < 0.0) a[0] = fmin(a[0], c[i] / (-wi));
         a[1] += g[i] * wi;
         a[2] += wi * wi;
@@ -480,6 +537,15 @@ __global__ __launch_bounds__(kBlock) void k_vals_mdt_plus_k(int64_t nnz, const d
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nnz;
          t += (int64_t)gridDim.x * kBlock)
         out[t] = m[t] / dt + k[t];
+}
+
+// float32 copy of a value array (round to nearest)
+__global__ __launch_bounds__(kBlock) void k_to_f32(int64_t m, const double *__restrict__ a,
+                                                   float *__restrict__ b)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * kBlock)
+        b[t] = (float)a[t];
 }
 
 // diag[i] = entry of row i in column i (sliced-ELL)
@@ -549,16 +615,27 @@ __global__ __launch_bounds__(kBlock) void k_sell_tail(int n, int nslices, const 
 }
 
 // ---------------------------------------------------------------- launchers
+// Instantiate KERNEL for the slice width class of the matrix; KERNEL may be a
+// parenthesised template-id that names the width parameter WM.
 #define NN_DISPATCH_W(wmax, KERNEL, grid, ...)                                             \
-    if ((wmax) <= 8) KERNEL<8><<<grid, kBlock, 0, ctx->stream>>>(__VA_ARGS__);             \
-    else if ((wmax) <= 16) KERNEL<16><<<grid, kBlock, 0, ctx->stream>>>(__VA_ARGS__);      \
-    else KERNEL<32><<<grid, kBlock, 0, ctx->stream>>>(__VA_ARGS__);
+    do {                                                                                   \
+        if ((wmax) <= 8) {                                                                 \
+            constexpr int WM = 8;                                                          \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+        } else if ((wmax) <= 16) {                                                         \
+            constexpr int WM = 16;                                                         \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+        } else {                                                                           \
+            constexpr int WM = 32;                                                         \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+        }                                                                                  \
+    } while (0)
 
 void launch_matvec(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *x, double *y)
 {
     if (A->n == 0) return;
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, k_matvec, P.nb, P, A->sl_off, A->sl_col, vals, x, y);
+    NN_DISPATCH_W(A->wmax, (k_matvec<WM>), P.nb, P, A->sl_off, A->sl_col, vals, x, y);
 }
 
 void launch_transient_rhs(nn_ctx *ctx, const nn_matrix *A, const double *c, const double *f,
@@ -566,7 +643,7 @@ void launch_transient_rhs(nn_ctx *ctx, const nn_matrix *A, const double *c, cons
 {
     if (A->n == 0) return;
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, k_transient_rhs, P.nb, P, A->sl_off, A->sl_col, A->mval, c, f, dt, ft);
+    NN_DISPATCH_W(A->wmax, (k_transient_rhs<WM>), P.nb, P, A->sl_off, A->sl_col, A->mval, c, f, dt, ft);
 }
 
 void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v)
@@ -579,53 +656,90 @@ void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const doub
                  const double *f, double *g)
 {
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, k_grad, P.nb, P, A->sl_off, A->sl_col, vals, c, f, g, ctx->partials);
+    NN_DISPATCH_W(A->wmax, (k_grad<WM>), P.nb, P, A->sl_off, A->sl_col, vals, c, f, g, ctx->partials);
 }
 
-void launch_trial(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
-                  const double *d, double t, const double *g, const uint8_t *mask, double *ks)
+void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
+                  double t, const double *g, const uint8_t *mask, double *ks)
 {
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, k_trial, P.nb, P, A->sl_off, A->sl_col, vals, c, d, t, g, mask, ks,
-                  ctx->partials);
+    if (V.v32) {
+        if (d.f32) {
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float>), P.nb, P, A->sl_off, A->sl_col, V.v32,
+                          c, d.f32, t, g, mask, ks, ctx->partials);
+        } else {
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double>), P.nb, P, A->sl_off, A->sl_col,
+                          V.v32, c, d.f64, t, g, mask, ks, ctx->partials);
+        }
+    } else {
+        NN_DISPATCH_W(A->wmax, (k_trial<WM, double, double>), P.nb, P, A->sl_off, A->sl_col, V.v64,
+                      c, d.f64, t, g, mask, ks, ctx->partials);
+    }
 }
 
-void launch_apply(nn_ctx *ctx, int64_t n, double *c, const double *d, double t)
+void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t)
 {
     Part P = make_part(n);
-    k_apply<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d, t);
+    if (d.f32) k_apply<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d.f32, t);
+    else k_apply<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d.f64, t);
 }
 
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks)
+                     double *g, const double *ks, bool f32)
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
-    k_cg_setup<<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask, W.dm, W.r,
-                                                 W.z, W.p0, W.q, W.w, ctx->partials, ctx->scal);
+    if (f32)
+        k_cg_setup<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
+                                                            W.dm32, W.r32, W.z32, W.p32, W.q32,
+                                                            W.w32, ctx->partials, ctx->scal);
+    else
+        k_cg_setup<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
+                                                             W.dm, W.r, W.z, W.p0, W.q, W.w,
+                                                             ctx->partials, ctx->scal);
 }
 
-void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const double *vals, int j, int max_it,
-                    double rtol)
+void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol)
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
-    NN_DISPATCH_W(A->wmax, k_cg_spmv, P.nb, P, A->sl_off, A->sl_col, vals, W.mask, W.z, W.p0, W.q,
-                  ctx->partials, ctx->scal, j, max_it, rtol * rtol);
+    if (V.v32) {
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float>), P.nb, P, A->sl_off, A->sl_col, V.v32,
+                      W.mask, W.z32, W.p32, W.q32, ctx->partials, ctx->scal, j, max_it, rtol * rtol);
+    } else {
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double>), P.nb, P, A->sl_off, A->sl_col,
+                      V.v64, W.mask, W.z, W.p0, W.q, ctx->partials, ctx->scal, j, max_it,
+                      rtol * rtol);
+    }
 }
 
-void launch_cg_update(nn_ctx *ctx, int64_t n, int j)
+void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32)
 {
     Part P = make_part(n);
     Workspace &W = ctx->ws;
-    k_cg_update<<<P.nb, kBlock, 0, ctx->stream>>>(P, W.mask, W.p0, W.q, W.dm, W.w, W.r, W.z,
-                                                  ctx->partials, ctx->scal, j);
+    if (f32)
+        k_cg_update<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, W.mask, W.p32, W.q32, W.dm32, W.w32,
+                                                             W.r32, W.z32, ctx->partials, ctx->scal, j);
+    else
+        k_cg_update<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, W.mask, W.p0, W.q, W.dm, W.w, W.r,
+                                                              W.z, ctx->partials, ctx->scal, j);
 }
 
-void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, const double *w, const double *g)
+void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g)
 {
     Part P = make_part(n);
-    k_breakpoint<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w, g, ctx->partials);
+    if (w.f32)
+        k_breakpoint<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f32, g, ctx->partials);
+    else
+        k_breakpoint<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f64, g, ctx->partials);
+}
+
+void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b)
+{
+    int64_t nb = (m + kBlock - 1) / kBlock;
+    if (nb > 2048) nb = 2048;
+    if (nb < 1) nb = 1;
+    k_to_f32<<<(int)nb, kBlock, 0, ctx->stream>>>(m, a, b);
 }
 
 void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active)

@@ -61,7 +61,22 @@ struct Workspace {
     double *g = nullptr, *w = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
     double *p0 = nullptr, *p1 = nullptr, *ks0 = nullptr, *ks1 = nullptr, *dm = nullptr;
     double *ft = nullptr;  // transient right-hand side
+    // float32 CG vectors of the mixed-precision inner solve
+    float *w32 = nullptr, *r32 = nullptr, *z32 = nullptr, *q32 = nullptr, *p32 = nullptr,
+          *dm32 = nullptr;
     uint8_t *mask = nullptr;
+};
+
+// Matrix values used by a kernel: float32 when v32 is set, else float64.
+struct Vals {
+    const double *v64 = nullptr;
+    const float *v32 = nullptr;
+};
+
+// A search direction in float64 or float32 (exactly one is set).
+struct Dir {
+    const double *f64 = nullptr;
+    const float *f32 = nullptr;
 };
 
 struct ProfEntry {
@@ -86,6 +101,8 @@ struct nn_matrix {
     double *kt = nullptr;      // M/dt + K values (transient), lazily formed
     double *kt_diag = nullptr;
     double kt_dt = 0.0;
+    float *val32 = nullptr;    // float32 K values (mixed precision), lazily formed
+    float *kt32 = nullptr;     // float32 M/dt + K values, formed with kt
     int wmax = 0;              // widest slice
     int max_row = 0;
 };
@@ -149,21 +166,23 @@ void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, d
 void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
                  const double *f, double *g);
 // [host] s = P(c + t d) - c gathered, ks = A s; g.s, s.As, s.s (sums); rows with mask == 0 skipped
-void launch_trial(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
-                  const double *d, double t, const double *g, const uint8_t *mask, double *ks);
+void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
+                  double t, const double *g, const uint8_t *mask, double *ks);
 // c = P(c + t d)
-void launch_apply(nn_ctx *ctx, int64_t n, double *c, const double *d, double t);
-// CG set-up on the face of (c, g + ks); partials of r.z, r.r, #free, nnz(free) in SLOT_U0
+void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t);
+// CG set-up on the face of (c, g + ks); partials of r.z, r.r, #free, nnz(free) in SLOT_U0;
+// f32 selects the float32 CG vectors
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks);
+                     double *g, const double *ks, bool f32);
 // CG iteration j: direction update + matrix pass (prologue: scalars from the
-// previous kernel's partials)
-void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const double *vals, int j, int max_it,
-                    double rtol);
+// previous kernel's partials); float32 values and vectors when V.v32 is set
+void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol);
 // CG iteration j: vector update
-void launch_cg_update(nn_ctx *ctx, int64_t n, int j);
+void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32);
 // [host] min over w<0 of c/(-w) min, g.w sum, w.w sum
-void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, const double *w, const double *g);
+void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g);
+// b = (float)a
+void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b);
 // active = (c == 0)
 void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active);
 // out = m/dt + k
@@ -182,8 +201,11 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
                         int with_mass, nn_matrix **K_out, double *F_dev, int64_t *dof_of_node);
 
 // ---------------------------------------------------------------- solver (solver.hip)
-nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag,
-                     const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st);
+// vals: float64 values (gradient, always); vals32: float32 values for the
+// searches and the inner CG (mixed precision) or null.
+nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
+                     const double *diag, const double *f, const nn_opts *o, double *c,
+                     uint8_t *active, nn_stats *st);
 
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);
 

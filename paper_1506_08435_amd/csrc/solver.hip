@@ -45,8 +45,9 @@ struct Bytes {
 };
 }  // namespace
 
-nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag,
-                     const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st)
+nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
+                     const double *diag, const double *f, const nn_opts *o, double *c,
+                     uint8_t *active, nn_stats *st)
 {
     const int64_t n = A->n;
     nn_stats S;
@@ -71,6 +72,20 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     DevScalars &H = *ctx->h_scal;
     const Bytes B{(double)n, (double)A->nnz};
     const double tol = o->tol;
+    // Mixed precision: the searches and the inner CG use float32 values (and
+    // float32 CG vectors); the gradient g = K c - f that decides convergence,
+    // the KKT report and all reductions stay float64, so the fixed point is
+    // the float64 KKT point.
+    const bool mixed = vals32 != nullptr;
+    Vals VS;
+    if (mixed) VS.v32 = vals32;
+    else VS.v64 = vals;
+    const double vb = mixed ? 4.0 : 8.0;                  // bytes per vector entry in CG
+    const double spmv_s = 4.0 * (n + 1) + (4.0 + (mixed ? 4.0 : 8.0)) * A->nnz + 16.0 * n;
+    Dir dir_g, dir_w;
+    dir_g.f64 = W.g;
+    if (mixed) dir_w.f32 = W.w32;
+    else dir_w.f64 = W.w;
 
     static const int kInitOps[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
     static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
@@ -115,6 +130,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         S.min_c = red[3];
         S.n_active = (int32_t)red[4];
         S.outer_its = outer;
+        if (mixed) S.refinements = outer + 1;   // float64 residual evaluations
         if (S.kkt_rel <= tol) {
             result = NN_OK;
             break;
@@ -128,12 +144,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         double *ksbuf[2] = {W.ks0, W.ks1};
         int cur = 0;
         auto trial_cauchy = [&](double t, int buf, double &gs, double &sks, double &ss) -> nn_status {
-            prof_begin(ctx, KC_TRIAL, B.spmv() + 16.0 * n);
-            launch_trial(ctx, A, vals, c, W.g, -t, W.g, nullptr, ksbuf[buf]);
+            prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
+            launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ksbuf[buf]);
             prof_end(ctx);
             S.spmvs++;
             S.cauchy_trials++;
-            S.bytes_moved += B.spmv() + 16.0 * n;
+            S.bytes_moved += spmv_s + 16.0 * n;
             nn_status r2 = host_reduce(ctx, n, 3, kTrialOps, red);
             gs = red[0];
             sks = red[1];
@@ -173,14 +189,14 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         }
         t_cauchy = t;
         prof_begin(ctx, KC_OTHER, 24.0 * n);
-        launch_apply(ctx, n, c, W.g, -t);
+        launch_apply(ctx, n, c, dir_g, -t);
         prof_end(ctx);
         S.bytes_moved += 24.0 * n;
         double step_norm = std::sqrt(ss);
 
         // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur]);
+        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], mixed);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
         int it_seen = 0, j_next = 0;
@@ -188,18 +204,20 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             const size_t mark = ctx->prof_live.size();
             for (int k = 0; k < chunk; k++, j_next++) {
                 prof_begin(ctx, KC_CG_SPMV, -1.0);
-                launch_cg_spmv(ctx, A, vals, j_next, o->max_cg, o->inner_rtol);
+                launch_cg_spmv(ctx, A, VS, j_next, o->max_cg, o->inner_rtol);
                 prof_end(ctx);
                 prof_begin(ctx, KC_CG_UPDATE, -1.0);
-                launch_cg_update(ctx, n, j_next);
+                launch_cg_update(ctx, n, j_next, mixed);
                 prof_end(ctx);
             }
             if ((rc = read_scalars(ctx)) != NN_OK) return rc;
             const int ran = H.it - it_seen;
             // byte model of the launches that did work; the rest exited at once
             const double nf = H.n_free, nzf = H.nnz_free;
-            const double b_spmv = n + 12.0 * nzf + 44.0 * nf;
-            const double b_upd = n + 64.0 * nf;
+            // matrix pass on the free rows (indices 4 B, values 8 or 4 B), z gathered,
+            // p and q read and written; update: p, q, dm, w, r read, w, r, z written
+            const double b_spmv = n + 4.0 * nf + (4.0 + (mixed ? 4.0 : 8.0)) * nzf + 5.0 * vb * nf;
+            const double b_upd = n + 8.0 * vb * nf;
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
                 const int idx = (int)(e - mark) / 2;
@@ -217,7 +235,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
 
         // ---- 4. projected search along w
         prof_begin(ctx, KC_OTHER, 24.0 * n);
-        launch_breakpoint(ctx, n, c, W.w, W.g);
+        launch_breakpoint(ctx, n, c, dir_w, W.g);
         prof_end(ctx);
         S.bytes_moved += 24.0 * n;
         if ((rc = host_reduce(ctx, n, 3, kBrkOps, red)) != NN_OK) return rc;
@@ -227,12 +245,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             double ts = tmax;
             if (bmin < tmax) {
                 for (int k = 0; k < kMaxTrials; k++) {
-                    prof_begin(ctx, KC_TRIAL, B.spmv() + 16.0 * n);
-                    launch_trial(ctx, A, vals, c, W.w, ts, W.g, W.mask, nullptr);
+                    prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
+                    launch_trial(ctx, A, VS, c, dir_w, ts, W.g, W.mask, nullptr);
                     prof_end(ctx);
                     S.spmvs++;
                     S.search_trials++;
-                    S.bytes_moved += B.spmv() + 16.0 * n;
+                    S.bytes_moved += spmv_s + 16.0 * n;
                     if ((rc = host_reduce(ctx, n, 3, kTrialOps, red)) != NN_OK) return rc;
                     const double g2 = red[0], s2 = red[1];
                     if (g2 < 0.0 && g2 + 0.5 * s2 <= kMu0 * g2) break;
@@ -245,7 +263,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             }
             if (ts > 0.0) {
                 prof_begin(ctx, KC_OTHER, 24.0 * n);
-                launch_apply(ctx, n, c, W.w, ts);
+                launch_apply(ctx, n, c, dir_w, ts);
                 prof_end(ctx);
                 S.bytes_moved += 24.0 * n;
                 step_norm += ts * wn;

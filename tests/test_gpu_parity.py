@@ -18,6 +18,7 @@ from paper_1506_08435_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 PARITY_TOL = 1e-8
+MIXED_TOL = 1e-6     # stated bound for the mixed-precision path
 
 
 @pytest.fixture(scope="module")
@@ -118,7 +119,7 @@ def test_solve_matches_oracle(ctx, name):
           f"cg={st['cg_its']} {st['seconds'] * 1e3:.1f} ms")
 
 
-@pytest.mark.parametrize("rtol", [1e-1, 1e-2, 1e-3])
+@pytest.mark.parametrize("rtol", [0.5, 1e-1, 1e-2, 1e-3])
 def test_inner_tolerances_same_minimiser(ctx, rtol):
     """TRON1/2/3 inner tolerances reach the same minimiser (Sec. 5.1)."""
     p = W.square2d(48)
@@ -299,4 +300,54 @@ def test_full_size_cube128_certificate(ctx):
         assert np.array_equal(col[a:b], S.col[a:b])
         assert np.abs(val[a:b] - S.K[a:b]).max() <= 1e-14 * np.abs(S.K[a:b]).max()
     print(f"cube128: kkt {k.r:.3e} outer {st['outer_its']} cg {st['cg_its']} "
+          f"{st['seconds']:.3f} s -> {S.n / st['seconds'] / 1e6:.2f} M DOF/s")
+
+
+# ---------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("name", ["square2d_64", "cube3d_21_ragged", "transient_field_20x18x9",
+                                  "batch_member_5"])
+def test_mixed_precision_matches_oracle(ctx, name):
+    """float32 values and CG vectors inside, float64 residual outside: the
+    result is the float64 minimiser (stated bound 1e-6; the error is printed)."""
+    from paper_1506_08435_amd import nnqp
+    p = SOLVE_CASES[name]()
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, precision=nnqp.NN_MIXED)
+    c, active = _np(c), _np(active)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    err = _check_solution(S, c, active, ref.c, tol=MIXED_TOL)
+    assert st["refinements"] == st["outer_its"] + 1
+    print(f"mixed {name}: err={err:.2e} outer={st['outer_its']} cg={st['cg_its']}")
+
+
+def test_mixed_transient_steps_match_oracle(ctx):
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.config_transient3d(16, 14, 8, ell=3.0)
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    S = oracle.assemble(p, with_mass=True)
+    dt = 1e-3
+    c_ref = np.zeros(S.n)
+    c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    for step in range(3):
+        r = oracle.transient_step(S, dt, c_ref, tol=1e-13)
+        c, active, st = ctx.step_transient(K, dt, F, c, tol=1e-12, precision=nnqp.NN_MIXED)
+        Kt, ft = oracle.transient_system(S, dt, c_ref)
+        S_t = oracle.System(n=S.n, rowptr=S.rowptr, col=S.col, K=Kt, M=None, F=ft, dof=S.dof)
+        _check_solution(S_t, _np(c), _np(active), r.c, tol=MIXED_TOL)
+        c_ref = r.c
+
+
+def test_mixed_full_size_cube128_certificate(ctx):
+    from paper_1506_08435_amd import nnqp
+    p = W.config_cube128()
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-8, inner_rtol=0.5, precision=nnqp.NN_MIXED)
+    c = _np(c)
+    assert c.min() >= 0.0
+    S = oracle.assemble(p)
+    k = oracle.kkt(S, c)
+    assert k.r <= 1e-8 * (1 + 1e-6), k.r
+    print(f"mixed cube128: kkt {k.r:.3e} outer {st['outer_its']} cg {st['cg_its']} "
           f"{st['seconds']:.3f} s -> {S.n / st['seconds'] / 1e6:.2f} M DOF/s")
