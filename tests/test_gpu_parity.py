@@ -351,3 +351,28 @@ def test_mixed_full_size_cube128_certificate(ctx):
     assert k.r <= 1e-8 * (1 + 1e-6), k.r
     print(f"mixed cube128: kkt {k.r:.3e} outer {st['outer_its']} cg {st['cg_its']} "
           f"{st['seconds']:.3f} s -> {S.n / st['seconds'] / 1e6:.2f} M DOF/s")
+
+
+def test_full_size_transient_steps_certified(ctx):
+    """The 256x256x64 heterogeneous transient workload: the first backward-Euler
+    steps (FP64 and mixed) are certified by the oracle's own assembly of K, M and
+    its own K~ = M/dt + K, f~ = F + M c^n/dt."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.config_transient3d()
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    S = oracle.assemble(p, with_mass=True)
+    assert S.n == K.n == 4096575
+    dt = 1e-3
+    for prec in (nnqp.NN_FP64, nnqp.NN_MIXED):
+        c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+        c_prev = np.zeros(S.n)
+        for step in range(2):
+            c, active, st = ctx.step_transient(K, dt, F, c, tol=1e-8, inner_rtol=0.5, precision=prec)
+            cn = _np(c).copy()
+            Kt, ft = oracle.transient_system(S, dt, c_prev)
+            k = oracle.kkt(S, cn, F=ft, vals=Kt)
+            assert cn.min() >= 0.0
+            assert k.r <= 1e-8 * (1 + 1e-6), (prec, step, k.r)
+            c_prev = cn
+        print(f"transient full size prec={prec}: step kkt {k.r:.2e}, {st['seconds'] * 1e3:.1f} ms")
