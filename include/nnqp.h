@@ -104,7 +104,7 @@ typedef struct {
     int32_t cauchy_trials;
     int32_t search_trials;
     int32_t refinements;  /* outer FP64 refinement steps (NN_MIXED) */
-    int32_t reserved;
+    int32_t status;       /* nn_status of this solve (per member in nn_solve_batch) */
     double bytes_moved;   /* algorithmic HBM bytes of the solve (perfect-cache model) */
     double seconds;       /* device time of the solve (HIP events on the stream) */
 } nn_stats;
@@ -200,6 +200,31 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
 nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *f_dev,
                             const nn_opts *opts, double *c_dev, uint8_t *active_dev,
                             nn_stats *stats);
+
+/*
+ * Solve nprob independent problems of the nn_solve_nonneg kind together
+ * (the batched form of the same method: every step is one launch over all
+ * members, each member keeps its own step lengths, trust radius, CG scalars
+ * and stopping test).  A member's result depends only on its own K, f and
+ * start value: it is bitwise the same in any batch, alone or mixed, and for
+ * any launch shape.  The CG iterations run as a captured hipGraph; launch
+ * shapes are tuned per size class on first use (one short timing pass).
+ *
+ *   K, f, c  host arrays of nprob entries (K: matrices of this context's
+ *            device; f, c: device [K[p]->n] float64, c in/out as in
+ *            nn_solve_nonneg); members may differ in size and pattern
+ *   active   host array of nprob device uint8 [n] outputs (entries may be
+ *            NULL), or NULL
+ *   stats    host array of nprob reports, or NULL; stats[p].status is the
+ *            member's own status, stats[p].seconds the whole call's time
+ * Options apply to every member.  Returns NN_OK when every member reached
+ * tol; otherwise the status of the first member that did not (the others are
+ * still solved and reported).  Workspace (about 100 bytes per row of the
+ * whole batch) is allocated for the call and released before return.
+ */
+nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
+                         const double *const *f_dev, const nn_opts *opts, double *const *c_dev,
+                         uint8_t *const *active_dev, nn_stats *stats);
 
 /* Device time per launch of the library's kernel classes, accumulated while
  * profiling is on (nn_set_profiling).  For class k: counts[k] launches and

@@ -108,6 +108,13 @@ void prof_end(nn_ctx *ctx)
     (void)hipEventRecord(ctx->prof_live.back().b, ctx->stream);
 }
 
+void prof_add(nn_ctx *ctx, int cls, double ms, double bytes)
+{
+    ctx->prof_count[cls]++;
+    ctx->prof_ms[cls] += ms;
+    ctx->prof_bytes[cls] += bytes > 0 ? bytes : 0.0;
+}
+
 void prof_collect(nn_ctx *ctx)
 {
     if (ctx->prof_live.empty()) return;
@@ -189,6 +196,7 @@ void nn_destroy(nn_ctx *ctx)
     if (ctx->h_part) (void)hipHostFree(ctx->h_part);
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (ProfEntry &p : ctx->prof_live) {
@@ -458,6 +466,35 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     o.c0_mode = 1;   // warm start from c^(n)
     return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, K->kt_diag, ctx->ws.ft, &o, c_dev,
                       active_dev, stats);
+}
+
+nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
+                         const double *const *f_dev, const nn_opts *opts, double *const *c_dev,
+                         uint8_t *const *active_dev, nn_stats *stats)
+{
+    NN_CHECK_CTX(ctx);
+    if (nprob < 0) return fail(ctx, NN_EINVAL, "nprob must be >= 0");
+    if (nprob > 0 && (!K || !f_dev || !c_dev)) return fail(ctx, NN_EINVAL, "null argument");
+    nn_status st = check_opts(ctx, opts);
+    if (st != NN_OK) return st;
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    for (int p = 0; p < nprob; p++) {
+        if (!K[p]) return fail(ctx, NN_EINVAL, "null matrix in batch");
+        if (K[p]->n > 0 && (!f_dev[p] || !c_dev[p]))
+            return fail(ctx, NN_EINVAL, "null f or c in batch");
+        if (K[p]->n > 0)
+            spans.push_back({(uintptr_t)c_dev[p], (uintptr_t)c_dev[p] + sizeof(double) * K[p]->n});
+    }
+    // members write their c concurrently: the buffers must not overlap
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); k++)
+        if (spans[k].first < spans[k - 1].second)
+            return fail(ctx, NN_EINVAL, "solution buffers of two batch members overlap");
+    if (nprob == 0) {
+        ctx->err.clear();
+        return NN_OK;
+    }
+    return solve_batch_impl(ctx, nprob, K, f_dev, opts, c_dev, active_dev, stats);
 }
 
 nn_status nn_set_profiling(nn_ctx *ctx, int on)

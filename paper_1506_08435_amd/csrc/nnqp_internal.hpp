@@ -110,6 +110,7 @@ struct nn_matrix {
 struct nn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture (batched CG)
     std::string err;
     double *partials = nullptr;      // [kSlots][kMaxBlocks][kMaxRed]
     double *h_part = nullptr;        // pinned host copy of one slot
@@ -152,6 +153,8 @@ nn_status host_reduce(nn_ctx *ctx, int64_t n, int nv, const int *ops, double *ou
 void prof_begin(nn_ctx *ctx, int cls, double bytes);
 void prof_end(nn_ctx *ctx);
 void prof_collect(nn_ctx *ctx);
+// add one timed launch of class cls (ms, algorithmic bytes) to the totals
+void prof_add(nn_ctx *ctx, int cls, double ms, double bytes);
 
 // ---------------------------------------------------------------- kernel launchers
 // (kernels.hip).  All launch on ctx->stream with the partition of the rows.
@@ -208,5 +211,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                      uint8_t *active, nn_stats *st);
 
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);
+
+// ---------------------------------------------------------------- batched solver (batch.hip)
+// P problems solved together; arrays are host arrays of P entries (see
+// nn_solve_batch).  Arguments are validated by the caller.
+nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double *const *f,
+                           const nn_opts *o, double *const *c, uint8_t *const *active,
+                           nn_stats *stats);
 
 }  // namespace nnqp

@@ -61,8 +61,9 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
         S.seconds = ms * 1e-3;
         prof_collect(ctx);
+        if (e != hipSuccess) rc = fail(ctx, NN_EHIP, hipGetErrorString(e));
+        S.status = (int32_t)rc;
         if (st) *st = S;
-        if (e != hipSuccess) return fail(ctx, NN_EHIP, hipGetErrorString(e));
         return rc;
     };
     if (n == 0) return finish(NN_OK);

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "NN_OK", 1: "NN_EINVAL", 2: "NN_ENONFINITE", 3: "NN_ENOTSPD",
 # exported symbols declared in include/nnqp.h (checked by the ABI test)
 SYMBOLS = ("nn_create", "nn_destroy", "nn_last_error", "nn_default_opts", "nn_assemble",
            "nn_matrix_from_csr", "nn_matrix_info", "nn_matrix_export", "nn_matrix_bytes",
-           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_step_transient",
+           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_step_transient", "nn_solve_batch",
            "nn_set_profiling", "nn_kernel_times")
 
 
@@ -57,11 +57,11 @@ class Stats(ctypes.Structure):
                 ("outer_its", ctypes.c_int32), ("cg_its", ctypes.c_int32),
                 ("spmvs", ctypes.c_int32), ("n_active", ctypes.c_int32),
                 ("cauchy_trials", ctypes.c_int32), ("search_trials", ctypes.c_int32),
-                ("refinements", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("bytes_moved", ctypes.c_double), ("seconds", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "nn_matvec": (i32, [vp, vp, ctypes.c_int, vp, vp]),
         "nn_solve_nonneg": (i32, [vp, vp, vp, P(Opts), vp, vp, P(Stats)]),
         "nn_step_transient": (i32, [vp, vp, dbl, vp, P(Opts), vp, vp, P(Stats)]),
+        "nn_solve_batch": (i32, [vp, i32, P(vp), P(vp), P(Opts), P(vp), P(vp), P(Stats)]),
         "nn_set_profiling": (i32, [vp, ctypes.c_int]),
         "nn_kernel_times": (i32, [vp, vp, vp, vp, ctypes.c_int]),
     }
@@ -276,6 +277,34 @@ class Context:
         d = st_out.as_dict()
         d["status"] = st
         return c[:A.n], active[:A.n], d
+
+    def solve_batch(self, As, fs, opts: Optional[Opts] = None, cs=None, actives=None,
+                    allow_fail: bool = False, **kw):
+        """Solve len(As) independent problems with one batched call
+        (nn_solve_batch).  Returns (cs, actives, stats list, status).  Each
+        c in `cs` (device float64, one per problem) is the warm start when
+        opts.c0_mode == 1 and is overwritten with that member's solution."""
+        t = self.torch
+        o = opts if opts is not None else default_opts(**kw)
+        P = len(As)
+        if len(fs) != P:
+            raise ValueError("one load vector per matrix")
+        if cs is None:
+            cs = [t.zeros(max(A.n, 1), dtype=t.float64, device=self.device) for A in As]
+        if actives is None:
+            actives = [t.empty(max(A.n, 1), dtype=t.uint8, device=self.device) for A in As]
+        arr = ctypes.c_void_p * max(P, 1)
+        Ka = arr(*[A.handle for A in As])
+        fa = arr(*[_ptr(f) for f in fs])
+        ca = arr(*[_ptr(c) for c in cs])
+        aa = arr(*[_ptr(a) for a in actives])
+        st_arr = (Stats * max(P, 1))()
+        st = self.lib.nn_solve_batch(self.handle, P, Ka, fa, ctypes.byref(o), ca, aa, st_arr)
+        if not allow_fail:
+            self._check(st, "nn_solve_batch")
+        stats = [st_arr[k].as_dict() for k in range(P)]
+        return ([c[:A.n] for c, A in zip(cs, As)], [a[:A.n] for a, A in zip(actives, As)],
+                stats, st)
 
     # ---------------------------------------------------------------- profiling
     def set_profiling(self, on: bool):

@@ -376,3 +376,151 @@ def test_full_size_transient_steps_certified(ctx):
             assert k.r <= 1e-8 * (1 + 1e-6), (prec, step, k.r)
             c_prev = cn
         print(f"transient full size prec={prec}: step kkt {k.r:.2e}, {st['seconds'] * 1e3:.1f} ms")
+
+
+# ---------------------------------------------------------------- batched solves
+def _batch_set():
+    """Members of uneven size and kind: seeded 2D batch members (several
+    slices each, ragged tails), the tiny 2D and 3D cases, a small cube."""
+    probs = [W.batch_problem(i, n_range=(8, 48)) for i in range(10)]
+    probs += [W.tiny2d(), W.tiny3d(), W.cube3d(7), W.square2d(23, theta=2.0, ratio=1e-2)]
+    return probs
+
+
+@pytest.fixture(scope="module")
+def batch_members(ctx):
+    probs = _batch_set()
+    Ks, Fs, Ss = [], [], []
+    for p in probs:
+        K, F, _ = ctx.assemble(p)
+        Ks.append(K)
+        Fs.append(F)
+        Ss.append(oracle.assemble(p))
+    return probs, Ks, Fs, Ss
+
+
+def test_batch_matches_oracle(ctx, batch_members):
+    probs, Ks, Fs, Ss = batch_members
+    cs, acts, stats, st = ctx.solve_batch(Ks, Fs, tol=1e-12, inner_rtol=0.1)
+    assert st == 0
+    for p, S, c, a, s in zip(probs, Ss, cs, acts, stats):
+        ref = oracle.solve(S, tol=1e-13)
+        assert ref.certified
+        err = _check_solution(S, _np(c), _np(a), ref.c)
+        k = oracle.kkt(S, _np(c))
+        assert k.r <= 1.01e-12 + 4 * ref.floor, (p.name, k.r)
+        assert s["status"] == 0 and s["kkt_rel"] <= 1e-12
+        print(f"{p.name}: n={S.n} err={err:.2e} kkt={k.r:.2e} outer={s['outer_its']} cg={s['cg_its']}")
+
+
+def test_batch_member_result_independent_of_batch(ctx, batch_members):
+    """Each member's result is bitwise the same alone, in the full batch and
+    in a permuted sub-batch (per-member slice partials, fixed combine order)."""
+    import torch
+    _, Ks, Fs, _ = batch_members
+    full, _, st_full, _ = ctx.solve_batch(Ks, Fs, tol=1e-10)
+    order = [5, 2, 11, 0, 13, 7]
+    sub, _, st_sub, _ = ctx.solve_batch([Ks[k] for k in order], [Fs[k] for k in order], tol=1e-10)
+    for j, k in enumerate(order):
+        assert torch.equal(sub[j], full[k]), k
+        assert st_sub[j]["outer_its"] == st_full[k]["outer_its"]
+        assert st_sub[j]["cg_its"] == st_full[k]["cg_its"]
+    for k in (0, 3, 12):
+        alone, _, st_alone, _ = ctx.solve_batch([Ks[k]], [Fs[k]], tol=1e-10)
+        assert torch.equal(alone[0], full[k]), k
+        assert st_alone[0]["cg_its"] == st_full[k]["cg_its"]
+
+
+def test_batch_agrees_with_single_solver(ctx, batch_members):
+    _, Ks, Fs, Ss = batch_members
+    cs, _, _, _ = ctx.solve_batch(Ks, Fs, tol=1e-12)
+    for K, F, S, cb in zip(Ks, Fs, Ss, cs):
+        c1, _, _ = ctx.solve_nonneg(K, F, tol=1e-12)
+        c1, cb = _np(c1), _np(cb)
+        assert np.abs(c1 - cb).max() <= PARITY_TOL * np.abs(c1).max()
+        assert np.array_equal(c1 == 0.0, cb == 0.0) or oracle.kkt(S, cb).r <= 1.01e-12
+
+
+def test_batch_mixed_precision_matches_oracle(ctx, batch_members):
+    from paper_1506_08435_amd import nnqp
+    probs, Ks, Fs, Ss = batch_members
+    cs, acts, stats, st = ctx.solve_batch(Ks, Fs, tol=1e-10, precision=nnqp.NN_MIXED)
+    assert st == 0
+    for p, S, c, a, s in zip(probs, Ss, cs, acts, stats):
+        ref = oracle.solve(S, tol=1e-13)
+        c = _np(c)
+        assert c.min() >= 0.0
+        err = np.abs(c - ref.c).max() / np.abs(ref.c).max()
+        assert err <= MIXED_TOL, (p.name, err)
+        assert oracle.kkt(S, c).r <= 1.01e-10
+        assert s["refinements"] == s["outer_its"] + 1
+        print(f"mixed {p.name}: err={err:.2e} refinements={s['refinements']}")
+
+
+def test_batch_edge_members(ctx, batch_members):
+    """Empty batch; a member with no free DOF; a member with f <= 0 (exact
+    zero); warm start from the solution (no outer iteration)."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    _, Ks, Fs, Ss = batch_members
+    cs, _, stats, st = ctx.solve_batch([], [])
+    assert st == 0 and cs == [] and stats == []
+    Kz, Fz, _ = ctx.assemble(W.square2d(1))          # all nodes on the boundary
+    assert Kz.n == 0
+    neg = -Fs[0]
+    cs, acts, stats, st = ctx.solve_batch([Kz, Ks[0], Ks[1]], [Fz, neg, Fs[1]], tol=1e-12)
+    assert st == 0
+    assert torch.count_nonzero(cs[1]).item() == 0 and bool(acts[1].all())
+    ref = oracle.solve(Ss[1], tol=1e-13)
+    _check_solution(Ss[1], _np(cs[2]), _np(acts[2]), ref.c)
+    warm = [cs[2].clone()]
+    o = nnqp.default_opts(tol=1e-12, c0_mode=1)
+    cw, _, sw, st = ctx.solve_batch([Ks[1]], [Fs[1]], opts=o, cs=warm)
+    assert st == 0 and sw[0]["outer_its"] == 0
+    assert torch.equal(cw[0], cs[2])
+
+
+def test_batch_rejects_overlapping_outputs(ctx, batch_members):
+    import torch
+    from paper_1506_08435_amd import nnqp
+    _, Ks, Fs, _ = batch_members
+    buf = torch.zeros(Ks[0].n + Ks[1].n, dtype=torch.float64, device=ctx.device)
+    with pytest.raises(nnqp.NnError):
+        ctx.solve_batch([Ks[0], Ks[0]], [Fs[0], Fs[0]], cs=[buf, buf[1:]], tol=1e-8)
+
+
+@pytest.mark.timeout(400)
+def test_full_size_batch_512_certified(ctx):
+    """The 512-member batch (grid sides U{32..256}) in one batched call, FP64 at
+    tol 1e-8: every member certified by its own report; the oracle recomputes
+    the KKT residual of a sample of members and solves two of them."""
+    import time
+    probs = [W.batch_problem(i) for i in range(512)]
+    Ks, Fs = [], []
+    for p in probs:
+        K, F, _ = ctx.assemble(p)
+        Ks.append(K)
+        Fs.append(F)
+    t0 = time.perf_counter()
+    cs, acts, stats, st = ctx.solve_batch(Ks, Fs, tol=1e-8, inner_rtol=0.1)
+    wall = time.perf_counter() - t0
+    assert st == 0
+    ndof = sum(K.n for K in Ks)
+    print(f"batch 512: {ndof} DOF, {wall:.2f} s, {ndof / wall:.3e} DOF/s, "
+          f"max outer {max(s['outer_its'] for s in stats)}")
+    for s in stats:
+        assert s["status"] == 0 and s["kkt_rel"] <= 1e-8 and s["min_c"] >= 0.0
+    rng = np.random.default_rng(11)
+    sample = sorted(set(rng.choice(512, size=12, replace=False).tolist()) |
+                    {int(np.argmax([K.n for K in Ks]))})
+    for k in sample:
+        S = oracle.assemble(probs[k])
+        c = _np(cs[k])
+        assert c.min() >= 0.0
+        assert oracle.kkt(S, c).r <= 1.01e-8, k
+    for k in sample[:2]:
+        S = oracle.assemble(probs[k])
+        ref = oracle.solve(S, tol=1e-12)
+        err = np.abs(_np(cs[k]) - ref.c).max() / np.abs(ref.c).max()
+        print(f"member {k} (n={S.n}): err vs oracle {err:.2e}")
+        assert err <= 1e-6   # KKT tol 1e-8 bounds the error by cond(K) * 1e-8
