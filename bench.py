@@ -194,6 +194,52 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def run_serve(args):
+    """Continuous-batching server on a Poisson stream of transient requests
+    (2D/3D 50/50, free DOF log-uniform in [1e3, 1e6], 10 backward-Euler steps
+    each, dt = 1e-3, KKT tol 1e-8 per step), FP64 and mixed precision on the
+    same stream; p50/p99 latency (arrival to last step) and DOF*steps/s."""
+    from paper_1506_08435_amd import nnqp, workloads as W
+    from paper_1506_08435_amd.serve import Request, Server
+    arrivals = W.serve_arrivals(args.nreq, args.rate, seed=args.serve_seed)
+    reqs = [Request(k, W.serve_problem(k, seed=args.serve_seed), args.serve_steps, float(arrivals[k]))
+            for k in range(args.nreq)]
+    dofs = [r.problem.n_free for r in reqs]
+    out = {}
+    budget = int(args.hbm_budget_gib * (1 << 30)) if args.hbm_budget_gib > 0 else None
+    for prec_name in ("fp64", "mixed"):
+        prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
+        srv = Server(precision=prec, hbm_budget=budget, tol=1e-8, inner_rtol=args.inner_rtol)
+        rep = srv.run(reqs)
+        sm = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.summary().items()}
+        sm["max_kkt_rel"] = max(s["kkt_rel"] for r in rep.results for s in r.step_stats)
+        out[prec_name] = sm
+    line = {"metric": "served transient requests: p50/p99 latency and solved DOF*steps/s",
+            "workload": f"serve: {args.nreq} requests, Poisson arrivals at {args.rate}/s, 2D/3D 50/50, "
+                        f"free DOF log-uniform in [1e3, 1e6] (here {min(dofs)}..{max(dofs)}, "
+                        f"total {sum(dofs)}), {args.serve_steps} backward-Euler steps each, dt = 1e-3",
+            "n_gpus": 1, **out}
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle
+        sample = [r for r in reqs if r.problem.n_free <= 20000][:args.cpu_members]
+        t0 = time.perf_counter()
+        ds = 0
+        for r in sample:
+            S = oracle.assemble(r.problem, with_mass=True)
+            c = np.zeros(S.n)
+            for _ in range(args.serve_steps):
+                c = oracle.transient_step(S, 1e-3, c, tol=1e-8).c
+            ds += S.n * args.serve_steps
+        sec = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(ds / sec, 1), "unit": "DOF*steps/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"oracle assembly + {args.serve_steps} steps of the first "
+                                          f"{len(sample)} requests with at most 20000 DOF, one after "
+                                          f"another: {sec:.2f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,7 +255,13 @@ def main():
     ap.add_argument("--verbose", action="store_true", help="per-outer-iteration trace on stderr")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 512 MiB device-to-device copies first (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["cube", "transient", "batch"], default="cube")
+    ap.add_argument("--workload", choices=["cube", "transient", "batch", "serve"], default="cube")
+    ap.add_argument("--nreq", type=int, default=32, help="requests of the serve workload")
+    ap.add_argument("--rate", type=float, default=50.0, help="arrival rate (requests/s)")
+    ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--serve-seed", type=int, default=50)
+    ap.add_argument("--hbm-budget-gib", type=float, default=0.0,
+                    help="server HBM budget (0: 3/4 of the free device memory)")
     ap.add_argument("--nbatch", type=int, default=512, help="members of the batch workload")
     ap.add_argument("--cpu-members", type=int, default=16,
                     help="batch members the CPU-baseline sample solves")
@@ -227,6 +279,9 @@ def main():
         return
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     import torch

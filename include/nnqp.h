@@ -226,6 +226,22 @@ nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
                          const double *const *f_dev, const nn_opts *opts, double *const *c_dev,
                          uint8_t *const *active_dev, nn_stats *stats);
 
+/*
+ * One backward-Euler step of nprob independent transient problems together
+ * (nn_step_transient for every member, in one batched solve): member p gets
+ * c_p^(n+1) = argmin_{c >= 0} 1/2 c.K~_p c - c.(f_p + M_p c_p^(n) / dt) with
+ * K~_p = M_p/dt + K_p formed once per dt and kept with the matrix.  Every K[p]
+ * must carry capacity values; c_dev[p] holds c^(n) on entry (also the warm
+ * start) and c^(n+1) on return.  A member's result is bitwise the same as
+ * in a batch of its own.  Other arguments and the return value as
+ * nn_solve_batch.  This is the step a continuous-batching server takes for
+ * all its resident transient requests at once.
+ */
+nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K, double dt,
+                                  const double *const *f_dev, const nn_opts *opts,
+                                  double *const *c_dev, uint8_t *const *active_dev,
+                                  nn_stats *stats);
+
 /* Device time per launch of the library's kernel classes, accumulated while
  * profiling is on (nn_set_profiling).  For class k: counts[k] launches and
  * total_ms[k] milliseconds measured with HIP events on the context stream.

@@ -136,6 +136,31 @@ void prof_collect(nn_ctx *ctx)
 
 }  // namespace nnqp
 
+namespace nnqp {
+
+// M/dt + K values for a backward-Euler step (formed once per dt, kept with K)
+nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed)
+{
+    const int64_t n = K->n;
+    if (n == 0 || (K->kt && K->kt_dt == dt && (!mixed || K->kt32))) return NN_OK;
+    if (!K->kt) {
+        if (hipMalloc(&K->kt, sizeof(double) * std::max<int64_t>(K->nsell, 1)) != hipSuccess ||
+            hipMalloc(&K->kt_diag, sizeof(double) * n) != hipSuccess)
+            return fail(ctx, NN_EOOM, "transient matrix allocation");
+    }
+    if (mixed && !K->kt32 &&
+        hipMalloc(&K->kt32, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
+        return fail(ctx, NN_EOOM, "transient float32 allocation");
+    launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
+    launch_diag(ctx, K, K->kt, K->kt_diag);
+    if (K->kt32) launch_to_f32(ctx, K->nsell, K->kt, K->kt32);
+    NN_HIP_TRY(ctx, hipGetLastError());
+    K->kt_dt = dt;
+    return NN_OK;
+}
+
+}  // namespace nnqp
+
 using namespace nnqp;
 
 #define NN_CHECK_CTX(ctx)                               \
@@ -432,6 +457,7 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
     return solve_impl(ctx, K, K->val, v32, K->diag, f_dev, opts, c_dev, active_dev, stats);
 }
 
+
 nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *f_dev,
                             const nn_opts *opts, double *c_dev, uint8_t *active_dev,
                             nn_stats *stats)
@@ -445,21 +471,7 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     const int64_t n = K->n;
     const bool mixed = opts->precision == NN_MIXED;
     if (n == 0) return solve_impl(ctx, K, K->val, nullptr, K->diag, f_dev, opts, c_dev, active_dev, stats);
-    if (!K->kt || K->kt_dt != dt || (mixed && !K->kt32)) {
-        if (!K->kt) {
-            if (hipMalloc(&K->kt, sizeof(double) * std::max<int64_t>(K->nsell, 1)) != hipSuccess ||
-                hipMalloc(&K->kt_diag, sizeof(double) * n) != hipSuccess)
-                return fail(ctx, NN_EOOM, "transient matrix allocation");
-        }
-        if (mixed && !K->kt32 &&
-            hipMalloc(&K->kt32, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
-            return fail(ctx, NN_EOOM, "transient float32 allocation");
-        launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
-        launch_diag(ctx, K, K->kt, K->kt_diag);
-        if (K->kt32) launch_to_f32(ctx, K->nsell, K->kt, K->kt32);
-        NN_HIP_TRY(ctx, hipGetLastError());
-        K->kt_dt = dt;
-    }
+    if ((st = ensure_transient(ctx, K, dt, mixed)) != NN_OK) return st;
     if ((st = ensure_workspace(ctx, n)) != NN_OK) return st;
     launch_transient_rhs(ctx, K, c_dev, f_dev, dt, ctx->ws.ft);
     nn_opts o = *opts;
@@ -468,11 +480,12 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
                       active_dev, stats);
 }
 
-nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
-                         const double *const *f_dev, const nn_opts *opts, double *const *c_dev,
-                         uint8_t *const *active_dev, nn_stats *stats)
+// Shared checks of the batched entry points: arguments, options, and that
+// no two members' solution buffers overlap (they are written concurrently).
+static nn_status check_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
+                             const double *const *f_dev, const nn_opts *opts,
+                             double *const *c_dev, bool need_mass)
 {
-    NN_CHECK_CTX(ctx);
     if (nprob < 0) return fail(ctx, NN_EINVAL, "nprob must be >= 0");
     if (nprob > 0 && (!K || !f_dev || !c_dev)) return fail(ctx, NN_EINVAL, "null argument");
     nn_status st = check_opts(ctx, opts);
@@ -480,21 +493,53 @@ nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int p = 0; p < nprob; p++) {
         if (!K[p]) return fail(ctx, NN_EINVAL, "null matrix in batch");
+        if (need_mass && !K[p]->mval)
+            return fail(ctx, NN_EINVAL, "batch member has no capacity values (assemble with_mass)");
         if (K[p]->n > 0 && (!f_dev[p] || !c_dev[p]))
             return fail(ctx, NN_EINVAL, "null f or c in batch");
         if (K[p]->n > 0)
             spans.push_back({(uintptr_t)c_dev[p], (uintptr_t)c_dev[p] + sizeof(double) * K[p]->n});
     }
-    // members write their c concurrently: the buffers must not overlap
     std::sort(spans.begin(), spans.end());
     for (size_t k = 1; k < spans.size(); k++)
         if (spans[k].first < spans[k - 1].second)
             return fail(ctx, NN_EINVAL, "solution buffers of two batch members overlap");
+    return NN_OK;
+}
+
+nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K, double dt,
+                                  const double *const *f_dev, const nn_opts *opts,
+                                  double *const *c_dev, uint8_t *const *active_dev,
+                                  nn_stats *stats)
+{
+    NN_CHECK_CTX(ctx);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NN_EINVAL, "dt must be > 0");
+    nn_status st = check_batch(ctx, nprob, K, f_dev, opts, c_dev, true);
+    if (st != NN_OK) return st;
+    const bool mixed = opts->precision == NN_MIXED;
+    for (int p = 0; p < nprob; p++)
+        if ((st = ensure_transient(ctx, K[p], dt, mixed)) != NN_OK) return st;
     if (nprob == 0) {
         ctx->err.clear();
         return NN_OK;
     }
-    return solve_batch_impl(ctx, nprob, K, f_dev, opts, c_dev, active_dev, stats);
+    nn_opts o = *opts;
+    o.c0_mode = 1;   // warm start from c^(n)
+    return solve_batch_impl(ctx, nprob, K, f_dev, &o, c_dev, active_dev, stats, dt);
+}
+
+nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
+                         const double *const *f_dev, const nn_opts *opts, double *const *c_dev,
+                         uint8_t *const *active_dev, nn_stats *stats)
+{
+    NN_CHECK_CTX(ctx);
+    nn_status st = check_batch(ctx, nprob, K, f_dev, opts, c_dev, false);
+    if (st != NN_OK) return st;
+    if (nprob == 0) {
+        ctx->err.clear();
+        return NN_OK;
+    }
+    return solve_batch_impl(ctx, nprob, K, f_dev, opts, c_dev, active_dev, stats, 0.0);
 }
 
 nn_status nn_set_profiling(nn_ctx *ctx, int on)

@@ -79,7 +79,9 @@ struct BDev {
     const double *const *diag;      // per problem diagonal
     const int *const *rowptr;       // per problem CSR row pointers
     double *const *c;               // per problem solution vectors (local rows)
-    const double *const *f;         // per problem loads
+    const double *const *f;         // per problem loads of the solve
+    const double *const *f0;        // per problem loads (transient step: f of f + M c/dt)
+    const double *const *mv;        // per problem capacity values (transient step)
     uint8_t *const *act_out;        // per problem active-set outputs (entries may be null)
     BProb *bp;
     double *part;                   // [nslices][kBNV]
@@ -190,6 +192,21 @@ __global__ void kb_init(BDev B, int mode, double c0v)
                            a[3] += isfinite(cv) ? 0.0 : 1.0;
                            c[il] = proj0b(cv);
                        }
+                   });
+}
+
+// Right-hand side of a backward-Euler step, ft = f0 + (M c) / dt, written
+// into the concatenated vector ft (the solve's loads point into it).
+template <int WMAX>
+__global__ void kb_transient_rhs(BDev B, double dt, double *__restrict__ ft)
+{
+    const int ops[1] = {OP_SUM};
+    for_bslices<1>(B, ops, [&](int p) { return B.bp[p].active != 0; },
+                   [&](int p, int s, int i, int il, bool row, double (&)[1]) {
+                       const double *c = B.c[p];
+                       const double mc =
+                           bsell_row<WMAX>(B, B.mv[p], p, s, [&](int j) { return c[j]; });
+                       if (row) ft[i] = B.f0[p][il] + mc / dt;
                    });
 }
 
@@ -561,10 +578,11 @@ struct Events {
 
 nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double *const *f,
                            const nn_opts *o, double *const *c, uint8_t *const *active,
-                           nn_stats *stats)
+                           nn_stats *stats, double dt)
 {
     hipStream_t st = ctx->stream;
     const bool mixed = o->precision == NN_MIXED;
+    const bool transient = dt > 0.0;
     std::vector<nn_stats> SP(P);
     for (nn_stats &x : SP) std::memset(&x, 0, sizeof(x));
 
@@ -582,7 +600,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
             return fail(ctx, NN_EINVAL, "batch too large: total rows must stay below 2^31");
         for (int t = 0; t < nsl[p]; t++) sprob.push_back(p);
         if (n > 0) wmax = std::max(wmax, K[p]->wmax);
-        if (mixed && n > 0 && !K[p]->val32) {
+        if (mixed && n > 0 && !transient && !K[p]->val32) {
             if (hipMalloc(&K[p]->val32, sizeof(float) * std::max<int64_t>(K[p]->nsell, 1)) !=
                 hipSuccess)
                 return fail(ctx, NN_EOOM, "float32 value allocation");
@@ -604,13 +622,15 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     const int **d_so = A.d<const int *>(P), **d_sc = A.d<const int *>(P),
               **d_rp = A.d<const int *>(P);
     const double **d_v64 = A.d<const double *>(P), **d_diag = A.d<const double *>(P),
-                 **d_f = A.d<const double *>(P);
+                 **d_f = A.d<const double *>(P), **d_f0 = A.d<const double *>(P),
+                 **d_mv = A.d<const double *>(P);
     const float **d_v32 = A.d<const float *>(P);
     double **d_c = A.d<double *>(P);
     uint8_t **d_act = A.d<uint8_t *>(P);
     BProb *d_bp = A.d<BProb>(P);
     double *d_part = A.d<double>((size_t)S * kBNV), *d_pres = A.d<double>((size_t)P * kBNV);
     double *g = A.d<double>(R), *ks0 = A.d<double>(R), *ks1 = A.d<double>(R);
+    double *ft = transient ? A.d<double>(R) : nullptr;
     uint8_t *mask = A.d<uint8_t>(R);
     double *w64 = nullptr, *r64 = nullptr, *z64 = nullptr, *p64 = nullptr, *q64 = nullptr,
            *dm64 = nullptr;
@@ -625,7 +645,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     }
     BProb *hb = A.h<BProb>(P);
     double *pres = A.h<double>((size_t)P * kBNV);
-    const void **tab = (const void **)A.h<void *>((size_t)P * 9);
+    const void **tab = (const void **)A.h<void *>((size_t)P * 11);
     // Uploads from pinned memory read their source when they execute, so
     // the host writes each upload into a staging copy that it does not touch
     // again until the copy's event has completed.
@@ -643,20 +663,23 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         return fail(ctx, NN_EHIP, "event creation");
     hipEvent_t t0 = ev_t.ev[0], t1 = ev_t.ev[1];
 
+    // a transient step solves with the M/dt + K values, loads f + M c/dt
     for (int p = 0; p < P; p++) {
         tab[0 * P + p] = K[p]->sl_off;
         tab[1 * P + p] = K[p]->sl_col;
         tab[2 * P + p] = K[p]->rowptr;
-        tab[3 * P + p] = K[p]->val;
-        tab[4 * P + p] = K[p]->diag;
-        tab[5 * P + p] = f[p];
-        tab[6 * P + p] = K[p]->val32;
+        tab[3 * P + p] = transient ? K[p]->kt : K[p]->val;
+        tab[4 * P + p] = transient ? K[p]->kt_diag : K[p]->diag;
+        tab[5 * P + p] = transient ? (const void *)(ft + (size_t)s0[p] * kSlice) : f[p];
+        tab[6 * P + p] = transient ? K[p]->kt32 : K[p]->val32;
         tab[7 * P + p] = c[p];
         tab[8 * P + p] = active ? active[p] : nullptr;
+        tab[9 * P + p] = f[p];
+        tab[10 * P + p] = K[p]->mval;
     }
     {
-        void *dsts[9] = {d_so, d_sc, d_rp, d_v64, d_diag, d_f, d_v32, d_c, d_act};
-        for (int k = 0; k < 9; k++)
+        void *dsts[11] = {d_so, d_sc, d_rp, d_v64, d_diag, d_f, d_v32, d_c, d_act, d_f0, d_mv};
+        for (int k = 0; k < 11; k++)
             NN_HIP_TRY(ctx, hipMemcpyAsync(dsts[k], tab + (size_t)k * P, sizeof(void *) * P,
                                            hipMemcpyHostToDevice, st));
         NN_HIP_TRY(ctx, hipMemcpyAsync(d_sprob, sprob.data(), sizeof(int) * S,
@@ -684,6 +707,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     B.rowptr = d_rp;
     B.c = d_c;
     B.f = d_f;
+    B.f0 = d_f0;
+    B.mv = d_mv;
     B.act_out = d_act;
     B.bp = d_bp;
     B.part = d_part;
@@ -767,6 +792,9 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     NN_HIP_TRY(ctx, select(is_active) ? hipSuccess : hipErrorUnknown);
     NN_HIP_TRY(ctx, hipEventRecord(t0, st));
 
+    // ---- transient right-hand sides (from c^n, before the start point is set)
+    if (transient)
+        NN_BDISPATCH(wmax, (kb_transient_rhs<WM>), grid_for(sh, n_sl), sh.block, st, B, dt, ft);
     // ---- start point and load statistics
     hipLaunchKernelGGL(kb_init, dim3(grid_for(sh, n_sl)), dim3(sh.block), 0, st, B,
                        o->c0_mode == 1 ? 1 : 0, o->c0_value);

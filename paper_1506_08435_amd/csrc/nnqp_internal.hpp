@@ -214,9 +214,14 @@ nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);
 
 // ---------------------------------------------------------------- batched solver (batch.hip)
 // P problems solved together; arrays are host arrays of P entries (see
-// nn_solve_batch).  Arguments are validated by the caller.
+// nn_solve_batch).  Arguments are validated by the caller.  dt > 0: one
+// backward-Euler step of every member (its M/dt + K values must have been
+// formed by ensure_transient; f is the load, c = c^n in and c^(n+1) out).
 nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double *const *f,
                            const nn_opts *o, double *const *c, uint8_t *const *active,
-                           nn_stats *stats);
+                           nn_stats *stats, double dt);
+// Form (once per dt) the M/dt + K values, their diagonal and, for mixed
+// precision, their float32 copy.
+nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed);
 
 }  // namespace nnqp

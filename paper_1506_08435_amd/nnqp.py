@@ -28,8 +28,8 @@ STATUS_NAMES = {0: "NN_OK", 1: "NN_EINVAL", 2: "NN_ENONFINITE", 3: "NN_ENOTSPD",
 # exported symbols declared in include/nnqp.h (checked by the ABI test)
 SYMBOLS = ("nn_create", "nn_destroy", "nn_last_error", "nn_default_opts", "nn_assemble",
            "nn_matrix_from_csr", "nn_matrix_info", "nn_matrix_export", "nn_matrix_bytes",
-           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_step_transient", "nn_solve_batch",
-           "nn_set_profiling", "nn_kernel_times")
+           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_step_transient",
+           "nn_solve_batch", "nn_step_transient_batch", "nn_set_profiling", "nn_kernel_times")
 
 
 class NnError(RuntimeError):
@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH):
         "nn_solve_nonneg": (i32, [vp, vp, vp, P(Opts), vp, vp, P(Stats)]),
         "nn_step_transient": (i32, [vp, vp, dbl, vp, P(Opts), vp, vp, P(Stats)]),
         "nn_solve_batch": (i32, [vp, i32, P(vp), P(vp), P(Opts), P(vp), P(vp), P(Stats)]),
+        "nn_step_transient_batch": (i32, [vp, i32, P(vp), dbl, P(vp), P(Opts), P(vp), P(vp),
+                                          P(Stats)]),
         "nn_set_profiling": (i32, [vp, ctypes.c_int]),
         "nn_kernel_times": (i32, [vp, vp, vp, vp, ctypes.c_int]),
     }
@@ -134,6 +136,10 @@ class Matrix:
     n: int
     nnz: int
     has_mass: bool
+
+    def bytes(self, precision: int = NN_FP64) -> int:
+        """Device bytes of the matrix and one solve's work vectors (nn_matrix_bytes)."""
+        return self.ctx.matrix_bytes(self, precision)
 
     def free(self):
         if self.handle:
@@ -305,6 +311,28 @@ class Context:
         stats = [st_arr[k].as_dict() for k in range(P)]
         return ([c[:A.n] for c, A in zip(cs, As)], [a[:A.n] for a, A in zip(actives, As)],
                 stats, st)
+
+    def step_transient_batch(self, As, dt: float, fs, cs, opts: Optional[Opts] = None,
+                             actives=None, allow_fail: bool = False, **kw):
+        """One backward-Euler step of every member (nn_step_transient_batch):
+        each c in `cs` holds c^n and is overwritten with c^(n+1).  Returns
+        (cs, actives, stats list, status)."""
+        t = self.torch
+        o = opts if opts is not None else default_opts(**kw)
+        P = len(As)
+        if len(fs) != P or len(cs) != P:
+            raise ValueError("one load and one state vector per matrix")
+        if actives is None:
+            actives = [t.empty(max(A.n, 1), dtype=t.uint8, device=self.device) for A in As]
+        arr = ctypes.c_void_p * max(P, 1)
+        st_arr = (Stats * max(P, 1))()
+        st = self.lib.nn_step_transient_batch(
+            self.handle, P, arr(*[A.handle for A in As]), float(dt), arr(*[_ptr(f) for f in fs]),
+            ctypes.byref(o), arr(*[_ptr(c) for c in cs]), arr(*[_ptr(a) for a in actives]), st_arr)
+        if not allow_fail:
+            self._check(st, "nn_step_transient_batch")
+        return ([c[:A.n] for c, A in zip(cs, As)], [a[:A.n] for a, A in zip(actives, As)],
+                [st_arr[k].as_dict() for k in range(P)], st)
 
     # ---------------------------------------------------------------- profiling
     def set_profiling(self, on: bool):

@@ -1,0 +1,237 @@
+"""Continuous-batching server for transient non-negative diffusion solves.
+
+A request is a P1 problem (mesh, tensor, source) and a number of
+backward-Euler steps (Sec. 2.2.2, eq. Eq:non-negative with lower bound 0),
+each step a non-negative QP warm-started from the previous one.  The server:
+
+* admits arrived requests first-in first-out while their device memory fits
+  the HBM budget (estimated from the mesh, replaced by nn_matrix_bytes once
+  assembled); a request larger than the whole budget is rejected;
+* assembles admitted requests on worker threads, each with its own library
+  context and stream, so assembly overlaps the solves already running;
+* keeps K, M/dt + K, f, c and the active set of every resident request on the
+  device for all of its steps;
+* runs ticks: one batched call (nn_step_transient_batch) advances every
+  resident request by one step; requests that arrive or finish assembling
+  join at the next tick, finished requests leave and free their memory.
+
+Because a batch member's arithmetic does not depend on the other members, a
+request's result is bitwise the same whether it is served alone or in any mix.
+The Python here only sequences calls; every step runs in the HIP library.
+"""
+import collections
+import concurrent.futures as cf
+import dataclasses
+import math
+import threading
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import nnqp
+
+NN_EBUDGET = nnqp.NN_EBUDGET
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    problem: object          # workloads.Problem
+    steps: int
+    arrival: float           # seconds after the stream starts
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    n: int
+    steps: int
+    arrival: float
+    admitted: float = math.nan
+    started: float = math.nan     # first tick that included the request
+    finished: float = math.nan
+    status: int = 0
+    step_stats: list = dataclasses.field(default_factory=list)
+    c: object = None              # final state (device tensor) when kept
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclasses.dataclass
+class Report:
+    results: List[Result]
+    makespan: float
+    ticks: int
+    mean_batch: float
+    deferred: int                 # requests that waited for memory before admission
+    peak_bytes: int
+    budget: int
+
+    def summary(self) -> dict:
+        done = [r for r in self.results if r.status == 0]
+        lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+        dof_steps = sum(r.n * r.steps for r in done)
+        return {"requests": len(self.results), "completed": len(done),
+                "rejected": sum(r.status == NN_EBUDGET for r in self.results),
+                "p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99)),
+                "mean_latency_s": float(lat.mean()), "max_latency_s": float(lat.max()),
+                "makespan_s": self.makespan, "dof_steps_per_s": dof_steps / self.makespan,
+                "requests_per_s": len(done) / self.makespan, "ticks": self.ticks,
+                "mean_resident_per_tick": self.mean_batch, "admission_waits": self.deferred,
+                "peak_resident_bytes": self.peak_bytes, "hbm_budget_bytes": self.budget}
+
+
+def estimate_bytes(problem, precision: int) -> int:
+    """Device bytes of a request before assembly: free DOF from the Dirichlet
+    mask, nonzeros per row of a structured P1 mesh (7 in 2D, 15 in 3D)."""
+    n = int((np.asarray(problem.dirichlet) == 0).sum())
+    per_row = 7 if problem.dim == 2 else 15
+    nnz = n * per_row
+    b = 8.0 * n + 16.0 * nnz + 4.0 * n          # CSR, sliced-ELL (padding ignored)
+    b += 24.0 * nnz + 16.0 * n                  # capacity and M/dt + K values, diagonals
+    b += 89.0 * n                               # solver work vectors
+    if precision == nnqp.NN_MIXED:
+        b += 4.0 * nnz + 40.0 * n
+    return int(b + 17.0 * n)                    # f, c, active set
+
+
+class Server:
+    def __init__(self, device: int = 0, hbm_budget: Optional[int] = None,
+                 precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
+                 inner_rtol: float = 0.5, assemble_workers: int = 2, keep_states: bool = False):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.ctx = nnqp.Context(device)
+        self.precision = precision
+        self.dt = dt
+        self.opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision)
+        free, total = torch.cuda.mem_get_info(device)
+        self.budget = int(hbm_budget) if hbm_budget else int(0.75 * free)
+        self.workers = assemble_workers
+        self.keep_states = keep_states
+        self._tls = threading.local()
+
+    # worker-thread assembly on the thread's own context and stream
+    def _assemble(self, req: Request):
+        torch = self.torch
+        if getattr(self._tls, "ctx", None) is None:
+            stream = torch.cuda.Stream(self.device)
+            self._tls.ctx = nnqp.Context(self.device, stream=stream)
+        wctx = self._tls.ctx
+        with torch.cuda.stream(wctx.stream):
+            K, F, _ = wctx.assemble(req.problem, with_mass=True)
+        wctx.stream.synchronize()
+        return K, F
+
+    def run(self, requests: List[Request]) -> Report:
+        torch = self.torch
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        results = {r.rid: Result(r.rid, 0, r.steps, r.arrival) for r in reqs}
+        pending = collections.deque(reqs)
+        waiting = collections.deque()
+        assembling = {}
+        resident = []
+        used = 0
+        peak = 0
+        ticks = 0
+        batch_sum = 0
+        waited = set()
+        pool = cf.ThreadPoolExecutor(max_workers=self.workers)
+        t0 = time.perf_counter()
+        try:
+            while pending or waiting or assembling or resident:
+                now = time.perf_counter() - t0
+                while pending and pending[0].arrival <= now:
+                    waiting.append(pending.popleft())
+                # admission: first in, first out, while the estimate fits
+                while waiting:
+                    req = waiting[0]
+                    est = estimate_bytes(req.problem, self.precision)
+                    if est > self.budget:
+                        waiting.popleft()
+                        res = results[req.rid]
+                        res.status = NN_EBUDGET
+                        res.finished = time.perf_counter() - t0
+                        continue
+                    if used + est > self.budget:
+                        waited.add(req.rid)
+                        break
+                    waiting.popleft()
+                    used += est
+                    peak = max(peak, used)
+                    results[req.rid].admitted = time.perf_counter() - t0
+                    assembling[pool.submit(self._assemble, req)] = (req, est)
+                # assembled requests become resident
+                for fut in [f for f in assembling if f.done()]:
+                    req, est = assembling.pop(fut)
+                    K, F = fut.result()
+                    nb = K.bytes(self.precision) + 17 * K.n
+                    used += nb - est
+                    peak = max(peak, used)
+                    c = torch.zeros(max(K.n, 1), dtype=torch.float64, device=self.ctx.device)
+                    act = torch.empty(max(K.n, 1), dtype=torch.uint8, device=self.ctx.device)
+                    results[req.rid].n = K.n
+                    resident.append({"req": req, "K": K, "F": F, "c": c, "act": act, "bytes": nb,
+                                     "done": 0})
+                if resident:
+                    tnow = time.perf_counter() - t0
+                    for s in resident:
+                        r = results[s["req"].rid]
+                        if math.isnan(r.started):
+                            r.started = tnow
+                    _, _, stats, st = self.ctx.step_transient_batch(
+                        [s["K"] for s in resident], self.dt, [s["F"] for s in resident],
+                        [s["c"] for s in resident], opts=self.opts,
+                        actives=[s["act"] for s in resident], allow_fail=True)
+                    ticks += 1
+                    batch_sum += len(resident)
+                    tend = time.perf_counter() - t0
+                    keep = []
+                    for s, stt in zip(resident, stats):
+                        r = results[s["req"].rid]
+                        r.step_stats.append(stt)
+                        s["done"] += 1
+                        if stt["status"] != 0 and r.status == 0:
+                            r.status = stt["status"]
+                        if s["done"] >= s["req"].steps or stt["status"] not in (0,):
+                            r.finished = tend
+                            if self.keep_states:
+                                r.c = s["c"][:s["K"].n].clone()
+                            s["K"].free()
+                            used -= s["bytes"]
+                        else:
+                            keep.append(s)
+                    resident = keep
+                elif assembling:
+                    cf.wait(list(assembling), timeout=0.05, return_when=cf.FIRST_COMPLETED)
+                elif pending and not waiting:
+                    time.sleep(max(0.0, min(0.05, pending[0].arrival - (time.perf_counter() - t0))))
+        finally:
+            pool.shutdown(wait=True)
+        torch.cuda.synchronize()
+        makespan = time.perf_counter() - t0
+        return Report([results[r.rid] for r in reqs], makespan, ticks,
+                      batch_sum / max(ticks, 1), len(waited), peak, self.budget)
+
+
+def solve_alone(req: Request, precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
+                inner_rtol: float = 0.5, ctx=None):
+    """The same request run by itself (a batch of one per step): final c and
+    per-step stats."""
+    import torch
+    ctx = ctx or nnqp.Context(0)
+    opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision)
+    K, F, _ = ctx.assemble(req.problem, with_mass=True)
+    c = torch.zeros(max(K.n, 1), dtype=torch.float64, device=ctx.device)
+    stats = []
+    for _ in range(req.steps):
+        _, _, st, _ = ctx.step_transient_batch([K], dt, [F], [c], opts=opts)
+        stats.append(st[0])
+    out = c[:K.n].clone()
+    K.free()
+    return out, stats

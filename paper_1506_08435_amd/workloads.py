@@ -272,6 +272,40 @@ def batch_problem(index: int, seed: int = 8435, nprob: int = 512,
                        aniso2d_tensor(theta, 10.0 ** (-a)), f_elem=f_elem)
 
 
+# ---------------------------------------------------------------- served request stream
+def serve_problem(index: int, seed: int = 50, dof_range=(1e3, 1e6)) -> Problem:
+    """One request of the served stream: 2D or 3D with probability 1/2, free
+    DOF log-uniform in dof_range.  2D as a batch member (random theta,
+    anisotropy 10^-U(1,4), source on a random square of side U[0.1, 0.3]);
+    3D with the cube tensor (1, 1e-2, 1e-4) and the source on a random cube
+    of side U[0.1, 0.3]."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, index]))
+    dim = 2 if rng.uniform() < 0.5 else 3
+    dof = math.exp(rng.uniform(math.log(dof_range[0]), math.log(dof_range[1])))
+    n = max(2, int(round(dof ** (1.0 / dim))) + 1)      # (n-1)^dim free DOF
+    side = float(rng.uniform(0.1, 0.3))
+    corner = rng.uniform(0.0, 1.0 - side, size=dim)
+    h = 1.0 / n
+    cx = (np.arange(n) + 0.5) * h
+    ins = [(cx >= corner[k]) & (cx <= corner[k] + side) for k in range(dim)]
+    if dim == 2:
+        theta = float(rng.uniform(0.0, math.pi))
+        a = float(rng.uniform(1.0, 4.0))
+        cell_f = (ins[1][:, None] & ins[0][None, :]).astype(np.float64).ravel()
+        return box_problem(f"serve{seed}_{index}_2d_n{n}", (n, n), h,
+                           aniso2d_tensor(theta, 10.0 ** (-a)), f_elem=np.repeat(cell_f, 2))
+    cell_f = (ins[2][:, None, None] & ins[1][None, :, None] & ins[0][None, None, :])
+    cell_f = cell_f.astype(np.float64).ravel()                      # [z, y, x] -> x fastest
+    return box_problem(f"serve{seed}_{index}_3d_n{n}", (n, n, n), h, aniso3d_tensor(),
+                       f_elem=np.repeat(cell_f, 6))
+
+
+def serve_arrivals(nreq: int, rate: float, seed: int = 50) -> np.ndarray:
+    """Poisson arrival times (seconds) of nreq requests at `rate` per second."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 1 << 20]))
+    return np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+
+
 # ---------------------------------------------------------------- manufactured solution
 def mms_problem(dim: int, n: int) -> Problem:
     """c = prod sin(pi x_k) with constant anisotropic D; f = -div(D grad c)

@@ -1,0 +1,99 @@
+"""Continuous-batching server: served results equal the same request run
+alone (bitwise: a batch member's arithmetic does not depend on the mix), match
+the oracle's backward-Euler steps, and admission respects the HBM budget.
+The stream generator is checked on the CPU."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_08435_amd import workloads as W
+
+
+def _requests(n, steps, dof_range=(150, 2500), gap=0.002, seed=7):
+    from paper_1506_08435_amd.serve import Request
+    return [Request(k, W.serve_problem(k, seed=seed, dof_range=dof_range), steps, k * gap)
+            for k in range(n)]
+
+
+# ---------------------------------------------------------------- CPU: stream generator
+def test_serve_stream_mix_and_sizes():
+    dims, dofs = [], []
+    for k in range(400):
+        p = W.serve_problem(k, seed=3, dof_range=(1e3, 3e4))
+        dims.append(p.dim)
+        dofs.append(p.n_free)
+        assert p.f_elem.max() == 1.0 and p.f_elem.min() == 0.0
+    dims = np.array(dims)
+    assert 0.4 < (dims == 2).mean() < 0.6                       # 50/50 2D / 3D
+    logd = np.log(np.array(dofs))
+    # log-uniform in [1e3, 3e4], up to the rounding of the grid side
+    assert logd.min() > np.log(1e3) - 0.7 and logd.max() < np.log(3e4) + 0.7
+    assert abs(np.median(logd) - 0.5 * (np.log(1e3) + np.log(3e4))) < 0.4
+
+
+def test_serve_arrivals_poisson():
+    t = W.serve_arrivals(20000, rate=500.0, seed=1)
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert np.all(gaps > 0)
+    assert abs(gaps.mean() - 1 / 500.0) < 0.03 / 500.0 * 3
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.05            # exponential: CV = 1
+
+
+# ---------------------------------------------------------------- GPU
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_served_result_equals_alone(prec):
+    import torch
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import Server, solve_alone
+    precision = nnqp.NN_MIXED if prec == "mixed" else nnqp.NN_FP64
+    reqs = _requests(7, steps=3)
+    srv = Server(precision=precision, tol=1e-10, inner_rtol=0.1, keep_states=True)
+    rep = srv.run(reqs)
+    assert all(r.status == 0 for r in rep.results)
+    assert rep.mean_batch > 1.5, "requests should overlap on the device"
+    ctx = nnqp.Context(0)
+    for req, res in zip(reqs, rep.results):
+        c_alone, st_alone = solve_alone(req, precision=precision, tol=1e-10, inner_rtol=0.1, ctx=ctx)
+        assert torch.equal(res.c, c_alone), req.rid
+        assert [s["cg_its"] for s in res.step_stats] == [s["cg_its"] for s in st_alone]
+        assert all(s["kkt_rel"] <= 1e-10 for s in res.step_stats)
+    print(rep.summary())
+
+
+@pytest.mark.gpu
+def test_served_steps_match_oracle():
+    from paper_1506_08435_amd.serve import Server
+    reqs = _requests(4, steps=3)
+    srv = Server(tol=1e-12, inner_rtol=0.1, keep_states=True)
+    rep = srv.run(reqs)
+    for req, res in zip(reqs, rep.results):
+        S = oracle.assemble(req.problem, with_mass=True)
+        c_ref = np.zeros(S.n)
+        for _ in range(req.steps):
+            r = oracle.transient_step(S, 1e-3, c_ref, tol=1e-13)
+            assert r.certified
+            c_ref = r.c
+        c = res.c.cpu().numpy()
+        assert c.min() >= 0.0
+        err = np.abs(c - c_ref).max() / np.abs(c_ref).max()
+        assert err <= 1e-8, (req.rid, err)
+
+
+@pytest.mark.gpu
+def test_admission_respects_budget():
+    from paper_1506_08435_amd.serve import NN_EBUDGET, Request, Server, estimate_bytes
+    from paper_1506_08435_amd import nnqp
+    reqs = _requests(8, steps=2, gap=0.0)
+    big = max(estimate_bytes(r.problem, nnqp.NN_FP64) for r in reqs)
+    budget = int(2.2 * big)
+    huge = Request(99, W.serve_problem(0, seed=11, dof_range=(2e5, 2.1e5)), 1, 0.0)
+    assert estimate_bytes(huge.problem, nnqp.NN_FP64) > budget
+    srv = Server(hbm_budget=budget, tol=1e-8)
+    rep = srv.run(reqs + [huge])
+    by = {r.rid: r for r in rep.results}
+    assert by[99].status == NN_EBUDGET
+    assert all(by[r.rid].status == 0 for r in reqs)
+    assert rep.peak_bytes <= budget
+    assert rep.deferred > 0
+    print(rep.summary())
