@@ -246,9 +246,14 @@ nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *
  * profiling is on (nn_set_profiling).  For class k: counts[k] launches and
  * total_ms[k] milliseconds measured with HIP events on the context stream.
  * Classes: 0 CG SpMV (fused direction update), 1 CG vector update,
- * 2 gradient SpMV, 3 projected-step SpMV, 4 other. */
+ * 2 gradient SpMV, 3 projected-step SpMV, 4 other.
+ * nn_set_profiling: classes = 0 turns profiling off; otherwise bit k of
+ * `classes` times class k (NN_PROF_ALL: every class).  Each timed launch is
+ * bracketed by two events on the stream, so timing fewer classes perturbs a
+ * timed run less. */
 #define NN_KCLASSES 5
-nn_status nn_set_profiling(nn_ctx *ctx, int on);
+#define NN_PROF_ALL 0x1f
+nn_status nn_set_profiling(nn_ctx *ctx, int classes);
 /* counts/total_ms/total_bytes: host arrays of NN_KCLASSES entries or NULL.
  * total_bytes is the algorithmic (perfect-cache) byte count of the timed
  * launches.  Launches that found their work already finished (CG iterations

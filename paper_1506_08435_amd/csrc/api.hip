@@ -91,7 +91,8 @@ static hipEvent_t pool_event(nn_ctx *ctx)
 
 void prof_begin(nn_ctx *ctx, int cls, double bytes)
 {
-    if (!ctx->prof) return;
+    ctx->prof_open = false;
+    if (!ctx->prof || !((ctx->prof_mask >> cls) & 1)) return;
     ProfEntry p;
     p.cls = cls;
     p.a = pool_event(ctx);
@@ -100,12 +101,14 @@ void prof_begin(nn_ctx *ctx, int cls, double bytes)
     p.valid = 1;
     (void)hipEventRecord(p.a, ctx->stream);
     ctx->prof_live.push_back(p);
+    ctx->prof_open = true;
 }
 
 void prof_end(nn_ctx *ctx)
 {
-    if (!ctx->prof || ctx->prof_live.empty()) return;
+    if (!ctx->prof_open || ctx->prof_live.empty()) return;
     (void)hipEventRecord(ctx->prof_live.back().b, ctx->stream);
+    ctx->prof_open = false;
 }
 
 void prof_add(nn_ctx *ctx, int cls, double ms, double bytes)
@@ -388,6 +391,7 @@ nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes)
     const double n = (double)A->n, nnz = (double)A->nnz, ns = (double)A->nsell;
     double b = 4.0 * (n + 1) + 4.0 * nnz;                   // CSR pattern
     b += 4.0 * (A->nslices + 1) + 12.0 * ns + 8.0 * n;      // sliced-ELL columns, values, diag
+    if (A->sl_d16) b += 2.0 * ns;                           // int16 column offsets
     if (A->mval) b += 16.0 * ns + 8.0 * n;                  // capacity + transient values, diag
     b += 11.0 * 8.0 * n + n;                                // solver work vectors + mask
     if (precision == NN_MIXED) b += 4.0 * ns + 40.0 * n;    // float32 values and vectors
@@ -402,6 +406,7 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
     int *iv[] = {A->rowptr, A->col, A->sl_off, A->sl_col};
     for (int *p : iv)
         if (p) (void)hipFree(p);
+    if (A->sl_d16) (void)hipFree(A->sl_d16);
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
     for (double *p : dv)
         if (p) (void)hipFree(p);
@@ -542,10 +547,11 @@ nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
     return solve_batch_impl(ctx, nprob, K, f_dev, opts, c_dev, active_dev, stats, 0.0);
 }
 
-nn_status nn_set_profiling(nn_ctx *ctx, int on)
+nn_status nn_set_profiling(nn_ctx *ctx, int classes)
 {
     NN_CHECK_CTX(ctx);
-    ctx->prof = on != 0;
+    ctx->prof = classes != 0;
+    ctx->prof_mask = classes & NN_PROF_ALL;
     return NN_OK;
 }
 

@@ -208,6 +208,20 @@ nn_status sell_build(nn_ctx *ctx, nn_matrix *A, const int64_t *rowptr_host, cons
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A)
 {
     if (A->n > 0) {
+        // int16 column offsets for the float32-value passes, kept only when
+        // every |col - row| fits
+        short *sd = nullptr;
+        NN_HIP_TRY(ctx, hipMalloc(&sd, sizeof(short) * std::max<int64_t>(A->nsell, 1)));
+        launch_sell_d16(ctx, A, sd);
+        static const int kMaxOp[1] = {OP_MAX};
+        double span = 0.0;
+        nn_status rc = host_reduce(ctx, A->n, 1, kMaxOp, &span);
+        if (rc != NN_OK) {
+            (void)hipFree(sd);
+            return rc;
+        }
+        if (span <= 32767.0) A->sl_d16 = sd;
+        else (void)hipFree(sd);
         NN_HIP_TRY(ctx, hipMalloc(&A->diag, sizeof(double) * A->n));
         launch_diag(ctx, A, A->val, A->diag);
         std::vector<double> d(A->n);

@@ -74,6 +74,7 @@ struct BDev {
     const int *s0, *nrow;           // per problem: first slice, rows
     const int *const *so;           // per problem sliced-ELL offsets
     const int *const *sc;           // per problem sliced-ELL columns (local)
+    const short *const *sd;         // per problem int16 offsets col - row (or null)
     const double *const *v64;       // per problem float64 values
     const float *const *v32;        // per problem float32 values (mixed precision)
     const double *const *diag;      // per problem diagonal
@@ -132,17 +133,32 @@ __device__ __forceinline__ void for_bslices(const BDev &B, const int (&ops)[NV],
     }
 }
 
+// Column modes of the batched matrix passes (as in the single-problem
+// kernels): int32 columns, or int16 offsets from the row (float32 values,
+// when every member has them).  Float64 values load with the non-temporal
+// hint, float32 values normally (as in the single-problem kernels).
+enum { CM_I32 = 0, CM_D16 = 2 };
+
+__device__ __forceinline__ double bld_val(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float bld_val(const float *p) { return *p; }
+
 // Row sums of slice s of problem p: sum_k val(k) x(col(k)), with the same
 // wave-uniform load phases (eight entries each) and column order as the
 // single-problem kernels.  Padding and rows past the end hold valid columns.
-template <int WMAX, class VT, class X>
+template <int WMAX, int CM, class VT, class X>
 __device__ __forceinline__ double bsell_row(const BDev &B, const VT *__restrict__ sv, int p, int s,
                                             X x)
 {
     const int lane = threadIdx.x & 63;
     const int ls = s - B.s0[p];
+    const int lrow = ls * kSlice + lane;
     const int *__restrict__ so = B.so[p];
     const int *__restrict__ sc = B.sc[p];
+    const short *__restrict__ sd = B.sd[p];
+    auto col = [&](int e) {
+        if (CM == CM_D16) return lrow + (int)sd[e];
+        return sc[e];
+    };
     const int off = so[ls];
     const int w = (so[ls + 1] - off) >> 6;
     double acc = 0.0;
@@ -154,8 +170,8 @@ __device__ __forceinline__ double bsell_row(const BDev &B, const VT *__restrict_
 #pragma unroll
         for (int k = 0; k < H; k++) {
             if (h0 + k < w) {
-                cc[k] = sc[off + (h0 + k) * kSlice + lane];
-                vv[k] = sv[off + (h0 + k) * kSlice + lane];
+                cc[k] = col(off + (h0 + k) * kSlice + lane);
+                vv[k] = bld_val(sv + off + (h0 + k) * kSlice + lane);
             } else {
                 cc[k] = 0;
                 vv[k] = VT(0);
@@ -167,7 +183,7 @@ __device__ __forceinline__ double bsell_row(const BDev &B, const VT *__restrict_
     }
     for (int k = WMAX; k < w; k++) {
         const int e = off + k * kSlice + lane;
-        acc += (double)sv[e] * x(sc[e]);
+        acc += (double)bld_val(sv + e) * x(col(e));
     }
     return acc;
 }
@@ -205,7 +221,7 @@ __global__ void kb_transient_rhs(BDev B, double dt, double *__restrict__ ft)
                    [&](int p, int s, int i, int il, bool row, double (&)[1]) {
                        const double *c = B.c[p];
                        const double mc =
-                           bsell_row<WMAX>(B, B.mv[p], p, s, [&](int j) { return c[j]; });
+                           bsell_row<WMAX, CM_I32>(B, B.mv[p], p, s, [&](int j) { return c[j]; });
                        if (row) ft[i] = B.f0[p][il] + mc / dt;
                    });
 }
@@ -219,7 +235,7 @@ __global__ void kb_grad(BDev B, double *__restrict__ g)
                    [&](int p, int s, int i, int il, bool row, double (&a)[5]) {
                        const double *c = B.c[p];
                        const double kc =
-                           bsell_row<WMAX>(B, B.v64[p], p, s, [&](int j) { return c[j]; });
+                           bsell_row<WMAX, CM_I32>(B, B.v64[p], p, s, [&](int j) { return c[j]; });
                        if (!row) return;
                        const double gi = kc - B.f[p][il];
                        const double cv = c[il];
@@ -237,7 +253,7 @@ __global__ void kb_grad(BDev B, double *__restrict__ g)
 // s = P(c + t_p d) - c formed for every gathered column, ks = K s (written to
 // buffer ksbuf_p when write_ks); g.s, s.Ks, s.s.  With a mask only free rows
 // are formed (d vanishes elsewhere, so s does too).
-template <int WMAX, class VT, class VD>
+template <int WMAX, int CM, class VT, class VD>
 __global__ void kb_trial(BDev B, const VT *const *vals, const VD *__restrict__ d,
                          const double *__restrict__ g, const uint8_t *__restrict__ mask,
                          double *__restrict__ ks0, double *__restrict__ ks1, int write_ks)
@@ -254,7 +270,7 @@ __global__ void kb_trial(BDev B, const VT *const *vals, const VD *__restrict__ d
                        };
                        const bool live = row && (mask == nullptr || mask[i] != 0);
                        if (__ballot(live) == 0) return;
-                       const double ksv = bsell_row<WMAX>(B, vals[p], p, s, sv);
+                       const double ksv = bsell_row<WMAX, CM>(B, vals[p], p, s, sv);
                        if (!live) return;
                        if (write_ks) (B.bp[p].ksbuf ? ks1 : ks0)[i] = ksv;
                        const double si = sv(il);
@@ -327,7 +343,7 @@ __global__ void kb_cg_setup(BDev B, double *__restrict__ g, const double *__rest
 // CG matrix pass for the running problems: p <- z + beta_p p and
 // q <- K z + beta_p q on the free rows (one gather of z, as in the
 // single-problem pass); p.q.
-template <int WMAX, class VT, class VV>
+template <int WMAX, int CM, class VT, class VV>
 __global__ void kb_cg_spmv(BDev B, const VT *const *vals, const uint8_t *__restrict__ mask,
                            const VV *__restrict__ z, VV *__restrict__ pv, VV *__restrict__ q)
 {
@@ -337,7 +353,7 @@ __global__ void kb_cg_spmv(BDev B, const VT *const *vals, const uint8_t *__restr
                        const bool live = row && mask[i] != 0;
                        if (__ballot(live) == 0) return;
                        const int r0 = B.s0[p] * kSlice;
-                       const double kz = bsell_row<WMAX>(
+                       const double kz = bsell_row<WMAX, CM>(
                            B, vals[p], p, s, [&](int j) { return (double)z[r0 + j]; });
                        if (!live) return;
                        const double beta = B.bp[p].beta;
@@ -614,6 +630,9 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         return NN_OK;
     }
     const int64_t R = S * kSlice;
+    bool all_d16 = true;
+    for (int p = 0; p < P; p++)
+        if (K[p]->n > 0 && !K[p]->sl_d16) all_d16 = false;
 
     // ---- tables, work vectors, lists, pinned state mirrors
     Arena A;
@@ -621,6 +640,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     int *d_list = A.d<int>((size_t)2 + P + S);
     const int **d_so = A.d<const int *>(P), **d_sc = A.d<const int *>(P),
               **d_rp = A.d<const int *>(P);
+    const short **d_sd = A.d<const short *>(P);
     const double **d_v64 = A.d<const double *>(P), **d_diag = A.d<const double *>(P),
                  **d_f = A.d<const double *>(P), **d_f0 = A.d<const double *>(P),
                  **d_mv = A.d<const double *>(P);
@@ -645,7 +665,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     }
     BProb *hb = A.h<BProb>(P);
     double *pres = A.h<double>((size_t)P * kBNV);
-    const void **tab = (const void **)A.h<void *>((size_t)P * 11);
+    const void **tab = (const void **)A.h<void *>((size_t)P * 12);
     // Uploads from pinned memory read their source when they execute, so
     // the host writes each upload into a staging copy that it does not touch
     // again until the copy's event has completed.
@@ -676,10 +696,11 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         tab[8 * P + p] = active ? active[p] : nullptr;
         tab[9 * P + p] = f[p];
         tab[10 * P + p] = K[p]->mval;
+        tab[11 * P + p] = K[p]->sl_d16;
     }
     {
-        void *dsts[11] = {d_so, d_sc, d_rp, d_v64, d_diag, d_f, d_v32, d_c, d_act, d_f0, d_mv};
-        for (int k = 0; k < 11; k++)
+        void *dsts[12] = {d_so, d_sc, d_rp, d_v64, d_diag, d_f, d_v32, d_c, d_act, d_f0, d_mv, d_sd};
+        for (int k = 0; k < 12; k++)
             NN_HIP_TRY(ctx, hipMemcpyAsync(dsts[k], tab + (size_t)k * P, sizeof(void *) * P,
                                            hipMemcpyHostToDevice, st));
         NN_HIP_TRY(ctx, hipMemcpyAsync(d_sprob, sprob.data(), sizeof(int) * S,
@@ -701,6 +722,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     B.nrow = d_nrow;
     B.so = d_so;
     B.sc = d_sc;
+    B.sd = d_sd;
     B.v64 = d_v64;
     B.v32 = d_v32;
     B.diag = d_diag;
@@ -872,15 +894,22 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     const double *gptr = g;
     auto trial = [&](bool along_w, const uint8_t *m, int write_ks) {
         const int gr = grid();
-        if (mixed) {
+        if (mixed && all_d16) {
             if (along_w)
-                NN_BDISPATCH(wmax, (kb_trial<WM, float, float>), gr, blk, st, B, d_v32,
+                NN_BDISPATCH(wmax, (kb_trial<WM, CM_D16, float, float>), gr, blk, st, B, d_v32,
                              (const float *)w32, gptr, m, ks0, ks1, write_ks);
             else
-                NN_BDISPATCH(wmax, (kb_trial<WM, float, double>), gr, blk, st, B, d_v32, gptr,
-                             gptr, m, ks0, ks1, write_ks);
+                NN_BDISPATCH(wmax, (kb_trial<WM, CM_D16, float, double>), gr, blk, st, B, d_v32,
+                             gptr, gptr, m, ks0, ks1, write_ks);
+        } else if (mixed) {
+            if (along_w)
+                NN_BDISPATCH(wmax, (kb_trial<WM, CM_I32, float, float>), gr, blk, st, B, d_v32,
+                             (const float *)w32, gptr, m, ks0, ks1, write_ks);
+            else
+                NN_BDISPATCH(wmax, (kb_trial<WM, CM_I32, float, double>), gr, blk, st, B, d_v32,
+                             gptr, gptr, m, ks0, ks1, write_ks);
         } else {
-            NN_BDISPATCH(wmax, (kb_trial<WM, double, double>), gr, blk, st, B, d_v64,
+            NN_BDISPATCH(wmax, (kb_trial<WM, CM_I32, double, double>), gr, blk, st, B, d_v64,
                          along_w ? (const double *)w64 : gptr, gptr, m, ks0, ks1, write_ks);
         }
         hipLaunchKernelGGL((kb_finalize<3, 0>), dim3(fgrid()), dim3(kFinBlock), 0, st, B,
@@ -898,12 +927,15 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     // (problems), optionally bracketed by timing events
     auto cg_iter = [&](hipStream_t s, int gr, int fg, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[0], s);
-        if (mixed)
-            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, float, float>), gr, blk, s, B, d_v32, mask, z32,
-                         p32, q32);
+        if (mixed && all_d16)
+            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, CM_D16, float, float>), gr, blk, s, B, d_v32, mask,
+                         z32, p32, q32);
+        else if (mixed)
+            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, CM_I32, float, float>), gr, blk, s, B, d_v32, mask,
+                         z32, p32, q32);
         else
-            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, double, double>), gr, blk, s, B, d_v64, mask, z64,
-                         p64, q64);
+            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, CM_I32, double, double>), gr, blk, s, B, d_v64, mask,
+                         z64, p64, q64);
         if (ev) (void)hipEventRecord(ev[1], s);
         hipLaunchKernelGGL((kb_finalize<1, 2>), dim3(fg), dim3(kFinBlock), 0, s, B, opsc(OP_SUM),
                            0.0);
@@ -968,6 +1000,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     hipEvent_t *chunk_ev = ctx->prof ? ev_cg.ev.data() : nullptr;
 
     const double vb = mixed ? 4.0 : 8.0;   // bytes per CG vector entry and per value
+    const double ib = (mixed && all_d16) ? 2.0 : 4.0;   // bytes per column index
     std::vector<int> it_before(P);
     std::vector<double> b_spmv(chunk), b_upd(chunk);
     nn_status err = NN_OK;
@@ -1051,7 +1084,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                 const double n = nrow[p], nz = (double)K[p]->nnz;
                 SP[p].spmvs++;
                 SP[p].cauchy_trials++;
-                SP[p].bytes_moved += 4.0 * (n + 1) + (4.0 + vb) * nz + 32.0 * n;
+                SP[p].bytes_moved += 4.0 * (n + 1) + (ib + vb) * nz + 32.0 * n;
                 const bool ok = ok_dec(p, r[0], r[1], r[2]);
                 if (cst[p] == C_FIRST) {
                     if (ok) {
@@ -1138,7 +1171,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                 const int ran = hb[p].it - it_before[p];
                 if (ran <= 0) continue;
                 const double n = nrow[p], nf = hb[p].n_free, nzf = hb[p].nnz_free;
-                const double bs = n + 4.0 * nf + (4.0 + vb) * nzf + 5.0 * vb * nf;
+                const double bs = n + 4.0 * nf + (ib + vb) * nzf + 5.0 * vb * nf;
                 const double bu = n + 8.0 * vb * nf;
                 for (int k = 0; k < ran && k < chunk; k++) {
                     b_spmv[k] += bs;
@@ -1155,8 +1188,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                             hipSuccess &&
                         hipEventElapsedTime(&m2, chunk_ev[4 * k + 2], chunk_ev[4 * k + 3]) ==
                             hipSuccess) {
-                        prof_add(ctx, KC_CG_SPMV, m1, b_spmv[k]);
-                        prof_add(ctx, KC_CG_UPDATE, m2, b_upd[k]);
+                        if ((ctx->prof_mask >> KC_CG_SPMV) & 1) prof_add(ctx, KC_CG_SPMV, m1, b_spmv[k]);
+                        if ((ctx->prof_mask >> KC_CG_UPDATE) & 1) prof_add(ctx, KC_CG_UPDATE, m2, b_upd[k]);
                     }
                 }
             }
@@ -1225,7 +1258,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                 const double n = nrow[p], nz = (double)K[p]->nnz;
                 SP[p].spmvs++;
                 SP[p].search_trials++;
-                SP[p].bytes_moved += 4.0 * (n + 1) + (4.0 + vb) * nz + 32.0 * n;
+                SP[p].bytes_moved += 4.0 * (n + 1) + (ib + vb) * nz + 32.0 * n;
                 if (r[0] < 0.0 && r[0] + 0.5 * r[1] <= kMu0 * r[0]) {
                     sst[p] = 2;
                 } else {

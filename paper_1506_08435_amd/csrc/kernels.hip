@@ -138,6 +138,27 @@ __device__ __forceinline__ void for_rows(const Part &P, Body body)
     }
 }
 
+// Column readers of the sliced-ELL entries (entry e of the slice holding row).
+// Float32-value passes read int16 offsets from the row when the pattern
+// allows (|col - row| <= 32767); float64-value passes, and patterns with
+// wider offsets, read int32 columns.
+struct ColsI32 {
+    const int *c;
+    __device__ __forceinline__ int operator()(int e, int) const { return c[e]; }
+};
+struct ColsD16 {
+    const short *d;
+    __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
+};
+
+// Matrix values are read once per pass.  Float64 values are loaded with the
+// non-temporal hint, which keeps the value stream from displacing the
+// gathered vector in the caches (measured on the 128^3 pattern: the CG matrix
+// pass 97 -> 80 us); for float32 values the hint is slower, so they load
+// normally.
+__device__ __forceinline__ double ld_val(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_val(const float *p) { return *p; }
+
 // Sliced-ELL product row by row: for each owned row i with active(i), the sum
 // over the row's entries k = 0..w-1 (column order) of val * x(col), then
 // epi(i, sum, pre(i)).  Padding entries have value 0 and column i.
@@ -153,9 +174,8 @@ __device__ __forceinline__ void for_rows(const Part &P, Body body)
 #ifndef NNQP_LOAD_PHASE
 #define NNQP_LOAD_PHASE 8
 #endif
-template <int WMAX, class VT, class Act, class Pre, class X, class Epi>
-__device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__ so,
-                                          const int *__restrict__ sc,
+template <int WMAX, class VT, class Cols, class Act, class Pre, class X, class Epi>
+__device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__ so, Cols sc,
                                           const VT *__restrict__ sv, Act active, Pre pre, X x,
                                           Epi epi)
 {
@@ -198,8 +218,8 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
 #pragma unroll
                 for (int k = 0; k < H; k++) {
                     if (h0 + k < w[t]) {
-                        cc[t][k] = sc[off[t] + (h0 + k) * kSlice + lane];
-                        vv[t][k] = sv[off[t] + (h0 + k) * kSlice + lane];
+                        cc[t][k] = sc(off[t] + (h0 + k) * kSlice + lane, row[t]);
+                        vv[t][k] = ld_val(sv + off[t] + (h0 + k) * kSlice + lane);
                     } else {
                         cc[t][k] = 0;
                         vv[t][k] = VT(0);
@@ -215,7 +235,7 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
         for (int t = 0; t < NS; t++) {
             for (int k = WMAX; k < w[t]; k++) {
                 const int e = off[t] + k * kSlice + lane;
-                acc[t] += (double)sv[e] * x(sc[e]);
+                acc[t] += (double)ld_val(sv + e) * x(sc(e, row[t]));
             }
             if (act[t]) epi(row[t], acc[t], pv[t]);
         }
@@ -240,9 +260,8 @@ struct AllRows {
 __device__ __forceinline__ double proj0(double x) { return x > 0.0 ? x : 0.0; }
 
 // ---------------------------------------------------------------- kernels
-template <int WMAX>
-__global__ __launch_bounds__(kBlock) void k_matvec(Part P, const int *__restrict__ so,
-                                                   const int *__restrict__ sc,
+template <int WMAX, class Cols>
+__global__ __launch_bounds__(kBlock) void k_matvec(Part P, const int *__restrict__ so, Cols sc,
                                                    const double *__restrict__ v,
                                                    const double *__restrict__ x, double *__restrict__ y)
 {
@@ -251,9 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec(Part P, const int *__restrict
 }
 
 // ft = f + (M c) / dt
-template <int WMAX>
-__global__ __launch_bounds__(kBlock) void k_transient_rhs(Part P, const int *__restrict__ so,
-                                                          const int *__restrict__ sc,
+template <int WMAX, class Cols>
+__global__ __launch_bounds__(kBlock) void k_transient_rhs(Part P, const int *__restrict__ so, Cols sc,
                                                           const double *__restrict__ m,
                                                           const double *__restrict__ c,
                                                           const double *__restrict__ f, double dt,
@@ -268,9 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_transient_rhs(Part P, const int *__r
 // |pg|^2, #non-finite, ||min(c,g)||_inf, min c, #(c == 0)
 constexpr uint32_t kOpsGrad = OPS5(OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM);
 
-template <int WMAX>
-__global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__ so,
-                                                 const int *__restrict__ sc,
+template <int WMAX, class Cols>
+__global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__ so, Cols sc,
                                                  const double *__restrict__ v,
                                                  const double *__restrict__ c,
                                                  const double *__restrict__ f,
@@ -298,9 +315,8 @@ __global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__
 // skipped when a mask is given (there d = 0, so s = 0 and they add nothing).
 constexpr uint32_t kOpsTrial = OPS3(OP_SUM, OP_SUM, OP_SUM);
 
-template <int WMAX, class VT, class VD>
-__global__ __launch_bounds__(kBlock) void k_trial(Part P, const int *__restrict__ so,
-                                                  const int *__restrict__ sc,
+template <int WMAX, class VT, class VD, class Cols>
+__global__ __launch_bounds__(kBlock) void k_trial(Part P, const int *__restrict__ so, Cols sc,
                                                   const VT *__restrict__ v,
                                                   const double *__restrict__ c,
                                                   const VD *__restrict__ d, double t,
@@ -413,9 +429,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
 // formed together, using K p = K z + beta (K p_old): only z is gathered, and
 // p, q are updated in place on the free rows; partials of p.q into SLOT_Q.
 // Columns outside the free set contribute 0 because z vanishes there.
-template <int WMAX, class VT, class VV>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restrict__ so,
-                                                    const int *__restrict__ sc,
+template <int WMAX, class VT, class VV, class Cols>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restrict__ so, Cols sc,
                                                     const VT *__restrict__ v,
                                                     const uint8_t *__restrict__ mask,
                                                     const VV *__restrict__ z,
@@ -614,6 +629,28 @@ __global__ __launch_bounds__(kBlock) void k_sell_tail(int n, int nslices, const 
     }
 }
 
+// int16 offsets col - row of the sliced-ELL entries and the largest |col - row|
+// over real rows (one partial per block, SLOT_HOST).  Lanes past the last row
+// get offsets that point at the last row, so every decoded column is valid.
+__global__ __launch_bounds__(kBlock) void k_sell_d16(Part P, const int *__restrict__ so,
+                                                     const int *__restrict__ sc,
+                                                     short *__restrict__ sd, double *partials)
+{
+    double a[1];
+    red_init<OP_MAX, 1>(a);
+    for_rows(P, [&](int i, bool act) {
+        const int s = i / kSlice, lane = i % kSlice;
+        const int off = so[s], w = (so[s + 1] - off) / kSlice;
+        for (int k = 0; k < w; k++) {
+            const int e = off + k * kSlice + lane;
+            const int d = act ? sc[e] - i : (P.n - 1) - i;
+            if (act) a[0] = fmax(a[0], (double)abs(d));
+            sd[e] = (short)max(-32768, min(32767, d));
+        }
+    });
+    block_partial<OP_MAX, 1>(a, slot_ptr(partials, SLOT_HOST));
+}
+
 // ---------------------------------------------------------------- launchers
 // Instantiate KERNEL for the slice width class of the matrix; KERNEL may be a
 // parenthesised template-id that names the width parameter WM.
@@ -635,7 +672,7 @@ void launch_matvec(nn_ctx *ctx, const nn_matrix *A, const double *vals, const do
 {
     if (A->n == 0) return;
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, (k_matvec<WM>), P.nb, P, A->sl_off, A->sl_col, vals, x, y);
+    NN_DISPATCH_W(A->wmax, (k_matvec<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col}, vals, x, y);
 }
 
 void launch_transient_rhs(nn_ctx *ctx, const nn_matrix *A, const double *c, const double *f,
@@ -643,7 +680,8 @@ void launch_transient_rhs(nn_ctx *ctx, const nn_matrix *A, const double *c, cons
 {
     if (A->n == 0) return;
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, (k_transient_rhs<WM>), P.nb, P, A->sl_off, A->sl_col, A->mval, c, f, dt, ft);
+    NN_DISPATCH_W(A->wmax, (k_transient_rhs<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col}, A->mval,
+                  c, f, dt, ft);
 }
 
 void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v)
@@ -656,24 +694,38 @@ void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const doub
                  const double *f, double *g)
 {
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, (k_grad<WM>), P.nb, P, A->sl_off, A->sl_col, vals, c, f, g, ctx->partials);
+    NN_DISPATCH_W(A->wmax, (k_grad<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col}, vals, c, f, g,
+                  ctx->partials);
 }
 
 void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
                   double t, const double *g, const uint8_t *mask, double *ks)
 {
     Part P = make_part(A->n);
-    if (V.v32) {
-        if (d.f32) {
-            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float>), P.nb, P, A->sl_off, A->sl_col, V.v32,
-                          c, d.f32, t, g, mask, ks, ctx->partials);
-        } else {
-            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double>), P.nb, P, A->sl_off, A->sl_col,
+    if (V.v32 && A->sl_d16) {
+        const ColsD16 cols{A->sl_d16};
+        if (d.f32)
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsD16>), P.nb, P, A->sl_off, cols,
+                          V.v32, c, d.f32, t, g, mask, ks, ctx->partials);
+        else
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsD16>), P.nb, P, A->sl_off, cols,
                           V.v32, c, d.f64, t, g, mask, ks, ctx->partials);
-        }
+    } else if (V.v32) {
+        const ColsI32 cols{A->sl_col};
+        if (d.f32)
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsI32>), P.nb, P, A->sl_off, cols,
+                          V.v32, c, d.f32, t, g, mask, ks, ctx->partials);
+        else
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsI32>), P.nb, P, A->sl_off, cols,
+                          V.v32, c, d.f64, t, g, mask, ks, ctx->partials);
     } else {
-        NN_DISPATCH_W(A->wmax, (k_trial<WM, double, double>), P.nb, P, A->sl_off, A->sl_col, V.v64,
-                      c, d.f64, t, g, mask, ks, ctx->partials);
+        const ColsI32 cols{A->sl_col};
+        if (d.f32)
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, double, float, ColsI32>), P.nb, P, A->sl_off, cols,
+                          V.v64, c, d.f32, t, g, mask, ks, ctx->partials);
+        else
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, double, double, ColsI32>), P.nb, P, A->sl_off, cols,
+                          V.v64, c, d.f64, t, g, mask, ks, ctx->partials);
     }
 }
 
@@ -703,13 +755,18 @@ void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int m
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
-    if (V.v32) {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float>), P.nb, P, A->sl_off, A->sl_col, V.v32,
-                      W.mask, W.z32, W.p32, W.q32, ctx->partials, ctx->scal, j, max_it, rtol * rtol);
+    if (V.v32 && A->sl_d16) {
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16>), P.nb, P, A->sl_off,
+                      ColsD16{A->sl_d16}, V.v32, W.mask, W.z32, W.p32, W.q32, ctx->partials,
+                      ctx->scal, j, max_it, rtol * rtol);
+    } else if (V.v32) {
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsI32>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v32, W.mask, W.z32, W.p32, W.q32, ctx->partials,
+                      ctx->scal, j, max_it, rtol * rtol);
     } else {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double>), P.nb, P, A->sl_off, A->sl_col,
-                      V.v64, W.mask, W.z, W.p0, W.q, ctx->partials, ctx->scal, j, max_it,
-                      rtol * rtol);
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double, ColsI32>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v64, W.mask, W.z, W.p0, W.q, ctx->partials, ctx->scal,
+                      j, max_it, rtol * rtol);
     }
 }
 
@@ -755,6 +812,12 @@ void launch_axpby_vals(nn_ctx *ctx, int64_t nnz, const double *m, double dt, con
     if (nb > 2048) nb = 2048;
     if (nb < 1) nb = 1;
     k_vals_mdt_plus_k<<<(int)nb, kBlock, 0, ctx->stream>>>(nnz, m, dt, k, out);
+}
+
+void launch_sell_d16(nn_ctx *ctx, const nn_matrix *A, short *sd)
+{
+    Part P = make_part(A->n);
+    k_sell_d16<<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, A->sl_col, sd, ctx->partials);
 }
 
 void launch_diag(nn_ctx *ctx, const nn_matrix *A, const double *vals, double *diag)

@@ -95,6 +95,7 @@ struct nn_matrix {
     int64_t nslices = 0, nsell = 0;
     int *sl_off = nullptr;     // [nslices+1] first entry of each 64-row slice
     int *sl_col = nullptr;     // [nsell] column of each sliced-ELL entry (padding: own row)
+    short *sl_d16 = nullptr;   // [nsell] col - row as int16 when every offset fits, else null
     double *val = nullptr;     // K values, sliced-ELL order [nsell]
     double *mval = nullptr;    // M values, sliced-ELL order (or null)
     double *diag = nullptr;    // diag(K)
@@ -119,6 +120,8 @@ struct nn_ctx {
     nnqp::Workspace ws;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool prof = false;
+    int prof_mask = 0;         // classes timed while prof is on
+    bool prof_open = false;    // a begin event was recorded and awaits its end
     std::vector<nnqp::ProfEntry> prof_live;
     std::vector<hipEvent_t> ev_pool;
     int64_t prof_count[NN_KCLASSES] = {0};
@@ -191,6 +194,8 @@ void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active);
 // out = m/dt + k
 void launch_axpby_vals(nn_ctx *ctx, int64_t nnz, const double *m, double dt, const double *k,
                        double *out);
+// [host] int16 offsets col - row into sd; max |col - row| over real rows (max)
+void launch_sell_d16(nn_ctx *ctx, const nn_matrix *A, short *sd);
 void launch_diag(nn_ctx *ctx, const nn_matrix *A, const double *vals, double *diag);
 // csr -> sliced-ELL: col, values (and capacity values), diag
 void launch_csr_to_sell(nn_ctx *ctx, nn_matrix *A, const double *csr_val, const double *csr_mval);

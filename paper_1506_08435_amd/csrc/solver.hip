@@ -82,7 +82,10 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     if (mixed) VS.v32 = vals32;
     else VS.v64 = vals;
     const double vb = mixed ? 4.0 : 8.0;                  // bytes per vector entry in CG
-    const double spmv_s = 4.0 * (n + 1) + (4.0 + (mixed ? 4.0 : 8.0)) * A->nnz + 16.0 * n;
+    // index bytes of the search and CG passes: float32-value passes read
+    // int16 column offsets when the matrix has them
+    const double ib = (mixed && A->sl_d16) ? 2.0 : 4.0;
+    const double spmv_s = 4.0 * (n + 1) + (ib + vb) * A->nnz + 16.0 * n;
     Dir dir_g, dir_w;
     dir_g.f64 = W.g;
     if (mixed) dir_w.f32 = W.w32;
@@ -215,14 +218,14 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             const int ran = H.it - it_seen;
             // byte model of the launches that did work; the rest exited at once
             const double nf = H.n_free, nzf = H.nnz_free;
-            // matrix pass on the free rows (indices 4 B, values 8 or 4 B), z gathered,
+            // matrix pass on the free rows (indices 4 or 2 B, values 8 or 4 B), z gathered,
             // p and q read and written; update: p, q, dm, w, r read, w, r, z written
-            const double b_spmv = n + 4.0 * nf + (4.0 + (mixed ? 4.0 : 8.0)) * nzf + 5.0 * vb * nf;
+            const double b_spmv = n + 4.0 * nf + (ib + vb) * nzf + 5.0 * vb * nf;
             const double b_upd = n + 8.0 * vb * nf;
+            int seen[NN_KCLASSES] = {0};   // launches of each class in this chunk
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
-                const int idx = (int)(e - mark) / 2;
-                P.valid = idx < ran;
+                P.valid = seen[P.cls]++ < ran;
                 P.bytes = P.cls == KC_CG_SPMV ? b_spmv : b_upd;
             }
             S.bytes_moved += ran * (b_spmv + b_upd);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libnnqp.so")
 NN_OK, NN_EINVAL, NN_ENONFINITE, NN_ENOTSPD, NN_EMAXIT, NN_EOOM, NN_EHIP, NN_EBUDGET = range(8)
 NN_FP64, NN_MIXED = 0, 1
 NN_KCLASSES = 5
+NN_PROF_ALL = 0x1F
 KCLASS_NAMES = ("cg_spmv", "cg_update", "grad", "trial", "other")
 STATUS_NAMES = {0: "NN_OK", 1: "NN_EINVAL", 2: "NN_ENONFINITE", 3: "NN_ENOTSPD", 4: "NN_EMAXIT",
                 5: "NN_EOOM", 6: "NN_EHIP", 7: "NN_EBUDGET"}
@@ -335,8 +336,13 @@ class Context:
                 [st_arr[k].as_dict() for k in range(P)], st)
 
     # ---------------------------------------------------------------- profiling
-    def set_profiling(self, on: bool):
-        self._check(self.lib.nn_set_profiling(self.handle, int(on)), "nn_set_profiling")
+    def set_profiling(self, on, classes=None):
+        """Time kernel launches with HIP events: on=False stops; `classes`
+        (names from KCLASS_NAMES) limits timing to those classes."""
+        mask = 0
+        if on:
+            mask = NN_PROF_ALL if classes is None else sum(1 << KCLASS_NAMES.index(c) for c in classes)
+        self._check(self.lib.nn_set_profiling(self.handle, mask), "nn_set_profiling")
 
     def kernel_times(self, reset: bool = False) -> dict:
         counts = np.zeros(NN_KCLASSES, dtype=np.int64)
