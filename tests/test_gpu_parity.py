@@ -524,3 +524,24 @@ def test_full_size_batch_512_certified(ctx):
         err = np.abs(_np(cs[k]) - ref.c).max() / np.abs(ref.c).max()
         print(f"member {k} (n={S.n}): err vs oracle {err:.2e}")
         assert err <= 1e-6   # KKT tol 1e-8 bounds the error by cond(K) * 1e-8
+
+
+def test_mixed_precision_wide_pattern_matches_oracle(ctx):
+    """A pattern whose column offsets exceed int16 (plane offset 184^2 =
+    33,856): the float32 passes fall back to int32 columns."""
+    from paper_1506_08435_amd import nnqp
+    cells = (185, 185, 3)
+    f = W.cell_box_indicator(cells, (69, 69, 0), (116, 116, 3))
+    p = W.box_problem("wide3d", cells, 1.0 / 185, W.aniso3d_tensor(), f_elem=f)
+    K, F, _ = ctx.assemble(p)
+    S = oracle.assemble(p)
+    assert int(np.abs(S.col.astype(np.int64) - np.repeat(np.arange(S.n), np.diff(S.rowptr))).max()) > 32767
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-10, precision=nnqp.NN_MIXED)
+    ref = oracle.solve(S, tol=1e-13)
+    c = _np(c)
+    assert c.min() >= 0.0
+    err = np.abs(c - ref.c).max() / np.abs(ref.c).max()
+    assert err <= MIXED_TOL, err
+    assert oracle.kkt(S, c).r <= 1.01e-10
+    c64, _, _ = ctx.solve_nonneg(K, F, tol=1e-10)
+    assert np.abs(_np(c64) - ref.c).max() / np.abs(ref.c).max() <= PARITY_TOL

@@ -97,3 +97,18 @@ def test_admission_respects_budget():
     assert rep.peak_bytes <= budget
     assert rep.deferred > 0
     print(rep.summary())
+
+
+@pytest.mark.gpu
+def test_admission_estimate_bounds_assembled_bytes():
+    """The pre-assembly estimate used for admission is never below the
+    assembled request's own figure (nn_matrix_bytes + f, c, active)."""
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import estimate_bytes
+    ctx = nnqp.Context(0)
+    for k in range(8):
+        p = W.serve_problem(k, seed=21, dof_range=(500, 60000))
+        K, F, _ = ctx.assemble(p, with_mass=True)
+        for prec in (nnqp.NN_FP64, nnqp.NN_MIXED):
+            assert estimate_bytes(p, prec) >= K.bytes(prec) + 17 * K.n, (k, prec)
+        K.free()
