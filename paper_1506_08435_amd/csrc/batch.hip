@@ -1,28 +1,39 @@
 // Batched solver: many independent non-negative QPs (Sec. 2.1.3, eq.
-// non-negative) advanced together by one set of launches.
+// non-negative) advanced together.
 //
-// Every step of the TRON-style outer iteration (the same steps, constants and
-// tests as the single-problem solver) is one grid-stride launch over the
-// slices of all problems; each problem keeps its own control state (Cauchy
-// step, trust radius, CG scalars, stopping test, counters) in per-problem
-// device and host arrays, and a problem that has converged drops out of the
-// launches.
+// Each member runs the single-problem method (the same steps, constants and
+// tests: gradient and KKT test, Cauchy search, Jacobi-PCG on the free face,
+// projected search, trust-region update), but the members do not move in
+// lockstep: every member carries its own phase in a device-resident state
+// machine, and one global step advances every member by one step of its own
+// phase.  A global step is four launches over all members:
 //
-// Layout: the problems keep their own sliced-ELL matrices, reached through
-// per-problem pointer tables.  The batch numbers their 64-row slices
-// consecutively (a slice never spans two problems) and concatenates the work
+//   row pass     per slice, by the member's phase: gradient g = K c - f,
+//                Cauchy trial along -g, CG matrix pass, or projected-search
+//                trial along the CG step (one sliced-ELL pass each);
+//   transition   one block per member: combine its slice partials, take the
+//                decision the host takes in the single-problem solver
+//                (convergence, trial accepted, CG step length) and choose
+//                the member's vector operation;
+//   vector pass  per slice, by that operation: Cauchy step with CG set-up,
+//                CG vector update, breakpoint search, or step along w;
+//   transition   combine the vector-pass partials (CG scalars, breakpoint),
+//                choose the member's next phase.
+//
+// A member that needs many iterations therefore does not hold the others
+// back: while it is in a long CG, the others run their own Cauchy searches,
+// gradients and CGs in the same launches.  The host only replays chunks of
+// global steps (captured once per size class as hipGraphs) and, between
+// chunks, drops finished members from the device lists the launches walk.
+//
+// Layout: the members keep their own sliced-ELL matrices, reached through
+// per-member pointer tables.  The batch numbers their 64-row slices
+// consecutively (a slice never spans two members) and concatenates the work
 // vectors over those slices, so global row s*64 + lane is local row
-// (s - first slice of its problem)*64 + lane.  Each reduction leaves one
-// partial per slice; a finalize kernel with one block per problem combines the
-// slices of its problem in a fixed order.  A member's arithmetic therefore
-// depends only on its own data: its result is bitwise the same in any batch
-// and for any launch shape the autotuner picks.
-//
-// The CG iteration (matrix pass, finalize, vector update, finalize) takes all
-// its scalars from device memory, so a chunk of iterations is captured once
-// per call into a hipGraph and replayed until every member's CG has stopped.
-// The autotuner times the batched matrix pass over block sizes and grid sizes
-// once per size class and keeps the fastest shape.
+// (s - first slice of its member)*64 + lane.  Every reduction leaves one
+// partial per slice, and a member's partials are combined by its own block
+// in a fixed order: a member's arithmetic depends only on its own data, so
+// its result is bitwise the same in any batch and for any launch shape.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -33,7 +44,7 @@
 
 #include "nnqp_internal.hpp"
 
-// 1: CG chunks replayed as a captured graph; 0: launched one by one
+// 1: chunks of global steps replayed as captured graphs; 0: launched one by one
 #ifndef NNQP_BATCH_GRAPH
 #define NNQP_BATCH_GRAPH 1
 #endif
@@ -43,50 +54,76 @@ namespace nnqp {
 namespace {
 
 constexpr int kBNV = 5;          // values per slice partial
-constexpr int kFinBlock = 256;   // threads of a finalize block (one block per problem)
+constexpr int kFinBlock = 256;   // threads of a transition block (one block per member)
 constexpr double kMu0 = 0.01;    // sufficient-decrease constant
 constexpr double kExtrap = 10.0; // Cauchy extrapolation factor
 constexpr double kInterp = 0.1;  // Cauchy interpolation factor
 constexpr double kBack = 0.5;    // projected-search backtracking factor
 constexpr int kMaxTrials = 60;
 
-// Per-problem state read and written by the batched kernels.
-struct BProb {
-    double t;          // step of the current trial / apply; 0: not taking part
-    double rz;         // r.z of the current CG iteration
-    double rr_stop;    // CG stops when r.r <= rr_stop
-    double alpha, beta;
-    double n_free, nnz_free;
-    int it;            // CG iterations done
-    int max_it;
-    int done;          // CG: 0 running, 1 stopped, 3 breakdown, 4 non-finite
-    int ksbuf;         // which K s buffer a Cauchy trial writes
-    int active;        // 1 while the problem iterates
-    int pad;
+// member phases: what the next row pass does for the member
+enum : int {
+    PH_DONE = 0,    // finished (status set)
+    PH_GRAD = 1,    // gradient and convergence test
+    PH_CAUCHY = 2,  // Cauchy search trial along -g
+    PH_CG = 3,      // CG iteration
+    PH_BREAK = 4,   // breakpoint of the step along w (vector pass only)
+    PH_SEARCH = 5,  // projected-search trial along w
+    PH_APPLYW = 6   // take the step along w (vector pass only)
+};
+// vector-pass operations chosen by the first transition
+enum : int { VO_NONE = 0, VO_SETUP = 1, VO_UPDATE = 2, VO_BREAK = 3, VO_APPLYW = 4 };
+// Cauchy search sub-states
+enum : int { CS_FIRST = 0, CS_EXT = 1, CS_INT = 2 };
+
+// Per-member state, in device memory (mirrored on the host between chunks).
+struct BState {
+    // control
+    int phase, vop, status, outer;
+    int cst, cur, ksbuf, ntrial;     // Cauchy sub-state, accepted K s buffer, trial buffer, trials
+    int it, cgdone, nsearch, max_outer;
+    int max_cg, pad0;
+    double t, tcau, ttrial;          // accepted Cauchy step, its start value, signed trial step
+    double gs, sks, ss;              // accepted Cauchy trial: g.s, s.Ks, s.s
+    double delta, normf, tol, rtol2;
+    double rz, rr_stop, alpha, beta, n_free, nnz_free;   // CG
+    double bmin, wn, ts, stepn;      // projected search along w, step length of the iteration
+    double n, nnz, ib, vb;           // rows, nonzeros, index and value bytes (byte model)
+    // report
+    double kkt_rel, kkt_nat, min_c, bytes;
+    int n_active, cg_its, spmvs, cauchy_trials, search_trials, refinements, mixed, pad1;
 };
 
 struct BDev {
     int P, nslices;
-    const int *cnt;                 // [2] slices and problems in the current lists
-    const int *plist;               // problems taking part in the current step
-    const int *slist;               // their slices, problem by problem
-    const int *sprob;               // [nslices] problem of each slice
-    const int *s0, *nrow;           // per problem: first slice, rows
-    const int *const *so;           // per problem sliced-ELL offsets
-    const int *const *sc;           // per problem sliced-ELL columns (local)
-    const short *const *sd;         // per problem int16 offsets col - row (or null)
-    const double *const *v64;       // per problem float64 values
-    const float *const *v32;        // per problem float32 values (mixed precision)
-    const double *const *diag;      // per problem diagonal
-    const int *const *rowptr;       // per problem CSR row pointers
-    double *const *c;               // per problem solution vectors (local rows)
-    const double *const *f;         // per problem loads of the solve
-    const double *const *f0;        // per problem loads (transient step: f of f + M c/dt)
-    const double *const *mv;        // per problem capacity values (transient step)
-    uint8_t *const *act_out;        // per problem active-set outputs (entries may be null)
-    BProb *bp;
+    const int *cnt;                 // [2] slices and members in the current lists
+    const int *plist;               // members taking part in the current launches
+    const int *slist;               // their slices, member by member
+    const int *sprob;               // [nslices] member of each slice
+    const int *s0, *nrow;           // per member: first slice, rows
+    const int *const *so;           // per member sliced-ELL offsets
+    const int *const *sc;           // per member sliced-ELL columns (local)
+    const short *const *sd;         // per member int16 offsets col - row (or null)
+    const double *const *v64;       // per member float64 values
+    const float *const *v32;        // per member float32 values (mixed precision)
+    const double *const *diag;      // per member diagonal
+    const int *const *rowptr;       // per member CSR row pointers
+    double *const *c;               // per member solution vectors (local rows)
+    const double *const *f;         // per member loads of the solve
+    const double *const *f0;        // per member loads (transient step: f of f + M c/dt)
+    const double *const *mv;        // per member capacity values (transient step)
+    uint8_t *const *act_out;        // per member active-set outputs (entries may be null)
+    BState *st;
     double *part;                   // [nslices][kBNV]
-    double *pres;                   // [P][kBNV]
+    double *pres;                   // [P][kBNV] (start-up reductions)
+};
+
+// Work vectors of the batched solve, concatenated over the slices.
+template <class VV>
+struct BVec {
+    double *g, *ks0, *ks1;
+    uint8_t *mask;
+    VV *w, *r, *z, *p, *q, *dm;
 };
 
 __device__ __forceinline__ double bcomb(int op, double a, double b)
@@ -102,9 +139,9 @@ __device__ __forceinline__ double bident(int op)
 __device__ __forceinline__ double proj0b(double x) { return x > 0.0 ? x : 0.0; }
 
 // Walk the slices of the current list grid-stride, one wavefront per slice.
-// For a slice of a problem with take(p): body(p, s, global row, local row, row
+// For a slice of a member with take(p): body(p, s, global row, local row, row
 // exists, a); every listed slice then stores its wave-combined partials
-// (identities when the problem did not take part).
+// (identities when the member did not take part).
 template <int NV, class Take, class Body>
 __device__ __forceinline__ void for_bslices(const BDev &B, const int (&ops)[NV], Take take,
                                             Body body)
@@ -142,7 +179,7 @@ enum { CM_I32 = 0, CM_D16 = 2 };
 __device__ __forceinline__ double bld_val(const double *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float bld_val(const float *p) { return *p; }
 
-// Row sums of slice s of problem p: sum_k val(k) x(col(k)), with the same
+// Row sums of slice s of member p: sum_k val(k) x(col(k)), with the same
 // wave-uniform load phases (eight entries each) and column order as the
 // single-problem kernels.  Padding and rows past the end hold valid columns.
 template <int WMAX, int CM, class VT, class X>
@@ -188,12 +225,14 @@ __device__ __forceinline__ double bsell_row(const BDev &B, const VT *__restrict_
     return acc;
 }
 
-// ---------------------------------------------------------------- kernels
+__device__ __forceinline__ bool running(const BDev &B, int p) { return B.st[p].phase != PH_DONE; }
+
+// ---------------------------------------------------------------- start-up kernels
 // c = c0v (mode 0) or P(c) (mode 1); |f|^2, max f, #non-finite f, #non-finite c
 __global__ void kb_init(BDev B, int mode, double c0v)
 {
     const int ops[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
-    for_bslices<4>(B, ops, [&](int p) { return B.bp[p].active != 0; },
+    for_bslices<4>(B, ops, [&](int p) { return running(B, p); },
                    [&](int p, int, int, int il, bool row, double (&a)[4]) {
                        if (!row) return;
                        const double fi = B.f[p][il];
@@ -217,7 +256,7 @@ template <int WMAX>
 __global__ void kb_transient_rhs(BDev B, double dt, double *__restrict__ ft)
 {
     const int ops[1] = {OP_SUM};
-    for_bslices<1>(B, ops, [&](int p) { return B.bp[p].active != 0; },
+    for_bslices<1>(B, ops, [&](int p) { return running(B, p); },
                    [&](int p, int s, int i, int il, bool row, double (&)[1]) {
                        const double *c = B.c[p];
                        const double mc =
@@ -226,179 +265,19 @@ __global__ void kb_transient_rhs(BDev B, double dt, double *__restrict__ ft)
                    });
 }
 
-// g = K c - f; |pg|^2, #non-finite, ||min(c,g)||_inf, min c, #(c == 0)
+// g = K c - f over the listed slices (the launch-shape tuner times this pass)
 template <int WMAX>
 __global__ void kb_grad(BDev B, double *__restrict__ g)
 {
-    const int ops[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
-    for_bslices<5>(B, ops, [&](int p) { return B.bp[p].active != 0; },
-                   [&](int p, int s, int i, int il, bool row, double (&a)[5]) {
+    const int ops[1] = {OP_SUM};
+    for_bslices<1>(B, ops, [&](int p) { return running(B, p); },
+                   [&](int p, int s, int i, int il, bool row, double (&a)[1]) {
                        const double *c = B.c[p];
                        const double kc =
                            bsell_row<WMAX, CM_I32>(B, B.v64[p], p, s, [&](int j) { return c[j]; });
                        if (!row) return;
-                       const double gi = kc - B.f[p][il];
-                       const double cv = c[il];
-                       g[i] = gi;
-                       const double pg = cv > 0.0 ? gi : (gi < 0.0 ? gi : 0.0);
-                       a[0] += pg * pg;
-                       a[1] += (isfinite(gi) && isfinite(cv)) ? 0.0 : 1.0;
-                       a[2] = fmax(a[2], fabs(fmin(cv, gi)));
-                       a[3] = fmin(a[3], cv);
-                       a[4] += cv == 0.0 ? 1.0 : 0.0;
-                   });
-}
-
-// Trial of a projected search for the problems with t_p != 0:
-// s = P(c + t_p d) - c formed for every gathered column, ks = K s (written to
-// buffer ksbuf_p when write_ks); g.s, s.Ks, s.s.  With a mask only free rows
-// are formed (d vanishes elsewhere, so s does too).
-template <int WMAX, int CM, class VT, class VD>
-__global__ void kb_trial(BDev B, const VT *const *vals, const VD *__restrict__ d,
-                         const double *__restrict__ g, const uint8_t *__restrict__ mask,
-                         double *__restrict__ ks0, double *__restrict__ ks1, int write_ks)
-{
-    const int ops[3] = {OP_SUM, OP_SUM, OP_SUM};
-    for_bslices<3>(B, ops, [&](int p) { return B.bp[p].active != 0 && B.bp[p].t != 0.0; },
-                   [&](int p, int s, int i, int il, bool row, double (&a)[3]) {
-                       const double t = B.bp[p].t;
-                       const double *c = B.c[p];
-                       const int r0 = B.s0[p] * kSlice;
-                       auto sv = [&](int j) {
-                           const double cj = c[j];
-                           return proj0b(cj + t * (double)d[r0 + j]) - cj;
-                       };
-                       const bool live = row && (mask == nullptr || mask[i] != 0);
-                       if (__ballot(live) == 0) return;
-                       const double ksv = bsell_row<WMAX, CM>(B, vals[p], p, s, sv);
-                       if (!live) return;
-                       if (write_ks) (B.bp[p].ksbuf ? ks1 : ks0)[i] = ksv;
-                       const double si = sv(il);
-                       a[0] += g[i] * si;
-                       a[1] += si * ksv;
-                       a[2] += si * si;
-                   });
-}
-
-// c = P(c + t_p d) for the problems with t_p != 0
-template <class VD>
-__global__ void kb_apply(BDev B, const VD *__restrict__ d)
-{
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    const int nw = gridDim.x * wpb;
-    const int nlist = B.cnt[0];
-    for (int k = blockIdx.x * wpb + wid; k < nlist; k += nw) {
-        const int s = B.slist[k];
-        const int p = B.sprob[s];
-        const double t = B.bp[p].t;
-        if (!B.bp[p].active || t == 0.0) continue;
-        const int il = (s - B.s0[p]) * kSlice + lane;
-        if (il >= B.nrow[p]) continue;
-        double *c = B.c[p];
-        c[il] = proj0b(c[il] + t * (double)d[s * kSlice + lane]);
-    }
-}
-
-// CG set-up on the face of (c, g + ks_p): g <- g + ks, free = not (c == 0 and
-// g >= 0), dm = 1/diag on free rows (0 elsewhere), r = -g on free rows,
-// z = dm r, p = q = w = 0.  r.z, r.r, #free, nnz of the free rows.
-template <class VV>
-__global__ void kb_cg_setup(BDev B, double *__restrict__ g, const double *__restrict__ ks0,
-                            const double *__restrict__ ks1, uint8_t *__restrict__ mask,
-                            VV *__restrict__ dm, VV *__restrict__ r, VV *__restrict__ z,
-                            VV *__restrict__ pv, VV *__restrict__ q, VV *__restrict__ w)
-{
-    const int ops[4] = {OP_SUM, OP_SUM, OP_SUM, OP_SUM};
-    for_bslices<4>(B, ops, [&](int p) { return B.bp[p].active != 0; },
-                   [&](int p, int, int i, int il, bool row, double (&a)[4]) {
-                       if (!row) {
-                           mask[i] = 0;
-                           dm[i] = r[i] = z[i] = pv[i] = q[i] = w[i] = VV(0);
-                           return;
-                       }
-                       const double *ks = B.bp[p].ksbuf ? ks1 : ks0;
-                       const double gi = g[i] + ks[i];
-                       g[i] = gi;
-                       const double cv = B.c[p][il];
-                       const bool fr = !(cv == 0.0 && gi >= 0.0);
-                       const VV dmi = fr ? (VV)(1.0 / B.diag[p][il]) : VV(0);
-                       const VV ri = fr ? (VV)(-gi) : VV(0);
-                       const VV zi = dmi * ri;
-                       mask[i] = fr ? 1 : 0;
-                       dm[i] = dmi;
-                       r[i] = ri;
-                       z[i] = zi;
-                       pv[i] = VV(0);
-                       q[i] = VV(0);
-                       w[i] = VV(0);
-                       a[0] += (double)ri * (double)zi;
-                       a[1] += (double)ri * (double)ri;
-                       a[2] += fr ? 1.0 : 0.0;
-                       const int *rp = B.rowptr[p];
-                       a[3] += fr ? (double)(rp[il + 1] - rp[il]) : 0.0;
-                   });
-}
-
-// CG matrix pass for the running problems: p <- z + beta_p p and
-// q <- K z + beta_p q on the free rows (one gather of z, as in the
-// single-problem pass); p.q.
-template <int WMAX, int CM, class VT, class VV>
-__global__ void kb_cg_spmv(BDev B, const VT *const *vals, const uint8_t *__restrict__ mask,
-                           const VV *__restrict__ z, VV *__restrict__ pv, VV *__restrict__ q)
-{
-    const int ops[1] = {OP_SUM};
-    for_bslices<1>(B, ops, [&](int p) { return B.bp[p].active != 0 && B.bp[p].done == 0; },
-                   [&](int p, int s, int i, int, bool row, double (&a)[1]) {
-                       const bool live = row && mask[i] != 0;
-                       if (__ballot(live) == 0) return;
-                       const int r0 = B.s0[p] * kSlice;
-                       const double kz = bsell_row<WMAX, CM>(
-                           B, vals[p], p, s, [&](int j) { return (double)z[r0 + j]; });
-                       if (!live) return;
-                       const double beta = B.bp[p].beta;
-                       const VV pi = (VV)fma(beta, (double)pv[i], (double)z[i]);
-                       const VV qi = (VV)fma(beta, (double)q[i], kz);
-                       pv[i] = pi;
-                       q[i] = qi;
-                       a[0] += (double)pi * (double)qi;
-                   });
-}
-
-// CG vector update on the free rows of the running problems:
-// w += alpha p, r -= alpha q, z = dm r; r.z, r.r
-template <class VV>
-__global__ void kb_cg_update(BDev B, const uint8_t *__restrict__ mask, const VV *__restrict__ pv,
-                             const VV *__restrict__ q, const VV *__restrict__ dm,
-                             VV *__restrict__ w, VV *__restrict__ r, VV *__restrict__ z)
-{
-    const int ops[2] = {OP_SUM, OP_SUM};
-    for_bslices<2>(B, ops, [&](int p) { return B.bp[p].active != 0 && B.bp[p].done == 0; },
-                   [&](int p, int, int i, int, bool row, double (&a)[2]) {
-                       if (!row || !mask[i]) return;
-                       const double alpha = B.bp[p].alpha;
-                       const VV ri = (VV)((double)r[i] - alpha * (double)q[i]);
-                       const VV zi = dm[i] * ri;
-                       w[i] = (VV)((double)w[i] + alpha * (double)pv[i]);
-                       r[i] = ri;
-                       z[i] = zi;
-                       a[0] += (double)ri * (double)zi;
-                       a[1] += (double)ri * (double)ri;
-                   });
-}
-
-// Breakpoint of the search along w: min over w < 0 of c/(-w); g.w; w.w
-template <class VV>
-__global__ void kb_breakpoint(BDev B, const VV *__restrict__ w, const double *__restrict__ g)
-{
-    const int ops[3] = {OP_MIN, OP_SUM, OP_SUM};
-    for_bslices<3>(B, ops, [&](int p) { return B.bp[p].active != 0; },
-                   [&](int p, int, int i, int il, bool row, double (&a)[3]) {
-                       if (!row) return;
-                       const double wi = (double)w[i];
-                       if (wi < 0.0) a[0] = fmin(a[0], B.c[p][il] / (-wi));
-                       a[1] += g[i] * wi;
-                       a[2] += wi * wi;
+                       g[i] = kc - B.f[p][il];
+                       a[0] += g[i];
                    });
 }
 
@@ -416,27 +295,17 @@ __global__ void kb_active(BDev B)
     }
 }
 
-// Combine the slice partials of listed problem blockIdx.x in a fixed order (thread t
-// takes slices t, t + 256, ...; then a wave butterfly; then the four waves in
-// order) into pres[p].  MODE adds the CG scalar logic that follows the
-// reduction: 1 after the set-up, 2 after the matrix pass, 3 after the update.
-// Problems that are inactive (or, for MODE 2 and 3, whose CG has stopped) are
-// skipped, so their state is left untouched.
-template <int NV, int MODE>
-__global__ __launch_bounds__(kFinBlock) void kb_finalize(BDev B, int ops_code, double rtol2)
+// Combine NV slice partials of member p in a fixed order (thread t takes
+// slices t, t + 256, ...; then a wave butterfly; then the four waves in
+// order).  Every thread of the block calls it; thread 0 gets true and the
+// result, the others false.
+template <int NV>
+__device__ __forceinline__ bool member_reduce(const BDev &B, int p, const int (&ops)[NV],
+                                              double (&a)[NV])
 {
-    if ((int)blockIdx.x >= B.cnt[1]) return;
-    const int p = B.plist[blockIdx.x];
-    BProb &bp = B.bp[p];
-    if (!bp.active || (MODE >= 2 && bp.done)) return;
-    __shared__ double sh[kFinBlock / 64][NV];
-    int ops[NV];
-    double a[NV];
+    __shared__ double sh[kFinBlock / 64][kBNV];
 #pragma unroll
-    for (int k = 0; k < NV; k++) {
-        ops[k] = (ops_code >> (2 * k)) & 3;
-        a[k] = bident(ops[k]);
-    }
+    for (int k = 0; k < NV; k++) a[k] = bident(ops[k]);
     const int s1 = B.s0[p] + (B.nrow[p] + kSlice - 1) / kSlice;
     for (int s = B.s0[p] + threadIdx.x; s < s1; s += kFinBlock)
 #pragma unroll
@@ -450,47 +319,465 @@ __global__ __launch_bounds__(kFinBlock) void kb_finalize(BDev B, int ops_code, d
 #pragma unroll
         for (int k = 0; k < NV; k++) sh[wid][k] = a[k];
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0) return false;
 #pragma unroll
     for (int k = 0; k < NV; k++) {
         double v = sh[0][k];
         for (int w = 1; w < kFinBlock / 64; w++) v = bcomb(ops[k], v, sh[w][k]);
         a[k] = v;
-        B.pres[(size_t)p * kBNV + k] = v;
     }
-    if (MODE == 1) {
-        // r.z_0, r.r_0, #free, nnz(free); stop before the first iteration
-        // when the face is empty or the residual vanishes
-        bp.rz = a[0];
-        bp.rr_stop = rtol2 * a[1];
-        bp.n_free = a[2];
-        bp.nnz_free = a[NV > 3 ? 3 : 0];
-        bp.beta = 0.0;
-        bp.alpha = 0.0;
-        bp.it = 0;
-        if (!isfinite(a[0]) || !isfinite(a[1])) bp.done = 4;
-        else if (a[1] == 0.0 || a[2] == 0.0 || bp.max_it <= 0 || !(a[0] > 0.0)) bp.done = 1;
-        else bp.done = 0;
-    } else if (MODE == 2) {
-        // alpha = r.z / p.q; breakdown on non-positive or non-finite curvature
-        const double pq = a[0];
-        if (!isfinite(pq)) bp.done = 4;
-        else if (!(pq > 0.0)) bp.done = 3;
-        else bp.alpha = bp.rz / pq;
-    } else if (MODE == 3) {
-        // iteration done: beta for the next one, stopping test on r.r
-        const double rz = a[0], rr = a[NV > 1 ? 1 : 0];
-        bp.it += 1;
-        bp.beta = rz / bp.rz;
-        bp.rz = rz;
-        if (!isfinite(rz) || !isfinite(rr)) bp.done = 4;
-        else if (rr <= bp.rr_stop || bp.it >= bp.max_it || !(rz > 0.0)) bp.done = 1;
+    return true;
+}
+
+// start-up reduction: |f|^2, max f, #non-finite f, #non-finite c into pres
+__global__ __launch_bounds__(kFinBlock) void kb_reduce_init(BDev B)
+{
+    if ((int)blockIdx.x >= B.cnt[1]) return;
+    const int p = B.plist[blockIdx.x];
+    const int ops[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
+    double a[4];
+    if (!member_reduce<4>(B, p, ops, a)) return;
+    for (int k = 0; k < 4; k++) B.pres[(size_t)p * kBNV + k] = a[k];
+}
+
+// ---------------------------------------------------------------- global step
+// Row pass: per listed slice, the matrix pass of the member's phase.
+//   GRAD    g = K c - f (float64 values); |pg|^2, #non-finite, ||min(c,g)||_inf,
+//           min c, #(c == 0)
+//   CAUCHY  s = P(c + ttrial g) - c gathered, ks = K s into buffer ksbuf;
+//           g.s, s.Ks, s.s
+//   CG      p <- z + beta p, q <- K z + beta q on the free rows; p.q
+//   SEARCH  s = P(c + ts w) - c on the free rows, K s; g.s, s.Ks, s.s
+template <int WMAX, int CM, class VT, class VV>
+__global__ void kb_rows(BDev B, const VT *const *vals, BVec<VV> V)
+{
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    const int nlist = B.cnt[0];
+    for (int k = blockIdx.x * wpb + wid; k < nlist; k += nw) {
+        const int s = B.slist[k];
+        const int p = B.sprob[s];
+        const BState &S = B.st[p];
+        const int ph = S.phase;
+        const int il = (s - B.s0[p]) * kSlice + lane;
+        const int i = s * kSlice + lane;
+        const bool row = il < B.nrow[p];
+        const int r0 = B.s0[p] * kSlice;
+        double *__restrict__ c = B.c[p];
+        double a[kBNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (ph == PH_GRAD) {
+            a[2] = -INFINITY;
+            a[3] = INFINITY;
+            const double kc =
+                bsell_row<WMAX, CM_I32>(B, B.v64[p], p, s, [&](int j) { return c[j]; });
+            if (row) {
+                const double gi = kc - B.f[p][il];
+                const double cv = c[il];
+                V.g[i] = gi;
+                const double pg = cv > 0.0 ? gi : (gi < 0.0 ? gi : 0.0);
+                a[0] = pg * pg;
+                a[1] = (isfinite(gi) && isfinite(cv)) ? 0.0 : 1.0;
+                a[2] = fabs(fmin(cv, gi));
+                a[3] = cv;
+                a[4] = cv == 0.0 ? 1.0 : 0.0;
+            }
+        } else if (ph == PH_CAUCHY) {
+            const double t = S.ttrial;
+            const double *__restrict__ g = V.g;
+            auto sv = [&](int j) {
+                const double cj = c[j];
+                return proj0b(cj + t * g[r0 + j]) - cj;
+            };
+            const double ksv = bsell_row<WMAX, CM>(B, vals[p], p, s, sv);
+            if (row) {
+                (S.ksbuf ? V.ks1 : V.ks0)[i] = ksv;
+                const double si = sv(il);
+                a[0] = g[i] * si;
+                a[1] = si * ksv;
+                a[2] = si * si;
+            }
+        } else if (ph == PH_CG) {
+            const bool live = S.cgdone == 0 && row && V.mask[i] != 0;
+            if (__ballot(live) != 0) {
+                const VV *__restrict__ z = V.z;
+                const double kz =
+                    bsell_row<WMAX, CM>(B, vals[p], p, s, [&](int j) { return (double)z[r0 + j]; });
+                if (live) {
+                    const double beta = S.beta;
+                    const VV pi = (VV)fma(beta, (double)V.p[i], (double)z[i]);
+                    const VV qi = (VV)fma(beta, (double)V.q[i], kz);
+                    V.p[i] = pi;
+                    V.q[i] = qi;
+                    a[0] = (double)pi * (double)qi;
+                }
+            }
+        } else if (ph == PH_SEARCH) {
+            const bool live = row && V.mask[i] != 0;
+            if (__ballot(live) != 0) {
+                const double t = S.ts;
+                const VV *__restrict__ w = V.w;
+                auto sv = [&](int j) {
+                    const double cj = c[j];
+                    return proj0b(cj + t * (double)w[r0 + j]) - cj;
+                };
+                const double ksv = bsell_row<WMAX, CM>(B, vals[p], p, s, sv);
+                if (live) {
+                    const double si = sv(il);
+                    a[0] = V.g[i] * si;
+                    a[1] = si * ksv;
+                    a[2] = si * si;
+                }
+            }
+        } else {
+            continue;   // no row work: the transition does not read these partials
+        }
+        // wave combination (the phase is uniform in the wave)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+            for (int v = 0; v < kBNV; v++) {
+                const double other = __shfl_xor(a[v], o, 64);
+                if (ph == PH_GRAD && v == 2) a[v] = fmax(a[v], other);
+                else if (ph == PH_GRAD && v == 3) a[v] = fmin(a[v], other);
+                else a[v] += other;
+            }
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int v = 0; v < kBNV; v++) B.part[(size_t)s * kBNV + v] = a[v];
     }
 }
 
-constexpr int opsc(int a, int b = 0, int c = 0, int d = 0, int e = 0)
+__device__ __forceinline__ void radius_update(BState &S)
 {
-    return a | (b << 2) | (c << 4) | (d << 6) | (e << 8);
+    if (isfinite(S.delta) && S.stepn >= 0.99 * S.delta) S.delta *= 4.0;
+}
+
+// First transition: combine the row-pass partials of the member and decide.
+__global__ __launch_bounds__(kFinBlock) void kb_step1(BDev B)
+{
+    if ((int)blockIdx.x >= B.cnt[1]) return;
+    const int p = B.plist[blockIdx.x];
+    BState &S = B.st[p];
+    const int ph = S.phase;
+    double a[kBNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ph == PH_GRAD) {
+        const int ops[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
+        if (!member_reduce<5>(B, p, ops, a)) return;
+    } else if (ph == PH_CAUCHY || ph == PH_SEARCH) {
+        const int ops[3] = {OP_SUM, OP_SUM, OP_SUM};
+        double b[3];
+        if (!member_reduce<3>(B, p, ops, b)) return;
+        a[0] = b[0], a[1] = b[1], a[2] = b[2];
+    } else if (ph == PH_CG) {
+        const int ops[1] = {OP_SUM};
+        double b[1];
+        if (!member_reduce<1>(B, p, ops, b)) return;
+        a[0] = b[0];
+    } else if (threadIdx.x != 0) {
+        return;
+    }
+    const double n = S.n, nnz = S.nnz;
+    const double trial_bytes = 4.0 * (n + 1) + (S.ib + S.vb) * nnz + 32.0 * n;
+    S.vop = VO_NONE;
+    if (ph == PH_GRAD) {
+        // gradient, KKT report, convergence test
+        S.spmvs++;
+        S.bytes += 4.0 * (n + 1) + 12.0 * nnz + 32.0 * n;
+        if (a[1] != 0.0) {
+            S.status = NN_ENONFINITE;
+            S.phase = PH_DONE;
+            return;
+        }
+        S.kkt_rel = sqrt(a[0]) / S.normf;
+        S.kkt_nat = a[2];
+        S.min_c = a[3];
+        S.n_active = (int)a[4];
+        if (S.mixed) S.refinements = S.outer + 1;
+        if (S.kkt_rel <= S.tol) {
+            S.status = NN_OK;
+            S.phase = PH_DONE;
+        } else if (S.outer >= S.max_outer) {
+            S.status = NN_EMAXIT;
+            S.phase = PH_DONE;
+        } else {
+            // Cauchy search from the previous step length
+            S.cst = CS_FIRST;
+            S.t = S.tcau;
+            S.cur = 0;
+            S.ntrial = 0;
+            S.ttrial = -S.t;
+            S.ksbuf = 0;
+            S.phase = PH_CAUCHY;
+        }
+    } else if (ph == PH_CAUCHY) {
+        S.spmvs++;
+        S.cauchy_trials++;
+        S.bytes += trial_bytes;
+        const bool ok = a[0] < 0.0 && a[0] + 0.5 * a[1] <= kMu0 * a[0] && sqrt(a[2]) <= S.delta;
+        bool accept = false;
+        if (S.cst == CS_FIRST) {
+            if (ok) {
+                S.gs = a[0], S.sks = a[1], S.ss = a[2];
+                S.cst = CS_EXT;
+            } else {
+                S.cst = CS_INT;
+                S.t *= kInterp;
+            }
+        } else if (S.cst == CS_EXT) {
+            if (!ok) {
+                accept = true;
+            } else {
+                const bool same = a[0] == S.gs && a[1] == S.sks;
+                S.t *= kExtrap;
+                S.cur ^= 1;
+                S.gs = a[0], S.sks = a[1], S.ss = a[2];
+                // stop when every moving variable has reached its bound
+                if (same || ++S.ntrial >= 20) accept = true;
+            }
+        } else {
+            S.gs = a[0], S.sks = a[1], S.ss = a[2];
+            if (ok) {
+                accept = true;
+            } else if (++S.ntrial >= kMaxTrials || !(a[0] < 0.0)) {
+                // no decrease along -g at this precision: stationary up to rounding
+                S.status = NN_EMAXIT;
+                S.phase = PH_DONE;
+                return;
+            } else {
+                S.t *= kInterp;
+            }
+        }
+        if (accept) {
+            S.tcau = S.t;
+            S.stepn = sqrt(S.ss);
+            S.vop = VO_SETUP;   // Cauchy step and CG set-up in the vector pass
+            S.phase = PH_CG;
+        } else if (S.cst == CS_EXT) {
+            S.ttrial = -S.t * kExtrap;
+            S.ksbuf = S.cur ^ 1;
+        } else {
+            S.ttrial = -S.t;
+            S.ksbuf = S.cur;
+        }
+    } else if (ph == PH_CG) {
+        // alpha = r.z / p.q; breakdown on non-positive or non-finite curvature
+        const double pq = a[0];
+        if (S.cgdone != 0) {
+            S.phase = PH_BREAK;
+        } else if (!isfinite(pq)) {
+            S.status = NN_ENONFINITE;
+            S.phase = PH_DONE;
+        } else if (!(pq > 0.0)) {
+            S.status = NN_ENOTSPD;
+            S.phase = PH_DONE;
+        } else {
+            S.alpha = S.rz / pq;
+            S.vop = VO_UPDATE;
+        }
+    } else if (ph == PH_SEARCH) {
+        S.spmvs++;
+        S.search_trials++;
+        S.bytes += trial_bytes;
+        bool accept = false;
+        if (a[0] < 0.0 && a[0] + 0.5 * a[1] <= kMu0 * a[0]) {
+            accept = true;
+        } else {
+            S.ts *= kBack;
+            if (S.ts <= S.bmin) {
+                S.ts = S.bmin;   // no bound is crossed: decrease is guaranteed
+                accept = true;
+            } else if (++S.nsearch >= kMaxTrials) {
+                accept = true;
+            }
+        }
+        if (accept) {
+            S.vop = VO_APPLYW;
+            S.phase = PH_APPLYW;
+        }
+    } else if (ph == PH_BREAK) {
+        S.vop = VO_BREAK;
+    } else if (ph == PH_APPLYW) {
+        S.vop = VO_APPLYW;
+    }
+}
+
+// Vector pass: per listed slice, the operation the first transition chose.
+//   SETUP   c = P(c - t g), g += K s (accepted Cauchy trial); free = not
+//           (c == 0 and g >= 0); dm = 1/diag, r = -g on free rows; z = dm r;
+//           p = q = w = 0; r.z, r.r, #free, nnz of the free rows
+//   UPDATE  w += alpha p, r -= alpha q, z = dm r on free rows; r.z, r.r
+//   BREAK   min over w < 0 of c/(-w), g.w, w.w
+//   APPLYW  c = P(c + ts w)
+template <class VV>
+__global__ void kb_vec(BDev B, BVec<VV> V)
+{
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    const int nlist = B.cnt[0];
+    for (int k = blockIdx.x * wpb + wid; k < nlist; k += nw) {
+        const int s = B.slist[k];
+        const int p = B.sprob[s];
+        const BState &S = B.st[p];
+        const int vop = S.vop;
+        if (vop == VO_NONE) continue;
+        const int il = (s - B.s0[p]) * kSlice + lane;
+        const int i = s * kSlice + lane;
+        const bool row = il < B.nrow[p];
+        double *__restrict__ c = B.c[p];
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if (vop == VO_SETUP) {
+            if (!row) {
+                V.mask[i] = 0;
+                V.dm[i] = V.r[i] = V.z[i] = V.p[i] = V.q[i] = V.w[i] = VV(0);
+            } else {
+                const double gi0 = V.g[i];
+                const double cv = proj0b(c[il] - S.t * gi0);
+                const double gi = gi0 + (S.cur ? V.ks1 : V.ks0)[i];
+                c[il] = cv;
+                V.g[i] = gi;
+                const bool fr = !(cv == 0.0 && gi >= 0.0);
+                const VV dmi = fr ? (VV)(1.0 / B.diag[p][il]) : VV(0);
+                const VV ri = fr ? (VV)(-gi) : VV(0);
+                const VV zi = dmi * ri;
+                V.mask[i] = fr ? 1 : 0;
+                V.dm[i] = dmi;
+                V.r[i] = ri;
+                V.z[i] = zi;
+                V.p[i] = VV(0);
+                V.q[i] = VV(0);
+                V.w[i] = VV(0);
+                a[0] = (double)ri * (double)zi;
+                a[1] = (double)ri * (double)ri;
+                a[2] = fr ? 1.0 : 0.0;
+                const int *rp = B.rowptr[p];
+                a[3] = fr ? (double)(rp[il + 1] - rp[il]) : 0.0;
+            }
+        } else if (vop == VO_UPDATE) {
+            if (row && V.mask[i]) {
+                const double alpha = S.alpha;
+                const VV ri = (VV)((double)V.r[i] - alpha * (double)V.q[i]);
+                const VV zi = V.dm[i] * ri;
+                V.w[i] = (VV)((double)V.w[i] + alpha * (double)V.p[i]);
+                V.r[i] = ri;
+                V.z[i] = zi;
+                a[0] = (double)ri * (double)zi;
+                a[1] = (double)ri * (double)ri;
+            }
+        } else if (vop == VO_BREAK) {
+            a[0] = INFINITY;
+            if (row) {
+                const double wi = (double)V.w[i];
+                if (wi < 0.0) a[0] = c[il] / (-wi);
+                a[1] = V.g[i] * wi;
+                a[2] = wi * wi;
+            }
+        } else {   // VO_APPLYW
+            if (row) c[il] = proj0b(c[il] + S.ts * (double)V.w[i]);
+            continue;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const double other = __shfl_xor(a[v], o, 64);
+                a[v] = (vop == VO_BREAK && v == 0) ? fmin(a[v], other) : a[v] + other;
+            }
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int v = 0; v < 4; v++) B.part[(size_t)s * kBNV + v] = a[v];
+    }
+}
+
+// Second transition: combine the vector-pass partials and choose the phase
+// of the member's next global step.
+__global__ __launch_bounds__(kFinBlock) void kb_step2(BDev B)
+{
+    if ((int)blockIdx.x >= B.cnt[1]) return;
+    const int p = B.plist[blockIdx.x];
+    BState &S = B.st[p];
+    const int vop = S.vop;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (vop == VO_SETUP) {
+        const int ops[4] = {OP_SUM, OP_SUM, OP_SUM, OP_SUM};
+        if (!member_reduce<4>(B, p, ops, a)) return;
+    } else if (vop == VO_UPDATE) {
+        const int ops[2] = {OP_SUM, OP_SUM};
+        double b[2];
+        if (!member_reduce<2>(B, p, ops, b)) return;
+        a[0] = b[0], a[1] = b[1];
+    } else if (vop == VO_BREAK) {
+        const int ops[3] = {OP_MIN, OP_SUM, OP_SUM};
+        double b[3];
+        if (!member_reduce<3>(B, p, ops, b)) return;
+        a[0] = b[0], a[1] = b[1], a[2] = b[2];
+    } else if (threadIdx.x != 0) {
+        return;
+    }
+    const double n = S.n;
+    if (vop == VO_SETUP) {
+        // CG start on the free face: stop before the first iteration when the
+        // face is empty or the residual vanishes
+        S.bytes += 24.0 * n + 88.0 * n;
+        S.rz = a[0];
+        S.rr_stop = S.rtol2 * a[1];
+        S.n_free = a[2];
+        S.nnz_free = a[3];
+        S.beta = 0.0;
+        S.alpha = 0.0;
+        S.it = 0;
+        if (!isfinite(a[0]) || !isfinite(a[1])) {
+            S.status = NN_ENONFINITE;
+            S.phase = PH_DONE;
+        } else if (a[1] == 0.0 || a[2] == 0.0 || S.max_cg <= 0 || !(a[0] > 0.0)) {
+            S.cgdone = 1;
+            S.phase = PH_BREAK;
+        } else {
+            S.cgdone = 0;
+            S.phase = PH_CG;
+        }
+    } else if (vop == VO_UPDATE) {
+        // iteration done: beta for the next one, stopping test on r.r
+        const double rz = a[0], rr = a[1];
+        const double nf = S.n_free, nzf = S.nnz_free;
+        S.bytes += n + 4.0 * nf + (S.ib + S.vb) * nzf + 5.0 * S.vb * nf + n + 8.0 * S.vb * nf;
+        S.it += 1;
+        S.cg_its++;
+        S.spmvs++;
+        S.beta = rz / S.rz;
+        S.rz = rz;
+        if (!isfinite(rz) || !isfinite(rr)) {
+            S.status = NN_ENONFINITE;
+            S.phase = PH_DONE;
+        } else if (rr <= S.rr_stop || S.it >= S.max_cg || !(rz > 0.0)) {
+            S.cgdone = 1;
+            S.phase = PH_BREAK;
+        }
+    } else if (vop == VO_BREAK) {
+        S.bytes += 24.0 * n;
+        S.bmin = a[0];
+        S.wn = sqrt(a[2]);
+        if (S.it > 0 && a[1] < 0.0 && S.wn > 0.0) {
+            S.ts = fmin(1.0, S.delta / S.wn);
+            S.nsearch = 0;
+            S.phase = S.bmin >= S.ts ? PH_APPLYW : PH_SEARCH;
+        } else {
+            // no step along w: radius update on the Cauchy step, next iteration
+            radius_update(S);
+            S.outer++;
+            S.phase = PH_GRAD;
+        }
+    } else if (vop == VO_APPLYW) {
+        S.bytes += 24.0 * n;
+        S.stepn += S.ts * S.wn;
+        radius_update(S);
+        S.outer++;
+        S.phase = PH_GRAD;
+    }
+    S.vop = VO_NONE;
 }
 
 // ---------------------------------------------------------------- host side
@@ -557,8 +844,8 @@ struct Arena {
     }
 };
 
-// Captured CG chunks, one per launch-size class (the grid of a captured
-// launch is fixed; the lists it walks are read from device memory).
+// Captured chunks of global steps, one per launch-size class (the grid of a
+// captured launch is fixed; the lists it walks are read from device memory).
 struct GraphCache {
     struct G {
         hipGraph_t graph = nullptr;
@@ -589,6 +876,25 @@ struct Events {
         return true;
     }
 };
+
+// Algorithmic bytes of the row pass of one member in its current state (the
+// same byte model as the member's own transitions).
+double row_bytes(const BState &S)
+{
+    const double n = S.n, nnz = S.nnz;
+    switch (S.phase) {
+    case PH_GRAD:
+        return 4.0 * (n + 1) + 12.0 * nnz + 32.0 * n;
+    case PH_CAUCHY:
+    case PH_SEARCH:
+        return 4.0 * (n + 1) + (S.ib + S.vb) * nnz + 32.0 * n;
+    case PH_CG:
+        return S.cgdone ? 0.0
+                        : n + 4.0 * S.n_free + (S.ib + S.vb) * S.nnz_free + 5.0 * S.vb * S.n_free;
+    default:
+        return 0.0;
+    }
+}
 
 }  // namespace
 
@@ -633,6 +939,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     bool all_d16 = true;
     for (int p = 0; p < P; p++)
         if (K[p]->n > 0 && !K[p]->sl_d16) all_d16 = false;
+    const double vb = mixed ? 4.0 : 8.0;                // bytes per CG vector entry and per value
+    const double ib = (mixed && all_d16) ? 2.0 : 4.0;   // bytes per column index
 
     // ---- tables, work vectors, lists, pinned state mirrors
     Arena A;
@@ -647,39 +955,37 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     const float **d_v32 = A.d<const float *>(P);
     double **d_c = A.d<double *>(P);
     uint8_t **d_act = A.d<uint8_t *>(P);
-    BProb *d_bp = A.d<BProb>(P);
+    BState *d_st = A.d<BState>(P);
     double *d_part = A.d<double>((size_t)S * kBNV), *d_pres = A.d<double>((size_t)P * kBNV);
     double *g = A.d<double>(R), *ks0 = A.d<double>(R), *ks1 = A.d<double>(R);
     double *ft = transient ? A.d<double>(R) : nullptr;
     uint8_t *mask = A.d<uint8_t>(R);
-    double *w64 = nullptr, *r64 = nullptr, *z64 = nullptr, *p64 = nullptr, *q64 = nullptr,
-           *dm64 = nullptr;
-    float *w32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr,
-          *dm32 = nullptr;
+    BVec<double> V64{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    BVec<float> V32{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (mixed) {
-        w32 = A.d<float>(R), r32 = A.d<float>(R), z32 = A.d<float>(R);
-        p32 = A.d<float>(R), q32 = A.d<float>(R), dm32 = A.d<float>(R);
+        V32.w = A.d<float>(R), V32.r = A.d<float>(R), V32.z = A.d<float>(R);
+        V32.p = A.d<float>(R), V32.q = A.d<float>(R), V32.dm = A.d<float>(R);
     } else {
-        w64 = A.d<double>(R), r64 = A.d<double>(R), z64 = A.d<double>(R);
-        p64 = A.d<double>(R), q64 = A.d<double>(R), dm64 = A.d<double>(R);
+        V64.w = A.d<double>(R), V64.r = A.d<double>(R), V64.z = A.d<double>(R);
+        V64.p = A.d<double>(R), V64.q = A.d<double>(R), V64.dm = A.d<double>(R);
     }
-    BProb *hb = A.h<BProb>(P);
+    BState *hs = A.h<BState>(P);
     double *pres = A.h<double>((size_t)P * kBNV);
     const void **tab = (const void **)A.h<void *>((size_t)P * 12);
     // Uploads from pinned memory read their source when they execute, so
     // the host writes each upload into a staging copy that it does not touch
     // again until the copy's event has completed.
     constexpr int kStage = 4;
-    BProb *bp_stage[kStage];
+    BState *st_stage[kStage];
     int *lst_stage[kStage];
     for (int k = 0; k < kStage; k++) {
-        bp_stage[k] = A.h<BProb>(P);
+        st_stage[k] = A.h<BState>(P);
         lst_stage[k] = A.h<int>((size_t)2 + P + S);
     }
     if (!A.ok) return fail(ctx, NN_EOOM, "batch workspace allocation failed");
-    Events ev_bp, ev_lst, ev_t;
-    if (!ev_bp.create(kStage, hipEventDisableTiming) || !ev_lst.create(kStage, hipEventDisableTiming) ||
-        !ev_t.create(2, hipEventDefault))
+    Events ev_st, ev_lst, ev_t;
+    if (!ev_st.create(kStage, hipEventDisableTiming) ||
+        !ev_lst.create(kStage, hipEventDisableTiming) || !ev_t.create(2, hipEventDefault))
         return fail(ctx, NN_EHIP, "event creation");
     hipEvent_t t0 = ev_t.ev[0], t1 = ev_t.ev[1];
 
@@ -732,48 +1038,51 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     B.f0 = d_f0;
     B.mv = d_mv;
     B.act_out = d_act;
-    B.bp = d_bp;
+    B.st = d_st;
     B.part = d_part;
     B.pres = d_pres;
 
-    std::memset(hb, 0, sizeof(BProb) * P);
+    // ---- member states
+    std::memset(hs, 0, sizeof(BState) * P);
     for (int p = 0; p < P; p++) {
-        hb[p].active = nrow[p] > 0 ? 1 : 0;
-        hb[p].max_it = o->max_cg;
+        BState &M = hs[p];
+        M.phase = nrow[p] > 0 ? PH_GRAD : PH_DONE;
+        M.status = NN_OK;
+        M.max_outer = o->max_outer;
+        M.max_cg = o->max_cg;
+        M.tcau = 1.0;
+        M.delta = o->delta0 > 0.0 ? o->delta0 : INFINITY;
+        M.tol = o->tol;
+        M.rtol2 = o->inner_rtol * o->inner_rtol;
+        M.n = (double)nrow[p];
+        M.nnz = (double)K[p]->nnz;
+        M.ib = ib;
+        M.vb = vb;
+        M.mixed = mixed ? 1 : 0;
     }
-    int bp_next = 0, lst_next = 0;
+    int st_next = 0, lst_next = 0;
     auto push = [&]() {
-        const int k = bp_next;
-        bp_next = (bp_next + 1) % kStage;
-        if (hipEventSynchronize(ev_bp.ev[k]) != hipSuccess) return false;
-        std::memcpy(bp_stage[k], hb, sizeof(BProb) * P);
-        return hipMemcpyAsync(d_bp, bp_stage[k], sizeof(BProb) * P, hipMemcpyHostToDevice, st) ==
+        const int k = st_next;
+        st_next = (st_next + 1) % kStage;
+        if (hipEventSynchronize(ev_st.ev[k]) != hipSuccess) return false;
+        std::memcpy(st_stage[k], hs, sizeof(BState) * P);
+        return hipMemcpyAsync(d_st, st_stage[k], sizeof(BState) * P, hipMemcpyHostToDevice, st) ==
                    hipSuccess &&
-               hipEventRecord(ev_bp.ev[k], st) == hipSuccess;
+               hipEventRecord(ev_st.ev[k], st) == hipSuccess;
     };
-    auto pull_state = [&]() {
-        return hipMemcpyAsync(hb, d_bp, sizeof(BProb) * P, hipMemcpyDeviceToHost, st) ==
+    auto pull = [&]() {
+        return hipMemcpyAsync(hs, d_st, sizeof(BState) * P, hipMemcpyDeviceToHost, st) ==
                    hipSuccess &&
                hipStreamSynchronize(st) == hipSuccess;
     };
-    auto pull_res = [&]() {
-        return hipMemcpyAsync(pres, d_pres, sizeof(double) * P * kBNV, hipMemcpyDeviceToHost,
-                              st) == hipSuccess &&
-               hipStreamSynchronize(st) == hipSuccess;
-    };
-    auto any_active = [&]() {
-        for (int p = 0; p < P; p++)
-            if (hb[p].active) return true;
-        return false;
-    };
-    // The problems taking part in a step, and their slices, as device lists:
-    // rebuilt and uploaded only when the selection changes.
+    // The members still running, and their slices, as device lists: rebuilt
+    // and uploaded only when the set changes.
     std::vector<char> sel(P, 0), sel_cur(P, 2);
     int n_sl = 0, n_pr = 0;
-    auto select = [&](auto pred) -> bool {
+    auto select = [&]() -> bool {
         bool same = true;
         for (int p = 0; p < P; p++) {
-            sel[p] = pred(p) ? 1 : 0;
+            sel[p] = hs[p].phase != PH_DONE ? 1 : 0;
             same = same && sel[p] == sel_cur[p];
         }
         if (same) return true;
@@ -796,7 +1105,6 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                               st) == hipSuccess &&
                hipEventRecord(ev_lst.ev[k], st) == hipSuccess;
     };
-    auto is_active = [&](int p) { return hb[p].active != 0; };
 
     int num_cu = 256;
     {
@@ -811,7 +1119,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     };
 
     NN_HIP_TRY(ctx, push() ? hipSuccess : hipErrorUnknown);
-    NN_HIP_TRY(ctx, select(is_active) ? hipSuccess : hipErrorUnknown);
+    NN_HIP_TRY(ctx, select() ? hipSuccess : hipErrorUnknown);
     NN_HIP_TRY(ctx, hipEventRecord(t0, st));
 
     // ---- transient right-hand sides (from c^n, before the start point is set)
@@ -820,44 +1128,38 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     // ---- start point and load statistics
     hipLaunchKernelGGL(kb_init, dim3(grid_for(sh, n_sl)), dim3(sh.block), 0, st, B,
                        o->c0_mode == 1 ? 1 : 0, o->c0_value);
-    hipLaunchKernelGGL((kb_finalize<4, 0>), dim3(std::max(n_pr, 1)), dim3(kFinBlock), 0, st, B,
-                       opsc(OP_SUM, OP_MAX, OP_SUM, OP_SUM), 0.0);
-    if (!pull_res()) return fail(ctx, NN_EHIP, "batch read-back");
-    std::vector<double> normf(P, 0.0), tcau(P, 1.0), delta(P, INFINITY);
-    std::vector<int> status(P, NN_EMAXIT), outer(P, 0);
+    hipLaunchKernelGGL(kb_reduce_init, dim3(std::max(n_pr, 1)), dim3(kFinBlock), 0, st, B);
+    NN_HIP_TRY(ctx, hipMemcpyAsync(pres, d_pres, sizeof(double) * P * kBNV, hipMemcpyDeviceToHost,
+                                   st));
+    NN_HIP_TRY(ctx, hipStreamSynchronize(st));
     for (int p = 0; p < P; p++) {
-        if (!hb[p].active) {
-            status[p] = NN_OK;
-            continue;
-        }
+        BState &M = hs[p];
+        if (M.phase == PH_DONE) continue;
         const double *r = &pres[(size_t)p * kBNV];
-        normf[p] = std::sqrt(r[0]);
-        SP[p].norm_f = normf[p];
-        SP[p].bytes_moved += 16.0 * nrow[p];
-        if (o->delta0 > 0.0) delta[p] = o->delta0;
+        M.normf = std::sqrt(r[0]);
+        M.bytes += 16.0 * nrow[p];
         if (r[2] != 0.0 || r[3] != 0.0) {
-            status[p] = NN_ENONFINITE;
-            hb[p].active = 0;
+            M.status = NN_ENONFINITE;
+            M.phase = PH_DONE;
         } else if (!(r[1] > 0.0)) {
             // f <= 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0
             NN_HIP_TRY(ctx, hipMemsetAsync(c[p], 0, sizeof(double) * nrow[p], st));
-            status[p] = NN_OK;
-            SP[p].n_active = nrow[p];
-            hb[p].active = 0;
+            M.n_active = nrow[p];
+            M.phase = PH_DONE;
         }
     }
+    NN_HIP_TRY(ctx, push() ? hipSuccess : hipErrorUnknown);
+    NN_HIP_TRY(ctx, select() ? hipSuccess : hipErrorUnknown);
 
     // ---- launch shape for this size class
     const auto key = std::make_tuple((int)std::log2((double)R), width_class(wmax), (int)mixed);
     auto &cache = shape_cache();
     if (cache.count(key)) {
         sh = cache[key];
-    } else if (any_active()) {
-        // time the gradient pass (the batched matrix pass with the most
-        // per-row work) for each candidate shape; it writes only g and the
-        // slice partials, which the first outer iteration overwrites
-        NN_HIP_TRY(ctx, push() ? hipSuccess : hipErrorUnknown);
-        NN_HIP_TRY(ctx, select(is_active) ? hipSuccess : hipErrorUnknown);
+    } else if (n_pr > 0) {
+        // time the gradient pass over all running members for each candidate
+        // shape; it writes only g and the slice partials, which the first
+        // global step overwrites
         float best = INFINITY;
         Shape pick = sh;
         for (int blk : {256, 512, 1024})
@@ -887,77 +1189,35 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         NN_HIP_TRY(ctx, hipEventRecord(t0, st));   // the call's clock restarts after tuning
     }
     const int blk = sh.block;
-    auto grid = [&]() { return grid_for(sh, n_sl); };
-    auto fgrid = [&]() { return std::max(n_pr, 1); };
 
-    // ---- launch helpers (each on the current lists)
-    const double *gptr = g;
-    auto trial = [&](bool along_w, const uint8_t *m, int write_ks) {
-        const int gr = grid();
-        if (mixed && all_d16) {
-            if (along_w)
-                NN_BDISPATCH(wmax, (kb_trial<WM, CM_D16, float, float>), gr, blk, st, B, d_v32,
-                             (const float *)w32, gptr, m, ks0, ks1, write_ks);
-            else
-                NN_BDISPATCH(wmax, (kb_trial<WM, CM_D16, float, double>), gr, blk, st, B, d_v32,
-                             gptr, gptr, m, ks0, ks1, write_ks);
-        } else if (mixed) {
-            if (along_w)
-                NN_BDISPATCH(wmax, (kb_trial<WM, CM_I32, float, float>), gr, blk, st, B, d_v32,
-                             (const float *)w32, gptr, m, ks0, ks1, write_ks);
-            else
-                NN_BDISPATCH(wmax, (kb_trial<WM, CM_I32, float, double>), gr, blk, st, B, d_v32,
-                             gptr, gptr, m, ks0, ks1, write_ks);
-        } else {
-            NN_BDISPATCH(wmax, (kb_trial<WM, CM_I32, double, double>), gr, blk, st, B, d_v64,
-                         along_w ? (const double *)w64 : gptr, gptr, m, ks0, ks1, write_ks);
-        }
-        hipLaunchKernelGGL((kb_finalize<3, 0>), dim3(fgrid()), dim3(kFinBlock), 0, st, B,
-                           opsc(OP_SUM, OP_SUM, OP_SUM), 0.0);
-    };
-    auto apply = [&](bool along_w) {
-        if (mixed && along_w)
-            hipLaunchKernelGGL((kb_apply<float>), dim3(grid()), dim3(blk), 0, st, B,
-                               (const float *)w32);
-        else
-            hipLaunchKernelGGL((kb_apply<double>), dim3(grid()), dim3(blk), 0, st, B,
-                               along_w ? (const double *)w64 : gptr);
-    };
-    // one CG iteration on stream s with launch grids gr (slices) and fg
-    // (problems), optionally bracketed by timing events
-    auto cg_iter = [&](hipStream_t s, int gr, int fg, hipEvent_t *ev) {
+    // ---- one global step on stream s with grids gr (slices) and fg (members),
+    // the row and vector passes optionally bracketed by timing events
+    auto step = [&](hipStream_t s, int gr, int fg, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[0], s);
         if (mixed && all_d16)
-            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, CM_D16, float, float>), gr, blk, s, B, d_v32, mask,
-                         z32, p32, q32);
+            NN_BDISPATCH(wmax, (kb_rows<WM, CM_D16, float, float>), gr, blk, s, B, d_v32, V32);
         else if (mixed)
-            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, CM_I32, float, float>), gr, blk, s, B, d_v32, mask,
-                         z32, p32, q32);
+            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, float, float>), gr, blk, s, B, d_v32, V32);
         else
-            NN_BDISPATCH(wmax, (kb_cg_spmv<WM, CM_I32, double, double>), gr, blk, s, B, d_v64, mask,
-                         z64, p64, q64);
+            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, double, double>), gr, blk, s, B, d_v64, V64);
         if (ev) (void)hipEventRecord(ev[1], s);
-        hipLaunchKernelGGL((kb_finalize<1, 2>), dim3(fg), dim3(kFinBlock), 0, s, B, opsc(OP_SUM),
-                           0.0);
+        hipLaunchKernelGGL(kb_step1, dim3(fg), dim3(kFinBlock), 0, s, B);
         if (ev) (void)hipEventRecord(ev[2], s);
         if (mixed)
-            hipLaunchKernelGGL((kb_cg_update<float>), dim3(gr), dim3(blk), 0, s, B, mask, p32, q32,
-                               dm32, w32, r32, z32);
+            hipLaunchKernelGGL((kb_vec<float>), dim3(gr), dim3(blk), 0, s, B, V32);
         else
-            hipLaunchKernelGGL((kb_cg_update<double>), dim3(gr), dim3(blk), 0, s, B, mask, p64,
-                               q64, dm64, w64, r64, z64);
+            hipLaunchKernelGGL((kb_vec<double>), dim3(gr), dim3(blk), 0, s, B, V64);
         if (ev) (void)hipEventRecord(ev[3], s);
-        hipLaunchKernelGGL((kb_finalize<2, 3>), dim3(fg), dim3(kFinBlock), 0, s, B,
-                           opsc(OP_SUM, OP_SUM), 0.0);
+        hipLaunchKernelGGL(kb_step2, dim3(fg), dim3(kFinBlock), 0, s, B);
     };
 
-    // ---- CG chunks.  Without profiling a chunk is captured into a graph on
-    // the context's private capture stream (the caller's stream may be the
-    // legacy default stream, which cannot be captured) and replayed on the
-    // caller's stream; one graph per size class of the running list (the
-    // grid is fixed at capture, the lists are read from device memory).
-    // With profiling on, or if capture fails, the launches are enqueued one
-    // by one, bracketed by events when profiling.
+    // ---- chunks of global steps.  Without profiling a chunk is captured
+    // into a graph on the context's private capture stream (the caller's
+    // stream may be the legacy default stream, which cannot be captured) and
+    // replayed on the caller's stream, one graph per size class of the
+    // running list.  With profiling on, or if capture fails, steps are
+    // launched one by one (with profiling, one step per chunk, each pass
+    // bracketed by events).
     const int chunk = o->cg_chunk > 0 ? o->cg_chunk : 16;
     GraphCache graphs;
     bool use_graph = NNQP_BATCH_GRAPH && !ctx->prof;
@@ -972,12 +1232,12 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         auto it = graphs.by_class.find(cls);
         if (it != graphs.by_class.end()) return it->second.exec;
         const int gr = grid_for(sh, (int64_t)1 << cls);
-        const int fg = std::min(P, 1 << cls);   // a listed problem owns at least one slice
+        const int fg = std::min(P, 1 << cls);   // a listed member owns at least one slice
         if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }
-        for (int k = 0; k < chunk; k++) cg_iter(ctx->cap_stream, gr, fg, nullptr);
+        for (int k = 0; k < chunk; k++) step(ctx->cap_stream, gr, fg, nullptr);
         hipGraph_t gph = nullptr;
         const bool ended = hipStreamEndCapture(ctx->cap_stream, &gph) == hipSuccess && gph;
         (void)hipGetLastError();
@@ -994,311 +1254,77 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         graphs.by_class[cls] = GraphCache::G{gph, ex};
         return ex;
     };
-    Events ev_cg;
-    if (ctx->prof && !ev_cg.create((size_t)4 * chunk, hipEventDefault))
+    Events ev_step;
+    if (ctx->prof && !ev_step.create(4, hipEventDefault))
         return fail(ctx, NN_EHIP, "event creation");
-    hipEvent_t *chunk_ev = ctx->prof ? ev_cg.ev.data() : nullptr;
 
-    const double vb = mixed ? 4.0 : 8.0;   // bytes per CG vector entry and per value
-    const double ib = (mixed && all_d16) ? 2.0 : 4.0;   // bytes per column index
-    std::vector<int> it_before(P);
-    std::vector<double> b_spmv(chunk), b_upd(chunk);
+    // Every member's step count is bounded by its caps (outer iterations,
+    // trials per search, CG iterations); the guard only stops a runaway loop.
+    const int64_t max_steps =
+        (int64_t)(o->max_outer + 1) * (4 + 2 * kMaxTrials + 21 + o->max_cg) + 16;
     nn_status err = NN_OK;
-#define NN_BFAIL(msg)                  \
-    {                                  \
-        err = fail(ctx, NN_EHIP, msg); \
-        break;                         \
-    }
-
-    enum { C_FIRST, C_EXT, C_INT, C_DONE };
-    std::vector<int> cst(P), cur(P), nstep(P), sst(P);
-    std::vector<double> t(P), gs(P), sks(P), ss(P), bmin(P), wn(P), ts(P);
-    auto ok_dec = [&](int p, double a, double b, double s2) {
-        return a < 0.0 && a + 0.5 * b <= kMu0 * a && std::sqrt(s2) <= delta[p];
-    };
-    auto stepping = [&](int p) { return hb[p].active != 0 && hb[p].t != 0.0; };
-    for (int it_outer = 0; any_active(); it_outer++) {
-        // ---- 1. gradient, convergence test per problem
-        for (int p = 0; p < P; p++) hb[p].t = 0.0;
-        if (!push() || !select(is_active)) NN_BFAIL("batch state upload");
-        prof_begin(ctx, KC_GRAD, -1.0);
-        NN_BDISPATCH(wmax, (kb_grad<WM>), grid(), blk, st, B, g);
-        prof_end(ctx);
-        hipLaunchKernelGGL((kb_finalize<5, 0>), dim3(fgrid()), dim3(kFinBlock), 0, st, B,
-                           opsc(OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM), 0.0);
-        if (!pull_res()) NN_BFAIL("batch read-back");
-        for (int p = 0; p < P; p++) {
-            if (!hb[p].active) continue;
-            const double *r = &pres[(size_t)p * kBNV];
-            const double n = nrow[p], nz = (double)K[p]->nnz;
-            SP[p].spmvs++;
-            SP[p].bytes_moved += 4.0 * (n + 1) + 12.0 * nz + 32.0 * n;
-            if (r[1] != 0.0) {
-                status[p] = NN_ENONFINITE;
-                hb[p].active = 0;
-                continue;
-            }
-            SP[p].kkt_rel = std::sqrt(r[0]) / normf[p];
-            SP[p].kkt_nat_inf = r[2];
-            SP[p].min_c = r[3];
-            SP[p].n_active = (int32_t)r[4];
-            SP[p].outer_its = outer[p];
-            if (mixed) SP[p].refinements = outer[p] + 1;
-            if (SP[p].kkt_rel <= o->tol) {
-                status[p] = NN_OK;
-                hb[p].active = 0;
-            } else if (outer[p] >= o->max_outer) {
-                status[p] = NN_EMAXIT;
-                hb[p].active = 0;
-            }
+    int64_t steps = 0;
+    while (steps < max_steps) {
+        if (!select()) {
+            err = fail(ctx, NN_EHIP, "batch list upload");
+            break;
         }
-        if (!any_active()) break;
-
-        // ---- 2. Cauchy points: per-problem projected searches along -g
-        // (start from the previous step, extrapolate x10 while the decrease
-        // test holds, else interpolate x0.1 until it holds)
-        for (int p = 0; p < P; p++) {
-            cst[p] = hb[p].active ? C_FIRST : C_DONE;
-            cur[p] = 0;
-            nstep[p] = 0;
-            t[p] = tcau[p];
+        if (n_pr == 0) break;
+        const int gr = grid_for(sh, n_sl);
+        if (ctx->prof) {
+            // one step; algorithmic bytes of the row pass from the states
+            double brow = 0.0;
+            for (int p = 0; p < P; p++)
+                if (hs[p].phase != PH_DONE) brow += row_bytes(hs[p]);
+            step(st, gr, std::max(n_pr, 1), ev_step.ev.data());
+            steps++;
+            if (!pull()) {
+                err = fail(ctx, NN_EHIP, "batch read-back");
+                break;
+            }
+            float m1 = 0.f, m2 = 0.f;
+            if (brow > 0.0 && ((ctx->prof_mask >> KC_CG_SPMV) & 1) &&
+                hipEventElapsedTime(&m1, ev_step.ev[0], ev_step.ev[1]) == hipSuccess)
+                prof_add(ctx, KC_CG_SPMV, m1, brow);
+            if (((ctx->prof_mask >> KC_CG_UPDATE) & 1) &&
+                hipEventElapsedTime(&m2, ev_step.ev[2], ev_step.ev[3]) == hipSuccess)
+                prof_add(ctx, KC_CG_UPDATE, m2, 0.0);
+            (void)hipGetLastError();
+            continue;
         }
-        for (;;) {
-            bool any = false;
-            for (int p = 0; p < P; p++) {
-                hb[p].t = 0.0;
-                if (!hb[p].active || cst[p] == C_DONE) continue;
-                any = true;
-                hb[p].t = -(cst[p] == C_EXT ? t[p] * kExtrap : t[p]);
-                hb[p].ksbuf = cst[p] == C_EXT ? (cur[p] ^ 1) : cur[p];
+        hipGraphExec_t ex = use_graph ? graph_for(n_sl) : nullptr;
+        if (ex) {
+            if (hipGraphLaunch(ex, st) != hipSuccess) {
+                err = fail(ctx, NN_EHIP, "graph launch");
+                break;
             }
-            if (!any) break;
-            if (!push() || !select(stepping)) NN_BFAIL("batch state upload");
-            prof_begin(ctx, KC_TRIAL, -1.0);
-            trial(false, nullptr, 1);
-            prof_end(ctx);
-            if (!pull_res()) NN_BFAIL("batch read-back");
-            for (int p = 0; p < P; p++) {
-                if (!hb[p].active || cst[p] == C_DONE) continue;
-                const double *r = &pres[(size_t)p * kBNV];
-                const double n = nrow[p], nz = (double)K[p]->nnz;
-                SP[p].spmvs++;
-                SP[p].cauchy_trials++;
-                SP[p].bytes_moved += 4.0 * (n + 1) + (ib + vb) * nz + 32.0 * n;
-                const bool ok = ok_dec(p, r[0], r[1], r[2]);
-                if (cst[p] == C_FIRST) {
-                    if (ok) {
-                        gs[p] = r[0], sks[p] = r[1], ss[p] = r[2];
-                        cst[p] = C_EXT;
-                    } else {
-                        cst[p] = C_INT;
-                        t[p] *= kInterp;
-                    }
-                } else if (cst[p] == C_EXT) {
-                    if (!ok) {
-                        cst[p] = C_DONE;
-                    } else {
-                        const bool same = r[0] == gs[p] && r[1] == sks[p];
-                        t[p] *= kExtrap;
-                        cur[p] ^= 1;
-                        gs[p] = r[0], sks[p] = r[1], ss[p] = r[2];
-                        // stop when every moving variable has reached its bound
-                        if (same || ++nstep[p] >= 20) cst[p] = C_DONE;
-                    }
-                } else {
-                    gs[p] = r[0], sks[p] = r[1], ss[p] = r[2];
-                    if (ok) {
-                        cst[p] = C_DONE;
-                    } else if (++nstep[p] >= kMaxTrials || !(r[0] < 0.0)) {
-                        // no decrease along -g at this precision: stationary up to rounding
-                        status[p] = NN_EMAXIT;
-                        hb[p].active = 0;
-                        cst[p] = C_DONE;
-                    } else {
-                        t[p] *= kInterp;
-                    }
-                }
-            }
+        } else {
+            for (int k = 0; k < chunk; k++) step(st, gr, std::max(n_pr, 1), nullptr);
         }
-        if (err != NN_OK) break;
-        if (!any_active()) break;
-        for (int p = 0; p < P; p++) {
-            hb[p].t = 0.0;
-            if (!hb[p].active) continue;
-            tcau[p] = t[p];
-            hb[p].t = -t[p];
-            hb[p].ksbuf = cur[p];
-            SP[p].bytes_moved += 24.0 * nrow[p];
+        steps += chunk;
+        if (!pull()) {
+            err = fail(ctx, NN_EHIP, "batch read-back");
+            break;
         }
-        if (!push() || !select(is_active)) NN_BFAIL("batch state upload");
-        apply(false);
-
-        // ---- 3. Jacobi-PCG on every free face together
-        if (mixed)
-            hipLaunchKernelGGL((kb_cg_setup<float>), dim3(grid()), dim3(blk), 0, st, B, g, ks0,
-                               ks1, mask, dm32, r32, z32, p32, q32, w32);
-        else
-            hipLaunchKernelGGL((kb_cg_setup<double>), dim3(grid()), dim3(blk), 0, st, B, g, ks0,
-                               ks1, mask, dm64, r64, z64, p64, q64, w64);
-        hipLaunchKernelGGL((kb_finalize<4, 1>), dim3(fgrid()), dim3(kFinBlock), 0, st, B,
-                           opsc(OP_SUM, OP_SUM, OP_SUM, OP_SUM), o->inner_rtol * o->inner_rtol);
-        if (!pull_state()) NN_BFAIL("batch read-back");
-        for (int p = 0; p < P; p++) {
-            it_before[p] = 0;
-            if (hb[p].active) SP[p].bytes_moved += 88.0 * nrow[p];
-        }
-        auto running = [&](int p) { return hb[p].active != 0 && hb[p].done == 0; };
-        for (int guard = 0; guard <= o->max_cg / chunk + 1; guard++) {
-            if (!select(running)) NN_BFAIL("batch list upload");
-            if (n_pr == 0) break;
-            hipGraphExec_t ex = use_graph ? graph_for(n_sl) : nullptr;
-            if (ex) {
-                if (hipGraphLaunch(ex, st) != hipSuccess) NN_BFAIL("graph launch");
-            } else {
-                for (int k = 0; k < chunk; k++)
-                    cg_iter(st, grid(), fgrid(), chunk_ev ? chunk_ev + (size_t)4 * k : nullptr);
-            }
-            if (!pull_state()) NN_BFAIL("batch read-back");
-            // launch k of the chunk did work for the problems that ran more
-            // than k iterations in it; byte model as in the single-problem
-            // solver (mask, free-row values and indices, gathered and
-            // streamed vectors)
-            std::fill(b_spmv.begin(), b_spmv.end(), 0.0);
-            std::fill(b_upd.begin(), b_upd.end(), 0.0);
-            int ran_max = 0;
-            for (int p = 0; p < P; p++) {
-                if (!hb[p].active) continue;
-                const int ran = hb[p].it - it_before[p];
-                if (ran <= 0) continue;
-                const double n = nrow[p], nf = hb[p].n_free, nzf = hb[p].nnz_free;
-                const double bs = n + 4.0 * nf + (ib + vb) * nzf + 5.0 * vb * nf;
-                const double bu = n + 8.0 * vb * nf;
-                for (int k = 0; k < ran && k < chunk; k++) {
-                    b_spmv[k] += bs;
-                    b_upd[k] += bu;
-                }
-                SP[p].bytes_moved += ran * (bs + bu);
-                ran_max = std::max(ran_max, ran);
-                it_before[p] = hb[p].it;
-            }
-            if (chunk_ev) {
-                for (int k = 0; k < ran_max && k < chunk; k++) {
-                    float m1 = 0.f, m2 = 0.f;
-                    if (hipEventElapsedTime(&m1, chunk_ev[4 * k], chunk_ev[4 * k + 1]) ==
-                            hipSuccess &&
-                        hipEventElapsedTime(&m2, chunk_ev[4 * k + 2], chunk_ev[4 * k + 3]) ==
-                            hipSuccess) {
-                        if ((ctx->prof_mask >> KC_CG_SPMV) & 1) prof_add(ctx, KC_CG_SPMV, m1, b_spmv[k]);
-                        if ((ctx->prof_mask >> KC_CG_UPDATE) & 1) prof_add(ctx, KC_CG_UPDATE, m2, b_upd[k]);
-                    }
-                }
-            }
-        }
-        if (err != NN_OK) break;
-        for (int p = 0; p < P; p++) {
-            if (!hb[p].active) continue;
-            SP[p].cg_its += hb[p].it;
-            SP[p].spmvs += hb[p].it;
-            if (hb[p].done == 4) {
-                status[p] = NN_ENONFINITE;
-                hb[p].active = 0;
-            } else if (hb[p].done == 3) {
-                status[p] = NN_ENOTSPD;
-                hb[p].active = 0;
-            } else if (hb[p].done == 0) {
-                status[p] = NN_EMAXIT;   // CG still running after the launch guard
-                hb[p].active = 0;
-            }
-        }
-        if (!any_active()) break;
-
-        // ---- 4. projected searches along w (no matrix pass when no free
-        // variable reaches its bound before the step)
-        for (int p = 0; p < P; p++) hb[p].t = 0.0;
-        if (!push() || !select(is_active)) NN_BFAIL("batch state upload");
-        if (mixed)
-            hipLaunchKernelGGL((kb_breakpoint<float>), dim3(grid()), dim3(blk), 0, st, B, w32, gptr);
-        else
-            hipLaunchKernelGGL((kb_breakpoint<double>), dim3(grid()), dim3(blk), 0, st, B, w64,
-                               gptr);
-        hipLaunchKernelGGL((kb_finalize<3, 0>), dim3(fgrid()), dim3(kFinBlock), 0, st, B,
-                           opsc(OP_MIN, OP_SUM, OP_SUM), 0.0);
-        if (!pull_res()) NN_BFAIL("batch read-back");
-        for (int p = 0; p < P; p++) {
-            sst[p] = 0;   // 0 no step, 1 searching, 2 step chosen
-            if (!hb[p].active) continue;
-            SP[p].bytes_moved += 24.0 * nrow[p];
-            const double *r = &pres[(size_t)p * kBNV];
-            bmin[p] = r[0];
-            wn[p] = std::sqrt(r[2]);
-            if (hb[p].it > 0 && r[1] < 0.0 && wn[p] > 0.0) {
-                ts[p] = std::min(1.0, delta[p] / wn[p]);
-                sst[p] = bmin[p] >= ts[p] ? 2 : 1;
-                nstep[p] = 0;
-            }
-        }
-        for (;;) {
-            bool any = false;
-            for (int p = 0; p < P; p++) {
-                hb[p].t = 0.0;
-                if (hb[p].active && sst[p] == 1) {
-                    hb[p].t = ts[p];
-                    any = true;
-                }
-            }
-            if (!any) break;
-            if (!push() || !select(stepping)) NN_BFAIL("batch state upload");
-            prof_begin(ctx, KC_TRIAL, -1.0);
-            trial(true, mask, 0);
-            prof_end(ctx);
-            if (!pull_res()) NN_BFAIL("batch read-back");
-            for (int p = 0; p < P; p++) {
-                if (!hb[p].active || sst[p] != 1) continue;
-                const double *r = &pres[(size_t)p * kBNV];
-                const double n = nrow[p], nz = (double)K[p]->nnz;
-                SP[p].spmvs++;
-                SP[p].search_trials++;
-                SP[p].bytes_moved += 4.0 * (n + 1) + (ib + vb) * nz + 32.0 * n;
-                if (r[0] < 0.0 && r[0] + 0.5 * r[1] <= kMu0 * r[0]) {
-                    sst[p] = 2;
-                } else {
-                    ts[p] *= kBack;
-                    if (ts[p] <= bmin[p]) {
-                        ts[p] = bmin[p];   // no bound is crossed: decrease is guaranteed
-                        sst[p] = 2;
-                    } else if (++nstep[p] >= kMaxTrials) {
-                        sst[p] = 2;
-                    }
-                }
-            }
-        }
-        if (err != NN_OK) break;
-        for (int p = 0; p < P; p++) {
-            hb[p].t = 0.0;
-            if (!hb[p].active) continue;
-            double step = std::sqrt(ss[p]);
-            if (sst[p] == 2 && ts[p] > 0.0) {
-                hb[p].t = ts[p];
-                step += ts[p] * wn[p];
-                SP[p].bytes_moved += 24.0 * nrow[p];
-            }
-            // ---- 5. radius update (exact model: ratio one)
-            if (std::isfinite(delta[p]) && step >= 0.99 * delta[p]) delta[p] *= 4.0;
-            outer[p]++;
-        }
-        if (!push() || !select(stepping)) NN_BFAIL("batch state upload");
-        if (n_pr > 0) apply(true);
         if (o->verbose) {
-            int na = 0;
-            for (int p = 0; p < P; p++) na += hb[p].active ? 1 : 0;
+            int nr = 0, ncg = 0;
+            for (int p = 0; p < P; p++) {
+                nr += hs[p].phase != PH_DONE ? 1 : 0;
+                ncg += hs[p].phase == PH_CG ? 1 : 0;
+            }
             std::fprintf(stderr,
-                         "nnqp batch outer %3d: %d of %d problems iterating; member 0: kkt %.3e "
-                         "free %.0f cauchy t %.3g cg %d breakpoint %.3g step %.3g\n",
-                         it_outer, na, P, SP[0].kkt_rel, hb[0].n_free, tcau[0], hb[0].it, bmin[0],
-                         sst[0] == 2 ? ts[0] : 0.0);
+                         "nnqp batch step %lld: %d of %d members running (%d in CG); member 0: "
+                         "outer %d kkt %.3e\n",
+                         (long long)steps, nr, P, ncg, hs[0].outer, hs[0].kkt_rel);
         }
     }
-#undef NN_BFAIL
+    if (err == NN_OK && steps >= max_steps) {
+        for (int p = 0; p < P; p++)
+            if (hs[p].phase != PH_DONE) {
+                hs[p].status = NN_EMAXIT;
+                hs[p].phase = PH_DONE;
+            }
+    }
     // ---- outputs
     if (active) {
         const int64_t blocks = std::min<int64_t>((S + 3) / 4, (int64_t)num_cu * 8);
@@ -1313,9 +1339,23 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     if (e != hipSuccess) return fail(ctx, NN_EHIP, hipGetErrorString(e));
     int first_bad = -1;
     for (int p = 0; p < P; p++) {
-        SP[p].seconds = ms * 1e-3;   // the whole batched call
-        SP[p].status = status[p];
-        if (status[p] != NN_OK && first_bad < 0) first_bad = p;
+        const BState &M = hs[p];
+        nn_stats &Q = SP[p];
+        Q.kkt_rel = M.kkt_rel;
+        Q.kkt_nat_inf = M.kkt_nat;
+        Q.min_c = M.min_c;
+        Q.norm_f = M.normf;
+        Q.outer_its = M.outer;
+        Q.cg_its = M.cg_its;
+        Q.spmvs = M.spmvs;
+        Q.n_active = M.n_active;
+        Q.cauchy_trials = M.cauchy_trials;
+        Q.search_trials = M.search_trials;
+        Q.refinements = M.refinements;
+        Q.status = M.status;
+        Q.bytes_moved = M.bytes;
+        Q.seconds = ms * 1e-3;   // the whole batched call
+        if (M.status != NN_OK && first_bad < 0) first_bad = p;
     }
     if (stats)
         for (int p = 0; p < P; p++) stats[p] = SP[p];
@@ -1324,8 +1364,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         std::snprintf(msg, sizeof(msg),
                       "batch member %d (the first affected) ended with status %d; every member's "
                       "status is in its stats",
-                      first_bad, status[first_bad]);
-        return fail(ctx, (nn_status)status[first_bad], msg);
+                      first_bad, hs[first_bad].status);
+        return fail(ctx, (nn_status)hs[first_bad].status, msg);
     }
     ctx->err.clear();
     return NN_OK;
