@@ -116,6 +116,16 @@ struct BDev {
     BState *st;
     double *part;                   // [nslices][kBNV]
     double *pres;                   // [P][kBNV] (start-up reductions)
+    // the batch as one block-diagonal sliced-ELL matrix and concatenated
+    // vectors (global rows s*64 + lane), copied in at the start of a call
+    const int *gso;                 // [nslices+1] first entry of each slice
+    const int *gcol;                // global column of each entry
+    const short *gd16;              // col - row (int16), or null
+    const double *gv64;             // float64 values of the solve
+    const float *gv32;              // float32 values (mixed precision), or null
+    double *cg, *fg;                // solution and load
+    const double *dg;               // diagonal of the solve's matrix (1 on rows past the end)
+    const int *rlen;                // entries of each row (0 past the end)
 };
 
 // Work vectors of the batched solve, concatenated over the slices.
@@ -225,7 +235,107 @@ __device__ __forceinline__ double bsell_row(const BDev &B, const VT *__restrict_
     return acc;
 }
 
+// Row sums over the concatenated matrix: slice s, global row i = s*64 + lane,
+// global columns (int16 offsets from the row in CM_D16 mode).
+template <int WMAX, int CM, class VT, class X>
+__device__ __forceinline__ double gsell_row(const BDev &B, const VT *__restrict__ sv, int s, int i,
+                                            X x)
+{
+    const int lane = threadIdx.x & 63;
+    const int *__restrict__ gc = B.gcol;
+    const short *__restrict__ gd = B.gd16;
+    auto col = [&](int e) {
+        if (CM == CM_D16) return i + (int)gd[e];
+        return gc[e];
+    };
+    const int off = B.gso[s];
+    const int w = (B.gso[s + 1] - off) >> 6;
+    double acc = 0.0;
+    constexpr int H = WMAX < 8 ? WMAX : 8;
+#pragma unroll
+    for (int h0 = 0; h0 < WMAX; h0 += H) {
+        int cc[H];
+        VT vv[H];
+#pragma unroll
+        for (int k = 0; k < H; k++) {
+            if (h0 + k < w) {
+                cc[k] = col(off + (h0 + k) * kSlice + lane);
+                vv[k] = bld_val(sv + off + (h0 + k) * kSlice + lane);
+            } else {
+                cc[k] = 0;
+                vv[k] = VT(0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < H; k++)
+            if (h0 + k < w) acc += (double)vv[k] * x(cc[k]);
+    }
+    for (int k = WMAX; k < w; k++) {
+        const int e = off + k * kSlice + lane;
+        acc += (double)bld_val(sv + e) * x(col(e));
+    }
+    return acc;
+}
+
 __device__ __forceinline__ bool running(const BDev &B, int p) { return B.st[p].phase != PH_DONE; }
+
+// Copy the members into the concatenated layout (every slice of the batch):
+// c, f, diagonal and row lengths into the global vectors; slice offsets
+// (ebase[p] + the member's own offset), global columns, int16 offsets and
+// values into the global matrix arrays.  Rows past a member's end get c = 0,
+// f = 0, diagonal 1, length 0; their entries keep their valid columns.
+__global__ void kb_gather(BDev B, const int64_t *__restrict__ ebase, int *__restrict__ gso,
+                          int *__restrict__ gcol, short *__restrict__ gd16,
+                          double *__restrict__ gv64, float *__restrict__ gv32,
+                          double *__restrict__ dg, int *__restrict__ rlen, int copy_f)
+{
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    for (int s = blockIdx.x * wpb + wid; s < B.nslices; s += nw) {
+        const int p = B.sprob[s];
+        const int ls = s - B.s0[p];
+        const int il = ls * kSlice + lane, i = s * kSlice + lane;
+        const int r0 = B.s0[p] * kSlice;
+        const bool row = il < B.nrow[p];
+        B.cg[i] = row ? B.c[p][il] : 0.0;
+        if (copy_f) B.fg[i] = row ? B.f[p][il] : 0.0;
+        dg[i] = row ? B.diag[p][il] : 1.0;
+        rlen[i] = row ? B.rowptr[p][il + 1] - B.rowptr[p][il] : 0;
+        const int *so = B.so[p];
+        const int src = so[ls], w = (so[ls + 1] - src) >> 6;
+        const int dst = (int)(ebase[p] + src);
+        if (lane == 0) gso[s] = dst;
+        const int *sc = B.sc[p];
+        const short *sd = B.sd[p];
+        const double *v64 = B.v64[p];
+        const float *v32 = B.v32[p];
+        for (int k = 0; k < w; k++) {
+            const int es = src + k * kSlice + lane, ed = dst + k * kSlice + lane;
+            gcol[ed] = sc[es] + r0;
+            if (gd16) gd16[ed] = sd[es];
+            gv64[ed] = v64[es];
+            if (gv32) gv32[ed] = v32[es];
+        }
+    }
+}
+
+// Copy the solution back to the members' vectors, and the active sets.
+__global__ void kb_scatter(BDev B)
+{
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    for (int s = blockIdx.x * wpb + wid; s < B.nslices; s += nw) {
+        const int p = B.sprob[s];
+        const int il = (s - B.s0[p]) * kSlice + lane;
+        if (il >= B.nrow[p]) continue;
+        const double cv = B.cg[s * kSlice + lane];
+        B.c[p][il] = cv;
+        uint8_t *out = B.act_out[p];
+        if (out) out[il] = cv == 0.0 ? 1 : 0;
+    }
+}
 
 // ---------------------------------------------------------------- start-up kernels
 // c = c0v (mode 0) or P(c) (mode 1); |f|^2, max f, #non-finite f, #non-finite c
@@ -233,19 +343,19 @@ __global__ void kb_init(BDev B, int mode, double c0v)
 {
     const int ops[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
     for_bslices<4>(B, ops, [&](int p) { return running(B, p); },
-                   [&](int p, int, int, int il, bool row, double (&a)[4]) {
+                   [&](int, int, int i, int, bool row, double (&a)[4]) {
                        if (!row) return;
-                       const double fi = B.f[p][il];
+                       const double fi = B.fg[i];
                        a[0] += fi * fi;
                        a[1] = fmax(a[1], fi);
                        a[2] += isfinite(fi) ? 0.0 : 1.0;
-                       double *c = B.c[p];
+                       double *c = B.cg;
                        if (mode == 0) {
-                           c[il] = c0v;
+                           c[i] = c0v;
                        } else {
-                           const double cv = c[il];
+                           const double cv = c[i];
                            a[3] += isfinite(cv) ? 0.0 : 1.0;
-                           c[il] = proj0b(cv);
+                           c[i] = proj0b(cv);
                        }
                    });
 }
@@ -262,6 +372,7 @@ __global__ void kb_transient_rhs(BDev B, double dt, double *__restrict__ ft)
                        const double mc =
                            bsell_row<WMAX, CM_I32>(B, B.mv[p], p, s, [&](int j) { return c[j]; });
                        if (row) ft[i] = B.f0[p][il] + mc / dt;
+                       else ft[i] = 0.0;
                    });
 }
 
@@ -271,28 +382,14 @@ __global__ void kb_grad(BDev B, double *__restrict__ g)
 {
     const int ops[1] = {OP_SUM};
     for_bslices<1>(B, ops, [&](int p) { return running(B, p); },
-                   [&](int p, int s, int i, int il, bool row, double (&a)[1]) {
-                       const double *c = B.c[p];
+                   [&](int, int s, int i, int, bool row, double (&a)[1]) {
+                       const double *c = B.cg;
                        const double kc =
-                           bsell_row<WMAX, CM_I32>(B, B.v64[p], p, s, [&](int j) { return c[j]; });
+                           gsell_row<WMAX, CM_I32>(B, B.gv64, s, i, [&](int j) { return c[j]; });
                        if (!row) return;
-                       g[i] = kc - B.f[p][il];
+                       g[i] = kc - B.fg[i];
                        a[0] += g[i];
                    });
-}
-
-// active-set outputs: 1 where c == 0
-__global__ void kb_active(BDev B)
-{
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    const int nw = gridDim.x * wpb;
-    for (int s = blockIdx.x * wpb + wid; s < B.nslices; s += nw) {
-        const int p = B.sprob[s];
-        uint8_t *out = B.act_out[p];
-        const int il = (s - B.s0[p]) * kSlice + lane;
-        if (out && il < B.nrow[p]) out[il] = B.c[p][il] == 0.0 ? 1 : 0;
-    }
 }
 
 // Combine NV slice partials of member p in a fixed order (thread t takes
@@ -349,31 +446,28 @@ __global__ __launch_bounds__(kFinBlock) void kb_reduce_init(BDev B)
 //   CG      p <- z + beta p, q <- K z + beta q on the free rows; p.q
 //   SEARCH  s = P(c + ts w) - c on the free rows, K s; g.s, s.Ks, s.s
 template <int WMAX, int CM, class VT, class VV>
-__global__ void kb_rows(BDev B, const VT *const *vals, BVec<VV> V)
+__global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
 {
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
     const int nlist = B.cnt[0];
+    const double *__restrict__ c = B.cg;
     for (int k = blockIdx.x * wpb + wid; k < nlist; k += nw) {
         const int s = B.slist[k];
         const int p = B.sprob[s];
         const BState &S = B.st[p];
         const int ph = S.phase;
-        const int il = (s - B.s0[p]) * kSlice + lane;
         const int i = s * kSlice + lane;
-        const bool row = il < B.nrow[p];
-        const int r0 = B.s0[p] * kSlice;
-        double *__restrict__ c = B.c[p];
+        const bool row = (s - B.s0[p]) * kSlice + lane < B.nrow[p];
         double a[kBNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if (ph == PH_GRAD) {
             a[2] = -INFINITY;
             a[3] = INFINITY;
-            const double kc =
-                bsell_row<WMAX, CM_I32>(B, B.v64[p], p, s, [&](int j) { return c[j]; });
+            const double kc = gsell_row<WMAX, CM_I32>(B, B.gv64, s, i, [&](int j) { return c[j]; });
             if (row) {
-                const double gi = kc - B.f[p][il];
-                const double cv = c[il];
+                const double gi = kc - B.fg[i];
+                const double cv = c[i];
                 V.g[i] = gi;
                 const double pg = cv > 0.0 ? gi : (gi < 0.0 ? gi : 0.0);
                 a[0] = pg * pg;
@@ -387,12 +481,12 @@ __global__ void kb_rows(BDev B, const VT *const *vals, BVec<VV> V)
             const double *__restrict__ g = V.g;
             auto sv = [&](int j) {
                 const double cj = c[j];
-                return proj0b(cj + t * g[r0 + j]) - cj;
+                return proj0b(cj + t * g[j]) - cj;
             };
-            const double ksv = bsell_row<WMAX, CM>(B, vals[p], p, s, sv);
+            const double ksv = gsell_row<WMAX, CM>(B, gvals, s, i, sv);
             if (row) {
                 (S.ksbuf ? V.ks1 : V.ks0)[i] = ksv;
-                const double si = sv(il);
+                const double si = sv(i);
                 a[0] = g[i] * si;
                 a[1] = si * ksv;
                 a[2] = si * si;
@@ -402,7 +496,7 @@ __global__ void kb_rows(BDev B, const VT *const *vals, BVec<VV> V)
             if (__ballot(live) != 0) {
                 const VV *__restrict__ z = V.z;
                 const double kz =
-                    bsell_row<WMAX, CM>(B, vals[p], p, s, [&](int j) { return (double)z[r0 + j]; });
+                    gsell_row<WMAX, CM>(B, gvals, s, i, [&](int j) { return (double)z[j]; });
                 if (live) {
                     const double beta = S.beta;
                     const VV pi = (VV)fma(beta, (double)V.p[i], (double)z[i]);
@@ -419,11 +513,11 @@ __global__ void kb_rows(BDev B, const VT *const *vals, BVec<VV> V)
                 const VV *__restrict__ w = V.w;
                 auto sv = [&](int j) {
                     const double cj = c[j];
-                    return proj0b(cj + t * (double)w[r0 + j]) - cj;
+                    return proj0b(cj + t * (double)w[j]) - cj;
                 };
-                const double ksv = bsell_row<WMAX, CM>(B, vals[p], p, s, sv);
+                const double ksv = gsell_row<WMAX, CM>(B, gvals, s, i, sv);
                 if (live) {
-                    const double si = sv(il);
+                    const double si = sv(i);
                     a[0] = V.g[i] * si;
                     a[1] = si * ksv;
                     a[2] = si * si;
@@ -623,10 +717,9 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
         const BState &S = B.st[p];
         const int vop = S.vop;
         if (vop == VO_NONE) continue;
-        const int il = (s - B.s0[p]) * kSlice + lane;
         const int i = s * kSlice + lane;
-        const bool row = il < B.nrow[p];
-        double *__restrict__ c = B.c[p];
+        const bool row = (s - B.s0[p]) * kSlice + lane < B.nrow[p];
+        double *__restrict__ c = B.cg;
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         if (vop == VO_SETUP) {
             if (!row) {
@@ -634,12 +727,12 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
                 V.dm[i] = V.r[i] = V.z[i] = V.p[i] = V.q[i] = V.w[i] = VV(0);
             } else {
                 const double gi0 = V.g[i];
-                const double cv = proj0b(c[il] - S.t * gi0);
+                const double cv = proj0b(c[i] - S.t * gi0);
                 const double gi = gi0 + (S.cur ? V.ks1 : V.ks0)[i];
-                c[il] = cv;
+                c[i] = cv;
                 V.g[i] = gi;
                 const bool fr = !(cv == 0.0 && gi >= 0.0);
-                const VV dmi = fr ? (VV)(1.0 / B.diag[p][il]) : VV(0);
+                const VV dmi = fr ? (VV)(1.0 / B.dg[i]) : VV(0);
                 const VV ri = fr ? (VV)(-gi) : VV(0);
                 const VV zi = dmi * ri;
                 V.mask[i] = fr ? 1 : 0;
@@ -652,8 +745,7 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
                 a[0] = (double)ri * (double)zi;
                 a[1] = (double)ri * (double)ri;
                 a[2] = fr ? 1.0 : 0.0;
-                const int *rp = B.rowptr[p];
-                a[3] = fr ? (double)(rp[il + 1] - rp[il]) : 0.0;
+                a[3] = fr ? (double)B.rlen[i] : 0.0;
             }
         } else if (vop == VO_UPDATE) {
             if (row && V.mask[i]) {
@@ -670,12 +762,12 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
             a[0] = INFINITY;
             if (row) {
                 const double wi = (double)V.w[i];
-                if (wi < 0.0) a[0] = c[il] / (-wi);
+                if (wi < 0.0) a[0] = c[i] / (-wi);
                 a[1] = V.g[i] * wi;
                 a[2] = wi * wi;
             }
         } else {   // VO_APPLYW
-            if (row) c[il] = proj0b(c[il] + S.ts * (double)V.w[i]);
+            if (row) c[i] = proj0b(c[i] + S.ts * (double)V.w[i]);
             continue;
         }
 #pragma unroll
@@ -958,8 +1050,23 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     BState *d_st = A.d<BState>(P);
     double *d_part = A.d<double>((size_t)S * kBNV), *d_pres = A.d<double>((size_t)P * kBNV);
     double *g = A.d<double>(R), *ks0 = A.d<double>(R), *ks1 = A.d<double>(R);
-    double *ft = transient ? A.d<double>(R) : nullptr;
     uint8_t *mask = A.d<uint8_t>(R);
+    // concatenated layout: vectors and the block-diagonal matrix
+    std::vector<int64_t> ebase(P);
+    int64_t E = 0;
+    for (int p = 0; p < P; p++) {
+        ebase[p] = E;
+        E += K[p]->n > 0 ? K[p]->nsell : 0;
+    }
+    if (E >= (int64_t)1 << 31) return fail(ctx, NN_EINVAL, "batch too large: sliced-ELL entries must stay below 2^31");
+    double *cg = A.d<double>(R), *fg = A.d<double>(R), *dg = A.d<double>(R);
+    int *rlen = A.d<int>(R);
+    double *ft = fg;   // a transient step's loads f + M c/dt are formed in place
+    int *gso = A.d<int>(S + 1), *gcol = A.d<int>(E);
+    int64_t *d_ebase = A.d<int64_t>(P);
+    double *gv64 = A.d<double>(E);
+    float *gv32 = mixed ? A.d<float>(E) : nullptr;
+    short *gd16 = (mixed && all_d16) ? A.d<short>(E) : nullptr;
     BVec<double> V64{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     BVec<float> V32{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (mixed) {
@@ -1014,6 +1121,10 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         NN_HIP_TRY(ctx, hipMemcpyAsync(d_s0, s0.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
         NN_HIP_TRY(ctx,
                    hipMemcpyAsync(d_nrow, nrow.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+        NN_HIP_TRY(ctx, hipMemcpyAsync(d_ebase, ebase.data(), sizeof(int64_t) * P,
+                                       hipMemcpyHostToDevice, st));
+        const int e_total = (int)E;
+        NN_HIP_TRY(ctx, hipMemcpyAsync(gso + S, &e_total, sizeof(int), hipMemcpyHostToDevice, st));
         // the pageable sources above must stay alive until the copies finish
         NN_HIP_TRY(ctx, hipStreamSynchronize(st));
     }
@@ -1041,6 +1152,15 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     B.st = d_st;
     B.part = d_part;
     B.pres = d_pres;
+    B.gso = gso;
+    B.gcol = gcol;
+    B.gd16 = gd16;
+    B.gv64 = gv64;
+    B.gv32 = gv32;
+    B.cg = cg;
+    B.fg = fg;
+    B.dg = dg;
+    B.rlen = rlen;
 
     // ---- member states
     std::memset(hs, 0, sizeof(BState) * P);
@@ -1125,6 +1245,13 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     // ---- transient right-hand sides (from c^n, before the start point is set)
     if (transient)
         NN_BDISPATCH(wmax, (kb_transient_rhs<WM>), grid_for(sh, n_sl), sh.block, st, B, dt, ft);
+    // ---- the members into the concatenated layout
+    {
+        const int64_t blocks = std::min<int64_t>((S + 3) / 4, (int64_t)num_cu * 8);
+        hipLaunchKernelGGL(kb_gather, dim3((int)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, B,
+                           (const int64_t *)d_ebase, gso, gcol, gd16, gv64, gv32, dg, rlen,
+                           transient ? 0 : 1);
+    }
     // ---- start point and load statistics
     hipLaunchKernelGGL(kb_init, dim3(grid_for(sh, n_sl)), dim3(sh.block), 0, st, B,
                        o->c0_mode == 1 ? 1 : 0, o->c0_value);
@@ -1143,7 +1270,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
             M.phase = PH_DONE;
         } else if (!(r[1] > 0.0)) {
             // f <= 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0
-            NN_HIP_TRY(ctx, hipMemsetAsync(c[p], 0, sizeof(double) * nrow[p], st));
+            NN_HIP_TRY(ctx, hipMemsetAsync(cg + (size_t)s0[p] * kSlice, 0,
+                                           sizeof(double) * nrow[p], st));
             M.n_active = nrow[p];
             M.phase = PH_DONE;
         }
@@ -1195,11 +1323,14 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     auto step = [&](hipStream_t s, int gr, int fg, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[0], s);
         if (mixed && all_d16)
-            NN_BDISPATCH(wmax, (kb_rows<WM, CM_D16, float, float>), gr, blk, s, B, d_v32, V32);
+            NN_BDISPATCH(wmax, (kb_rows<WM, CM_D16, float, float>), gr, blk, s, B,
+                         (const float *)gv32, V32);
         else if (mixed)
-            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, float, float>), gr, blk, s, B, d_v32, V32);
+            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, float, float>), gr, blk, s, B,
+                         (const float *)gv32, V32);
         else
-            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, double, double>), gr, blk, s, B, d_v64, V64);
+            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, double, double>), gr, blk, s, B,
+                         (const double *)gv64, V64);
         if (ev) (void)hipEventRecord(ev[1], s);
         hipLaunchKernelGGL(kb_step1, dim3(fg), dim3(kFinBlock), 0, s, B);
         if (ev) (void)hipEventRecord(ev[2], s);
@@ -1325,10 +1456,10 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                 hs[p].phase = PH_DONE;
             }
     }
-    // ---- outputs
-    if (active) {
+    // ---- outputs: the solutions back into the members' vectors, active sets
+    {
         const int64_t blocks = std::min<int64_t>((S + 3) / 4, (int64_t)num_cu * 8);
-        hipLaunchKernelGGL(kb_active, dim3((int)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, B);
+        hipLaunchKernelGGL(kb_scatter, dim3((int)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, B);
     }
     (void)hipEventRecord(t1, st);
     const hipError_t e = hipEventSynchronize(t1);
