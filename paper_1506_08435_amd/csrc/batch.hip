@@ -453,9 +453,16 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
     const int nw = gridDim.x * wpb;
     const int nlist = B.cnt[0];
     const double *__restrict__ c = B.cg;
-    for (int k = blockIdx.x * wpb + wid; k < nlist; k += nw) {
-        const int s = B.slist[k];
-        const int p = B.sprob[s];
+    int k = blockIdx.x * wpb + wid;
+    int s_next = k < nlist ? B.slist[k] : 0;
+    int p_next = k < nlist ? B.sprob[s_next] : 0;
+    for (; k < nlist; k += nw) {
+        const int s = s_next;
+        const int p = p_next;
+        if (k + nw < nlist) {   // next slice's list entry and member, ahead of this slice's work
+            s_next = B.slist[k + nw];
+            p_next = B.sprob[s_next];
+        }
         const BState &S = B.st[p];
         const int ph = S.phase;
         const int i = s * kSlice + lane;
@@ -526,20 +533,29 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
         } else {
             continue;   // no row work: the transition does not read these partials
         }
-        // wave combination (the phase is uniform in the wave)
+        // wave combination (the phase is uniform in the wave): only the
+        // values the phase reports
+        const int nv = ph == PH_GRAD ? 5 : (ph == PH_CG ? 1 : 3);
+        if (nv == 1) {
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
+            for (int o = 32; o >= 1; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+        } else if (nv == 3) {
 #pragma unroll
-            for (int v = 0; v < kBNV; v++) {
-                const double other = __shfl_xor(a[v], o, 64);
-                if (ph == PH_GRAD && v == 2) a[v] = fmax(a[v], other);
-                else if (ph == PH_GRAD && v == 3) a[v] = fmin(a[v], other);
-                else a[v] += other;
+            for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+                for (int v = 0; v < 3; v++) a[v] += __shfl_xor(a[v], o, 64);
+        } else {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                a[0] += __shfl_xor(a[0], o, 64);
+                a[1] += __shfl_xor(a[1], o, 64);
+                a[2] = fmax(a[2], __shfl_xor(a[2], o, 64));
+                a[3] = fmin(a[3], __shfl_xor(a[3], o, 64));
+                a[4] += __shfl_xor(a[4], o, 64);
             }
         }
         if (lane == 0)
-#pragma unroll
-            for (int v = 0; v < kBNV; v++) B.part[(size_t)s * kBNV + v] = a[v];
+            for (int v = 0; v < nv; v++) B.part[(size_t)s * kBNV + v] = a[v];
     }
 }
 
