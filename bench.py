@@ -52,7 +52,19 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(n_side: int, threads: int):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_side: int, threads: int, single_n: int = 32):
+    """The oracle on the host: all threads on the n_side^3 cube, and one
+    thread on a smaller cube (the paper's single-core comparison axis)."""
     import numpy as np  # noqa: F401
     import oracle
     from paper_1506_08435_amd import workloads as W
@@ -61,11 +73,75 @@ def cpu_baseline(n_side: int, threads: int):
     p = W.cube3d(n_side)
     S = oracle.assemble(p)
     r = oracle.solve(S, tol=1e-8)
-    return {"value": S.n / r.seconds, "unit": "DOF/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": (f"oracle GPCG + face solve, tol 1e-8, on the same workload at {n_side}^3 cells "
-                       f"({S.n} free DOF) instead of 128^3: {r.seconds:.2f} s"),
-            "seconds": r.seconds}
+    nthr = oracle.num_threads()
+    out = {"value": S.n / r.seconds, "unit": "DOF/s", "cores": nthr, "kind": "oracle",
+           "sample": (f"oracle GPCG + face solve, tol 1e-8, on the same workload at {n_side}^3 cells "
+                      f"({S.n} free DOF) instead of 128^3: {r.seconds:.2f} s"),
+           "seconds": r.seconds, "cpu_model": cpu_model(),
+           "affinity_cores": len(os.sched_getaffinity(0))}
+    if single_n > 0:
+        oracle.set_num_threads(1)
+        S1 = oracle.assemble(W.cube3d(single_n))
+        r1 = oracle.solve(S1, tol=1e-8)
+        oracle.set_num_threads(nthr)
+        out["single_thread"] = {"value": S1.n / r1.seconds, "unit": "DOF/s", "cores": 1,
+                                "sample": f"{single_n}^3 cells ({S1.n} free DOF): {r1.seconds:.2f} s"}
+    return out
+
+
+def triad_gbs(torch) -> float:
+    """Achievable HBM bandwidth: a = b + s c on 3 x 512 MiB float64 vectors,
+    median of 10 launches timed with events (bytes: 2 reads + 1 write)."""
+    n = 64 << 20
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.ones(n, dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ts = []
+    for _ in range(12):
+        ev[0].record()
+        torch.add(b, c, alpha=0.5, out=a)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    del a, b, c
+    ts = sorted(ts[2:])
+    return 24.0 * n / (ts[len(ts) // 2] * 1e-3) / 1e9
+
+
+def run_small(args):
+    """The 64x64 2D workload (3,969 free DOF): launch-bound, so latency per
+    solve (median of many) and DOF/s, FP64 and mixed."""
+    import torch
+    from paper_1506_08435_amd import nnqp, workloads as W
+    p = W.config_small()
+    ctx = nnqp.Context(0)
+    K, F, _ = ctx.assemble(p)
+    out = {}
+    for prec_name in ("fp64", "mixed"):
+        prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
+        opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec)
+        c = torch.empty(K.n, dtype=torch.float64, device=ctx.device)
+        for _ in range(3):
+            ctx.solve_nonneg(K, F, opts=opts, c=c)
+        lat = []
+        for _ in range(args.small_reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st = ctx.solve_nonneg(K, F, opts=opts, c=c)
+            lat.append(time.perf_counter() - t0)
+        lat.sort()
+        med = lat[len(lat) // 2]
+        out[prec_name] = {"value": round(K.n / med, 1), "unit": "DOF/s",
+                          "median_latency_ms": round(med * 1e3, 3),
+                          "p99_latency_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))] * 1e3, 3),
+                          "kkt_rel": st["kkt_rel"], "outer_its": st["outer_its"], "cg_its": st["cg_its"]}
+    line = {"metric": "solve latency and DOF/s, small 2D problem (launch-bound)",
+            "workload": f"square2d_64: 64^2 cells x 2 triangles, {K.n} free DOF, {K.nnz} nnz, "
+                        f"D = R(pi/6) diag(1, 1e-3) R^T, f = 1 on [3/8,5/8]^2, KKT tol 1e-8, "
+                        f"{args.small_reps} solves",
+            "n_gpus": 1, **out}
+    print(json.dumps(line), flush=True)
 
 
 def run_transient(args):
@@ -201,32 +277,34 @@ def run_serve(args):
     same stream; p50/p99 latency (arrival to last step) and DOF*steps/s."""
     from paper_1506_08435_amd import nnqp, workloads as W
     from paper_1506_08435_amd.serve import Request, Server
-    arrivals = W.serve_arrivals(args.nreq, args.rate, seed=args.serve_seed)
-    reqs = [Request(k, W.serve_problem(k, seed=args.serve_seed), args.serve_steps, float(arrivals[k]))
-            for k in range(args.nreq)]
-    dofs = [r.problem.n_free for r in reqs]
+    problems = [W.serve_problem(k, seed=args.serve_seed) for k in range(args.nreq)]
+    dofs = [p.n_free for p in problems]
     out = {}
     budget = int(args.hbm_budget_gib * (1 << 30)) if args.hbm_budget_gib > 0 else None
-    for prec_name in ("fp64", "mixed"):
-        prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
-        srv = Server(precision=prec, hbm_budget=budget, tol=1e-8, inner_rtol=args.inner_rtol)
-        rep = srv.run(reqs)
-        sm = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.summary().items()}
-        sm["max_kkt_rel"] = max(s["kkt_rel"] for r in rep.results for s in r.step_stats)
-        out[prec_name] = sm
+    for rate in args.rates:
+        arrivals = W.serve_arrivals(args.nreq, rate, seed=args.serve_seed)
+        reqs = [Request(k, problems[k], args.serve_steps, float(arrivals[k])) for k in range(args.nreq)]
+        for prec_name in ("fp64", "mixed"):
+            prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
+            srv = Server(precision=prec, hbm_budget=budget, tol=1e-8, inner_rtol=args.serve_inner_rtol)
+            rep = srv.run(reqs)
+            sm = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.summary().items()}
+            sm["max_kkt_rel"] = max(s["kkt_rel"] for r in rep.results for s in r.step_stats)
+            out[f"rate{rate:g}_{prec_name}"] = sm
     line = {"metric": "served transient requests: p50/p99 latency and solved DOF*steps/s",
-            "workload": f"serve: {args.nreq} requests, Poisson arrivals at {args.rate}/s, 2D/3D 50/50, "
-                        f"free DOF log-uniform in [1e3, 1e6] (here {min(dofs)}..{max(dofs)}, "
-                        f"total {sum(dofs)}), {args.serve_steps} backward-Euler steps each, dt = 1e-3",
+            "workload": f"serve: {args.nreq} requests per rate, Poisson arrivals at {args.rates} per s, "
+                        f"2D/3D 50/50, free DOF log-uniform in [1e3, 1e6] (here {min(dofs)}..{max(dofs)}, "
+                        f"total {sum(dofs)}), {args.serve_steps} backward-Euler steps each, dt = 1e-3, "
+                        f"seed {args.serve_seed}",
             "n_gpus": 1, **out}
     if not args.no_cpu_baseline:
         import numpy as np
         import oracle
-        sample = [r for r in reqs if r.problem.n_free <= 20000][:args.cpu_members]
+        sample = [p for p in problems if p.n_free <= 60000][:args.cpu_members]
         t0 = time.perf_counter()
         ds = 0
-        for r in sample:
-            S = oracle.assemble(r.problem, with_mass=True)
+        for pr in sample:
+            S = oracle.assemble(pr, with_mass=True)
             c = np.zeros(S.n)
             for _ in range(args.serve_steps):
                 c = oracle.transient_step(S, 1e-3, c, tol=1e-8).c
@@ -235,7 +313,7 @@ def run_serve(args):
         line["cpu_baseline"] = {"value": round(ds / sec, 1), "unit": "DOF*steps/s",
                                 "cores": oracle.num_threads(), "kind": "oracle",
                                 "sample": f"oracle assembly + {args.serve_steps} steps of the first "
-                                          f"{len(sample)} requests with at most 20000 DOF, one after "
+                                          f"{len(sample)} requests with at most 60000 DOF, one after "
                                           f"another: {sec:.2f} s"}
     print(json.dumps(line), flush=True)
 
@@ -257,11 +335,18 @@ def main():
     ap.add_argument("--verbose", action="store_true", help="per-outer-iteration trace on stderr")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 512 MiB device-to-device copies first (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["cube", "transient", "batch", "serve"], default="cube")
+    ap.add_argument("--workload", choices=["cube", "small", "transient", "batch", "serve"],
+                    default="cube")
+    ap.add_argument("--small-reps", type=int, default=50, help="solves timed by the small workload")
+    ap.add_argument("--no-triad", action="store_true",
+                    help="skip the achievable-bandwidth (triad) reference")
     ap.add_argument("--nreq", type=int, default=32, help="requests of the serve workload")
-    ap.add_argument("--rate", type=float, default=50.0, help="arrival rate (requests/s)")
+    ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 500.0, 2000.0],
+                    help="arrival rates (requests/s) of the serve workload")
     ap.add_argument("--serve-steps", type=int, default=10)
-    ap.add_argument("--serve-seed", type=int, default=50)
+    ap.add_argument("--serve-seed", type=int, default=2015)
+    ap.add_argument("--serve-inner-rtol", type=float, default=0.1,
+                    help="inner CG tolerance of the served solves (TRON1)")
     ap.add_argument("--hbm-budget-gib", type=float, default=0.0,
                     help="server HBM budget (0: 3/4 of the free device memory)")
     ap.add_argument("--nbatch", type=int, default=512, help="members of the batch workload")
@@ -284,6 +369,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "small":
+        run_small(args)
         return
 
     import torch
@@ -335,6 +423,10 @@ def main():
                 "kernel": "k_cg_spmv (CG matrix pass with fused direction update)",
                 "launches": dom["count"], "avg_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+    if not args.no_triad:
+        tri = triad_gbs(torch)
+        roofline["achievable_triad_GBps"] = round(tri, 1)
+        roofline["frac_of_achievable"] = round(achieved / tri, 4)
 
     out = {
         "metric": "solved DOF/s at KKT tol 1e-8",
@@ -355,7 +447,8 @@ def main():
                                + " from c0 = 1e-8 to KKT tol 1e-8",
                    "inner_rtol": args.inner_rtol, "solver": "TRON-style active-set Newton-CG"},
         "roofline": roofline,
-        "solve": {"outer_its": stats[-1]["outer_its"], "cg_its": stats[-1]["cg_its"],
+        "solve": {"median_device_ms": round(1e3 * sorted(x["seconds"] for x in stats)[len(stats) // 2], 3),
+                  "outer_its": stats[-1]["outer_its"], "cg_its": stats[-1]["cg_its"],
                   "spmvs": stats[-1]["spmvs"], "kkt_rel": stats[-1]["kkt_rel"],
                   "device_s": round(stats[-1]["seconds"], 4),
                   "algorithmic_GBps_whole_solve": round(stats[-1]["bytes_moved"] / stats[-1]["seconds"] / 1e9, 1),
