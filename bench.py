@@ -338,6 +338,9 @@ def main():
     ap.add_argument("--workload", choices=["cube", "small", "transient", "batch", "serve"],
                     default="cube")
     ap.add_argument("--small-reps", type=int, default=50, help="solves timed by the small workload")
+    ap.add_argument("--no-galerkin", action="store_true",
+                    help="skip the unconstrained Galerkin baseline solve (cube workload)")
+    ap.add_argument("--galerkin-reps", type=int, default=3)
     ap.add_argument("--no-triad", action="store_true",
                     help="skip the achievable-bandwidth (triad) reference")
     ap.add_argument("--nreq", type=int, default=32, help="requests of the serve workload")
@@ -427,6 +430,9 @@ def main():
         tri = triad_gbs(torch)
         roofline["achievable_triad_GBps"] = round(tri, 1)
         roofline["frac_of_achievable"] = round(achieved / tri, 4)
+    galerkin = None
+    if not args.no_galerkin and prec == nnqp.NN_FP64:
+        galerkin = run_galerkin(ctx, K, F, n, stats, args)
 
     out = {
         "metric": "solved DOF/s at KKT tol 1e-8",
@@ -456,9 +462,32 @@ def main():
                                          "avg_us": round(v["ms"] / max(v["count"], 1) * 1e3, 2)}
                                      for k, v in kt.items() if v["count"]}},
     }
+    if galerkin is not None:
+        out["galerkin"] = galerkin
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
     print(json.dumps(out), flush=True)
+
+
+def run_galerkin(ctx, K, F, n, stats, args):
+    """The unconstrained Galerkin baseline on the same system (Jacobi-PCG to
+    ||K c - f|| <= 1e-8 ||f||): its time, the DMP statistics of its solution
+    (Table Tab:S5_cube_dmp) and the time ratio of the non-negative solve to
+    it (Tables Tab:S5_cube_times_mustang/wolf compare the same two)."""
+    from paper_1506_08435_amd import nnqp
+    opts = nnqp.default_opts(tol=1e-8, max_cg=200000)
+    ctx.solve_galerkin(K, F, opts=opts)               # warm-up
+    runs = [ctx.solve_galerkin(K, F, opts=opts)[1] for _ in range(args.galerkin_reps)]
+    g_med = sorted(r["seconds"] for r in runs)[len(runs) // 2]
+    nn_med = sorted(x["seconds"] for x in stats)[len(stats) // 2]
+    r = runs[-1]
+    return {"median_device_ms": round(g_med * 1e3, 3), "cg_its": r["cg_its"],
+            "residual_rel": r["kkt_rel"], "min_c": r["min_c"], "max_c": r["max_c"],
+            "negative_nodes": r["n_negative"],
+            "pct_negative": round(100.0 * r["n_negative"] / max(n, 1), 2),
+            "algorithmic_GBps": round(r["bytes_moved"] / r["seconds"] / 1e9, 1),
+            "nonneg_over_galerkin_time": round(nn_med / g_med, 3),
+            "nonneg_min_c": stats[-1]["min_c"]}
 
 
 if __name__ == "__main__":

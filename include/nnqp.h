@@ -103,10 +103,14 @@ typedef struct {
     int32_t n_active;     /* #{i : c_i == 0} */
     int32_t cauchy_trials;
     int32_t search_trials;
-    int32_t refinements;  /* outer FP64 refinement steps (NN_MIXED) */
+    int32_t refinements;  /* outer FP64 refinement steps (NN_MIXED); residual
+                             replacement restarts (nn_solve_galerkin) */
     int32_t status;       /* nn_status of this solve (per member in nn_solve_batch) */
     double bytes_moved;   /* algorithmic HBM bytes of the solve (perfect-cache model) */
     double seconds;       /* device time of the solve (HIP events on the stream) */
+    double max_c;         /* max_i c_i (nn_solve_galerkin only, else 0) */
+    int32_t n_negative;   /* #{i : c_i < 0} (nn_solve_galerkin only, else 0) */
+    int32_t reserved;
 } nn_stats;
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t;
@@ -188,6 +192,29 @@ nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_
 nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
                           const nn_opts *opts, double *c_dev, uint8_t *active_dev,
                           nn_stats *stats);
+
+/*
+ * Unconstrained single-field Galerkin solution (Sec. 2.1.2,
+ * eq. Single_field_formulation): K c = f, the baseline that violates the
+ * discrete maximum principle (Sec. 5.1, Table Tab:S5_cube_dmp).  Jacobi-
+ * preconditioned CG from c = 0 until the true residual satisfies
+ * ||K c - f||_2 <= tol ||f||_2: CG runs to that bound on its recursive
+ * residual, and if the true residual misses it CG restarts from c on
+ * f - K c (residual replacement; a few restarts at most, each must halve the
+ * residual).  opts->max_cg caps the CG iterations of all passes together;
+ * opts->max_outer, inner_rtol, c0_mode, c0_value and delta0 are not used.
+ * Float64 only (opts->precision must be NN_FP64, else NN_EINVAL).
+ *   f_dev   device [n] float64 (free DOFs, as from nn_assemble)
+ *   c_dev   device [n] float64, out: the Galerkin solution (any sign)
+ *   stats   host or NULL: kkt_rel = true ||K c - f||_2 / ||f||_2, min_c, max_c,
+ *           n_negative = #{c_i < 0}, cg_its, refinements = restarts, spmvs,
+ *           bytes_moved, seconds
+ * Returns NN_EMAXIT (c and stats filled) if the cap is reached or the
+ * residual stalls above tol, NN_ENOTSPD if CG meets non-positive curvature,
+ * NN_ENONFINITE on a non-finite value.
+ */
+nn_status nn_solve_galerkin(nn_ctx *ctx, nn_matrix *K, const double *f_dev, const nn_opts *opts,
+                            double *c_dev, nn_stats *stats);
 
 /*
  * One backward-Euler step of the transient problem (Sec. 2.2.2,

@@ -463,6 +463,18 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
 }
 
 
+nn_status nn_solve_galerkin(nn_ctx *ctx, nn_matrix *K, const double *f_dev, const nn_opts *opts,
+                            double *c_dev, nn_stats *stats)
+{
+    NN_CHECK_CTX(ctx);
+    if (!K || (K->n > 0 && (!f_dev || !c_dev))) return fail(ctx, NN_EINVAL, "null argument");
+    nn_status st = check_opts(ctx, opts);
+    if (st != NN_OK) return st;
+    if (opts->precision != NN_FP64)
+        return fail(ctx, NN_EINVAL, "the Galerkin solve runs in float64 only");
+    return galerkin_impl(ctx, K, f_dev, opts, c_dev, stats);
+}
+
 nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *f_dev,
                             const nn_opts *opts, double *c_dev, uint8_t *active_dev,
                             nn_stats *stats)

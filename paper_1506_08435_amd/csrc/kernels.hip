@@ -310,6 +310,40 @@ __global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__
     block_partial<kOpsGrad, 5>(a, slot_ptr(partials, SLOT_HOST));
 }
 
+// Residual report of an unconstrained solve: r = K c - f (not stored);
+// |r|^2, #non-finite, max c, min c, #(c < 0)
+constexpr uint32_t kOpsResid = OPS5(OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM);
+
+template <int WMAX, class Cols>
+__global__ __launch_bounds__(kBlock) void k_resid(Part P, const int *__restrict__ so, Cols sc,
+                                                  const double *__restrict__ v,
+                                                  const double *__restrict__ c,
+                                                  const double *__restrict__ f, double *partials)
+{
+    double a[5];
+    red_init<kOpsResid, 5>(a);
+    sell_rows<WMAX>(P, so, sc, v, AllRows(), [&](int i) { return Two{c[i], f[i]}; },
+                    [&](int j) { return c[j]; }, [&](int, double s, Two cf) {
+                        const double ri = s - cf.b;
+                        a[0] += ri * ri;
+                        a[1] += (isfinite(ri) && isfinite(cf.a)) ? 0.0 : 1.0;
+                        a[2] = fmax(a[2], cf.a);
+                        a[3] = fmin(a[3], cf.a);
+                        a[4] += cf.a < 0.0 ? 1.0 : 0.0;
+                    });
+    block_partial<kOpsResid, 5>(a, slot_ptr(partials, SLOT_HOST));
+}
+
+// c += w (no projection: the unconstrained solve)
+template <class VV>
+__global__ __launch_bounds__(kBlock) void k_add(Part P, double *__restrict__ c,
+                                                const VV *__restrict__ w)
+{
+    for_rows(P, [&](int i, bool act) {
+        if (act) c[i] += (double)w[i];
+    });
+}
+
 // Trial point of a projected search: s = P(c + t d) - c, formed for every
 // gathered column; ks = K s; report g.s, s.Ks, s.s.  Rows with mask == 0 are
 // skipped when a mask is given (there d = 0, so s = 0 and they add nothing).
@@ -390,7 +424,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
     Part P, const int *__restrict__ rp, const double *__restrict__ diag,
     const double *__restrict__ c, double *__restrict__ g, const double *__restrict__ ks,
     uint8_t *__restrict__ mask, VV *__restrict__ dm, VV *__restrict__ r, VV *__restrict__ z,
-    VV *__restrict__ p, VV *__restrict__ q, VV *__restrict__ w, double *partials, DevScalars *S)
+    VV *__restrict__ p, VV *__restrict__ q, VV *__restrict__ w, double *partials, DevScalars *S,
+    int all_free)
 {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for_rows(P, [&](int i, bool act) {
@@ -398,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
         const double gi = ks ? g[i] + ks[i] : g[i];
         if (ks) g[i] = gi;
         const double cv = c[i];
-        const bool fr = !(cv == 0.0 && gi >= 0.0);
+        const bool fr = all_free || !(cv == 0.0 && gi >= 0.0);
         const VV dmi = fr ? (VV)(1.0 / diag[i]) : VV(0);
         const VV ri = fr ? (VV)(-gi) : VV(0);
         const VV zi = dmi * ri;
@@ -736,19 +771,35 @@ void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t)
     else k_apply<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d.f64, t);
 }
 
+void launch_resid(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
+                  const double *f)
+{
+    Part P = make_part(A->n);
+    NN_DISPATCH_W(A->wmax, (k_resid<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col}, vals, c,
+                  f, ctx->partials);
+}
+
+void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w)
+{
+    Part P = make_part(n);
+    k_add<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w);
+}
+
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32)
+                     double *g, const double *ks, bool f32, bool all_free)
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
     if (f32)
         k_cg_setup<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
                                                             W.dm32, W.r32, W.z32, W.p32, W.q32,
-                                                            W.w32, ctx->partials, ctx->scal);
+                                                            W.w32, ctx->partials, ctx->scal,
+                                                            all_free ? 1 : 0);
     else
         k_cg_setup<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
                                                              W.dm, W.r, W.z, W.p0, W.q, W.w,
-                                                             ctx->partials, ctx->scal);
+                                                             ctx->partials, ctx->scal,
+                                                             all_free ? 1 : 0);
 }
 
 void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol)

@@ -179,7 +179,12 @@ void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t);
 // CG set-up on the face of (c, g + ks); partials of r.z, r.r, #free, nnz(free) in SLOT_U0;
 // f32 selects the float32 CG vectors
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32);
+                     double *g, const double *ks, bool f32, bool all_free = false);
+// [host] r = A c - f (not stored): |r|^2 sum, #nonfinite sum, max c max, min c min, #(c<0) sum
+void launch_resid(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
+                  const double *f);
+// c += w (float64 CG solution vector)
+void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w);
 // CG iteration j: direction update + matrix pass (prologue: scalars from the
 // previous kernel's partials); float32 values and vectors when V.v32 is set
 void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol);
@@ -216,6 +221,10 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                      uint8_t *active, nn_stats *st);
 
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);
+
+// Unconstrained Galerkin solve K c = f by Jacobi-PCG from c = 0 (solver.hip).
+nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const nn_opts *o,
+                        double *c, nn_stats *st);
 
 // ---------------------------------------------------------------- batched solver (batch.hip)
 // P problems solved together; arrays are host arrays of P entries (see

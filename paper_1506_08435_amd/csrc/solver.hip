@@ -285,4 +285,135 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     return finish(result);
 }
 
+// Unconstrained Galerkin solve (Sec. 2.1.2, eq. Single_field_formulation):
+// K c = f by Jacobi-PCG from c = 0, the baseline the paper runs with CG and a
+// block Jacobi preconditioner (Sec. 5.1).  The same CG kernels as the inner
+// solve run with every row free; the CG stops at ||r|| <= tol ||f|| on its
+// recursive residual, and the report gives the true residual ||K c - f||,
+// min c, max c and the number of negative entries (the DMP statistics of
+// Table Tab:S5_cube_dmp).
+nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const nn_opts *o,
+                        double *c, nn_stats *st)
+{
+    const int64_t n = A->n;
+    nn_stats S;
+    std::memset(&S, 0, sizeof(S));
+    NN_HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    auto finish = [&](nn_status rc) -> nn_status {
+        (void)hipEventRecord(ctx->ev1, ctx->stream);
+        hipError_t e = hipEventSynchronize(ctx->ev1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        S.seconds = ms * 1e-3;
+        prof_collect(ctx);
+        if (e != hipSuccess) rc = fail(ctx, NN_EHIP, hipGetErrorString(e));
+        S.status = (int32_t)rc;
+        if (st) *st = S;
+        return rc;
+    };
+    if (n == 0) return finish(NN_OK);
+    nn_status rc = ensure_workspace(ctx, n);
+    if (rc != NN_OK) return rc;
+    Workspace &W = ctx->ws;
+    DevScalars &H = *ctx->h_scal;
+    const Bytes B{(double)n, (double)A->nnz};
+    static const int kInitOps[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
+    static const int kResidOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
+    double red[kMaxRed];
+
+    prof_begin(ctx, KC_OTHER, 16.0 * n);
+    launch_init(ctx, n, c, f, 0, 0.0);   // c = 0; ||f||, non-finite f
+    prof_end(ctx);
+    if ((rc = host_reduce(ctx, n, 4, kInitOps, red)) != NN_OK) return rc;
+    S.bytes_moved += 16.0 * n;
+    const double normf = std::sqrt(red[0]);
+    S.norm_f = normf;
+    if (red[2] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite value in f"));
+    if (normf == 0.0) return finish(NN_OK);   // c = 0 solves K c = 0
+
+    // CG on K w = -g with every row free, then c += w and the true residual.
+    // The matrix pass forms K p by the recurrence K p = K z + beta K p_old, so
+    // CG's recursive residual drifts from f - K c by rounding; when the true
+    // residual misses tol the solve restarts from c on f - K c (residual
+    // replacement), at most kMaxRestarts times and while each restart gains.
+    constexpr int kMaxRestarts = 8;
+    Vals VS;
+    VS.v64 = A->val;
+    const int chunk = o->cg_chunk > 0 ? o->cg_chunk : 16;
+    const double b_spmv = n + 4.0 * n + 12.0 * A->nnz + 40.0 * n;
+    const double b_upd = n + 64.0 * n;
+    double rel = 1.0;   // ||f - K c|| / ||f|| at c = 0
+    for (int restart = 0;; restart++) {
+        prof_begin(ctx, KC_GRAD, B.spmv() + 16.0 * n);
+        launch_grad(ctx, A, A->val, c, f, W.g);   // g = K c - f
+        prof_end(ctx);
+        S.spmvs++;
+        S.bytes_moved += B.spmv() + 16.0 * n;
+        prof_begin(ctx, KC_OTHER, 40.0 * n);
+        launch_cg_setup(ctx, A, A->diag, c, W.g, nullptr, false, true);
+        prof_end(ctx);
+        S.bytes_moved += 88.0 * n;
+        const double rtol = std::min(0.5, o->tol / rel);
+        const int budget = o->max_cg - S.cg_its;
+        int it_seen = 0, j_next = 0;
+        for (;;) {
+            const size_t mark = ctx->prof_live.size();
+            for (int k = 0; k < chunk; k++, j_next++) {
+                prof_begin(ctx, KC_CG_SPMV, -1.0);
+                launch_cg_spmv(ctx, A, VS, j_next, budget, rtol);
+                prof_end(ctx);
+                prof_begin(ctx, KC_CG_UPDATE, -1.0);
+                launch_cg_update(ctx, n, j_next, false);
+                prof_end(ctx);
+            }
+            if ((rc = read_scalars(ctx)) != NN_OK) return rc;
+            const int ran = H.it - it_seen;
+            int seen[NN_KCLASSES] = {0};
+            for (size_t e = mark; e < ctx->prof_live.size(); e++) {
+                ProfEntry &P = ctx->prof_live[e];
+                P.valid = seen[P.cls]++ < ran;
+                P.bytes = P.cls == KC_CG_SPMV ? b_spmv : b_upd;
+            }
+            S.bytes_moved += ran * (b_spmv + b_upd);
+            S.spmvs += ran;
+            it_seen = H.it;
+            if (H.done) break;
+        }
+        S.cg_its += it_seen;
+        if (H.done == 4) return finish(fail(ctx, NN_ENONFINITE, "non-finite value in CG"));
+        if (H.done == 3) return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature in CG"));
+
+        prof_begin(ctx, KC_OTHER, 24.0 * n);
+        launch_add(ctx, n, c, W.w);
+        prof_end(ctx);
+        S.bytes_moved += 24.0 * n;
+        prof_begin(ctx, KC_OTHER, B.spmv() + 16.0 * n);
+        launch_resid(ctx, A, A->val, c, f);
+        prof_end(ctx);
+        S.spmvs++;
+        S.bytes_moved += B.spmv() + 16.0 * n;
+        if ((rc = host_reduce(ctx, n, 5, kResidOps, red)) != NN_OK) return rc;
+        if (red[1] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite solution"));
+        const double prev = rel;
+        rel = std::sqrt(red[0]) / normf;
+        S.kkt_rel = rel;
+        S.max_c = red[2];
+        S.min_c = red[3];
+        S.n_negative = (int32_t)red[4];
+        S.refinements = restart;
+        if (o->verbose)
+            std::fprintf(stderr,
+                         "nnqp galerkin pass %d cg %d residual %.3e min c %.6g max c %.6g "
+                         "negative %d\n",
+                         restart, it_seen, rel, S.min_c, S.max_c, S.n_negative);
+        if (rel <= o->tol) break;
+        if (S.cg_its >= o->max_cg)
+            return finish(fail(ctx, NN_EMAXIT, "CG iteration cap reached"));
+        if (restart >= kMaxRestarts || !(rel < 0.5 * prev))
+            return finish(fail(ctx, NN_EMAXIT, "true residual stalled above tol (rounding floor)"));
+    }
+    ctx->err.clear();
+    return finish(NN_OK);
+}
+
 }  // namespace nnqp

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "NN_OK", 1: "NN_EINVAL", 2: "NN_ENONFINITE", 3: "NN_ENOTSPD",
 # exported symbols declared in include/nnqp.h (checked by the ABI test)
 SYMBOLS = ("nn_create", "nn_destroy", "nn_last_error", "nn_default_opts", "nn_assemble",
            "nn_matrix_from_csr", "nn_matrix_info", "nn_matrix_export", "nn_matrix_bytes",
-           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_step_transient",
+           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_solve_galerkin", "nn_step_transient",
            "nn_solve_batch", "nn_step_transient_batch", "nn_set_profiling", "nn_kernel_times")
 
 
@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
                 ("spmvs", ctypes.c_int32), ("n_active", ctypes.c_int32),
                 ("cauchy_trials", ctypes.c_int32), ("search_trials", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("bytes_moved", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("bytes_moved", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("max_c", ctypes.c_double), ("n_negative", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "nn_matrix_free": (None, [vp, vp]),
         "nn_matvec": (i32, [vp, vp, ctypes.c_int, vp, vp]),
         "nn_solve_nonneg": (i32, [vp, vp, vp, P(Opts), vp, vp, P(Stats)]),
+        "nn_solve_galerkin": (i32, [vp, vp, vp, P(Opts), vp, P(Stats)]),
         "nn_step_transient": (i32, [vp, vp, dbl, vp, P(Opts), vp, vp, P(Stats)]),
         "nn_solve_batch": (i32, [vp, i32, P(vp), P(vp), P(Opts), P(vp), P(vp), P(Stats)]),
         "nn_step_transient_batch": (i32, [vp, i32, P(vp), dbl, P(vp), P(Opts), P(vp), P(vp),
@@ -270,6 +273,23 @@ class Context:
         d = st_out.as_dict()
         d["status"] = st
         return c[:A.n], active[:A.n], d
+
+    def solve_galerkin(self, A: Matrix, f, opts: Optional[Opts] = None, c=None,
+                       allow_maxit: bool = False, **kw):
+        """Unconstrained Galerkin solve K c = f (nn_solve_galerkin).  Returns
+        (c, stats dict); stats carry min_c, max_c, n_negative and the true
+        relative residual in kkt_rel."""
+        t = self.torch
+        o = opts if opts is not None else default_opts(**kw)
+        if c is None:
+            c = t.empty(max(A.n, 1), dtype=t.float64, device=self.device)
+        st_out = Stats()
+        st = self.lib.nn_solve_galerkin(self.handle, A.handle, _ptr(f), ctypes.byref(o), _ptr(c),
+                                        ctypes.byref(st_out))
+        self._check(st, "nn_solve_galerkin", allow=(NN_OK, NN_EMAXIT) if allow_maxit else (NN_OK,))
+        d = st_out.as_dict()
+        d["status"] = st
+        return c[:A.n], d
 
     def step_transient(self, A: Matrix, dt: float, f, c, opts: Optional[Opts] = None,
                        active=None, allow_maxit: bool = False, **kw):

@@ -48,12 +48,32 @@ def test_null_arguments_rejected_without_device_work():
     assert lib.nn_solve_nonneg(None, None, None, None, None, None, None) == nnqp.NN_EINVAL
 
 
-def test_struct_layouts_match_header():
-    """Field offsets of the ctypes mirrors follow the C declarations."""
+def test_struct_layouts_match_header(tmp_path):
+    """Size and every field offset of the ctypes mirrors equal what the C
+    compiler lays out for the declarations in include/nnqp.h."""
+    import shutil
+    import subprocess
     from paper_1506_08435_amd import nnqp
-    assert ctypes.sizeof(nnqp.Opts) == 2 * 8 + 4 * 4 + 2 * 8 + 2 * 4
-    assert ctypes.sizeof(nnqp.Stats) == 4 * 8 + 8 * 4 + 2 * 8
-    assert nnqp.Mesh.coords.offset == 24
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"nn_opts": nnqp.Opts, "nn_stats": nnqp.Stats, "nn_mesh": nnqp.Mesh}
+    lines = ['#include <stdio.h>', '#include "nnqp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

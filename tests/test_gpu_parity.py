@@ -545,3 +545,83 @@ def test_mixed_precision_wide_pattern_matches_oracle(ctx):
     assert oracle.kkt(S, c).r <= 1.01e-10
     c64, _, _ = ctx.solve_nonneg(K, F, tol=1e-10)
     assert np.abs(_np(c64) - ref.c).max() / np.abs(ref.c).max() <= PARITY_TOL
+
+
+# ---------------------------------------------------------------- Galerkin baseline
+GAL_CASES = ["square2d_64", "square2d_45_theta1", "cube3d_16", "cube3d_21_ragged",
+             "transient_field_20x18x9"]
+
+
+@pytest.mark.parametrize("name", GAL_CASES)
+def test_galerkin_matches_oracle(ctx, name):
+    """Unconstrained K c = f (Sec. 2.1.2) on the GPU vs the oracle's PCG: the
+    solutions agree, the reported DMP statistics are those of the returned c,
+    and the sign of every node the oracle decides clearly agrees."""
+    p = SOLVE_CASES[name]()
+    K, F, _ = ctx.assemble(p)
+    c, st = ctx.solve_galerkin(K, F, tol=1e-12, max_cg=200000)
+    c = _np(c)
+    S = oracle.assemble(p)
+    ref = oracle.galerkin(S, rtol=1e-13)
+    scale = np.abs(ref).max()
+    err = np.abs(c - ref).max() / scale
+    assert err <= PARITY_TOL, err
+    assert st["min_c"] == c.min() and st["max_c"] == c.max()
+    assert st["n_negative"] == int((c < 0).sum())
+    clear = np.abs(ref) > 1e-8 * scale
+    assert np.array_equal(c[clear] < 0, ref[clear] < 0)
+    res = np.linalg.norm(oracle.spmv(S, c) - S.F) / np.linalg.norm(S.F)
+    # the two residual evaluations differ by their own rounding only
+    assert res <= 1.05e-12 and abs(st["kkt_rel"] - res) <= 5e-14
+    print(f"{name}: n={S.n} err={err:.2e} res={res:.2e} cg={st['cg_its']} "
+          f"restarts={st['refinements']} "
+          f"negative={st['n_negative']} min={st['min_c']:.4g}")
+
+
+def test_galerkin_edge_cases(ctx):
+    from paper_1506_08435_amd import nnqp
+    p = W.square2d(20)
+    p.f_elem = np.zeros_like(p.f_elem)
+    K, F, _ = ctx.assemble(p)
+    c, st = ctx.solve_galerkin(K, F)
+    assert np.array_equal(_np(c), np.zeros(K.n)) and st["cg_its"] == 0
+    # a load of either sign: the Galerkin solution is linear in f
+    p = W.square2d(24, theta=0.7, ratio=1e-2)
+    K, F, _ = ctx.assemble(p)
+    c1 = _np(ctx.solve_galerkin(K, F, tol=1e-12)[0]).copy()
+    c2 = _np(ctx.solve_galerkin(K, -F, tol=1e-12)[0]).copy()
+    assert np.abs(c1 + c2).max() <= 1e-10 * np.abs(c1).max()
+    # empty system, float64 only, non-finite load, iteration cap
+    E, FE, _ = ctx.assemble(W.square2d(1))
+    assert ctx.solve_galerkin(E, FE)[1]["status"] == 0
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_galerkin(K, F, precision=nnqp.NN_MIXED)
+    assert ei.value.status == nnqp.NN_EINVAL
+    bad = F.clone()
+    bad[5] = float("inf")
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_galerkin(K, bad)
+    assert ei.value.status == nnqp.NN_ENONFINITE
+    c, st = ctx.solve_galerkin(K, F, tol=1e-13, max_cg=3, allow_maxit=True)
+    assert st["status"] == nnqp.NN_EMAXIT and st["cg_its"] == 3
+    assert np.isfinite(_np(c)).all()
+
+
+def test_full_size_cube128_galerkin(ctx):
+    """The 128^3 benchmark system: the Galerkin solution reaches the residual
+    tolerance (re-evaluated by the oracle's own assembly and SpMV), violates
+    non-negativity while the QP solution does not, and its DMP statistics are
+    those of the returned vector."""
+    p = W.config_cube128()
+    K, F, _ = ctx.assemble(p)
+    c, st = ctx.solve_galerkin(K, F, tol=1e-8, max_cg=200000)
+    c = _np(c)
+    S = oracle.assemble(p)
+    res = np.linalg.norm(oracle.spmv(S, c) - S.F) / np.linalg.norm(S.F)
+    assert res <= 1.01e-8, res
+    assert st["min_c"] == c.min() < 0.0 and st["n_negative"] == int((c < 0).sum()) > 0
+    cn, _, stn = ctx.solve_nonneg(K, F, tol=1e-8)
+    assert _np(cn).min() >= 0.0
+    print(f"cube128 Galerkin: cg {st['cg_its']} {st['seconds']:.3f} s, negative "
+          f"{st['n_negative']}/{S.n} ({100 * st['n_negative'] / S.n:.1f}%), min {st['min_c']:.4g}, "
+          f"max {st['max_c']:.4g}; non-negative solve {stn['seconds']:.3f} s")

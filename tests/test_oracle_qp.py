@@ -198,3 +198,32 @@ def test_kkt_report_special_points(oracle_mod):
     nanc = c_bf.copy()
     nanc[0] = np.nan
     assert oracle_mod.kkt(S, nanc).nonfinite >= 1
+
+
+@pytest.mark.parametrize("maker", [
+    W.config_small,
+    lambda: W.square2d(37, theta=1.1, ratio=3e-3),
+    lambda: W.cube3d(10),
+])
+def test_galerkin_oracle_equals_direct_solve(oracle_mod, maker):
+    """The oracle's unconstrained solve (Sec. 2.1.2, eq. Single_field_formulation,
+    by Jacobi-PCG) against a sparse direct factorisation of the same K; the
+    Galerkin solution takes negative values on these anisotropic problems
+    (the DMP violation of Table Tab:S5_cube_dmp)."""
+    S = oracle_mod.assemble(maker())
+    ref = spl.spsolve(S.to_scipy().tocsc(), S.F)
+    c = oracle_mod.galerkin(S, rtol=1e-13)
+    assert np.abs(c - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert np.linalg.norm(S.to_scipy() @ c - S.F) <= 1.01e-13 * np.linalg.norm(S.F)
+    assert c.min() < 0.0 and (c < 0).sum() == (ref < 0).sum()
+
+
+def test_galerkin_oracle_m_matrix_is_nonnegative(oracle_mod):
+    """Isotropic Kuhn mesh: K is a Stieltjes matrix, K^-1 >= 0, so the Galerkin
+    solution of a non-negative load is non-negative and equals the QP's."""
+    p = _isotropic(W.cube3d(9))
+    S = oracle_mod.assemble(p)
+    c = oracle_mod.galerkin(S, rtol=1e-13)
+    assert c.min() > 0.0
+    r = oracle_mod.solve(S, tol=1e-13)
+    np.testing.assert_allclose(c, r.c, rtol=0, atol=1e-11 * r.c.max())
