@@ -4,10 +4,13 @@ TEST INFRASTRUCTURE ONLY: imported by `tests/`, by `__graft_entry__.smoke()`
 and by the CPU-baseline leg of `bench.py`, never by the product package.  It
 shares no code with the HIP library.
 
-* `assemble`      P1 stiffness / mass / load, Dirichlet nodes eliminated
+* `assemble`      P1 stiffness / mass / load, Dirichlet nodes eliminated,
+                  non-zero Dirichlet values lifted into the load
                   (Sec. 2.1.2-2.1.3; capacity matrix Sec. 2.2.2)  [oracle.c]
-* `solve`         unique minimiser of 1/2 c.Kc - c.F s.t. c >= 0
-                  (Sec. 2.1.3, eq. non-negative)                  [oracle.c]
+* `solve`         unique minimiser of 1/2 c.Kc - c.F s.t. lo <= c <= hi
+                  (Sec. 2.1.3, eq. non-negative: [0, inf); Sec. 2.2.2 and
+                  the DMP Remark of Sec. 5: [c_min, c_max])        [oracle.c]
+* `galerkin`      unconstrained K c = F by Jacobi-PCG (Sec. 2.1.2) [oracle.c]
 * `kkt`           KKT certificate of a candidate c               [oracle.c]
 * `transient_step` one backward-Euler QP (Sec. 2.2.2)             [oracle.c]
 * `brute.brute_force` exhaustive active-set enumeration, N <= 12   [brute.py]
@@ -51,21 +54,24 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.or_assemble.restype = ctypes.c_void_p
     lib.or_assemble.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _f64p, _i32p, _f64p,
-                                ctypes.c_int64, _f64p, _f64p, _u8p, ctypes.c_int,
+                                ctypes.c_int64, _f64p, _f64p, _u8p, _f64p, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_int)]
     lib.or_free.argtypes = [ctypes.c_void_p]
     lib.or_problem_sizes.argtypes = [ctypes.c_void_p, _i64p, _i64p]
     lib.or_problem_export.argtypes = [ctypes.c_void_p, _i64p, _i32p, _f64p, _f64p, _f64p, _i64p]
     lib.or_spmv.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p]
-    lib.or_kkt.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p, _f64p]
+    lib.or_kkt.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, ctypes.c_double,
+                           ctypes.c_double, _f64p, _f64p]
     lib.or_solve.restype = ctypes.c_int
     lib.or_solve.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, ctypes.c_double,
-                             ctypes.c_int64, _f64p, ctypes.POINTER(OrStats)]
+                             ctypes.c_double, ctypes.c_double, ctypes.c_int64, _f64p,
+                             ctypes.POINTER(OrStats)]
     lib.or_galerkin.restype = ctypes.c_int64
     lib.or_galerkin.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, ctypes.c_double, _f64p]
     lib.or_transient_step.restype = ctypes.c_int
     lib.or_transient_step.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, ctypes.c_double,
-                                      _f64p, _f64p, ctypes.c_double, ctypes.c_int64, _f64p,
+                                      _f64p, _f64p, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int64, _f64p,
                                       ctypes.POINTER(OrStats)]
     lib.or_transient_system.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p,
                                         ctypes.c_double, _f64p, _f64p, _f64p, _f64p]
@@ -102,7 +108,8 @@ class System:
 
 def assemble(problem, with_mass: bool = False) -> System:
     """Assemble from a problem object exposing dim, coords, elems, D, kscale,
-    f_elem and dirichlet arrays."""
+    f_elem and dirichlet arrays (and optionally dirichlet_values: the value of
+    c at each Dirichlet node, lifted into F)."""
     lib = _load()
     dim = int(problem.dim)
     coords = np.ascontiguousarray(problem.coords, dtype=np.float64)
@@ -112,11 +119,14 @@ def assemble(problem, with_mass: bool = False) -> System:
     ks = None if problem.kscale is None else np.ascontiguousarray(problem.kscale, dtype=np.float64)
     f = np.ascontiguousarray(problem.f_elem, dtype=np.float64)
     dmask = np.ascontiguousarray(problem.dirichlet, dtype=np.uint8)
+    dv = getattr(problem, "dirichlet_values", None)
+    dv = None if dv is None else np.ascontiguousarray(dv, dtype=np.float64)
     st = ctypes.c_int(0)
     h = lib.or_assemble(dim, coords.shape[0], elems.shape[0], _p(coords, ctypes.c_double),
                         _p(elems, ctypes.c_int32), _p(D, ctypes.c_double), nD,
                         None if ks is None else _p(ks, ctypes.c_double), _p(f, ctypes.c_double),
-                        _p(dmask, ctypes.c_uint8), int(with_mass), ctypes.byref(st))
+                        _p(dmask, ctypes.c_uint8), None if dv is None else _p(dv, ctypes.c_double),
+                        int(with_mass), ctypes.byref(st))
     if not h:
         raise RuntimeError(f"oracle assembly failed (status {st.value})")
     try:
@@ -153,27 +163,31 @@ def spmv(sysm: System, x: np.ndarray, vals: Optional[np.ndarray] = None) -> np.n
 @dataclasses.dataclass
 class KKT:
     r: float          # ||pg||_2 / ||F||_2
-    nat_inf: float    # ||min(c, g)||_inf
+    nat_inf: float    # ||c - P(c - g)||_inf (= ||min(c, g)||_inf for [0, inf))
     min_c: float
-    comp_inf: float   # max |c_i g_i|
+    comp_inf: float   # max min(c_i - lo, hi - c_i) |g_i|
     normF: float
     nonfinite: int
-    min_g_active: float
-    n_zero: int
+    min_g_active: float   # min g over {c == lo}
+    n_zero: int           # #{c == lo}
+    max_c: float = 0.0
+    max_g_upper: float = -np.inf   # max g over {c == hi}
+    n_upper: int = 0               # #{c == hi}
 
 
 def kkt(sysm: System, c: np.ndarray, F: Optional[np.ndarray] = None,
-        vals: Optional[np.ndarray] = None) -> KKT:
+        vals: Optional[np.ndarray] = None, lo: float = 0.0, hi: float = np.inf) -> KKT:
     lib = _load()
     v = sysm.K if vals is None else np.ascontiguousarray(vals, dtype=np.float64)
     F = sysm.F if F is None else np.ascontiguousarray(F, dtype=np.float64)
     c = np.ascontiguousarray(c, dtype=np.float64)
-    out = np.zeros(8)
+    out = np.zeros(11)
     lib.or_kkt(sysm.n, _p(sysm.rowptr, ctypes.c_int64), _p(sysm.col, ctypes.c_int32),
-               _p(v, ctypes.c_double), _p(F, ctypes.c_double), _p(c, ctypes.c_double),
-               _p(out, ctypes.c_double))
+               _p(v, ctypes.c_double), _p(F, ctypes.c_double), float(lo), float(hi),
+               _p(c, ctypes.c_double), _p(out, ctypes.c_double))
     return KKT(r=out[0], nat_inf=out[1], min_c=out[2], comp_inf=out[3], normF=out[4],
-               nonfinite=int(out[5]), min_g_active=out[6], n_zero=int(out[7]))
+               nonfinite=int(out[5]), min_g_active=out[6], n_zero=int(out[7]), max_c=out[8],
+               max_g_upper=out[9], n_upper=int(out[10]))
 
 
 @dataclasses.dataclass
@@ -193,9 +207,9 @@ class SolveResult:
 
 def solve(sysm: System, tol: float = 1e-12, c0: Optional[np.ndarray] = None,
           F: Optional[np.ndarray] = None, vals: Optional[np.ndarray] = None,
-          max_outer: int = 20000) -> SolveResult:
-    """Minimise 1/2 c.Kc - c.F over c >= 0 to ||pg||/||F|| <= tol, finishing
-    with a face solve and a KKT check."""
+          max_outer: int = 20000, lo: float = 0.0, hi: float = np.inf) -> SolveResult:
+    """Minimise 1/2 c.Kc - c.F over lo <= c <= hi to ||pg||/||F|| <= tol,
+    finishing with a face solve and a KKT check."""
     lib = _load()
     v = sysm.K if vals is None else np.ascontiguousarray(vals, dtype=np.float64)
     F = sysm.F if F is None else np.ascontiguousarray(F, dtype=np.float64)
@@ -203,8 +217,8 @@ def solve(sysm: System, tol: float = 1e-12, c0: Optional[np.ndarray] = None,
     st = OrStats()
     t0 = time.perf_counter()
     rc = lib.or_solve(sysm.n, _p(sysm.rowptr, ctypes.c_int64), _p(sysm.col, ctypes.c_int32),
-                      _p(v, ctypes.c_double), _p(F, ctypes.c_double), tol, max_outer,
-                      _p(c, ctypes.c_double), ctypes.byref(st))
+                      _p(v, ctypes.c_double), _p(F, ctypes.c_double), float(lo), float(hi), tol,
+                      max_outer, _p(c, ctypes.c_double), ctypes.byref(st))
     dt = time.perf_counter() - t0
     return SolveResult(c=c[:sysm.n], status=rc, r=st.r, outer=st.outer, gp_steps=st.gp_steps,
                        cg_its=st.cg_its, face_its=st.face_its, polishes=st.polishes,
@@ -235,7 +249,7 @@ def transient_system(sysm: System, dt: float, cn: np.ndarray):
 
 
 def transient_step(sysm: System, dt: float, cn: np.ndarray, tol: float = 1e-12,
-                   max_outer: int = 20000) -> SolveResult:
+                   max_outer: int = 20000, lo: float = 0.0, hi: float = np.inf) -> SolveResult:
     lib = _load()
     cn = np.ascontiguousarray(cn, dtype=np.float64)
     c = np.zeros(max(sysm.n, 1))
@@ -244,8 +258,8 @@ def transient_step(sysm: System, dt: float, cn: np.ndarray, tol: float = 1e-12,
     rc = lib.or_transient_step(sysm.n, _p(sysm.rowptr, ctypes.c_int64),
                                _p(sysm.col, ctypes.c_int32), _p(sysm.K, ctypes.c_double),
                                _p(sysm.M, ctypes.c_double), dt, _p(sysm.F, ctypes.c_double),
-                               _p(cn, ctypes.c_double), tol, max_outer, _p(c, ctypes.c_double),
-                               ctypes.byref(st))
+                               _p(cn, ctypes.c_double), float(lo), float(hi), tol, max_outer,
+                               _p(c, ctypes.c_double), ctypes.byref(st))
     dt_s = time.perf_counter() - t0
     return SolveResult(c=c[:sysm.n], status=rc, r=st.r, outer=st.outer, gp_steps=st.gp_steps,
                        cg_its=st.cg_its, face_its=st.face_its, polishes=st.polishes,
@@ -260,11 +274,14 @@ def set_num_threads(t: int) -> None:
     _load().or_set_num_threads(int(t))
 
 
-def nondegenerate_masks(c_ref: np.ndarray, g_ref: np.ndarray, F: np.ndarray, rel: float = 1e-8):
-    """Nodes whose status the oracle fixes unambiguously: free if
-    c > rel*||c||_inf, strictly active if c == 0 and g > rel*||F||_inf."""
+def nondegenerate_masks(c_ref: np.ndarray, g_ref: np.ndarray, F: np.ndarray, rel: float = 1e-8,
+                        lo: float = 0.0, hi: float = np.inf):
+    """Nodes whose status the oracle fixes unambiguously: free if c is more
+    than rel*||c||_inf inside both bounds, strictly active if c is at a bound
+    with a gradient of the binding sign larger than rel*||F||_inf (returned
+    together: at lo, or at hi)."""
     cmax = float(np.max(np.abs(c_ref))) if c_ref.size else 0.0
     fmax = float(np.max(np.abs(F))) if F.size else 0.0
-    free = c_ref > rel * cmax
-    strict = (c_ref == 0.0) & (g_ref > rel * fmax)
+    free = (c_ref > lo + rel * cmax) & (c_ref < hi - rel * cmax)
+    strict = ((c_ref == lo) & (g_ref > rel * fmax)) | ((c_ref == hi) & (g_ref < -rel * fmax))
     return free, strict

@@ -10,12 +10,16 @@
  *     simplicial mesh (Sec. 2.1.2, bilinear form B and functional L of
  *     eq. functionals_B_L; Sec. 2.1.3 discrete system eq. Helmholtz_discrete;
  *     Sec. 2.2.2 capacity matrix), homogeneous Dirichlet nodes eliminated.
- *   - The unique minimiser of 1/2 c.Kc - c.F subject to c >= 0
- *     (Sec. 2.1.3, eq. non-negative), i.e. the vector with
- *     c >= 0, g = Kc - F >= 0, c_i g_i = 0.
+ *   - Dirichlet nodes with given values c_D are eliminated by lifting:
+ *     F_F -= K_FD c_D (the Dirichlet part of the space U, Sec. 2.1.2).
+ *   - The unique minimiser of 1/2 c.Kc - c.F subject to lo <= c <= hi
+ *     (Sec. 2.1.3, eq. non-negative with lo = 0, hi = +inf; Sec. 2.2.2,
+ *     eq. Eq:non-negative with c_min <= c <= c_max; the DMP variant of the
+ *     Remark in Sec. 5 takes [0, 1]), i.e. the feasible c whose gradient
+ *     g = Kc - F satisfies g_i >= 0 where c_i = lo, g_i <= 0 where c_i = hi and
+ *     g_i = 0 in between.
  *   - One backward-Euler step of the transient QP (Sec. 2.2.2,
- *     eq. Eq:non-negative with K~ = M/dt + K, f~ = f + M c^(n)/dt), lower
- *     bound 0 only.
+ *     eq. Eq:non-negative with K~ = M/dt + K, f~ = f + M c^(n)/dt).
  *
  * How the minimiser is found: any correct method may be used because the
  * result is unique; this file uses gradient-projection conjugate gradients
@@ -172,12 +176,15 @@ void or_free(or_problem *P)
  *   kscale  [ne] or NULL: D_e = kscale[e] * D
  *   f_elem  [ne]: element-constant source; the load uses the one-point rule
  *           F^e_a = |e| f_e / (d+1), exact for element-constant f.
- *   dirichlet [nn]: 1 = node carries c = 0 and is eliminated.
+ *   dirichlet [nn]: 1 = Dirichlet node, eliminated.
+ *   dvals   [nn] or NULL: the value of c at each Dirichlet node (NULL: 0);
+ *           F_r -= K_rj c_j for every Dirichlet neighbour j of a free row r.
  */
 or_problem *or_assemble(int dim, int64_t nn, int64_t ne, const double *coords,
                         const int32_t *elems, const double *D, int64_t nD,
                         const double *kscale, const double *f_elem,
-                        const uint8_t *dirichlet, int with_mass, int *status)
+                        const uint8_t *dirichlet, const double *dvals, int with_mass,
+                        int *status)
 {
     *status = OR_EINVAL;
     if ((dim != 2 && dim != 3) || nn < 0 || ne < 0 || (nD != 1 && nD != ne)) return NULL;
@@ -263,7 +270,10 @@ or_problem *or_assemble(int dim, int64_t nn, int64_t ne, const double *coords,
             P->F[r] += vol * f_elem[e] / (double)nv;
             for (int b = 0; b < nv; b++) {
                 int64_t c = P->dof[elems[e * nv + b]];
-                if (c < 0) continue;
+                if (c < 0) {
+                    if (dvals) P->F[r] -= Ke[a][b] * dvals[elems[e * nv + b]];
+                    continue;
+                }
                 int64_t s = find_slot(P, r, (int32_t)c);
                 P->K[s] += Ke[a][b];
                 if (with_mass) P->M[s] += p1_mass(dim, vol, a, b);
@@ -303,6 +313,7 @@ typedef struct {
     const int32_t *ci;
     const double *v;
     const double *F;
+    double lo, hi;   /* bounds lo <= c <= hi (hi may be +inf) */
 } qp_t;
 
 void or_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
@@ -339,15 +350,26 @@ static double dot(int64_t n, const double *a, const double *b)
     return s;
 }
 
-/* Projection onto c >= 0 with a canonical +0.0 (NaN maps to +0.0; callers
- * count non-finite values separately). */
-static inline double proj(double x) { return x > 0.0 ? x : 0.0; }
-
-/* Projected gradient: g_i where c_i > 0, min(g_i, 0) where c_i = 0. */
-static inline double pgrad(double c, double g) { return c > 0.0 ? g : (g < 0.0 ? g : 0.0); }
-
-static double pg_norm(int64_t n, const double *c, const double *g)
+/* Projection onto [lo, hi] (NaN maps to lo; callers count non-finite values
+ * separately; with lo = 0 the result is a canonical +0.0). */
+static inline double proj(const qp_t *Q, double x)
 {
+    double y = x > Q->lo ? x : Q->lo;
+    return y < Q->hi ? y : Q->hi;
+}
+
+/* Projected gradient: g_i strictly between the bounds, min(g_i, 0) at the
+ * lower bound, max(g_i, 0) at the upper bound. */
+static inline double pgrad(const qp_t *Q, double c, double g)
+{
+    if (c <= Q->lo) return g < 0.0 ? g : 0.0;
+    if (c >= Q->hi) return g > 0.0 ? g : 0.0;
+    return g;
+}
+
+static double pg_norm(const qp_t *Q, const double *c, const double *g)
+{
+    int64_t n = Q->n;
     int64_t nc = (n + OR_CHUNK - 1) / OR_CHUNK;
     double *part = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
 #pragma omp parallel for schedule(static)
@@ -355,7 +377,7 @@ static double pg_norm(int64_t n, const double *c, const double *g)
         double s = 0.0;
         int64_t hi = (t + 1) * OR_CHUNK < n ? (t + 1) * OR_CHUNK : n;
         for (int64_t i = t * OR_CHUNK; i < hi; i++) {
-            double p = pgrad(c[i], g[i]);
+            double p = pgrad(Q, c[i], g[i]);
             s += p * p;
         }
         part[t] = s;
@@ -388,40 +410,54 @@ static void gradient(const qp_t *Q, const double *c, double *g)
     for (int64_t i = 0; i < Q->n; i++) g[i] -= Q->F[i];
 }
 
-/* binding: c_i = 0 and g_i >= 0 (a zero gradient counts as binding) */
-static inline int binding(double c, double g) { return c == 0.0 && g >= 0.0; }
+/* binding: at the lower bound with g_i >= 0, or at the upper bound with
+ * g_i <= 0 (a zero gradient counts as binding) */
+static inline int binding(const qp_t *Q, double c, double g)
+{
+    return (c == Q->lo && g >= 0.0) || (c == Q->hi && g <= 0.0);
+}
 
 /*
- * KKT report for c (used as the certificate):
- *   out[0] = ||pg||_2 / ||F||_2  (||pg||_2 when F = 0)
- *   out[1] = ||min(c, g)||_inf
- *   out[2] = min_i c_i
- *   out[3] = max_i |c_i g_i|
- *   out[4] = ||F||_2
- *   out[5] = number of non-finite entries of c or g
- *   out[6] = min_i g_i over {c_i = 0}  (+inf if none)
- *   out[7] = number of i with c_i == 0
+ * KKT report for c under lo <= c <= hi (used as the certificate):
+ *   out[0]  = ||pg||_2 / ||F||_2  (||pg||_2 when F = 0)
+ *   out[1]  = ||c - P(c - g)||_inf  (natural residual; ||min(c, g)||_inf for [0, inf))
+ *   out[2]  = min_i c_i
+ *   out[3]  = max_i min(c_i - lo, hi - c_i) |g_i|  (complementarity)
+ *   out[4]  = ||F||_2
+ *   out[5]  = number of non-finite entries of c or g
+ *   out[6]  = min_i g_i over {c_i = lo}  (+inf if none)
+ *   out[7]  = number of i with c_i == lo
+ *   out[8]  = max_i c_i
+ *   out[9]  = max_i g_i over {c_i = hi}  (-inf if none)
+ *   out[10] = number of i with c_i == hi
  */
 void or_kkt(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
-            const double *F, const double *c, double *out)
+            const double *F, double lo, double hi, const double *c, double *out)
 {
-    qp_t Q = {n, rp, ci, v, F};
+    qp_t Q = {n, rp, ci, v, F, lo, hi};
     double *g = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     gradient(&Q, c, g);
-    double pg2 = 0, nat = 0, minc = INFINITY, comp = 0, ff = 0, nonfin = 0, ming = INFINITY, nact = 0;
+    double pg2 = 0, nat = 0, minc = INFINITY, maxc = -INFINITY, comp = 0, ff = 0, nonfin = 0;
+    double ming = INFINITY, nlo = 0, maxg = -INFINITY, nhi = 0;
     for (int64_t i = 0; i < n; i++) {
-        double p = pgrad(c[i], g[i]);
+        double p = pgrad(&Q, c[i], g[i]);
         pg2 += p * p;
-        double m = fabs(fmin(c[i], g[i]));
+        double m = fabs(c[i] - proj(&Q, c[i] - g[i]));
         if (m > nat) nat = m;
         if (c[i] < minc) minc = c[i];
-        double cg = fabs(c[i] * g[i]);
+        if (c[i] > maxc) maxc = c[i];
+        double dist = fmin(c[i] - lo, hi - c[i]);
+        double cg = dist * fabs(g[i]);
         if (cg > comp) comp = cg;
         ff += F[i] * F[i];
         if (!isfinite(c[i]) || !isfinite(g[i])) nonfin += 1;
-        if (c[i] == 0.0) {
-            nact += 1;
+        if (c[i] == lo) {
+            nlo += 1;
             if (g[i] < ming) ming = g[i];
+        }
+        if (c[i] == hi) {
+            nhi += 1;
+            if (g[i] > maxg) maxg = g[i];
         }
     }
     double nf = sqrt(ff);
@@ -432,7 +468,10 @@ void or_kkt(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
     out[4] = nf;
     out[5] = nonfin;
     out[6] = ming;
-    out[7] = nact;
+    out[7] = nlo;
+    out[8] = n > 0 ? maxc : 0.0;
+    out[9] = maxg;
+    out[10] = nhi;
     free(g);
 }
 
@@ -491,7 +530,7 @@ static int64_t pcg_face(const qp_t *Q, const uint8_t *mask, const double *b, dou
 int64_t or_galerkin(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                     const double *F, double rtol, double *c)
 {
-    qp_t Q = {n, rp, ci, v, F};
+    qp_t Q = {n, rp, ci, v, F, -INFINITY, INFINITY};
     uint8_t *mask = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
     double *work = (double *)malloc(sizeof(double) * 5 * (size_t)(n > 0 ? n : 1));
     memset(mask, 1, (size_t)n);
@@ -526,7 +565,7 @@ static double projected_search(const qp_t *Q, double *x, double *g, const double
     int64_t n = Q->n;
     double t = t0, dq = 0.0;
     for (int trial = 0; trial < 80; trial++) {
-        for (int64_t i = 0; i < n; i++) { y[i] = proj(x[i] + t * d[i]); s[i] = y[i] - x[i]; }
+        for (int64_t i = 0; i < n; i++) { y[i] = proj(Q, x[i] + t * d[i]); s[i] = y[i] - x[i]; }
         spmv(Q, s, Ks);
         (*spmvs)++;
         double gs = dot(n, g, s), sKs = dot(n, s, Ks);
@@ -540,10 +579,11 @@ static double projected_search(const qp_t *Q, double *x, double *g, const double
 }
 
 int or_solve(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *F,
-             double tol, int64_t max_outer, double *c, or_stats *st)
+             double lo, double hi, double tol, int64_t max_outer, double *c, or_stats *st)
 {
     const double mu = 0.01, eta1 = 0.1, eta2 = 0.1;
-    qp_t Q = {n, rp, ci, v, F};
+    qp_t Q = {n, rp, ci, v, F, lo, hi};
+    if (!(lo < hi) || !isfinite(lo)) return OR_EINVAL;
     memset(st, 0, sizeof(*st));
     if (n == 0) { st->certified = 1; return OR_OK; }
     size_t sz = sizeof(double) * (size_t)n;
@@ -561,39 +601,43 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, c
             if (ci[k] == i && v[k] > 0.0) dinv[i] = 1.0 / v[k];
     }
     int rc = OR_ENOCONV;
-    if (!(fmax > 0.0)) {
-        /* F <= 0: c = 0 gives g = -F >= 0, so c = 0 is the minimiser. */
+    if (lo == 0.0 && !(fmax > 0.0)) {
+        /* F <= 0 with lower bound 0: c = 0 gives g = -F >= 0, so c = 0 is the
+         * minimiser. */
         memset(c, 0, sz);
         st->certified = 1;
         rc = OR_OK;
         goto done;
     }
-    for (int64_t i = 0; i < n; i++) c[i] = proj(c[i]);
+    for (int64_t i = 0; i < n; i++) c[i] = proj(&Q, c[i]);
     gradient(&Q, c, g);
     double inner_tol = tol;
     for (int64_t outer = 0; outer < max_outer; outer++) {
         st->outer = outer + 1;
-        double rel = pg_norm(n, c, g) / nf;
+        double rel = pg_norm(&Q, c, g) / nf;
         st->r = rel;
         if (rel <= inner_tol) {
             /* Face solve on the binding set of c, then check the KKT conditions. */
             st->polishes++;
+            /* binding variables stay at their bound value */
             for (int64_t i = 0; i < n; i++) {
-                mask[i] = binding(c[i], g[i]) ? 0 : 1;
-                y[i] = mask[i] ? c[i] : 0.0;
+                mask[i] = binding(&Q, c[i], g[i]) ? 0 : 1;
+                y[i] = c[i];
             }
             st->face_its += pcg_face(&Q, mask, F, y, 1e-15 * nf, 20 * n + 2000, work);
-            double ymax = 0.0, ymin = 0.0;
+            /* how far the face solution left the box, relative to its size */
+            double yabs = 0.0, outside = 0.0;
             for (int64_t i = 0; i < n; i++) {
-                if (y[i] > ymax) ymax = y[i];
-                if (y[i] < ymin) ymin = y[i];
+                if (fabs(y[i]) > yabs) yabs = fabs(y[i]);
+                if (lo - y[i] > outside) outside = lo - y[i];
+                if (y[i] - hi > outside) outside = y[i] - hi;
             }
-            for (int64_t i = 0; i < n; i++) y[i] = proj(y[i]);
+            for (int64_t i = 0; i < n; i++) y[i] = proj(&Q, y[i]);
             gradient(&Q, y, d);
-            double rel_y = pg_norm(n, y, d) / nf;
+            double rel_y = pg_norm(&Q, y, d) / nf;
             double floor_y = residual_floor(&Q, y, nf);
             st->floor = floor_y;
-            if (ymin >= -1e-10 * ymax && rel_y <= (tol > floor_y ? tol : floor_y)) {
+            if (outside <= 1e-10 * yabs && rel_y <= (tol > floor_y ? tol : floor_y)) {
                 memcpy(c, y, sz);
                 memcpy(g, d, sz);
                 st->r = rel_y;
@@ -615,7 +659,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, c
         double dmax = 0.0;
         for (int j = 0; j < 50; j++) {
             for (int64_t i = 0; i < n; i++) {
-                b_old[i] = (uint8_t)binding(c[i], g[i]);
+                b_old[i] = (uint8_t)binding(&Q, c[i], g[i]);
                 d[i] = b_old[i] ? 0.0 : -g[i];
             }
             double dd = dot(n, d, d);
@@ -629,14 +673,14 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, c
             if (dec > dmax) dmax = dec;
             int same = 1;
             for (int64_t i = 0; i < n && same; i++)
-                if ((uint8_t)binding(c[i], g[i]) != b_old[i]) same = 0;
+                if ((uint8_t)binding(&Q, c[i], g[i]) != b_old[i]) same = 0;
             if (same || dec <= eta1 * dmax) break;
         }
 
-        /* Conjugate-gradient phase on the face of c (c_i = 0 held fixed). */
+        /* Conjugate-gradient phase on the face of c (variables at a bound held fixed). */
         for (int face = 0; face < 50; face++) {
             for (int64_t i = 0; i < n; i++) {
-                mask[i] = c[i] > 0.0;
+                mask[i] = c[i] > lo && c[i] < hi;
                 r[i] = mask[i] ? -g[i] : 0.0;
                 z[i] = mask[i] ? dinv[i] * r[i] : 0.0;
                 p[i] = z[i];
@@ -664,11 +708,11 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, c
                 for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
             }
             projected_search(&Q, c, g, w, 1.0, mu, y, s, Ks, &spmvs);
-            if (pg_norm(n, c, g) / nf <= inner_tol) break;
-            /* stay on the face while every active variable is binding */
+            if (pg_norm(&Q, c, g) / nf <= inner_tol) break;
+            /* stay on the face while every variable at a bound is binding */
             int same = 1;
             for (int64_t i = 0; i < n && same; i++)
-                if (c[i] == 0.0 && !binding(c[i], g[i])) same = 0;
+                if ((c[i] == lo || c[i] == hi) && !binding(&Q, c[i], g[i])) same = 0;
             if (!same) break;
         }
     }
@@ -682,7 +726,8 @@ done:
  * solve the bound-constrained QP warm-started from c^n. c_out may alias nothing. */
 int or_transient_step(int64_t n, const int64_t *rp, const int32_t *ci, const double *Kv,
                       const double *Mv, double dt, const double *F, const double *cn,
-                      double tol, int64_t max_outer, double *c_out, or_stats *st)
+                      double lo, double hi, double tol, int64_t max_outer, double *c_out,
+                      or_stats *st)
 {
     int64_t nnz = rp[n];
     double *Kt = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
@@ -691,7 +736,7 @@ int or_transient_step(int64_t n, const int64_t *rp, const int32_t *ci, const dou
     or_spmv(n, rp, ci, Mv, cn, ft);
     for (int64_t i = 0; i < n; i++) ft[i] = F[i] + ft[i] / dt;
     memcpy(c_out, cn, sizeof(double) * (size_t)n);
-    int rc = or_solve(n, rp, ci, Kt, ft, tol, max_outer, c_out, st);
+    int rc = or_solve(n, rp, ci, Kt, ft, lo, hi, tol, max_outer, c_out, st);
     free(Kt);
     free(ft);
     return rc;

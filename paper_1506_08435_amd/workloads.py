@@ -41,8 +41,12 @@ class Problem:
     D          float64 [nD, dim, dim]     nD == 1 (one tensor) or n_elems
     kscale     float64 [n_elems] or None  per-element scalar multiplying D
     f_elem     float64 [n_elems]          source value on each element
-    dirichlet  uint8   [n_nodes]          1 = homogeneous Dirichlet node
+    dirichlet  uint8   [n_nodes]          1 = Dirichlet node
     cells      cell counts per axis of the structured grid
+    dirichlet_values float64 [n_nodes] or None: c at the Dirichlet nodes
+               (None: homogeneous, c = 0)
+    bounds     (lo, hi) of the constrained problem: (0, inf) is the
+               non-negative QP, (0, 1) the DMP variant
     """
     name: str
     dim: int
@@ -55,6 +59,8 @@ class Problem:
     cells: Tuple[int, ...]
     h: float
     exact: Optional[Callable[[np.ndarray], np.ndarray]] = None
+    dirichlet_values: Optional[np.ndarray] = None
+    bounds: Tuple[float, float] = (0.0, math.inf)
 
     @property
     def n_nodes(self) -> int:
@@ -178,6 +184,17 @@ def aniso3d_tensor(eigs=(1.0, 1e-2, 1e-4)) -> np.ndarray:
     return principal_tensor(aniso3d_rotation(), eigs)
 
 
+def dispersion_tensor(v: Sequence[float], alpha_L: float, alpha_T: float,
+                      D_M: float = 0.0) -> np.ndarray:
+    """Velocity-dependent dispersion (Sec. 5, eq. S5_dispersion_tensor):
+    (alpha_T |v| + D_M) I + (alpha_L - alpha_T) v v^T / |v|; principal values
+    alpha_L |v| + D_M along v and alpha_T |v| + D_M across it."""
+    v = np.asarray(v, dtype=np.float64)
+    speed = float(np.linalg.norm(v))
+    D = (alpha_T * speed + D_M) * np.eye(v.size) + (alpha_L - alpha_T) * np.outer(v, v) / speed
+    return 0.5 * (D + D.T)
+
+
 # ---------------------------------------------------------------- problems
 def box_problem(name: str, cells: Sequence[int], h: float, D: np.ndarray,
                 f_elem: Optional[np.ndarray] = None, kscale=None) -> Problem:
@@ -202,6 +219,41 @@ def square2d(n: int = 64, theta: float = math.pi / 6, ratio: float = 1e-3) -> Pr
 def cube3d(n: int = 128, eigs=(1.0, 1e-2, 1e-4)) -> Problem:
     """Unit cube, n^3 cells x 6 Kuhn tets, f = 1 on the central cube of side 1/4."""
     return box_problem(f"cube3d_n{n}", (n, n, n), 1.0 / n, aniso3d_tensor(eigs))
+
+
+def cube_hole(k: int = 14, alpha_L: float = 1.0, alpha_T: float = 1e-3, D_M: float = 0.0,
+              v=(1.0, 1.0, 1.0), inner: float = 1.0, bounds=(0.0, 1.0)) -> Problem:
+    """Structured stand-in for the unit cube with the cubic hole
+    [4/9, 5/9]^3 (Sec. 5.1): n = 9k cells per side, the k^3 cells of the hole
+    removed, c = 0 on the outer boundary, c = `inner` on the hole's boundary,
+    f = 0, D the dispersion tensor of velocity v = (1, 1, 1) with alpha_L = 1,
+    alpha_T = 1e-3, D_M = 0, bounds [0, 1] (the DMP variant of the non-negative
+    method).  Nodes strictly inside the hole belong to no element; they are
+    flagged Dirichlet (value `inner`) so that node ids stay lexicographic.
+    The grid is mirrored in x (x -> 1 - x; the domain is symmetric), so every
+    cell's Kuhn diagonal runs along (-1, 1, 1), across the flow: with the
+    diagonal along v = (1, 1, 1) the P1 stiffness of this tensor is an
+    M-matrix and the Galerkin solution keeps the maximum principle, which the
+    paper's unstructured meshes do not."""
+    n = 9 * int(k)
+    cells = (n, n, n)
+    coords, elems = structured_simplex_mesh(cells, 1.0 / n)
+    coords[:, 0] = 1.0 - coords[:, 0]
+    lo, hi = 4 * k, 5 * k
+    in_hole = cell_box_indicator(cells, (lo, lo, lo), (hi, hi, hi)) > 0.0
+    elems = np.ascontiguousarray(elems[~in_hole])
+    npts = n + 1
+    kk, jj, ii = np.meshgrid(np.arange(npts), np.arange(npts), np.arange(npts), indexing="ij")
+    ii, jj, kk = ii.ravel(), jj.ravel(), kk.ravel()
+    outer = box_dirichlet(cells).astype(bool)
+    hole = ((ii >= lo) & (ii <= hi) & (jj >= lo) & (jj <= hi) & (kk >= lo) & (kk <= hi))
+    dirichlet = (outer | hole).astype(np.uint8)
+    dvals = np.where(hole, float(inner), 0.0)
+    D = dispersion_tensor(v, alpha_L, alpha_T, D_M).reshape(1, 3, 3)
+    return Problem(name=f"cube_hole_k{k}", dim=3, coords=coords, elems=elems,
+                   D=np.ascontiguousarray(D), kscale=None,
+                   f_elem=np.zeros(elems.shape[0]), dirichlet=dirichlet, cells=cells, h=1.0 / n,
+                   dirichlet_values=np.ascontiguousarray(dvals), bounds=tuple(bounds))
 
 
 def config_small() -> Problem:

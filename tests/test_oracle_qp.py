@@ -227,3 +227,126 @@ def test_galerkin_oracle_m_matrix_is_nonnegative(oracle_mod):
     assert c.min() > 0.0
     r = oracle_mod.solve(S, tol=1e-13)
     np.testing.assert_allclose(c, r.c, rtol=0, atol=1e-11 * r.c.max())
+
+
+# ---------------------------------------------------------------- two-sided bounds, lifting
+def test_box_random_dense_qps_match_brute_force(oracle_mod):
+    """lo <= c <= hi (Sec. 2.2.2, eq. Eq:non-negative): random SPD QPs with
+    random bounds against exhaustive enumeration of lower/free/upper."""
+    rng = np.random.default_rng(2015)
+    uppers = 0
+    for trial in range(40):
+        n = int(rng.integers(1, 8))
+        A = rng.standard_normal((n, n))
+        K = A @ A.T + 0.3 * np.eye(n)
+        F = 2.0 * rng.standard_normal(n)
+        lo = float(rng.uniform(-0.5, 0.2))
+        hi = lo + float(rng.uniform(0.1, 1.0))
+        c_bf, sets = brute.brute_force(K, F, lo=lo, hi=hi)
+        S = _system_from_dense(oracle_mod, K, F)
+        r = oracle_mod.solve(S, tol=1e-13, lo=lo, hi=hi)
+        assert r.status == 0 and r.certified
+        scale = max(np.abs(c_bf).max(), 1e-300)
+        np.testing.assert_allclose(r.c, c_bf, rtol=0, atol=1e-11 * scale, err_msg=f"trial {trial}")
+        assert r.c.min() >= lo and r.c.max() <= hi
+        uppers += int((r.c == hi).sum())
+    assert uppers > 0          # the upper bound was exercised
+
+
+@pytest.mark.parametrize("maker", [W.tiny2d, W.tiny3d])
+def test_tiny_meshes_capped_match_brute_force(oracle_mod, maker):
+    S = oracle_mod.assemble(maker())
+    K = S.to_scipy().toarray()
+    hi = 0.6 * oracle_mod.solve(S, tol=1e-13).c.max()
+    c_bf, sets = brute.brute_force(K, S.F, hi=hi)
+    r = oracle_mod.solve(S, tol=1e-13, hi=hi)
+    assert r.certified and (r.c == hi).any() and (r.c == 0).any()
+    np.testing.assert_allclose(r.c, c_bf, rtol=0, atol=1e-13 * hi)
+
+
+def test_box_reflection_swaps_the_bounds(oracle_mod):
+    """c* solves (F, [0, 1]) iff 1 - c* solves (K 1 - F, [0, 1]): the map
+    c -> 1 - c exchanges the two bounds and the sign of the gradient, so a
+    mistake on either side of the box breaks the identity."""
+    p = W.square2d(24, theta=1.0, ratio=1e-3)
+    p.f_elem = 30.0 * p.f_elem
+    S = oracle_mod.assemble(p)
+    r = oracle_mod.solve(S, tol=1e-13, hi=1.0)
+    assert (r.c == 1.0).sum() > 0 and (r.c == 0.0).sum() > 0
+    F2 = oracle_mod.spmv(S, np.ones(S.n)) - S.F
+    r2 = oracle_mod.solve(S, tol=1e-13, F=F2, hi=1.0)
+    np.testing.assert_allclose(r2.c, 1.0 - r.c, rtol=0, atol=1e-11)
+    k = oracle_mod.kkt(S, r.c, lo=0.0, hi=1.0)
+    assert k.r <= 1e-12 and k.n_upper == (r.c == 1.0).sum() and k.max_g_upper <= 0.0
+    assert k.min_g_active >= -1e-12 * np.abs(S.F).max()
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.square2d(9, theta=0.4, ratio=1e-2),
+    lambda: W.cube3d(6),
+])
+def test_lifting_reproduces_linear_boundary_data(oracle_mod, maker):
+    """P1 reproduces linear functions: with f = 0 and Dirichlet values a.x + b
+    on the whole boundary, the lifted system K c = F - K_FD c_D has the linear
+    function itself as its solution at the free nodes, for any constant D."""
+    p = maker()
+    p.f_elem = np.zeros_like(p.f_elem)
+    a = np.array([0.7, -1.3, 0.4][:p.dim])
+    lin = p.coords @ a + 0.25
+    p.dirichlet_values = np.where(p.dirichlet == 1, lin, 0.0)
+    S = oracle_mod.assemble(p)
+    c = spl.spsolve(S.to_scipy().tocsc(), S.F)
+    free_nodes = np.flatnonzero(S.dof >= 0)
+    np.testing.assert_allclose(c, lin[free_nodes], rtol=0, atol=1e-12)
+    assert np.abs(oracle_mod.galerkin(S, rtol=1e-14) - lin[free_nodes]).max() <= 1e-11
+
+
+def test_cube_hole_workload_and_dmp(oracle_mod):
+    """The structured cube-with-hole stand-in (Sec. 5.1): geometry, the
+    dispersion tensor (eq. S5_dispersion_tensor), Galerkin DMP violation and
+    a certified [0, 1] solution."""
+    k = 2
+    p = W.cube_hole(k)
+    n = 9 * k
+    assert p.n_elems == 6 * (n ** 3 - k ** 3)
+    used = np.zeros(p.n_nodes, dtype=bool)
+    used[p.elems.ravel()] = True
+    assert (p.dirichlet[~used] == 1).all() and (p.dirichlet_values[~used] == 1.0).all()
+    x = p.coords
+    on_hole = np.all((x >= 4.0 / 9 - 1e-12) & (x <= 5.0 / 9 + 1e-12), axis=1)
+    assert np.array_equal(p.dirichlet_values == 1.0, on_hole)
+    D = p.D[0]
+    v = np.ones(3) / math.sqrt(3.0)
+    np.testing.assert_allclose(D @ v, math.sqrt(3.0) * v, rtol=1e-14)
+    u = np.array([1.0, -1.0, 0.0]) / math.sqrt(2.0)
+    np.testing.assert_allclose(D @ u, math.sqrt(3.0) * 1e-3 * u, atol=1e-15)
+    S = oracle_mod.assemble(p)
+    gal = spl.spsolve(S.to_scipy().tocsc(), S.F)
+    assert (gal < 0).mean() > 0.2                    # DMP violated by Galerkin
+    r = oracle_mod.solve(S, tol=1e-12, lo=0.0, hi=1.0)
+    assert r.certified and r.c.min() >= 0.0 and r.c.max() <= 1.0
+    kk = oracle_mod.kkt(S, r.c, lo=0.0, hi=1.0)
+    assert kk.r <= 1e-12 and kk.n_zero > 0
+
+
+def test_isotropic_hole_dmp_box_equals_galerkin(oracle_mod):
+    """Isotropic D on the Kuhn mesh: K is a Stieltjes matrix and the lifted
+    data lie in [0, 1], so the Galerkin solution keeps the maximum principle
+    and the [0, 1]-bounded QP returns it."""
+    p = W.cube_hole(2)
+    p.D = np.eye(3)[None].copy()
+    S = oracle_mod.assemble(p)
+    gal = spl.spsolve(S.to_scipy().tocsc(), S.F)
+    assert gal.min() > 0.0 and gal.max() < 1.0
+    r = oracle_mod.solve(S, tol=1e-13, lo=0.0, hi=1.0)
+    np.testing.assert_allclose(r.c, gal, rtol=0, atol=1e-12)
+
+
+def test_transient_box_large_dt_is_steady(oracle_mod):
+    p = W.square2d(16, theta=0.5, ratio=1e-2)
+    p.f_elem = 20.0 * p.f_elem
+    S = oracle_mod.assemble(p, with_mass=True)
+    steady = oracle_mod.solve(S, tol=1e-13, hi=0.5)
+    assert (steady.c == 0.5).any()
+    r = oracle_mod.transient_step(S, 1e12, np.zeros(S.n), tol=1e-13, hi=0.5)
+    np.testing.assert_allclose(r.c, steady.c, rtol=0, atol=1e-10)
