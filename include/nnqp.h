@@ -81,26 +81,37 @@ typedef struct {
     int32_t max_cg;       /* CG iterations per inner solve; default 5000 */
     int32_t precision;    /* nn_precision; default NN_FP64 */
     int32_t c0_mode;      /* 0: start from c = c0_value everywhere (Algorithm 1 of the
-                             paper starts from 1e-8); 1: start from the caller's c,
-                             projected onto c >= 0 (warm start).  Default 0. */
-    double c0_value;      /* default 1e-8 */
+                             paper starts from 1e-8); 1: start from the caller's c
+                             (warm start).  Either start is projected onto
+                             [lower, upper].  Default 0. */
+    double c0_value;      /* default 1e-8; must be finite */
     double delta0;        /* initial trust-region radius; <= 0 means unbounded
                              (default).  The model is the objective itself, so the
                              radius only ever grows. */
     int32_t cg_chunk;     /* CG iterations enqueued between convergence reads; default 16 */
     int32_t verbose;      /* 1: one line per outer iteration on stderr; default 0 */
+    double lower;         /* bounds lower <= c <= upper of the constrained solves
+                             (Sec. 2.2.2, eq. Eq:non-negative: c_min 1 <= c <= c_max 1).
+                             Default [0, +inf): the non-negative QP (*); [0, 1] is the
+                             DMP variant (Remark in Sec. 5).  lower finite, upper > lower
+                             (may be +inf).  The batched entry points take the default
+                             only; nn_solve_galerkin ignores them. */
+    double upper;
 } nn_opts;
 
 /* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */
 typedef struct {
-    double kkt_rel;       /* ||pg||_2 / ||f||_2 at the returned c (f the solve's rhs) */
-    double kkt_nat_inf;   /* ||min(c, g)||_inf */
-    double min_c;         /* min_i c_i (>= 0 on every path) */
+    double kkt_rel;       /* ||pg||_2 / ||f||_2 at the returned c (f the solve's rhs);
+                             pg_i = g_i strictly inside the bounds, min(g_i, 0) at lower,
+                             max(g_i, 0) at upper */
+    double kkt_nat_inf;   /* ||c - P(c - g)||_inf, P the projection on [lower, upper]
+                             (= ||min(c, g)||_inf for [0, inf)) */
+    double min_c;         /* min_i c_i (>= lower on every constrained path) */
     double norm_f;        /* ||f||_2 */
     int32_t outer_its;
     int32_t cg_its;
     int32_t spmvs;        /* sparse matrix-vector products of every kind */
-    int32_t n_active;     /* #{i : c_i == 0} */
+    int32_t n_active;     /* #{i : c_i == lower or c_i == upper} (#{c_i == 0} by default) */
     int32_t cauchy_trials;
     int32_t search_trials;
     int32_t refinements;  /* outer FP64 refinement steps (NN_MIXED); residual
@@ -132,26 +143,33 @@ nn_status nn_default_opts(nn_opts *opts);
  *                                                     Sec. 2.2.2; F_{0,0} = 1/dt, Sec. 3.2)
  *   F_i  = sum_e |e| f_e / (d+1)                      (functional L with element-constant f)
  *
- * Homogeneous Dirichlet nodes (dirichlet[v] != 0) are eliminated: their rows
- * and columns are dropped (c = 0 there).
+ * Dirichlet nodes (dirichlet[v] != 0) are eliminated: their rows and columns
+ * are dropped.  With dirichlet_values their prescribed values c_D are lifted
+ * into the load, F_i -= sum_j K_ij c_D,j over the Dirichlet neighbours j of
+ * each free node i (the trial space U of Sec. 2.1.2 with c = c^p on the
+ * Dirichlet boundary); without them c = 0 there.
  *   D        host [nD * dim * dim]; nD = 1 (one tensor) or n_elems (one per element);
  *            each tensor symmetric positive definite (Sec. 2.1, eq. symmetry and
  *            positive definiteness of D).
  *   kscale   host [n_elems] or NULL: element e uses kscale[e] * D_e.
  *   f_elem   host [n_elems]: source value on each element.
  *   dirichlet host [n_nodes]: 1 = Dirichlet node.
+ *   dirichlet_values host [n_nodes] or NULL: c at the Dirichlet nodes (entries
+ *            at free nodes are ignored); NULL = homogeneous.
  *   K_out    receives a library-owned matrix (free with nn_matrix_free).
  *   F_dev    device [n] or NULL: receives F.  n = number of free nodes, known
  *            beforehand by the caller (count of dirichlet == 0).
  *   dof_of_node host [n_nodes] or NULL: receives the DOF index of each node, -1
  *            for Dirichlet nodes.
  * Errors: NN_EINVAL (sizes, ids out of range, degenerate element, nnz >= 2^31),
- *         NN_ENONFINITE (NaN/Inf in coords, D, kscale or f), NN_ENOTSPD (a
+ *         NN_ENONFINITE (NaN/Inf in coords, D, kscale, f or a Dirichlet
+ *         value), NN_ENOTSPD (a
  *         non-positive diagonal entry of K), NN_EOOM, NN_EHIP.
  */
 nn_status nn_assemble(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64_t nD,
                       const double *kscale, const double *f_elem, const uint8_t *dirichlet,
-                      int with_mass, nn_matrix **K_out, double *F_dev, int64_t *dof_of_node);
+                      const double *dirichlet_values, int with_mass, nn_matrix **K_out,
+                      double *F_dev, int64_t *dof_of_node);
 
 /* Wrap a caller CSR matrix (host arrays, copied to the device): rowptr [n+1]
  * (int64, rowptr[0] = 0), col [nnz] (int32, ascending within each row,
@@ -174,13 +192,18 @@ nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_
                     double *y_dev);
 
 /*
- * Solve (*) for c (Sec. 2.1.3, eq. non-negative).  The minimiser is unique
- * because K is positive definite; it is the c with c >= 0, g = K c - f >= 0
- * and c_i g_i = 0.
+ * Solve (*) for c (Sec. 2.1.3, eq. non-negative), or with the two-sided
+ * bounds opts->lower <= c <= opts->upper (Sec. 2.2.2, eq. Eq:non-negative;
+ * [0, 1] is the DMP variant of the Remark in Sec. 5).  The minimiser is
+ * unique because K is positive definite; it is the feasible c whose gradient
+ * g = K c - f is >= 0 where c_i = lower, <= 0 where c_i = upper and 0 in
+ * between (for [0, inf): c >= 0, g >= 0, c_i g_i = 0).
  *   f_dev     device [n]
  *   c_dev     device [n]; in: warm start when opts->c0_mode == 1; out: solution
- *             with c_i >= 0 exactly (projection writes +0.0).
- *   active_dev device [n] uint8 or NULL; out: 1 where c_i == 0.
+ *             with lower <= c_i <= upper exactly (the projection writes the
+ *             bound value itself; +0.0 for a lower bound 0).
+ *   active_dev device [n] uint8 or NULL; out: 1 where c_i == lower, 2 where
+ *             c_i == upper, else 0.
  *   stats     host or NULL.
  * With opts->precision == NN_MIXED the Cauchy and projected searches and the
  * inner CG run on float32 copies of the values with float32 CG vectors, while
@@ -244,7 +267,8 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
  *            NULL), or NULL
  *   stats    host array of nprob reports, or NULL; stats[p].status is the
  *            member's own status, stats[p].seconds the whole call's time
- * Options apply to every member.  Returns NN_OK when every member reached
+ * Options apply to every member; the bounds must be the default [0, inf)
+ * (NN_EINVAL otherwise).  Returns NN_OK when every member reached
  * tol; otherwise the status of the first member that did not (the others are
  * still solved and reported).  Workspace (about 100 bytes per row of the
  * whole batch) is allocated for the call and released before return.

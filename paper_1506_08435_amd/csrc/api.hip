@@ -254,17 +254,20 @@ nn_status nn_default_opts(nn_opts *o)
     o->c0_value = 1e-8;
     o->delta0 = 0.0;
     o->cg_chunk = 16;
+    o->lower = 0.0;
+    o->upper = INFINITY;
     return NN_OK;
 }
 
 nn_status nn_assemble(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64_t nD,
                       const double *kscale, const double *f_elem, const uint8_t *dirichlet,
-                      int with_mass, nn_matrix **K_out, double *F_dev, int64_t *dof_of_node)
+                      const double *dirichlet_values, int with_mass, nn_matrix **K_out,
+                      double *F_dev, int64_t *dof_of_node)
 {
     NN_CHECK_CTX(ctx);
     if (K_out) *K_out = nullptr;
-    return assemble_impl(ctx, mesh, D, nD, kscale, f_elem, dirichlet, with_mass, K_out, F_dev,
-                         dof_of_node);
+    return assemble_impl(ctx, mesh, D, nD, kscale, f_elem, dirichlet, dirichlet_values, with_mass,
+                         K_out, F_dev, dof_of_node);
 }
 
 nn_status nn_matrix_from_csr(nn_ctx *ctx, int64_t n, const int64_t *rowptr, const int32_t *col,
@@ -437,8 +440,10 @@ static nn_status check_opts(nn_ctx *ctx, const nn_opts *o)
     if (o->precision != NN_FP64 && o->precision != NN_MIXED)
         return fail(ctx, NN_EINVAL, "unknown precision");
     if (o->c0_mode != 0 && o->c0_mode != 1) return fail(ctx, NN_EINVAL, "unknown c0_mode");
-    if (o->c0_mode == 0 && !(o->c0_value >= 0.0 && std::isfinite(o->c0_value)))
-        return fail(ctx, NN_EINVAL, "c0_value must be finite and >= 0");
+    if (o->c0_mode == 0 && !std::isfinite(o->c0_value))
+        return fail(ctx, NN_EINVAL, "c0_value must be finite");
+    if (!std::isfinite(o->lower) || std::isnan(o->upper) || !(o->upper > o->lower))
+        return fail(ctx, NN_EINVAL, "bounds must satisfy lower finite, upper > lower");
     return NN_OK;
 }
 
@@ -507,6 +512,8 @@ static nn_status check_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
     if (nprob > 0 && (!K || !f_dev || !c_dev)) return fail(ctx, NN_EINVAL, "null argument");
     nn_status st = check_opts(ctx, opts);
     if (st != NN_OK) return st;
+    if (opts->lower != 0.0 || opts->upper != INFINITY)
+        return fail(ctx, NN_EINVAL, "the batched solver takes the bounds [0, inf) only");
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int p = 0; p < nprob; p++) {
         if (!K[p]) return fail(ctx, NN_EINVAL, "null matrix in batch");

@@ -68,6 +68,7 @@ struct AsmArgs {
     int per_elem_D;
     const double *kscale;   // [ne] or null
     const double *f;        // [ne]
+    const double *dval;     // [nn] Dirichlet values or null (homogeneous)
     const int *dof;         // [nn]
     const int *rowptr;
     const int *col;
@@ -151,7 +152,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs A)
         const double moff = vol / (double)(nv * (nv + 1));
         for (int b = 0; b < nv; b++) {
             const int j = A.dof[vid[b]];
-            if (j < 0) continue;
+            if (j < 0) {
+                // Dirichlet neighbour: its prescribed value moves to the load
+                if (A.dval) Frow -= vol * stiff_entry(dim, Dm, gr[la], gr[b]) * A.dval[vid[b]];
+                continue;
+            }
             int slot = s0;
             while (slot < s1 && A.col[slot] != j) slot++;
             if (slot >= s1) continue;   // cannot happen: the pattern holds every element pair
@@ -239,7 +244,8 @@ nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A)
 
 nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64_t nD,
                         const double *kscale, const double *f_elem, const uint8_t *dirichlet,
-                        int with_mass, nn_matrix **K_out, double *F_dev, int64_t *dof_of_node)
+                        const double *dvals, int with_mass, nn_matrix **K_out, double *F_dev,
+                        int64_t *dof_of_node)
 {
     if (!mesh || !K_out || !D || !f_elem || !dirichlet)
         return fail(ctx, NN_EINVAL, "null argument to nn_assemble");
@@ -267,6 +273,10 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
         if (kscale && !(std::isfinite(kscale[e]) && kscale[e] > 0.0))
             return fail(ctx, NN_ENONFINITE, "kscale must be finite and positive");
     }
+    if (dvals)
+        for (int64_t v = 0; v < nn; v++)
+            if (dirichlet[v] && !std::isfinite(dvals[v]))
+                return fail(ctx, NN_ENONFINITE, "non-finite Dirichlet value");
 
     // ---- free-DOF numbering
     std::vector<int> dof(nn);
@@ -339,7 +349,7 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
         nn_matrix_free(ctx, M);
         return st;
     };
-    DevBuf d_free, d_incp, d_ince, d_elems, d_coords, d_D, d_ks, d_f, d_dof, d_F, d_val, d_mval;
+    DevBuf d_free, d_incp, d_ince, d_elems, d_coords, d_D, d_ks, d_f, d_dv, d_dof, d_F, d_val, d_mval;
     auto up = [&](DevBuf &b, const void *src, size_t bytes) -> hipError_t {
         hipError_t e = hipMalloc(&b.p, bytes > 0 ? bytes : 8);
         if (e != hipSuccess) return e;
@@ -363,6 +373,7 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
     NN_UP(d_D, D, sizeof(double) * nD * dim * dim);
     if (kscale) NN_UP(d_ks, kscale, sizeof(double) * ne);
     NN_UP(d_f, f_elem, sizeof(double) * ne);
+    if (dvals) NN_UP(d_dv, dvals, sizeof(double) * nn);
     NN_UP(d_dof, dof.data(), sizeof(int) * nn);
     {
         hipError_t e = hipMalloc(&M->rowptr, sizeof(int) * (n + 1));
@@ -396,6 +407,7 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
     args.per_elem_D = nD == 1 ? 0 : 1;
     args.kscale = (const double *)d_ks.p;
     args.f = (const double *)d_f.p;
+    args.dval = (const double *)d_dv.p;
     args.dof = (const int *)d_dof.p;
     args.rowptr = M->rowptr;
     args.col = M->col;

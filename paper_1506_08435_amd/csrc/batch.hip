@@ -1270,7 +1270,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     }
     // ---- start point and load statistics
     hipLaunchKernelGGL(kb_init, dim3(grid_for(sh, n_sl)), dim3(sh.block), 0, st, B,
-                       o->c0_mode == 1 ? 1 : 0, o->c0_value);
+                       o->c0_mode == 1 ? 1 : 0, std::max(o->c0_value, 0.0));
     hipLaunchKernelGGL(kb_reduce_init, dim3(std::max(n_pr, 1)), dim3(kFinBlock), 0, st, B);
     NN_HIP_TRY(ctx, hipMemcpyAsync(pres, d_pres, sizeof(double) * P * kBNV, hipMemcpyDeviceToHost,
                                    st));

@@ -257,7 +257,12 @@ struct AllRows {
     __device__ __forceinline__ bool operator()(int) const { return true; }
 };
 
-__device__ __forceinline__ double proj0(double x) { return x > 0.0 ? x : 0.0; }
+// projection on [lo, hi]; NaN maps to lo (for lo = 0 the result is +0.0)
+__device__ __forceinline__ double proj_box(double x, Box B)
+{
+    const double y = x > B.lo ? x : B.lo;
+    return y < B.hi ? y : B.hi;
+}
 
 // ---------------------------------------------------------------- kernels
 template <int WMAX, class Cols>
@@ -283,7 +288,10 @@ __global__ __launch_bounds__(kBlock) void k_transient_rhs(Part P, const int *__r
 }
 
 // g = K c - f with the projected-gradient report:
-// |pg|^2, #non-finite, ||min(c,g)||_inf, min c, #(c == 0)
+// |pg|^2, #non-finite, ||c - P(c - g)||_inf, min c, #(c at a bound)
+// pg_i = g_i strictly inside [lo, hi], min(g_i, 0) at lo, max(g_i, 0) at hi;
+// the natural residual c - P(c - g) = max(c - hi, min(g, c - lo)) (min(c, g)
+// for [0, inf)).
 constexpr uint32_t kOpsGrad = OPS5(OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM);
 
 template <int WMAX, class Cols>
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__
                                                  const double *__restrict__ v,
                                                  const double *__restrict__ c,
                                                  const double *__restrict__ f,
-                                                 double *__restrict__ g, double *partials)
+                                                 double *__restrict__ g, double *partials, Box B)
 {
     double a[5];
     red_init<kOpsGrad, 5>(a);
@@ -300,12 +308,12 @@ __global__ __launch_bounds__(kBlock) void k_grad(Part P, const int *__restrict__
         const double gi = s - cf.b;
         const double cv = cf.a;
         g[i] = gi;
-        const double pg = cv > 0.0 ? gi : (gi < 0.0 ? gi : 0.0);
+        const double pg = cv > B.lo ? (cv < B.hi ? gi : fmax(gi, 0.0)) : fmin(gi, 0.0);
         a[0] += pg * pg;
         a[1] += (isfinite(gi) && isfinite(cv)) ? 0.0 : 1.0;
-        a[2] = fmax(a[2], fabs(fmin(cv, gi)));
+        a[2] = fmax(a[2], fabs(fmax(cv - B.hi, fmin(gi, cv - B.lo))));
         a[3] = fmin(a[3], cv);
-        a[4] += cv == 0.0 ? 1.0 : 0.0;
+        a[4] += (cv == B.lo || cv == B.hi) ? 1.0 : 0.0;
     });
     block_partial<kOpsGrad, 5>(a, slot_ptr(partials, SLOT_HOST));
 }
@@ -356,11 +364,11 @@ __global__ __launch_bounds__(kBlock) void k_trial(Part P, const int *__restrict_
                                                   const VD *__restrict__ d, double t,
                                                   const double *__restrict__ g,
                                                   const uint8_t *__restrict__ mask,
-                                                  double *__restrict__ ks, double *partials)
+                                                  double *__restrict__ ks, double *partials, Box B)
 {
     auto sv = [&](int j) {
         const double cj = c[j];
-        return proj0(cj + t * (double)d[j]) - cj;
+        return proj_box(cj + t * (double)d[j], B) - cj;
     };
     double a[3];
     red_init<kOpsTrial, 3>(a);
@@ -378,10 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_trial(Part P, const int *__restrict_
 // c = P(c + t d)
 template <class VD>
 __global__ __launch_bounds__(kBlock) void k_apply(Part P, double *__restrict__ c,
-                                                  const VD *__restrict__ d, double t)
+                                                  const VD *__restrict__ d, double t, Box B)
 {
     for_rows(P, [&](int i, bool act) {
-        if (act) c[i] = proj0(c[i] + t * (double)d[i]);
+        if (act) c[i] = proj_box(c[i] + t * (double)d[i], B);
     });
 }
 
@@ -391,7 +399,7 @@ constexpr uint32_t kOpsInit = OPS4(OP_SUM, OP_MAX, OP_SUM, OP_SUM);
 
 __global__ __launch_bounds__(kBlock) void k_init(Part P, double *__restrict__ c,
                                                  const double *__restrict__ f, int mode, double c0v,
-                                                 double *partials)
+                                                 double *partials, Box B)
 {
     double a[4];
     red_init<kOpsInit, 4>(a);
@@ -406,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Part P, double *__restrict__ c,
         } else {
             const double cv = c[i];
             a[3] += isfinite(cv) ? 0.0 : 1.0;
-            c[i] = proj0(cv);
+            c[i] = proj_box(cv, B);
         }
     });
     block_partial<kOpsInit, 4>(a, slot_ptr(partials, SLOT_HOST));
@@ -425,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
     const double *__restrict__ c, double *__restrict__ g, const double *__restrict__ ks,
     uint8_t *__restrict__ mask, VV *__restrict__ dm, VV *__restrict__ r, VV *__restrict__ z,
     VV *__restrict__ p, VV *__restrict__ q, VV *__restrict__ w, double *partials, DevScalars *S,
-    int all_free)
+    Box B, int all_free)
 {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for_rows(P, [&](int i, bool act) {
@@ -433,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
         const double gi = ks ? g[i] + ks[i] : g[i];
         if (ks) g[i] = gi;
         const double cv = c[i];
-        const bool fr = all_free || !(cv == 0.0 && gi >= 0.0);
+        const bool fr = all_free || !((cv == B.lo && gi >= 0.0) || (cv == B.hi && gi <= 0.0));
         const VV dmi = fr ? (VV)(1.0 / diag[i]) : VV(0);
         const VV ri = fr ? (VV)(-gi) : VV(0);
         const VV zi = dmi * ri;
@@ -550,22 +558,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__r
     if (blockIdx.x == 0 && threadIdx.x == 0) S->it = j + 1;
 }
 
-// Largest step along w before a free variable reaches its bound:
-// min over w_i < 0 of c_i / (-w_i), g.w, w.w
+// Largest step along w before a free variable reaches a bound:
+// min over w_i < 0 of (c_i - lo) / (-w_i) and over w_i > 0 of (hi - c_i) / w_i
+// (+inf for hi = +inf), g.w, w.w
 constexpr uint32_t kOpsBrk = OPS3(OP_MIN, OP_SUM, OP_SUM);
 
 template <class VV>
 __global__ __launch_bounds__(kBlock) void k_breakpoint(Part P, const double *__restrict__ c,
                                                        const VV *__restrict__ w,
                                                        const double *__restrict__ g,
-                                                       double *partials)
+                                                       double *partials, Box B)
 {
     double a[3];
     red_init<kOpsBrk, 3>(a);
     for_rows(P, [&](int i, bool act) {
         if (!act) return;
         const double wi = (double)w[i];
-        if (wi < 0.0) a[0] = fmin(a[0], c[i] / (-wi));
+        if (wi < 0.0) a[0] = fmin(a[0], (c[i] - B.lo) / (-wi));
+        else if (wi > 0.0) a[0] = fmin(a[0], (B.hi - c[i]) / wi);
         a[1] += g[i] * wi;
         a[2] += wi * wi;
     });
@@ -573,10 +583,10 @@ __global__ __launch_bounds__(kBlock) void k_breakpoint(Part P, const double *__r
 }
 
 __global__ __launch_bounds__(kBlock) void k_active(Part P, const double *__restrict__ c,
-                                                   uint8_t *__restrict__ active)
+                                                   uint8_t *__restrict__ active, Box B)
 {
     for_rows(P, [&](int i, bool act) {
-        if (act) active[i] = c[i] == 0.0 ? 1 : 0;
+        if (act) active[i] = c[i] == B.lo ? 1 : (c[i] == B.hi ? 2 : 0);
     });
 }
 
@@ -719,56 +729,56 @@ void launch_transient_rhs(nn_ctx *ctx, const nn_matrix *A, const double *c, cons
                   c, f, dt, ft);
 }
 
-void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v)
+void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v, Box B)
 {
     Part P = make_part(n);
-    k_init<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, f, mode, c0v, ctx->partials);
+    k_init<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, f, mode, c0v, ctx->partials, B);
 }
 
 void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
-                 const double *f, double *g)
+                 const double *f, double *g, Box B)
 {
     Part P = make_part(A->n);
     NN_DISPATCH_W(A->wmax, (k_grad<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col}, vals, c, f, g,
-                  ctx->partials);
+                  ctx->partials, B);
 }
 
 void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
-                  double t, const double *g, const uint8_t *mask, double *ks)
+                  double t, const double *g, const uint8_t *mask, double *ks, Box B)
 {
     Part P = make_part(A->n);
     if (V.v32 && A->sl_d16) {
         const ColsD16 cols{A->sl_d16};
         if (d.f32)
             NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsD16>), P.nb, P, A->sl_off, cols,
-                          V.v32, c, d.f32, t, g, mask, ks, ctx->partials);
+                          V.v32, c, d.f32, t, g, mask, ks, ctx->partials, B);
         else
             NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsD16>), P.nb, P, A->sl_off, cols,
-                          V.v32, c, d.f64, t, g, mask, ks, ctx->partials);
+                          V.v32, c, d.f64, t, g, mask, ks, ctx->partials, B);
     } else if (V.v32) {
         const ColsI32 cols{A->sl_col};
         if (d.f32)
             NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsI32>), P.nb, P, A->sl_off, cols,
-                          V.v32, c, d.f32, t, g, mask, ks, ctx->partials);
+                          V.v32, c, d.f32, t, g, mask, ks, ctx->partials, B);
         else
             NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsI32>), P.nb, P, A->sl_off, cols,
-                          V.v32, c, d.f64, t, g, mask, ks, ctx->partials);
+                          V.v32, c, d.f64, t, g, mask, ks, ctx->partials, B);
     } else {
         const ColsI32 cols{A->sl_col};
         if (d.f32)
             NN_DISPATCH_W(A->wmax, (k_trial<WM, double, float, ColsI32>), P.nb, P, A->sl_off, cols,
-                          V.v64, c, d.f32, t, g, mask, ks, ctx->partials);
+                          V.v64, c, d.f32, t, g, mask, ks, ctx->partials, B);
         else
             NN_DISPATCH_W(A->wmax, (k_trial<WM, double, double, ColsI32>), P.nb, P, A->sl_off, cols,
-                          V.v64, c, d.f64, t, g, mask, ks, ctx->partials);
+                          V.v64, c, d.f64, t, g, mask, ks, ctx->partials, B);
     }
 }
 
-void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t)
+void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t, Box B)
 {
     Part P = make_part(n);
-    if (d.f32) k_apply<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d.f32, t);
-    else k_apply<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d.f64, t);
+    if (d.f32) k_apply<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d.f32, t, B);
+    else k_apply<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, d.f64, t, B);
 }
 
 void launch_resid(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
@@ -786,19 +796,19 @@ void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w)
 }
 
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32, bool all_free)
+                     double *g, const double *ks, bool f32, Box B, bool all_free)
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
     if (f32)
         k_cg_setup<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
                                                             W.dm32, W.r32, W.z32, W.p32, W.q32,
-                                                            W.w32, ctx->partials, ctx->scal,
+                                                            W.w32, ctx->partials, ctx->scal, B,
                                                             all_free ? 1 : 0);
     else
         k_cg_setup<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
                                                              W.dm, W.r, W.z, W.p0, W.q, W.w,
-                                                             ctx->partials, ctx->scal,
+                                                             ctx->partials, ctx->scal, B,
                                                              all_free ? 1 : 0);
 }
 
@@ -833,13 +843,13 @@ void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32)
                                                               W.z, ctx->partials, ctx->scal, j);
 }
 
-void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g)
+void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g, Box B)
 {
     Part P = make_part(n);
     if (w.f32)
-        k_breakpoint<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f32, g, ctx->partials);
+        k_breakpoint<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f32, g, ctx->partials, B);
     else
-        k_breakpoint<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f64, g, ctx->partials);
+        k_breakpoint<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f64, g, ctx->partials, B);
 }
 
 void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b)
@@ -850,10 +860,10 @@ void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b)
     k_to_f32<<<(int)nb, kBlock, 0, ctx->stream>>>(m, a, b);
 }
 
-void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active)
+void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active, Box B)
 {
     Part P = make_part(n);
-    k_active<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, active);
+    k_active<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, active, B);
 }
 
 void launch_axpby_vals(nn_ctx *ctx, int64_t nnz, const double *m, double dt, const double *k,

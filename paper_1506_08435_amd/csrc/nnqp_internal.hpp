@@ -73,6 +73,14 @@ struct Vals {
     const float *v32 = nullptr;
 };
 
+// Bounds lo <= c <= hi of a constrained solve (hi may be +inf; lo finite).
+// Default: the non-negative QP.  Projection P(x) = min(max(x, lo), hi), with
+// NaN mapped to lo.
+struct Box {
+    double lo = 0.0;
+    double hi = __builtin_inf();
+};
+
 // A search direction in float64 or float32 (exactly one is set).
 struct Dir {
     const double *f64 = nullptr;
@@ -167,19 +175,21 @@ enum { KC_CG_SPMV = 0, KC_CG_UPDATE = 1, KC_GRAD = 2, KC_TRIAL = 3, KC_OTHER = 4
 
 void launch_matvec(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *x, double *y);
 // [host] c = c0v (mode 0) or P(c) (mode 1); |f|^2 sum, max f, #nonfinite f sum, #nonfinite c sum
-void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v);
-// [host] g = A c - f; |pg|^2 sum, #nonfinite sum, ||min(c,g)||_inf max, min c min, #(c==0) sum
+void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v, Box B);
+// [host] g = A c - f; |pg|^2 sum, #nonfinite sum, ||c - P(c - g)||_inf max, min c min,
+// #(c at a bound) sum
 void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
-                 const double *f, double *g);
+                 const double *f, double *g, Box B);
 // [host] s = P(c + t d) - c gathered, ks = A s; g.s, s.As, s.s (sums); rows with mask == 0 skipped
 void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
-                  double t, const double *g, const uint8_t *mask, double *ks);
+                  double t, const double *g, const uint8_t *mask, double *ks, Box B);
 // c = P(c + t d)
-void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t);
-// CG set-up on the face of (c, g + ks); partials of r.z, r.r, #free, nnz(free) in SLOT_U0;
-// f32 selects the float32 CG vectors
+void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t, Box B);
+// CG set-up on the face of (c, g + ks) (every row not binding: not at lo with
+// g >= 0, not at hi with g <= 0; every row when all_free); partials of r.z,
+// r.r, #free, nnz(free) in SLOT_U0; f32 selects the float32 CG vectors
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32, bool all_free = false);
+                     double *g, const double *ks, bool f32, Box B, bool all_free);
 // [host] r = A c - f (not stored): |r|^2 sum, #nonfinite sum, max c max, min c min, #(c<0) sum
 void launch_resid(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
                   const double *f);
@@ -190,12 +200,13 @@ void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w);
 void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol);
 // CG iteration j: vector update
 void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32);
-// [host] min over w<0 of c/(-w) min, g.w sum, w.w sum
-void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g);
+// [host] first bound crossing along w: min over w<0 of (c-lo)/(-w) and over
+// w>0 of (hi-c)/w, min; g.w sum, w.w sum
+void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g, Box B);
 // b = (float)a
 void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b);
-// active = (c == 0)
-void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active);
+// active = 1 where c == lo, 2 where c == hi, else 0
+void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active, Box B);
 // out = m/dt + k
 void launch_axpby_vals(nn_ctx *ctx, int64_t nnz, const double *m, double dt, const double *k,
                        double *out);
@@ -211,7 +222,8 @@ void launch_transient_rhs(nn_ctx *ctx, const nn_matrix *A, const double *c, cons
 // ---------------------------------------------------------------- assembly (assemble.hip)
 nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64_t nD,
                         const double *kscale, const double *f_elem, const uint8_t *dirichlet,
-                        int with_mass, nn_matrix **K_out, double *F_dev, int64_t *dof_of_node);
+                        const double *dvals, int with_mass, nn_matrix **K_out, double *F_dev,
+                        int64_t *dof_of_node);
 
 // ---------------------------------------------------------------- solver (solver.hip)
 // vals: float64 values (gradient, always); vals32: float32 values for the

@@ -1,7 +1,9 @@
 // Active-set projected-Newton / trust-region solver for
-//     min 1/2 c.Kc - c.f  subject to  c >= 0
-// (arXiv:1506.08435 Sec. 2.1.3, eq. non-negative), in the manner of TRON
-// (Lin & More 1999), which the paper uses through TAO (Sec. 3.1, Sec. 5.1).
+//     min 1/2 c.Kc - c.f  subject to  lo <= c <= hi
+// (arXiv:1506.08435 Sec. 2.1.3, eq. non-negative: [0, inf); Sec. 2.2.2,
+// eq. Eq:non-negative and the DMP Remark of Sec. 5: [c_min, c_max]), in the
+// manner of TRON (Lin & More 1999), which the paper uses through TAO
+// (Sec. 3.1, Sec. 5.1).  P below is the projection on [lo, hi].
 //
 // Outer iteration k (all vector work in kernels.hip; the host only sequences
 // launches and reads a few scalars):
@@ -11,12 +13,13 @@
 //      previous iteration's value and is extrapolated (x10) while the test
 //      holds, or interpolated (x0.1) until it holds.  Each trial is one
 //      project-on-gather SpMV that returns g.s and s.Ks.
-//   3. Free face at the Cauchy point: every variable except those with c = 0
-//      and g >= 0 (a zero gradient counts as binding).  Jacobi-PCG on
+//   3. Free face at the Cauchy point: every variable except the binding ones,
+//      c = lo with g >= 0 or c = hi with g <= 0 (a zero gradient counts as
+//      binding).  Jacobi-PCG on
 //      K_FF w = -g_F from w = 0 until ||r|| <= inner_rtol ||g_F|| (TRON's
 //      inner tolerance, Sec. 5.1 TRON1/2/3), all scalars kept on the device.
 //   4. Projected search along w from the Cauchy point: if no free variable
-//      crosses zero for a unit step the step is taken without a matrix pass
+//      crosses a bound for a unit step the step is taken without a matrix pass
 //      (CG from zero guarantees sufficient decrease along its own iterate);
 //      otherwise P(c + t w) is tried for t = 1, 1/2, ... down to the first
 //      breakpoint, where the step is again safe.
@@ -52,9 +55,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     const int64_t n = A->n;
     nn_stats S;
     std::memset(&S, 0, sizeof(S));
+    Box box;
+    box.lo = o->lower;
+    box.hi = o->upper;
     NN_HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     auto finish = [&](nn_status rc) -> nn_status {
-        if (active && n > 0) launch_active(ctx, n, c, active);
+        if (active && n > 0) launch_active(ctx, n, c, active, box);
         (void)hipEventRecord(ctx->ev1, ctx->stream);
         hipError_t e = hipEventSynchronize(ctx->ev1);
         float ms = 0.f;
@@ -99,7 +105,9 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
 
     // ---- start point and load statistics
     prof_begin(ctx, KC_OTHER, 16.0 * n);
-    launch_init(ctx, n, c, f, o->c0_mode == 1 ? 1 : 0, o->c0_value);
+    // the start value is projected on the bounds
+    const double c0v = std::min(std::max(o->c0_value, box.lo), box.hi);
+    launch_init(ctx, n, c, f, o->c0_mode == 1 ? 1 : 0, c0v, box);
     prof_end(ctx);
     if ((rc = host_reduce(ctx, n, 4, kInitOps, red)) != NN_OK) return rc;
     S.bytes_moved += 16.0 * n;
@@ -107,8 +115,8 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     S.norm_f = normf;
     if (red[2] != 0.0 || red[3] != 0.0)
         return finish(fail(ctx, NN_ENONFINITE, "non-finite value in f or the initial c"));
-    if (!(fmax > 0.0)) {
-        // f <= 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0.
+    if (box.lo == 0.0 && !(fmax > 0.0)) {
+        // f <= 0 with lower bound 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0.
         NN_HIP_TRY(ctx, hipMemsetAsync(c, 0, sizeof(double) * n, ctx->stream));
         S.n_active = (int32_t)n;
         S.kkt_rel = 0.0;
@@ -123,7 +131,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     for (int outer = 0;; outer++) {
         // ---- 1. gradient and convergence test
         prof_begin(ctx, KC_GRAD, B.spmv() + 16.0 * n);
-        launch_grad(ctx, A, vals, c, f, W.g);
+        launch_grad(ctx, A, vals, c, f, W.g, box);
         prof_end(ctx);
         S.spmvs++;
         S.bytes_moved += B.spmv() + 16.0 * n;
@@ -149,7 +157,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         int cur = 0;
         auto trial_cauchy = [&](double t, int buf, double &gs, double &sks, double &ss) -> nn_status {
             prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
-            launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ksbuf[buf]);
+            launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ksbuf[buf], box);
             prof_end(ctx);
             S.spmvs++;
             S.cauchy_trials++;
@@ -193,14 +201,14 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         }
         t_cauchy = t;
         prof_begin(ctx, KC_OTHER, 24.0 * n);
-        launch_apply(ctx, n, c, dir_g, -t);
+        launch_apply(ctx, n, c, dir_g, -t, box);
         prof_end(ctx);
         S.bytes_moved += 24.0 * n;
         double step_norm = std::sqrt(ss);
 
         // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], mixed);
+        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], mixed, box, false);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
         int it_seen = 0, j_next = 0;
@@ -239,7 +247,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
 
         // ---- 4. projected search along w
         prof_begin(ctx, KC_OTHER, 24.0 * n);
-        launch_breakpoint(ctx, n, c, dir_w, W.g);
+        launch_breakpoint(ctx, n, c, dir_w, W.g, box);
         prof_end(ctx);
         S.bytes_moved += 24.0 * n;
         if ((rc = host_reduce(ctx, n, 3, kBrkOps, red)) != NN_OK) return rc;
@@ -250,7 +258,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             if (bmin < tmax) {
                 for (int k = 0; k < kMaxTrials; k++) {
                     prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
-                    launch_trial(ctx, A, VS, c, dir_w, ts, W.g, W.mask, nullptr);
+                    launch_trial(ctx, A, VS, c, dir_w, ts, W.g, W.mask, nullptr, box);
                     prof_end(ctx);
                     S.spmvs++;
                     S.search_trials++;
@@ -267,7 +275,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             }
             if (ts > 0.0) {
                 prof_begin(ctx, KC_OTHER, 24.0 * n);
-                launch_apply(ctx, n, c, dir_w, ts);
+                launch_apply(ctx, n, c, dir_w, ts, box);
                 prof_end(ctx);
                 S.bytes_moved += 24.0 * n;
                 step_norm += ts * wn;
@@ -322,7 +330,8 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
     double red[kMaxRed];
 
     prof_begin(ctx, KC_OTHER, 16.0 * n);
-    launch_init(ctx, n, c, f, 0, 0.0);   // c = 0; ||f||, non-finite f
+    const Box unbounded{-INFINITY, INFINITY};
+    launch_init(ctx, n, c, f, 0, 0.0, unbounded);   // c = 0; ||f||, non-finite f
     prof_end(ctx);
     if ((rc = host_reduce(ctx, n, 4, kInitOps, red)) != NN_OK) return rc;
     S.bytes_moved += 16.0 * n;
@@ -345,12 +354,12 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
     double rel = 1.0;   // ||f - K c|| / ||f|| at c = 0
     for (int restart = 0;; restart++) {
         prof_begin(ctx, KC_GRAD, B.spmv() + 16.0 * n);
-        launch_grad(ctx, A, A->val, c, f, W.g);   // g = K c - f
+        launch_grad(ctx, A, A->val, c, f, W.g, unbounded);   // g = K c - f
         prof_end(ctx);
         S.spmvs++;
         S.bytes_moved += B.spmv() + 16.0 * n;
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, A->diag, c, W.g, nullptr, false, true);
+        launch_cg_setup(ctx, A, A->diag, c, W.g, nullptr, false, unbounded, true);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
         const double rtol = std::min(0.5, o->tol / rel);

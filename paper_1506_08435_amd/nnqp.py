@@ -49,7 +49,8 @@ class Opts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("max_cg", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("c0_mode", ctypes.c_int32),
                 ("c0_value", ctypes.c_double), ("delta0", ctypes.c_double),
-                ("cg_chunk", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+                ("cg_chunk", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("lower", ctypes.c_double), ("upper", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -90,7 +91,7 @@ def load_library(path: str = LIB_PATH):
         "nn_destroy": (None, [vp]),
         "nn_last_error": (ctypes.c_char_p, [vp]),
         "nn_default_opts": (i32, [P(Opts)]),
-        "nn_assemble": (i32, [vp, P(Mesh), vp, i64, vp, vp, vp, ctypes.c_int, P(vp), vp, vp]),
+        "nn_assemble": (i32, [vp, P(Mesh), vp, i64, vp, vp, vp, vp, ctypes.c_int, P(vp), vp, vp]),
         "nn_matrix_from_csr": (i32, [vp, i64, vp, vp, vp, vp, P(vp)]),
         "nn_matrix_info": (i32, [vp, P(i64), P(i64), P(ctypes.c_int)]),
         "nn_matrix_export": (i32, [vp, vp, vp, vp, vp, vp]),
@@ -205,13 +206,16 @@ class Context:
         ks = None if problem.kscale is None else np.ascontiguousarray(problem.kscale, dtype=np.float64)
         f = np.ascontiguousarray(problem.f_elem, dtype=np.float64)
         dmask = np.ascontiguousarray(problem.dirichlet, dtype=np.uint8)
+        dv = getattr(problem, "dirichlet_values", None)
+        dv = None if dv is None else np.ascontiguousarray(dv, dtype=np.float64)
         n = int((dmask == 0).sum())
         mesh = Mesh(dim, coords.shape[0], elems.shape[0], _ptr(coords), _ptr(elems))
         F = t.empty(max(n, 1), dtype=t.float64, device=self.device)
         dof = np.empty(coords.shape[0], dtype=np.int64)
         h = ctypes.c_void_p()
         st = self.lib.nn_assemble(self.handle, ctypes.byref(mesh), _ptr(D), nD, _ptr(ks), _ptr(f),
-                                  _ptr(dmask), int(with_mass), ctypes.byref(h), _ptr(F), _ptr(dof))
+                                  _ptr(dmask), _ptr(dv), int(with_mass), ctypes.byref(h), _ptr(F),
+                                  _ptr(dof))
         self._check(st, "nn_assemble")
         return self._wrap(h.value), F[:n], dof
 

@@ -625,3 +625,158 @@ def test_full_size_cube128_galerkin(ctx):
     print(f"cube128 Galerkin: cg {st['cg_its']} {st['seconds']:.3f} s, negative "
           f"{st['n_negative']}/{S.n} ({100 * st['n_negative'] / S.n:.1f}%), min {st['min_c']:.4g}, "
           f"max {st['max_c']:.4g}; non-negative solve {stn['seconds']:.3f} s")
+
+
+# ---------------------------------------------------------------- two-sided bounds, lifting
+def _capped(p, factor):
+    """The problem with an upper bound at `factor` times the max of its
+    non-negative solution (so both bounds are active)."""
+    S = oracle.assemble(p)
+    cmax = oracle.solve(S, tol=1e-12).c.max()
+    p.bounds = (0.0, float(factor * cmax))
+    return p
+
+
+BOX_CASES = {
+    "square2d_64_capped": lambda: _capped(W.config_small(), 0.5),
+    "cube3d_16_capped": lambda: _capped(W.cube3d(16), 0.4),
+    "cube_hole_k2": lambda: W.cube_hole(2),
+    "cube_hole_k3": lambda: W.cube_hole(3),
+    "square2d_40_shifted": lambda: _shifted(W.square2d(40, theta=1.1, ratio=1e-2)),
+}
+
+
+def _shifted(p):
+    """Bounds [-1e-6, 0.02]: a negative lower bound (the f <= 0 shortcut does
+    not apply), both bounds active."""
+    p.bounds = (-1e-6, 0.02)
+    return p
+
+
+def _check_box(S, c, active, ref_c, lo, hi, tol=PARITY_TOL):
+    assert c.min() >= lo and c.max() <= hi, (c.min(), c.max())
+    codes = np.where(c == lo, 1, np.where(c == hi, 2, 0))
+    assert np.array_equal(active, codes)
+    scale = np.abs(ref_c).max()
+    err = np.abs(c - ref_c).max() / scale
+    assert err <= tol, err
+    g_ref = oracle.spmv(S, ref_c) - S.F
+    free, strict = oracle.nondegenerate_masks(ref_c, g_ref, S.F, lo=lo, hi=hi)
+    assert np.all((c[free] > lo) & (c[free] < hi)), "a free node came out at a bound"
+    assert np.array_equal(c[strict], ref_c[strict]), "a strictly active node came out free"
+    return err
+
+
+@pytest.mark.parametrize("name", sorted(BOX_CASES))
+def test_box_solve_matches_oracle(ctx, name):
+    """lo <= c <= hi (Sec. 2.2.2, eq. Eq:non-negative; [0, 1] on the cube with
+    a hole, the DMP variant of Sec. 5) through the C ABI vs the oracle."""
+    p = BOX_CASES[name]()
+    lo, hi = p.bounds
+    K, F, _ = ctx.assemble(p)
+    S = oracle.assemble(p)
+    assert np.abs(_np(F) - S.F).max() <= 1e-14 * max(np.abs(S.F).max(), 1e-300)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, lower=lo, upper=hi)
+    c, active = _np(c), _np(active)
+    ref = oracle.solve(S, tol=1e-13, lo=lo, hi=hi)
+    assert ref.certified
+    err = _check_box(S, c, active, ref.c, lo, hi)
+    k = oracle.kkt(S, c, lo=lo, hi=hi)
+    assert k.r <= 1.01e-12 + 4 * ref.floor
+    n_hi = int((c == hi).sum())
+    print(f"{name}: n={S.n} err={err:.2e} kkt={k.r:.2e} at lo {int((c == lo).sum())} at hi {n_hi} "
+          f"outer={st['outer_its']} cg={st['cg_its']}")
+
+
+def test_box_mixed_precision_matches_oracle(ctx):
+    from paper_1506_08435_amd import nnqp
+    p = W.cube_hole(3)
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-10, lower=0.0, upper=1.0,
+                                     precision=nnqp.NN_MIXED)
+    c = _np(c)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13, lo=0.0, hi=1.0)
+    assert c.min() >= 0.0 and c.max() <= 1.0
+    assert np.abs(c - ref.c).max() / np.abs(ref.c).max() <= MIXED_TOL
+    assert oracle.kkt(S, c, lo=0.0, hi=1.0).r <= 1.01e-10
+
+
+def test_box_transient_steps_match_oracle(ctx):
+    import torch
+    p = W.config_transient3d(14, 12, 8, ell=2.0)
+    S = oracle.assemble(p, with_mass=True)
+    hi = 0.5 * oracle.solve(S, tol=1e-12).c.max()
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    cref = np.zeros(S.n)
+    for step in range(4):
+        _, active, st = ctx.step_transient(K, 0.05, F, c, tol=1e-12, upper=hi)
+        cref = oracle.transient_step(S, 0.05, cref, tol=1e-13, hi=hi).c
+        cg = _np(c)
+        assert cg.max() <= hi and cg.min() >= 0.0
+        err = np.abs(cg - cref).max() / max(np.abs(cref).max(), 1e-300)
+        assert err <= PARITY_TOL, (step, err)
+    assert (cref == hi).any()
+
+
+def test_bounds_validation(ctx, batch_members):
+    from paper_1506_08435_amd import nnqp
+    p = W.square2d(8)
+    K, F, _ = ctx.assemble(p)
+    for kw in ({"lower": 1.0, "upper": 1.0}, {"lower": float("-inf")},
+               {"upper": float("nan")}, {"lower": 0.5, "upper": 0.1}):
+        with pytest.raises(nnqp.NnError) as ei:
+            ctx.solve_nonneg(K, F, **kw)
+        assert ei.value.status == nnqp.NN_EINVAL
+    As, Fs = batch_members[1][:2], batch_members[2][:2]
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_batch(As, Fs, upper=1.0)
+    assert ei.value.status == nnqp.NN_EINVAL
+    # a start value outside the box is projected onto it
+    c, _, st = ctx.solve_nonneg(K, F, tol=1e-12, c0_value=5.0, upper=0.01)
+    c2, _, _ = ctx.solve_nonneg(K, F, tol=1e-12, upper=0.01)
+    assert np.abs(_np(c) - _np(c2)).max() <= 1e-9 * 0.01
+
+
+def test_lifted_assembly_linear_data(ctx):
+    """Lifting on the GPU: f = 0 with linear Dirichlet data on the whole
+    boundary gives back the linear function (P1 reproduces it)."""
+    p = W.cube3d(8)
+    p.f_elem = np.zeros_like(p.f_elem)
+    lin = p.coords @ np.array([0.7, -1.3, 0.4]) + 0.25
+    p.dirichlet_values = np.where(p.dirichlet == 1, lin, 0.0)
+    K, F, dof = ctx.assemble(p)
+    S = oracle.assemble(p)
+    assert np.abs(_np(F) - S.F).max() <= 1e-14 * np.abs(S.F).max()
+    c, st = ctx.solve_galerkin(K, F, tol=1e-13, max_cg=100000)
+    free_nodes = np.flatnonzero(dof >= 0)
+    assert np.abs(_np(c) - lin[free_nodes]).max() <= 1e-10
+    bad = p.dirichlet_values.copy()
+    bad[0] = float("nan")
+    p.dirichlet_values = bad
+    from paper_1506_08435_amd import nnqp
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.assemble(p)
+    assert ei.value.status == nnqp.NN_ENONFINITE
+
+
+def test_full_size_cube_hole_dmp(ctx):
+    """The cube-with-hole stand-in at 126^3 cells (about 2M DOF) with bounds
+    [0, 1], in the benchmark's configuration: the oracle certifies the KKT
+    conditions of the GPU solution with its own assembly; the Galerkin
+    solution of the same system violates the maximum principle."""
+    p = W.cube_hole(14)
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-8, lower=0.0, upper=1.0, inner_rtol=0.5)
+    c = _np(c)
+    assert c.min() >= 0.0 and c.max() <= 1.0
+    S = oracle.assemble(p)
+    assert S.n == K.n
+    k = oracle.kkt(S, c, lo=0.0, hi=1.0)
+    assert k.r <= 1e-8 * (1 + 1e-6) and k.nonfinite == 0
+    g, gst = ctx.solve_galerkin(K, F, tol=1e-8, max_cg=200000)
+    assert gst["n_negative"] > 0.2 * S.n and gst["min_c"] < 0.0
+    print(f"cube_hole_k14: n={S.n} kkt {k.r:.3e} outer {st['outer_its']} cg {st['cg_its']} "
+          f"{st['seconds']:.3f} s; Galerkin {gst['seconds']:.3f} s, negative "
+          f"{100 * gst['n_negative'] / S.n:.1f}%, min {gst['min_c']:.4g}, max {gst['max_c']:.4g}")
