@@ -144,6 +144,79 @@ def run_small(args):
     print(json.dumps(line), flush=True)
 
 
+def run_hole(args):
+    """The structured cube-with-hole stand-in (Sec. 5.1): 9k cells per side,
+    c = 0 outside, c = 1 on the hole, f = 0, dispersion tensor of v = (1,1,1),
+    bounds [0, 1] (the DMP variant).  Times K bounded solves (DOF/s), then the
+    Galerkin baseline on the same system with its DMP statistics (Table
+    Tab:S5_cube_dmp) and the time ratio (Tables Tab:S5_cube_times_*)."""
+    import torch
+    from paper_1506_08435_amd import nnqp, workloads as W
+    p = W.cube_hole(args.hole_k)
+    ctx = nnqp.Context(0)
+    K, F, _ = ctx.assemble(p)
+    n = K.n
+    prec = nnqp.NN_MIXED if args.precision == "mixed" else nnqp.NN_FP64
+    opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
+                             lower=0.0, upper=1.0)
+    c = torch.empty(n, dtype=torch.float64, device=ctx.device)
+    act = torch.empty(n, dtype=torch.uint8, device=ctx.device)
+    for _ in range(args.warmup):
+        ctx.solve_nonneg(K, F, opts=opts, c=c, active=act)
+    ctx.set_profiling(not args.no_kernel_timing, ("cg_spmv",))
+    ctx.kernel_times(reset=True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, st = ctx.solve_nonneg(K, F, opts=opts, c=c, active=act)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_profiling(False)
+    dom = kt["cg_spmv"]
+    avg_ms = dom["ms"] / max(dom["count"], 1)
+    bpl = dom["bytes"] / max(dom["count"], 1)
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if dom["count"] else 0.0
+    at_lo = int((act[:n] == 1).sum().item())
+    at_hi = int((act[:n] == 2).sum().item())
+    gopts = nnqp.default_opts(tol=1e-8, max_cg=200000)
+    ctx.solve_galerkin(K, F, opts=gopts)
+    gal = [ctx.solve_galerkin(K, F, opts=gopts) for _ in range(args.galerkin_reps)]
+    g_med = sorted(g[1]["seconds"] for g in gal)[len(gal) // 2]
+    gc, gst = gal[-1]
+    over = int((gc > 1.0).sum().item())
+    nn_med = sorted(x["seconds"] for x in stats)[len(stats) // 2]
+    line = {
+        "metric": "solved DOF/s at KKT tol 1e-8, bounds [0, 1]",
+        "value": round(n * args.steps / wall, 1), "unit": "DOF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "dtype": "f64" if prec == nnqp.NN_FP64 else "f32 values+CG vectors / f64 residual",
+        "data": "synthetic",
+        "config": {"workload": f"cube_hole_k{args.hole_k}: [0,1]^3 minus [4/9,5/9]^3, "
+                               f"{9 * args.hole_k}^3 cells x 6 P1 tets (hole removed), {n} free DOF, "
+                               f"{K.nnz} nnz, c = 0 outside / 1 on the hole (lifted), f = 0, "
+                               f"D = dispersion(v = (1,1,1), alpha_L = 1, alpha_T = 1e-3), "
+                               f"bounds [0, 1], from c0 = 1e-8 to KKT tol 1e-8",
+                   "inner_rtol": args.inner_rtol},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "k_cg_spmv", "launches": dom["count"],
+                     "avg_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": round(bpl)},
+        "solve": {"median_device_ms": round(nn_med * 1e3, 3), "outer_its": stats[-1]["outer_its"],
+                  "cg_its": stats[-1]["cg_its"], "kkt_rel": stats[-1]["kkt_rel"],
+                  "min_c": stats[-1]["min_c"], "nodes_at_0": at_lo, "nodes_at_1": at_hi},
+        "galerkin": {"median_device_ms": round(g_med * 1e3, 3), "cg_its": gst["cg_its"],
+                     "residual_rel": gst["kkt_rel"], "min_c": gst["min_c"], "max_c": gst["max_c"],
+                     "negative_nodes": gst["n_negative"], "nodes_above_1": over,
+                     "pct_violating": round(100.0 * (gst["n_negative"] + over) / max(n, 1), 2),
+                     "bounded_over_galerkin_time": round(nn_med / g_med, 3)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_transient(args):
     """50 backward-Euler steps of the 256x256x64 heterogeneous workload (warm
     started, K~ = M/dt + K formed once); value = free DOF x steps / second."""
@@ -335,8 +408,10 @@ def main():
     ap.add_argument("--verbose", action="store_true", help="per-outer-iteration trace on stderr")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 512 MiB device-to-device copies first (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["cube", "small", "transient", "batch", "serve"],
+    ap.add_argument("--workload", choices=["cube", "small", "transient", "batch", "serve", "hole"],
                     default="cube")
+    ap.add_argument("--hole-k", type=int, default=14,
+                    help="cube-with-hole workload: 9k cells per side (k = 14: about 2M DOF)")
     ap.add_argument("--small-reps", type=int, default=50, help="solves timed by the small workload")
     ap.add_argument("--no-galerkin", action="store_true",
                     help="skip the unconstrained Galerkin baseline solve (cube workload)")
@@ -375,6 +450,9 @@ def main():
         return
     if args.workload == "small":
         run_small(args)
+        return
+    if args.workload == "hole":
+        run_hole(args)
         return
 
     import torch
