@@ -70,6 +70,14 @@ typedef struct {
     const int32_t *elems;    /* host [n_elems * (dim + 1)], node ids in [0, n_nodes) */
 } nn_mesh;
 
+/* Bound-constrained method of nn_solve_nonneg and nn_step_transient (the two
+ * TAO solvers the paper runs, Sec. 3.1 and Sec. 5.1). */
+typedef enum {
+    NN_TRON = 0,   /* active-set projected Newton-CG with a trust region (Lin & More) */
+    NN_BLMVM = 1   /* bounded limited-memory variable metric (Benson & More): gradient
+                      only, an L-BFGS matrix built from projected-gradient differences */
+} nn_method;
+
 /* Solver options; fill with nn_default_opts() and override. */
 typedef struct {
     double tol;           /* stop when ||pg(c)||_2 <= tol * ||f||_2, pg the projected
@@ -97,6 +105,10 @@ typedef struct {
                              (may be +inf).  The batched entry points take the default
                              only; nn_solve_galerkin ignores them. */
     double upper;
+    int32_t method;       /* nn_method: NN_TRON (default) or NN_BLMVM */
+    int32_t lmm_vectors;  /* BLMVM: stored (s, y) pairs, 1..8; default 5 (TAO's default) */
+    int32_t max_lm_its;   /* BLMVM: iteration cap; default 20000 */
+    int32_t reserved;
 } nn_opts;
 
 /* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */
@@ -209,8 +221,18 @@ nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_
  * inner CG run on float32 copies of the values with float32 CG vectors, while
  * every outer iteration re-evaluates the float64 residual g = K c - f that
  * decides convergence; the first mixed solve attaches the float32 copy to K.
- * Returns NN_EMAXIT (c feasible, stats filled) if max_outer is reached before
- * ||pg|| <= tol ||f||; NN_ENONFINITE if a non-finite value appears.
+ * With opts->method == NN_BLMVM the same minimiser is found by the bounded
+ * limited-memory variable-metric method (float64 only; NN_EINVAL with
+ * NN_MIXED): each iteration forms d = -H pg from the compact L-BFGS
+ * representation of lmm_vectors pairs (s = step, y = difference of projected
+ * gradients), drops the components that point out of the box at a bound, and
+ * takes the exact minimiser of the quadratic along d when no bound is
+ * crossed, else a projected backtracking search; stats.outer_its counts its
+ * iterations (cap max_lm_its), cg_its is 0.  Workspace of (2 lmm_vectors + 4)
+ * float64 vectors of length n is kept with the context.
+ * Returns NN_EMAXIT (c feasible, stats filled) if max_outer (TRON) or
+ * max_lm_its (BLMVM) is reached before ||pg|| <= tol ||f||; NN_ENONFINITE if
+ * a non-finite value appears.
  */
 nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
                           const nn_opts *opts, double *c_dev, uint8_t *active_dev,

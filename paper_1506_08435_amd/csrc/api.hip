@@ -220,6 +220,7 @@ void nn_destroy(nn_ctx *ctx)
     for (float *v : fvecs)
         if (v) (void)hipFree(v);
     if (W.mask) (void)hipFree(W.mask);
+    lm_release(ctx);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->h_part) (void)hipHostFree(ctx->h_part);
     if (ctx->scal) (void)hipFree(ctx->scal);
@@ -256,6 +257,9 @@ nn_status nn_default_opts(nn_opts *o)
     o->cg_chunk = 16;
     o->lower = 0.0;
     o->upper = INFINITY;
+    o->method = NN_TRON;
+    o->lmm_vectors = 5;
+    o->max_lm_its = 20000;
     return NN_OK;
 }
 
@@ -444,6 +448,13 @@ static nn_status check_opts(nn_ctx *ctx, const nn_opts *o)
         return fail(ctx, NN_EINVAL, "c0_value must be finite");
     if (!std::isfinite(o->lower) || std::isnan(o->upper) || !(o->upper > o->lower))
         return fail(ctx, NN_EINVAL, "bounds must satisfy lower finite, upper > lower");
+    if (o->method != NN_TRON && o->method != NN_BLMVM) return fail(ctx, NN_EINVAL, "unknown method");
+    if (o->method == NN_BLMVM) {
+        if (o->lmm_vectors < 1 || o->lmm_vectors > 8)
+            return fail(ctx, NN_EINVAL, "lmm_vectors must be in 1..8");
+        if (o->max_lm_its < 0) return fail(ctx, NN_EINVAL, "bad iteration cap");
+        if (o->precision != NN_FP64) return fail(ctx, NN_EINVAL, "BLMVM runs in float64 only");
+    }
     return NN_OK;
 }
 
@@ -454,6 +465,8 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
     if (!K || (K->n > 0 && (!f_dev || !c_dev))) return fail(ctx, NN_EINVAL, "null argument");
     nn_status st = check_opts(ctx, opts);
     if (st != NN_OK) return st;
+    if (opts->method == NN_BLMVM)
+        return blmvm_impl(ctx, K, K->val, f_dev, opts, c_dev, active_dev, stats);
     const float *v32 = nullptr;
     if (opts->precision == NN_MIXED && K->n > 0) {
         if (!K->val32) {
@@ -498,6 +511,7 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     launch_transient_rhs(ctx, K, c_dev, f_dev, dt, ctx->ws.ft);
     nn_opts o = *opts;
     o.c0_mode = 1;   // warm start from c^(n)
+    if (o.method == NN_BLMVM) return blmvm_impl(ctx, K, K->kt, ctx->ws.ft, &o, c_dev, active_dev, stats);
     return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, K->kt_diag, ctx->ws.ft, &o, c_dev,
                       active_dev, stats);
 }
@@ -514,6 +528,7 @@ static nn_status check_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
     if (st != NN_OK) return st;
     if (opts->lower != 0.0 || opts->upper != INFINITY)
         return fail(ctx, NN_EINVAL, "the batched solver takes the bounds [0, inf) only");
+    if (opts->method != NN_TRON) return fail(ctx, NN_EINVAL, "the batched solver runs TRON only");
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int p = 0; p < nprob; p++) {
         if (!K[p]) return fail(ctx, NN_EINVAL, "null matrix in batch");

@@ -1,0 +1,599 @@
+// Bounded limited-memory variable-metric (BLMVM) solver for
+//     min 1/2 c.Kc - c.f  subject to  lo <= c <= hi
+// the gradient-only method the paper runs beside TRON through TAO (Sec. 3.1,
+// Sec. 5.1; the objective and gradient callbacks of eq. S3_tao_objective and
+// eq. S3_tao_gradient are all it uses).  The method is that of Benson & More
+// (2001): an L-BFGS inverse-Hessian approximation H built from the steps s and
+// the differences y of projected gradients, search direction d = -H pg, and a
+// projected line search.  Here, for the quadratic objective:
+//
+//   1. Pair pass (one kernel over the rows): pg at the current point, the new
+//      y = pg - pg_prev when a step was just taken, and every inner product
+//      the compact representation needs (s_j.pg, y_j.pg, s_j.y, y_j.y, s.s).
+//   2. Coefficient kernel (one wavefront): accepts the new pair when
+//      s.y > 1e-12 |s| |y| (else drops it; a full memory then loses its
+//      oldest pair), sets gamma = s.y / y.y, and solves the small triangular
+//      systems of the compact form (Byrd, Nocedal & Schnabel 1994)
+//          H v = gamma v + S t - gamma Y p,  p = R^-1 S'v,
+//          t = R^-T ((D + gamma Y'Y) p - gamma Y'v),
+//      R the upper triangle of S'Y and D its diagonal (pairs oldest first).
+//   3. Direction pass: d = -H pg from those coefficients, with every
+//      component that points out of the box at a bound set to zero (the
+//      projection would cancel it for any step), the first bound crossing
+//      along d, g.d and d.d.
+//   4. Line search: when no bound is crossed up to t = 1, one trial at t = 1
+//      gives K d, and the step is the exact minimiser of the quadratic along
+//      d (capped at the first crossing); otherwise projected backtracking
+//      c(t) = P(c + t d), t = 1, 1/2, ..., until the sufficient-decrease test
+//      holds, finishing with the exact step on the segment [0, crossing] if t
+//      reaches it.  Each trial is one matrix pass that gathers P(c + t d) and
+//      returns the gradient K c(t) - f at the trial point.
+//   5. Step kernel: c <- c(t), s stored in the next pair slot, g updated.
+// g is refreshed with a plain gradient pass every 50 iterations that did not
+// end on a freshly computed gradient, and before convergence is accepted.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "nnqp_internal.hpp"
+#include "rows.hpp"
+
+namespace nnqp {
+
+namespace {
+
+constexpr int kLmMax = 8;                  // pair slots supported
+constexpr int kLmNV = 4 * kLmMax + 3;      // values of the pair pass at kLmMax
+constexpr double kLmMu = 0.01;             // sufficient-decrease constant
+constexpr double kLmCurv = 1e-12;          // pair acceptance: s.y > kLmCurv |s| |y|
+constexpr int kLmRefresh = 50;             // iterations between gradient refreshes
+constexpr int kLmMaxTrials = 60;
+
+struct LmState {
+    int count;        // stored pairs
+    int head;         // slot the next pair is written to
+    int pending;      // a step was taken: its s is in slot head, its y is formed next
+    int accepted;     // pairs accepted / rejected so far
+    int rejected;
+    double gamma;     // H0 = gamma I
+    double pg2;       // |pg|^2 at the current point
+    double nonfinite; // non-finite c or g entries at the current point
+    double sy[kLmMax][kLmMax];   // s_a . y_b by slot (used for a older than or equal to b)
+    double yy[kLmMax][kLmMax];   // y_a . y_b by slot
+    double sc[kLmMax];           // coefficient of s_slot in H pg
+    double yc[kLmMax];           // coefficient of y_slot in H pg
+};
+
+// slot j is live in the pair pass: a stored pair, or the pair being formed
+__device__ __forceinline__ bool lm_live(int j, int M, int count, int head, int pending)
+{
+    const int age = (head - j + M) % M;   // 1 = newest stored pair, ..., M = oldest when full
+    return (pending && j == head) || (age >= 1 && age <= count) || (count == M && j == head);
+}
+
+// Block total of NV sums (fixed order: butterfly within the wavefront, waves
+// in order) stored as this block's partial part[k * kMaxBlocks + block].
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&a)[NV], double *part)
+{
+    __shared__ double sh[kWaves][NV];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; k++)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) a[k] += __shfl_xor(a[k], o, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; k++) sh[wid][k] = a[k];
+    __syncthreads();
+    for (int k = threadIdx.x; k < NV; k += kBlock) {
+        double v = sh[0][k];
+        for (int w = 1; w < kWaves; w++) v += sh[w][k];
+        part[k * kMaxBlocks + blockIdx.x] = v;
+    }
+}
+
+// 1. pair pass (see the file comment); values: |pg|^2, #non-finite,
+// s_j.pg, y_j.pg, s_j.y, y_j.y (j = 0..M-1 by slot), s.s
+template <int M>
+__global__ __launch_bounds__(kBlock) void kl_pairs(Part P, const double *__restrict__ c,
+                                                   const double *__restrict__ g,
+                                                   double *__restrict__ pg,
+                                                   const double *__restrict__ S,
+                                                   double *__restrict__ Y, int64_t ld,
+                                                   const LmState *__restrict__ st, Box B,
+                                                   double *part)
+{
+    constexpr int NV = 4 * M + 3;
+    const int count = st->count, head = st->head, pending = st->pending;
+    bool live[M];
+#pragma unroll
+    for (int j = 0; j < M; j++) live[j] = lm_live(j, M, count, head, pending);
+    double a[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) a[k] = 0.0;
+    for_rows(P, [&](int i, bool act) {
+        if (!act) return;
+        const double ci = c[i], gi = g[i];
+        const double pgi = ci > B.lo ? (ci < B.hi ? gi : fmax(gi, 0.0)) : fmin(gi, 0.0);
+        a[0] += pgi * pgi;
+        a[1] += (isfinite(ci) && isfinite(gi)) ? 0.0 : 1.0;
+        double yn = 0.0, sn = 0.0;
+        if (pending) {
+            yn = pgi - pg[i];
+            sn = S[head * ld + i];
+            Y[head * ld + i] = yn;
+            a[2 + 4 * M] += sn * sn;
+        }
+        pg[i] = pgi;
+#pragma unroll
+        for (int j = 0; j < M; j++) {
+            if (!live[j]) continue;
+            const bool fresh = pending && j == head;
+            const double sj = fresh ? sn : S[j * ld + i];
+            const double yj = fresh ? yn : Y[j * ld + i];
+            a[2 + j] += sj * pgi;
+            a[2 + M + j] += yj * pgi;
+            if (pending) {
+                a[2 + 2 * M + j] += sj * yn;
+                a[2 + 3 * M + j] += yj * yn;
+            }
+        }
+    });
+    block_sums<NV>(a, part);
+}
+
+// 2. coefficient kernel: one wavefront; thread 0 does the small algebra
+template <int M>
+__global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double *part)
+{
+    constexpr int NV = 4 * M + 3;
+    __shared__ double t[NV];
+    for (int k = threadIdx.x; k < NV; k += 64) {
+        double v = 0.0;
+        for (int b = 0; b < nb; b++) v += part[k * kMaxBlocks + b];
+        t[k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int count = st->count, head = st->head;
+    st->pg2 = t[0];
+    st->nonfinite = t[1];
+    if (st->pending) {
+        const double sy = t[2 + 2 * M + head], yy = t[2 + 3 * M + head], ss = t[2 + 4 * M];
+        const bool ok = isfinite(sy) && isfinite(yy) && yy > 0.0 &&
+                        sy > kLmCurv * sqrt(ss) * sqrt(yy);
+        if (ok) {
+            // column `head` of S'Y and Y'Y against every pair that stays
+            for (int j = 0; j < M; j++) {
+                if (!lm_live(j, M, count, head, 1)) continue;
+                st->sy[j][head] = t[2 + 2 * M + j];
+                st->yy[j][head] = t[2 + 3 * M + j];
+                st->yy[head][j] = t[2 + 3 * M + j];
+            }
+            count = count < M ? count + 1 : M;
+            head = (head + 1) % M;
+            st->gamma = sy / yy;
+            st->accepted++;
+        } else {
+            if (count == M) count = M - 1;   // its oldest pair was overwritten
+            st->rejected++;
+        }
+        st->pending = 0;
+    }
+    st->count = count;
+    st->head = head;
+    // compact-form coefficients over the pairs, oldest first
+    int sl[M];
+    double u[M], w[M], p[M], z[M], tp[M];
+    for (int k = 0; k < count; k++) {
+        sl[k] = (head - count + k + 2 * M) % M;
+        u[k] = t[2 + sl[k]];
+        w[k] = t[2 + M + sl[k]];
+    }
+    const double gam = st->gamma;
+    for (int a = count - 1; a >= 0; a--) {
+        double v = u[a];
+        for (int b = a + 1; b < count; b++) v -= st->sy[sl[a]][sl[b]] * p[b];
+        p[a] = v / st->sy[sl[a]][sl[a]];
+    }
+    for (int a = 0; a < count; a++) {
+        double v = st->sy[sl[a]][sl[a]] * p[a] - gam * w[a];
+        for (int b = 0; b < count; b++) v += gam * st->yy[sl[a]][sl[b]] * p[b];
+        z[a] = v;
+    }
+    for (int a = 0; a < count; a++) {
+        double v = z[a];
+        for (int b = 0; b < a; b++) v -= st->sy[sl[b]][sl[a]] * tp[b];
+        tp[a] = v / st->sy[sl[a]][sl[a]];
+    }
+    for (int j = 0; j < M; j++) {
+        st->sc[j] = 0.0;
+        st->yc[j] = 0.0;
+    }
+    for (int a = 0; a < count; a++) {
+        st->sc[sl[a]] = tp[a];
+        st->yc[sl[a]] = -gam * p[a];
+    }
+}
+
+// drop every stored pair (before the coefficients are formed again)
+__global__ void kl_forget(LmState *st) { st->count = 0; }
+
+__global__ void kl_state_init(LmState *st, double gamma)
+{
+    st->count = 0;
+    st->head = 0;
+    st->pending = 0;
+    st->accepted = 0;
+    st->rejected = 0;
+    st->gamma = gamma;
+}
+
+// 3. direction pass: d = -H pg, outward components at a bound zeroed;
+// first crossing (min), g.d, d.d
+template <int M>
+__global__ __launch_bounds__(kBlock) void kl_dir(Part P, const double *__restrict__ c,
+                                                 const double *__restrict__ g,
+                                                 const double *__restrict__ pg,
+                                                 const double *__restrict__ S,
+                                                 const double *__restrict__ Y, int64_t ld,
+                                                 const LmState *__restrict__ st, Box B,
+                                                 double *__restrict__ d, double *partials)
+{
+    const int count = st->count, head = st->head;
+    const double gam = st->gamma;
+    bool live[M];
+    double sc[M], yc[M];
+#pragma unroll
+    for (int j = 0; j < M; j++) {
+        live[j] = lm_live(j, M, count, head, 0) && count > 0;
+        sc[j] = st->sc[j];
+        yc[j] = st->yc[j];
+    }
+    constexpr uint32_t kOps = OPS3(OP_MIN, OP_SUM, OP_SUM);
+    double a[3];
+    red_init<kOps, 3>(a);
+    for_rows(P, [&](int i, bool act) {
+        if (!act) return;
+        double di = -gam * pg[i];
+#pragma unroll
+        for (int j = 0; j < M; j++)
+            if (live[j]) di -= sc[j] * S[j * ld + i] + yc[j] * Y[j * ld + i];
+        const double ci = c[i];
+        if ((ci <= B.lo && di < 0.0) || (ci >= B.hi && di > 0.0)) di = 0.0;
+        d[i] = di;
+        if (di < 0.0) a[0] = fmin(a[0], (ci - B.lo) / (-di));
+        else if (di > 0.0) a[0] = fmin(a[0], (B.hi - ci) / di);
+        a[1] += g[i] * di;
+        a[2] += di * di;
+    });
+    block_partial<kOps, 3>(a, slot_ptr(partials, SLOT_HOST));
+}
+
+// 4. trial: gathers c(t) = P(c + t d), writes gn = K c(t) - f; g.s, s.(gn - g), s.s
+// with s = c(t) - c
+template <int WMAX, class Cols>
+__global__ __launch_bounds__(kBlock) void kl_trial(Part P, const int *__restrict__ so, Cols cols,
+                                                   const double *__restrict__ v,
+                                                   const double *__restrict__ c,
+                                                   const double *__restrict__ d, double t,
+                                                   const double *__restrict__ f,
+                                                   const double *__restrict__ g,
+                                                   double *__restrict__ gn, Box B,
+                                                   double *partials)
+{
+    auto ct = [&](int j) { return proj_box(c[j] + t * d[j], B); };
+    constexpr uint32_t kOps = OPS3(OP_SUM, OP_SUM, OP_SUM);
+    double a[3];
+    red_init<kOps, 3>(a);
+    sell_rows<WMAX>(P, so, cols, v, AllRows(),
+                    [&](int i) { return Three{ct(i) - c[i], f[i], g[i]}; }, ct,
+                    [&](int i, double kc, Three x) {
+                        const double gni = kc - x.b;
+                        gn[i] = gni;
+                        a[0] += x.c * x.a;
+                        a[1] += x.a * (gni - x.c);
+                        a[2] += x.a * x.a;
+                    });
+    block_partial<kOps, 3>(a, slot_ptr(partials, SLOT_HOST));
+}
+
+// 5. step: c <- P(c + t d), s -> slot head, g <- g + gscale (gn - g)
+// (gscale = 1: the trial's gradient itself)
+__global__ __launch_bounds__(kBlock) void kl_step(Part P, double *__restrict__ c,
+                                                  const double *__restrict__ d, double t,
+                                                  double *__restrict__ g,
+                                                  const double *__restrict__ gn, double gscale,
+                                                  double *__restrict__ S, int64_t ld,
+                                                  LmState *st, Box B)
+{
+    const int head = st->head;
+    for_rows(P, [&](int i, bool act) {
+        if (!act) return;
+        const double ci = c[i];
+        const double cn = proj_box(ci + t * d[i], B);
+        S[head * ld + i] = cn - ci;
+        c[i] = cn;
+        g[i] = gscale == 1.0 ? gn[i] : g[i] + gscale * (gn[i] - g[i]);
+    });
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->pending = 1;
+}
+
+template <int M>
+void launch_pairs_coef(nn_ctx *ctx, const Part &P, const double *c, const double *g, Box B)
+{
+    LmWork &L = ctx->lm;
+    kl_pairs<M><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, g, L.pg, L.S, L.Y, L.cap,
+                                                  (const LmState *)L.state, B, L.part);
+    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P.nb, (LmState *)L.state, L.part);
+}
+
+template <int M>
+void launch_coef(nn_ctx *ctx, const Part &P)
+{
+    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P.nb, (LmState *)ctx->lm.state, ctx->lm.part);
+}
+
+template <int M>
+void launch_dir(nn_ctx *ctx, const Part &P, const double *c, const double *g, Box B)
+{
+    LmWork &L = ctx->lm;
+    kl_dir<M><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, g, L.pg, L.S, L.Y, L.cap,
+                                                (const LmState *)L.state, B, L.d, ctx->partials);
+}
+
+#define NN_LM_DISPATCH(m, fn, ...)                  \
+    switch (m) {                                    \
+    case 1: fn<1>(__VA_ARGS__); break;              \
+    case 2: fn<2>(__VA_ARGS__); break;              \
+    case 3: fn<3>(__VA_ARGS__); break;              \
+    case 4: fn<4>(__VA_ARGS__); break;              \
+    case 5: fn<5>(__VA_ARGS__); break;              \
+    case 6: fn<6>(__VA_ARGS__); break;              \
+    case 7: fn<7>(__VA_ARGS__); break;              \
+    default: fn<8>(__VA_ARGS__); break;             \
+    }
+
+nn_status ensure_lm(nn_ctx *ctx, int64_t n, int m)
+{
+    LmWork &L = ctx->lm;
+    if (L.state && L.cap >= n && L.m >= m) return NN_OK;
+    lm_release(ctx);
+    const int64_t cap = std::max<int64_t>(n, 64);
+    hipError_t e = hipMalloc(&L.S, sizeof(double) * cap * m);
+    if (e == hipSuccess) e = hipMalloc(&L.Y, sizeof(double) * cap * m);
+    if (e == hipSuccess) e = hipMalloc(&L.pg, sizeof(double) * cap);
+    if (e == hipSuccess) e = hipMalloc(&L.d, sizeof(double) * cap);
+    if (e == hipSuccess) e = hipMalloc(&L.gn, sizeof(double) * cap);
+    if (e == hipSuccess) e = hipMalloc(&L.part, sizeof(double) * kLmNV * kMaxBlocks);
+    if (e == hipSuccess) e = hipMalloc(&L.state, sizeof(LmState));
+    if (e == hipSuccess) e = hipHostMalloc(&L.h_state, sizeof(LmState), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        lm_release(ctx);
+        return fail(ctx, NN_EOOM, std::string("BLMVM workspace: ") + hipGetErrorString(e));
+    }
+    // stale slots are never read as pairs, but keep them finite
+    e = hipMemsetAsync(L.S, 0, sizeof(double) * cap * m, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L.Y, 0, sizeof(double) * cap * m, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, NN_EHIP, hipGetErrorString(e));
+    L.cap = cap;
+    L.m = m;
+    return NN_OK;
+}
+
+}  // namespace
+
+void lm_release(nn_ctx *ctx)
+{
+    LmWork &L = ctx->lm;
+    double *bufs[] = {L.S, L.Y, L.pg, L.d, L.gn, L.part};
+    for (double *b : bufs)
+        if (b) (void)hipFree(b);
+    if (L.state) (void)hipFree(L.state);
+    if (L.h_state) (void)hipHostFree(L.h_state);
+    L = LmWork();
+}
+
+nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *f,
+                     const nn_opts *o, double *c, uint8_t *active, nn_stats *st)
+{
+    const int64_t n = A->n;
+    nn_stats S;
+    std::memset(&S, 0, sizeof(S));
+    Box box;
+    box.lo = o->lower;
+    box.hi = o->upper;
+    NN_HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    auto finish = [&](nn_status rc) -> nn_status {
+        if (active && n > 0) launch_active(ctx, n, c, active, box);
+        (void)hipEventRecord(ctx->ev1, ctx->stream);
+        hipError_t e = hipEventSynchronize(ctx->ev1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        S.seconds = ms * 1e-3;
+        prof_collect(ctx);
+        if (e != hipSuccess) rc = fail(ctx, NN_EHIP, hipGetErrorString(e));
+        S.status = (int32_t)rc;
+        if (st) *st = S;
+        return rc;
+    };
+    if (n == 0) return finish(NN_OK);
+    const int M = std::min(std::max(o->lmm_vectors, 1), kLmMax);
+    nn_status rc = ensure_workspace(ctx, n);
+    if (rc != NN_OK) return rc;
+    if ((rc = ensure_lm(ctx, n, M)) != NN_OK) return rc;
+    Workspace &W = ctx->ws;
+    LmWork &L = ctx->lm;
+    LmState &H = *(LmState *)L.h_state;
+    const Part P = make_part(n);
+    const double nd = (double)n, nnz = (double)A->nnz;
+    const double b_grad = 4.0 * (nd + 1) + 12.0 * nnz + 32.0 * nd;
+    const double b_trial = 4.0 * (nd + 1) + 12.0 * nnz + 40.0 * nd;
+    static const int kInitOps[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
+    static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
+    static const int kDirOps[3] = {OP_MIN, OP_SUM, OP_SUM};
+    static const int kTrialOps[3] = {OP_SUM, OP_SUM, OP_SUM};
+    double red[kMaxRed];
+
+    // ---- start point, load statistics, first gradient
+    const double c0v = std::min(std::max(o->c0_value, box.lo), box.hi);
+    prof_begin(ctx, KC_OTHER, 16.0 * n);
+    launch_init(ctx, n, c, f, o->c0_mode == 1 ? 1 : 0, c0v, box);
+    prof_end(ctx);
+    if ((rc = host_reduce(ctx, n, 4, kInitOps, red)) != NN_OK) return rc;
+    S.bytes_moved += 16.0 * n;
+    const double normf = std::sqrt(red[0]), fmax = red[1];
+    S.norm_f = normf;
+    if (red[2] != 0.0 || red[3] != 0.0)
+        return finish(fail(ctx, NN_ENONFINITE, "non-finite value in f or the initial c"));
+    if (box.lo == 0.0 && !(fmax > 0.0)) {
+        NN_HIP_TRY(ctx, hipMemsetAsync(c, 0, sizeof(double) * n, ctx->stream));
+        S.n_active = (int32_t)n;
+        return finish(NN_OK);
+    }
+    // gradient pass with the KKT report; true when the point is converged
+    auto refresh = [&](bool &conv) -> nn_status {
+        prof_begin(ctx, KC_GRAD, b_grad);
+        launch_grad(ctx, A, vals, c, f, W.g, box);
+        prof_end(ctx);
+        S.spmvs++;
+        S.bytes_moved += b_grad;
+        nn_status r2 = host_reduce(ctx, n, 5, kGradOps, red);
+        if (r2 != NN_OK) return r2;
+        if (red[1] != 0.0) return fail(ctx, NN_ENONFINITE, "non-finite gradient");
+        S.kkt_rel = std::sqrt(red[0]) / normf;
+        S.kkt_nat_inf = red[2];
+        S.min_c = red[3];
+        S.n_active = (int32_t)red[4];
+        conv = S.kkt_rel <= o->tol;
+        return NN_OK;
+    };
+    bool conv = false;
+    if ((rc = refresh(conv)) != NN_OK) return finish(rc);
+    if (conv) return finish(NN_OK);
+    kl_state_init<<<1, 1, 0, ctx->stream>>>((LmState *)L.state, 1.0);
+
+    const double vp = 8.0 * n;   // bytes of one vector pass
+    bool fresh = true;
+    int since_fresh = 0;
+    nn_status result = NN_EMAXIT;
+    for (int it = 0;; it++) {
+        // ---- 1-3. pairs, coefficients, direction
+        const double live = std::min(it, M);
+        prof_begin(ctx, KC_OTHER, vp * (5.0 + 2.0 * live));
+        NN_LM_DISPATCH(M, launch_pairs_coef, ctx, P, c, W.g, box);
+        prof_end(ctx);
+        prof_begin(ctx, KC_OTHER, vp * (4.0 + 2.0 * live));
+        NN_LM_DISPATCH(M, launch_dir, ctx, P, c, W.g, box);
+        prof_end(ctx);
+        S.bytes_moved += vp * (9.0 + 4.0 * live);
+        NN_HIP_TRY(ctx, hipMemcpyAsync(L.h_state, L.state, sizeof(LmState), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+        if ((rc = host_reduce(ctx, n, 3, kDirOps, red)) != NN_OK) return finish(rc);
+        if (H.nonfinite != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite iterate"));
+        S.outer_its = it;
+        const double rel = std::sqrt(H.pg2) / normf;
+        if (rel <= o->tol) {
+            if (fresh) {
+                S.kkt_rel = rel;
+                result = NN_OK;
+                break;
+            }
+            if ((rc = refresh(conv)) != NN_OK) return finish(rc);
+            fresh = true;
+            since_fresh = 0;
+            if (conv) {
+                result = NN_OK;
+                break;
+            }
+            continue;   // pairs and direction again from the fresh gradient
+        }
+        if (it >= o->max_lm_its) {
+            fail(ctx, NN_EMAXIT, "BLMVM iteration cap reached");
+            break;
+        }
+        double bmin = red[0], gd = red[1];
+        if (!(gd < 0.0)) {
+            // not a descent direction: forget the pairs, d = -gamma pg
+            kl_forget<<<1, 1, 0, ctx->stream>>>((LmState *)L.state);
+            NN_LM_DISPATCH(M, launch_coef, ctx, P);
+            NN_LM_DISPATCH(M, launch_dir, ctx, P, c, W.g, box);
+            S.bytes_moved += vp * 4.0;
+            S.refinements++;   // memory resets
+            if ((rc = host_reduce(ctx, n, 3, kDirOps, red)) != NN_OK) return finish(rc);
+            bmin = red[0];
+            gd = red[1];
+            if (!(gd < 0.0)) {
+                fail(ctx, NN_EMAXIT, "no descent direction above the tolerance (rounding floor)");
+                break;
+            }
+        }
+        // ---- 4. line search
+        auto trial = [&](double t, double &gs, double &sks) -> nn_status {
+            prof_begin(ctx, KC_TRIAL, b_trial);
+            NN_DISPATCH_W(A->wmax, (kl_trial<WM, ColsI32>), P.nb, P, A->sl_off,
+                          ColsI32{A->sl_col}, vals, c, L.d, t, f, W.g, L.gn, box,
+                          ctx->partials);
+            prof_end(ctx);
+            S.spmvs++;
+            S.search_trials++;
+            S.bytes_moved += b_trial;
+            nn_status r2 = host_reduce(ctx, n, 3, kTrialOps, red);
+            gs = red[0];
+            sks = red[1];
+            return r2;
+        };
+        double t, gscale, gs, sks;
+        if (bmin >= 1.0) {
+            if ((rc = trial(1.0, gs, sks)) != NN_OK) return finish(rc);
+            if (!(sks > 0.0))
+                return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature along the direction"));
+            t = std::min(-gs / sks, bmin);
+            gscale = t;
+        } else {
+            t = 1.0;
+            gscale = 1.0;
+            int k = 0;
+            for (;; k++) {
+                if ((rc = trial(t, gs, sks)) != NN_OK) return finish(rc);
+                if (gs < 0.0 && gs + 0.5 * sks <= kLmMu * gs) break;
+                t *= 0.5;
+                if (t <= bmin || k + 1 >= kLmMaxTrials) {
+                    // exact step on the segment before the first crossing
+                    t = bmin;
+                    if ((rc = trial(t, gs, sks)) != NN_OK) return finish(rc);
+                    if (!(sks > 0.0))
+                        return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature along the direction"));
+                    gscale = std::min(-gs / sks, 1.0);
+                    t *= gscale;
+                    break;
+                }
+            }
+        }
+        // ---- 5. step
+        prof_begin(ctx, KC_OTHER, 56.0 * n);
+        kl_step<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, L.d, t, W.g, L.gn, gscale, L.S, L.cap,
+                                                  (LmState *)L.state, box);
+        prof_end(ctx);
+        S.bytes_moved += 56.0 * n;
+        fresh = gscale == 1.0;
+        since_fresh = fresh ? 0 : since_fresh + 1;
+        if (since_fresh >= kLmRefresh) {
+            if ((rc = refresh(conv)) != NN_OK) return finish(rc);
+            fresh = true;
+            since_fresh = 0;
+        }
+        if (o->verbose)
+            std::fprintf(stderr, "nnqp blmvm %5d |pg|/|f| %.3e pairs %d gamma %.3g crossing %.3g step %.3g\n",
+                         it, rel, H.count, H.gamma, bmin, t);
+    }
+    // final report from a fresh gradient
+    if ((rc = refresh(conv)) != NN_OK) return finish(rc);
+    if (result == NN_OK && !conv) result = NN_EMAXIT;
+    if (result == NN_OK) ctx->err.clear();
+    return finish(result);
+}
+
+}  // namespace nnqp

@@ -67,6 +67,16 @@ struct Workspace {
     uint8_t *mask = nullptr;
 };
 
+// Buffers of the BLMVM solver (blmvm.hip), kept with the context.
+struct LmWork {
+    int64_t cap = 0;   // length of every vector
+    int m = 0;         // pair slots
+    double *S = nullptr, *Y = nullptr;   // [m][cap]: steps s and projected-gradient differences y
+    double *pg = nullptr, *d = nullptr, *gn = nullptr;
+    double *part = nullptr;              // [value][kMaxBlocks] partials of the pair pass
+    void *state = nullptr, *h_state = nullptr;   // device state and its pinned mirror
+};
+
 // Matrix values used by a kernel: float32 when v32 is set, else float64.
 struct Vals {
     const double *v64 = nullptr;
@@ -126,6 +136,7 @@ struct nn_ctx {
     nnqp::DevScalars *scal = nullptr;
     nnqp::DevScalars *h_scal = nullptr;  // pinned mirror
     nnqp::Workspace ws;
+    nnqp::LmWork lm;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool prof = false;
     int prof_mask = 0;         // classes timed while prof is on
@@ -233,6 +244,11 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                      uint8_t *active, nn_stats *st);
 
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);
+
+// The same problem by BLMVM (blmvm.hip); vals are float64 values of A.
+nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *f,
+                     const nn_opts *o, double *c, uint8_t *active, nn_stats *st);
+void lm_release(nn_ctx *ctx);
 
 // Unconstrained Galerkin solve K c = f by Jacobi-PCG from c = 0 (solver.hip).
 nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const nn_opts *o,

@@ -1,0 +1,261 @@
+// Device-side building blocks shared by the row-parallel kernels of
+// kernels.hip and blmvm.hip: fixed-order block reductions into per-block
+// partials, the slice walkers over the 64-row sliced-ELL layout, and the
+// projection on the bounds.  Header-only (templates and inline functions).
+#pragma once
+
+#include <cmath>
+
+#include "nnqp_internal.hpp"
+
+namespace nnqp {
+
+// ---------------------------------------------------------------- reductions
+template <uint32_t OPS>
+__device__ __forceinline__ constexpr int op_of(int k)
+{
+    return (int)((OPS >> (2 * k)) & 3u);
+}
+
+#define OPS2(a, b) ((uint32_t)(a) | ((uint32_t)(b) << 2))
+#define OPS3(a, b, c) (OPS2(a, b) | ((uint32_t)(c) << 4))
+#define OPS4(a, b, c, d) (OPS3(a, b, c) | ((uint32_t)(d) << 6))
+#define OPS5(a, b, c, d, e) (OPS4(a, b, c, d) | ((uint32_t)(e) << 8))
+
+__device__ __forceinline__ double red_comb(int op, double a, double b)
+{
+    return op == OP_SUM ? a + b : (op == OP_MIN ? fmin(a, b) : fmax(a, b));
+}
+
+template <uint32_t OPS, int NV>
+__device__ __forceinline__ void red_init(double (&a)[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        const int op = op_of<OPS>(k);
+        a[k] = op == OP_SUM ? 0.0 : (op == OP_MIN ? INFINITY : -INFINITY);
+    }
+}
+
+template <uint32_t OPS, int NV>
+__device__ __forceinline__ void wave_red(double (&a)[NV])
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; k++) a[k] = red_comb(op_of<OPS>(k), a[k], __shfl_xor(a[k], o, 64));
+}
+
+// Block-wide combination (waves in order) of a[]; every thread gets the block
+// total.  Thread k combines value k across the waves, so the combine costs a
+// handful of registers instead of one per wave and value.
+template <uint32_t OPS, int NV>
+__device__ __forceinline__ void block_red(double (&a)[NV], double (*sh)[NV + 1])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_red<OPS, NV>(a);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; k++) sh[wid][k] = a[k];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x;
+        const int op = (int)((OPS >> (2 * k)) & 3u);
+        double v = sh[0][k];
+#pragma nounroll
+        for (int w = 1; w < kWaves; w++) v = red_comb(op, v, sh[w][k]);
+        sh[kWaves][k] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; k++) a[k] = sh[kWaves][k];
+}
+
+__device__ __forceinline__ double *slot_ptr(double *partials, int s)
+{
+    return partials + (size_t)s * kMaxRed * kMaxBlocks;
+}
+
+// Store this block's total of a[] as its partial: slot[k * kMaxBlocks + block].
+template <uint32_t OPS, int NV>
+__device__ __forceinline__ void block_partial(double (&a)[NV], double *slot)
+{
+    __shared__ double sh[kWaves + 1][NV + 1];
+    block_red<OPS, NV>(a, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; k++) slot[k * kMaxBlocks + blockIdx.x] = a[k];
+}
+
+// Combine the partials of `nb` blocks left in `slot` by the previous kernel:
+// every block runs the same fixed-order combination and gets the same bits.
+template <uint32_t OPS, int NV>
+__device__ __forceinline__ void combine_partials(const double *slot, int nb, double (&a)[NV])
+{
+    __shared__ double sh[kWaves + 1][NV + 1];
+    red_init<OPS, NV>(a);
+    for (int b = threadIdx.x; b < nb; b += kBlock)
+#pragma unroll
+        for (int k = 0; k < NV; k++) a[k] = red_comb(op_of<OPS>(k), a[k], slot[k * kMaxBlocks + b]);
+    block_red<OPS, NV>(a, sh);
+}
+
+// ---------------------------------------------------------------- slice walkers
+// Calls body(i, act) for the row i = 64 s + lane of every slice s this
+// wavefront owns; act = i < n.  The loop trip count is uniform in a wavefront.
+template <class Body>
+__device__ __forceinline__ void for_rows(const Part &P, Body body)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = P.nb * kWaves;
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += nw) {
+        const int i = s * kSlice + lane;
+        body(i, i < P.n);
+    }
+}
+
+// Column readers of the sliced-ELL entries (entry e of the slice holding row).
+// Float32-value passes read int16 offsets from the row when the pattern
+// allows (|col - row| <= 32767); float64-value passes, and patterns with
+// wider offsets, read int32 columns.
+struct ColsI32 {
+    const int *c;
+    __device__ __forceinline__ int operator()(int e, int) const { return c[e]; }
+};
+struct ColsD16 {
+    const short *d;
+    __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
+};
+
+// Matrix values are read once per pass.  Float64 values are loaded with the
+// non-temporal hint, which keeps the value stream from displacing the
+// gathered vector in the caches (measured on the 128^3 pattern: the CG matrix
+// pass 97 -> 80 us); for float32 values the hint is slower, so they load
+// normally.
+__device__ __forceinline__ double ld_val(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_val(const float *p) { return *p; }
+
+// Sliced-ELL product row by row: for each owned row i with active(i), the sum
+// over the row's entries k = 0..w-1 (column order) of val * x(col), then
+// epi(i, sum, pre(i)).  Padding entries have value 0 and column i.
+// The SpMV passes are latency-bound (each slice is a chain: offsets ->
+// indices/values -> gathers -> own-row data -> stores), so a wavefront keeps
+// NS slices in flight at once, issues the slice offsets and the own-row loads
+// of pre() before any gather, and loads entries eight at a time (all eight
+// before their gathers, which keeps the kernels under 64 VGPRs).  Slices wider
+// than WMAX finish in a plain loop.
+#ifndef NNQP_SLICES_IN_FLIGHT
+#define NNQP_SLICES_IN_FLIGHT 1
+#endif
+#ifndef NNQP_LOAD_PHASE
+#define NNQP_LOAD_PHASE 8
+#endif
+template <int WMAX, class VT, class Cols, class Act, class Pre, class X, class Epi>
+__device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__ so, Cols sc,
+                                          const VT *__restrict__ sv, Act active, Pre pre, X x,
+                                          Epi epi)
+{
+    constexpr int NS = NNQP_SLICES_IN_FLIGHT;
+    using PV = decltype(pre(0));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = P.nb * kWaves;
+    for (int s0 = blockIdx.x * kWaves + wid; s0 < P.nslices; s0 += NS * nw) {
+        int off[NS], w[NS], row[NS];
+        bool act[NS];
+        PV pv[NS];
+#pragma unroll
+        for (int t = 0; t < NS; t++) {
+            const int s = s0 + t * nw;
+            const bool has = s < P.nslices;
+            off[t] = has ? so[s] : 0;
+            w[t] = has ? (so[s + 1] - off[t]) >> 6 : 0;   // slice width (uniform in the wave)
+            row[t] = s * kSlice + lane;
+            act[t] = has && row[t] < P.n && active(row[t]);
+            pv[t] = act[t] ? pre(row[t]) : PV();
+        }
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < NS; t++) any = any || (__ballot(act[t]) != 0);
+        if (!any) continue;
+        // Every lane of a live slice loads and gathers under the wave-uniform
+        // test k < w: padding and inactive rows hold valid columns, so this
+        // stays in bounds, and their sums are discarded below.  Per-lane
+        // predication here would cost more issue slots than the bytes saved.
+        double acc[NS];
+#pragma unroll
+        for (int t = 0; t < NS; t++) acc[t] = 0.0;
+        constexpr int H = WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE;
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX; h0 += H) {
+            int cc[NS][H];
+            VT vv[NS][H];
+#pragma unroll
+            for (int t = 0; t < NS; t++)
+#pragma unroll
+                for (int k = 0; k < H; k++) {
+                    if (h0 + k < w[t]) {
+                        cc[t][k] = sc(off[t] + (h0 + k) * kSlice + lane, row[t]);
+                        vv[t][k] = ld_val(sv + off[t] + (h0 + k) * kSlice + lane);
+                    } else {
+                        cc[t][k] = 0;
+                        vv[t][k] = VT(0);
+                    }
+                }
+#pragma unroll
+            for (int t = 0; t < NS; t++)
+#pragma unroll
+                for (int k = 0; k < H; k++)
+                    if (h0 + k < w[t]) acc[t] += (double)vv[t][k] * x(cc[t][k]);
+        }
+#pragma unroll
+        for (int t = 0; t < NS; t++) {
+            for (int k = WMAX; k < w[t]; k++) {
+                const int e = off[t] + k * kSlice + lane;
+                acc[t] += (double)ld_val(sv + e) * x(sc(e, row[t]));
+            }
+            if (act[t]) epi(row[t], acc[t], pv[t]);
+        }
+    }
+}
+
+struct NoPre {
+    __device__ __forceinline__ int operator()(int) const { return 0; }
+};
+
+struct Two {
+    double a, b;
+};
+struct Three {
+    double a, b, c;
+};
+
+struct AllRows {
+    __device__ __forceinline__ bool operator()(int) const { return true; }
+};
+
+// projection on [lo, hi]; NaN maps to lo (for lo = 0 the result is +0.0)
+__device__ __forceinline__ double proj_box(double x, Box B)
+{
+    const double y = x > B.lo ? x : B.lo;
+    return y < B.hi ? y : B.hi;
+}
+
+// Launch KERNEL (a template over WM, the unrolled slice width; may be a
+// parenthesised template-id) with the instance that covers the widest slice
+// `wmax`; kBlock threads per block on ctx->stream.
+#define NN_DISPATCH_W(wmax, KERNEL, grid, ...)                                             \
+    do {                                                                                   \
+        if ((wmax) <= 8) {                                                                 \
+            constexpr int WM = 8;                                                          \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+        } else if ((wmax) <= 16) {                                                         \
+            constexpr int WM = 16;                                                         \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+        } else {                                                                           \
+            constexpr int WM = 32;                                                         \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+        }                                                                                  \
+    } while (0)
+
+}  // namespace nnqp

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libnnqp.so")
 
 NN_OK, NN_EINVAL, NN_ENONFINITE, NN_ENOTSPD, NN_EMAXIT, NN_EOOM, NN_EHIP, NN_EBUDGET = range(8)
 NN_FP64, NN_MIXED = 0, 1
+NN_TRON, NN_BLMVM = 0, 1
 NN_KCLASSES = 5
 NN_PROF_ALL = 0x1F
 KCLASS_NAMES = ("cg_spmv", "cg_update", "grad", "trial", "other")
@@ -50,7 +51,9 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("c0_mode", ctypes.c_int32),
                 ("c0_value", ctypes.c_double), ("delta0", ctypes.c_double),
                 ("cg_chunk", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("lower", ctypes.c_double), ("upper", ctypes.c_double)]
+                ("lower", ctypes.c_double), ("upper", ctypes.c_double),
+                ("method", ctypes.c_int32), ("lmm_vectors", ctypes.c_int32),
+                ("max_lm_its", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -780,3 +780,92 @@ def test_full_size_cube_hole_dmp(ctx):
     print(f"cube_hole_k14: n={S.n} kkt {k.r:.3e} outer {st['outer_its']} cg {st['cg_its']} "
           f"{st['seconds']:.3f} s; Galerkin {gst['seconds']:.3f} s, negative "
           f"{100 * gst['n_negative'] / S.n:.1f}%, min {gst['min_c']:.4g}, max {gst['max_c']:.4g}")
+
+
+# ---------------------------------------------------------------- BLMVM
+BLMVM_CASES = {
+    "square2d_64": lambda: W.config_small(),
+    "cube3d_21_ragged": lambda: W.cube3d(21),
+    "cube_hole_k2": lambda: W.cube_hole(2),
+    "square2d_64_capped": lambda: _capped(W.config_small(), 0.5),
+    "square2d_40_shifted": lambda: _shifted(W.square2d(40, theta=1.1, ratio=1e-2)),
+    "transient_field_20x18x9": lambda: W.config_transient3d(20, 18, 9, ell=3.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BLMVM_CASES))
+def test_blmvm_matches_oracle(ctx, name):
+    """The bounded limited-memory variable-metric method (the paper's second
+    TAO solver, Sec. 5.1) reaches the same unique minimiser as the oracle."""
+    from paper_1506_08435_amd import nnqp
+    p = BLMVM_CASES[name]()
+    lo, hi = p.bounds
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, lower=lo, upper=hi, method=nnqp.NN_BLMVM)
+    c, active = _np(c), _np(active)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13, lo=lo, hi=hi)
+    err = _check_box(S, c, active, ref.c, lo, hi)
+    k = oracle.kkt(S, c, lo=lo, hi=hi)
+    assert k.r <= 1.01e-12 + 4 * ref.floor
+    assert st["cg_its"] == 0 and st["outer_its"] > 0
+    print(f"{name}: n={S.n} err={err:.2e} kkt={k.r:.2e} its={st['outer_its']} "
+          f"trials={st['search_trials']} resets={st['refinements']} {st['seconds'] * 1e3:.1f} ms")
+
+
+def test_blmvm_memory_sizes_and_options(ctx):
+    from paper_1506_08435_amd import nnqp
+    p = W.cube3d(14)
+    K, F, _ = ctx.assemble(p)
+    ref = _np(ctx.solve_nonneg(K, F, tol=1e-12)[0]).copy()
+    for m in (1, 3, 8):
+        c, _, st = ctx.solve_nonneg(K, F, tol=1e-12, method=nnqp.NN_BLMVM, lmm_vectors=m)
+        assert np.abs(_np(c) - ref).max() <= 1e-8 * ref.max(), m
+    a = _np(ctx.solve_nonneg(K, F, tol=1e-10, method=nnqp.NN_BLMVM)[0]).copy()
+    b = _np(ctx.solve_nonneg(K, F, tol=1e-10, method=nnqp.NN_BLMVM)[0]).copy()
+    assert np.array_equal(a, b)                      # deterministic
+    for kw in ({"lmm_vectors": 0}, {"lmm_vectors": 9}, {"precision": nnqp.NN_MIXED},
+               {"method": 7}):
+        with pytest.raises(nnqp.NnError) as ei:
+            ctx.solve_nonneg(K, F, method=kw.pop("method", nnqp.NN_BLMVM), **kw)
+        assert ei.value.status == nnqp.NN_EINVAL
+    c, _, st = ctx.solve_nonneg(K, F, tol=1e-12, method=nnqp.NN_BLMVM, max_lm_its=5,
+                                allow_maxit=True)
+    assert st["status"] == nnqp.NN_EMAXIT and _np(c).min() >= 0.0
+    # f <= 0 with lower bound 0: exact zero, no iteration
+    q = W.square2d(12)
+    q.f_elem = -q.f_elem
+    K2, F2, _ = ctx.assemble(q)
+    c, act, st = ctx.solve_nonneg(K2, F2, method=nnqp.NN_BLMVM)
+    assert np.array_equal(_np(c), np.zeros(K2.n)) and _np(act).all()
+
+
+def test_blmvm_transient_steps_match_oracle(ctx):
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.config_transient3d(14, 12, 8, ell=2.0)
+    S = oracle.assemble(p, with_mass=True)
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    cref = np.zeros(S.n)
+    for step in range(3):
+        ctx.step_transient(K, 0.05, F, c, tol=1e-12, method=nnqp.NN_BLMVM)
+        cref = oracle.transient_step(S, 0.05, cref, tol=1e-13).c
+        err = np.abs(_np(c) - cref).max() / np.abs(cref).max()
+        assert err <= PARITY_TOL, (step, err)
+
+
+def test_full_size_cube128_blmvm(ctx):
+    """BLMVM on the 128^3 benchmark system at the metric tolerance, certified
+    by the oracle's KKT evaluation."""
+    from paper_1506_08435_amd import nnqp
+    p = W.config_cube128()
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-8, method=nnqp.NN_BLMVM)
+    c = _np(c)
+    assert c.min() >= 0.0
+    S = oracle.assemble(p)
+    k = oracle.kkt(S, c)
+    assert k.r <= 1e-8 * (1 + 1e-6), k.r
+    print(f"cube128 BLMVM: kkt {k.r:.3e} its {st['outer_its']} trials {st['search_trials']} "
+          f"resets {st['refinements']} {st['seconds']:.3f} s")
