@@ -188,6 +188,9 @@ def run_hole(args):
     gc, gst = gal[-1]
     over = int((gc > 1.0).sum().item())
     nn_med = sorted(x["seconds"] for x in stats)[len(stats) // 2]
+    gal_block = {"median_device_ms": round(g_med * 1e3, 3)}
+    blmvm = None if args.no_blmvm or prec != nnqp.NN_FP64 else \
+        run_blmvm(ctx, K, F, n, stats, gal_block, args, bounds=(0.0, 1.0))
     line = {
         "metric": "solved DOF/s at KKT tol 1e-8, bounds [0, 1]",
         "value": round(n * args.steps / wall, 1), "unit": "DOF/s", "n_gpus": 1,
@@ -214,6 +217,8 @@ def run_hole(args):
                      "pct_violating": round(100.0 * (gst["n_negative"] + over) / max(n, 1), 2),
                      "bounded_over_galerkin_time": round(nn_med / g_med, 3)},
     }
+    if blmvm is not None:
+        line["blmvm"] = blmvm
     print(json.dumps(line), flush=True)
 
 
@@ -416,6 +421,9 @@ def main():
     ap.add_argument("--no-galerkin", action="store_true",
                     help="skip the unconstrained Galerkin baseline solve (cube workload)")
     ap.add_argument("--galerkin-reps", type=int, default=3)
+    ap.add_argument("--no-blmvm", action="store_true",
+                    help="skip the BLMVM comparison solves (cube and hole workloads)")
+    ap.add_argument("--blmvm-reps", type=int, default=3)
     ap.add_argument("--no-triad", action="store_true",
                     help="skip the achievable-bandwidth (triad) reference")
     ap.add_argument("--nreq", type=int, default=32, help="requests of the serve workload")
@@ -511,6 +519,9 @@ def main():
     galerkin = None
     if not args.no_galerkin and prec == nnqp.NN_FP64:
         galerkin = run_galerkin(ctx, K, F, n, stats, args)
+    blmvm = None
+    if not args.no_blmvm and prec == nnqp.NN_FP64:
+        blmvm = run_blmvm(ctx, K, F, n, stats, galerkin, args)
 
     out = {
         "metric": "solved DOF/s at KKT tol 1e-8",
@@ -542,6 +553,8 @@ def main():
     }
     if galerkin is not None:
         out["galerkin"] = galerkin
+    if blmvm is not None:
+        out["blmvm"] = blmvm
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
     print(json.dumps(out), flush=True)
@@ -566,6 +579,28 @@ def run_galerkin(ctx, K, F, n, stats, args):
             "algorithmic_GBps": round(r["bytes_moved"] / r["seconds"] / 1e9, 1),
             "nonneg_over_galerkin_time": round(nn_med / g_med, 3),
             "nonneg_min_c": stats[-1]["min_c"]}
+
+
+def run_blmvm(ctx, K, F, n, stats, galerkin, args, bounds=(0.0, float("inf"))):
+    """The paper's second bound-constrained solver on the same system, to the
+    same tolerance: median time of a few solves, iterations, and its time
+    relative to TRON and to the Galerkin solve (the columns of Tables
+    Tab:S5_cube_times_mustang/wolf)."""
+    from paper_1506_08435_amd import nnqp
+    opts = nnqp.default_opts(tol=1e-8, method=nnqp.NN_BLMVM, lower=bounds[0], upper=bounds[1])
+    ctx.solve_nonneg(K, F, opts=opts)                 # warm-up
+    runs = [ctx.solve_nonneg(K, F, opts=opts)[2] for _ in range(args.blmvm_reps)]
+    med = sorted(r["seconds"] for r in runs)[len(runs) // 2]
+    nn_med = sorted(x["seconds"] for x in stats)[len(stats) // 2]
+    r = runs[-1]
+    out = {"median_device_ms": round(med * 1e3, 3), "iterations": r["outer_its"],
+           "line_search_trials": r["search_trials"], "memory_resets": r["refinements"],
+           "kkt_rel": r["kkt_rel"], "dof_per_s": round(n / med, 1),
+           "algorithmic_GBps": round(r["bytes_moved"] / r["seconds"] / 1e9, 1),
+           "blmvm_over_tron_time": round(med / nn_med, 3)}
+    if galerkin is not None:
+        out["blmvm_over_galerkin_time"] = round(med * 1e3 / galerkin["median_device_ms"], 3)
+    return out
 
 
 if __name__ == "__main__":

@@ -150,10 +150,12 @@ __global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double 
 {
     constexpr int NV = 4 * M + 3;
     __shared__ double t[NV];
-    for (int k = threadIdx.x; k < NV; k += 64) {
+    // block partials: lane-strided sums, then a butterfly (fixed order)
+    for (int k = 0; k < NV; k++) {
         double v = 0.0;
-        for (int b = 0; b < nb; b++) v += part[k * kMaxBlocks + b];
-        t[k] = v;
+        for (int b = threadIdx.x; b < nb; b += 64) v += part[k * kMaxBlocks + b];
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (threadIdx.x == 0) t[k] = v;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void kl_dir(Part P, const double *__restric
         a[1] += g[i] * di;
         a[2] += di * di;
     });
-    block_partial<kOps, 3>(a, slot_ptr(partials, SLOT_HOST));
+    block_partial<kOps, 3>(a, slot_ptr(partials, SLOT_Q));
 }
 
 // 4. trial: gathers c(t) = P(c + t d), writes gn = K c(t) - f; g.s, s.(gn - g), s.s
@@ -370,6 +372,8 @@ nn_status ensure_lm(nn_ctx *ctx, int64_t n, int m)
     if (e == hipSuccess) e = hipMalloc(&L.part, sizeof(double) * kLmNV * kMaxBlocks);
     if (e == hipSuccess) e = hipMalloc(&L.state, sizeof(LmState));
     if (e == hipSuccess) e = hipHostMalloc(&L.h_state, sizeof(LmState), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&L.h_dir, sizeof(double) * 3 * kMaxBlocks, hipHostMallocDefault);
     if (e != hipSuccess) {
         lm_release(ctx);
         return fail(ctx, NN_EOOM, std::string("BLMVM workspace: ") + hipGetErrorString(e));
@@ -393,6 +397,7 @@ void lm_release(nn_ctx *ctx)
         if (b) (void)hipFree(b);
     if (L.state) (void)hipFree(L.state);
     if (L.h_state) (void)hipHostFree(L.h_state);
+    if (L.h_dir) (void)hipHostFree(L.h_dir);
     L = LmWork();
 }
 
@@ -433,7 +438,6 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     const double b_trial = 4.0 * (nd + 1) + 12.0 * nnz + 40.0 * nd;
     static const int kInitOps[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
     static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
-    static const int kDirOps[3] = {OP_MIN, OP_SUM, OP_SUM};
     static const int kTrialOps[3] = {OP_SUM, OP_SUM, OP_SUM};
     double red[kMaxRed];
 
@@ -474,24 +478,60 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     if ((rc = refresh(conv)) != NN_OK) return finish(rc);
     if (conv) return finish(NN_OK);
     kl_state_init<<<1, 1, 0, ctx->stream>>>((LmState *)L.state, 1.0);
+    std::memset(L.h_state, 0, sizeof(LmState));
 
     const double vp = 8.0 * n;   // bytes of one vector pass
+    // Trial at step t along d: gathers P(c + t d), writes K c(t) - f; the
+    // partials (g.s, s.(gn - g), s.s) stay in the host slot.
+    auto launch_trial_t = [&](double t) {
+        prof_begin(ctx, KC_TRIAL, b_trial);
+        NN_DISPATCH_W(A->wmax, (kl_trial<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col},
+                      vals, c, L.d, t, f, W.g, L.gn, box, ctx->partials);
+        prof_end(ctx);
+        S.spmvs++;
+        S.search_trials++;
+        S.bytes_moved += b_trial;
+    };
+    auto read_trial = [&](double &gs, double &sks) -> nn_status {
+        nn_status r2 = host_reduce(ctx, n, 3, kTrialOps, red);
+        gs = red[0];
+        sks = red[1];
+        return r2;
+    };
+    // Direction pass (partials in SLOT_Q) and, without waiting for it, the
+    // first trial t = 1 (both line searches start there); one synchronisation
+    // returns the state, the direction summary and the trial.
+    double bmin = INFINITY, gd = 0.0, gs1 = 0.0, sks1 = 0.0;
+    auto direction_and_first_trial = [&]() -> nn_status {
+        const double live = std::min(H.count + 1, M);
+        prof_begin(ctx, KC_OTHER, vp * (4.0 + 2.0 * live));
+        NN_LM_DISPATCH(M, launch_dir, ctx, P, c, W.g, box);
+        prof_end(ctx);
+        launch_trial_t(1.0);
+        NN_HIP_TRY(ctx, hipMemcpyAsync(L.h_state, L.state, sizeof(LmState),
+                                       hipMemcpyDeviceToHost, ctx->stream));
+        const size_t cnt = (size_t)2 * kMaxBlocks + P.nb;
+        NN_HIP_TRY(ctx, hipMemcpyAsync(L.h_dir, slot_ptr(ctx->partials, SLOT_Q),
+                                       sizeof(double) * cnt, hipMemcpyDeviceToHost, ctx->stream));
+        nn_status r2 = read_trial(gs1, sks1);   // synchronises the stream
+        if (r2 != NN_OK) return r2;
+        bmin = INFINITY;
+        gd = 0.0;
+        for (int b = 0; b < P.nb; b++) bmin = std::fmin(bmin, L.h_dir[b]);
+        for (int b = 0; b < P.nb; b++) gd += L.h_dir[kMaxBlocks + b];
+        return NN_OK;
+    };
     bool fresh = true;
     int since_fresh = 0;
     nn_status result = NN_EMAXIT;
     for (int it = 0;; it++) {
-        // ---- 1-3. pairs, coefficients, direction
+        // ---- 1-3. pairs, coefficients, direction (+ first trial)
         const double live = std::min(it, M);
         prof_begin(ctx, KC_OTHER, vp * (5.0 + 2.0 * live));
         NN_LM_DISPATCH(M, launch_pairs_coef, ctx, P, c, W.g, box);
         prof_end(ctx);
-        prof_begin(ctx, KC_OTHER, vp * (4.0 + 2.0 * live));
-        NN_LM_DISPATCH(M, launch_dir, ctx, P, c, W.g, box);
-        prof_end(ctx);
         S.bytes_moved += vp * (9.0 + 4.0 * live);
-        NN_HIP_TRY(ctx, hipMemcpyAsync(L.h_state, L.state, sizeof(LmState), hipMemcpyDeviceToHost,
-                                       ctx->stream));
-        if ((rc = host_reduce(ctx, n, 3, kDirOps, red)) != NN_OK) return finish(rc);
+        if ((rc = direction_and_first_trial()) != NN_OK) return finish(rc);
         if (H.nonfinite != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite iterate"));
         S.outer_its = it;
         const double rel = std::sqrt(H.pg2) / normf;
@@ -514,40 +554,21 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             fail(ctx, NN_EMAXIT, "BLMVM iteration cap reached");
             break;
         }
-        double bmin = red[0], gd = red[1];
         if (!(gd < 0.0)) {
             // not a descent direction: forget the pairs, d = -gamma pg
             kl_forget<<<1, 1, 0, ctx->stream>>>((LmState *)L.state);
             NN_LM_DISPATCH(M, launch_coef, ctx, P);
-            NN_LM_DISPATCH(M, launch_dir, ctx, P, c, W.g, box);
             S.bytes_moved += vp * 4.0;
             S.refinements++;   // memory resets
-            if ((rc = host_reduce(ctx, n, 3, kDirOps, red)) != NN_OK) return finish(rc);
-            bmin = red[0];
-            gd = red[1];
+            if ((rc = direction_and_first_trial()) != NN_OK) return finish(rc);
             if (!(gd < 0.0)) {
                 fail(ctx, NN_EMAXIT, "no descent direction above the tolerance (rounding floor)");
                 break;
             }
         }
-        // ---- 4. line search
-        auto trial = [&](double t, double &gs, double &sks) -> nn_status {
-            prof_begin(ctx, KC_TRIAL, b_trial);
-            NN_DISPATCH_W(A->wmax, (kl_trial<WM, ColsI32>), P.nb, P, A->sl_off,
-                          ColsI32{A->sl_col}, vals, c, L.d, t, f, W.g, L.gn, box,
-                          ctx->partials);
-            prof_end(ctx);
-            S.spmvs++;
-            S.search_trials++;
-            S.bytes_moved += b_trial;
-            nn_status r2 = host_reduce(ctx, n, 3, kTrialOps, red);
-            gs = red[0];
-            sks = red[1];
-            return r2;
-        };
-        double t, gscale, gs, sks;
+        // ---- 4. line search (the trial at t = 1 is in gs1, sks1)
+        double t, gscale, gs = gs1, sks = sks1;
         if (bmin >= 1.0) {
-            if ((rc = trial(1.0, gs, sks)) != NN_OK) return finish(rc);
             if (!(sks > 0.0))
                 return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature along the direction"));
             t = std::min(-gs / sks, bmin);
@@ -555,21 +576,22 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         } else {
             t = 1.0;
             gscale = 1.0;
-            int k = 0;
-            for (;; k++) {
-                if ((rc = trial(t, gs, sks)) != NN_OK) return finish(rc);
+            for (int k = 0;; k++) {
                 if (gs < 0.0 && gs + 0.5 * sks <= kLmMu * gs) break;
                 t *= 0.5;
                 if (t <= bmin || k + 1 >= kLmMaxTrials) {
                     // exact step on the segment before the first crossing
                     t = bmin;
-                    if ((rc = trial(t, gs, sks)) != NN_OK) return finish(rc);
+                    launch_trial_t(t);
+                    if ((rc = read_trial(gs, sks)) != NN_OK) return finish(rc);
                     if (!(sks > 0.0))
                         return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature along the direction"));
                     gscale = std::min(-gs / sks, 1.0);
                     t *= gscale;
                     break;
                 }
+                launch_trial_t(t);
+                if ((rc = read_trial(gs, sks)) != NN_OK) return finish(rc);
             }
         }
         // ---- 5. step

@@ -72,7 +72,7 @@ __device__ __forceinline__ void block_red(double (&a)[NV], double (*sh)[NV + 1])
     for (int k = 0; k < NV; k++) a[k] = sh[kWaves][k];
 }
 
-__device__ __forceinline__ double *slot_ptr(double *partials, int s)
+__host__ __device__ __forceinline__ double *slot_ptr(double *partials, int s)
 {
     return partials + (size_t)s * kMaxRed * kMaxBlocks;
 }
