@@ -63,6 +63,8 @@ struct LmState {
     double yy[kLmMax][kLmMax];   // y_a . y_b by slot
     double sc[kLmMax];           // coefficient of s_slot in H pg
     double yc[kLmMax];           // coefficient of y_slot in H pg
+    double bmin, gd;             // direction: first bound crossing, g.d
+    double gs, sks;              // trial at t = 1: g.s, s.(gn - g)
 };
 
 // slot j is live in the pair pass: a stored pair, or the pair being formed
@@ -144,79 +146,133 @@ __global__ __launch_bounds__(kBlock) void kl_pairs(Part P, const double *__restr
     block_sums<NV>(a, part);
 }
 
-// 2. coefficient kernel: one wavefront; thread 0 does the small algebra
+// 2. coefficient kernel: one wavefront.  The lanes combine the block
+// partials (lane-strided sums, then a butterfly: fixed order) and stage the
+// S'Y and Y'Y tables in LDS; lane 0 does the small algebra.
 template <int M>
 __global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double *part)
 {
     constexpr int NV = 4 * M + 3;
     __shared__ double t[NV];
-    // block partials: lane-strided sums, then a butterfly (fixed order)
-    for (int k = 0; k < NV; k++) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nb; b += 64) v += part[k * kMaxBlocks + b];
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (threadIdx.x == 0) t[k] = v;
+    __shared__ double sy[M][M], yy[M][M];
+    const int lane = threadIdx.x;
+    {
+        double acc[NV];
+#pragma unroll
+        for (int k = 0; k < NV; k++) acc[k] = 0.0;
+        for (int b = lane; b < nb; b += 64)
+#pragma unroll
+            for (int k = 0; k < NV; k++) acc[k] += part[k * kMaxBlocks + b];
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            double v = acc[k];
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) t[k] = v;
+        }
+    }
+    for (int e = lane; e < M * M; e += 64) {
+        sy[e / M][e % M] = st->sy[e / M][e % M];
+        yy[e / M][e % M] = st->yy[e / M][e % M];
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    int count = st->count, head = st->head;
-    st->pg2 = t[0];
-    st->nonfinite = t[1];
-    if (st->pending) {
-        const double sy = t[2 + 2 * M + head], yy = t[2 + 3 * M + head], ss = t[2 + 4 * M];
-        const bool ok = isfinite(sy) && isfinite(yy) && yy > 0.0 &&
-                        sy > kLmCurv * sqrt(ss) * sqrt(yy);
-        if (ok) {
-            // column `head` of S'Y and Y'Y against every pair that stays
-            for (int j = 0; j < M; j++) {
-                if (!lm_live(j, M, count, head, 1)) continue;
-                st->sy[j][head] = t[2 + 2 * M + j];
-                st->yy[j][head] = t[2 + 3 * M + j];
-                st->yy[head][j] = t[2 + 3 * M + j];
+    if (lane == 0) {
+        int count = st->count, head = st->head;
+        double gam = st->gamma;
+        st->pg2 = t[0];
+        st->nonfinite = t[1];
+        if (st->pending) {
+            const double sny = t[2 + 2 * M + head], yny = t[2 + 3 * M + head], ss = t[2 + 4 * M];
+            const bool ok = isfinite(sny) && isfinite(yny) && yny > 0.0 &&
+                            sny > kLmCurv * sqrt(ss) * sqrt(yny);
+            if (ok) {
+                // column `head` of S'Y and Y'Y against every pair that stays
+                for (int j = 0; j < M; j++) {
+                    if (!lm_live(j, M, count, head, 1)) continue;
+                    sy[j][head] = t[2 + 2 * M + j];
+                    yy[j][head] = t[2 + 3 * M + j];
+                    yy[head][j] = t[2 + 3 * M + j];
+                }
+                count = count < M ? count + 1 : M;
+                head = (head + 1) % M;
+                gam = sny / yny;
+                st->accepted++;
+            } else {
+                if (count == M) count = M - 1;   // its oldest pair was overwritten
+                st->rejected++;
             }
-            count = count < M ? count + 1 : M;
-            head = (head + 1) % M;
-            st->gamma = sy / yy;
-            st->accepted++;
-        } else {
-            if (count == M) count = M - 1;   // its oldest pair was overwritten
-            st->rejected++;
+            st->pending = 0;
         }
-        st->pending = 0;
+        st->count = count;
+        st->head = head;
+        st->gamma = gam;
+        // compact-form coefficients over the pairs, oldest first
+        int sl[M];
+        double u[M], w[M], p[M], z[M], tp[M];
+        for (int k = 0; k < count; k++) {
+            sl[k] = (head - count + k + 2 * M) % M;
+            u[k] = t[2 + sl[k]];
+            w[k] = t[2 + M + sl[k]];
+        }
+        for (int a = count - 1; a >= 0; a--) {
+            double v = u[a];
+            for (int b = a + 1; b < count; b++) v -= sy[sl[a]][sl[b]] * p[b];
+            p[a] = v / sy[sl[a]][sl[a]];
+        }
+        for (int a = 0; a < count; a++) {
+            double v = sy[sl[a]][sl[a]] * p[a] - gam * w[a];
+            for (int b = 0; b < count; b++) v += gam * yy[sl[a]][sl[b]] * p[b];
+            z[a] = v;
+        }
+        for (int a = 0; a < count; a++) {
+            double v = z[a];
+            for (int b = 0; b < a; b++) v -= sy[sl[b]][sl[a]] * tp[b];
+            tp[a] = v / sy[sl[a]][sl[a]];
+        }
+        double sc[M], yc[M];
+        for (int j = 0; j < M; j++) {
+            sc[j] = 0.0;
+            yc[j] = 0.0;
+        }
+        for (int a = 0; a < count; a++) {
+            sc[sl[a]] = tp[a];
+            yc[sl[a]] = -gam * p[a];
+        }
+        for (int j = 0; j < M; j++) {
+            st->sc[j] = sc[j];
+            st->yc[j] = yc[j];
+        }
     }
-    st->count = count;
-    st->head = head;
-    // compact-form coefficients over the pairs, oldest first
-    int sl[M];
-    double u[M], w[M], p[M], z[M], tp[M];
-    for (int k = 0; k < count; k++) {
-        sl[k] = (head - count + k + 2 * M) % M;
-        u[k] = t[2 + sl[k]];
-        w[k] = t[2 + M + sl[k]];
+    __syncthreads();
+    for (int e = lane; e < M * M; e += 64) {
+        st->sy[e / M][e % M] = sy[e / M][e % M];
+        st->yy[e / M][e % M] = yy[e / M][e % M];
     }
-    const double gam = st->gamma;
-    for (int a = count - 1; a >= 0; a--) {
-        double v = u[a];
-        for (int b = a + 1; b < count; b++) v -= st->sy[sl[a]][sl[b]] * p[b];
-        p[a] = v / st->sy[sl[a]][sl[a]];
+}
+
+// Line-search summary for the host: combines the direction pass partials
+// (SLOT_Q: first crossing, g.d) and the trial's (host slot: g.s, s.(gn - g))
+// into the state, so one small copy returns everything.
+__global__ __launch_bounds__(64) void kl_summary(int nb, LmState *st, double *partials)
+{
+    const double *q = slot_ptr(partials, SLOT_Q), *h = slot_ptr(partials, SLOT_HOST);
+    double bm = INFINITY, gd = 0.0, gs = 0.0, sks = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64) {
+        bm = fmin(bm, q[b]);
+        gd += q[kMaxBlocks + b];
+        gs += h[b];
+        sks += h[kMaxBlocks + b];
     }
-    for (int a = 0; a < count; a++) {
-        double v = st->sy[sl[a]][sl[a]] * p[a] - gam * w[a];
-        for (int b = 0; b < count; b++) v += gam * st->yy[sl[a]][sl[b]] * p[b];
-        z[a] = v;
+    for (int o = 32; o >= 1; o >>= 1) {
+        bm = fmin(bm, __shfl_xor(bm, o, 64));
+        gd += __shfl_xor(gd, o, 64);
+        gs += __shfl_xor(gs, o, 64);
+        sks += __shfl_xor(sks, o, 64);
     }
-    for (int a = 0; a < count; a++) {
-        double v = z[a];
-        for (int b = 0; b < a; b++) v -= st->sy[sl[b]][sl[a]] * tp[b];
-        tp[a] = v / st->sy[sl[a]][sl[a]];
-    }
-    for (int j = 0; j < M; j++) {
-        st->sc[j] = 0.0;
-        st->yc[j] = 0.0;
-    }
-    for (int a = 0; a < count; a++) {
-        st->sc[sl[a]] = tp[a];
-        st->yc[sl[a]] = -gam * p[a];
+    if (threadIdx.x == 0) {
+        st->bmin = bm;
+        st->gd = gd;
+        st->gs = gs;
+        st->sks = sks;
     }
 }
 
@@ -323,19 +379,26 @@ __global__ __launch_bounds__(kBlock) void kl_step(Part P, double *__restrict__ c
     if (blockIdx.x == 0 && threadIdx.x == 0) st->pending = 1;
 }
 
+// The pair pass holds 4M + 3 accumulators per lane (95 VGPRs at M = 5), so
+// one 1024-thread block fits a CU: it runs one block per CU and walks more
+// slices per wavefront instead of queueing a second round of blocks.
+constexpr int kPairBlocks = 256;
+
 template <int M>
 void launch_pairs_coef(nn_ctx *ctx, const Part &P, const double *c, const double *g, Box B)
 {
     LmWork &L = ctx->lm;
-    kl_pairs<M><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, g, L.pg, L.S, L.Y, L.cap,
-                                                  (const LmState *)L.state, B, L.part);
-    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P.nb, (LmState *)L.state, L.part);
+    const Part P1 = make_part(P.n, kPairBlocks);
+    kl_pairs<M><<<P1.nb, kBlock, 0, ctx->stream>>>(P1, c, g, L.pg, L.S, L.Y, L.cap,
+                                                   (const LmState *)L.state, B, L.part);
+    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P1.nb, (LmState *)L.state, L.part);
 }
 
 template <int M>
 void launch_coef(nn_ctx *ctx, const Part &P)
 {
-    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P.nb, (LmState *)ctx->lm.state, ctx->lm.part);
+    const Part P1 = make_part(P.n, kPairBlocks);
+    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P1.nb, (LmState *)ctx->lm.state, ctx->lm.part);
 }
 
 template <int M>
@@ -372,8 +435,6 @@ nn_status ensure_lm(nn_ctx *ctx, int64_t n, int m)
     if (e == hipSuccess) e = hipMalloc(&L.part, sizeof(double) * kLmNV * kMaxBlocks);
     if (e == hipSuccess) e = hipMalloc(&L.state, sizeof(LmState));
     if (e == hipSuccess) e = hipHostMalloc(&L.h_state, sizeof(LmState), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&L.h_dir, sizeof(double) * 3 * kMaxBlocks, hipHostMallocDefault);
     if (e != hipSuccess) {
         lm_release(ctx);
         return fail(ctx, NN_EOOM, std::string("BLMVM workspace: ") + hipGetErrorString(e));
@@ -397,7 +458,6 @@ void lm_release(nn_ctx *ctx)
         if (b) (void)hipFree(b);
     if (L.state) (void)hipFree(L.state);
     if (L.h_state) (void)hipHostFree(L.h_state);
-    if (L.h_dir) (void)hipHostFree(L.h_dir);
     L = LmWork();
 }
 
@@ -508,17 +568,14 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         NN_LM_DISPATCH(M, launch_dir, ctx, P, c, W.g, box);
         prof_end(ctx);
         launch_trial_t(1.0);
+        kl_summary<<<1, 64, 0, ctx->stream>>>(P.nb, (LmState *)L.state, ctx->partials);
         NN_HIP_TRY(ctx, hipMemcpyAsync(L.h_state, L.state, sizeof(LmState),
                                        hipMemcpyDeviceToHost, ctx->stream));
-        const size_t cnt = (size_t)2 * kMaxBlocks + P.nb;
-        NN_HIP_TRY(ctx, hipMemcpyAsync(L.h_dir, slot_ptr(ctx->partials, SLOT_Q),
-                                       sizeof(double) * cnt, hipMemcpyDeviceToHost, ctx->stream));
-        nn_status r2 = read_trial(gs1, sks1);   // synchronises the stream
-        if (r2 != NN_OK) return r2;
-        bmin = INFINITY;
-        gd = 0.0;
-        for (int b = 0; b < P.nb; b++) bmin = std::fmin(bmin, L.h_dir[b]);
-        for (int b = 0; b < P.nb; b++) gd += L.h_dir[kMaxBlocks + b];
+        NN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        bmin = H.bmin;
+        gd = H.gd;
+        gs1 = H.gs;
+        sks1 = H.sks;
         return NN_OK;
     };
     bool fresh = true;

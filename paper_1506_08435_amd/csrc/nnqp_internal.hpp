@@ -75,7 +75,6 @@ struct LmWork {
     double *pg = nullptr, *d = nullptr, *gn = nullptr;
     double *part = nullptr;              // [value][kMaxBlocks] partials of the pair pass
     void *state = nullptr, *h_state = nullptr;   // device state and its pinned mirror
-    double *h_dir = nullptr;             // pinned copy of the direction pass partials
 };
 
 // Matrix values used by a kernel: float32 when v32 is set, else float64.
