@@ -158,7 +158,7 @@ def run_hole(args):
     n = K.n
     prec = nnqp.NN_MIXED if args.precision == "mixed" else nnqp.NN_FP64
     opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
-                             lower=0.0, upper=1.0)
+                             lower=0.0, upper=1.0, precond_degree=args.precond_degree)
     c = torch.empty(n, dtype=torch.float64, device=ctx.device)
     act = torch.empty(n, dtype=torch.uint8, device=ctx.device)
     for _ in range(args.warmup):
@@ -203,7 +203,7 @@ def run_hole(args):
                                f"{K.nnz} nnz, c = 0 outside / 1 on the hole (lifted), f = 0, "
                                f"D = dispersion(v = (1,1,1), alpha_L = 1, alpha_T = 1e-3), "
                                f"bounds [0, 1], from c0 = 1e-8 to KKT tol 1e-8",
-                   "inner_rtol": args.inner_rtol},
+                   "inner_rtol": args.inner_rtol, "precond_degree": args.precond_degree},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "kernel": "k_cg_spmv", "launches": dom["count"],
@@ -234,7 +234,8 @@ def run_transient(args):
     out = {}
     for prec_name in ("fp64", "mixed"):
         prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
-        opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec)
+        opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
+                                 precond_degree=args.precond_degree)
         c = torch.zeros(n, dtype=torch.float64, device=ctx.device)
         ctx.step_transient(K, args.dt, F, c, opts=opts)          # warm-up (forms K~)
         c.zero_()
@@ -266,6 +267,8 @@ def run_transient(args):
             "workload": f"transient3d_{'x'.join(map(str, args.tdims))}: {n} free DOF, {K.nnz} nnz, "
                         f"D = exp(G) R diag(1,.1,1e-3) R^T (Gaussian random field, seed 1506), "
                         f"dt = {args.dt}, {args.tsteps} steps from c0 = 0, warm-started",
+            "precond": "Jacobi" if args.precond_degree <= 1 else
+                       f"Chebyshev-Jacobi degree {args.precond_degree}",
             "n_gpus": 1, **out}
     print(json.dumps(line), flush=True)
 
@@ -405,6 +408,8 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=0.5,
                     help="relative tolerance of each inner CG solve (does not change the minimiser)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precond-degree", type=int, default=1,
+                    help="inner CG preconditioner: 1 = Jacobi, k > 1 = Chebyshev of degree k")
     ap.add_argument("--cpu-n", type=int, default=64, help="cube side of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -480,7 +485,7 @@ def main():
     n = K.n
     prec = nnqp.NN_MIXED if args.precision == "mixed" else nnqp.NN_FP64
     opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, verbose=int(args.verbose),
-                             precision=prec)
+                             precision=prec, precond_degree=args.precond_degree)
     c = torch.empty(n, dtype=torch.float64, device=ctx.device)
     for _ in range(args.warmup):
         ctx.solve_nonneg(K, F, opts=opts, c=c)
@@ -540,7 +545,9 @@ def main():
                                f"{K.nnz} nnz, D = R diag(1,1e-2,1e-4) R^T, f = 1 on central cube, "
                                + ("FP64 plain solve" if prec == nnqp.NN_FP64 else "mixed-precision solve")
                                + " from c0 = 1e-8 to KKT tol 1e-8",
-                   "inner_rtol": args.inner_rtol, "solver": "TRON-style active-set Newton-CG"},
+                   "inner_rtol": args.inner_rtol, "solver": "TRON-style active-set Newton-CG",
+                   "precond": "Jacobi" if args.precond_degree <= 1 else
+                              f"Chebyshev-Jacobi degree {args.precond_degree}"},
         "roofline": roofline,
         "solve": {"median_device_ms": round(1e3 * sorted(x["seconds"] for x in stats)[len(stats) // 2], 3),
                   "outer_its": stats[-1]["outer_its"], "cg_its": stats[-1]["cg_its"],

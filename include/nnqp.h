@@ -108,7 +108,13 @@ typedef struct {
     int32_t method;       /* nn_method: NN_TRON (default) or NN_BLMVM */
     int32_t lmm_vectors;  /* BLMVM: stored (s, y) pairs, 1..8; default 5 (TAO's default) */
     int32_t max_lm_its;   /* BLMVM: iteration cap; default 20000 */
-    int32_t reserved;
+    int32_t precond_degree; /* preconditioner of the CG solves (TRON's inner CG, the
+                             Galerkin solve): 0 or 1 = Jacobi (default); k = 2..8 =
+                             Chebyshev polynomial of degree k in D^-1 A (the Chebyshev
+                             iteration with the Jacobi splitting on [lmax/30, lmax], lmax
+                             the Gershgorin bound): k matrix passes per CG iteration,
+                             fewer CG iterations.  The minimiser does not change.  The
+                             batched entry points take 0 or 1 only. */
 } nn_opts;
 
 /* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */

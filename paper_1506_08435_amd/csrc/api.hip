@@ -220,6 +220,12 @@ void nn_destroy(nn_ctx *ctx)
     for (float *v : fvecs)
         if (v) (void)hipFree(v);
     if (W.mask) (void)hipFree(W.mask);
+    double *cv[] = {W.cres, W.cdz[0], W.cdz[1]};
+    for (double *v : cv)
+        if (v) (void)hipFree(v);
+    float *cf[] = {W.cres32, W.cdz32[0], W.cdz32[1]};
+    for (float *v : cf)
+        if (v) (void)hipFree(v);
     lm_release(ctx);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->h_part) (void)hipHostFree(ctx->h_part);
@@ -449,6 +455,8 @@ static nn_status check_opts(nn_ctx *ctx, const nn_opts *o)
     if (!std::isfinite(o->lower) || std::isnan(o->upper) || !(o->upper > o->lower))
         return fail(ctx, NN_EINVAL, "bounds must satisfy lower finite, upper > lower");
     if (o->method != NN_TRON && o->method != NN_BLMVM) return fail(ctx, NN_EINVAL, "unknown method");
+    if (o->precond_degree < 0 || o->precond_degree > 8)
+        return fail(ctx, NN_EINVAL, "precond_degree must be in 0..8");
     if (o->method == NN_BLMVM) {
         if (o->lmm_vectors < 1 || o->lmm_vectors > 8)
             return fail(ctx, NN_EINVAL, "lmm_vectors must be in 1..8");
@@ -529,6 +537,8 @@ static nn_status check_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
     if (opts->lower != 0.0 || opts->upper != INFINITY)
         return fail(ctx, NN_EINVAL, "the batched solver takes the bounds [0, inf) only");
     if (opts->method != NN_TRON) return fail(ctx, NN_EINVAL, "the batched solver runs TRON only");
+    if (opts->precond_degree > 1)
+        return fail(ctx, NN_EINVAL, "the batched solver uses the Jacobi preconditioner only");
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int p = 0; p < nprob; p++) {
         if (!K[p]) return fail(ctx, NN_EINVAL, "null matrix in batch");

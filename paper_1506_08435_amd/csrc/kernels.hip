@@ -203,7 +203,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
     const double *__restrict__ c, double *__restrict__ g, const double *__restrict__ ks,
     uint8_t *__restrict__ mask, VV *__restrict__ dm, VV *__restrict__ r, VV *__restrict__ z,
     VV *__restrict__ p, VV *__restrict__ q, VV *__restrict__ w, double *partials, DevScalars *S,
-    Box B, int all_free)
+    Box B, int all_free, VV *__restrict__ cres, VV *__restrict__ cdz0, VV *__restrict__ cdz1,
+    double inv_theta)
 {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for_rows(P, [&](int i, bool act) {
@@ -214,7 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
         const bool fr = all_free || !((cv == B.lo && gi >= 0.0) || (cv == B.hi && gi <= 0.0));
         const VV dmi = fr ? (VV)(1.0 / diag[i]) : VV(0);
         const VV ri = fr ? (VV)(-gi) : VV(0);
-        const VV zi = dmi * ri;
+        // Jacobi z = dm r, or the first Chebyshev term dm r / theta
+        const VV zi = cres ? (VV)((double)dmi * (double)ri * inv_theta) : dmi * ri;
         mask[i] = fr ? 1 : 0;
         dm[i] = dmi;
         r[i] = ri;
@@ -222,6 +224,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
         p[i] = VV(0);
         q[i] = VV(0);
         w[i] = VV(0);
+        if (cres) {
+            cres[i] = ri;
+            cdz0[i] = zi;
+            cdz1[i] = VV(0);
+        }
         a[0] += (double)ri * (double)zi;
         a[1] += (double)ri * (double)ri;
         a[2] += fr ? 1.0 : 0.0;
@@ -291,7 +298,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restric
 // CG iteration j, vector update on free rows.
 // Prologue: p.q_j from SLOT_Q, alpha_j = r.z_j / p.q_j (r.z_j stored by the
 // matrix pass).  Body: w += alpha p, r -= alpha q, z = dm r; partials of
-// r.z_{j+1}, r.r_{j+1} into slot U[(j+1)%2].
+// r.z_{j+1}, r.r_{j+1} into slot U[(j+1)%2].  With the Chebyshev
+// preconditioner (cres set) z starts as dm r / theta, the Chebyshev residual
+// and first increment are set, and the last Chebyshev pass replaces r.z.
 template <class VV>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__restrict__ mask,
                                                       const VV *__restrict__ p,
@@ -299,7 +308,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__r
                                                       const VV *__restrict__ dm,
                                                       VV *__restrict__ w, VV *__restrict__ r,
                                                       VV *__restrict__ z, double *partials,
-                                                      DevScalars *S, int j)
+                                                      DevScalars *S, int j, VV *__restrict__ cres,
+                                                      VV *__restrict__ cdz0, double inv_theta)
 {
     if (S->done) return;
     double pqa[1];
@@ -317,15 +327,69 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__r
     for_rows(P, [&](int i, bool act) {
         if (!act || !mask[i]) return;
         const VV ri = (VV)((double)r[i] - alpha * (double)q[i]);
-        const VV zi = dm[i] * ri;
+        const VV zi = cres ? (VV)((double)dm[i] * (double)ri * inv_theta) : dm[i] * ri;
         w[i] = (VV)((double)w[i] + alpha * (double)p[i]);
         r[i] = ri;
         z[i] = zi;
+        if (cres) {
+            cres[i] = ri;
+            cdz0[i] = zi;
+        }
         a[0] += (double)ri * (double)zi;
         a[1] += (double)ri * (double)ri;
     });
     block_partial<kOpsU, 4>(a, slot_ptr(partials, ((j + 1) & 1) ? SLOT_U1 : SLOT_U0));
     if (blockIdx.x == 0 && threadIdx.x == 0) S->it = j + 1;
+}
+
+// One step of the Chebyshev iteration for A_FF z = r from z = 0 with the
+// Jacobi splitting (the polynomial preconditioner of the inner CG), on the
+// free rows: res -= A dzp (dzp gathered; zero off the face), dzn = ca dzp +
+// cb dm res, z += dzn.  The last step leaves r.z in value 0 of `slot` (the
+// slot whose r.r the update or set-up kernel wrote).
+template <int WMAX, class VT, class VV, class Cols>
+__global__ __launch_bounds__(kBlock) void k_cheb(Part P, const int *__restrict__ so, Cols sc,
+                                                 const VT *__restrict__ v,
+                                                 const uint8_t *__restrict__ mask,
+                                                 const VV *__restrict__ dm,
+                                                 const VV *__restrict__ r, VV *__restrict__ res,
+                                                 const VV *__restrict__ dzp, VV *__restrict__ dzn,
+                                                 VV *__restrict__ z, double ca, double cb,
+                                                 int last, int slot, double *partials,
+                                                 DevScalars *S)
+{
+    if (S->done) return;
+    double a[1] = {0.0};
+    sell_rows<WMAX>(P, so, sc, v, [&](int i) { return mask[i] != 0; },
+                    [&](int i) { return Three{(double)res[i], (double)dzp[i], (double)z[i]}; },
+                    [&](int jj) { return (double)dzp[jj]; }, [&](int i, double kd, Three x) {
+                        const double rn = x.a - kd;
+                        const double dn = ca * x.b + cb * (double)dm[i] * rn;
+                        const VV zn = (VV)(x.c + dn);
+                        res[i] = (VV)rn;
+                        dzn[i] = (VV)dn;
+                        z[i] = zn;
+                        a[0] += (double)r[i] * (double)zn;
+                    });
+    if (last) block_partial<OP_SUM, 1>(a, slot_ptr(partials, slot));
+}
+
+// Gershgorin bound of the spectrum of D^-1 A: max over rows of sum_j |a_ij| / a_ii
+// (an upper bound for every principal submatrix too).
+__global__ __launch_bounds__(kBlock) void k_gersh(Part P, const int *__restrict__ so,
+                                                  const double *__restrict__ v,
+                                                  const double *__restrict__ diag, double *partials)
+{
+    double a[1] = {0.0};
+    for_rows(P, [&](int i, bool act) {
+        if (!act) return;
+        const int s = i / kSlice, lane = i % kSlice;
+        const int off = so[s], w = (so[s + 1] - off) / kSlice;
+        double sum = 0.0;
+        for (int k = 0; k < w; k++) sum += fabs(v[off + k * kSlice + lane]);
+        a[0] = fmax(a[0], sum / diag[i]);
+    });
+    block_partial<OP_MAX, 1>(a, slot_ptr(partials, SLOT_HOST));
 }
 
 // Largest step along w before a free variable reaches a bound:
@@ -553,20 +617,51 @@ void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w)
 }
 
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32, Box B, bool all_free)
+                     double *g, const double *ks, bool f32, Box B, bool all_free,
+                     const Cheb *ch)
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
+    const double it = ch ? 1.0 / ch->theta : 0.0;
     if (f32)
-        k_cg_setup<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
-                                                            W.dm32, W.r32, W.z32, W.p32, W.q32,
-                                                            W.w32, ctx->partials, ctx->scal, B,
-                                                            all_free ? 1 : 0);
+        k_cg_setup<float><<<P.nb, kBlock, 0, ctx->stream>>>(
+            P, A->rowptr, diag, c, g, ks, W.mask, W.dm32, W.r32, W.z32, W.p32, W.q32, W.w32,
+            ctx->partials, ctx->scal, B, all_free ? 1 : 0, ch ? W.cres32 : nullptr,
+            ch ? W.cdz32[0] : nullptr, ch ? W.cdz32[1] : nullptr, it);
     else
-        k_cg_setup<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->rowptr, diag, c, g, ks, W.mask,
-                                                             W.dm, W.r, W.z, W.p0, W.q, W.w,
-                                                             ctx->partials, ctx->scal, B,
-                                                             all_free ? 1 : 0);
+        k_cg_setup<double><<<P.nb, kBlock, 0, ctx->stream>>>(
+            P, A->rowptr, diag, c, g, ks, W.mask, W.dm, W.r, W.z, W.p0, W.q, W.w, ctx->partials,
+            ctx->scal, B, all_free ? 1 : 0, ch ? W.cres : nullptr, ch ? W.cdz[0] : nullptr,
+            ch ? W.cdz[1] : nullptr, it);
+}
+
+void launch_cheb(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const Cheb &ch, int step,
+                 int slot)
+{
+    Part P = make_part(A->n);
+    Workspace &W = ctx->ws;
+    const double ca = ch.ca[step], cb = ch.cb[step];
+    const int last = step == ch.degree - 1 ? 1 : 0;
+    const int ip = (step - 1) & 1, in = step & 1;
+    if (V.v32 && A->sl_d16) {
+        NN_DISPATCH_W(A->wmax, (k_cheb<WM, float, float, ColsD16>), P.nb, P, A->sl_off,
+                      ColsD16{A->sl_d16}, V.v32, W.mask, W.dm32, W.r32, W.cres32, W.cdz32[ip],
+                      W.cdz32[in], W.z32, ca, cb, last, slot, ctx->partials, ctx->scal);
+    } else if (V.v32) {
+        NN_DISPATCH_W(A->wmax, (k_cheb<WM, float, float, ColsI32>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v32, W.mask, W.dm32, W.r32, W.cres32, W.cdz32[ip],
+                      W.cdz32[in], W.z32, ca, cb, last, slot, ctx->partials, ctx->scal);
+    } else {
+        NN_DISPATCH_W(A->wmax, (k_cheb<WM, double, double, ColsI32>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v64, W.mask, W.dm, W.r, W.cres, W.cdz[ip], W.cdz[in],
+                      W.z, ca, cb, last, slot, ctx->partials, ctx->scal);
+    }
+}
+
+void launch_gersh(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag)
+{
+    Part P = make_part(A->n);
+    k_gersh<<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, vals, diag, ctx->partials);
 }
 
 void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol)
@@ -588,16 +683,19 @@ void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int m
     }
 }
 
-void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32)
+void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32, const Cheb *ch)
 {
     Part P = make_part(n);
     Workspace &W = ctx->ws;
+    const double it = ch ? 1.0 / ch->theta : 0.0;
     if (f32)
-        k_cg_update<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, W.mask, W.p32, W.q32, W.dm32, W.w32,
-                                                             W.r32, W.z32, ctx->partials, ctx->scal, j);
+        k_cg_update<float><<<P.nb, kBlock, 0, ctx->stream>>>(
+            P, W.mask, W.p32, W.q32, W.dm32, W.w32, W.r32, W.z32, ctx->partials, ctx->scal, j,
+            ch ? W.cres32 : nullptr, ch ? W.cdz32[0] : nullptr, it);
     else
-        k_cg_update<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, W.mask, W.p0, W.q, W.dm, W.w, W.r,
-                                                              W.z, ctx->partials, ctx->scal, j);
+        k_cg_update<double><<<P.nb, kBlock, 0, ctx->stream>>>(
+            P, W.mask, W.p0, W.q, W.dm, W.w, W.r, W.z, ctx->partials, ctx->scal, j,
+            ch ? W.cres : nullptr, ch ? W.cdz[0] : nullptr, it);
 }
 
 void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g, Box B)

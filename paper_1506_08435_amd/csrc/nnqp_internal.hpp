@@ -65,6 +65,22 @@ struct Workspace {
     float *w32 = nullptr, *r32 = nullptr, *z32 = nullptr, *q32 = nullptr, *p32 = nullptr,
           *dm32 = nullptr;
     uint8_t *mask = nullptr;
+    // Chebyshev preconditioner vectors (allocated on first use): residual of
+    // the inner Chebyshev iteration and its two increments (ping-pong)
+    int64_t cheb_cap = 0;
+    double *cres = nullptr, *cdz[2] = {nullptr, nullptr};
+    float *cres32 = nullptr, *cdz32[2] = {nullptr, nullptr};
+};
+
+// Chebyshev polynomial preconditioner of degree `degree` for the inner CG:
+// z = q(D^-1 A) D^-1 r, the Chebyshev iteration for A z = r from z = 0 with
+// the Jacobi splitting on the interval [lmax / ratio, lmax], lmax the
+// Gershgorin bound of D^-1 A.  theta, delta: centre and half-width of the
+// interval; step i >= 1 forms dz_i = ca[i] dz_{i-1} + cb[i] D^-1 res_i.
+struct Cheb {
+    int degree = 1;
+    double theta = 1.0, delta = 0.0;
+    double ca[16] = {0}, cb[16] = {0};
 };
 
 // Buffers of the BLMVM solver (blmvm.hip), kept with the context.
@@ -200,7 +216,18 @@ void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t, Box B);
 // g >= 0, not at hi with g <= 0; every row when all_free); partials of r.z,
 // r.r, #free, nnz(free) in SLOT_U0; f32 selects the float32 CG vectors
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32, Box B, bool all_free);
+                     double *g, const double *ks, bool f32, Box B, bool all_free,
+                     const Cheb *ch = nullptr);
+// Chebyshev step `step` (1..degree-1) on the free rows; the last one writes
+// r.z into value 0 of partial slot `slot`
+void launch_cheb(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const Cheb &ch, int step,
+                 int slot);
+// [host] Gershgorin bound of D^-1 A (max)
+void launch_gersh(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag);
+// Chebyshev coefficients for `degree` on [lmax / ratio, lmax], and the vectors
+// it needs; degree <= 1 leaves ch->degree = 1 (plain Jacobi)
+nn_status cheb_prepare(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag,
+                       int degree, Cheb *ch);
 // [host] r = A c - f (not stored): |r|^2 sum, #nonfinite sum, max c max, min c min, #(c<0) sum
 void launch_resid(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
                   const double *f);
@@ -209,8 +236,8 @@ void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w);
 // CG iteration j: direction update + matrix pass (prologue: scalars from the
 // previous kernel's partials); float32 values and vectors when V.v32 is set
 void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol);
-// CG iteration j: vector update
-void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32);
+// CG iteration j: vector update (Chebyshev start terms when ch is given)
+void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32, const Cheb *ch = nullptr);
 // [host] first bound crossing along w: min over w<0 of (c-lo)/(-w) and over
 // w>0 of (hi-c)/w, min; g.w sum, w.w sum
 void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g, Box B);

@@ -48,6 +48,58 @@ struct Bytes {
 };
 }  // namespace
 
+// Chebyshev preconditioner set-up: lmax = Gershgorin bound of D^-1 A (valid
+// for every face, a principal submatrix), interval [lmax / 30, lmax], the
+// coefficients of the Chebyshev iteration (Saad, Iterative Methods for Sparse
+// Linear Systems, Sec. 12.3), and its work vectors.  The polynomial q with
+// z = q(D^-1 A) D^-1 r satisfies 1 - lambda q(lambda) = T_k(.)/T_k(sigma) in
+// (-1, 1) on (0, lmax], so q > 0 there and the preconditioner is SPD.
+nn_status cheb_prepare(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag,
+                       int degree, Cheb *ch)
+{
+    *ch = Cheb();
+    if (degree <= 1) return NN_OK;
+    constexpr double kRatio = 30.0;
+    Workspace &W = ctx->ws;
+    const int64_t n = A->n;
+    if (W.cheb_cap < n) {
+        double **dv[] = {&W.cres, &W.cdz[0], &W.cdz[1]};
+        float **fv[] = {&W.cres32, &W.cdz32[0], &W.cdz32[1]};
+        for (double **v : dv)
+            if (*v) (void)hipFree(*v), *v = nullptr;
+        for (float **v : fv)
+            if (*v) (void)hipFree(*v), *v = nullptr;
+        W.cheb_cap = 0;
+        for (double **v : dv)
+            if (hipMalloc(v, sizeof(double) * std::max<int64_t>(n, 1)) != hipSuccess)
+                return fail(ctx, NN_EOOM, "Chebyshev vectors");
+        for (float **v : fv)
+            if (hipMalloc(v, sizeof(float) * std::max<int64_t>(n, 1)) != hipSuccess)
+                return fail(ctx, NN_EOOM, "Chebyshev vectors");
+        W.cheb_cap = std::max<int64_t>(n, 1);
+    }
+    launch_gersh(ctx, A, vals, diag);
+    static const int kMaxOp[1] = {OP_MAX};
+    double lmax = 0.0;
+    nn_status rc = host_reduce(ctx, n, 1, kMaxOp, &lmax);
+    if (rc != NN_OK) return rc;
+    if (!(lmax > 0.0) || !std::isfinite(lmax))
+        return fail(ctx, NN_ENONFINITE, "no finite spectral bound for the Chebyshev preconditioner");
+    const double lmin = lmax / kRatio;
+    ch->degree = degree;
+    ch->theta = 0.5 * (lmax + lmin);
+    ch->delta = 0.5 * (lmax - lmin);
+    const double sigma = ch->theta / ch->delta;
+    double rho = 1.0 / sigma;
+    for (int i = 1; i < degree; i++) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        ch->ca[i] = rn * rho;
+        ch->cb[i] = 2.0 * rn / ch->delta;
+        rho = rn;
+    }
+    return NN_OK;
+}
+
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
                      const double *diag, const double *f, const nn_opts *o, double *c,
                      uint8_t *active, nn_stats *st)
@@ -122,6 +174,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         S.kkt_rel = 0.0;
         return finish(NN_OK);
     }
+
+    Cheb cheb;
+    if ((rc = cheb_prepare(ctx, A, vals, diag, o->precond_degree, &cheb)) != NN_OK)
+        return finish(rc);
+    const Cheb *chp = cheb.degree > 1 ? &cheb : nullptr;
+    const int csteps = cheb.degree - 1;   // Chebyshev passes per CG iteration
 
     double t_cauchy = 1.0;
     double delta = o->delta0 > 0.0 ? o->delta0 : INFINITY;
@@ -208,9 +266,10 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
 
         // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], mixed, box, false);
+        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], mixed, box, false, chp);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
+        for (int st = 1; st <= csteps; st++) launch_cheb(ctx, A, VS, cheb, st, SLOT_U0);
         int it_seen = 0, j_next = 0;
         for (;;) {
             const size_t mark = ctx->prof_live.size();
@@ -219,8 +278,14 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                 launch_cg_spmv(ctx, A, VS, j_next, o->max_cg, o->inner_rtol);
                 prof_end(ctx);
                 prof_begin(ctx, KC_CG_UPDATE, -1.0);
-                launch_cg_update(ctx, n, j_next, mixed);
+                launch_cg_update(ctx, n, j_next, mixed, chp);
                 prof_end(ctx);
+                const int slot = ((j_next + 1) & 1) ? SLOT_U1 : SLOT_U0;
+                for (int st = 1; st <= csteps; st++) {
+                    prof_begin(ctx, KC_OTHER, -1.0);
+                    launch_cheb(ctx, A, VS, cheb, st, slot);
+                    prof_end(ctx);
+                }
             }
             if ((rc = read_scalars(ctx)) != NN_OK) return rc;
             const int ran = H.it - it_seen;
@@ -229,15 +294,18 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             // matrix pass on the free rows (indices 4 or 2 B, values 8 or 4 B), z gathered,
             // p and q read and written; update: p, q, dm, w, r read, w, r, z written
             const double b_spmv = n + 4.0 * nf + (ib + vb) * nzf + 5.0 * vb * nf;
-            const double b_upd = n + 8.0 * vb * nf;
+            const double b_upd = n + 8.0 * vb * nf + (chp ? 2.0 * vb * nf : 0.0);
+            // Chebyshev pass: matrix on the free rows, dz gathered, res and z
+            // read and written, dzp, dm, r read, dzn written
+            const double b_cheb = n + 4.0 * nf + (ib + vb) * nzf + 8.0 * vb * nf;
             int seen[NN_KCLASSES] = {0};   // launches of each class in this chunk
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
-                P.valid = seen[P.cls]++ < ran;
-                P.bytes = P.cls == KC_CG_SPMV ? b_spmv : b_upd;
+                P.valid = seen[P.cls]++ < (P.cls == KC_OTHER ? ran * csteps : ran);
+                P.bytes = P.cls == KC_CG_SPMV ? b_spmv : (P.cls == KC_OTHER ? b_cheb : b_upd);
             }
-            S.bytes_moved += ran * (b_spmv + b_upd);
-            S.spmvs += ran;
+            S.bytes_moved += ran * (b_spmv + b_upd + csteps * b_cheb);
+            S.spmvs += ran * (1 + csteps);
             it_seen = H.it;
             if (H.done) break;
         }
@@ -348,6 +416,11 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
     constexpr int kMaxRestarts = 8;
     Vals VS;
     VS.v64 = A->val;
+    Cheb cheb;
+    if ((rc = cheb_prepare(ctx, A, A->val, A->diag, o->precond_degree, &cheb)) != NN_OK)
+        return finish(rc);
+    const Cheb *chp = cheb.degree > 1 ? &cheb : nullptr;
+    const int csteps = cheb.degree - 1;
     const int chunk = o->cg_chunk > 0 ? o->cg_chunk : 16;
     const double b_spmv = n + 4.0 * n + 12.0 * A->nnz + 40.0 * n;
     const double b_upd = n + 64.0 * n;
@@ -359,9 +432,10 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
         S.spmvs++;
         S.bytes_moved += B.spmv() + 16.0 * n;
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, A->diag, c, W.g, nullptr, false, unbounded, true);
+        launch_cg_setup(ctx, A, A->diag, c, W.g, nullptr, false, unbounded, true, chp);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
+        for (int st = 1; st <= csteps; st++) launch_cheb(ctx, A, VS, cheb, st, SLOT_U0);
         const double rtol = std::min(0.5, o->tol / rel);
         const int budget = o->max_cg - S.cg_its;
         int it_seen = 0, j_next = 0;
@@ -372,19 +446,26 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
                 launch_cg_spmv(ctx, A, VS, j_next, budget, rtol);
                 prof_end(ctx);
                 prof_begin(ctx, KC_CG_UPDATE, -1.0);
-                launch_cg_update(ctx, n, j_next, false);
+                launch_cg_update(ctx, n, j_next, false, chp);
                 prof_end(ctx);
+                const int slot = ((j_next + 1) & 1) ? SLOT_U1 : SLOT_U0;
+                for (int st = 1; st <= csteps; st++) {
+                    prof_begin(ctx, KC_OTHER, -1.0);
+                    launch_cheb(ctx, A, VS, cheb, st, slot);
+                    prof_end(ctx);
+                }
             }
             if ((rc = read_scalars(ctx)) != NN_OK) return rc;
             const int ran = H.it - it_seen;
+            const double b_cheb = n + 4.0 * n + 12.0 * A->nnz + 64.0 * n;
             int seen[NN_KCLASSES] = {0};
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
-                P.valid = seen[P.cls]++ < ran;
-                P.bytes = P.cls == KC_CG_SPMV ? b_spmv : b_upd;
+                P.valid = seen[P.cls]++ < (P.cls == KC_OTHER ? ran * csteps : ran);
+                P.bytes = P.cls == KC_CG_SPMV ? b_spmv : (P.cls == KC_OTHER ? b_cheb : b_upd);
             }
-            S.bytes_moved += ran * (b_spmv + b_upd);
-            S.spmvs += ran;
+            S.bytes_moved += ran * (b_spmv + b_upd + csteps * b_cheb);
+            S.spmvs += ran * (1 + csteps);
             it_seen = H.it;
             if (H.done) break;
         }

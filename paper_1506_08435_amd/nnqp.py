@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
                 ("cg_chunk", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("lower", ctypes.c_double), ("upper", ctypes.c_double),
                 ("method", ctypes.c_int32), ("lmm_vectors", ctypes.c_int32),
-                ("max_lm_its", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_lm_its", ctypes.c_int32), ("precond_degree", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -869,3 +869,54 @@ def test_full_size_cube128_blmvm(ctx):
     assert k.r <= 1e-8 * (1 + 1e-6), k.r
     print(f"cube128 BLMVM: kkt {k.r:.3e} its {st['outer_its']} trials {st['search_trials']} "
           f"resets {st['refinements']} {st['seconds']:.3f} s")
+
+
+# ---------------------------------------------------------------- Chebyshev preconditioner
+@pytest.mark.parametrize("name", ["cube3d_21_ragged", "transient_field_20x18x9", "square2d_64"])
+def test_chebyshev_preconditioner_same_minimiser(ctx, name):
+    """Polynomial (Chebyshev-Jacobi) preconditioning of TRON's inner CG: the
+    minimiser is the oracle's for every degree, and the CG iteration count
+    falls with the degree."""
+    p = SOLVE_CASES[name]()
+    K, F, _ = ctx.assemble(p)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    its = {}
+    for k in (1, 2, 3, 5):
+        c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, inner_rtol=0.1, precond_degree=k)
+        _check_solution(S, _np(c), _np(active), ref.c)
+        assert oracle.kkt(S, _np(c)).r <= 1.01e-12 + 4 * ref.floor
+        its[k] = st["cg_its"]
+    assert its[3] < its[1] and its[5] < its[2], its
+    print(f"{name}: CG iterations by degree {its}")
+
+
+def test_chebyshev_mixed_galerkin_and_options(ctx):
+    from paper_1506_08435_amd import nnqp
+    p = W.cube3d(21)
+    K, F, _ = ctx.assemble(p)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-10, precond_degree=3, precision=nnqp.NN_MIXED)
+    assert np.abs(_np(c) - ref.c).max() / ref.c.max() <= MIXED_TOL
+    g_ref = oracle.galerkin(S, rtol=1e-13)
+    g1, s1 = ctx.solve_galerkin(K, F, tol=1e-12, max_cg=100000)
+    g3, s3 = ctx.solve_galerkin(K, F, tol=1e-12, max_cg=100000, precond_degree=3)
+    for g in (g1, g3):
+        assert np.abs(_np(g) - g_ref).max() / np.abs(g_ref).max() <= PARITY_TOL
+    assert s3["cg_its"] < s1["cg_its"]
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_nonneg(K, F, precond_degree=9)
+    assert ei.value.status == nnqp.NN_EINVAL
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_batch([K], [F], precond_degree=2)
+    assert ei.value.status == nnqp.NN_EINVAL
+    # a bounded transient step with the polynomial preconditioner
+    import torch
+    q = W.config_transient3d(14, 12, 8, ell=2.0)
+    Sq = oracle.assemble(q, with_mass=True)
+    Kq, Fq, _ = ctx.assemble(q, with_mass=True)
+    cq = torch.zeros(Kq.n, dtype=torch.float64, device=ctx.device)
+    ctx.step_transient(Kq, 0.05, Fq, cq, tol=1e-12, precond_degree=4)
+    rq = oracle.transient_step(Sq, 0.05, np.zeros(Sq.n), tol=1e-13).c
+    assert np.abs(_np(cq) - rq).max() / np.abs(rq).max() <= PARITY_TOL
