@@ -102,8 +102,7 @@ typedef struct {
                              (Sec. 2.2.2, eq. Eq:non-negative: c_min 1 <= c <= c_max 1).
                              Default [0, +inf): the non-negative QP (*); [0, 1] is the
                              DMP variant (Remark in Sec. 5).  lower finite, upper > lower
-                             (may be +inf).  The batched entry points take the default
-                             only; nn_solve_galerkin ignores them. */
+                             (may be +inf).  nn_solve_galerkin ignores them. */
     double upper;
     int32_t method;       /* nn_method: NN_TRON (default) or NN_BLMVM */
     int32_t lmm_vectors;  /* BLMVM: stored (s, y) pairs, 1..8; default 5 (TAO's default) */
@@ -295,8 +294,9 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
  *            NULL), or NULL
  *   stats    host array of nprob reports, or NULL; stats[p].status is the
  *            member's own status, stats[p].seconds the whole call's time
- * Options apply to every member; the bounds must be the default [0, inf)
- * (NN_EINVAL otherwise).  Returns NN_OK when every member reached
+ * Options apply to every member (the bounds too; TRON with the Jacobi
+ * preconditioner only: NN_EINVAL for NN_BLMVM or precond_degree > 1).
+ * Returns NN_OK when every member reached
  * tol; otherwise the status of the first member that did not (the others are
  * still solved and reported).  Workspace (about 100 bytes per row of the
  * whole batch) is allocated for the call and released before return.

@@ -534,8 +534,6 @@ static nn_status check_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
     if (nprob > 0 && (!K || !f_dev || !c_dev)) return fail(ctx, NN_EINVAL, "null argument");
     nn_status st = check_opts(ctx, opts);
     if (st != NN_OK) return st;
-    if (opts->lower != 0.0 || opts->upper != INFINITY)
-        return fail(ctx, NN_EINVAL, "the batched solver takes the bounds [0, inf) only");
     if (opts->method != NN_TRON) return fail(ctx, NN_EINVAL, "the batched solver runs TRON only");
     if (opts->precond_degree > 1)
         return fail(ctx, NN_EINVAL, "the batched solver uses the Jacobi preconditioner only");

@@ -126,6 +126,7 @@ struct BDev {
     double *cg, *fg;                // solution and load
     const double *dg;               // diagonal of the solve's matrix (1 on rows past the end)
     const int *rlen;                // entries of each row (0 past the end)
+    double lo, hi;                  // bounds lo <= c <= hi of every member
 };
 
 // Work vectors of the batched solve, concatenated over the slices.
@@ -146,7 +147,12 @@ __device__ __forceinline__ double bident(int op)
     return op == OP_SUM ? 0.0 : (op == OP_MIN ? INFINITY : -INFINITY);
 }
 
-__device__ __forceinline__ double proj0b(double x) { return x > 0.0 ? x : 0.0; }
+// projection on [lo, hi]; NaN maps to lo (+0.0 for lo = 0)
+__device__ __forceinline__ double projb(const BDev &B, double x)
+{
+    const double y = x > B.lo ? x : B.lo;
+    return y < B.hi ? y : B.hi;
+}
 
 // Walk the slices of the current list grid-stride, one wavefront per slice.
 // For a slice of a member with take(p): body(p, s, global row, local row, row
@@ -333,7 +339,7 @@ __global__ void kb_scatter(BDev B)
         const double cv = B.cg[s * kSlice + lane];
         B.c[p][il] = cv;
         uint8_t *out = B.act_out[p];
-        if (out) out[il] = cv == 0.0 ? 1 : 0;
+        if (out) out[il] = cv == B.lo ? 1 : (cv == B.hi ? 2 : 0);
     }
 }
 
@@ -355,7 +361,7 @@ __global__ void kb_init(BDev B, int mode, double c0v)
                        } else {
                            const double cv = c[i];
                            a[3] += isfinite(cv) ? 0.0 : 1.0;
-                           c[i] = proj0b(cv);
+                           c[i] = projb(B, cv);
                        }
                    });
 }
@@ -476,19 +482,19 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
                 const double gi = kc - B.fg[i];
                 const double cv = c[i];
                 V.g[i] = gi;
-                const double pg = cv > 0.0 ? gi : (gi < 0.0 ? gi : 0.0);
+                const double pg = cv > B.lo ? (cv < B.hi ? gi : fmax(gi, 0.0)) : fmin(gi, 0.0);
                 a[0] = pg * pg;
                 a[1] = (isfinite(gi) && isfinite(cv)) ? 0.0 : 1.0;
-                a[2] = fabs(fmin(cv, gi));
+                a[2] = fabs(fmax(cv - B.hi, fmin(gi, cv - B.lo)));
                 a[3] = cv;
-                a[4] = cv == 0.0 ? 1.0 : 0.0;
+                a[4] = (cv == B.lo || cv == B.hi) ? 1.0 : 0.0;
             }
         } else if (ph == PH_CAUCHY) {
             const double t = S.ttrial;
             const double *__restrict__ g = V.g;
             auto sv = [&](int j) {
                 const double cj = c[j];
-                return proj0b(cj + t * g[j]) - cj;
+                return projb(B, cj + t * g[j]) - cj;
             };
             const double ksv = gsell_row<WMAX, CM>(B, gvals, s, i, sv);
             if (row) {
@@ -520,7 +526,7 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
                 const VV *__restrict__ w = V.w;
                 auto sv = [&](int j) {
                     const double cj = c[j];
-                    return proj0b(cj + t * (double)w[j]) - cj;
+                    return projb(B, cj + t * (double)w[j]) - cj;
                 };
                 const double ksv = gsell_row<WMAX, CM>(B, gvals, s, i, sv);
                 if (live) {
@@ -743,11 +749,11 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
                 V.dm[i] = V.r[i] = V.z[i] = V.p[i] = V.q[i] = V.w[i] = VV(0);
             } else {
                 const double gi0 = V.g[i];
-                const double cv = proj0b(c[i] - S.t * gi0);
+                const double cv = projb(B, c[i] - S.t * gi0);
                 const double gi = gi0 + (S.cur ? V.ks1 : V.ks0)[i];
                 c[i] = cv;
                 V.g[i] = gi;
-                const bool fr = !(cv == 0.0 && gi >= 0.0);
+                const bool fr = !((cv == B.lo && gi >= 0.0) || (cv == B.hi && gi <= 0.0));
                 const VV dmi = fr ? (VV)(1.0 / B.dg[i]) : VV(0);
                 const VV ri = fr ? (VV)(-gi) : VV(0);
                 const VV zi = dmi * ri;
@@ -778,12 +784,13 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
             a[0] = INFINITY;
             if (row) {
                 const double wi = (double)V.w[i];
-                if (wi < 0.0) a[0] = c[i] / (-wi);
+                if (wi < 0.0) a[0] = (c[i] - B.lo) / (-wi);
+                else if (wi > 0.0) a[0] = (B.hi - c[i]) / wi;
                 a[1] = V.g[i] * wi;
                 a[2] = wi * wi;
             }
         } else {   // VO_APPLYW
-            if (row) c[i] = proj0b(c[i] + S.ts * (double)V.w[i]);
+            if (row) c[i] = projb(B, c[i] + S.ts * (double)V.w[i]);
             continue;
         }
 #pragma unroll
@@ -1177,6 +1184,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     B.fg = fg;
     B.dg = dg;
     B.rlen = rlen;
+    B.lo = o->lower;
+    B.hi = o->upper;
 
     // ---- member states
     std::memset(hs, 0, sizeof(BState) * P);
@@ -1270,7 +1279,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     }
     // ---- start point and load statistics
     hipLaunchKernelGGL(kb_init, dim3(grid_for(sh, n_sl)), dim3(sh.block), 0, st, B,
-                       o->c0_mode == 1 ? 1 : 0, std::max(o->c0_value, 0.0));
+                       o->c0_mode == 1 ? 1 : 0, std::min(std::max(o->c0_value, o->lower), o->upper));
     hipLaunchKernelGGL(kb_reduce_init, dim3(std::max(n_pr, 1)), dim3(kFinBlock), 0, st, B);
     NN_HIP_TRY(ctx, hipMemcpyAsync(pres, d_pres, sizeof(double) * P * kBNV, hipMemcpyDeviceToHost,
                                    st));
@@ -1284,8 +1293,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         if (r[2] != 0.0 || r[3] != 0.0) {
             M.status = NN_ENONFINITE;
             M.phase = PH_DONE;
-        } else if (!(r[1] > 0.0)) {
-            // f <= 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0
+        } else if (o->lower == 0.0 && !(r[1] > 0.0)) {
+            // f <= 0 with lower bound 0: c = 0 satisfies c >= 0, g = -f >= 0, c.g = 0
             NN_HIP_TRY(ctx, hipMemsetAsync(cg + (size_t)s0[p] * kSlice, 0,
                                            sizeof(double) * nrow[p], st));
             M.n_active = nrow[p];

@@ -108,14 +108,17 @@ def estimate_bytes(problem, precision: int) -> int:
 class Server:
     def __init__(self, device: int = 0, hbm_budget: Optional[int] = None,
                  precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
-                 inner_rtol: float = 0.1, assemble_workers: int = 2, keep_states: bool = False):
+                 inner_rtol: float = 0.1, assemble_workers: int = 2, keep_states: bool = False,
+                 bounds=(0.0, math.inf)):
         import torch
         self.torch = torch
         self.device = device
         self.ctx = nnqp.Context(device)
         self.precision = precision
         self.dt = dt
-        self.opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision)
+        # bounds c_min <= c <= c_max of every step (Sec. 2.2.2, eq. Eq:non-negative)
+        self.opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision,
+                                      lower=float(bounds[0]), upper=float(bounds[1]))
         free, total = torch.cuda.mem_get_info(device)
         self.budget = int(hbm_budget) if hbm_budget else int(0.75 * free)
         self.workers = assemble_workers
@@ -226,12 +229,13 @@ class Server:
 
 
 def solve_alone(req: Request, precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
-                inner_rtol: float = 0.1, ctx=None):
+                inner_rtol: float = 0.1, ctx=None, bounds=(0.0, math.inf)):
     """The same request run by itself (a batch of one per step): final c and
     per-step stats."""
     import torch
     ctx = ctx or nnqp.Context(0)
-    opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision)
+    opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision,
+                             lower=float(bounds[0]), upper=float(bounds[1]))
     K, F, _ = ctx.assemble(req.problem, with_mass=True)
     c = torch.zeros(max(K.n, 1), dtype=torch.float64, device=ctx.device)
     stats = []

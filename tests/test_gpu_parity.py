@@ -731,7 +731,7 @@ def test_bounds_validation(ctx, batch_members):
         assert ei.value.status == nnqp.NN_EINVAL
     As, Fs = batch_members[1][:2], batch_members[2][:2]
     with pytest.raises(nnqp.NnError) as ei:
-        ctx.solve_batch(As, Fs, upper=1.0)
+        ctx.solve_batch(As, Fs, lower=0.5, upper=0.5)
     assert ei.value.status == nnqp.NN_EINVAL
     # a start value outside the box is projected onto it
     c, _, st = ctx.solve_nonneg(K, F, tol=1e-12, c0_value=5.0, upper=0.01)
@@ -920,3 +920,25 @@ def test_chebyshev_mixed_galerkin_and_options(ctx):
     ctx.step_transient(Kq, 0.05, Fq, cq, tol=1e-12, precond_degree=4)
     rq = oracle.transient_step(Sq, 0.05, np.zeros(Sq.n), tol=1e-13).c
     assert np.abs(_np(cq) - rq).max() / np.abs(rq).max() <= PARITY_TOL
+
+
+def test_batch_two_sided_bounds_match_oracle(ctx, batch_members):
+    """The batched solver with bounds [0, hi] shared by all members (both
+    bounds active in most members) vs the oracle, member by member, and
+    bitwise equal to the same member solved alone."""
+    probs, Ks, Fs, Ss = batch_members
+    maxes = [oracle.solve(S, tol=1e-12).c.max() for S in Ss if S.n > 0]
+    hi = float(0.5 * np.median(maxes))
+    cs, acts, stats, status = ctx.solve_batch(Ks, Fs, tol=1e-12, upper=hi)
+    assert status == 0
+    uppers = 0
+    for S, c, act, st in zip(Ss, cs, acts, stats):
+        if S.n == 0:
+            continue
+        c, act = _np(c), _np(act)
+        ref = oracle.solve(S, tol=1e-13, hi=hi)
+        _check_box(S, c, act, ref.c, 0.0, hi)
+        uppers += int((c == hi).sum())
+    assert uppers > 0
+    one, _, _, _ = ctx.solve_batch([Ks[3]], [Fs[3]], tol=1e-12, upper=hi)
+    assert np.array_equal(_np(one[0]), _np(cs[3]))

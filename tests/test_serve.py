@@ -81,6 +81,36 @@ def test_served_steps_match_oracle():
 
 
 @pytest.mark.gpu
+def test_served_bounded_steps_match_oracle_and_alone():
+    """Served transient steps with the bounds c_min = 0, c_max = 2e-3 of every
+    step (Sec. 2.2.2, eq. Eq:non-negative; the cap is active): the oracle's
+    bounded backward-Euler steps, and bitwise the request run alone."""
+    import torch
+    from paper_1506_08435_amd.serve import Server, solve_alone
+    hi = 2e-3
+    reqs = _requests(4, steps=3)
+    srv = Server(tol=1e-12, inner_rtol=0.1, keep_states=True, bounds=(0.0, hi))
+    rep = srv.run(reqs)
+    capped = 0
+    for req, res in zip(reqs, rep.results):
+        assert res.status == 0
+        S = oracle.assemble(req.problem, with_mass=True)
+        c_ref = np.zeros(S.n)
+        for _ in range(req.steps):
+            r = oracle.transient_step(S, 1e-3, c_ref, tol=1e-13, hi=hi)
+            assert r.certified
+            c_ref = r.c
+        c = res.c.cpu().numpy()
+        assert c.min() >= 0.0 and c.max() <= hi
+        err = np.abs(c - c_ref).max() / np.abs(c_ref).max()
+        assert err <= 1e-8, (req.rid, err)
+        capped += int((c == hi).sum())
+        c_alone, _ = solve_alone(req, tol=1e-12, inner_rtol=0.1, bounds=(0.0, hi))
+        assert torch.equal(res.c, c_alone)
+    assert capped > 0
+
+
+@pytest.mark.gpu
 def test_admission_respects_budget():
     from paper_1506_08435_amd.serve import NN_EBUDGET, Request, Server, estimate_bytes
     from paper_1506_08435_amd import nnqp
