@@ -28,7 +28,9 @@
 //      holds, finishing with the exact step on the segment [0, crossing] if t
 //      reaches it.  Each trial is one matrix pass that gathers P(c + t d) and
 //      returns the gradient K c(t) - f at the trial point.
-//   5. Step kernel: c <- c(t), s stored in the next pair slot, g updated.
+//   5. Step: c <- c(t), s stored in the next pair slot, g updated; done by
+//      the next iteration's pair pass (one pass over the rows fewer), or by a
+//      step kernel when a gradient refresh comes first.
 // g is refreshed with a plain gradient pass every 50 iterations that did not
 // end on a freshly computed gradient, and before convergence is accepted.
 #include <algorithm>
@@ -97,18 +99,24 @@ __device__ __forceinline__ void block_sums(double (&a)[NV], double *part)
 }
 
 // 1. pair pass (see the file comment); values: |pg|^2, #non-finite,
-// s_j.pg, y_j.pg, s_j.y, y_j.y (j = 0..M-1 by slot), s.s
+// s_j.pg, y_j.pg, s_j.y, y_j.y (j = 0..M-1 by slot), s.s.
+// With `apply` the step of the previous iteration is taken here first (the
+// step kernel fused in): c <- P(c + t d), s = c_new - c into slot head,
+// g <- g + gscale (gn - g) (gscale = 1: gn itself), and the pair is formed
+// from that s.
 template <int M>
-__global__ __launch_bounds__(kBlock) void kl_pairs(Part P, const double *__restrict__ c,
-                                                   const double *__restrict__ g,
+__global__ __launch_bounds__(kBlock) void kl_pairs(Part P, double *__restrict__ c,
+                                                   double *__restrict__ g,
                                                    double *__restrict__ pg,
-                                                   const double *__restrict__ S,
+                                                   double *__restrict__ S,
                                                    double *__restrict__ Y, int64_t ld,
                                                    const LmState *__restrict__ st, Box B,
-                                                   double *part)
+                                                   double *part, int apply,
+                                                   const double *__restrict__ d, double t,
+                                                   const double *__restrict__ gn, double gscale)
 {
     constexpr int NV = 4 * M + 3;
-    const int count = st->count, head = st->head, pending = st->pending;
+    const int count = st->count, head = st->head, pending = apply || st->pending;
     bool live[M];
 #pragma unroll
     for (int j = 0; j < M; j++) live[j] = lm_live(j, M, count, head, pending);
@@ -117,14 +125,24 @@ __global__ __launch_bounds__(kBlock) void kl_pairs(Part P, const double *__restr
     for (int k = 0; k < NV; k++) a[k] = 0.0;
     for_rows(P, [&](int i, bool act) {
         if (!act) return;
-        const double ci = c[i], gi = g[i];
+        double ci = c[i], gi = g[i], sn = 0.0;
+        if (apply) {
+            const double cn = proj_box(ci + t * d[i], B);
+            sn = cn - ci;
+            ci = cn;
+            gi = gscale == 1.0 ? gn[i] : gi + gscale * (gn[i] - gi);
+            c[i] = ci;
+            g[i] = gi;
+            S[head * ld + i] = sn;
+        } else if (pending) {
+            sn = S[head * ld + i];
+        }
         const double pgi = ci > B.lo ? (ci < B.hi ? gi : fmax(gi, 0.0)) : fmin(gi, 0.0);
         a[0] += pgi * pgi;
         a[1] += (isfinite(ci) && isfinite(gi)) ? 0.0 : 1.0;
-        double yn = 0.0, sn = 0.0;
+        double yn = 0.0;
         if (pending) {
             yn = pgi - pg[i];
-            sn = S[head * ld + i];
             Y[head * ld + i] = yn;
             a[2 + 4 * M] += sn * sn;
         }
@@ -150,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void kl_pairs(Part P, const double *__restr
 // partials (lane-strided sums, then a butterfly: fixed order) and stage the
 // S'Y and Y'Y tables in LDS; lane 0 does the small algebra.
 template <int M>
-__global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double *part)
+__global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double *part, int applied)
 {
     constexpr int NV = 4 * M + 3;
     __shared__ double t[NV];
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double 
         double gam = st->gamma;
         st->pg2 = t[0];
         st->nonfinite = t[1];
-        if (st->pending) {
+        if (st->pending || applied) {
             const double sny = t[2 + 2 * M + head], yny = t[2 + 3 * M + head], ss = t[2 + 4 * M];
             const bool ok = isfinite(sny) && isfinite(yny) && yny > 0.0 &&
                             sny > kLmCurv * sqrt(ss) * sqrt(yny);
@@ -384,21 +402,25 @@ __global__ __launch_bounds__(kBlock) void kl_step(Part P, double *__restrict__ c
 // slices per wavefront instead of queueing a second round of blocks.
 constexpr int kPairBlocks = 256;
 
+// Pair pass and coefficients; with apply, the pending step (t, gscale) is
+// taken inside the pair pass.
 template <int M>
-void launch_pairs_coef(nn_ctx *ctx, const Part &P, const double *c, const double *g, Box B)
+void launch_pairs_coef(nn_ctx *ctx, const Part &P, double *c, double *g, Box B, bool apply,
+                       double t, double gscale)
 {
     LmWork &L = ctx->lm;
     const Part P1 = make_part(P.n, kPairBlocks);
     kl_pairs<M><<<P1.nb, kBlock, 0, ctx->stream>>>(P1, c, g, L.pg, L.S, L.Y, L.cap,
-                                                   (const LmState *)L.state, B, L.part);
-    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P1.nb, (LmState *)L.state, L.part);
+                                                   (const LmState *)L.state, B, L.part,
+                                                   apply ? 1 : 0, L.d, t, L.gn, gscale);
+    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P1.nb, (LmState *)L.state, L.part, apply ? 1 : 0);
 }
 
 template <int M>
 void launch_coef(nn_ctx *ctx, const Part &P)
 {
     const Part P1 = make_part(P.n, kPairBlocks);
-    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P1.nb, (LmState *)ctx->lm.state, ctx->lm.part);
+    kl_coef<M><<<1, 64, 0, ctx->stream>>>(P1.nb, (LmState *)ctx->lm.state, ctx->lm.part, 0);
 }
 
 template <int M>
@@ -580,14 +602,21 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     };
     bool fresh = true;
     int since_fresh = 0;
+    // the step of an iteration is taken by the next pair pass unless a
+    // gradient refresh comes in between
+    bool step_pending = false;
+    double step_t = 0.0, step_gscale = 1.0;
     nn_status result = NN_EMAXIT;
     for (int it = 0;; it++) {
-        // ---- 1-3. pairs, coefficients, direction (+ first trial)
+        // ---- 1-3. (pending step,) pairs, coefficients, direction (+ first trial)
         const double live = std::min(it, M);
-        prof_begin(ctx, KC_OTHER, vp * (5.0 + 2.0 * live));
-        NN_LM_DISPATCH(M, launch_pairs_coef, ctx, P, c, W.g, box);
+        const double b_pairs = vp * (5.0 + 2.0 * live) + (step_pending ? vp * 3.0 : 0.0);
+        prof_begin(ctx, KC_OTHER, b_pairs);
+        NN_LM_DISPATCH(M, launch_pairs_coef, ctx, P, c, W.g, box, step_pending, step_t,
+                       step_gscale);
         prof_end(ctx);
-        S.bytes_moved += vp * (9.0 + 4.0 * live);
+        S.bytes_moved += b_pairs + vp * (4.0 + 2.0 * live);
+        step_pending = false;
         if ((rc = direction_and_first_trial()) != NN_OK) return finish(rc);
         if (H.nonfinite != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite iterate"));
         S.outer_its = it;
@@ -651,18 +680,22 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                 if ((rc = read_trial(gs, sks)) != NN_OK) return finish(rc);
             }
         }
-        // ---- 5. step
-        prof_begin(ctx, KC_OTHER, 56.0 * n);
-        kl_step<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, L.d, t, W.g, L.gn, gscale, L.S, L.cap,
-                                                  (LmState *)L.state, box);
-        prof_end(ctx);
-        S.bytes_moved += 56.0 * n;
+        // ---- 5. step: taken by the next pair pass, or here before a refresh
         fresh = gscale == 1.0;
         since_fresh = fresh ? 0 : since_fresh + 1;
         if (since_fresh >= kLmRefresh) {
+            prof_begin(ctx, KC_OTHER, 56.0 * n);
+            kl_step<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, L.d, t, W.g, L.gn, gscale, L.S,
+                                                      L.cap, (LmState *)L.state, box);
+            prof_end(ctx);
+            S.bytes_moved += 56.0 * n;
             if ((rc = refresh(conv)) != NN_OK) return finish(rc);
             fresh = true;
             since_fresh = 0;
+        } else {
+            step_pending = true;
+            step_t = t;
+            step_gscale = gscale;
         }
         if (o->verbose)
             std::fprintf(stderr, "nnqp blmvm %5d |pg|/|f| %.3e pairs %d gamma %.3g crossing %.3g step %.3g\n",
