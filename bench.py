@@ -23,7 +23,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_spmv_cube128_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1506_08435_amd", "csrc", "kernels.hip")]
+# sources of the CG matrix pass (its code, its slice walker, its constants)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1506_08435_amd", "csrc", f)
+                  for f in ("kernels.hip", "rows.hpp", "nnqp_internal.hpp")]
 
 
 def kernel_hash() -> str:
@@ -219,6 +221,7 @@ def run_hole(args):
     }
     if blmvm is not None:
         line["blmvm"] = blmvm
+        line["tron_levels"] = run_tron_levels(ctx, K, F, args, bounds=(0.0, 1.0))
     print(json.dumps(line), flush=True)
 
 
@@ -562,6 +565,8 @@ def main():
         out["galerkin"] = galerkin
     if blmvm is not None:
         out["blmvm"] = blmvm
+    if not args.no_blmvm and prec == nnqp.NN_FP64:
+        out["tron_levels"] = run_tron_levels(ctx, K, F, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
     print(json.dumps(out), flush=True)
@@ -586,6 +591,22 @@ def run_galerkin(ctx, K, F, n, stats, args):
             "algorithmic_GBps": round(r["bytes_moved"] / r["seconds"] / 1e9, 1),
             "nonneg_over_galerkin_time": round(nn_med / g_med, 3),
             "nonneg_min_c": stats[-1]["min_c"]}
+
+
+def run_tron_levels(ctx, K, F, args, bounds=(0.0, float("inf"))):
+    """TRON with the paper's three inner CG tolerances (TRON1/2/3: 1e-1, 1e-2,
+    1e-3, Sec. 5.1), median device time of a few solves each: the TRON columns
+    of Tables Tab:S5_cube_times_mustang/wolf."""
+    from paper_1506_08435_amd import nnqp
+    out = {}
+    for name, rtol in (("tron1", 1e-1), ("tron2", 1e-2), ("tron3", 1e-3)):
+        opts = nnqp.default_opts(tol=1e-8, inner_rtol=rtol, lower=bounds[0], upper=bounds[1])
+        ctx.solve_nonneg(K, F, opts=opts)
+        runs = [ctx.solve_nonneg(K, F, opts=opts)[2] for _ in range(args.blmvm_reps)]
+        r = runs[-1]
+        out[name] = {"median_device_ms": round(sorted(x["seconds"] for x in runs)[len(runs) // 2] * 1e3, 3),
+                     "outer_its": r["outer_its"], "cg_its": r["cg_its"]}
+    return out
 
 
 def run_blmvm(ctx, K, F, n, stats, galerkin, args, bounds=(0.0, float("inf"))):
