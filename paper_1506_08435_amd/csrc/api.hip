@@ -20,7 +20,8 @@ nn_status ensure_workspace(nn_ctx *ctx, int64_t n)
 {
     Workspace &W = ctx->ws;
     if (W.cap >= n && W.g) return NN_OK;
-    double **vecs[] = {&W.g, &W.w, &W.r, &W.z, &W.q, &W.p0, &W.p1, &W.ks0, &W.ks1, &W.dm, &W.ft};
+    double **vecs[] = {&W.g,   &W.w,   &W.r,  &W.z,  &W.q,   &W.p0,  &W.p1,
+                       &W.ks0, &W.ks1, &W.dm, &W.ft, &W.ks2};
     for (double **v : vecs)
         if (*v) {
             (void)hipFree(*v);
@@ -190,6 +191,8 @@ nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
     bool ok = hipMalloc(&ctx->partials, part_bytes) == hipSuccess &&
               hipHostMalloc(&ctx->h_part, sizeof(double) * kMaxBlocks * kMaxRed,
                             hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_multi, sizeof(double) * kMaxBlocks * (5 + 3 * kLadder),
+                            hipHostMallocDefault) == hipSuccess &&
               hipMalloc(&ctx->scal, sizeof(DevScalars)) == hipSuccess &&
               hipHostMalloc(&ctx->h_scal, sizeof(DevScalars), hipHostMallocDefault) == hipSuccess &&
               hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
@@ -213,7 +216,8 @@ void nn_destroy(nn_ctx *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     Workspace &W = ctx->ws;
-    double *vecs[] = {W.g, W.w, W.r, W.z, W.q, W.p0, W.p1, W.ks0, W.ks1, W.dm, W.ft};
+    double *vecs[] = {W.g,   W.w,   W.r,  W.z,  W.q,   W.p0,  W.p1,
+                      W.ks0, W.ks1, W.dm, W.ft, W.ks2};
     for (double *v : vecs)
         if (v) (void)hipFree(v);
     float *fvecs[] = {W.w32, W.r32, W.z32, W.q32, W.p32, W.dm32};
@@ -229,6 +233,7 @@ void nn_destroy(nn_ctx *ctx)
     lm_release(ctx);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->h_part) (void)hipHostFree(ctx->h_part);
+    if (ctx->h_multi) (void)hipHostFree(ctx->h_multi);
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);

@@ -153,6 +153,46 @@ __global__ __launch_bounds__(kBlock) void k_trial(Part P, const int *__restrict_
     block_partial<kOpsTrial, 3>(a, slot_ptr(partials, SLOT_HOST));
 }
 
+// Cauchy ladder: the projected steepest-descent trial s_k = P(c - t_k g) - c
+// for kLadder step lengths in one matrix pass (the entries are read once and
+// each gathered column yields all kLadder trial values); ks_k = K s_k; per k
+// the sums g.s_k, s_k.Ks_k, s_k.s_k as values 3k, 3k+1, 3k+2 of a
+// 3 kLadder-value partial starting at SLOT_U0 (it may span SLOT_U1).
+struct Ladder {
+    double t[kLadder];
+    double *ks[kLadder];
+};
+
+template <int WMAX, class VT, class Cols>
+__global__ __launch_bounds__(kBlock) void k_ladder(Part P, const int *__restrict__ so, Cols sc,
+                                                   const VT *__restrict__ v,
+                                                   const double *__restrict__ c,
+                                                   const double *__restrict__ g, Ladder L, Box B,
+                                                   double *partials)
+{
+    double a[3 * kLadder];
+#pragma unroll
+    for (int k = 0; k < 3 * kLadder; k++) a[k] = 0.0;
+    auto trials = [&](int j, double (&out)[kLadder]) {
+        const double cj = c[j], gj = g[j];
+#pragma unroll
+        for (int k = 0; k < kLadder; k++) out[k] = proj_box(cj - L.t[k] * gj, B) - cj;
+    };
+    sell_rows_n<WMAX, kLadder>(P, so, sc, v, [&](int i) { return Two{c[i], g[i]}; }, trials,
+                               [&](int i, double (&kv)[kLadder], Two cg) {
+                                   double si[kLadder];
+                                   trials(i, si);
+#pragma unroll
+                                   for (int k = 0; k < kLadder; k++) {
+                                       L.ks[k][i] = kv[k];
+                                       a[3 * k] += cg.b * si[k];
+                                       a[3 * k + 1] += si[k] * kv[k];
+                                       a[3 * k + 2] += si[k] * si[k];
+                                   }
+                               });
+    block_partial<0u, 3 * kLadder>(a, slot_ptr(partials, SLOT_U0));
+}
+
 // c = P(c + t d)
 template <class VD>
 __global__ __launch_bounds__(kBlock) void k_apply(Part P, double *__restrict__ c,
@@ -593,6 +633,27 @@ void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *
             NN_DISPATCH_W(A->wmax, (k_trial<WM, double, double, ColsI32>), P.nb, P, A->sl_off, cols,
                           V.v64, c, d.f64, t, g, mask, ks, ctx->partials, B);
     }
+}
+
+void launch_ladder(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c,
+                   const double *g, const double *t, double *const *ks, Box B)
+{
+    // 3 kLadder accumulators per lane: one 1024-thread block per CU
+    Part P = make_part(A->n, kLadderBlocks);
+    Ladder L;
+    for (int k = 0; k < kLadder; k++) {
+        L.t[k] = t[k];
+        L.ks[k] = ks[k];
+    }
+    if (V.v32 && A->sl_d16)
+        NN_DISPATCH_W(A->wmax, (k_ladder<WM, float, ColsD16>), P.nb, P, A->sl_off,
+                      ColsD16{A->sl_d16}, V.v32, c, g, L, B, ctx->partials);
+    else if (V.v32)
+        NN_DISPATCH_W(A->wmax, (k_ladder<WM, float, ColsI32>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v32, c, g, L, B, ctx->partials);
+    else
+        NN_DISPATCH_W(A->wmax, (k_ladder<WM, double, ColsI32>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v64, c, g, L, B, ctx->partials);
 }
 
 void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t, Box B)

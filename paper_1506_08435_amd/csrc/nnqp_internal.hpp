@@ -25,6 +25,8 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kSlice = 64;
 constexpr int kMaxBlocks = 512;    // 2 workgroups per CU on 256 CUs
 constexpr int kMaxRed = 8;         // values per reduction
+constexpr int kLadder = 3;         // step lengths of one Cauchy ladder pass (odd)
+constexpr int kLadderBlocks = 256; // blocks of a ladder pass
 
 struct Part {
     int n = 0;        // rows
@@ -61,6 +63,7 @@ struct Workspace {
     double *g = nullptr, *w = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
     double *p0 = nullptr, *p1 = nullptr, *ks0 = nullptr, *ks1 = nullptr, *dm = nullptr;
     double *ft = nullptr;  // transient right-hand side
+    double *ks2 = nullptr;   // third Cauchy ladder product (with ks0, ks1)
     // float32 CG vectors of the mixed-precision inner solve
     float *w32 = nullptr, *r32 = nullptr, *z32 = nullptr, *q32 = nullptr, *p32 = nullptr,
           *dm32 = nullptr;
@@ -149,6 +152,7 @@ struct nn_ctx {
     std::string err;
     double *partials = nullptr;      // [kSlots][kMaxBlocks][kMaxRed]
     double *h_part = nullptr;        // pinned host copy of one slot
+    double *h_multi = nullptr;       // pinned host copy of the gradient + Cauchy ladder partials
     nnqp::DevScalars *scal = nullptr;
     nnqp::DevScalars *h_scal = nullptr;  // pinned mirror
     nnqp::Workspace ws;
@@ -210,6 +214,10 @@ void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const doub
 // [host] s = P(c + t d) - c gathered, ks = A s; g.s, s.As, s.s (sums); rows with mask == 0 skipped
 void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
                   double t, const double *g, const uint8_t *mask, double *ks, Box B);
+// [SLOT_U0..U1, 15 values] Cauchy ladder: for k < kLadder, s_k = P(c - t[k] g) - c,
+// ks[k] = A s_k; g.s_k, s_k.A s_k, s_k.s_k as values 3k..3k+2
+void launch_ladder(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c,
+                   const double *g, const double *t, double *const *ks, Box B);
 // c = P(c + t d)
 void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t, Box B);
 // CG set-up on the face of (c, g + ks) (every row not binding: not at lo with

@@ -219,6 +219,60 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
     }
 }
 
+// NT products in one pass: like sell_rows, with x(j, out) filling NT values
+// per gathered column and epi(i, acc[NT], pre(i)).  Entries are loaded eight
+// at a time before their gathers; one slice per wavefront in flight.
+template <int WMAX, int NT, class VT, class Cols, class Pre, class X, class Epi>
+__device__ __forceinline__ void sell_rows_n(const Part &P, const int *__restrict__ so, Cols sc,
+                                            const VT *__restrict__ sv, Pre pre, X x, Epi epi)
+{
+    using PV = decltype(pre(0));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = P.nb * kWaves;
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += nw) {
+        const int off = so[s];
+        const int w = (so[s + 1] - off) >> 6;
+        const int row = s * kSlice + lane;
+        const bool act = row < P.n;
+        const PV pv = act ? pre(row) : PV();
+        double acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[t] = 0.0;
+        constexpr int H = WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE;
+        double xv[NT];
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX; h0 += H) {
+            int cc[H];
+            VT vv[H];
+#pragma unroll
+            for (int k = 0; k < H; k++) {
+                if (h0 + k < w) {
+                    cc[k] = sc(off + (h0 + k) * kSlice + lane, row);
+                    vv[k] = ld_val(sv + off + (h0 + k) * kSlice + lane);
+                } else {
+                    cc[k] = 0;
+                    vv[k] = VT(0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < H; k++)
+                if (h0 + k < w) {
+                    x(cc[k], xv);
+#pragma unroll
+                    for (int t = 0; t < NT; t++) acc[t] += (double)vv[k] * xv[t];
+                }
+        }
+        for (int k = WMAX; k < w; k++) {
+            const int e = off + k * kSlice + lane;
+            x(sc(e, row), xv);
+            const double vk = (double)ld_val(sv + e);
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t] += vk * xv[t];
+        }
+        if (act) epi(row, acc, pv);
+    }
+}
+
 struct NoPre {
     __device__ __forceinline__ int operator()(int) const { return 0; }
 };

@@ -100,6 +100,38 @@ nn_status cheb_prepare(nn_ctx *ctx, const nn_matrix *A, const double *vals, cons
     return NN_OK;
 }
 
+// One synchronisation for the gradient report (5 values, host slot) and the
+// Cauchy ladder (3 kLadder values from SLOT_U0 on); both combined in block order.
+static nn_status read_grad_and_ladder(nn_ctx *ctx, int64_t n, double *grad, double *ladder)
+{
+    const Part P = make_part(n), PL = make_part(n, kLadderBlocks);
+    double *h = ctx->h_multi;
+    const size_t ng = (size_t)4 * kMaxBlocks + P.nb;
+    const size_t nl = (size_t)(3 * kLadder - 1) * kMaxBlocks + PL.nb;
+    NN_HIP_TRY(ctx, hipMemcpyAsync(h, ctx->partials, sizeof(double) * ng, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    const double *lsrc = ctx->partials + (size_t)SLOT_U0 * kMaxRed * kMaxBlocks;
+    NN_HIP_TRY(ctx, hipMemcpyAsync(h + (size_t)5 * kMaxBlocks, lsrc, sizeof(double) * nl,
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    NN_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
+    for (int k = 0; k < 5; k++) {
+        const int op = kGradOps[k];
+        double a = op == OP_SUM ? 0.0 : (op == OP_MIN ? INFINITY : -INFINITY);
+        for (int b = 0; b < P.nb; b++) {
+            const double v = h[(size_t)k * kMaxBlocks + b];
+            a = op == OP_SUM ? a + v : (op == OP_MIN ? std::fmin(a, v) : std::fmax(a, v));
+        }
+        grad[k] = a;
+    }
+    for (int k = 0; k < 3 * kLadder; k++) {
+        double a = 0.0;
+        for (int b = 0; b < PL.nb; b++) a += h[(size_t)(5 + k) * kMaxBlocks + b];
+        ladder[k] = a;
+    }
+    return NN_OK;
+}
+
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
                      const double *diag, const double *f, const nn_opts *o, double *c,
                      uint8_t *active, nn_stats *st)
@@ -150,7 +182,6 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     else dir_w.f64 = W.w;
 
     static const int kInitOps[4] = {OP_SUM, OP_MAX, OP_SUM, OP_SUM};
-    static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
     static const int kTrialOps[3] = {OP_SUM, OP_SUM, OP_SUM};
     static const int kBrkOps[3] = {OP_MIN, OP_SUM, OP_SUM};
     double red[kMaxRed];
@@ -186,14 +217,30 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     const int chunk = o->cg_chunk > 0 ? o->cg_chunk : 16;
     nn_status result = NN_EMAXIT;
 
+    static_assert(kLadder == 3, "ladder buffers: ks0, ks1, ks2");
+    double *const ladder_ks[kLadder] = {W.ks0, W.ks1, W.ks2};
     for (int outer = 0;; outer++) {
-        // ---- 1. gradient and convergence test
+        // ---- 1. gradient and convergence test, with the Cauchy ladder around
+        // the previous step length issued behind it (one synchronisation for
+        // both; the ladder is unused on the last iteration)
         prof_begin(ctx, KC_GRAD, B.spmv() + 16.0 * n);
         launch_grad(ctx, A, vals, c, f, W.g, box);
         prof_end(ctx);
         S.spmvs++;
         S.bytes_moved += B.spmv() + 16.0 * n;
-        if ((rc = host_reduce(ctx, n, 5, kGradOps, red)) != NN_OK) return rc;
+        // ladder ..., t_c / 10, t_c, 10 t_c, ... around the previous step
+        // length, formed as the sequential search forms them (repeated x0.1
+        // and x10)
+        constexpr int kMid = kLadder / 2;
+        double lt[kLadder];
+        lt[kMid] = t_cauchy;
+        for (int r = kMid - 1; r >= 0; r--) lt[r] = lt[r + 1] * kInterp;
+        for (int r = kMid + 1; r < kLadder; r++) lt[r] = lt[r - 1] * kExtrap;
+        prof_begin(ctx, KC_TRIAL, spmv_s + (16.0 + 8.0 * kLadder) * n);
+        launch_ladder(ctx, A, VS, c, W.g, lt, ladder_ks, box);
+        prof_end(ctx);
+        double lres[3 * kLadder];
+        if ((rc = read_grad_and_ladder(ctx, n, red, lres)) != NN_OK) return rc;
         if (red[1] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite gradient"));
         S.kkt_rel = std::sqrt(red[0]) / normf;
         S.kkt_nat_inf = red[2];
@@ -209,13 +256,20 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             fail(ctx, NN_EMAXIT, "outer iteration cap reached");
             break;
         }
+        S.spmvs += kLadder;
+        S.cauchy_trials += kLadder;
+        S.bytes_moved += spmv_s + (16.0 + 8.0 * kLadder) * n;
 
-        // ---- 2. Cauchy point along the projected steepest-descent path
-        double *ksbuf[2] = {W.ks0, W.ks1};
-        int cur = 0;
-        auto trial_cauchy = [&](double t, int buf, double &gs, double &sks, double &ss) -> nn_status {
+        // ---- 2. Cauchy point along the projected steepest-descent path.
+        // The decisions are those of the sequential search (start at t_c,
+        // extrapolate x10 while the test holds, else interpolate x0.1 until
+        // it holds), read off the ladder; a search that leaves the ladder
+        // continues with single trials.
+        double *best_ks = ladder_ks[kMid];
+        auto scratch_for = [&](const double *busy) { return busy == W.ks0 ? W.ks1 : W.ks0; };
+        auto trial_cauchy = [&](double t, double *ks, double &gs, double &sks, double &ss) -> nn_status {
             prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
-            launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ksbuf[buf], box);
+            launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ks, box);
             prof_end(ctx);
             S.spmvs++;
             S.cauchy_trials++;
@@ -229,28 +283,60 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         auto ok_decrease = [&](double gs, double sks, double ss) {
             return gs < 0.0 && gs + 0.5 * sks <= kMu0 * gs && std::sqrt(ss) <= delta;
         };
-        double gs, sks, ss;
-        double t = t_cauchy;
-        if ((rc = trial_cauchy(t, cur, gs, sks, ss)) != NN_OK) return rc;
+        auto lg = [&](int k) { return lres[3 * k]; };
+        auto lk = [&](int k) { return lres[3 * k + 1]; };
+        auto ls = [&](int k) { return lres[3 * k + 2]; };
+        double t = lt[kMid], gs = lg(kMid), sks = lk(kMid), ss = ls(kMid);
         if (ok_decrease(gs, sks, ss)) {
-            for (int k = 0; k < 20; k++) {
+            int k = 0;
+            bool open_end = true;   // the chain may continue past the ladder
+            for (int r = kMid + 1; r < kLadder; r++, k++) {
+                if (!ok_decrease(lg(r), lk(r), ls(r))) {
+                    open_end = false;
+                    break;
+                }
+                const bool same = lg(r) == gs && lk(r) == sks;
+                t = lt[r];
+                best_ks = ladder_ks[r];
+                gs = lg(r);
+                sks = lk(r);
+                ss = ls(r);
+                if (same) {   // every moving variable has reached its bound
+                    open_end = false;
+                    break;
+                }
+            }
+            for (; open_end && k < 20; k++) {
                 double gs2, sks2, ss2;
-                if ((rc = trial_cauchy(t * kExtrap, cur ^ 1, gs2, sks2, ss2)) != NN_OK) return rc;
+                double *ks_try = scratch_for(best_ks);
+                if ((rc = trial_cauchy(t * kExtrap, ks_try, gs2, sks2, ss2)) != NN_OK) return rc;
                 if (!ok_decrease(gs2, sks2, ss2)) break;
                 const bool same = gs2 == gs && sks2 == sks;
                 t *= kExtrap;
-                cur ^= 1;
+                best_ks = ks_try;
                 gs = gs2;
                 sks = sks2;
                 ss = ss2;
-                if (same) break;   // every moving variable has reached its bound
+                if (same) break;
             }
         } else {
-            int k = 0;
-            do {
-                t *= kInterp;
-                if ((rc = trial_cauchy(t, cur, gs, sks, ss)) != NN_OK) return rc;
-            } while (!ok_decrease(gs, sks, ss) && ++k < kMaxTrials && gs < 0.0);
+            // t <- 0.1 t until the test holds, at most kMaxTrials times, while g.s < 0
+            int k = 0, r = kMid - 1;
+            for (;;) {
+                if (r >= 0) {
+                    t = lt[r];
+                    best_ks = ladder_ks[r];
+                    gs = lg(r);
+                    sks = lk(r);
+                    ss = ls(r);
+                    r--;
+                } else {
+                    t *= kInterp;
+                    best_ks = W.ks0;
+                    if ((rc = trial_cauchy(t, best_ks, gs, sks, ss)) != NN_OK) return rc;
+                }
+                if (ok_decrease(gs, sks, ss) || !(++k < kMaxTrials && gs < 0.0)) break;
+            }
             if (!ok_decrease(gs, sks, ss)) {
                 // no decrease possible along -g at this precision: stationary up to rounding
                 fail(ctx, NN_EMAXIT, "Cauchy search found no decrease (rounding floor)");
@@ -266,7 +352,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
 
         // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, diag, c, W.g, ksbuf[cur], mixed, box, false, chp);
+        launch_cg_setup(ctx, A, diag, c, W.g, best_ks, mixed, box, false, chp);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
         for (int st = 1; st <= csteps; st++) launch_cheb(ctx, A, VS, cheb, st, SLOT_U0);
