@@ -142,6 +142,26 @@ void prof_collect(nn_ctx *ctx)
 
 namespace nnqp {
 
+// The paired int16 offsets (and, when the float32 values exist, the paired
+// float32 values of K) used by the single-problem float32 passes.
+nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K)
+{
+    if (!K->sl_d16 || K->n == 0) return NN_OK;
+    const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
+    if (!K->d16p) {
+        if (hipMalloc(&K->d16p, sizeof(short) * m) != hipSuccess)
+            return fail(ctx, NN_EOOM, "paired offsets allocation");
+        launch_pair_d16(ctx, K, K->sl_d16, K->d16p);
+    }
+    if (K->val32 && !K->val32p) {
+        if (hipMalloc(&K->val32p, sizeof(float) * m) != hipSuccess)
+            return fail(ctx, NN_EOOM, "paired float32 allocation");
+        launch_pair_f32(ctx, K, K->val32, K->val32p);
+    }
+    NN_HIP_TRY(ctx, hipGetLastError());
+    return NN_OK;
+}
+
 // M/dt + K values for a backward-Euler step (formed once per dt, kept with K)
 nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed)
 {
@@ -158,6 +178,14 @@ nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed)
     launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
     launch_diag(ctx, K, K->kt, K->kt_diag);
     if (K->kt32) launch_to_f32(ctx, K->nsell, K->kt, K->kt32);
+    if (K->kt32 && K->sl_d16) {
+        nn_status st = ensure_paired(ctx, K);
+        if (st != NN_OK) return st;
+        if (!K->kt32p &&
+            hipMalloc(&K->kt32p, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
+            return fail(ctx, NN_EOOM, "transient float32 allocation");
+        launch_pair_f32(ctx, K, K->kt32, K->kt32p);
+    }
     NN_HIP_TRY(ctx, hipGetLastError());
     K->kt_dt = dt;
     return NN_OK;
@@ -425,10 +453,11 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
     for (int *p : iv)
         if (p) (void)hipFree(p);
     if (A->sl_d16) (void)hipFree(A->sl_d16);
+    if (A->d16p) (void)hipFree(A->d16p);
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
     for (double *p : dv)
         if (p) (void)hipFree(p);
-    float *fv[] = {A->val32, A->kt32};
+    float *fv[] = {A->val32, A->kt32, A->val32p, A->kt32p};
     for (float *p : fv)
         if (p) (void)hipFree(p);
     delete A;
@@ -489,8 +518,10 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
             NN_HIP_TRY(ctx, hipGetLastError());
         }
         v32 = K->val32;
+        if ((st = ensure_paired(ctx, K)) != NN_OK) return st;
     }
-    return solve_impl(ctx, K, K->val, v32, K->diag, f_dev, opts, c_dev, active_dev, stats);
+    return solve_impl(ctx, K, K->val, v32, v32 ? K->val32p : nullptr, K->diag, f_dev, opts, c_dev,
+                      active_dev, stats);
 }
 
 
@@ -518,15 +549,16 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     if (st != NN_OK) return st;
     const int64_t n = K->n;
     const bool mixed = opts->precision == NN_MIXED;
-    if (n == 0) return solve_impl(ctx, K, K->val, nullptr, K->diag, f_dev, opts, c_dev, active_dev, stats);
+    if (n == 0) return solve_impl(ctx, K, K->val, nullptr, nullptr, K->diag, f_dev, opts, c_dev,
+                                    active_dev, stats);
     if ((st = ensure_transient(ctx, K, dt, mixed)) != NN_OK) return st;
     if ((st = ensure_workspace(ctx, n)) != NN_OK) return st;
     launch_transient_rhs(ctx, K, c_dev, f_dev, dt, ctx->ws.ft);
     nn_opts o = *opts;
     o.c0_mode = 1;   // warm start from c^(n)
     if (o.method == NN_BLMVM) return blmvm_impl(ctx, K, K->kt, ctx->ws.ft, &o, c_dev, active_dev, stats);
-    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, K->kt_diag, ctx->ws.ft, &o, c_dev,
-                      active_dev, stats);
+    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32p : nullptr,
+                      K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev, stats);
 }
 
 // Shared checks of the batched entry points: arguments, options, and that

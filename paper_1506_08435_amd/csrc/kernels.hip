@@ -473,6 +473,24 @@ __global__ __launch_bounds__(kBlock) void k_vals_mdt_plus_k(int64_t nnz, const d
         out[t] = m[t] / dt + k[t];
 }
 
+// Paired copy of a sliced-ELL array (the layout of nn_matrix::d16p): within
+// slice s of width w, entry k of lane l moves from off + 64 k + l to
+// off + 128 (k / 2) + 2 l + k % 2 for k < 2 (w / 2); an odd last column stays.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_pair(Part P, const int *__restrict__ so,
+                                                 const T *__restrict__ src, T *__restrict__ dst)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += P.nb * kWaves) {
+        const int off = so[s], w = (so[s + 1] - off) / kSlice, wp = 2 * (w / 2);
+        for (int k = 0; k < w; k++) {
+            const int from = off + k * kSlice + lane;
+            const int to = k < wp ? off + (k / 2) * 2 * kSlice + 2 * lane + (k & 1) : from;
+            dst[to] = src[from];
+        }
+    }
+}
+
 // float32 copy of a value array (round to nearest)
 __global__ __launch_bounds__(kBlock) void k_to_f32(int64_t m, const double *__restrict__ a,
                                                    float *__restrict__ b)
@@ -608,7 +626,15 @@ void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *
                   double t, const double *g, const uint8_t *mask, double *ks, Box B)
 {
     Part P = make_part(A->n);
-    if (V.v32 && A->sl_d16) {
+    if (V.v32p && A->d16p) {
+        const ColsD16P cols{A->d16p};
+        if (d.f32)
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsD16P>), P.nb, P, A->sl_off, cols,
+                          V.v32p, c, d.f32, t, g, mask, ks, ctx->partials, B);
+        else
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsD16P>), P.nb, P, A->sl_off, cols,
+                          V.v32p, c, d.f64, t, g, mask, ks, ctx->partials, B);
+    } else if (V.v32 && A->sl_d16) {
         const ColsD16 cols{A->sl_d16};
         if (d.f32)
             NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsD16>), P.nb, P, A->sl_off, cols,
@@ -729,7 +755,11 @@ void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int m
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
-    if (V.v32 && A->sl_d16) {
+    if (V.v32p && A->d16p) {
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16P>), P.nb, P, A->sl_off,
+                      ColsD16P{A->d16p}, V.v32p, W.mask, W.z32, W.p32, W.q32, ctx->partials,
+                      ctx->scal, j, max_it, rtol * rtol);
+    } else if (V.v32 && A->sl_d16) {
         NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16>), P.nb, P, A->sl_off,
                       ColsD16{A->sl_d16}, V.v32, W.mask, W.z32, W.p32, W.q32, ctx->partials,
                       ctx->scal, j, max_it, rtol * rtol);
@@ -766,6 +796,18 @@ void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const dou
         k_breakpoint<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f32, g, ctx->partials, B);
     else
         k_breakpoint<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f64, g, ctx->partials, B);
+}
+
+void launch_pair_f32(nn_ctx *ctx, const nn_matrix *A, const float *src, float *dst)
+{
+    Part P = make_part(A->n);
+    k_pair<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, src, dst);
+}
+
+void launch_pair_d16(nn_ctx *ctx, const nn_matrix *A, const short *src, short *dst)
+{
+    Part P = make_part(A->n);
+    k_pair<short><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, src, dst);
 }
 
 void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b)

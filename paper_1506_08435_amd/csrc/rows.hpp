@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "nnqp_internal.hpp"
 
@@ -127,6 +128,11 @@ struct ColsD16 {
     const short *d;
     __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
 };
+// int16 offsets in the paired layout (float32 values only; see nn_matrix::d16p)
+struct ColsD16P {
+    const short *d;
+    __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
+};
 
 // Matrix values are read once per pass.  Float64 values are loaded with the
 // non-temporal hint, which keeps the value stream from displacing the
@@ -151,11 +157,72 @@ __device__ __forceinline__ float ld_val(const float *p) { return *p; }
 #ifndef NNQP_LOAD_PHASE
 #define NNQP_LOAD_PHASE 8
 #endif
+// Paired layout (ColsD16P, float32 values): the pair (2k, 2k+1) of the row
+// of lane l sits at off + 128 k + 2 l, so one 8-byte load brings both values
+// and one 4-byte load both offsets; an odd last column stays column-major.
+template <int WMAX, class Act, class Pre, class X, class Epi>
+__device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__restrict__ so,
+                                                 ColsD16P sc, const float *__restrict__ sv,
+                                                 Act active, Pre pre, X x, Epi epi)
+{
+    using PV = decltype(pre(0));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = P.nb * kWaves;
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += nw) {
+        const int off = so[s];
+        const int w = (so[s + 1] - off) >> 6;   // uniform in the wave
+        const int np = w >> 1;
+        const int row = s * kSlice + lane;
+        const bool act = row < P.n && active(row);
+        const PV pv = act ? pre(row) : PV();
+        if (__ballot(act) == 0) continue;
+        double acc = 0.0;
+        constexpr int H = (WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE) / 2;   // pairs per phase
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX / 2; h0 += H) {
+            int cc[2 * H];
+            float vv[2 * H];
+#pragma unroll
+            for (int k = 0; k < H; k++) {
+                if (h0 + k < np) {
+                    const int e = off + (h0 + k) * 2 * kSlice + 2 * lane;
+                    const float2 v2 = *reinterpret_cast<const float2 *>(sv + e);
+                    const int d2 = *reinterpret_cast<const int *>(sc.d + e);
+                    cc[2 * k] = row + (int)(short)(d2 & 0xffff);
+                    cc[2 * k + 1] = row + (d2 >> 16);
+                    vv[2 * k] = v2.x;
+                    vv[2 * k + 1] = v2.y;
+                } else {
+                    cc[2 * k] = cc[2 * k + 1] = 0;
+                    vv[2 * k] = vv[2 * k + 1] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 2 * H; k++)
+                if (h0 + k / 2 < np) acc += (double)vv[k] * x(cc[k]);
+        }
+        for (int k = WMAX / 2; k < np; k++) {
+            const int e = off + k * 2 * kSlice + 2 * lane;
+            acc += (double)sv[e] * x(sc(e, row));
+            acc += (double)sv[e + 1] * x(sc(e + 1, row));
+        }
+        if (w & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            acc += (double)sv[e] * x(sc(e, row));
+        }
+        if (act) epi(row, acc, pv);
+    }
+}
+
 template <int WMAX, class VT, class Cols, class Act, class Pre, class X, class Epi>
 __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__ so, Cols sc,
                                           const VT *__restrict__ sv, Act active, Pre pre, X x,
                                           Epi epi)
 {
+    if constexpr (std::is_same<Cols, ColsD16P>::value) {
+        sell_rows_paired<WMAX>(P, so, sc, sv, active, pre, x, epi);
+        return;
+    } else {
     constexpr int NS = NNQP_SLICES_IN_FLIGHT;
     using PV = decltype(pre(0));
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -216,6 +283,7 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
             }
             if (act[t]) epi(row[t], acc[t], pv[t]);
         }
+    }
     }
 }
 

@@ -133,8 +133,8 @@ static nn_status read_grad_and_ladder(nn_ctx *ctx, int64_t n, double *grad, doub
 }
 
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
-                     const double *diag, const double *f, const nn_opts *o, double *c,
-                     uint8_t *active, nn_stats *st)
+                     const float *vals32p, const double *diag, const double *f, const nn_opts *o,
+                     double *c, uint8_t *active, nn_stats *st)
 {
     const int64_t n = A->n;
     nn_stats S;
@@ -169,8 +169,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     // the float64 KKT point.
     const bool mixed = vals32 != nullptr;
     Vals VS;
-    if (mixed) VS.v32 = vals32;
-    else VS.v64 = vals;
+    if (mixed) {
+        VS.v32 = vals32;
+        VS.v32p = (vals32p && A->d16p) ? vals32p : nullptr;
+    } else {
+        VS.v64 = vals;
+    }
     const double vb = mixed ? 4.0 : 8.0;                  // bytes per vector entry in CG
     // index bytes of the search and CG passes: float32-value passes read
     // int16 column offsets when the matrix has them
