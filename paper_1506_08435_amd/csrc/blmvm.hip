@@ -47,6 +47,7 @@ namespace {
 
 constexpr int kLmMax = 8;                  // pair slots supported
 constexpr int kLmNV = 4 * kLmMax + 3;      // values of the pair pass at kLmMax
+static_assert(kLmMax * kLmMax <= 64, "one lane per table entry in the coefficient kernel");
 constexpr double kLmMu = 0.01;             // sufficient-decrease constant
 constexpr double kLmCurv = 1e-12;          // pair acceptance: s.y > kLmCurv |s| |y|
 constexpr int kLmRefresh = 50;             // iterations between gradient refreshes
@@ -174,13 +175,27 @@ __global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double 
     __shared__ double t[NV];
     __shared__ double sy[M][M], yy[M][M];
     const int lane = threadIdx.x;
+    // every load is issued before the first use (the state scalars, the
+    // tables and the partials), so their latencies overlap
+    const int count0 = st->count, head0 = st->head, pend0 = st->pending;
+    const double gam0 = st->gamma;
+    double tsy = 0.0, tyy = 0.0;
+    if (lane < M * M) {
+        tsy = st->sy[lane / M][lane % M];
+        tyy = st->yy[lane / M][lane % M];
+    }
     {
         double acc[NV];
 #pragma unroll
         for (int k = 0; k < NV; k++) acc[k] = 0.0;
-        for (int b = lane; b < nb; b += 64)
+        // nb <= kMaxBlocks = 512: at most eight blocks per lane
 #pragma unroll
-            for (int k = 0; k < NV; k++) acc[k] += part[k * kMaxBlocks + b];
+        for (int r = 0; r < kMaxBlocks / 64; r++) {
+            const int b = lane + 64 * r;
+            if (b < nb)
+#pragma unroll
+                for (int k = 0; k < NV; k++) acc[k] += part[k * kMaxBlocks + b];
+        }
 #pragma unroll
         for (int k = 0; k < NV; k++) {
             double v = acc[k];
@@ -188,17 +203,17 @@ __global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double 
             if (lane == 0) t[k] = v;
         }
     }
-    for (int e = lane; e < M * M; e += 64) {
-        sy[e / M][e % M] = st->sy[e / M][e % M];
-        yy[e / M][e % M] = st->yy[e / M][e % M];
+    if (lane < M * M) {
+        sy[lane / M][lane % M] = tsy;
+        yy[lane / M][lane % M] = tyy;
     }
     __syncthreads();
     if (lane == 0) {
-        int count = st->count, head = st->head;
-        double gam = st->gamma;
+        int count = count0, head = head0;
+        double gam = gam0;
         st->pg2 = t[0];
         st->nonfinite = t[1];
-        if (st->pending || applied) {
+        if (pend0 || applied) {
             const double sny = t[2 + 2 * M + head], yny = t[2 + 3 * M + head], ss = t[2 + 4 * M];
             const bool ok = isfinite(sny) && isfinite(yny) && yny > 0.0 &&
                             sny > kLmCurv * sqrt(ss) * sqrt(yny);
@@ -261,9 +276,9 @@ __global__ __launch_bounds__(64) void kl_coef(int nb, LmState *st, const double 
         }
     }
     __syncthreads();
-    for (int e = lane; e < M * M; e += 64) {
-        st->sy[e / M][e % M] = sy[e / M][e % M];
-        st->yy[e / M][e % M] = yy[e / M][e % M];
+    if (lane < M * M) {
+        st->sy[lane / M][lane % M] = sy[lane / M][lane % M];
+        st->yy[lane / M][lane % M] = yy[lane / M][lane % M];
     }
 }
 
