@@ -39,6 +39,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -902,11 +903,18 @@ struct Shape {
 };
 
 // size class -> tuned shape (per process; the class is (log2 rows, widest
-// slice class, precision))
+// slice class, precision)).  Contexts on different threads share it, so every
+// access holds shape_mutex(); the launch shape changes no arithmetic.
 std::map<std::tuple<int, int, int>, Shape> &shape_cache()
 {
     static std::map<std::tuple<int, int, int>, Shape> m;
     return m;
+}
+
+std::mutex &shape_mutex()
+{
+    static std::mutex mu;
+    return mu;
 }
 
 int width_class(int wmax) { return wmax <= 8 ? 8 : (wmax <= 16 ? 16 : 32); }
@@ -1307,9 +1315,16 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     // ---- launch shape for this size class
     const auto key = std::make_tuple((int)std::log2((double)R), width_class(wmax), (int)mixed);
     auto &cache = shape_cache();
-    if (cache.count(key)) {
-        sh = cache[key];
-    } else if (n_pr > 0) {
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(shape_mutex());
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            sh = it->second;
+            cached = true;
+        }
+    }
+    if (!cached && n_pr > 0) {
         // time the gradient pass over all running members for each candidate
         // shape; it writes only g and the slice partials, which the first
         // global step overwrites
@@ -1334,7 +1349,10 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                 }
             }
         sh = pick;
-        cache[key] = sh;
+        {
+            std::lock_guard<std::mutex> lk(shape_mutex());
+            cache[key] = sh;
+        }
         if (o->verbose)
             std::fprintf(stderr,
                          "nnqp batch shape: %lld rows, slice width %d -> %d threads, %d blocks/CU\n",

@@ -13,7 +13,9 @@ each step a non-negative QP warm-started from the previous one.  The server:
   device for all of its steps;
 * runs ticks: one batched call (nn_step_transient_batch) advances every
   resident request by one step; requests that arrive or finish assembling
-  join at the next tick, finished requests leave and free their memory.
+  join at the next tick, finished requests leave and free their memory;
+* routes requests by size to lanes that tick independently on their own
+  streams, so small requests are not held by a large one's step.
 
 Because a batch member's arithmetic does not depend on the other members, a
 request's result is bitwise the same whether it is served alone or in any mix.
@@ -75,6 +77,7 @@ class Report:
     deferred: int                 # requests that waited for memory before admission
     peak_bytes: int
     budget: int
+    lane_ticks: list = dataclasses.field(default_factory=list)   # ticks run by each lane
 
     def summary(self) -> dict:
         done = [r for r in self.results if r.status == 0]
@@ -88,7 +91,8 @@ class Report:
                 "makespan_s": self.makespan, "dof_steps_per_s": dof_steps / self.makespan,
                 "requests_per_s": len(done) / self.makespan, "ticks": self.ticks,
                 "mean_resident_per_tick": self.mean_batch, "admission_waits": self.deferred,
-                "peak_resident_bytes": self.peak_bytes, "hbm_budget_bytes": self.budget}
+                "peak_resident_bytes": self.peak_bytes, "hbm_budget_bytes": self.budget,
+                "lane_ticks": list(self.lane_ticks)}
 
 
 def estimate_bytes(problem, precision: int) -> int:
@@ -105,15 +109,39 @@ def estimate_bytes(problem, precision: int) -> int:
     return int(b + 17.0 * n)                    # f, c, active set
 
 
+class _Lane:
+    """One batching lane: its own context and stream, queue and resident set."""
+
+    def __init__(self, idx, ctx, stream):
+        self.idx = idx
+        self.ctx = ctx
+        self.stream = stream
+        self.pending = collections.deque()
+        self.waiting = collections.deque()
+        self.assembling = {}
+        self.resident = []
+        self.ticks = 0
+        self.batch_sum = 0
+
+
 class Server:
+    """Continuous batching of transient requests.
+
+    Requests are routed by size (free DOF estimated from the Dirichlet mask)
+    to `len(lane_bounds) + 1` lanes.  Each lane runs its own tick loop on its
+    own context and stream, so the small requests of one lane step while a
+    large request of another lane is still inside its step (without lanes a
+    tick lasts as long as its slowest member); all lanes share one HBM
+    budget and admit first-in first-out within the lane.
+    """
+
     def __init__(self, device: int = 0, hbm_budget: Optional[int] = None,
                  precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
                  inner_rtol: float = 0.1, assemble_workers: int = 2, keep_states: bool = False,
-                 bounds=(0.0, math.inf)):
+                 bounds=(0.0, math.inf), lane_bounds=(30000, 300000)):
         import torch
         self.torch = torch
         self.device = device
-        self.ctx = nnqp.Context(device)
         self.precision = precision
         self.dt = dt
         # bounds c_min <= c <= c_max of every step (Sec. 2.2.2, eq. Eq:non-negative)
@@ -123,6 +151,7 @@ class Server:
         self.budget = int(hbm_budget) if hbm_budget else int(0.75 * free)
         self.workers = assemble_workers
         self.keep_states = keep_states
+        self.lane_bounds = tuple(sorted(lane_bounds))
         self._tls = threading.local()
 
     # worker-thread assembly on the thread's own context and stream
@@ -137,95 +166,126 @@ class Server:
         wctx.stream.synchronize()
         return K, F
 
+    def _lane_of(self, req: Request) -> int:
+        n = int((np.asarray(req.problem.dirichlet) == 0).sum())
+        return sum(1 for b in self.lane_bounds if n >= b)
+
     def run(self, requests: List[Request]) -> Report:
         torch = self.torch
         reqs = sorted(requests, key=lambda r: r.arrival)
         results = {r.rid: Result(r.rid, 0, r.steps, r.arrival) for r in reqs}
-        pending = collections.deque(reqs)
-        waiting = collections.deque()
-        assembling = {}
-        resident = []
-        used = 0
-        peak = 0
-        ticks = 0
-        batch_sum = 0
+        lanes = []
+        for k in range(len(self.lane_bounds) + 1):
+            stream = torch.cuda.Stream(self.device)
+            lanes.append(_Lane(k, nnqp.Context(self.device, stream=stream), stream))
+        for r in reqs:
+            lanes[self._lane_of(r)].pending.append(r)
+        shared = {"used": 0, "peak": 0}
+        lock = threading.Lock()
         waited = set()
         pool = cf.ThreadPoolExecutor(max_workers=self.workers)
         t0 = time.perf_counter()
+        errors = []
+
+        def lane_loop(L: _Lane):
+            try:
+                with torch.cuda.stream(L.stream):
+                    self._lane_loop(L, results, shared, lock, waited, pool, t0)
+            except BaseException as e:   # surfaced after the lanes join
+                errors.append(e)
+
+        threads = [threading.Thread(target=lane_loop, args=(L,)) for L in lanes]
         try:
-            while pending or waiting or assembling or resident:
-                now = time.perf_counter() - t0
-                while pending and pending[0].arrival <= now:
-                    waiting.append(pending.popleft())
-                # admission: first in, first out, while the estimate fits
-                while waiting:
-                    req = waiting[0]
-                    est = estimate_bytes(req.problem, self.precision)
-                    if est > self.budget:
-                        waiting.popleft()
-                        res = results[req.rid]
-                        res.status = NN_EBUDGET
-                        res.finished = time.perf_counter() - t0
-                        continue
-                    if used + est > self.budget:
-                        waited.add(req.rid)
-                        break
-                    waiting.popleft()
-                    used += est
-                    peak = max(peak, used)
-                    results[req.rid].admitted = time.perf_counter() - t0
-                    assembling[pool.submit(self._assemble, req)] = (req, est)
-                # assembled requests become resident
-                for fut in [f for f in assembling if f.done()]:
-                    req, est = assembling.pop(fut)
-                    K, F = fut.result()
-                    nb = K.bytes(self.precision) + 17 * K.n
-                    used += nb - est
-                    peak = max(peak, used)
-                    c = torch.zeros(max(K.n, 1), dtype=torch.float64, device=self.ctx.device)
-                    act = torch.empty(max(K.n, 1), dtype=torch.uint8, device=self.ctx.device)
-                    results[req.rid].n = K.n
-                    resident.append({"req": req, "K": K, "F": F, "c": c, "act": act, "bytes": nb,
-                                     "done": 0})
-                if resident:
-                    tnow = time.perf_counter() - t0
-                    for s in resident:
-                        r = results[s["req"].rid]
-                        if math.isnan(r.started):
-                            r.started = tnow
-                    _, _, stats, st = self.ctx.step_transient_batch(
-                        [s["K"] for s in resident], self.dt, [s["F"] for s in resident],
-                        [s["c"] for s in resident], opts=self.opts,
-                        actives=[s["act"] for s in resident], allow_fail=True)
-                    ticks += 1
-                    batch_sum += len(resident)
-                    tend = time.perf_counter() - t0
-                    keep = []
-                    for s, stt in zip(resident, stats):
-                        r = results[s["req"].rid]
-                        r.step_stats.append(stt)
-                        s["done"] += 1
-                        if stt["status"] != 0 and r.status == 0:
-                            r.status = stt["status"]
-                        if s["done"] >= s["req"].steps or stt["status"] not in (0,):
-                            r.finished = tend
-                            if self.keep_states:
-                                r.c = s["c"][:s["K"].n].clone()
-                            s["K"].free()
-                            used -= s["bytes"]
-                        else:
-                            keep.append(s)
-                    resident = keep
-                elif assembling:
-                    cf.wait(list(assembling), timeout=0.05, return_when=cf.FIRST_COMPLETED)
-                elif pending and not waiting:
-                    time.sleep(max(0.0, min(0.05, pending[0].arrival - (time.perf_counter() - t0))))
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
         finally:
             pool.shutdown(wait=True)
+        if errors:
+            raise errors[0]
         torch.cuda.synchronize()
         makespan = time.perf_counter() - t0
+        ticks = sum(L.ticks for L in lanes)
+        batch_sum = sum(L.batch_sum for L in lanes)
         return Report([results[r.rid] for r in reqs], makespan, ticks,
-                      batch_sum / max(ticks, 1), len(waited), peak, self.budget)
+                      batch_sum / max(ticks, 1), len(waited), shared["peak"], self.budget,
+                      [L.ticks for L in lanes])
+
+    def _lane_loop(self, L: _Lane, results, shared, lock, waited, pool, t0):
+        torch = self.torch
+        while L.pending or L.waiting or L.assembling or L.resident:
+            now = time.perf_counter() - t0
+            while L.pending and L.pending[0].arrival <= now:
+                L.waiting.append(L.pending.popleft())
+            # admission: first in, first out within the lane, while the estimate fits
+            while L.waiting:
+                req = L.waiting[0]
+                est = estimate_bytes(req.problem, self.precision)
+                if est > self.budget:
+                    L.waiting.popleft()
+                    res = results[req.rid]
+                    res.status = NN_EBUDGET
+                    res.finished = time.perf_counter() - t0
+                    continue
+                with lock:
+                    if shared["used"] + est > self.budget:
+                        waited.add(req.rid)
+                        break
+                    shared["used"] += est
+                    shared["peak"] = max(shared["peak"], shared["used"])
+                L.waiting.popleft()
+                results[req.rid].admitted = time.perf_counter() - t0
+                L.assembling[pool.submit(self._assemble, req)] = (req, est)
+            # assembled requests become resident
+            for fut in [f for f in L.assembling if f.done()]:
+                req, est = L.assembling.pop(fut)
+                K, F = fut.result()
+                nb = K.bytes(self.precision) + 17 * K.n
+                with lock:
+                    shared["used"] += nb - est
+                    shared["peak"] = max(shared["peak"], shared["used"])
+                c = torch.zeros(max(K.n, 1), dtype=torch.float64, device=L.ctx.device)
+                act = torch.empty(max(K.n, 1), dtype=torch.uint8, device=L.ctx.device)
+                results[req.rid].n = K.n
+                L.resident.append({"req": req, "K": K, "F": F, "c": c, "act": act, "bytes": nb,
+                                   "done": 0})
+            if L.resident:
+                tnow = time.perf_counter() - t0
+                for s in L.resident:
+                    r = results[s["req"].rid]
+                    if math.isnan(r.started):
+                        r.started = tnow
+                _, _, stats, st = L.ctx.step_transient_batch(
+                    [s["K"] for s in L.resident], self.dt, [s["F"] for s in L.resident],
+                    [s["c"] for s in L.resident], opts=self.opts,
+                    actives=[s["act"] for s in L.resident], allow_fail=True)
+                L.ticks += 1
+                L.batch_sum += len(L.resident)
+                tend = time.perf_counter() - t0
+                keep = []
+                for s, stt in zip(L.resident, stats):
+                    r = results[s["req"].rid]
+                    r.step_stats.append(stt)
+                    s["done"] += 1
+                    if stt["status"] != 0 and r.status == 0:
+                        r.status = stt["status"]
+                    if s["done"] >= s["req"].steps or stt["status"] not in (0,):
+                        r.finished = tend
+                        if self.keep_states:
+                            r.c = s["c"][:s["K"].n].clone()
+                        s["K"].free()
+                        with lock:
+                            shared["used"] -= s["bytes"]
+                    else:
+                        keep.append(s)
+                L.resident = keep
+            elif L.assembling:
+                cf.wait(list(L.assembling), timeout=0.05, return_when=cf.FIRST_COMPLETED)
+            elif L.pending and not L.waiting:
+                time.sleep(max(0.0, min(0.05, L.pending[0].arrival - (time.perf_counter() - t0))))
+            elif L.waiting:
+                time.sleep(0.002)   # waiting for memory that another lane will free
 
 
 def solve_alone(req: Request, precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,

@@ -62,6 +62,33 @@ def test_served_result_equals_alone(prec):
 
 
 @pytest.mark.gpu
+def test_lanes_tick_independently_and_equal_alone():
+    """Requests routed to three size lanes (free DOF < 400, < 1200, larger)
+    run on three streams at once; each result is still bitwise the request
+    run alone, and the HBM budget shared by the lanes holds."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import Server, estimate_bytes, solve_alone
+    reqs = _requests(12, steps=3, gap=0.0005, seed=9)
+    sizes = [int((np.asarray(r.problem.dirichlet) == 0).sum()) for r in reqs]
+    lanes = [sum(1 for b in (400, 1200) if n >= b) for n in sizes]
+    assert sorted(set(lanes)) == [0, 1, 2], sizes
+    budget = int(0.6 * sum(estimate_bytes(r.problem, nnqp.NN_FP64) for r in reqs))
+    srv = Server(hbm_budget=budget, tol=1e-10, inner_rtol=0.1, keep_states=True,
+                 lane_bounds=(400, 1200))
+    rep = srv.run(reqs)
+    assert all(r.status == 0 for r in rep.results)
+    assert all(t > 0 for t in rep.lane_ticks) and len(rep.lane_ticks) == 3
+    assert rep.peak_bytes <= budget
+    ctx = nnqp.Context(0)
+    for req, res in zip(reqs, rep.results):
+        c_alone, st_alone = solve_alone(req, tol=1e-10, inner_rtol=0.1, ctx=ctx)
+        assert torch.equal(res.c, c_alone), req.rid
+        assert [s["cg_its"] for s in res.step_stats] == [s["cg_its"] for s in st_alone]
+    print(rep.summary())
+
+
+@pytest.mark.gpu
 def test_served_steps_match_oracle():
     from paper_1506_08435_amd.serve import Server
     reqs = _requests(4, steps=3)
