@@ -200,7 +200,10 @@ nn_status nn_matrix_info(const nn_matrix *A, int64_t *n, int64_t *nnz, int *has_
 nn_status nn_matrix_export(nn_ctx *ctx, const nn_matrix *A, int64_t *rowptr, int32_t *col,
                            double *val, double *mval);
 /* Device bytes the matrix and one solve's work vectors occupy for a precision
- * (used to admit requests against an HBM budget). */
+ * (used to admit requests against an HBM budget), including the paired value
+ * and offset copies that single-problem solves have already made (the first
+ * single-problem solve of a matrix whose column offsets fit int16 adds
+ * 10 B per sliced-ELL entry in float64, 6 B in mixed precision). */
 nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes);
 void nn_matrix_free(nn_ctx *ctx, nn_matrix *A);
 

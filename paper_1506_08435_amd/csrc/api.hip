@@ -144,7 +144,11 @@ namespace nnqp {
 
 // The paired int16 offsets (and, when the float32 values exist, the paired
 // float32 values of K) used by the single-problem float32 passes.
-nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K)
+#ifndef NNQP_PAIR_F64
+#define NNQP_PAIR_F64 1   // float64 solves read the paired layout when it exists
+#endif
+
+nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K, bool f64)
 {
     if (!K->sl_d16 || K->n == 0) return NN_OK;
     const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
@@ -157,6 +161,11 @@ nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K)
         if (hipMalloc(&K->val32p, sizeof(float) * m) != hipSuccess)
             return fail(ctx, NN_EOOM, "paired float32 allocation");
         launch_pair_f32(ctx, K, K->val32, K->val32p);
+    }
+    if (f64 && !K->val64p) {
+        if (hipMalloc(&K->val64p, sizeof(double) * m) != hipSuccess)
+            return fail(ctx, NN_EOOM, "paired float64 allocation");
+        launch_pair_f64(ctx, K, K->val, K->val64p);
     }
     NN_HIP_TRY(ctx, hipGetLastError());
     return NN_OK;
@@ -179,7 +188,7 @@ nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed)
     launch_diag(ctx, K, K->kt, K->kt_diag);
     if (K->kt32) launch_to_f32(ctx, K->nsell, K->kt, K->kt32);
     if (K->kt32 && K->sl_d16) {
-        nn_status st = ensure_paired(ctx, K);
+        nn_status st = ensure_paired(ctx, K, false);
         if (st != NN_OK) return st;
         if (!K->kt32p &&
             hipMalloc(&K->kt32p, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
@@ -441,6 +450,11 @@ nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes)
     if (A->mval) b += 16.0 * ns + 8.0 * n;                  // capacity + transient values, diag
     b += 11.0 * 8.0 * n + n;                                // solver work vectors + mask
     if (precision == NN_MIXED) b += 4.0 * ns + 40.0 * n;    // float32 values and vectors
+    // paired copies already made by single-problem solves
+    if (A->d16p) b += 2.0 * ns;
+    if (A->val32p) b += 4.0 * ns;
+    if (A->kt32p) b += 4.0 * ns;
+    if (A->val64p) b += 8.0 * ns;
     *bytes = (size_t)b;
     return NN_OK;
 }
@@ -454,6 +468,7 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
         if (p) (void)hipFree(p);
     if (A->sl_d16) (void)hipFree(A->sl_d16);
     if (A->d16p) (void)hipFree(A->d16p);
+    if (A->val64p) (void)hipFree(A->val64p);
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
     for (double *p : dv)
         if (p) (void)hipFree(p);
@@ -518,10 +533,12 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
             NN_HIP_TRY(ctx, hipGetLastError());
         }
         v32 = K->val32;
-        if ((st = ensure_paired(ctx, K)) != NN_OK) return st;
     }
-    return solve_impl(ctx, K, K->val, v32, v32 ? K->val32p : nullptr, K->diag, f_dev, opts, c_dev,
-                      active_dev, stats);
+    // paired copies for the CG and search passes (when the int16 offsets exist)
+    const bool pair64 = NNQP_PAIR_F64 && v32 == nullptr;
+    if ((v32 || pair64) && (st = ensure_paired(ctx, K, pair64)) != NN_OK) return st;
+    return solve_impl(ctx, K, K->val, v32, v32 ? K->val32p : nullptr, v32 ? nullptr : K->val64p,
+                      K->diag, f_dev, opts, c_dev, active_dev, stats);
 }
 
 
@@ -549,15 +566,15 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     if (st != NN_OK) return st;
     const int64_t n = K->n;
     const bool mixed = opts->precision == NN_MIXED;
-    if (n == 0) return solve_impl(ctx, K, K->val, nullptr, nullptr, K->diag, f_dev, opts, c_dev,
-                                    active_dev, stats);
+    if (n == 0) return solve_impl(ctx, K, K->val, nullptr, nullptr, nullptr, K->diag, f_dev, opts,
+                                    c_dev, active_dev, stats);
     if ((st = ensure_transient(ctx, K, dt, mixed)) != NN_OK) return st;
     if ((st = ensure_workspace(ctx, n)) != NN_OK) return st;
     launch_transient_rhs(ctx, K, c_dev, f_dev, dt, ctx->ws.ft);
     nn_opts o = *opts;
     o.c0_mode = 1;   // warm start from c^(n)
     if (o.method == NN_BLMVM) return blmvm_impl(ctx, K, K->kt, ctx->ws.ft, &o, c_dev, active_dev, stats);
-    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32p : nullptr,
+    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32p : nullptr, nullptr,
                       K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev, stats);
 }
 

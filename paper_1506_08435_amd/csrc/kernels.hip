@@ -289,8 +289,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
 // formed together, using K p = K z + beta (K p_old): only z is gathered, and
 // p, q are updated in place on the free rows; partials of p.q into SLOT_Q.
 // Columns outside the free set contribute 0 because z vanishes there.
+#ifndef NNQP_CG_ATTR
+#define NNQP_CG_ATTR
+#endif
 template <int WMAX, class VT, class VV, class Cols>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restrict__ so, Cols sc,
+__global__ __launch_bounds__(kBlock) NNQP_CG_ATTR void k_cg_spmv(Part P, const int *__restrict__ so, Cols sc,
                                                     const VT *__restrict__ v,
                                                     const uint8_t *__restrict__ mask,
                                                     const VV *__restrict__ z,
@@ -650,6 +653,14 @@ void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *
         else
             NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsI32>), P.nb, P, A->sl_off, cols,
                           V.v32, c, d.f64, t, g, mask, ks, ctx->partials, B);
+    } else if (V.v64p && A->d16p) {
+        const ColsD16P cols{A->d16p};
+        if (d.f32)
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, double, float, ColsD16P>), P.nb, P, A->sl_off, cols,
+                          V.v64p, c, d.f32, t, g, mask, ks, ctx->partials, B);
+        else
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, double, double, ColsD16P>), P.nb, P, A->sl_off, cols,
+                          V.v64p, c, d.f64, t, g, mask, ks, ctx->partials, B);
     } else {
         const ColsI32 cols{A->sl_col};
         if (d.f32)
@@ -767,6 +778,10 @@ void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int m
         NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsI32>), P.nb, P, A->sl_off,
                       ColsI32{A->sl_col}, V.v32, W.mask, W.z32, W.p32, W.q32, ctx->partials,
                       ctx->scal, j, max_it, rtol * rtol);
+    } else if (V.v64p && A->d16p) {
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double, ColsD16P>), P.nb, P, A->sl_off,
+                      ColsD16P{A->d16p}, V.v64p, W.mask, W.z, W.p0, W.q, ctx->partials, ctx->scal,
+                      j, max_it, rtol * rtol);
     } else {
         NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double, ColsI32>), P.nb, P, A->sl_off,
                       ColsI32{A->sl_col}, V.v64, W.mask, W.z, W.p0, W.q, ctx->partials, ctx->scal,
@@ -802,6 +817,12 @@ void launch_pair_f32(nn_ctx *ctx, const nn_matrix *A, const float *src, float *d
 {
     Part P = make_part(A->n);
     k_pair<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, src, dst);
+}
+
+void launch_pair_f64(nn_ctx *ctx, const nn_matrix *A, const double *src, double *dst)
+{
+    Part P = make_part(A->n);
+    k_pair<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, src, dst);
 }
 
 void launch_pair_d16(nn_ctx *ctx, const nn_matrix *A, const short *src, short *dst)

@@ -101,6 +101,7 @@ struct Vals {
     const double *v64 = nullptr;
     const float *v32 = nullptr;
     const float *v32p = nullptr;   // v32 in the paired layout (with A->d16p), or null
+    const double *v64p = nullptr;  // v64 in the paired layout (with A->d16p), or null
 };
 
 // Bounds lo <= c <= hi of a constrained solve (hi may be +inf; lo finite).
@@ -134,13 +135,14 @@ struct nn_matrix {
     int *sl_off = nullptr;     // [nslices+1] first entry of each 64-row slice
     int *sl_col = nullptr;     // [nsell] column of each sliced-ELL entry (padding: own row)
     short *sl_d16 = nullptr;   // [nsell] col - row as int16 when every offset fits, else null
-    // Paired copies for the float32 passes of the single-problem solver (made
-    // with the float32 values when sl_d16 exists): within each slice, entries
-    // 2k and 2k+1 of a row sit side by side (one 8-byte value load and one
-    // 4-byte offset load per pair); an odd last column keeps its place.
+    // Paired copies for the CG and search passes of the single-problem solver
+    // (made when sl_d16 exists): within each slice, entries 2k and 2k+1 of a
+    // row sit side by side (one 8- or 16-byte value load and one 4-byte offset
+    // load per pair); an odd last column keeps its place.
     short *d16p = nullptr;
     float *val32p = nullptr;
     float *kt32p = nullptr;
+    double *val64p = nullptr;
     double *val = nullptr;     // K values, sliced-ELL order [nsell]
     double *mval = nullptr;    // M values, sliced-ELL order (or null)
     double *diag = nullptr;    // diag(K)
@@ -262,6 +264,7 @@ void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b);
 // paired copies of a sliced-ELL array of A (layout of nn_matrix::d16p)
 void launch_pair_f32(nn_ctx *ctx, const nn_matrix *A, const float *src, float *dst);
 void launch_pair_d16(nn_ctx *ctx, const nn_matrix *A, const short *src, short *dst);
+void launch_pair_f64(nn_ctx *ctx, const nn_matrix *A, const double *src, double *dst);
 // active = 1 where c == lo, 2 where c == hi, else 0
 void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active, Box B);
 // out = m/dt + k
@@ -284,10 +287,11 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
 
 // ---------------------------------------------------------------- solver (solver.hip)
 // vals: float64 values (gradient, always); vals32: float32 values for the
-// searches and the inner CG (mixed precision) or null.
+// searches and the inner CG (mixed precision) or null; vals32p / vals64p: the
+// same in the paired layout, or null.
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
-                     const float *vals32p, const double *diag, const double *f, const nn_opts *o,
-                     double *c, uint8_t *active, nn_stats *st);
+                     const float *vals32p, const double *vals64p, const double *diag,
+                     const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st);
 
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);
 

@@ -128,7 +128,7 @@ struct ColsD16 {
     const short *d;
     __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
 };
-// int16 offsets in the paired layout (float32 values only; see nn_matrix::d16p)
+// int16 offsets in the paired layout (see nn_matrix::d16p)
 struct ColsD16P {
     const short *d;
     __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
@@ -141,6 +141,23 @@ struct ColsD16P {
 // normally.
 __device__ __forceinline__ double ld_val(const double *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float ld_val(const float *p) { return *p; }
+
+// Both values of a pair in the paired layout (8-byte aligned for float32,
+// 16-byte aligned for float64): one 8- or 16-byte load, with the same hint
+// choice as ld_val.
+__device__ __forceinline__ void ld_pair(const float *p, float &a, float &b)
+{
+    const float2 v = *reinterpret_cast<const float2 *>(p);
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void ld_pair(const double *p, double &a, double &b)
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p));
+    a = v.x;
+    b = v.y;
+}
 
 // Sliced-ELL product row by row: for each owned row i with active(i), the sum
 // over the row's entries k = 0..w-1 (column order) of val * x(col), then
@@ -157,12 +174,15 @@ __device__ __forceinline__ float ld_val(const float *p) { return *p; }
 #ifndef NNQP_LOAD_PHASE
 #define NNQP_LOAD_PHASE 8
 #endif
-// Paired layout (ColsD16P, float32 values): the pair (2k, 2k+1) of the row
-// of lane l sits at off + 128 k + 2 l, so one 8-byte load brings both values
-// and one 4-byte load both offsets; an odd last column stays column-major.
-template <int WMAX, class Act, class Pre, class X, class Epi>
+// Paired layout (ColsD16P): the pair (2k, 2k+1) of the row of lane l sits at
+// off + 128 k + 2 l, so one 8-byte (float32) or 16-byte (float64) load brings
+// both values and one 4-byte load both offsets; an odd last column stays
+// column-major and is loaded after the pairs (loading it with the last pairs
+// holds more registers and, for float64 values, costs a wave per SIMD: the
+// 128^3 CG matrix pass went from 78 to 100 us).
+template <int WMAX, class VT, class Act, class Pre, class X, class Epi>
 __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__restrict__ so,
-                                                 ColsD16P sc, const float *__restrict__ sv,
+                                                 ColsD16P sc, const VT *__restrict__ sv,
                                                  Act active, Pre pre, X x, Epi epi)
 {
     using PV = decltype(pre(0));
@@ -181,20 +201,18 @@ __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__res
 #pragma unroll
         for (int h0 = 0; h0 < WMAX / 2; h0 += H) {
             int cc[2 * H];
-            float vv[2 * H];
+            VT vv[2 * H];
 #pragma unroll
             for (int k = 0; k < H; k++) {
                 if (h0 + k < np) {
                     const int e = off + (h0 + k) * 2 * kSlice + 2 * lane;
-                    const float2 v2 = *reinterpret_cast<const float2 *>(sv + e);
+                    ld_pair(sv + e, vv[2 * k], vv[2 * k + 1]);
                     const int d2 = *reinterpret_cast<const int *>(sc.d + e);
                     cc[2 * k] = row + (int)(short)(d2 & 0xffff);
                     cc[2 * k + 1] = row + (d2 >> 16);
-                    vv[2 * k] = v2.x;
-                    vv[2 * k + 1] = v2.y;
                 } else {
                     cc[2 * k] = cc[2 * k + 1] = 0;
-                    vv[2 * k] = vv[2 * k + 1] = 0.f;
+                    vv[2 * k] = vv[2 * k + 1] = VT(0);
                 }
             }
 #pragma unroll
@@ -203,12 +221,12 @@ __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__res
         }
         for (int k = WMAX / 2; k < np; k++) {
             const int e = off + k * 2 * kSlice + 2 * lane;
-            acc += (double)sv[e] * x(sc(e, row));
-            acc += (double)sv[e + 1] * x(sc(e + 1, row));
+            acc += (double)ld_val(sv + e) * x(sc(e, row));
+            acc += (double)ld_val(sv + e + 1) * x(sc(e + 1, row));
         }
         if (w & 1) {
             const int e = off + (w - 1) * kSlice + lane;
-            acc += (double)sv[e] * x(sc(e, row));
+            acc += (double)ld_val(sv + e) * x(sc(e, row));
         }
         if (act) epi(row, acc, pv);
     }

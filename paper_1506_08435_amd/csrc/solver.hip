@@ -133,8 +133,8 @@ static nn_status read_grad_and_ladder(nn_ctx *ctx, int64_t n, double *grad, doub
 }
 
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
-                     const float *vals32p, const double *diag, const double *f, const nn_opts *o,
-                     double *c, uint8_t *active, nn_stats *st)
+                     const float *vals32p, const double *vals64p, const double *diag,
+                     const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st)
 {
     const int64_t n = A->n;
     nn_stats S;
@@ -174,11 +174,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         VS.v32p = (vals32p && A->d16p) ? vals32p : nullptr;
     } else {
         VS.v64 = vals;
+        VS.v64p = (vals64p && A->d16p) ? vals64p : nullptr;
     }
     const double vb = mixed ? 4.0 : 8.0;                  // bytes per vector entry in CG
-    // index bytes of the search and CG passes: float32-value passes read
-    // int16 column offsets when the matrix has them
-    const double ib = (mixed && A->sl_d16) ? 2.0 : 4.0;
+    // index bytes of the search and CG passes: int16 column offsets when the
+    // pass reads them (float32 values, or the paired float64 layout)
+    const double ib = ((mixed && A->sl_d16) || VS.v64p) ? 2.0 : 4.0;
     const double spmv_s = 4.0 * (n + 1) + (ib + vb) * A->nnz + 16.0 * n;
     Dir dir_g, dir_w;
     dir_g.f64 = W.g;
