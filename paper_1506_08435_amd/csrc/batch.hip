@@ -172,7 +172,7 @@ template <int NV, class Take, class Body>
 __device__ __forceinline__ void for_bslices(const BDev &B, const int (&ops)[NV], Take take,
                                             Body body)
 {
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
     const int nlist = B.cnt[0];
@@ -328,7 +328,7 @@ __global__ void kb_gather(BDev B, const int64_t *__restrict__ ebase, int *__rest
                           double *__restrict__ gv64, float *__restrict__ gv32,
                           double *__restrict__ dg, int *__restrict__ rlen, int copy_f)
 {
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
     for (int s = blockIdx.x * wpb + wid; s < B.nslices; s += nw) {
@@ -362,7 +362,7 @@ __global__ void kb_gather(BDev B, const int64_t *__restrict__ ebase, int *__rest
 // Copy the solution back to the members' vectors, and the active sets.
 __global__ void kb_scatter(BDev B)
 {
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int nw = gridDim.x * wpb;
     for (int s = blockIdx.x * wpb + wid; s < B.nslices; s += nw) {
@@ -450,7 +450,7 @@ __device__ __forceinline__ bool member_reduce(const BDev &B, int p, const int (&
     for (int o = 32; o >= 1; o >>= 1)
 #pragma unroll
         for (int k = 0; k < NV; k++) a[k] = bcomb(ops[k], a[k], __shfl_xor(a[k], o, 64));
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < NV; k++) sh[wid][k] = a[k];

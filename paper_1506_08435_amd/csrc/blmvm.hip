@@ -83,7 +83,7 @@ template <int NV>
 __device__ __forceinline__ void block_sums(double (&a)[NV], double *part)
 {
     __shared__ double sh[kWaves][NV];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id();
 #pragma unroll
     for (int k = 0; k < NV; k++)
 #pragma unroll

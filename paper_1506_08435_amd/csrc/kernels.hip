@@ -483,7 +483,7 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_pair(Part P, const int *__restrict__ so,
                                                  const T *__restrict__ src, T *__restrict__ dst)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id();
     for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += P.nb * kWaves) {
         const int off = so[s], w = (so[s + 1] - off) / kSlice, wp = 2 * (w / 2);
         for (int k = 0; k < w; k++) {
