@@ -171,30 +171,37 @@ nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K, bool f64)
     return NN_OK;
 }
 
-// M/dt + K values for a backward-Euler step (formed once per dt, kept with K)
-nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed)
+// M/dt + K values for a backward-Euler step (formed once per dt, kept with K).
+// `paired`: the single-problem solver will read the paired copy for this
+// precision (the batched solver reads the column-major values only).  Every
+// copy that exists is re-formed when dt changes.
+nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, bool paired)
 {
     const int64_t n = K->n;
-    if (n == 0 || (K->kt && K->kt_dt == dt && (!mixed || K->kt32))) return NN_OK;
+    if (n == 0) return NN_OK;
+    const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
+    const bool want32p = paired && mixed && K->sl_d16;
+    const bool want64p = paired && !mixed && NNQP_PAIR_F64 && K->sl_d16;
+    const bool fresh = K->kt && K->kt_dt == dt;
+    if (fresh && (!mixed || K->kt32) && (!want32p || K->kt32p) && (!want64p || K->kt64p))
+        return NN_OK;
     if (!K->kt) {
-        if (hipMalloc(&K->kt, sizeof(double) * std::max<int64_t>(K->nsell, 1)) != hipSuccess ||
+        if (hipMalloc(&K->kt, sizeof(double) * m) != hipSuccess ||
             hipMalloc(&K->kt_diag, sizeof(double) * n) != hipSuccess)
             return fail(ctx, NN_EOOM, "transient matrix allocation");
     }
-    if (mixed && !K->kt32 &&
-        hipMalloc(&K->kt32, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
+    if (mixed && !K->kt32 && hipMalloc(&K->kt32, sizeof(float) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient float32 allocation");
+    if ((want32p || want64p) && ensure_paired(ctx, K, false) != NN_OK) return NN_EOOM;
+    if (want32p && !K->kt32p && hipMalloc(&K->kt32p, sizeof(float) * m) != hipSuccess)
+        return fail(ctx, NN_EOOM, "transient float32 allocation");
+    if (want64p && !K->kt64p && hipMalloc(&K->kt64p, sizeof(double) * m) != hipSuccess)
+        return fail(ctx, NN_EOOM, "transient paired float64 allocation");
     launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
     launch_diag(ctx, K, K->kt, K->kt_diag);
     if (K->kt32) launch_to_f32(ctx, K->nsell, K->kt, K->kt32);
-    if (K->kt32 && K->sl_d16) {
-        nn_status st = ensure_paired(ctx, K, false);
-        if (st != NN_OK) return st;
-        if (!K->kt32p &&
-            hipMalloc(&K->kt32p, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
-            return fail(ctx, NN_EOOM, "transient float32 allocation");
-        launch_pair_f32(ctx, K, K->kt32, K->kt32p);
-    }
+    if (K->kt32 && K->kt32p) launch_pair_f32(ctx, K, K->kt32, K->kt32p);
+    if (K->kt64p) launch_pair_f64(ctx, K, K->kt, K->kt64p);
     NN_HIP_TRY(ctx, hipGetLastError());
     K->kt_dt = dt;
     return NN_OK;
@@ -455,6 +462,7 @@ nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes)
     if (A->val32p) b += 4.0 * ns;
     if (A->kt32p) b += 4.0 * ns;
     if (A->val64p) b += 8.0 * ns;
+    if (A->kt64p) b += 8.0 * ns;
     *bytes = (size_t)b;
     return NN_OK;
 }
@@ -469,6 +477,7 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
     if (A->sl_d16) (void)hipFree(A->sl_d16);
     if (A->d16p) (void)hipFree(A->d16p);
     if (A->val64p) (void)hipFree(A->val64p);
+    if (A->kt64p) (void)hipFree(A->kt64p);
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
     for (double *p : dv)
         if (p) (void)hipFree(p);
@@ -568,14 +577,15 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     const bool mixed = opts->precision == NN_MIXED;
     if (n == 0) return solve_impl(ctx, K, K->val, nullptr, nullptr, nullptr, K->diag, f_dev, opts,
                                     c_dev, active_dev, stats);
-    if ((st = ensure_transient(ctx, K, dt, mixed)) != NN_OK) return st;
+    if ((st = ensure_transient(ctx, K, dt, mixed, true)) != NN_OK) return st;
     if ((st = ensure_workspace(ctx, n)) != NN_OK) return st;
     launch_transient_rhs(ctx, K, c_dev, f_dev, dt, ctx->ws.ft);
     nn_opts o = *opts;
     o.c0_mode = 1;   // warm start from c^(n)
     if (o.method == NN_BLMVM) return blmvm_impl(ctx, K, K->kt, ctx->ws.ft, &o, c_dev, active_dev, stats);
-    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32p : nullptr, nullptr,
-                      K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev, stats);
+    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32p : nullptr,
+                      mixed ? nullptr : K->kt64p, K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev,
+                      stats);
 }
 
 // Shared checks of the batched entry points: arguments, options, and that
@@ -619,7 +629,7 @@ nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *
     if (st != NN_OK) return st;
     const bool mixed = opts->precision == NN_MIXED;
     for (int p = 0; p < nprob; p++)
-        if ((st = ensure_transient(ctx, K[p], dt, mixed)) != NN_OK) return st;
+        if ((st = ensure_transient(ctx, K[p], dt, mixed, false)) != NN_OK) return st;
     if (nprob == 0) {
         ctx->err.clear();
         return NN_OK;

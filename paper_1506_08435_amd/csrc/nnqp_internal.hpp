@@ -143,6 +143,7 @@ struct nn_matrix {
     float *val32p = nullptr;
     float *kt32p = nullptr;
     double *val64p = nullptr;
+    double *kt64p = nullptr;
     double *val = nullptr;     // K values, sliced-ELL order [nsell]
     double *mval = nullptr;    // M values, sliced-ELL order (or null)
     double *diag = nullptr;    // diag(K)
@@ -313,7 +314,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                            const nn_opts *o, double *const *c, uint8_t *const *active,
                            nn_stats *stats, double dt);
 // Form (once per dt) the M/dt + K values, their diagonal and, for mixed
-// precision, their float32 copy.
-nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed);
+// precision, their float32 copy; with `paired`, also the paired copy the
+// single-problem solver reads at this precision.
+nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, bool paired);
 
 }  // namespace nnqp

@@ -290,16 +290,40 @@ def gaussian_random_field(shape: Sequence[int], ell: float, seed: int,
     return np.ascontiguousarray(crop)
 
 
+def renumber_nodes(p: Problem, new_id: np.ndarray) -> Problem:
+    """The same problem with node o renamed new_id[o] (a permutation):
+    coordinates, Dirichlet flags and values move with their nodes, elements
+    keep their order and are rewritten in the new ids."""
+    new_id = np.asarray(new_id, dtype=np.int64)
+    assert new_id.shape == (p.n_nodes,) and np.array_equal(np.sort(new_id), np.arange(p.n_nodes))
+    coords = np.empty_like(p.coords)
+    coords[new_id] = p.coords
+    dirichlet = np.empty_like(p.dirichlet)
+    dirichlet[new_id] = p.dirichlet
+    dvals = None
+    if p.dirichlet_values is not None:
+        dvals = np.empty_like(p.dirichlet_values)
+        dvals[new_id] = p.dirichlet_values
+    return dataclasses.replace(p, coords=coords, dirichlet=dirichlet, dirichlet_values=dvals,
+                               elems=np.ascontiguousarray(new_id[p.elems].astype(np.int32)))
+
+
 def config_transient3d(nx=256, ny=256, nz=64, seed=1506, ell=8.0) -> Problem:
     """256 x 256 x 64 cubic cells (h = 1/256), D_e = exp(G_e) R diag(1, .1, 1e-3) R^T,
     G a seeded Gaussian random field (one value per cell, shared by its 6 tets),
-    f = 1 on the central box of each extent; used with backward Euler, dt = 1e-3."""
+    f = 1 on the central box of each extent; used with backward Euler, dt = 1e-3.
+    Nodes are numbered z fastest, then y, then x (the shortest axis first), so
+    the widest coupling of the stiffness is (nz + 1)(ny + 1) + nz + 2 = 16771
+    rows: column offsets fit int16 (with x fastest they would reach 66307)."""
     cells = (nx, ny, nz)
     G = gaussian_random_field(cells, ell, seed)          # [x, y, z]
     kcell = np.exp(G).transpose(2, 1, 0).ravel()         # cell order: x fastest
     kscale = np.repeat(kcell, 6)
     D0 = aniso3d_tensor((1.0, 0.1, 1e-3))
-    return box_problem(f"transient3d_{nx}x{ny}x{nz}", cells, 1.0 / nx, D0, kscale=kscale)
+    p = box_problem(f"transient3d_{nx}x{ny}x{nz}", cells, 1.0 / nx, D0, kscale=kscale)
+    k, j, i = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    new_id = (k + (nz + 1) * (j + (ny + 1) * i)).ravel()   # old ids run x fastest
+    return renumber_nodes(p, new_id)
 
 
 def batch_problem(index: int, seed: int = 8435, nprob: int = 512,
