@@ -78,7 +78,10 @@ typedef enum {
                       only, an L-BFGS matrix built from projected-gradient differences */
 } nn_method;
 
-/* Solver options; fill with nn_default_opts() and override. */
+/* Solver options; fill with nn_default_opts() and override.  Every
+ * reduction combines per-block partials in a fixed order (no atomics), so
+ * results are bitwise reproducible on the same device; there is no
+ * non-deterministic mode to select. */
 typedef struct {
     double tol;           /* stop when ||pg(c)||_2 <= tol * ||f||_2, pg the projected
                              gradient (g_i if c_i > 0, else min(g_i, 0)), g = K c - f.
@@ -142,8 +145,31 @@ typedef struct {
 } nn_stats;
 
 /* Create a context on HIP device `device` using `hip_stream` (a hipStream_t;
- * NULL = the null stream).  The stream must outlive the context. */
+ * NULL = the null stream).  The stream must outlive the context.  Device
+ * memory comes from hipMalloc and returns through hipFree. */
 nn_status nn_create(nn_ctx **ctx, int device, void *hip_stream);
+
+/* Device memory hooks for nn_create_ex.  alloc returns `bytes` (> 0) bytes
+ * of device memory on the context's device, usable on its stream and aligned
+ * to at least 256 bytes, or NULL when it cannot (the library then reports
+ * NN_EOOM); free_ takes back a pointer alloc returned.  `user` is passed
+ * through unchanged.  Both may be called from any library call on the
+ * context, including nn_destroy and nn_matrix_free. */
+typedef void *(*nn_alloc_fn)(size_t bytes, void *user);
+typedef void (*nn_free_fn)(void *ptr, void *user);
+
+/* nn_create with the caller's allocator (for example a framework's caching
+ * allocator): every device buffer of the context (work vectors, reduction
+ * partials, per-call batch arrays) and of each matrix it creates (nn_assemble,
+ * nn_matrix_from_csr; also the copies later solves add to the matrix) is taken
+ * from alloc and given back through free_.  A matrix keeps the hooks of the
+ * context that created it and frees through them whichever context frees it,
+ * so the hooks and `user` must stay valid until that context is destroyed and
+ * every matrix it created is freed.  alloc and free_ must both be non-NULL;
+ * NN_EINVAL otherwise.  Host staging buffers stay pinned host memory
+ * (hipHostMalloc). */
+nn_status nn_create_ex(nn_ctx **ctx, int device, void *hip_stream, nn_alloc_fn alloc,
+                       nn_free_fn free_, void *user);
 void nn_destroy(nn_ctx *ctx);
 /* Message for the last non-OK status on ctx (never NULL; "" if none). */
 const char *nn_last_error(const nn_ctx *ctx);

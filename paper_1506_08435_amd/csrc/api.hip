@@ -16,6 +16,21 @@ nn_status fail(nn_ctx *ctx, nn_status st, const std::string &msg)
     return st;
 }
 
+hipError_t dev_malloc_raw(const DevAlloc &a, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (!a.alloc) return hipMalloc(p, bytes);
+    *p = a.alloc(bytes > 0 ? bytes : 8, a.user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_free(const DevAlloc &a, void *p)
+{
+    if (!p) return;
+    if (a.free_) a.free_(p, a.user);
+    else (void)hipFree(p);
+}
+
 nn_status ensure_workspace(nn_ctx *ctx, int64_t n)
 {
     Workspace &W = ctx->ws;
@@ -24,27 +39,27 @@ nn_status ensure_workspace(nn_ctx *ctx, int64_t n)
                        &W.ks0, &W.ks1, &W.dm, &W.ft, &W.ks2};
     for (double **v : vecs)
         if (*v) {
-            (void)hipFree(*v);
+            dev_free(ctx->al, *v);
             *v = nullptr;
         }
     float **fv[] = {&W.w32, &W.r32, &W.z32, &W.q32, &W.p32, &W.dm32};
     for (float **v : fv)
         if (*v) {
-            (void)hipFree(*v);
+            dev_free(ctx->al, *v);
             *v = nullptr;
         }
-    if (W.mask) (void)hipFree(W.mask);
+    dev_free(ctx->al, W.mask);
     W.mask = nullptr;
     W.cap = 0;
     const int64_t cap = std::max<int64_t>(n, 1);
     for (double **v : vecs) {
-        hipError_t e = hipMalloc(v, sizeof(double) * cap);
+        hipError_t e = dev_malloc(ctx->al, v, sizeof(double) * cap);
         if (e != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
     }
-    if (hipMalloc(&W.mask, cap) != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
+    if (dev_malloc(ctx->al, &W.mask, cap) != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
     float **fvecs[] = {&W.w32, &W.r32, &W.z32, &W.q32, &W.p32, &W.dm32};
     for (float **v : fvecs) {
-        hipError_t e = hipMalloc(v, sizeof(float) * cap);
+        hipError_t e = dev_malloc(ctx->al, v, sizeof(float) * cap);
         if (e != hipSuccess) return fail(ctx, NN_EOOM, "workspace allocation failed");
     }
     W.cap = cap;
@@ -153,17 +168,17 @@ nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K, bool f64)
     if (!K->sl_d16 || K->n == 0) return NN_OK;
     const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
     if (!K->d16p) {
-        if (hipMalloc(&K->d16p, sizeof(short) * m) != hipSuccess)
+        if (dev_malloc(K->al, &K->d16p, sizeof(short) * m) != hipSuccess)
             return fail(ctx, NN_EOOM, "paired offsets allocation");
         launch_pair_d16(ctx, K, K->sl_d16, K->d16p);
     }
     if (K->val32 && !K->val32p) {
-        if (hipMalloc(&K->val32p, sizeof(float) * m) != hipSuccess)
+        if (dev_malloc(K->al, &K->val32p, sizeof(float) * m) != hipSuccess)
             return fail(ctx, NN_EOOM, "paired float32 allocation");
         launch_pair_f32(ctx, K, K->val32, K->val32p);
     }
     if (f64 && !K->val64p) {
-        if (hipMalloc(&K->val64p, sizeof(double) * m) != hipSuccess)
+        if (dev_malloc(K->al, &K->val64p, sizeof(double) * m) != hipSuccess)
             return fail(ctx, NN_EOOM, "paired float64 allocation");
         launch_pair_f64(ctx, K, K->val, K->val64p);
     }
@@ -186,16 +201,16 @@ nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, boo
     if (fresh && (!mixed || K->kt32) && (!want32p || K->kt32p) && (!want64p || K->kt64p))
         return NN_OK;
     if (!K->kt) {
-        if (hipMalloc(&K->kt, sizeof(double) * m) != hipSuccess ||
-            hipMalloc(&K->kt_diag, sizeof(double) * n) != hipSuccess)
+        if (dev_malloc(K->al, &K->kt, sizeof(double) * m) != hipSuccess ||
+            dev_malloc(K->al, &K->kt_diag, sizeof(double) * n) != hipSuccess)
             return fail(ctx, NN_EOOM, "transient matrix allocation");
     }
-    if (mixed && !K->kt32 && hipMalloc(&K->kt32, sizeof(float) * m) != hipSuccess)
+    if (mixed && !K->kt32 && dev_malloc(K->al, &K->kt32, sizeof(float) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient float32 allocation");
     if ((want32p || want64p) && ensure_paired(ctx, K, false) != NN_OK) return NN_EOOM;
-    if (want32p && !K->kt32p && hipMalloc(&K->kt32p, sizeof(float) * m) != hipSuccess)
+    if (want32p && !K->kt32p && dev_malloc(K->al, &K->kt32p, sizeof(float) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient float32 allocation");
-    if (want64p && !K->kt64p && hipMalloc(&K->kt64p, sizeof(double) * m) != hipSuccess)
+    if (want64p && !K->kt64p && dev_malloc(K->al, &K->kt64p, sizeof(double) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient paired float64 allocation");
     launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
     launch_diag(ctx, K, K->kt, K->kt_diag);
@@ -218,9 +233,7 @@ using namespace nnqp;
             return fail((ctx), NN_EHIP, "hipSetDevice"); \
     } while (0)
 
-extern "C" {
-
-nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
+static nn_status create_impl(nn_ctx **out, int device, void *hip_stream, const DevAlloc &al)
 {
     if (!out) return NN_EINVAL;
     *out = nullptr;
@@ -229,15 +242,16 @@ nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
     if (hipSetDevice(device) != hipSuccess) return NN_EHIP;
     nn_ctx *ctx = new (std::nothrow) nn_ctx();
     if (!ctx) return NN_EOOM;
+    ctx->al = al;
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
     const size_t part_bytes = sizeof(double) * kSlots * kMaxBlocks * kMaxRed;
-    bool ok = hipMalloc(&ctx->partials, part_bytes) == hipSuccess &&
+    bool ok = dev_malloc(ctx->al, &ctx->partials, part_bytes) == hipSuccess &&
               hipHostMalloc(&ctx->h_part, sizeof(double) * kMaxBlocks * kMaxRed,
                             hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&ctx->h_multi, sizeof(double) * kMaxBlocks * (5 + 3 * kLadder),
                             hipHostMallocDefault) == hipSuccess &&
-              hipMalloc(&ctx->scal, sizeof(DevScalars)) == hipSuccess &&
+              dev_malloc(ctx->al, &ctx->scal, sizeof(DevScalars)) == hipSuccess &&
               hipHostMalloc(&ctx->h_scal, sizeof(DevScalars), hipHostMallocDefault) == hipSuccess &&
               hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
     if (ok) {
@@ -253,6 +267,26 @@ nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
     return NN_OK;
 }
 
+extern "C" {
+
+nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
+{
+    return create_impl(out, device, hip_stream, DevAlloc{});
+}
+
+nn_status nn_create_ex(nn_ctx **out, int device, void *hip_stream, nn_alloc_fn alloc,
+                       nn_free_fn free_, void *user)
+{
+    if (out) *out = nullptr;
+    if (!alloc || !free_) return NN_EINVAL;
+    DevAlloc a;
+    a.alloc = alloc;
+    a.free_ = free_;
+    a.user = user;
+    return create_impl(out, device, hip_stream, a);
+}
+
+
 void nn_destroy(nn_ctx *ctx)
 {
     if (!ctx) return;
@@ -263,22 +297,22 @@ void nn_destroy(nn_ctx *ctx)
     double *vecs[] = {W.g,   W.w,   W.r,  W.z,  W.q,   W.p0,  W.p1,
                       W.ks0, W.ks1, W.dm, W.ft, W.ks2};
     for (double *v : vecs)
-        if (v) (void)hipFree(v);
+        dev_free(ctx->al, v);
     float *fvecs[] = {W.w32, W.r32, W.z32, W.q32, W.p32, W.dm32};
     for (float *v : fvecs)
-        if (v) (void)hipFree(v);
-    if (W.mask) (void)hipFree(W.mask);
+        dev_free(ctx->al, v);
+    dev_free(ctx->al, W.mask);
     double *cv[] = {W.cres, W.cdz[0], W.cdz[1]};
     for (double *v : cv)
-        if (v) (void)hipFree(v);
+        dev_free(ctx->al, v);
     float *cf[] = {W.cres32, W.cdz32[0], W.cdz32[1]};
     for (float *v : cf)
-        if (v) (void)hipFree(v);
+        dev_free(ctx->al, v);
     lm_release(ctx);
-    if (ctx->partials) (void)hipFree(ctx->partials);
+    dev_free(ctx->al, ctx->partials);
     if (ctx->h_part) (void)hipHostFree(ctx->h_part);
     if (ctx->h_multi) (void)hipHostFree(ctx->h_multi);
-    if (ctx->scal) (void)hipFree(ctx->scal);
+    dev_free(ctx->al, ctx->scal);
     if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -358,18 +392,19 @@ nn_status nn_matrix_from_csr(nn_ctx *ctx, int64_t n, const int64_t *rowptr, cons
     rp32[n] = (int)nnz;
     nn_matrix *M = new (std::nothrow) nn_matrix();
     if (!M) return fail(ctx, NN_EOOM, "host allocation");
+    M->al = ctx->al;
     M->n = n;
     M->nnz = nnz;
     const size_t nz = (size_t)std::max<int64_t>(nnz, 1);
     double *d_val = nullptr, *d_mval = nullptr;
     auto release = [&]() {
-        if (d_val) (void)hipFree(d_val);
-        if (d_mval) (void)hipFree(d_mval);
+        dev_free(ctx->al, d_val);
+        dev_free(ctx->al, d_mval);
     };
-    bool ok = hipMalloc(&M->rowptr, sizeof(int) * (n + 1)) == hipSuccess &&
-              hipMalloc(&M->col, sizeof(int) * nz) == hipSuccess &&
-              hipMalloc(&d_val, sizeof(double) * nz) == hipSuccess &&
-              (!mval || hipMalloc(&d_mval, sizeof(double) * nz) == hipSuccess);
+    bool ok = dev_malloc(M->al, &M->rowptr, sizeof(int) * (n + 1)) == hipSuccess &&
+              dev_malloc(M->al, &M->col, sizeof(int) * nz) == hipSuccess &&
+              dev_malloc(ctx->al, &d_val, sizeof(double) * nz) == hipSuccess &&
+              (!mval || dev_malloc(ctx->al, &d_mval, sizeof(double) * nz) == hipSuccess);
     if (!ok) {
         release();
         nn_matrix_free(ctx, M);
@@ -473,17 +508,17 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
     if (ctx) (void)hipSetDevice(ctx->device);
     int *iv[] = {A->rowptr, A->col, A->sl_off, A->sl_col};
     for (int *p : iv)
-        if (p) (void)hipFree(p);
-    if (A->sl_d16) (void)hipFree(A->sl_d16);
-    if (A->d16p) (void)hipFree(A->d16p);
-    if (A->val64p) (void)hipFree(A->val64p);
-    if (A->kt64p) (void)hipFree(A->kt64p);
+        dev_free(A->al, p);
+    dev_free(A->al, A->sl_d16);
+    dev_free(A->al, A->d16p);
+    dev_free(A->al, A->val64p);
+    dev_free(A->al, A->kt64p);
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
     for (double *p : dv)
-        if (p) (void)hipFree(p);
+        dev_free(A->al, p);
     float *fv[] = {A->val32, A->kt32, A->val32p, A->kt32p};
     for (float *p : fv)
-        if (p) (void)hipFree(p);
+        dev_free(A->al, p);
     delete A;
 }
 
@@ -536,7 +571,7 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
     const float *v32 = nullptr;
     if (opts->precision == NN_MIXED && K->n > 0) {
         if (!K->val32) {
-            if (hipMalloc(&K->val32, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
+            if (dev_malloc(K->al, &K->val32, sizeof(float) * std::max<int64_t>(K->nsell, 1)) != hipSuccess)
                 return fail(ctx, NN_EOOM, "float32 value allocation");
             launch_to_f32(ctx, K->nsell, K->val, K->val32);
             NN_HIP_TRY(ctx, hipGetLastError());
@@ -549,7 +584,6 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
     return solve_impl(ctx, K, K->val, v32, v32 ? K->val32p : nullptr, v32 ? nullptr : K->val64p,
                       K->diag, f_dev, opts, c_dev, active_dev, stats);
 }
-
 
 nn_status nn_solve_galerkin(nn_ctx *ctx, nn_matrix *K, const double *f_dev, const nn_opts *opts,
                             double *c_dev, nn_stats *stats)

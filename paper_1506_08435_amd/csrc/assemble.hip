@@ -45,12 +45,15 @@ void parallel_for(int64_t n, F &&fn)
     for (auto &x : th) x.join();
 }
 
+// A scratch device buffer of one call, taken from and returned to the
+// context's allocator.
 struct DevBuf {
+    const nnqp::DevAlloc &al;
     void *p = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
-    }
+    explicit DevBuf(const nnqp::DevAlloc &a) : al(a) {}
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { nnqp::dev_free(al, p); }
 };
 
 }  // namespace
@@ -197,10 +200,10 @@ nn_status sell_build(nn_ctx *ctx, nn_matrix *A, const int64_t *rowptr_host, cons
     A->wmax = wmax;
     std::vector<int> off32(off.begin(), off.end());
     const size_t ne = (size_t)std::max<int64_t>(nsell, 1);
-    hipError_t e = hipMalloc(&A->sl_off, sizeof(int) * (ns + 1));
-    if (e == hipSuccess) e = hipMalloc(&A->sl_col, sizeof(int) * ne);
-    if (e == hipSuccess) e = hipMalloc(&A->val, sizeof(double) * ne);
-    if (e == hipSuccess && csr_mval) e = hipMalloc(&A->mval, sizeof(double) * ne);
+    hipError_t e = dev_malloc(A->al, &A->sl_off, sizeof(int) * (ns + 1));
+    if (e == hipSuccess) e = dev_malloc(A->al, &A->sl_col, sizeof(int) * ne);
+    if (e == hipSuccess) e = dev_malloc(A->al, &A->val, sizeof(double) * ne);
+    if (e == hipSuccess && csr_mval) e = dev_malloc(A->al, &A->mval, sizeof(double) * ne);
     if (e != hipSuccess) return fail(ctx, NN_EOOM, "sliced-ELL allocation failed");
     NN_HIP_TRY(ctx, hipMemcpyAsync(A->sl_off, off32.data(), sizeof(int) * (ns + 1),
                                    hipMemcpyHostToDevice, ctx->stream));
@@ -216,18 +219,18 @@ nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A)
         // int16 column offsets for the float32-value passes, kept only when
         // every |col - row| fits
         short *sd = nullptr;
-        NN_HIP_TRY(ctx, hipMalloc(&sd, sizeof(short) * std::max<int64_t>(A->nsell, 1)));
+        NN_HIP_TRY(ctx, dev_malloc(A->al, &sd, sizeof(short) * std::max<int64_t>(A->nsell, 1)));
         launch_sell_d16(ctx, A, sd);
         static const int kMaxOp[1] = {OP_MAX};
         double span = 0.0;
         nn_status rc = host_reduce(ctx, A->n, 1, kMaxOp, &span);
         if (rc != NN_OK) {
-            (void)hipFree(sd);
+            dev_free(A->al, sd);
             return rc;
         }
         if (span <= 32767.0) A->sl_d16 = sd;
-        else (void)hipFree(sd);
-        NN_HIP_TRY(ctx, hipMalloc(&A->diag, sizeof(double) * A->n));
+        else dev_free(A->al, sd);
+        NN_HIP_TRY(ctx, dev_malloc(A->al, &A->diag, sizeof(double) * A->n));
         launch_diag(ctx, A, A->val, A->diag);
         std::vector<double> d(A->n);
         NN_HIP_TRY(ctx, hipMemcpyAsync(d.data(), A->diag, sizeof(double) * A->n,
@@ -343,15 +346,18 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
     // ---- device numeric phase
     nn_matrix *M = new (std::nothrow) nn_matrix();
     if (!M) return fail(ctx, NN_EOOM, "host allocation");
+    M->al = ctx->al;
     M->n = n;
     M->nnz = nnz;
     auto cleanup = [&](nn_status st) {
         nn_matrix_free(ctx, M);
         return st;
     };
-    DevBuf d_free, d_incp, d_ince, d_elems, d_coords, d_D, d_ks, d_f, d_dv, d_dof, d_F, d_val, d_mval;
+    const DevAlloc &ta = ctx->al;   // scratch of this call
+    DevBuf d_free(ta), d_incp(ta), d_ince(ta), d_elems(ta), d_coords(ta), d_D(ta), d_ks(ta),
+        d_f(ta), d_dv(ta), d_dof(ta), d_F(ta), d_val(ta), d_mval(ta);
     auto up = [&](DevBuf &b, const void *src, size_t bytes) -> hipError_t {
-        hipError_t e = hipMalloc(&b.p, bytes > 0 ? bytes : 8);
+        hipError_t e = dev_malloc(ta, &b.p, bytes > 0 ? bytes : 8);
         if (e != hipSuccess) return e;
         if (src && bytes > 0) e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, ctx->stream);
         return e;
@@ -376,12 +382,12 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
     if (dvals) NN_UP(d_dv, dvals, sizeof(double) * nn);
     NN_UP(d_dof, dof.data(), sizeof(int) * nn);
     {
-        hipError_t e = hipMalloc(&M->rowptr, sizeof(int) * (n + 1));
-        if (e == hipSuccess) e = hipMalloc(&M->col, sizeof(int) * std::max<int64_t>(nnz, 1));
-        if (e == hipSuccess) e = hipMalloc(&d_val.p, sizeof(double) * std::max<int64_t>(nnz, 1));
+        hipError_t e = dev_malloc(M->al, &M->rowptr, sizeof(int) * (n + 1));
+        if (e == hipSuccess) e = dev_malloc(M->al, &M->col, sizeof(int) * std::max<int64_t>(nnz, 1));
+        if (e == hipSuccess) e = dev_malloc(ta, &d_val.p, sizeof(double) * std::max<int64_t>(nnz, 1));
         if (e == hipSuccess && with_mass)
-            e = hipMalloc(&d_mval.p, sizeof(double) * std::max<int64_t>(nnz, 1));
-        if (e == hipSuccess && !F_dev) e = hipMalloc(&d_F.p, sizeof(double) * std::max<int64_t>(n, 1));
+            e = dev_malloc(ta, &d_mval.p, sizeof(double) * std::max<int64_t>(nnz, 1));
+        if (e == hipSuccess && !F_dev) e = dev_malloc(ta, &d_F.p, sizeof(double) * std::max<int64_t>(n, 1));
         if (e != hipSuccess) {
             fail(ctx, NN_EOOM, std::string("matrix allocation: ") + hipGetErrorString(e));
             return cleanup(NN_EOOM);

@@ -1000,13 +1000,15 @@ int width_class(int wmax) { return wmax <= 8 ? 8 : (wmax <= 16 ? 16 : 32); }
 
 // Device and pinned host memory of one batched call, released on every exit.
 struct Arena {
+    const DevAlloc &al;   // the context's device memory hooks
     std::vector<void *> dev, host;
     bool ok = true;
+    explicit Arena(const DevAlloc &a) : al(a) {}
     template <class T>
     T *d(size_t n)
     {
         void *p = nullptr;
-        if (hipMalloc(&p, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess) {
+        if (dev_malloc(al, &p, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess) {
             ok = false;
             return nullptr;
         }
@@ -1027,7 +1029,7 @@ struct Arena {
     }
     ~Arena()
     {
-        for (void *p : dev) (void)hipFree(p);
+        for (void *p : dev) dev_free(al, p);
         for (void *p : host) (void)hipHostFree(p);
     }
 };
@@ -1111,7 +1113,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         for (int t = 0; t < nsl[p]; t++) sprob.push_back(p);
         if (n > 0) wmax = std::max(wmax, K[p]->wmax);
         if (mixed && n > 0 && !transient && !K[p]->val32) {
-            if (hipMalloc(&K[p]->val32, sizeof(float) * std::max<int64_t>(K[p]->nsell, 1)) !=
+            if (dev_malloc(K[p]->al, &K[p]->val32, sizeof(float) * std::max<int64_t>(K[p]->nsell, 1)) !=
                 hipSuccess)
                 return fail(ctx, NN_EOOM, "float32 value allocation");
             launch_to_f32(ctx, K[p]->nsell, K[p]->val, K[p]->val32);
@@ -1131,7 +1133,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     const double ib = (mixed && all_d16) ? 2.0 : 4.0;   // bytes per column index
 
     // ---- tables, work vectors, lists, pinned state mirrors
-    Arena A;
+    Arena A(ctx->al);
     int *d_sprob = A.d<int>(S), *d_s0 = A.d<int>(P), *d_nrow = A.d<int>(P);
     int *d_list = A.d<int>((size_t)2 + P + S);
     SRec *d_srec = A.d<SRec>(S);

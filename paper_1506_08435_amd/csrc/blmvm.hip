@@ -464,13 +464,13 @@ nn_status ensure_lm(nn_ctx *ctx, int64_t n, int m)
     if (L.state && L.cap >= n && L.m >= m) return NN_OK;
     lm_release(ctx);
     const int64_t cap = std::max<int64_t>(n, 64);
-    hipError_t e = hipMalloc(&L.S, sizeof(double) * cap * m);
-    if (e == hipSuccess) e = hipMalloc(&L.Y, sizeof(double) * cap * m);
-    if (e == hipSuccess) e = hipMalloc(&L.pg, sizeof(double) * cap);
-    if (e == hipSuccess) e = hipMalloc(&L.d, sizeof(double) * cap);
-    if (e == hipSuccess) e = hipMalloc(&L.gn, sizeof(double) * cap);
-    if (e == hipSuccess) e = hipMalloc(&L.part, sizeof(double) * kLmNV * kMaxBlocks);
-    if (e == hipSuccess) e = hipMalloc(&L.state, sizeof(LmState));
+    hipError_t e = dev_malloc(ctx->al, &L.S, sizeof(double) * cap * m);
+    if (e == hipSuccess) e = dev_malloc(ctx->al, &L.Y, sizeof(double) * cap * m);
+    if (e == hipSuccess) e = dev_malloc(ctx->al, &L.pg, sizeof(double) * cap);
+    if (e == hipSuccess) e = dev_malloc(ctx->al, &L.d, sizeof(double) * cap);
+    if (e == hipSuccess) e = dev_malloc(ctx->al, &L.gn, sizeof(double) * cap);
+    if (e == hipSuccess) e = dev_malloc(ctx->al, &L.part, sizeof(double) * kLmNV * kMaxBlocks);
+    if (e == hipSuccess) e = dev_malloc(ctx->al, &L.state, sizeof(LmState));
     if (e == hipSuccess) e = hipHostMalloc(&L.h_state, sizeof(LmState), hipHostMallocDefault);
     if (e != hipSuccess) {
         lm_release(ctx);
@@ -491,9 +491,8 @@ void lm_release(nn_ctx *ctx)
 {
     LmWork &L = ctx->lm;
     double *bufs[] = {L.S, L.Y, L.pg, L.d, L.gn, L.part};
-    for (double *b : bufs)
-        if (b) (void)hipFree(b);
-    if (L.state) (void)hipFree(L.state);
+    for (double *b : bufs) dev_free(ctx->al, b);
+    dev_free(ctx->al, L.state);
     if (L.h_state) (void)hipHostFree(L.h_state);
     L = LmWork();
 }

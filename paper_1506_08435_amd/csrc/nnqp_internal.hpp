@@ -125,9 +125,29 @@ struct ProfEntry {
     int valid;
 };
 
+// Device memory through the caller's hooks (nn_create_ex) or, without
+// hooks, hipMalloc / hipFree.  Contexts and matrices each carry the hooks
+// their buffers came from.
+struct DevAlloc {
+    nn_alloc_fn alloc = nullptr;
+    nn_free_fn free_ = nullptr;
+    void *user = nullptr;
+};
+hipError_t dev_malloc_raw(const DevAlloc &a, void **p, size_t bytes);
+void dev_free(const DevAlloc &a, void *p);   // p may be null
+template <class T>
+inline hipError_t dev_malloc(const DevAlloc &a, T **p, size_t bytes)
+{
+    void *v = nullptr;
+    const hipError_t e = dev_malloc_raw(a, &v, bytes);
+    *p = static_cast<T *>(v);
+    return e;
+}
+
 }  // namespace nnqp
 
 struct nn_matrix {
+    nnqp::DevAlloc al;         // hooks of the creating context (frees go through them)
     int64_t n = 0, nnz = 0;
     int *rowptr = nullptr;     // CSR pattern [n+1] (boundary format, export)
     int *col = nullptr;        // [nnz]
@@ -157,6 +177,7 @@ struct nn_matrix {
 };
 
 struct nn_ctx {
+    nnqp::DevAlloc al;         // device memory hooks (default: hipMalloc / hipFree)
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture (batched CG)

@@ -65,16 +65,14 @@ nn_status cheb_prepare(nn_ctx *ctx, const nn_matrix *A, const double *vals, cons
     if (W.cheb_cap < n) {
         double **dv[] = {&W.cres, &W.cdz[0], &W.cdz[1]};
         float **fv[] = {&W.cres32, &W.cdz32[0], &W.cdz32[1]};
-        for (double **v : dv)
-            if (*v) (void)hipFree(*v), *v = nullptr;
-        for (float **v : fv)
-            if (*v) (void)hipFree(*v), *v = nullptr;
+        for (double **v : dv) dev_free(ctx->al, *v), *v = nullptr;
+        for (float **v : fv) dev_free(ctx->al, *v), *v = nullptr;
         W.cheb_cap = 0;
         for (double **v : dv)
-            if (hipMalloc(v, sizeof(double) * std::max<int64_t>(n, 1)) != hipSuccess)
+            if (dev_malloc(ctx->al, v, sizeof(double) * std::max<int64_t>(n, 1)) != hipSuccess)
                 return fail(ctx, NN_EOOM, "Chebyshev vectors");
         for (float **v : fv)
-            if (hipMalloc(v, sizeof(float) * std::max<int64_t>(n, 1)) != hipSuccess)
+            if (dev_malloc(ctx->al, v, sizeof(float) * std::max<int64_t>(n, 1)) != hipSuccess)
                 return fail(ctx, NN_EOOM, "Chebyshev vectors");
         W.cheb_cap = std::max<int64_t>(n, 1);
     }

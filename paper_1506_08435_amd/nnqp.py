@@ -28,10 +28,16 @@ STATUS_NAMES = {0: "NN_OK", 1: "NN_EINVAL", 2: "NN_ENONFINITE", 3: "NN_ENOTSPD",
                 5: "NN_EOOM", 6: "NN_EHIP", 7: "NN_EBUDGET"}
 
 # exported symbols declared in include/nnqp.h (checked by the ABI test)
-SYMBOLS = ("nn_create", "nn_destroy", "nn_last_error", "nn_default_opts", "nn_assemble",
+SYMBOLS = ("nn_create", "nn_create_ex", "nn_destroy", "nn_last_error", "nn_default_opts", "nn_assemble",
            "nn_matrix_from_csr", "nn_matrix_info", "nn_matrix_export", "nn_matrix_bytes",
            "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_solve_galerkin", "nn_step_transient",
            "nn_solve_batch", "nn_step_transient_batch", "nn_set_profiling", "nn_kernel_times")
+
+
+# device memory hooks of nn_create_ex: alloc(bytes, user) -> pointer or NULL,
+# free_(pointer, user)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class NnError(RuntimeError):
@@ -91,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     P = ctypes.POINTER
     sig = {
         "nn_create": (i32, [P(vp), ctypes.c_int, vp]),
+        "nn_create_ex": (i32, [P(vp), ctypes.c_int, vp, ALLOC_FN, FREE_FN, vp]),
         "nn_destroy": (None, [vp]),
         "nn_last_error": (ctypes.c_char_p, [vp]),
         "nn_default_opts": (i32, [P(Opts)]),
@@ -162,9 +169,16 @@ class Matrix:
 
 
 class Context:
-    """One device + one stream (torch's current stream unless given)."""
+    """One device + one stream (torch's current stream unless given).
 
-    def __init__(self, device: int = 0, stream=None):
+    allocator: None, the library takes device memory with hipMalloc; "torch",
+    every device buffer of the context and of the matrices it creates comes
+    from torch's caching allocator on this context's stream; or a pair of
+    callables (alloc(nbytes) -> device pointer as int, or None; free(ptr)).
+    The last two go through nn_create_ex.  Matrices keep a reference to their
+    context, so the hooks outlive them."""
+
+    def __init__(self, device: int = 0, stream=None, allocator=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the nnqp library needs an MI355X")
@@ -173,7 +187,31 @@ class Context:
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        st = self.lib.nn_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream))
+        sp = ctypes.c_void_p(self.stream.cuda_stream)
+        self._hooks = None
+        if allocator is None:
+            st = self.lib.nn_create(ctypes.byref(h), device, sp)
+        else:
+            if allocator == "torch":
+                dev, strm = device, self.stream
+                alloc_py = lambda nbytes: torch.cuda.caching_allocator_alloc(nbytes, dev, strm)
+                free_py = torch.cuda.caching_allocator_delete
+            elif isinstance(allocator, tuple) and len(allocator) == 2 and all(map(callable, allocator)):
+                alloc_py, free_py = allocator
+            else:
+                raise ValueError(f"allocator must be None, 'torch' or (alloc, free), not {allocator!r}")
+
+            def _alloc(nbytes, _user):
+                try:
+                    return alloc_py(int(nbytes)) or None
+                except Exception:   # out of memory: the library reports NN_EOOM
+                    return None
+
+            def _free(ptr, _user):
+                free_py(ptr)
+
+            self._hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+            st = self.lib.nn_create_ex(ctypes.byref(h), device, sp, self._hooks[0], self._hooks[1], None)
         if st != NN_OK:
             raise NnError(st, "nn_create failed")
         self.handle = h.value

@@ -46,6 +46,11 @@ def test_null_arguments_rejected_without_device_work():
     assert lib.nn_matrix_info(None, None, None, None) == nnqp.NN_EINVAL
     assert lib.nn_last_error(None) == b"null context"
     assert lib.nn_solve_nonneg(None, None, None, None, None, None, None) == nnqp.NN_EINVAL
+    # nn_create_ex needs both allocator hooks; it refuses before touching a device
+    h = ctypes.c_void_p(1234)
+    keep = nnqp.ALLOC_FN(lambda n, u: None)
+    assert lib.nn_create_ex(ctypes.byref(h), 0, None, keep, nnqp.FREE_FN(), None) == nnqp.NN_EINVAL
+    assert h.value is None
 
 
 def test_struct_layouts_match_header(tmp_path):

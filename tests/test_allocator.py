@@ -1,0 +1,97 @@
+"""Device memory through the caller's allocator (nn_create_ex): a context
+whose hooks are torch's caching allocator takes every device buffer from it
+(torch's own counter sees them), gives every one back, and computes bitwise
+the same results as a context on hipMalloc, for single, mixed-precision,
+transient and batched solves."""
+import pytest
+
+from paper_1506_08435_amd import workloads as W
+
+
+@pytest.mark.gpu
+def test_torch_allocator_hooks_same_results_and_all_memory_returned():
+    import torch
+    from paper_1506_08435_amd import nnqp
+
+    cube = W.cube3d(12)
+    members = [W.batch_problem(i, n_range=(8, 40)) for i in range(4)]
+    tr = W.config_transient3d(12, 10, 6, ell=2.0)
+
+    def run(ctx):
+        out = {}
+        K, F, _ = ctx.assemble(cube)
+        c, act, st = ctx.solve_nonneg(K, F, tol=1e-10)
+        out["fp64"] = (c.clone(), act.clone(), st["cg_its"])
+        c, act, st = ctx.solve_nonneg(K, F, tol=1e-10, precision=nnqp.NN_MIXED)
+        out["mixed"] = (c.clone(), act.clone(), st["cg_its"])
+        Kt, Ft, _ = ctx.assemble(tr, with_mass=True)
+        ct = torch.zeros(Kt.n, dtype=torch.float64, device=ctx.device)
+        for _ in range(2):
+            ct, _, _ = ctx.step_transient(Kt, 1e-3, Ft, ct, tol=1e-10)
+        out["transient"] = ct.clone()
+        Ks, Fs = [], []
+        for p in members:
+            Kb, Fb, _ = ctx.assemble(p)
+            Ks.append(Kb)
+            Fs.append(Fb)
+        cs, _, stats, _ = ctx.solve_batch(Ks, Fs, tol=1e-10)
+        out["batch"] = [x.clone() for x in cs]
+        for M in [K, Kt] + Ks:
+            M.free()
+        torch.cuda.synchronize()
+        return out
+
+    ref = run(nnqp.Context(0))
+    # torch's caching allocator behind counting hooks: every pointer the
+    # library takes is recorded until it comes back
+    live, seen, foreign = {}, [0], []
+
+    def alloc(nbytes):
+        p = torch.cuda.caching_allocator_alloc(nbytes, 0, torch.cuda.current_stream(0))
+        live[p] = nbytes
+        seen[0] += 1
+        return p
+
+    def free(p):   # runs inside a library call: record, assert afterwards
+        if p not in live:
+            foreign.append(p)
+            return
+        del live[p]
+        torch.cuda.caching_allocator_delete(p)
+
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    ctx = nnqp.Context(0, allocator=(alloc, free))
+    assert live                                           # reduction partials and scalars
+    K, F, _ = ctx.assemble(cube)
+    assert torch.cuda.memory_allocated() - base >= 12 * K.nnz   # the matrix lives in torch's pool
+    assert sum(live.values()) >= 12 * K.nnz
+    K.free()
+    del F
+    got = run(ctx)
+    for key in ("fp64", "mixed"):
+        assert torch.equal(got[key][0], ref[key][0]), key
+        assert torch.equal(got[key][1], ref[key][1]), key
+        assert got[key][2] == ref[key][2], key
+    assert torch.equal(got["transient"], ref["transient"])
+    for a, b in zip(got["batch"], ref["batch"]):
+        assert torch.equal(a, b)
+    assert seen[0] > 50                                   # batch arrays, copies, work vectors
+    ctx.close()
+    torch.cuda.synchronize()
+    assert not foreign, "freed pointers the hooks did not hand out"
+    assert not live, f"{len(live)} buffers not returned: {sorted(live.values())}"
+
+
+@pytest.mark.gpu
+def test_torch_allocator_keyword():
+    """allocator="torch": the library's buffers are counted by torch."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    ctx = nnqp.Context(0, allocator="torch")
+    K, F, _ = ctx.assemble(W.cube3d(10))
+    assert torch.cuda.memory_allocated() - base >= 12 * K.nnz
+    c, _, st = ctx.solve_nonneg(K, F, tol=1e-10)
+    assert st["kkt_rel"] <= 1e-10
