@@ -87,3 +87,21 @@ def test_batch_problem_seeded_ranges():
         ev = np.linalg.eigvalsh(p.D[0])
         assert 1e-4 <= ev[0] / ev[1] <= 1e-1
         assert p.f_elem.sum() > 0
+
+
+def test_transient_nodes_numbered_shortest_axis_first():
+    """The transient workload renumbers nodes z fastest: every element keeps
+    its geometry, Dirichlet flags follow their nodes, and the widest coupling
+    is (nz + 1)(ny + 1) + nz + 2 (16,771 at 256 x 256 x 64, within int16)."""
+    nx, ny, nz = 9, 7, 4
+    p = W.config_transient3d(nx, ny, nz, ell=2.0)
+    q = W.box_problem("lex", (nx, ny, nz), 1.0 / nx, W.aniso3d_tensor((1.0, 0.1, 1e-3)))
+    assert np.array_equal(p.coords[p.elems], q.coords[q.elems])
+    # a node's new id follows z, then y, then x
+    ijk = np.rint(p.coords / p.h).astype(np.int64)
+    assert np.array_equal(np.arange(p.n_nodes), ijk[:, 2] + (nz + 1) * (ijk[:, 1] + (ny + 1) * ijk[:, 0]))
+    on_box = (ijk == 0).any(1) | (ijk == [nx, ny, nz]).any(1)
+    assert np.array_equal(p.dirichlet.astype(bool), on_box)
+    e = p.elems.astype(np.int64)
+    assert (e.max(1) - e.min(1)).max() == (nz + 1) * (ny + 1) + nz + 2
+    assert (64 + 1) * (256 + 1) + 64 + 2 == 16771 < 32767
