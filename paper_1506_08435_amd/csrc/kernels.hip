@@ -163,6 +163,10 @@ struct Ladder {
     double *ks[kLadder];
 };
 
+#ifndef NNQP_LADDER_PHASE
+#define NNQP_LADDER_PHASE 4   // entries per load phase of the Cauchy ladder pass
+#endif
+
 template <int WMAX, class VT, class Cols>
 __global__ __launch_bounds__(kBlock) void k_ladder(Part P, const int *__restrict__ so, Cols sc,
                                                    const VT *__restrict__ v,
@@ -178,18 +182,22 @@ __global__ __launch_bounds__(kBlock) void k_ladder(Part P, const int *__restrict
 #pragma unroll
         for (int k = 0; k < kLadder; k++) out[k] = proj_box(cj - L.t[k] * gj, B) - cj;
     };
-    sell_rows_n<WMAX, kLadder>(P, so, sc, v, [&](int i) { return Two{c[i], g[i]}; }, trials,
-                               [&](int i, double (&kv)[kLadder], Two cg) {
-                                   double si[kLadder];
-                                   trials(i, si);
+    auto pre = [&](int i) { return Two{c[i], g[i]}; };
+    auto epi = [&](int i, double (&kv)[kLadder], Two cg) {
+        double si[kLadder];
+        trials(i, si);
 #pragma unroll
-                                   for (int k = 0; k < kLadder; k++) {
-                                       L.ks[k][i] = kv[k];
-                                       a[3 * k] += cg.b * si[k];
-                                       a[3 * k + 1] += si[k] * kv[k];
-                                       a[3 * k + 2] += si[k] * si[k];
-                                   }
-                               });
+        for (int k = 0; k < kLadder; k++) {
+            L.ks[k][i] = kv[k];
+            a[3 * k] += cg.b * si[k];
+            a[3 * k + 1] += si[k] * kv[k];
+            a[3 * k + 2] += si[k] * si[k];
+        }
+    };
+    // the nine running sums stay in registers for the whole pass, so the
+    // entries load NNQP_LADDER_PHASE at a time
+    sell_rows_n<WMAX, kLadder, VT, Cols, decltype(pre), decltype(trials), decltype(epi),
+                NNQP_LADDER_PHASE>(P, so, sc, v, pre, trials, epi);
     block_partial<0u, 3 * kLadder>(a, slot_ptr(partials, SLOT_U0));
 }
 
@@ -289,11 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
 // formed together, using K p = K z + beta (K p_old): only z is gathered, and
 // p, q are updated in place on the free rows; partials of p.q into SLOT_Q.
 // Columns outside the free set contribute 0 because z vanishes there.
-#ifndef NNQP_CG_ATTR
-#define NNQP_CG_ATTR
-#endif
 template <int WMAX, class VT, class VV, class Cols>
-__global__ __launch_bounds__(kBlock) NNQP_CG_ATTR void k_cg_spmv(Part P, const int *__restrict__ so, Cols sc,
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restrict__ so, Cols sc,
                                                     const VT *__restrict__ v,
                                                     const uint8_t *__restrict__ mask,
                                                     const VV *__restrict__ z,

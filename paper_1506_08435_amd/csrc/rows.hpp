@@ -315,7 +315,8 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
 // NT products in one pass: like sell_rows, with x(j, out) filling NT values
 // per gathered column and epi(i, acc[NT], pre(i)).  Entries are loaded eight
 // at a time before their gathers; one slice per wavefront in flight.
-template <int WMAX, int NT, class VT, class Cols, class Pre, class X, class Epi>
+template <int WMAX, int NT, class VT, class Cols, class Pre, class X, class Epi,
+          int PHASE = NNQP_LOAD_PHASE>
 __device__ __forceinline__ void sell_rows_n(const Part &P, const int *__restrict__ so, Cols sc,
                                             const VT *__restrict__ sv, Pre pre, X x, Epi epi)
 {
@@ -331,7 +332,7 @@ __device__ __forceinline__ void sell_rows_n(const Part &P, const int *__restrict
         double acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; t++) acc[t] = 0.0;
-        constexpr int H = WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE;
+        constexpr int H = WMAX < PHASE ? WMAX : PHASE;
         double xv[NT];
 #pragma unroll
         for (int h0 = 0; h0 < WMAX; h0 += H) {
