@@ -219,7 +219,8 @@ nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A)
         // int16 column offsets for the float32-value passes, kept only when
         // every |col - row| fits
         short *sd = nullptr;
-        NN_HIP_TRY(ctx, dev_malloc(A->al, &sd, sizeof(short) * std::max<int64_t>(A->nsell, 1)));
+        if (dev_malloc(A->al, &sd, sizeof(short) * std::max<int64_t>(A->nsell, 1)) != hipSuccess)
+            return fail(ctx, NN_EOOM, "int16 offset allocation failed");
         launch_sell_d16(ctx, A, sd);
         static const int kMaxOp[1] = {OP_MAX};
         double span = 0.0;
@@ -230,7 +231,8 @@ nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A)
         }
         if (span <= 32767.0) A->sl_d16 = sd;
         else dev_free(A->al, sd);
-        NN_HIP_TRY(ctx, dev_malloc(A->al, &A->diag, sizeof(double) * A->n));
+        if (dev_malloc(A->al, &A->diag, sizeof(double) * A->n) != hipSuccess)
+            return fail(ctx, NN_EOOM, "diagonal allocation failed");
         launch_diag(ctx, A, A->val, A->diag);
         std::vector<double> d(A->n);
         NN_HIP_TRY(ctx, hipMemcpyAsync(d.data(), A->diag, sizeof(double) * A->n,

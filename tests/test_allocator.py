@@ -95,3 +95,70 @@ def test_torch_allocator_keyword():
     assert torch.cuda.memory_allocated() - base >= 12 * K.nnz
     c, _, st = ctx.solve_nonneg(K, F, tol=1e-10)
     assert st["kkt_rel"] <= 1e-10
+
+
+@pytest.mark.gpu
+def test_allocator_failure_is_reported_and_leaks_nothing():
+    """The caller's allocator refusing the k-th request (forced from the host)
+    surfaces as NN_EOOM from whichever call needed the memory; every buffer
+    the library did get is still given back, and nothing it did not get is
+    freed."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+
+    cube = W.cube3d(6)
+    members = [W.batch_problem(i, n_range=(8, 16)) for i in range(3)]
+    outcomes = []
+    for limit in list(range(0, 40, 3)) + [60, 100, 400]:
+        live, foreign, count = {}, [], [0]
+
+        def alloc(nbytes):
+            count[0] += 1
+            if count[0] > limit:
+                return None
+            p = torch.cuda.caching_allocator_alloc(nbytes, 0, torch.cuda.current_stream(0))
+            live[p] = nbytes
+            return p
+
+        def free(p):
+            if p not in live:
+                foreign.append(p)
+                return
+            del live[p]
+            torch.cuda.caching_allocator_delete(p)
+
+        try:
+            ctx = nnqp.Context(0, allocator=(alloc, free))
+        except nnqp.NnError as e:
+            assert e.status == nnqp.NN_EOOM
+            outcomes.append("create")
+        else:
+            stage = "done"
+            mats = []
+            try:
+                stage = "assemble"
+                K, F, _ = ctx.assemble(cube)
+                mats.append(K)
+                stage = "solve"
+                c, _, st = ctx.solve_nonneg(K, F, tol=1e-10)
+                assert st["kkt_rel"] <= 1e-10
+                stage = "batch"
+                Ks, Fs = [], []
+                for p in members:
+                    Kb, Fb, _ = ctx.assemble(p)
+                    mats.append(Kb)
+                    Ks.append(Kb)
+                    Fs.append(Fb)
+                ctx.solve_batch(Ks, Fs, tol=1e-10)
+                stage = "done"
+            except nnqp.NnError as e:
+                assert e.status == nnqp.NN_EOOM, (limit, stage, str(e))
+            outcomes.append(stage)
+            for M in mats:
+                M.free()
+            ctx.close()
+        torch.cuda.synchronize()
+        assert not foreign, limit
+        assert not live, (limit, len(live))
+    assert outcomes[0] == "create" and outcomes[-1] == "done"
+    assert {"assemble", "solve", "batch"} <= set(outcomes), outcomes
