@@ -29,6 +29,10 @@
  *    fill an nn_stats or return sizes synchronise that stream before
  *    returning; nn_matvec does not (it is stream-ordered).
  *  - A context is not thread-safe; use one context per host thread.
+ *    Different contexts may run calls at the same time from different
+ *    threads (each on its own stream).  A matrix may be used by any context
+ *    on its device, but by one call at a time: solves add lazily formed
+ *    copies to it (float32 values, paired layouts, M/dt + K).
  */
 #ifndef NNQP_H
 #define NNQP_H
