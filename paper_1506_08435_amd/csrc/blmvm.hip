@@ -556,7 +556,7 @@ nn_status blmvm_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     // gradient pass with the KKT report; true when the point is converged
     auto refresh = [&](bool &conv) -> nn_status {
         prof_begin(ctx, KC_GRAD, b_grad);
-        launch_grad(ctx, A, vals, c, f, W.g, box);
+        launch_grad(ctx, A, vals, nullptr, c, f, W.g, box);
         prof_end(ctx);
         S.spmvs++;
         S.bytes_moved += b_grad;

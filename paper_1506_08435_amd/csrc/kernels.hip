@@ -622,12 +622,16 @@ void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, d
     k_init<<<P.nb, kBlock, 0, ctx->stream>>>(P, c, f, mode, c0v, ctx->partials, B);
 }
 
-void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
-                 const double *f, double *g, Box B)
+void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *vals_p,
+                 const double *c, const double *f, double *g, Box B)
 {
     Part P = make_part(A->n);
-    NN_DISPATCH_W(A->wmax, (k_grad<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col}, vals, c, f, g,
-                  ctx->partials, B);
+    if (vals_p && A->d16p)
+        NN_DISPATCH_W(A->wmax, (k_grad<WM, ColsD16P>), P.nb, P, A->sl_off, ColsD16P{A->d16p}, vals_p,
+                      c, f, g, ctx->partials, B);
+    else
+        NN_DISPATCH_W(A->wmax, (k_grad<WM, ColsI32>), P.nb, P, A->sl_off, ColsI32{A->sl_col}, vals,
+                      c, f, g, ctx->partials, B);
 }
 
 void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
@@ -693,6 +697,9 @@ void launch_ladder(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double 
     else if (V.v32)
         NN_DISPATCH_W(A->wmax, (k_ladder<WM, float, ColsI32>), P.nb, P, A->sl_off,
                       ColsI32{A->sl_col}, V.v32, c, g, L, B, ctx->partials);
+    else if (V.v64p && A->d16p)
+        NN_DISPATCH_W(A->wmax, (k_ladder<WM, double, ColsD16P>), P.nb, P, A->sl_off,
+                      ColsD16P{A->d16p}, V.v64p, c, g, L, B, ctx->partials);
     else
         NN_DISPATCH_W(A->wmax, (k_ladder<WM, double, ColsI32>), P.nb, P, A->sl_off,
                       ColsI32{A->sl_col}, V.v64, c, g, L, B, ctx->partials);

@@ -241,8 +241,8 @@ void launch_matvec(nn_ctx *ctx, const nn_matrix *A, const double *vals, const do
 void launch_init(nn_ctx *ctx, int64_t n, double *c, const double *f, int mode, double c0v, Box B);
 // [host] g = A c - f; |pg|^2 sum, #nonfinite sum, ||c - P(c - g)||_inf max, min c min,
 // #(c at a bound) sum
-void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *c,
-                 const double *f, double *g, Box B);
+void launch_grad(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *vals_p,
+                 const double *c, const double *f, double *g, Box B);
 // [host] s = P(c + t d) - c gathered, ks = A s; g.s, s.As, s.s (sums); rows with mask == 0 skipped
 void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *c, Dir d,
                   double t, const double *g, const uint8_t *mask, double *ks, Box B);

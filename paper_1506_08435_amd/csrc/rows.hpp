@@ -315,11 +315,81 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
 // NT products in one pass: like sell_rows, with x(j, out) filling NT values
 // per gathered column and epi(i, acc[NT], pre(i)).  Entries are loaded eight
 // at a time before their gathers; one slice per wavefront in flight.
+// sell_rows_n on the paired layout (see sell_rows_paired): PHASE / 2 pairs
+// per load phase, entries in the same order, so the sums are the same.
+template <int WMAX, int NT, class VT, class Pre, class X, class Epi, int PHASE>
+__device__ __forceinline__ void sell_rows_n_paired(const Part &P, const int *__restrict__ so,
+                                                   ColsD16P sc, const VT *__restrict__ sv,
+                                                   Pre pre, X x, Epi epi)
+{
+    using PV = decltype(pre(0));
+    const int lane = threadIdx.x & 63, wid = wave_id();
+    const int nw = P.nb * kWaves;
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += nw) {
+        const int off = so[s];
+        const int w = (so[s + 1] - off) >> 6;
+        const int np = w >> 1;
+        const int row = s * kSlice + lane;
+        const bool act = row < P.n;
+        const PV pv = act ? pre(row) : PV();
+        double acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[t] = 0.0;
+        constexpr int H = (WMAX < PHASE ? WMAX : PHASE) / 2;   // pairs per phase
+        double xv[NT];
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX / 2; h0 += H) {
+            int cc[2 * H];
+            VT vv[2 * H];
+#pragma unroll
+            for (int k = 0; k < H; k++) {
+                if (h0 + k < np) {
+                    const int e = off + (h0 + k) * 2 * kSlice + 2 * lane;
+                    ld_pair(sv + e, vv[2 * k], vv[2 * k + 1]);
+                    const int d2 = *reinterpret_cast<const int *>(sc.d + e);
+                    cc[2 * k] = row + (int)(short)(d2 & 0xffff);
+                    cc[2 * k + 1] = row + (d2 >> 16);
+                } else {
+                    cc[2 * k] = cc[2 * k + 1] = 0;
+                    vv[2 * k] = vv[2 * k + 1] = VT(0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 2 * H; k++)
+                if (h0 + k / 2 < np) {
+                    x(cc[k], xv);
+#pragma unroll
+                    for (int t = 0; t < NT; t++) acc[t] += (double)vv[k] * xv[t];
+                }
+        }
+        for (int k = WMAX / 2; k < np; k++)
+            for (int q = 0; q < 2; q++) {
+                const int e = off + k * 2 * kSlice + 2 * lane + q;
+                x(sc(e, row), xv);
+                const double vk = (double)ld_val(sv + e);
+#pragma unroll
+                for (int t = 0; t < NT; t++) acc[t] += vk * xv[t];
+            }
+        if (w & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            x(sc(e, row), xv);
+            const double vk = (double)ld_val(sv + e);
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t] += vk * xv[t];
+        }
+        if (act) epi(row, acc, pv);
+    }
+}
+
 template <int WMAX, int NT, class VT, class Cols, class Pre, class X, class Epi,
           int PHASE = NNQP_LOAD_PHASE>
 __device__ __forceinline__ void sell_rows_n(const Part &P, const int *__restrict__ so, Cols sc,
                                             const VT *__restrict__ sv, Pre pre, X x, Epi epi)
 {
+    if constexpr (std::is_same<Cols, ColsD16P>::value) {
+        sell_rows_n_paired<WMAX, NT, VT, Pre, X, Epi, PHASE>(P, so, sc, sv, pre, x, epi);
+        return;
+    } else {
     using PV = decltype(pre(0));
     const int lane = threadIdx.x & 63, wid = wave_id();
     const int nw = P.nb * kWaves;
@@ -364,6 +434,7 @@ __device__ __forceinline__ void sell_rows_n(const Part &P, const int *__restrict
             for (int t = 0; t < NT; t++) acc[t] += vk * xv[t];
         }
         if (act) epi(row, acc, pv);
+    }
     }
 }
 

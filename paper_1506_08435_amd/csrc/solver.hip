@@ -226,11 +226,13 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         // ---- 1. gradient and convergence test, with the Cauchy ladder around
         // the previous step length issued behind it (one synchronisation for
         // both; the ladder is unused on the last iteration)
-        prof_begin(ctx, KC_GRAD, B.spmv() + 16.0 * n);
-        launch_grad(ctx, A, vals, c, f, W.g, box);
+        // the float64 gradient reads the paired copy when the solve has one
+        const double grad_b = (VS.v64p ? spmv_s : B.spmv()) + 16.0 * n;
+        prof_begin(ctx, KC_GRAD, grad_b);
+        launch_grad(ctx, A, vals, VS.v64p, c, f, W.g, box);
         prof_end(ctx);
         S.spmvs++;
-        S.bytes_moved += B.spmv() + 16.0 * n;
+        S.bytes_moved += grad_b;
         // ladder ..., t_c / 10, t_c, 10 t_c, ... around the previous step
         // length, formed as the sequential search forms them (repeated x0.1
         // and x10)
@@ -516,7 +518,7 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
     double rel = 1.0;   // ||f - K c|| / ||f|| at c = 0
     for (int restart = 0;; restart++) {
         prof_begin(ctx, KC_GRAD, B.spmv() + 16.0 * n);
-        launch_grad(ctx, A, A->val, c, f, W.g, unbounded);   // g = K c - f
+        launch_grad(ctx, A, A->val, A->val64p, c, f, W.g, unbounded);   // g = K c - f
         prof_end(ctx);
         S.spmvs++;
         S.bytes_moved += B.spmv() + 16.0 * n;
