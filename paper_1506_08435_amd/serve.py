@@ -15,7 +15,8 @@ each step a non-negative QP warm-started from the previous one.  The server:
   resident request by one step; requests that arrive or finish assembling
   join at the next tick, finished requests leave and free their memory;
 * routes requests by size to lanes that tick independently on their own
-  streams, so small requests are not held by a large one's step.
+  streams, so small requests are not held by a large one's step; the top
+  lane steps each of its requests with the single-problem solver.
 
 Because a batch member's arithmetic does not depend on the other members, a
 request's result is bitwise the same whether it is served alone or in any mix.
@@ -95,9 +96,11 @@ class Report:
                 "lane_ticks": list(self.lane_ticks)}
 
 
-def estimate_bytes(problem, precision: int) -> int:
+def estimate_bytes(problem, precision: int, solo: bool = False) -> int:
     """Device bytes of a request before assembly: free DOF from the Dirichlet
-    mask, nonzeros per row of a structured P1 mesh (7 in 2D, 15 in 3D)."""
+    mask, nonzeros per row of a structured P1 mesh (7 in 2D, 15 in 3D).
+    solo: stepped by the single-problem solver, which adds the paired copies
+    (int16 offsets and values) and its own work vectors."""
     n = int((np.asarray(problem.dirichlet) == 0).sum())
     per_row = 7 if problem.dim == 2 else 15
     nnz = n * per_row
@@ -106,14 +109,27 @@ def estimate_bytes(problem, precision: int) -> int:
     b += 89.0 * n                               # solver work vectors
     if precision == nnqp.NN_MIXED:
         b += 4.0 * nnz + 40.0 * n
+    if solo:
+        b += (1.1 * (10.0 if precision == nnqp.NN_FP64 else 6.0)) * nnz + 40.0 * n
     return int(b + 17.0 * n)                    # f, c, active set
+
+
+def _step_one(ctx, K, dt, F, c, act, opts) -> dict:
+    """One backward-Euler step by the single-problem solver; a failing step
+    reports its status like a batch member does."""
+    try:
+        _, _, st = ctx.step_transient(K, dt, F, c, opts=opts, active=act, allow_maxit=True)
+        return st
+    except nnqp.NnError as e:
+        return {"status": e.status, "kkt_rel": math.inf, "cg_its": 0}
 
 
 class _Lane:
     """One batching lane: its own context and stream, queue and resident set."""
 
-    def __init__(self, idx, ctx, stream):
+    def __init__(self, idx, ctx, stream, solo=False):
         self.idx = idx
+        self.solo = solo
         self.ctx = ctx
         self.stream = stream
         self.pending = collections.deque()
@@ -138,7 +154,7 @@ class Server:
     def __init__(self, device: int = 0, hbm_budget: Optional[int] = None,
                  precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
                  inner_rtol: float = 0.1, assemble_workers: int = 2, keep_states: bool = False,
-                 bounds=(0.0, math.inf), lane_bounds=(30000, 300000)):
+                 bounds=(0.0, math.inf), lane_bounds=(30000, 300000), solo_lanes=1):
         import torch
         self.torch = torch
         self.device = device
@@ -152,6 +168,11 @@ class Server:
         self.workers = assemble_workers
         self.keep_states = keep_states
         self.lane_bounds = tuple(sorted(lane_bounds))
+        # the top `solo_lanes` lanes step each request with the single-problem
+        # solver (nn_step_transient) instead of one batched call: for the
+        # largest requests it is about twice as fast per step (paired layout,
+        # Cauchy ladder), and those requests set the tail latency
+        self.solo_from = len(self.lane_bounds) + 1 - max(0, int(solo_lanes))
         self._tls = threading.local()
 
     # worker-thread assembly on the thread's own context and stream
@@ -170,6 +191,10 @@ class Server:
         n = int((np.asarray(req.problem.dirichlet) == 0).sum())
         return sum(1 for b in self.lane_bounds if n >= b)
 
+    def is_solo(self, req: Request) -> bool:
+        """Whether the request is stepped by the single-problem solver."""
+        return self._lane_of(req) >= self.solo_from
+
     def run(self, requests: List[Request]) -> Report:
         torch = self.torch
         reqs = sorted(requests, key=lambda r: r.arrival)
@@ -177,7 +202,8 @@ class Server:
         lanes = []
         for k in range(len(self.lane_bounds) + 1):
             stream = torch.cuda.Stream(self.device)
-            lanes.append(_Lane(k, nnqp.Context(self.device, stream=stream), stream))
+            lanes.append(_Lane(k, nnqp.Context(self.device, stream=stream), stream,
+                               solo=k >= self.solo_from))
         for r in reqs:
             lanes[self._lane_of(r)].pending.append(r)
         shared = {"used": 0, "peak": 0}
@@ -221,7 +247,7 @@ class Server:
             # admission: first in, first out within the lane, while the estimate fits
             while L.waiting:
                 req = L.waiting[0]
-                est = estimate_bytes(req.problem, self.precision)
+                est = estimate_bytes(req.problem, self.precision, solo=L.solo)
                 if est > self.budget:
                     L.waiting.popleft()
                     res = results[req.rid]
@@ -242,6 +268,8 @@ class Server:
                 req, est = L.assembling.pop(fut)
                 K, F = fut.result()
                 nb = K.bytes(self.precision) + 17 * K.n
+                if L.solo:   # the paired copies and work vectors its steps will add
+                    nb = max(nb, est)
                 with lock:
                     shared["used"] += nb - est
                     shared["peak"] = max(shared["peak"], shared["used"])
@@ -256,10 +284,14 @@ class Server:
                     r = results[s["req"].rid]
                     if math.isnan(r.started):
                         r.started = tnow
-                _, _, stats, st = L.ctx.step_transient_batch(
-                    [s["K"] for s in L.resident], self.dt, [s["F"] for s in L.resident],
-                    [s["c"] for s in L.resident], opts=self.opts,
-                    actives=[s["act"] for s in L.resident], allow_fail=True)
+                if L.solo:
+                    stats = [_step_one(L.ctx, s["K"], self.dt, s["F"], s["c"], s["act"], self.opts)
+                             for s in L.resident]
+                else:
+                    _, _, stats, _ = L.ctx.step_transient_batch(
+                        [s["K"] for s in L.resident], self.dt, [s["F"] for s in L.resident],
+                        [s["c"] for s in L.resident], opts=self.opts,
+                        actives=[s["act"] for s in L.resident], allow_fail=True)
                 L.ticks += 1
                 L.batch_sum += len(L.resident)
                 tend = time.perf_counter() - t0
@@ -289,9 +321,9 @@ class Server:
 
 
 def solve_alone(req: Request, precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
-                inner_rtol: float = 0.1, ctx=None, bounds=(0.0, math.inf)):
-    """The same request run by itself (a batch of one per step): final c and
-    per-step stats."""
+                inner_rtol: float = 0.1, ctx=None, bounds=(0.0, math.inf), single: bool = False):
+    """The same request run by itself (a batch of one per step, or the
+    single-problem solver with `single`): final c and per-step stats."""
     import torch
     ctx = ctx or nnqp.Context(0)
     opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision,
@@ -300,8 +332,12 @@ def solve_alone(req: Request, precision: int = nnqp.NN_FP64, dt: float = 1e-3, t
     c = torch.zeros(max(K.n, 1), dtype=torch.float64, device=ctx.device)
     stats = []
     for _ in range(req.steps):
-        _, _, st, _ = ctx.step_transient_batch([K], dt, [F], [c], opts=opts)
-        stats.append(st[0])
+        if single:
+            _, _, st = ctx.step_transient(K, dt, F, c, opts=opts)
+            stats.append(st)
+        else:
+            _, _, st, _ = ctx.step_transient_batch([K], dt, [F], [c], opts=opts)
+            stats.append(st[0])
     out = c[:K.n].clone()
     K.free()
     return out, stats

@@ -64,8 +64,9 @@ def test_served_result_equals_alone(prec):
 @pytest.mark.gpu
 def test_lanes_tick_independently_and_equal_alone():
     """Requests routed to three size lanes (free DOF < 400, < 1200, larger)
-    run on three streams at once; each result is still bitwise the request
-    run alone, and the HBM budget shared by the lanes holds."""
+    run on three streams at once, the top lane stepping each request with the
+    single-problem solver; each result is still bitwise the request run alone
+    the same way, and the HBM budget shared by the lanes holds."""
     import torch
     from paper_1506_08435_amd import nnqp
     from paper_1506_08435_amd.serve import Server, estimate_bytes, solve_alone
@@ -81,10 +82,13 @@ def test_lanes_tick_independently_and_equal_alone():
     assert all(t > 0 for t in rep.lane_ticks) and len(rep.lane_ticks) == 3
     assert rep.peak_bytes <= budget
     ctx = nnqp.Context(0)
-    for req, res in zip(reqs, rep.results):
-        c_alone, st_alone = solve_alone(req, tol=1e-10, inner_rtol=0.1, ctx=ctx)
+    solo = [srv.is_solo(r) for r in reqs]
+    assert any(solo) and not all(solo)
+    for req, res, single in zip(reqs, rep.results, solo):
+        c_alone, st_alone = solve_alone(req, tol=1e-10, inner_rtol=0.1, ctx=ctx, single=single)
         assert torch.equal(res.c, c_alone), req.rid
         assert [s["cg_its"] for s in res.step_stats] == [s["cg_its"] for s in st_alone]
+        assert all(s["kkt_rel"] <= 1e-10 for s in res.step_stats)
     print(rep.summary())
 
 
