@@ -371,7 +371,7 @@ def run_serve(args):
         for prec_name in ("fp64", "mixed"):
             prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
             srv = Server(precision=prec, hbm_budget=budget, tol=1e-8, inner_rtol=args.serve_inner_rtol,
-                         lane_bounds=tuple(args.serve_lanes))
+                         lane_bounds=tuple(args.serve_lanes), solo_lanes=args.serve_solo_lanes)
             rep = srv.run(reqs)
             sm = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.summary().items()}
             sm["max_kkt_rel"] = max(s["kkt_rel"] for r in rep.results for s in r.step_stats)
@@ -380,7 +380,8 @@ def run_serve(args):
             "workload": f"serve: {args.nreq} requests per rate, Poisson arrivals at {args.rates} per s, "
                         f"2D/3D 50/50, free DOF log-uniform in [1e3, 1e6] (here {min(dofs)}..{max(dofs)}, "
                         f"total {sum(dofs)}), {args.serve_steps} backward-Euler steps each, dt = 1e-3, "
-                        f"seed {args.serve_seed}; size lanes split at {list(args.serve_lanes)} free DOF",
+                        f"seed {args.serve_seed}; size lanes split at {list(args.serve_lanes)} free DOF, "
+                        f"the top {args.serve_solo_lanes} stepped by the single-problem solver",
             "n_gpus": 1, **out}
     if not args.no_cpu_baseline:
         import numpy as np
@@ -444,6 +445,8 @@ def main():
                     help="inner CG tolerance of the served solves (TRON1)")
     ap.add_argument("--serve-lanes", type=float, nargs="*", default=[30000, 300000],
                     help="free-DOF bounds between the server's size lanes (none: one lane)")
+    ap.add_argument("--serve-solo-lanes", type=int, default=2,
+                    help="top lanes that step requests with the single-problem solver")
     ap.add_argument("--hbm-budget-gib", type=float, default=0.0,
                     help="server HBM budget (0: 3/4 of the free device memory)")
     ap.add_argument("--nbatch", type=int, default=512, help="members of the batch workload")

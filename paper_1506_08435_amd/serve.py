@@ -15,8 +15,8 @@ each step a non-negative QP warm-started from the previous one.  The server:
   resident request by one step; requests that arrive or finish assembling
   join at the next tick, finished requests leave and free their memory;
 * routes requests by size to lanes that tick independently on their own
-  streams, so small requests are not held by a large one's step; the top
-  lane steps each of its requests with the single-problem solver.
+  streams, so small requests are not held by a large one's step; the upper
+  lanes step each of their requests with the single-problem solver.
 
 Because a batch member's arithmetic does not depend on the other members, a
 request's result is bitwise the same whether it is served alone or in any mix.
@@ -154,7 +154,7 @@ class Server:
     def __init__(self, device: int = 0, hbm_budget: Optional[int] = None,
                  precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
                  inner_rtol: float = 0.1, assemble_workers: int = 2, keep_states: bool = False,
-                 bounds=(0.0, math.inf), lane_bounds=(30000, 300000), solo_lanes=1):
+                 bounds=(0.0, math.inf), lane_bounds=(30000, 300000), solo_lanes=2):
         import torch
         self.torch = torch
         self.device = device
@@ -171,7 +171,8 @@ class Server:
         # the top `solo_lanes` lanes step each request with the single-problem
         # solver (nn_step_transient) instead of one batched call: for the
         # largest requests it is about twice as fast per step (paired layout,
-        # Cauchy ladder), and those requests set the tail latency
+        # Cauchy ladder), and those requests set the tail latency; the many
+        # small requests of the bottom lane gain from sharing launches
         self.solo_from = len(self.lane_bounds) + 1 - max(0, int(solo_lanes))
         self._tls = threading.local()
 
