@@ -213,13 +213,15 @@ class Server:
         pool = cf.ThreadPoolExecutor(max_workers=self.workers)
         t0 = time.perf_counter()
         errors = []
+        abort = threading.Event()   # a failed lane stops the others (they may wait on its memory)
 
         def lane_loop(L: _Lane):
             try:
                 with torch.cuda.stream(L.stream):
-                    self._lane_loop(L, results, shared, lock, waited, pool, t0)
+                    self._lane_loop(L, results, shared, lock, waited, pool, t0, abort)
             except BaseException as e:   # surfaced after the lanes join
                 errors.append(e)
+                abort.set()
 
         threads = [threading.Thread(target=lane_loop, args=(L,)) for L in lanes]
         try:
@@ -239,9 +241,9 @@ class Server:
                       batch_sum / max(ticks, 1), len(waited), shared["peak"], self.budget,
                       [L.ticks for L in lanes])
 
-    def _lane_loop(self, L: _Lane, results, shared, lock, waited, pool, t0):
+    def _lane_loop(self, L: _Lane, results, shared, lock, waited, pool, t0, abort):
         torch = self.torch
-        while L.pending or L.waiting or L.assembling or L.resident:
+        while (L.pending or L.waiting or L.assembling or L.resident) and not abort.is_set():
             now = time.perf_counter() - t0
             while L.pending and L.pending[0].arrival <= now:
                 L.waiting.append(L.pending.popleft())

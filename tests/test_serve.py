@@ -173,3 +173,25 @@ def test_admission_estimate_bounds_assembled_bytes():
         for prec in (nnqp.NN_FP64, nnqp.NN_MIXED):
             assert estimate_bytes(p, prec) >= K.bytes(prec) + 17 * K.n, (k, prec)
         K.free()
+
+
+@pytest.mark.gpu
+def test_failed_request_stops_every_lane():
+    """A request whose assembly fails (a non-finite source, refused on the
+    host before any device work) raises from Server.run, and the other lanes
+    stop rather than run on or wait for memory the failed lane holds."""
+    import dataclasses
+    import time
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import Request, Server
+    reqs = _requests(6, steps=40, gap=0.0, seed=9)
+    bad = W.serve_problem(0, seed=5, dof_range=(2000, 2500))
+    bad = dataclasses.replace(bad, f_elem=np.full_like(bad.f_elem, np.nan))
+    reqs.append(Request(99, bad, 3, 0.0))
+    srv = Server(tol=1e-8, lane_bounds=(400, 1200))
+    assert srv.is_solo(reqs[-1])
+    t0 = time.perf_counter()
+    with pytest.raises(nnqp.NnError) as err:
+        srv.run(reqs)
+    assert err.value.status == nnqp.NN_ENONFINITE
+    assert time.perf_counter() - t0 < 60
