@@ -101,8 +101,13 @@ typedef struct {
                              [lower, upper].  Default 0. */
     double c0_value;      /* default 1e-8; must be finite */
     double delta0;        /* initial trust-region radius; <= 0 means unbounded
-                             (default).  The model is the objective itself, so the
-                             radius only ever grows. */
+                             (default).  With a radius, TRON's inner CG stops on the
+                             boundary of the ball of the radius left in the outer
+                             iteration (Steihaug), and the Cauchy step stays inside
+                             the radius.  The model is the objective itself, so the
+                             radius only ever grows (x4 when a step reaches it).
+                             The batched entry points scale the CG step back into
+                             the radius instead. */
     int32_t cg_chunk;     /* CG iterations enqueued between convergence reads; default 16 */
     int32_t verbose;      /* 1: one line per outer iteration on stderr; default 0 */
     double lower;         /* bounds lower <= c <= upper of the constrained solves
@@ -121,6 +126,13 @@ typedef struct {
                              the Gershgorin bound): k matrix passes per CG iteration,
                              fewer CG iterations.  The minimiser does not change.  The
                              batched entry points take 0 or 1 only. */
+    int32_t subspace;     /* TRON's subspace loop (Lin & More 1999): 1 = after a projected
+                             search that reached a new bound, and unless the CG stopped on
+                             the trust-region boundary, the CG and search repeat on the
+                             new face from a fresh gradient before the next Cauchy step;
+                             0 = every iteration starts with a Cauchy step.  Either way
+                             the minimiser is the same.  Default 1.  TRON single-problem
+                             entry points only (the batched ones run 0). */
 } nn_opts;
 
 /* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */
@@ -145,6 +157,11 @@ typedef struct {
     double seconds;       /* device time of the solve (HIP events on the stream) */
     double max_c;         /* max_i c_i (nn_solve_galerkin only, else 0) */
     int32_t n_negative;   /* #{i : c_i < 0} (nn_solve_galerkin only, else 0) */
+    int32_t subspace_its; /* iterations of TRON's subspace loop (CG steps without a new
+                             Cauchy step); included in outer_its */
+    int32_t radius_stops; /* inner solves that stopped on the trust-region radius (the CG
+                             step cut on its boundary, or no radius left after the Cauchy
+                             step) */
     int32_t reserved;
 } nn_stats;
 
@@ -331,8 +348,13 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
  * preconditioner only: NN_EINVAL for NN_BLMVM or precond_degree > 1).
  * Returns NN_OK when every member reached
  * tol; otherwise the status of the first member that did not (the others are
- * still solved and reported).  Workspace (about 100 bytes per row of the
- * whole batch) is allocated for the call and released before return.
+ * still solved and reported).  A failure of the call itself (invalid argument,
+ * allocation refused, HIP error) reaches no member: every stats[p].status is
+ * then that call status.  Workspace is allocated for the call and released
+ * before return: per row of the batch (rows of 64-row slices) 101 bytes in
+ * float64, 77 in mixed precision, plus per stored matrix entry (sliced-ELL,
+ * rows padded to the longest row of their slice) 12 bytes in float64, 18 in
+ * mixed precision (a concatenated copy of every member's matrix).
  */
 nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
                          const double *const *f_dev, const nn_opts *opts, double *const *c_dev,

@@ -200,11 +200,13 @@ nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, boo
     const bool fresh = K->kt && K->kt_dt == dt;
     if (fresh && (!mixed || K->kt32) && (!want32p || K->kt32p) && (!want64p || K->kt64p))
         return NN_OK;
-    if (!K->kt) {
-        if (dev_malloc(K->al, &K->kt, sizeof(double) * m) != hipSuccess ||
-            dev_malloc(K->al, &K->kt_diag, sizeof(double) * n) != hipSuccess)
-            return fail(ctx, NN_EOOM, "transient matrix allocation");
-    }
+    // each buffer is guarded on its own: a call that got one of them and was
+    // refused the other leaves the first in place, and a later call takes
+    // only the missing one (the values are formed below whenever kt_dt != dt)
+    if (!K->kt && dev_malloc(K->al, &K->kt, sizeof(double) * m) != hipSuccess)
+        return fail(ctx, NN_EOOM, "transient matrix allocation");
+    if (!K->kt_diag && dev_malloc(K->al, &K->kt_diag, sizeof(double) * n) != hipSuccess)
+        return fail(ctx, NN_EOOM, "transient diagonal allocation");
     if (mixed && !K->kt32 && dev_malloc(K->al, &K->kt32, sizeof(float) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient float32 allocation");
     if ((want32p || want64p) && ensure_paired(ctx, K, false) != NN_OK) return NN_EOOM;
@@ -349,6 +351,7 @@ nn_status nn_default_opts(nn_opts *o)
     o->method = NN_TRON;
     o->lmm_vectors = 5;
     o->max_lm_its = 20000;
+    o->subspace = 1;
     return NN_OK;
 }
 
@@ -533,7 +536,7 @@ nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_
     return NN_OK;
 }
 
-static nn_status check_opts(nn_ctx *ctx, const nn_opts *o)
+nn_status nnqp::check_opts(nn_ctx *ctx, const nn_opts *o)
 {
     if (!o) return fail(ctx, NN_EINVAL, "null options");
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(ctx, NN_EINVAL, "tol must be > 0");
@@ -550,6 +553,7 @@ static nn_status check_opts(nn_ctx *ctx, const nn_opts *o)
     if (o->method != NN_TRON && o->method != NN_BLMVM) return fail(ctx, NN_EINVAL, "unknown method");
     if (o->precond_degree < 0 || o->precond_degree > 8)
         return fail(ctx, NN_EINVAL, "precond_degree must be in 0..8");
+    if (o->subspace != 0 && o->subspace != 1) return fail(ctx, NN_EINVAL, "subspace must be 0 or 1");
     if (o->method == NN_BLMVM) {
         if (o->lmm_vectors < 1 || o->lmm_vectors > 8)
             return fail(ctx, NN_EINVAL, "lmm_vectors must be in 1..8");
@@ -652,12 +656,32 @@ static nn_status check_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
     return NN_OK;
 }
 
-nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K, double dt,
-                                  const double *const *f_dev, const nn_opts *opts,
-                                  double *const *c_dev, uint8_t *const *active_dev,
-                                  nn_stats *stats)
+// A failure of a batched call itself (invalid arguments, an allocation
+// refused, a HIP error) returns before any member is reported: every member
+// then carries that status, so a caller that reads only the per-member
+// reports (a server stepping its resident requests) cannot take an unstepped
+// member for a finished one.
+static void batch_stats_open(int32_t nprob, nn_stats *stats)
 {
-    NN_CHECK_CTX(ctx);
+    if (!stats) return;
+    for (int32_t p = 0; p < nprob; p++) {
+        std::memset(&stats[p], 0, sizeof(nn_stats));
+        stats[p].status = -1;   // not reported yet
+    }
+}
+static nn_status batch_stats_close(int32_t nprob, nn_stats *stats, nn_status rc)
+{
+    if (stats)
+        for (int32_t p = 0; p < nprob; p++)
+            if (stats[p].status == -1) stats[p].status = (int32_t)rc;
+    return rc;
+}
+
+static nn_status step_transient_batch_body(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
+                                           double dt, const double *const *f_dev,
+                                           const nn_opts *opts, double *const *c_dev,
+                                           uint8_t *const *active_dev, nn_stats *stats)
+{
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, NN_EINVAL, "dt must be > 0");
     nn_status st = check_batch(ctx, nprob, K, f_dev, opts, c_dev, true);
     if (st != NN_OK) return st;
@@ -673,11 +697,25 @@ nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *
     return solve_batch_impl(ctx, nprob, K, f_dev, &o, c_dev, active_dev, stats, dt);
 }
 
-nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
-                         const double *const *f_dev, const nn_opts *opts, double *const *c_dev,
-                         uint8_t *const *active_dev, nn_stats *stats)
+nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K, double dt,
+                                  const double *const *f_dev, const nn_opts *opts,
+                                  double *const *c_dev, uint8_t *const *active_dev,
+                                  nn_stats *stats)
 {
-    NN_CHECK_CTX(ctx);
+    batch_stats_open(nprob, stats);
+    if (!ctx) return batch_stats_close(nprob, stats, NN_EINVAL);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return batch_stats_close(nprob, stats, fail(ctx, NN_EHIP, "hipSetDevice"));
+    return batch_stats_close(nprob, stats,
+                             step_transient_batch_body(ctx, nprob, K, dt, f_dev, opts, c_dev,
+                                                       active_dev, stats));
+}
+
+static nn_status solve_batch_body(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
+                                  const double *const *f_dev, const nn_opts *opts,
+                                  double *const *c_dev, uint8_t *const *active_dev,
+                                  nn_stats *stats)
+{
     nn_status st = check_batch(ctx, nprob, K, f_dev, opts, c_dev, false);
     if (st != NN_OK) return st;
     if (nprob == 0) {
@@ -685,6 +723,19 @@ nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
         return NN_OK;
     }
     return solve_batch_impl(ctx, nprob, K, f_dev, opts, c_dev, active_dev, stats, 0.0);
+}
+
+nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
+                         const double *const *f_dev, const nn_opts *opts, double *const *c_dev,
+                         uint8_t *const *active_dev, nn_stats *stats)
+{
+    batch_stats_open(nprob, stats);
+    if (!ctx) return batch_stats_close(nprob, stats, NN_EINVAL);
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return batch_stats_close(nprob, stats, fail(ctx, NN_EHIP, "hipSetDevice"));
+    return batch_stats_close(nprob, stats,
+                             solve_batch_body(ctx, nprob, K, f_dev, opts, c_dev, active_dev,
+                                              stats));
 }
 
 nn_status nn_set_profiling(nn_ctx *ctx, int classes)

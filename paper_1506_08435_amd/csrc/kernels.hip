@@ -286,23 +286,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         S->done = 0;
         S->it = 0;
+        S->ww[0] = 0.0;   // w = 0
+        S->tr_hit = 0;
     }
 }
 
 // CG iteration j, matrix pass.
 // Prologue (identical in every block): r.z_j and r.r_j from the partials the
-// previous kernel left in slot U[j%2]; stop if r.r_j <= rtol^2 r.r_0 or at the
-// iteration cap; beta_j = r.z_j / r.z_{j-1} (0 for j = 0).
+// previous kernel left in slot U[j%2]; stop if r.r_j <= rtol^2 r.r_0, at the
+// iteration cap, or when the previous update stopped on the trust-region
+// boundary; beta_j = r.z_j / r.z_{j-1} (0 for j = 0).
 // Body: the direction update p <- z + beta p and its product q = K p are
 // formed together, using K p = K z + beta (K p_old): only z is gathered, and
-// p, q are updated in place on the free rows; partials of p.q into SLOT_Q.
+// p, q are updated in place on the free rows; partials of p.q into SLOT_Q
+// (with TR, also p.p and w.p, which the update needs for |w + alpha p|).
 // Columns outside the free set contribute 0 because z vanishes there.
-template <int WMAX, class VT, class VV, class Cols>
+template <int WMAX, class VT, class VV, class Cols, bool TR>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restrict__ so, Cols sc,
                                                     const VT *__restrict__ v,
                                                     const uint8_t *__restrict__ mask,
                                                     const VV *__restrict__ z,
                                                     VV *__restrict__ p, VV *__restrict__ q,
+                                                    const VV *__restrict__ w,
                                                     double *partials, DevScalars *S, int j,
                                                     int max_it, double rtol2)
 {
@@ -312,7 +317,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restric
     const double rz = u[0], rr2 = u[1];
     const double rr_stop = j == 0 ? rtol2 * rr2 : S->rr_stop;
     int done = 0;
-    if (!isfinite(rz) || !isfinite(rr2)) done = 4;
+    if (TR && j > 0 && S->tr_hit) done = 2;
+    else if (!isfinite(rz) || !isfinite(rr2)) done = 4;
     else if ((j == 0 && (rr2 == 0.0 || u[2] == 0.0)) || (j > 0 && rr2 <= rr_stop) ||
              j >= max_it || !(rz > 0.0))
         done = 1;
@@ -330,7 +336,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restric
         }
     }
     if (done) return;
-    double a[1] = {0.0};
+    constexpr int NQ = TR ? 3 : 1;
+    double a[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; k++) a[k] = 0.0;
     sell_rows<WMAX>(P, so, sc, v, [&](int i) { return mask[i] != 0; },
                     [&](int i) { return Three{(double)p[i], (double)q[i], (double)z[i]}; },
                     [&](int jj) { return (double)z[jj]; }, [&](int i, double kz, Three pqz) {
@@ -339,8 +348,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restric
                         p[i] = pi;
                         q[i] = qi;
                         a[0] += (double)pi * (double)qi;
+                        if constexpr (TR) {
+                            a[1] += (double)pi * (double)pi;
+                            a[2] += (double)w[i] * (double)pi;
+                        }
                     });
-    block_partial<OP_SUM, 1>(a, slot_ptr(partials, SLOT_Q));
+    block_partial<0u, NQ>(a, slot_ptr(partials, SLOT_Q));
 }
 
 // CG iteration j, vector update on free rows.
@@ -349,7 +362,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Part P, const int *__restric
 // r.z_{j+1}, r.r_{j+1} into slot U[(j+1)%2].  With the Chebyshev
 // preconditioner (cres set) z starts as dm r / theta, the Chebyshev residual
 // and first increment are set, and the last Chebyshev pass replaces r.z.
-template <class VV>
+// With a finite trust region (TR, radius^2 delta2) the step alpha that
+// would take |w + alpha p| past the radius is cut to the tau >= 0 with
+// |w + tau p| = radius (Steihaug's truncated CG, as TRON's inner solve),
+// using |w|^2 kept on the device by the recurrence
+// |w + t p|^2 = |w|^2 + 2 t w.p + t^2 p.p; the next matrix pass then ends
+// the CG (done = 2).
+template <class VV, bool TR>
 __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__restrict__ mask,
                                                       const VV *__restrict__ p,
                                                       const VV *__restrict__ q,
@@ -357,11 +376,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__r
                                                       VV *__restrict__ w, VV *__restrict__ r,
                                                       VV *__restrict__ z, double *partials,
                                                       DevScalars *S, int j, VV *__restrict__ cres,
-                                                      VV *__restrict__ cdz0, double inv_theta)
+                                                      VV *__restrict__ cdz0, double inv_theta,
+                                                      double delta2)
 {
     if (S->done) return;
-    double pqa[1];
-    combine_partials<OP_SUM, 1>(slot_ptr(partials, SLOT_Q), P.nb, pqa);
+    constexpr int NQ = TR ? 3 : 1;
+    double pqa[NQ];
+    combine_partials<0u, NQ>(slot_ptr(partials, SLOT_Q), P.nb, pqa);
     const double pq = pqa[0];
     if (!(pq > 0.0 && isfinite(pq))) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -370,7 +391,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Part P, const uint8_t *__r
         }
         return;
     }
-    const double alpha = S->rzh[j & 1] / pq;
+    double alpha = S->rzh[j & 1] / pq;
+    if constexpr (TR) {
+        const double pp = pqa[1], wp = pqa[2], ww = S->ww[j & 1];
+        double wn = ww + alpha * (2.0 * wp + alpha * pp);
+        int hit = 0;
+        if (wn >= delta2) {
+            // positive root of pp t^2 + 2 wp t + (ww - delta2) = 0 (ww <= delta2),
+            // in the form without cancellation for either sign of wp
+            const double room = fmax(delta2 - ww, 0.0);
+            const double disc = sqrt(wp * wp + pp * room);
+            alpha = wp >= 0.0 ? room / (wp + disc) : (disc - wp) / pp;
+            wn = delta2;
+            hit = 1;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S->ww[(j + 1) & 1] = wn;
+            S->tr_hit = hit;
+        }
+    }
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for_rows(P, [&](int i, bool act) {
         if (!act || !mask[i]) return;
@@ -774,46 +813,62 @@ void launch_gersh(nn_ctx *ctx, const nn_matrix *A, const double *vals, const dou
     k_gersh<<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, vals, diag, ctx->partials);
 }
 
-void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol)
+template <bool TR>
+static void cg_spmv_tr(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it,
+                       double rtol)
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
     if (V.v32p && A->d16p) {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16P>), P.nb, P, A->sl_off,
-                      ColsD16P{A->d16p}, V.v32p, W.mask, W.z32, W.p32, W.q32, ctx->partials,
-                      ctx->scal, j, max_it, rtol * rtol);
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16P, TR>), P.nb, P, A->sl_off,
+                      ColsD16P{A->d16p}, V.v32p, W.mask, W.z32, W.p32, W.q32, W.w32,
+                      ctx->partials, ctx->scal, j, max_it, rtol * rtol);
     } else if (V.v32 && A->sl_d16) {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16>), P.nb, P, A->sl_off,
-                      ColsD16{A->sl_d16}, V.v32, W.mask, W.z32, W.p32, W.q32, ctx->partials,
-                      ctx->scal, j, max_it, rtol * rtol);
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16, TR>), P.nb, P, A->sl_off,
+                      ColsD16{A->sl_d16}, V.v32, W.mask, W.z32, W.p32, W.q32, W.w32,
+                      ctx->partials, ctx->scal, j, max_it, rtol * rtol);
     } else if (V.v32) {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsI32>), P.nb, P, A->sl_off,
-                      ColsI32{A->sl_col}, V.v32, W.mask, W.z32, W.p32, W.q32, ctx->partials,
-                      ctx->scal, j, max_it, rtol * rtol);
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsI32, TR>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v32, W.mask, W.z32, W.p32, W.q32, W.w32,
+                      ctx->partials, ctx->scal, j, max_it, rtol * rtol);
     } else if (V.v64p && A->d16p) {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double, ColsD16P>), P.nb, P, A->sl_off,
-                      ColsD16P{A->d16p}, V.v64p, W.mask, W.z, W.p0, W.q, ctx->partials, ctx->scal,
-                      j, max_it, rtol * rtol);
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double, ColsD16P, TR>), P.nb, P, A->sl_off,
+                      ColsD16P{A->d16p}, V.v64p, W.mask, W.z, W.p0, W.q, W.w, ctx->partials,
+                      ctx->scal, j, max_it, rtol * rtol);
     } else {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double, ColsI32>), P.nb, P, A->sl_off,
-                      ColsI32{A->sl_col}, V.v64, W.mask, W.z, W.p0, W.q, ctx->partials, ctx->scal,
-                      j, max_it, rtol * rtol);
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, double, double, ColsI32, TR>), P.nb, P, A->sl_off,
+                      ColsI32{A->sl_col}, V.v64, W.mask, W.z, W.p0, W.q, W.w, ctx->partials,
+                      ctx->scal, j, max_it, rtol * rtol);
     }
 }
 
-void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32, const Cheb *ch)
+void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol,
+                    bool tr)
+{
+    if (tr) cg_spmv_tr<true>(ctx, A, V, j, max_it, rtol);
+    else cg_spmv_tr<false>(ctx, A, V, j, max_it, rtol);
+}
+
+template <bool TR>
+static void cg_update_tr(nn_ctx *ctx, int64_t n, int j, bool f32, const Cheb *ch, double delta2)
 {
     Part P = make_part(n);
     Workspace &W = ctx->ws;
     const double it = ch ? 1.0 / ch->theta : 0.0;
     if (f32)
-        k_cg_update<float><<<P.nb, kBlock, 0, ctx->stream>>>(
+        k_cg_update<float, TR><<<P.nb, kBlock, 0, ctx->stream>>>(
             P, W.mask, W.p32, W.q32, W.dm32, W.w32, W.r32, W.z32, ctx->partials, ctx->scal, j,
-            ch ? W.cres32 : nullptr, ch ? W.cdz32[0] : nullptr, it);
+            ch ? W.cres32 : nullptr, ch ? W.cdz32[0] : nullptr, it, delta2);
     else
-        k_cg_update<double><<<P.nb, kBlock, 0, ctx->stream>>>(
+        k_cg_update<double, TR><<<P.nb, kBlock, 0, ctx->stream>>>(
             P, W.mask, W.p0, W.q, W.dm, W.w, W.r, W.z, ctx->partials, ctx->scal, j,
-            ch ? W.cres : nullptr, ch ? W.cdz[0] : nullptr, it);
+            ch ? W.cres : nullptr, ch ? W.cdz[0] : nullptr, it, delta2);
+}
+
+void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32, const Cheb *ch, double delta2)
+{
+    if (std::isfinite(delta2)) cg_update_tr<true>(ctx, n, j, f32, ch, delta2);
+    else cg_update_tr<false>(ctx, n, j, f32, ch, delta2);
 }
 
 void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g, Box B)

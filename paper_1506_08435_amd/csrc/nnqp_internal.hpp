@@ -53,8 +53,11 @@ struct DevScalars {
     double rr_stop;        // stop when r.r <= rr_stop
     double n_free;         // free rows of the current face
     double nnz_free;       // nonzeros in the free rows (byte model)
-    int done;              // CG: 0 running, 1 converged/capped, 3 breakdown, 4 non-finite
+    double ww[2];          // |w_j|^2 of the CG iterate (trust-region solves), at j % 2
+    int done;              // CG: 0 running, 1 converged/capped, 2 trust-region boundary,
+                           // 3 breakdown, 4 non-finite
     int it;                // CG iterations done
+    int tr_hit;            // the last update stopped w on the trust-region boundary
 };
 
 // ---------------------------------------------------------------- objects
@@ -213,6 +216,9 @@ nn_status fail(nn_ctx *ctx, nn_status st, const std::string &msg);
     } while (0)
 
 nn_status ensure_workspace(nn_ctx *ctx, int64_t n);
+// Option checks shared by the solve entry points (api.hip).
+nn_status check_opts(nn_ctx *ctx, const nn_opts *o);
+
 // Sliced-ELL offsets of a CSR pattern: off[s] for s = 0..nslices, widest slice.
 void sell_offsets(const int64_t *rowptr, int64_t n, std::vector<int64_t> &off, int &wmax);
 // Device CSR values (ordered by rowptr) -> sliced-ELL arrays of A (col, vals, diag).
@@ -274,10 +280,15 @@ void launch_resid(nn_ctx *ctx, const nn_matrix *A, const double *vals, const dou
 // c += w (float64 CG solution vector)
 void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w);
 // CG iteration j: direction update + matrix pass (prologue: scalars from the
-// previous kernel's partials); float32 values and vectors when V.v32 is set
-void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol);
-// CG iteration j: vector update (Chebyshev start terms when ch is given)
-void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32, const Cheb *ch = nullptr);
+// previous kernel's partials); float32 values and vectors when V.v32 is set.
+// tr: a trust-region solve (the pass also reduces p.p and w.p for the update)
+void launch_cg_spmv(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, int max_it, double rtol,
+                    bool tr = false);
+// CG iteration j: vector update (Chebyshev start terms when ch is given).
+// delta2 finite: the iterate w stays in the ball |w| <= sqrt(delta2); a step
+// that would leave it stops on the boundary (Steihaug) and ends the CG.
+void launch_cg_update(nn_ctx *ctx, int64_t n, int j, bool f32, const Cheb *ch = nullptr,
+                      double delta2 = __builtin_inf());
 // [host] first bound crossing along w: min over w<0 of (c-lo)/(-w) and over
 // w>0 of (hi-c)/w, min; g.w sum, w.w sum
 void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const double *g, Box B);

@@ -18,14 +18,22 @@
 //      binding).  Jacobi-PCG on
 //      K_FF w = -g_F from w = 0 until ||r|| <= inner_rtol ||g_F|| (TRON's
 //      inner tolerance, Sec. 5.1 TRON1/2/3), all scalars kept on the device.
+//      With a finite trust radius the CG iterate is kept inside the ball of
+//      the radius left after the steps already taken in this outer iteration
+//      (Steihaug: the step that would leave it stops on its boundary).
 //   4. Projected search along w from the Cauchy point: if no free variable
 //      crosses a bound for a unit step the step is taken without a matrix pass
 //      (CG from zero guarantees sufficient decrease along its own iterate);
 //      otherwise P(c + t w) is tried for t = 1, 1/2, ... down to the first
 //      breakpoint, where the step is again safe.
-//   5. Trust region: the quadratic model is the objective, so the ratio of
+//   5. Subspace loop (TRON): when the search stopped on a new face (a free
+//      variable reached its bound) and the CG did not stop on the trust-region
+//      boundary, steps 3-4 repeat from the new point on its face (a fresh
+//      gradient, no new Cauchy step) before the outer iteration ends.
+//   6. Trust region: the quadratic model is the objective, so the ratio of
 //      actual to predicted reduction is one; the radius (unbounded unless the
-//      caller gives one) grows by 4x whenever a step reaches it.
+//      caller gives one) grows by 4x whenever the outer iteration's step
+//      reaches it.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -41,6 +49,7 @@ constexpr double kExtrap = 10.0;    // Cauchy extrapolation factor
 constexpr double kInterp = 0.1;     // Cauchy interpolation factor
 constexpr double kBack = 0.5;       // projected-search backtracking factor
 constexpr int kMaxTrials = 60;
+constexpr int kMaxSubspace = 100;   // subspace steps per outer iteration
 
 struct Bytes {
     double n, nnz;
@@ -217,15 +226,20 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
 
     double t_cauchy = 1.0;
     double delta = o->delta0 > 0.0 ? o->delta0 : INFINITY;
+    const bool tr = std::isfinite(delta);   // CG truncated at the trust-region boundary
     const int chunk = o->cg_chunk > 0 ? o->cg_chunk : 16;
     nn_status result = NN_EMAXIT;
+    bool subspace = false;    // this iteration continues the subspace loop (no Cauchy step)
+    int sub_run = 0;          // subspace steps taken in the current outer iteration
+    double step_outer = 0.0;  // bound on |c - c_k| over the current outer iteration
 
     static_assert(kLadder == 3, "ladder buffers: ks0, ks1, ks2");
     double *const ladder_ks[kLadder] = {W.ks0, W.ks1, W.ks2};
     for (int outer = 0;; outer++) {
         // ---- 1. gradient and convergence test, with the Cauchy ladder around
         // the previous step length issued behind it (one synchronisation for
-        // both; the ladder is unused on the last iteration)
+        // both; the ladder is unused on the last iteration and skipped on a
+        // subspace step)
         // the float64 gradient reads the paired copy when the solve has one
         const double grad_b = (VS.v64p ? spmv_s : B.spmv()) + 16.0 * n;
         prof_begin(ctx, KC_GRAD, grad_b);
@@ -241,11 +255,16 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         lt[kMid] = t_cauchy;
         for (int r = kMid - 1; r >= 0; r--) lt[r] = lt[r + 1] * kInterp;
         for (int r = kMid + 1; r < kLadder; r++) lt[r] = lt[r - 1] * kExtrap;
-        prof_begin(ctx, KC_TRIAL, spmv_s + (16.0 + 8.0 * kLadder) * n);
-        launch_ladder(ctx, A, VS, c, W.g, lt, ladder_ks, box);
-        prof_end(ctx);
         double lres[3 * kLadder];
-        if ((rc = read_grad_and_ladder(ctx, n, red, lres)) != NN_OK) return rc;
+        if (subspace) {
+            static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
+            if ((rc = host_reduce(ctx, n, 5, kGradOps, red)) != NN_OK) return rc;
+        } else {
+            prof_begin(ctx, KC_TRIAL, spmv_s + (16.0 + 8.0 * kLadder) * n);
+            launch_ladder(ctx, A, VS, c, W.g, lt, ladder_ks, box);
+            prof_end(ctx);
+            if ((rc = read_grad_and_ladder(ctx, n, red, lres)) != NN_OK) return rc;
+        }
         if (red[1] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite gradient"));
         S.kkt_rel = std::sqrt(red[0]) / normf;
         S.kkt_nat_inf = red[2];
@@ -261,115 +280,125 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             fail(ctx, NN_EMAXIT, "outer iteration cap reached");
             break;
         }
-        S.spmvs += kLadder;
-        S.cauchy_trials += kLadder;
-        S.bytes_moved += spmv_s + (16.0 + 8.0 * kLadder) * n;
-
-        // ---- 2. Cauchy point along the projected steepest-descent path.
-        // The decisions are those of the sequential search (start at t_c,
-        // extrapolate x10 while the test holds, else interpolate x0.1 until
-        // it holds), read off the ladder; a search that leaves the ladder
-        // continues with single trials.
-        double *best_ks = ladder_ks[kMid];
-        auto scratch_for = [&](const double *busy) { return busy == W.ks0 ? W.ks1 : W.ks0; };
-        auto trial_cauchy = [&](double t, double *ks, double &gs, double &sks, double &ss) -> nn_status {
-            prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
-            launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ks, box);
-            prof_end(ctx);
-            S.spmvs++;
-            S.cauchy_trials++;
-            S.bytes_moved += spmv_s + 16.0 * n;
-            nn_status r2 = host_reduce(ctx, n, 3, kTrialOps, red);
-            gs = red[0];
-            sks = red[1];
-            ss = red[2];
-            return r2;
-        };
-        auto ok_decrease = [&](double gs, double sks, double ss) {
-            return gs < 0.0 && gs + 0.5 * sks <= kMu0 * gs && std::sqrt(ss) <= delta;
-        };
-        auto lg = [&](int k) { return lres[3 * k]; };
-        auto lk = [&](int k) { return lres[3 * k + 1]; };
-        auto ls = [&](int k) { return lres[3 * k + 2]; };
-        double t = lt[kMid], gs = lg(kMid), sks = lk(kMid), ss = ls(kMid);
-        if (ok_decrease(gs, sks, ss)) {
-            int k = 0;
-            bool open_end = true;   // the chain may continue past the ladder
-            for (int r = kMid + 1; r < kLadder; r++, k++) {
-                if (!ok_decrease(lg(r), lk(r), ls(r))) {
-                    open_end = false;
-                    break;
-                }
-                const bool same = lg(r) == gs && lk(r) == sks;
-                t = lt[r];
-                best_ks = ladder_ks[r];
-                gs = lg(r);
-                sks = lk(r);
-                ss = ls(r);
-                if (same) {   // every moving variable has reached its bound
-                    open_end = false;
-                    break;
-                }
-            }
-            for (; open_end && k < 20; k++) {
-                double gs2, sks2, ss2;
-                double *ks_try = scratch_for(best_ks);
-                if ((rc = trial_cauchy(t * kExtrap, ks_try, gs2, sks2, ss2)) != NN_OK) return rc;
-                if (!ok_decrease(gs2, sks2, ss2)) break;
-                const bool same = gs2 == gs && sks2 == sks;
-                t *= kExtrap;
-                best_ks = ks_try;
-                gs = gs2;
-                sks = sks2;
-                ss = ss2;
-                if (same) break;
-            }
+        const double *cg_ks = nullptr;   // Cauchy-step product added to g at the CG set-up
+        if (subspace) {
+            S.subspace_its++;
         } else {
-            // t <- 0.1 t until the test holds, at most kMaxTrials times, while g.s < 0
-            int k = 0, r = kMid - 1;
-            for (;;) {
-                if (r >= 0) {
+            S.spmvs += kLadder;
+            S.cauchy_trials += kLadder;
+            S.bytes_moved += spmv_s + (16.0 + 8.0 * kLadder) * n;
+
+            // ---- 2. Cauchy point along the projected steepest-descent path.
+            // The decisions are those of the sequential search (start at t_c,
+            // extrapolate x10 while the test holds, else interpolate x0.1 until
+            // it holds), read off the ladder; a search that leaves the ladder
+            // continues with single trials.
+            double *best_ks = ladder_ks[kMid];
+            auto scratch_for = [&](const double *busy) { return busy == W.ks0 ? W.ks1 : W.ks0; };
+            auto trial_cauchy = [&](double t, double *ks, double &gs, double &sks, double &ss) -> nn_status {
+                prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
+                launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ks, box);
+                prof_end(ctx);
+                S.spmvs++;
+                S.cauchy_trials++;
+                S.bytes_moved += spmv_s + 16.0 * n;
+                nn_status r2 = host_reduce(ctx, n, 3, kTrialOps, red);
+                gs = red[0];
+                sks = red[1];
+                ss = red[2];
+                return r2;
+            };
+            auto ok_decrease = [&](double gs, double sks, double ss) {
+                return gs < 0.0 && gs + 0.5 * sks <= kMu0 * gs && std::sqrt(ss) <= delta;
+            };
+            auto lg = [&](int k) { return lres[3 * k]; };
+            auto lk = [&](int k) { return lres[3 * k + 1]; };
+            auto ls = [&](int k) { return lres[3 * k + 2]; };
+            double t = lt[kMid], gs = lg(kMid), sks = lk(kMid), ss = ls(kMid);
+            if (ok_decrease(gs, sks, ss)) {
+                int k = 0;
+                bool open_end = true;   // the chain may continue past the ladder
+                for (int r = kMid + 1; r < kLadder; r++, k++) {
+                    if (!ok_decrease(lg(r), lk(r), ls(r))) {
+                        open_end = false;
+                        break;
+                    }
+                    const bool same = lg(r) == gs && lk(r) == sks;
                     t = lt[r];
                     best_ks = ladder_ks[r];
                     gs = lg(r);
                     sks = lk(r);
                     ss = ls(r);
-                    r--;
-                } else {
-                    t *= kInterp;
-                    best_ks = W.ks0;
-                    if ((rc = trial_cauchy(t, best_ks, gs, sks, ss)) != NN_OK) return rc;
+                    if (same) {   // every moving variable has reached its bound
+                        open_end = false;
+                        break;
+                    }
                 }
-                if (ok_decrease(gs, sks, ss) || !(++k < kMaxTrials && gs < 0.0)) break;
+                for (; open_end && k < 20; k++) {
+                    double gs2, sks2, ss2;
+                    double *ks_try = scratch_for(best_ks);
+                    if ((rc = trial_cauchy(t * kExtrap, ks_try, gs2, sks2, ss2)) != NN_OK) return rc;
+                    if (!ok_decrease(gs2, sks2, ss2)) break;
+                    const bool same = gs2 == gs && sks2 == sks;
+                    t *= kExtrap;
+                    best_ks = ks_try;
+                    gs = gs2;
+                    sks = sks2;
+                    ss = ss2;
+                    if (same) break;
+                }
+            } else {
+                // t <- 0.1 t until the test holds, at most kMaxTrials times, while g.s < 0
+                int k = 0, r = kMid - 1;
+                for (;;) {
+                    if (r >= 0) {
+                        t = lt[r];
+                        best_ks = ladder_ks[r];
+                        gs = lg(r);
+                        sks = lk(r);
+                        ss = ls(r);
+                        r--;
+                    } else {
+                        t *= kInterp;
+                        best_ks = W.ks0;
+                        if ((rc = trial_cauchy(t, best_ks, gs, sks, ss)) != NN_OK) return rc;
+                    }
+                    if (ok_decrease(gs, sks, ss) || !(++k < kMaxTrials && gs < 0.0)) break;
+                }
+                if (!ok_decrease(gs, sks, ss)) {
+                    // no decrease possible along -g at this precision: stationary up to rounding
+                    fail(ctx, NN_EMAXIT, "Cauchy search found no decrease (rounding floor)");
+                    break;
+                }
             }
-            if (!ok_decrease(gs, sks, ss)) {
-                // no decrease possible along -g at this precision: stationary up to rounding
-                fail(ctx, NN_EMAXIT, "Cauchy search found no decrease (rounding floor)");
-                break;
-            }
+            t_cauchy = t;
+            prof_begin(ctx, KC_OTHER, 24.0 * n);
+            launch_apply(ctx, n, c, dir_g, -t, box);
+            prof_end(ctx);
+            S.bytes_moved += 24.0 * n;
+            step_outer = std::sqrt(ss);
+            cg_ks = best_ks;
         }
-        t_cauchy = t;
-        prof_begin(ctx, KC_OTHER, 24.0 * n);
-        launch_apply(ctx, n, c, dir_g, -t, box);
-        prof_end(ctx);
-        S.bytes_moved += 24.0 * n;
-        double step_norm = std::sqrt(ss);
 
-        // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point
+        // ---- 3. masked Jacobi-PCG on the free face of the Cauchy point (or
+        // of the current point on a subspace step), inside the radius left
+        const double delta_rem = delta - step_outer;
+        const double delta2 = tr ? std::max(delta_rem, 0.0) * std::max(delta_rem, 0.0) : INFINITY;
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, diag, c, W.g, best_ks, mixed, box, false, chp);
+        launch_cg_setup(ctx, A, diag, c, W.g, cg_ks, mixed, box, false, chp);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
         for (int st = 1; st <= csteps; st++) launch_cheb(ctx, A, VS, cheb, st, SLOT_U0);
         int it_seen = 0, j_next = 0;
-        for (;;) {
+        H.done = tr && !(delta_rem > 0.0) ? 2 : 0;   // no room left: no CG step
+        for (; !H.done;) {
             const size_t mark = ctx->prof_live.size();
             for (int k = 0; k < chunk; k++, j_next++) {
                 prof_begin(ctx, KC_CG_SPMV, -1.0);
-                launch_cg_spmv(ctx, A, VS, j_next, o->max_cg, o->inner_rtol);
+                launch_cg_spmv(ctx, A, VS, j_next, o->max_cg, o->inner_rtol, tr);
                 prof_end(ctx);
                 prof_begin(ctx, KC_CG_UPDATE, -1.0);
-                launch_cg_update(ctx, n, j_next, mixed, chp);
+                launch_cg_update(ctx, n, j_next, mixed, chp, delta2);
                 prof_end(ctx);
                 const int slot = ((j_next + 1) & 1) ? SLOT_U1 : SLOT_U0;
                 for (int st = 1; st <= csteps; st++) {
@@ -383,8 +412,9 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             // byte model of the launches that did work; the rest exited at once
             const double nf = H.n_free, nzf = H.nnz_free;
             // matrix pass on the free rows (indices 4 or 2 B, values 8 or 4 B), z gathered,
-            // p and q read and written; update: p, q, dm, w, r read, w, r, z written
-            const double b_spmv = n + 4.0 * nf + (ib + vb) * nzf + 5.0 * vb * nf;
+            // p and q read and written (and w read in a trust-region solve); update:
+            // p, q, dm, w, r read, w, r, z written
+            const double b_spmv = n + 4.0 * nf + (ib + vb) * nzf + (tr ? 6.0 : 5.0) * vb * nf;
             const double b_upd = n + 8.0 * vb * nf + (chp ? 2.0 * vb * nf : 0.0);
             // Chebyshev pass: matrix on the free rows, dz gathered, res and z
             // read and written, dzp, dm, r read, dzn written
@@ -398,11 +428,11 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             S.bytes_moved += ran * (b_spmv + b_upd + csteps * b_cheb);
             S.spmvs += ran * (1 + csteps);
             it_seen = H.it;
-            if (H.done) break;
         }
         S.cg_its += it_seen;
         if (H.done == 4) return finish(fail(ctx, NN_ENONFINITE, "non-finite value in CG"));
         if (H.done == 3) return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature in CG"));
+        const bool on_boundary = H.done == 2;   // the CG step stopped on the trust region
 
         // ---- 4. projected search along w
         prof_begin(ctx, KC_OTHER, 24.0 * n);
@@ -411,8 +441,10 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         S.bytes_moved += 24.0 * n;
         if ((rc = host_reduce(ctx, n, 3, kBrkOps, red)) != NN_OK) return rc;
         const double bmin = red[0], gw = red[1], wn = std::sqrt(red[2]);
+        bool new_face = false;   // the step reached a bound the CG face did not hold
         if (it_seen > 0 && gw < 0.0 && wn > 0.0) {
-            double tmax = std::min(1.0, delta / wn);
+            // |w| <= delta_rem up to rounding: the CG kept it in the ball
+            double tmax = std::min(1.0, delta_rem / wn);
             double ts = tmax;
             if (bmin < tmax) {
                 for (int k = 0; k < kMaxTrials; k++) {
@@ -437,16 +469,30 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                 launch_apply(ctx, n, c, dir_w, ts, box);
                 prof_end(ctx);
                 S.bytes_moved += 24.0 * n;
-                step_norm += ts * wn;
+                step_outer += ts * wn;
+                new_face = bmin <= ts;
             }
         }
         if (o->verbose)
             std::fprintf(stderr,
-                         "nnqp outer %3d kkt %.3e active %d free %.0f cauchy t %.3g cg %d "
-                         "breakpoint %.3g step %.3e\n",
-                         outer, S.kkt_rel, S.n_active, H.n_free, t_cauchy, it_seen, bmin, step_norm);
-        // ---- 5. radius update (exact model: ratio one)
-        if (std::isfinite(delta) && step_norm >= 0.99 * delta) delta *= 4.0;
+                         "nnqp outer %3d %s kkt %.3e active %d free %.0f cauchy t %.3g cg %d "
+                         "breakpoint %.3g step %.3e%s\n",
+                         outer, subspace ? "subspace" : "cauchy  ", S.kkt_rel, S.n_active,
+                         H.n_free, t_cauchy, it_seen, bmin, step_outer,
+                         on_boundary ? " (trust-region boundary)" : "");
+        if (on_boundary) S.radius_stops++;
+        // ---- 5. subspace loop: another CG step on the new face, unless the
+        // step stopped on the trust-region boundary
+        subspace = o->subspace && new_face && !on_boundary && sub_run < kMaxSubspace &&
+                   !(tr && step_outer >= 0.99 * delta);
+        if (subspace) {
+            sub_run++;
+            continue;
+        }
+        sub_run = 0;
+        // ---- 6. radius update (exact model: ratio one)
+        if (tr && step_outer >= 0.99 * delta) delta *= 4.0;
+        step_outer = 0.0;
     }
     if (result == NN_OK) ctx->err.clear();
     return finish(result);

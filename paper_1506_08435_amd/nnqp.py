@@ -59,7 +59,8 @@ class Opts(ctypes.Structure):
                 ("cg_chunk", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("lower", ctypes.c_double), ("upper", ctypes.c_double),
                 ("method", ctypes.c_int32), ("lmm_vectors", ctypes.c_int32),
-                ("max_lm_its", ctypes.c_int32), ("precond_degree", ctypes.c_int32)]
+                ("max_lm_its", ctypes.c_int32), ("precond_degree", ctypes.c_int32),
+                ("subspace", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -71,6 +72,7 @@ class Stats(ctypes.Structure):
                 ("refinements", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("bytes_moved", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("max_c", ctypes.c_double), ("n_negative", ctypes.c_int32),
+                ("subspace_its", ctypes.c_int32), ("radius_stops", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:

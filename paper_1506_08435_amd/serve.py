@@ -96,11 +96,27 @@ class Report:
                 "lane_ticks": list(self.lane_ticks)}
 
 
+def batch_workspace_bytes(n: int, dim: int, precision: int) -> int:
+    """Device bytes a batched call allocates for one member for the length of
+    the call: the member's rows in the concatenated work vectors (gradient,
+    two search products, mask, start value, load, diagonal, row lengths and
+    six CG vectors; whole 64-row slices) and its entries in the concatenated
+    block-diagonal matrix (int32 columns and float64 values; float32 values
+    and int16 offsets too in mixed precision), counted at the longest row of
+    a structured P1 pattern (7 in 2D, 15 in 3D) for every row of a slice."""
+    rows = 64 * ((n + 63) // 64)
+    nsell = (7 if dim == 2 else 15) * rows
+    if precision == nnqp.NN_MIXED:
+        return int(77.0 * rows + 18.0 * nsell)
+    return int(101.0 * rows + 12.0 * nsell)
+
+
 def estimate_bytes(problem, precision: int, solo: bool = False) -> int:
     """Device bytes of a request before assembly: free DOF from the Dirichlet
     mask, nonzeros per row of a structured P1 mesh (7 in 2D, 15 in 3D).
     solo: stepped by the single-problem solver, which adds the paired copies
-    (int16 offsets and values) and its own work vectors."""
+    (int16 offsets and values) and its own work vectors; otherwise stepped by
+    batched calls, whose per-call workspace is counted."""
     n = int((np.asarray(problem.dirichlet) == 0).sum())
     per_row = 7 if problem.dim == 2 else 15
     nnz = n * per_row
@@ -111,16 +127,27 @@ def estimate_bytes(problem, precision: int, solo: bool = False) -> int:
         b += 4.0 * nnz + 40.0 * n
     if solo:
         b += (1.1 * (10.0 if precision == nnqp.NN_FP64 else 6.0)) * nnz + 40.0 * n
+    else:
+        b += batch_workspace_bytes(n, problem.dim, precision)
     return int(b + 17.0 * n)                    # f, c, active set
 
 
+# statuses that belong to one request's step (the request fails, the server
+# goes on); any other status is a failure of the call itself
+_REQUEST_STATUSES = (nnqp.NN_EMAXIT, nnqp.NN_ENONFINITE, nnqp.NN_ENOTSPD)
+
+
 def _step_one(ctx, K, dt, F, c, act, opts) -> dict:
-    """One backward-Euler step by the single-problem solver; a failing step
-    reports its status like a batch member does."""
+    """One backward-Euler step by the single-problem solver.  A status of the
+    request's own problem (iteration cap, non-finite value, curvature) is
+    reported like a batch member's; any other failure (memory, HIP, invalid
+    argument) is raised, and the server stops."""
     try:
         _, _, st = ctx.step_transient(K, dt, F, c, opts=opts, active=act, allow_maxit=True)
         return st
     except nnqp.NnError as e:
+        if e.status not in _REQUEST_STATUSES:
+            raise
         return {"status": e.status, "kkt_rel": math.inf, "cg_its": 0}
 
 
@@ -154,7 +181,8 @@ class Server:
     def __init__(self, device: int = 0, hbm_budget: Optional[int] = None,
                  precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
                  inner_rtol: float = 0.1, assemble_workers: int = 2, keep_states: bool = False,
-                 bounds=(0.0, math.inf), lane_bounds=(30000, 300000), solo_lanes=2):
+                 bounds=(0.0, math.inf), lane_bounds=(30000, 300000), solo_lanes=2,
+                 allocator=None):
         import torch
         self.torch = torch
         self.device = device
@@ -174,6 +202,9 @@ class Server:
         # Cauchy ladder), and those requests set the tail latency; the many
         # small requests of the bottom lane gain from sharing launches
         self.solo_from = len(self.lane_bounds) + 1 - max(0, int(solo_lanes))
+        # device memory of every context the server makes (lanes and assembly
+        # workers): None for hipMalloc, else as nnqp.Context's `allocator`
+        self.allocator = allocator
         self._tls = threading.local()
 
     # worker-thread assembly on the thread's own context and stream
@@ -181,7 +212,7 @@ class Server:
         torch = self.torch
         if getattr(self._tls, "ctx", None) is None:
             stream = torch.cuda.Stream(self.device)
-            self._tls.ctx = nnqp.Context(self.device, stream=stream)
+            self._tls.ctx = nnqp.Context(self.device, stream=stream, allocator=self.allocator)
         wctx = self._tls.ctx
         with torch.cuda.stream(wctx.stream):
             K, F, _ = wctx.assemble(req.problem, with_mass=True)
@@ -203,8 +234,9 @@ class Server:
         lanes = []
         for k in range(len(self.lane_bounds) + 1):
             stream = torch.cuda.Stream(self.device)
-            lanes.append(_Lane(k, nnqp.Context(self.device, stream=stream), stream,
-                               solo=k >= self.solo_from))
+            lanes.append(_Lane(k, nnqp.Context(self.device, stream=stream,
+                                               allocator=self.allocator),
+                               stream, solo=k >= self.solo_from))
         for r in reqs:
             lanes[self._lane_of(r)].pending.append(r)
         shared = {"used": 0, "peak": 0}
@@ -273,6 +305,8 @@ class Server:
                 nb = K.bytes(self.precision) + 17 * K.n
                 if L.solo:   # the paired copies and work vectors its steps will add
                     nb = max(nb, est)
+                else:        # the workspace of the batched calls that step it
+                    nb += batch_workspace_bytes(K.n, req.problem.dim, self.precision)
                 with lock:
                     shared["used"] += nb - est
                     shared["peak"] = max(shared["peak"], shared["used"])
@@ -291,10 +325,15 @@ class Server:
                     stats = [_step_one(L.ctx, s["K"], self.dt, s["F"], s["c"], s["act"], self.opts)
                              for s in L.resident]
                 else:
-                    _, _, stats, _ = L.ctx.step_transient_batch(
+                    _, _, stats, rc = L.ctx.step_transient_batch(
                         [s["K"] for s in L.resident], self.dt, [s["F"] for s in L.resident],
                         [s["c"] for s in L.resident], opts=self.opts,
                         actives=[s["act"] for s in L.resident], allow_fail=True)
+                    # members failing on their own problems are reported per
+                    # request; a failure of the call itself stepped no member
+                    if rc not in (nnqp.NN_OK,) + _REQUEST_STATUSES:
+                        raise nnqp.NnError(rc, "nn_step_transient_batch: "
+                                           + L.ctx.last_error())
                 L.ticks += 1
                 L.batch_sum += len(L.resident)
                 tend = time.perf_counter() - t0

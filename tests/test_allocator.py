@@ -162,3 +162,53 @@ def test_allocator_failure_is_reported_and_leaks_nothing():
         assert not live, (limit, len(live))
     assert outcomes[0] == "create" and outcomes[-1] == "done"
     assert {"assemble", "solve", "batch"} <= set(outcomes), outcomes
+
+
+@pytest.mark.gpu
+def test_transient_step_after_refused_diagonal_matches_oracle():
+    """A backward-Euler step whose M/dt + K diagonal allocation is refused
+    (forced from the host: the first request of n float64 after arming) gives
+    NN_EOOM; the next step on the same matrix, with memory available, forms
+    the missing buffer and matches the oracle's step."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1506_08435_amd import nnqp
+
+    p = W.config_transient3d(12, 10, 6, ell=2.0)
+    S = oracle.assemble(p, with_mass=True)
+    arm = [False]
+    live = {}
+
+    def alloc(nbytes):
+        if arm[0] and nbytes == 8 * S.n:
+            arm[0] = False
+            return None
+        q = torch.cuda.caching_allocator_alloc(nbytes, 0, torch.cuda.current_stream(0))
+        live[q] = nbytes
+        return q
+
+    def free(q):
+        if live.pop(q, None) is not None:
+            torch.cuda.caching_allocator_delete(q)
+
+    ctx = nnqp.Context(0, allocator=(alloc, free))
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    assert K.n == S.n
+    c0 = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    arm[0] = True
+    with pytest.raises(nnqp.NnError) as err:
+        ctx.step_transient(K, 1e-3, F, c0.clone(), tol=1e-12)
+    assert err.value.status == nnqp.NN_EOOM
+    assert not arm[0], "the diagonal allocation was not the one refused"
+    c, _, st = ctx.step_transient(K, 1e-3, F, c0.clone(), tol=1e-12)
+    ref = oracle.transient_step(S, 1e-3, np.zeros(S.n), tol=1e-13)
+    assert ref.certified
+    c = c.cpu().numpy()
+    assert c.min() >= 0.0
+    err = np.abs(c - ref.c).max() / np.abs(ref.c).max()
+    assert err <= 1e-8, err
+    K.free()
+    ctx.close()
+    torch.cuda.synchronize()
+    assert not live

@@ -33,7 +33,15 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _check_solution(S, c, active, ref_c, tol=PARITY_TOL):
+# cases whose minimiser has no strictly active node (every node at zero is
+# degenerate, c = g = 0); every other case must have some, so the active-set
+# comparison below is never vacuous
+NO_STRICT = {"batch_member_5", "batch8435_3_n32"}
+
+
+def _check_solution(S, c, active, ref_c, tol=PARITY_TOL, strict_expected=True):
+    """strict_expected: whether the case has strictly active nodes (asserted
+    either way), or None (not asserted: a random sample of batch members)."""
     assert c.min() >= 0.0, c.min()
     assert np.array_equal(active.astype(bool), c == 0.0)
     scale = np.abs(ref_c).max()
@@ -41,6 +49,10 @@ def _check_solution(S, c, active, ref_c, tol=PARITY_TOL):
     assert err <= tol, err
     g_ref = oracle.spmv(S, ref_c) - S.F
     free, strict = oracle.nondegenerate_masks(ref_c, g_ref, S.F)
+    assert free.any(), "no free node to compare"
+    if strict_expected is not None:
+        assert strict.any() == strict_expected, "strictly active nodes: expected some" \
+            if strict_expected else "strictly active nodes: expected none"
     assert np.all(c[free] > 0.0), "a free node came out active"
     assert np.all(c[strict] == 0.0), "a strictly active node came out free"
     return err
@@ -112,7 +124,7 @@ def test_solve_matches_oracle(ctx, name):
     S = oracle.assemble(p)
     ref = oracle.solve(S, tol=1e-13)
     assert ref.certified
-    err = _check_solution(S, c, active, ref.c)
+    err = _check_solution(S, c, active, ref.c, strict_expected=name not in NO_STRICT)
     k = oracle.kkt(S, c)
     assert k.r <= 1.01e-12 + 4 * ref.floor
     print(f"{name}: n={S.n} err={err:.2e} kkt={k.r:.2e} outer={st['outer_its']} "
@@ -303,6 +315,102 @@ def test_full_size_cube128_certificate(ctx):
           f"{st['seconds']:.3f} s -> {S.n / st['seconds'] / 1e6:.2f} M DOF/s")
 
 
+# ---------------------------------------------------------------- full size, element by element
+# Above 512 blocks x 16 wavefronts x 64 rows = 524,288 rows every row pass
+# gives each wavefront two or more slices (the grid-stride walk the benchmark
+# times on the 128^3 cube); the Cauchy ladder pass (256 blocks) does so from
+# 262,144 rows.
+MULTI_SLICE_ROWS = 512 * 16 * 64
+
+
+@pytest.fixture(scope="module")
+def cube88(ctx):
+    """cube3d(88): 658,503 free DOF, the 128^3 workload's tensor and source
+    on a coarser grid; the oracle's minimiser at tol 1e-13, computed once."""
+    import time
+    p = W.cube3d(88)
+    S = oracle.assemble(p)
+    t0 = time.perf_counter()
+    ref = oracle.solve(S, tol=1e-13)
+    print(f"cube88 oracle: {time.perf_counter() - t0:.1f} s on {oracle.num_threads()} threads, "
+          f"r = {ref.r:.2e}, floor {ref.floor:.2e}")
+    assert ref.certified
+    K, F, _ = ctx.assemble(p)
+    assert K.n == S.n > MULTI_SLICE_ROWS
+    return p, S, ref, K, F
+
+
+@pytest.mark.timeout(600)
+def test_full_size_cube88_fp64_elementwise(ctx, cube88):
+    """The multi-slice launch path, element by element at the spec bar:
+    ||c - c_ref||_inf / ||c_ref||_inf <= 1e-8 with the active set identical
+    on every node the oracle decides (free and strictly active both present)."""
+    p, S, ref, K, F = cube88
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, inner_rtol=0.1)
+    c, active = _np(c), _np(active)
+    err = _check_solution(S, c, active, ref.c)
+    g_ref = oracle.spmv(S, ref.c) - S.F
+    free, strict = oracle.nondegenerate_masks(ref.c, g_ref, S.F)
+    k = oracle.kkt(S, c)
+    assert k.r <= 1.01e-12 + 4 * ref.floor
+    print(f"cube88 fp64: n={S.n} err={err:.2e} kkt={k.r:.2e} free {int(free.sum())} strict "
+          f"{int(strict.sum())} degenerate {S.n - int(free.sum()) - int(strict.sum())} "
+          f"outer={st['outer_its']} cg={st['cg_its']} {st['seconds'] * 1e3:.1f} ms")
+
+
+@pytest.mark.timeout(600)
+def test_full_size_cube88_mixed_elementwise(ctx, cube88):
+    """The same system in mixed precision (float32 values and CG vectors,
+    float64 residual): within the stated 1e-6 of the float64 oracle, error
+    printed; active set identical on the nodes the oracle decides."""
+    from paper_1506_08435_amd import nnqp
+    p, S, ref, K, F = cube88
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-10, inner_rtol=0.1, precision=nnqp.NN_MIXED)
+    c, active = _np(c), _np(active)
+    err = _check_solution(S, c, active, ref.c, tol=MIXED_TOL)
+    print(f"cube88 mixed: n={S.n} err={err:.2e} outer={st['outer_its']} cg={st['cg_its']} "
+          f"{st['seconds'] * 1e3:.1f} ms")
+
+
+@pytest.mark.timeout(900)
+def test_full_size_batch_512_elementwise(ctx):
+    """The 512-member batch in one batched call at tol 1e-12 (the concatenated
+    rows, 12.6 M, are far past the multi-slice threshold): sampled members,
+    the largest among them, element by element against the oracle at 1e-8
+    with identical nondegenerate active sets."""
+    probs = [W.batch_problem(i) for i in range(512)]
+    Ks, Fs = [], []
+    for p in probs:
+        K, F, _ = ctx.assemble(p)
+        Ks.append(K)
+        Fs.append(F)
+    from paper_1506_08435_amd import nnqp
+    assert sum(K.n for K in Ks) > MULTI_SLICE_ROWS
+    cs, acts, stats, st = ctx.solve_batch(Ks, Fs, tol=1e-12, inner_rtol=0.1, allow_fail=True)
+    # 1e-12 is at the float64 rounding floor of the most anisotropic members:
+    # those stop when no decrease is left (NN_EMAXIT) a little above it
+    floor = [k for k, s in enumerate(stats) if s["status"] != 0]
+    for s in stats:
+        assert s["status"] in (0, nnqp.NN_EMAXIT) and s["kkt_rel"] <= 1e-10, s
+    print(f"batch 512 at tol 1e-12: {len(floor)} members stopped at their rounding floor "
+          f"(max kkt {max(stats[k]['kkt_rel'] for k in floor) if floor else 0:.2e})")
+    rng = np.random.default_rng(1512)
+    sample = sorted(set(rng.choice(512, size=5, replace=False).tolist()) |
+                    {int(np.argmax([K.n for K in Ks]))} | set(floor[:1]))
+    any_strict = False
+    for k in sample:
+        S = oracle.assemble(probs[k])
+        ref = oracle.solve(S, tol=1e-13)
+        assert ref.certified
+        c, a = _np(cs[k]), _np(acts[k])
+        err = _check_solution(S, c, a, ref.c, strict_expected=None)
+        g_ref = oracle.spmv(S, ref.c) - S.F
+        any_strict |= bool(oracle.nondegenerate_masks(ref.c, g_ref, S.F)[1].any())
+        print(f"batch member {k} (n={S.n}): err {err:.2e} outer {stats[k]['outer_its']} "
+              f"cg {stats[k]['cg_its']}")
+    assert any_strict
+
+
 # ---------------------------------------------------------------- mixed precision
 @pytest.mark.parametrize("name", ["square2d_64", "cube3d_21_ragged", "transient_field_20x18x9",
                                   "batch_member_5"])
@@ -316,7 +424,8 @@ def test_mixed_precision_matches_oracle(ctx, name):
     c, active = _np(c), _np(active)
     S = oracle.assemble(p)
     ref = oracle.solve(S, tol=1e-13)
-    err = _check_solution(S, c, active, ref.c, tol=MIXED_TOL)
+    err = _check_solution(S, c, active, ref.c, tol=MIXED_TOL,
+                          strict_expected=name not in NO_STRICT)
     assert st["refinements"] == st["outer_its"] + 1
     print(f"mixed {name}: err={err:.2e} outer={st['outer_its']} cg={st['cg_its']}")
 
@@ -406,7 +515,7 @@ def test_batch_matches_oracle(ctx, batch_members):
     for p, S, c, a, s in zip(probs, Ss, cs, acts, stats):
         ref = oracle.solve(S, tol=1e-13)
         assert ref.certified
-        err = _check_solution(S, _np(c), _np(a), ref.c)
+        err = _check_solution(S, _np(c), _np(a), ref.c, strict_expected=p.name not in NO_STRICT)
         k = oracle.kkt(S, _np(c))
         assert k.r <= 1.01e-12 + 4 * ref.floor, (p.name, k.r)
         assert s["status"] == 0 and s["kkt_rel"] <= 1e-12
@@ -653,7 +762,16 @@ def _shifted(p):
     return p
 
 
-def _check_box(S, c, active, ref_c, lo, hi, tol=PARITY_TOL):
+# box cases whose upper bound binds strictly somewhere (on the cube with a
+# hole the solution stays below 1, so only the lower bound does)
+STRICT_UPPER = {"square2d_64_capped", "cube3d_16_capped", "square2d_40_shifted"}
+
+
+def _check_box(S, c, active, ref_c, lo, hi, tol=PARITY_TOL, strict_upper=True,
+               strict_lower=True):
+    """strict_upper / strict_lower: whether the case has strictly active
+    nodes at that bound (asserted either way), or None (not checked: members
+    of a batch that share one bound)."""
     assert c.min() >= lo and c.max() <= hi, (c.min(), c.max())
     codes = np.where(c == lo, 1, np.where(c == hi, 2, 0))
     assert np.array_equal(active, codes)
@@ -662,6 +780,11 @@ def _check_box(S, c, active, ref_c, lo, hi, tol=PARITY_TOL):
     assert err <= tol, err
     g_ref = oracle.spmv(S, ref_c) - S.F
     free, strict = oracle.nondegenerate_masks(ref_c, g_ref, S.F, lo=lo, hi=hi)
+    assert free.any(), "no free node to compare"
+    if strict_lower is not None:
+        assert (strict & (ref_c == lo)).any() == strict_lower
+    if strict_upper is not None:
+        assert (strict & (ref_c == hi)).any() == strict_upper
     assert np.all((c[free] > lo) & (c[free] < hi)), "a free node came out at a bound"
     assert np.array_equal(c[strict], ref_c[strict]), "a strictly active node came out free"
     return err
@@ -680,7 +803,7 @@ def test_box_solve_matches_oracle(ctx, name):
     c, active = _np(c), _np(active)
     ref = oracle.solve(S, tol=1e-13, lo=lo, hi=hi)
     assert ref.certified
-    err = _check_box(S, c, active, ref.c, lo, hi)
+    err = _check_box(S, c, active, ref.c, lo, hi, strict_upper=name in STRICT_UPPER)
     k = oracle.kkt(S, c, lo=lo, hi=hi)
     assert k.r <= 1.01e-12 + 4 * ref.floor
     n_hi = int((c == hi).sum())
@@ -805,7 +928,7 @@ def test_blmvm_matches_oracle(ctx, name):
     c, active = _np(c), _np(active)
     S = oracle.assemble(p)
     ref = oracle.solve(S, tol=1e-13, lo=lo, hi=hi)
-    err = _check_box(S, c, active, ref.c, lo, hi)
+    err = _check_box(S, c, active, ref.c, lo, hi, strict_upper=name in STRICT_UPPER)
     k = oracle.kkt(S, c, lo=lo, hi=hi)
     assert k.r <= 1.01e-12 + 4 * ref.floor
     assert st["cg_its"] == 0 and st["outer_its"] > 0
@@ -937,8 +1060,103 @@ def test_batch_two_sided_bounds_match_oracle(ctx, batch_members):
             continue
         c, act = _np(c), _np(act)
         ref = oracle.solve(S, tol=1e-13, hi=hi)
-        _check_box(S, c, act, ref.c, 0.0, hi)
+        _check_box(S, c, act, ref.c, 0.0, hi, strict_upper=None, strict_lower=None)
         uppers += int((c == hi).sum())
     assert uppers > 0
     one, _, _, _ = ctx.solve_batch([Ks[3]], [Fs[3]], tol=1e-12, upper=hi)
     assert np.array_equal(_np(one[0]), _np(cs[3]))
+
+
+# ---------------------------------------------------------------- trust region, subspace loop
+TR_CASES = {
+    "square2d_64": lambda: W.config_small(),
+    "cube3d_21_ragged": lambda: W.cube3d(21),
+    "transient_field_20x18x9": lambda: W.config_transient3d(20, 18, 9, ell=3.0),
+}
+
+
+@pytest.mark.parametrize("subspace", [0, 1])
+@pytest.mark.parametrize("name", sorted(TR_CASES))
+def test_trust_region_same_minimiser(ctx, name, subspace):
+    """A finite initial radius (TRON's trust region, Sec. 3.1): the CG stops
+    on the boundary (Steihaug) and the radius grows x4 when a step reaches
+    it; the solve takes more outer iterations than without a radius and
+    reaches the oracle's minimiser, with or without the subspace loop."""
+    p = TR_CASES[name]()
+    K, F, _ = ctx.assemble(p)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    delta0 = 1e-3 * float(np.linalg.norm(ref.c))
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, delta0=delta0, subspace=subspace)
+    err = _check_solution(S, _np(c), _np(active), ref.c, strict_expected=name not in NO_STRICT)
+    k = oracle.kkt(S, _np(c))
+    assert k.r <= 1.01e-12 + 4 * ref.floor
+    assert st["radius_stops"] > 0, "the radius never bound a step"
+    _, _, st_inf = ctx.solve_nonneg(K, F, tol=1e-12, subspace=subspace)
+    assert st_inf["radius_stops"] == 0
+    if not subspace:
+        assert st["subspace_its"] == 0 and st_inf["subspace_its"] == 0
+    print(f"{name} subspace={subspace}: delta0={delta0:.3e} err={err:.2e} outer "
+          f"{st['outer_its']} (unbounded {st_inf['outer_its']}), radius stops "
+          f"{st['radius_stops']}, subspace steps {st['subspace_its']} "
+          f"(unbounded {st_inf['subspace_its']}), cg {st['cg_its']}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("subspace", [0, 1])
+def test_trust_region_first_step_inside_radius(ctx, prec, subspace):
+    """One outer iteration from c0 with a small radius: the whole step (the
+    Cauchy step, the CG step cut at the boundary of the radius left, and any
+    subspace steps) stays inside the ball, and reaches a good part of it."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    precision = nnqp.NN_MIXED if prec == "mixed" else nnqp.NN_FP64
+    p = W.cube3d(16)
+    K, F, _ = ctx.assemble(p)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-12)
+    for frac in (1e-3, 3e-2):
+        delta0 = frac * float(np.linalg.norm(ref.c))
+        c0 = np.full(S.n, 1e-8)
+        c, _, st = ctx.solve_nonneg(K, F, tol=1e-14, delta0=delta0, max_outer=1,
+                                    allow_maxit=True, subspace=subspace, precision=precision)
+        assert st["status"] == nnqp.NN_EMAXIT
+        step = float(np.linalg.norm(_np(c) - c0))
+        assert step <= delta0 * (1 + 1e-9), (frac, step, delta0)
+        assert step >= 0.1 * delta0, (frac, step, delta0)
+        assert _np(c).min() >= 0.0
+        print(f"{prec} subspace={subspace} radius {delta0:.3e}: step {step:.3e} "
+              f"({step / delta0:.3f} of the radius), cg {st['cg_its']}")
+
+
+def test_trust_region_mixed_and_transient(ctx):
+    """Mixed precision and a backward-Euler step with a finite radius give the
+    float64 minimisers (1e-6 and 1e-8)."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.cube3d(21)
+    K, F, _ = ctx.assemble(p)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    delta0 = 1e-2 * float(np.linalg.norm(ref.c))
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-11, delta0=delta0, precision=nnqp.NN_MIXED)
+    err = _check_solution(S, _np(c), _np(active), ref.c, tol=MIXED_TOL)
+    print(f"mixed with radius: err {err:.2e} outer {st['outer_its']}")
+    q = W.config_transient3d(14, 12, 8, ell=2.0)
+    Sq = oracle.assemble(q, with_mass=True)
+    Kq, Fq, _ = ctx.assemble(q, with_mass=True)
+    r = oracle.transient_step(Sq, 1e-3, np.zeros(Sq.n), tol=1e-13)
+    cq = torch.zeros(Kq.n, dtype=torch.float64, device=ctx.device)
+    cq, aq, stq = ctx.step_transient(Kq, 1e-3, Fq, cq, tol=1e-12,
+                                     delta0=1e-2 * float(np.linalg.norm(r.c)))
+    Kt, ft = oracle.transient_system(Sq, 1e-3, np.zeros(Sq.n))
+    St = oracle.System(n=Sq.n, rowptr=Sq.rowptr, col=Sq.col, K=Kt, M=None, F=ft, dof=Sq.dof)
+    _check_solution(St, _np(cq), _np(aq), r.c)
+
+
+def test_subspace_option_validated(ctx):
+    from paper_1506_08435_amd import nnqp
+    K, F, _ = ctx.assemble(W.square2d(8))
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_nonneg(K, F, subspace=2)
+    assert ei.value.status == nnqp.NN_EINVAL

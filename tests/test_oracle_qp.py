@@ -350,3 +350,80 @@ def test_transient_box_large_dt_is_steady(oracle_mod):
     assert (steady.c == 0.5).any()
     r = oracle_mod.transient_step(S, 1e12, np.zeros(S.n), tol=1e-13, hi=0.5)
     np.testing.assert_allclose(r.c, steady.c, rtol=0, atol=1e-10)
+
+
+# ---------------------------------------------------------------- nondegenerate masks
+def _kkt_problem(c_star, g_star, seed):
+    """A dense SPD K and the load F = K c* - g* for which c* is the minimiser
+    whenever (c*, g*) satisfy the KKT conditions of the box."""
+    rng = np.random.default_rng(seed)
+    n = c_star.size
+    A = rng.standard_normal((n, n))
+    K = A @ A.T + n * np.eye(n)
+    return K, K @ c_star - g_star
+
+
+def test_nondegenerate_masks_hand_built_lower_bound(oracle_mod):
+    """Free, strictly active and degenerate nodes known by construction
+    (c >= 0, g >= 0, c.g = 0; Sec. 2.1.3, eq. non-negative), with ||c||_inf
+    = 2e-3 and ||F||_inf ~ 1e3: nodes 0, 3 and 6 free; node 4 free with c far
+    below the F scale but above 1e-8 ||c||_inf; node 1 strictly active; node
+    2 degenerate (c = g = 0); node 5 at zero with g above 1e-8 ||c||_inf but
+    below 1e-8 ||F||_inf, which the masks leave undecided (the two scales
+    swapped would call node 4 undecided and node 5 strict).  Brute force
+    confirms the minimiser, and its surviving assignments differ on the
+    degenerate node 2 only."""
+    c_star = np.array([1e-3, 0.0, 0.0, 2e-3, 1e-9, 0.0, 5e-4])
+    g_star = np.array([0.0, 4.0, 0.0, 0.0, 0.0, 1e-6, 0.0])
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((7, 7))
+    K = 1e5 * (A @ A.T + 7 * np.eye(7))
+    F = K @ c_star - g_star
+    assert 1e2 < np.abs(F).max() < 1e4
+    free, strict = oracle_mod.nondegenerate_masks(c_star, g_star, F)
+    assert free.tolist() == [True, False, False, True, True, False, True]
+    assert strict.tolist() == [False, True, False, False, False, False, False]
+    # the masks of the minimiser as brute force finds it
+    c_bf, survivors = brute.brute_force(K, F)
+    assert np.abs(c_bf - c_star).max() <= 1e-12 * np.abs(c_star).max()
+    g_bf = K @ c_bf - F
+    free_bf, strict_bf = oracle_mod.nondegenerate_masks(c_bf, g_bf, F)
+    assert np.array_equal(free_bf, free) and np.array_equal(strict_bf, strict)
+    sets = [set(a) for a in survivors]
+    assert len(sets) == 2 and set.union(*sets) - set.intersection(*sets) == {2}
+
+
+def test_nondegenerate_masks_hand_built_two_sided(oracle_mod):
+    """Box [lo, hi] = [-0.5, 1]: strict at lo needs g > 0, strict at hi needs
+    g < 0 (a sign slip on either side fails); nodes at a bound with g = 0 are
+    degenerate; free nodes are inside both bounds by more than 1e-8 ||c||_inf."""
+    lo, hi = -0.5, 1.0
+    c_star = np.array([lo, hi, 0.3, hi, lo, 0.9999, -0.2])
+    g_star = np.array([2.0, -3.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    K, F = _kkt_problem(c_star, g_star, 9)
+    free, strict = oracle_mod.nondegenerate_masks(c_star, g_star, F, lo=lo, hi=hi)
+    assert free.tolist() == [False, False, True, False, False, True, True]
+    assert strict.tolist() == [True, True, False, False, False, False, False]
+    c_bf, _ = brute.brute_force(K, F, lo=lo, hi=hi)
+    assert np.abs(c_bf - c_star).max() <= 1e-12
+    # the wrong sign on the upper side turns the strict upper node away
+    flipped = g_star.copy()
+    flipped[1] = 3.0
+    _, strict_f = oracle_mod.nondegenerate_masks(c_star, flipped, F, lo=lo, hi=hi)
+    assert not strict_f[1]
+
+
+def test_nondegenerate_masks_on_tiny_meshes(oracle_mod):
+    """On the brute-force meshes every node is decided (no degeneracy), the
+    masks partition the nodes, and the active ones are exactly the nodes the
+    unique surviving assignment puts at the bound."""
+    for p in (W.tiny2d(), W.tiny3d()):
+        S = oracle_mod.assemble(p)
+        Kd = S.to_scipy().toarray()
+        c_bf, survivors = brute.brute_force(Kd, S.F)
+        assert len(survivors) == 1
+        g = Kd @ c_bf - S.F
+        free, strict = oracle_mod.nondegenerate_masks(c_bf, g, S.F)
+        assert free.any() and strict.any()
+        assert not (free & strict).any() and (free | strict).all()
+        assert np.array_equal(strict, c_bf == 0.0)

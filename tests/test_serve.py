@@ -195,3 +195,130 @@ def test_failed_request_stops_every_lane():
         srv.run(reqs)
     assert err.value.status == nnqp.NN_ENONFINITE
     assert time.perf_counter() - t0 < 60
+
+
+@pytest.mark.gpu
+def test_served_mixed_solo_lane_equals_alone_and_oracle():
+    """Mixed precision with the upper lanes stepped by the single-problem
+    solver: each served result is bitwise the request run alone the same way
+    (batched or single-problem), and within 1e-6 of the oracle's float64
+    backward-Euler steps; the error of every request is printed."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import Server, solve_alone
+    reqs = _requests(8, steps=3, gap=0.0005, seed=9)
+    srv = Server(precision=nnqp.NN_MIXED, tol=1e-10, inner_rtol=0.1, keep_states=True,
+                 lane_bounds=(400, 1200))
+    solo = [srv.is_solo(r) for r in reqs]
+    assert any(solo) and not all(solo)
+    rep = srv.run(reqs)
+    assert all(r.status == 0 for r in rep.results)
+    ctx = nnqp.Context(0)
+    for req, res, single in zip(reqs, rep.results, solo):
+        c_alone, _ = solve_alone(req, precision=nnqp.NN_MIXED, tol=1e-10, inner_rtol=0.1,
+                                 ctx=ctx, single=single)
+        assert torch.equal(res.c, c_alone), req.rid
+        S = oracle.assemble(req.problem, with_mass=True)
+        c_ref = np.zeros(S.n)
+        for _ in range(req.steps):
+            r = oracle.transient_step(S, 1e-3, c_ref, tol=1e-13)
+            assert r.certified
+            c_ref = r.c
+        c = res.c.cpu().numpy()
+        assert c.min() >= 0.0
+        err = np.abs(c - c_ref).max() / np.abs(c_ref).max()
+        print(f"request {req.rid} n={S.n} {'single' if single else 'batched'} "
+              f"mixed rel err {err:.2e}")
+        assert err <= 1e-6, (req.rid, err)
+
+
+def _tracking_allocator(refuse=None):
+    """(alloc, free, state) over torch's caching allocator that counts live
+    and peak bytes; refuse(nbytes) -> True makes an allocation fail."""
+    import torch
+    state = {"live": {}, "bytes": 0, "peak": 0, "refused": 0}
+
+    def alloc(nbytes):
+        if refuse is not None and refuse(nbytes):
+            state["refused"] += 1
+            return None
+        p = torch.cuda.caching_allocator_alloc(nbytes, 0, torch.cuda.current_stream(0))
+        state["live"][p] = nbytes
+        state["bytes"] += nbytes
+        state["peak"] = max(state["peak"], state["bytes"])
+        return p
+
+    def free(p):
+        nb = state["live"].pop(p, None)
+        if nb is not None:
+            state["bytes"] -= nb
+            torch.cuda.caching_allocator_delete(p)
+
+    return alloc, free, state
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("solo", [False, True])
+def test_failed_step_call_stops_the_server(solo):
+    """A step whose call fails for want of memory (the caller's allocator
+    refuses every request from the lane threads after their first few, forced
+    from the host) raises NN_EOOM from Server.run, for a batched lane and for
+    a single-problem lane: no request is reported as stepped or finished."""
+    import threading
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import Server
+    main = threading.main_thread()
+    lane_allocs = [0]
+
+    def refuse(nbytes):
+        t = threading.current_thread()
+        if t is main or t.name.startswith("ThreadPoolExecutor"):
+            return False              # contexts and assembly get their memory
+        lane_allocs[0] += 1
+        return lane_allocs[0] > 3     # the first step's call is refused part-way
+    alloc, free, _ = _tracking_allocator(refuse)
+    reqs = _requests(4, steps=3, gap=0.0, seed=9)
+    bounds = (10, 20) if solo else (10 ** 7, 10 ** 8)
+    srv = Server(tol=1e-8, lane_bounds=bounds, allocator=(alloc, free))
+    assert all(srv.is_solo(r) == solo for r in reqs)
+    with pytest.raises(nnqp.NnError) as err:
+        srv.run(reqs)
+    assert err.value.status == nnqp.NN_EOOM
+    assert lane_allocs[0] > 3
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_admission_estimate_bounds_measured_step_memory(prec):
+    """The admission estimate of a request covers the device memory its steps
+    actually take, measured through the allocator hooks at the peak of one
+    step (matrix, the copies a step adds, and the batched call's workspace or
+    the single-problem solver's work vectors), plus f, c and the active set."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import estimate_bytes
+    precision = nnqp.NN_MIXED if prec == "mixed" else nnqp.NN_FP64
+    for k in range(6):
+        p = W.serve_problem(k, seed=21, dof_range=(500, 60000))
+        for solo in (False, True):
+            alloc, free, state = _tracking_allocator()
+            ctx = nnqp.Context(0, allocator=(alloc, free))
+            torch.cuda.synchronize()
+            base = state["bytes"]
+            state["peak"] = base
+            K, F, _ = ctx.assemble(p, with_mass=True)
+            c = torch.zeros(max(K.n, 1), dtype=torch.float64, device=ctx.device)
+            torch.cuda.synchronize()
+            state["peak"] = state["bytes"]   # the resident matrix, from here on
+            opts = nnqp.default_opts(tol=1e-8, precision=precision)
+            if solo:
+                ctx.step_transient(K, 1e-3, F, c, opts=opts)
+            else:
+                ctx.step_transient_batch([K], 1e-3, [F], [c], opts=opts)
+            torch.cuda.synchronize()
+            used = state["peak"] - base + 17 * K.n
+            est = estimate_bytes(p, precision, solo=solo)
+            print(f"problem {k} dim {p.dim} n={K.n} solo={solo} measured {used} estimate {est}")
+            assert est >= used, (k, solo, used, est)
+            K.free()
+            ctx.close()
