@@ -269,6 +269,33 @@ static nn_status create_impl(nn_ctx **out, int device, void *hip_stream, const D
     return NN_OK;
 }
 
+nn_status nnqp::check_opts(nn_ctx *ctx, const nn_opts *o)
+{
+    if (!o) return fail(ctx, NN_EINVAL, "null options");
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(ctx, NN_EINVAL, "tol must be > 0");
+    if (!(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
+        return fail(ctx, NN_EINVAL, "inner_rtol must be in (0, 1)");
+    if (o->max_outer < 0 || o->max_cg < 1) return fail(ctx, NN_EINVAL, "bad iteration caps");
+    if (o->precision != NN_FP64 && o->precision != NN_MIXED)
+        return fail(ctx, NN_EINVAL, "unknown precision");
+    if (o->c0_mode != 0 && o->c0_mode != 1) return fail(ctx, NN_EINVAL, "unknown c0_mode");
+    if (o->c0_mode == 0 && !std::isfinite(o->c0_value))
+        return fail(ctx, NN_EINVAL, "c0_value must be finite");
+    if (!std::isfinite(o->lower) || std::isnan(o->upper) || !(o->upper > o->lower))
+        return fail(ctx, NN_EINVAL, "bounds must satisfy lower finite, upper > lower");
+    if (o->method != NN_TRON && o->method != NN_BLMVM) return fail(ctx, NN_EINVAL, "unknown method");
+    if (o->precond_degree < 0 || o->precond_degree > 8)
+        return fail(ctx, NN_EINVAL, "precond_degree must be in 0..8");
+    if (o->subspace != 0 && o->subspace != 1) return fail(ctx, NN_EINVAL, "subspace must be 0 or 1");
+    if (o->method == NN_BLMVM) {
+        if (o->lmm_vectors < 1 || o->lmm_vectors > 8)
+            return fail(ctx, NN_EINVAL, "lmm_vectors must be in 1..8");
+        if (o->max_lm_its < 0) return fail(ctx, NN_EINVAL, "bad iteration cap");
+        if (o->precision != NN_FP64) return fail(ctx, NN_EINVAL, "BLMVM runs in float64 only");
+    }
+    return NN_OK;
+}
+
 extern "C" {
 
 nn_status nn_create(nn_ctx **out, int device, void *hip_stream)
@@ -536,32 +563,6 @@ nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_
     return NN_OK;
 }
 
-nn_status nnqp::check_opts(nn_ctx *ctx, const nn_opts *o)
-{
-    if (!o) return fail(ctx, NN_EINVAL, "null options");
-    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(ctx, NN_EINVAL, "tol must be > 0");
-    if (!(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
-        return fail(ctx, NN_EINVAL, "inner_rtol must be in (0, 1)");
-    if (o->max_outer < 0 || o->max_cg < 1) return fail(ctx, NN_EINVAL, "bad iteration caps");
-    if (o->precision != NN_FP64 && o->precision != NN_MIXED)
-        return fail(ctx, NN_EINVAL, "unknown precision");
-    if (o->c0_mode != 0 && o->c0_mode != 1) return fail(ctx, NN_EINVAL, "unknown c0_mode");
-    if (o->c0_mode == 0 && !std::isfinite(o->c0_value))
-        return fail(ctx, NN_EINVAL, "c0_value must be finite");
-    if (!std::isfinite(o->lower) || std::isnan(o->upper) || !(o->upper > o->lower))
-        return fail(ctx, NN_EINVAL, "bounds must satisfy lower finite, upper > lower");
-    if (o->method != NN_TRON && o->method != NN_BLMVM) return fail(ctx, NN_EINVAL, "unknown method");
-    if (o->precond_degree < 0 || o->precond_degree > 8)
-        return fail(ctx, NN_EINVAL, "precond_degree must be in 0..8");
-    if (o->subspace != 0 && o->subspace != 1) return fail(ctx, NN_EINVAL, "subspace must be 0 or 1");
-    if (o->method == NN_BLMVM) {
-        if (o->lmm_vectors < 1 || o->lmm_vectors > 8)
-            return fail(ctx, NN_EINVAL, "lmm_vectors must be in 1..8");
-        if (o->max_lm_its < 0) return fail(ctx, NN_EINVAL, "bad iteration cap");
-        if (o->precision != NN_FP64) return fail(ctx, NN_EINVAL, "BLMVM runs in float64 only");
-    }
-    return NN_OK;
-}
 
 nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
                           const nn_opts *opts, double *c_dev, uint8_t *active_dev, nn_stats *stats)
