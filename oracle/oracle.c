@@ -612,11 +612,23 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, c
     for (int64_t i = 0; i < n; i++) c[i] = proj(&Q, c[i]);
     gradient(&Q, c, g);
     double inner_tol = tol;
+    double best_rel = INFINITY;
+    int64_t since_best = 0;
     for (int64_t outer = 0; outer < max_outer; outer++) {
         st->outer = outer + 1;
         double rel = pg_norm(&Q, c, g) / nf;
         st->r = rel;
-        if (rel <= inner_tol) {
+        /* Near the rounding floor of the residual the iteration stops
+         * gaining: once r is below that floor and has not halved for thirty
+         * iterations, the face solve and certificate take over (they accept
+         * r at max(tol, floor)). */
+        if (rel < 0.5 * best_rel) {
+            best_rel = rel;
+            since_best = 0;
+        } else {
+            since_best++;
+        }
+        if (rel <= inner_tol || (since_best >= 30 && rel <= residual_floor(&Q, c, nf))) {
             /* Face solve on the binding set of c, then check the KKT conditions. */
             st->polishes++;
             /* binding variables stay at their bound value */

@@ -399,6 +399,7 @@ def test_full_size_batch_512_elementwise(ctx):
                     {int(np.argmax([K.n for K in Ks]))} | set(floor[:1]))
     any_strict = False
     for k in sample:
+        print(f"oracle on batch member {k} (n={Ks[k].n})", flush=True)
         S = oracle.assemble(probs[k])
         ref = oracle.solve(S, tol=1e-13)
         assert ref.certified
@@ -407,7 +408,7 @@ def test_full_size_batch_512_elementwise(ctx):
         g_ref = oracle.spmv(S, ref.c) - S.F
         any_strict |= bool(oracle.nondegenerate_masks(ref.c, g_ref, S.F)[1].any())
         print(f"batch member {k} (n={S.n}): err {err:.2e} outer {stats[k]['outer_its']} "
-              f"cg {stats[k]['cg_its']}")
+              f"cg {stats[k]['cg_its']}, oracle {ref.seconds:.1f} s r {ref.r:.2e}", flush=True)
     assert any_strict
 
 
