@@ -122,7 +122,8 @@ def run_small(args):
     out = {}
     for prec_name in ("fp64", "mixed"):
         prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
-        opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec)
+        opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
+                                 subspace=args.subspace)
         c = torch.empty(K.n, dtype=torch.float64, device=ctx.device)
         for _ in range(3):
             ctx.solve_nonneg(K, F, opts=opts, c=c)
@@ -160,7 +161,8 @@ def run_hole(args):
     n = K.n
     prec = nnqp.NN_MIXED if args.precision == "mixed" else nnqp.NN_FP64
     opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
-                             lower=0.0, upper=1.0, precond_degree=args.precond_degree)
+                             lower=0.0, upper=1.0, precond_degree=args.precond_degree,
+                             subspace=args.subspace)
     c = torch.empty(n, dtype=torch.float64, device=ctx.device)
     act = torch.empty(n, dtype=torch.uint8, device=ctx.device)
     for _ in range(args.warmup):
@@ -238,7 +240,7 @@ def run_transient(args):
     for prec_name in ("fp64", "mixed"):
         prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
         opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
-                                 precond_degree=args.precond_degree)
+                                 precond_degree=args.precond_degree, subspace=args.subspace)
         c = torch.zeros(n, dtype=torch.float64, device=ctx.device)
         ctx.step_transient(K, args.dt, F, c, opts=opts)          # warm-up (forms K~)
         c.zero_()
@@ -413,6 +415,9 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=0.5,
                     help="relative tolerance of each inner CG solve (does not change the minimiser)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--subspace", type=int, choices=[0, 1], default=1,
+                    help="TRON's subspace loop (1, the library default) or a Cauchy step every "
+                         "iteration (0); the minimiser is the same")
     ap.add_argument("--precond-degree", type=int, default=1,
                     help="inner CG preconditioner: 1 = Jacobi, k > 1 = Chebyshev of degree k")
     ap.add_argument("--cpu-n", type=int, default=64, help="cube side of the CPU-baseline sample")
@@ -494,7 +499,8 @@ def main():
     n = K.n
     prec = nnqp.NN_MIXED if args.precision == "mixed" else nnqp.NN_FP64
     opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, verbose=int(args.verbose),
-                             precision=prec, precond_degree=args.precond_degree)
+                             precision=prec, precond_degree=args.precond_degree,
+                             subspace=args.subspace)
     c = torch.empty(n, dtype=torch.float64, device=ctx.device)
     for _ in range(args.warmup):
         ctx.solve_nonneg(K, F, opts=opts, c=c)
