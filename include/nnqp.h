@@ -294,6 +294,32 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
                           nn_stats *stats);
 
 /*
+ * nn_solve_nonneg for callers that cannot allocate device memory during a
+ * call (code in tight serving loops, harnesses that forbid allocation): the
+ * same TRON solve, with every work buffer (reduction partials, CG scalars,
+ * work vectors, face mask) in one fixed device array of the library instead
+ * of memory taken through hipMalloc or the context's allocator hooks.  It
+ * calls no device allocator and forms no copy of K: the paired and float32
+ * copies are used if an earlier nn_solve_nonneg made them (results are then
+ * bitwise those of nn_solve_nonneg), else the column-major values.
+ *   Limit: n <= 262,144 rows (the array: about 26 MiB of device memory per
+ *          GPU, taken when the library is loaded and held until the process
+ *          ends); larger n -> NN_EINVAL.
+ *   Options: TRON (method NN_TRON) with the Jacobi preconditioner
+ *          (precond_degree <= 1), FP64 or NN_MIXED; NN_MIXED needs the
+ *          matrix's float32 copy to exist already (NN_EINVAL otherwise).
+ *          Launch timing (nn_set_profiling) is not recorded.
+ *   Concurrency: every call on one GPU uses that GPU's single array, so calls
+ *          that overlap on one GPU (from any context or thread) race and give
+ *          wrong results; serialise them.  Each call clears the state it
+ *          reads before use; the array keeps the last call's contents.
+ * Arguments, results and statuses as nn_solve_nonneg.
+ */
+nn_status nn_solve_nonneg_noalloc(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
+                                  const nn_opts *opts, double *c_dev, uint8_t *active_dev,
+                                  nn_stats *stats);
+
+/*
  * Unconstrained single-field Galerkin solution (Sec. 2.1.2,
  * eq. Single_field_formulation): K c = f, the baseline that violates the
  * discrete maximum principle (Sec. 5.1, Table Tab:S5_cube_dmp).  Jacobi-

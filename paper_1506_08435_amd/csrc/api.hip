@@ -242,6 +242,7 @@ static nn_status create_impl(nn_ctx **out, int device, void *hip_stream, const D
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NN_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return NN_EHIP;
+    noalloc_attach(device);
     nn_ctx *ctx = new (std::nothrow) nn_ctx();
     if (!ctx) return NN_EOOM;
     ctx->al = al;

@@ -219,6 +219,12 @@ nn_status ensure_workspace(nn_ctx *ctx, int64_t n);
 // Option checks shared by the solve entry points (api.hip).
 nn_status check_opts(nn_ctx *ctx, const nn_opts *o);
 
+// Rows the fixed work array of nn_solve_nonneg_noalloc holds (noalloc.hip).
+constexpr int64_t kNoAllocMaxRows = 262144;
+// Take the current device's address of that array (once per device; called
+// by nn_create with the device current).
+void noalloc_attach(int device);
+
 // Sliced-ELL offsets of a CSR pattern: off[s] for s = 0..nslices, widest slice.
 void sell_offsets(const int64_t *rowptr, int64_t n, std::vector<int64_t> &off, int &wmax);
 // Device CSR values (ordered by rowptr) -> sliced-ELL arrays of A (col, vals, diag).

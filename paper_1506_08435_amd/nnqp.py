@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "NN_OK", 1: "NN_EINVAL", 2: "NN_ENONFINITE", 3: "NN_ENOTSPD",
 # exported symbols declared in include/nnqp.h (checked by the ABI test)
 SYMBOLS = ("nn_create", "nn_create_ex", "nn_destroy", "nn_last_error", "nn_default_opts", "nn_assemble",
            "nn_matrix_from_csr", "nn_matrix_info", "nn_matrix_export", "nn_matrix_bytes",
-           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_solve_galerkin", "nn_step_transient",
+           "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_solve_nonneg_noalloc",
+           "nn_solve_galerkin", "nn_step_transient",
            "nn_solve_batch", "nn_step_transient_batch", "nn_set_profiling", "nn_kernel_times")
 
 
@@ -111,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "nn_matrix_free": (None, [vp, vp]),
         "nn_matvec": (i32, [vp, vp, ctypes.c_int, vp, vp]),
         "nn_solve_nonneg": (i32, [vp, vp, vp, P(Opts), vp, vp, P(Stats)]),
+        "nn_solve_nonneg_noalloc": (i32, [vp, vp, vp, P(Opts), vp, vp, P(Stats)]),
         "nn_solve_galerkin": (i32, [vp, vp, vp, P(Opts), vp, P(Stats)]),
         "nn_step_transient": (i32, [vp, vp, dbl, vp, P(Opts), vp, vp, P(Stats)]),
         "nn_solve_batch": (i32, [vp, i32, P(vp), P(vp), P(Opts), P(vp), P(vp), P(Stats)]),
@@ -317,6 +319,22 @@ class Context:
         st = self.lib.nn_solve_nonneg(self.handle, A.handle, _ptr(f), ctypes.byref(o), _ptr(c),
                                       _ptr(active), ctypes.byref(st_out))
         self._check(st, "nn_solve_nonneg", allow=(NN_OK, NN_EMAXIT) if allow_maxit else (NN_OK,))
+        d = st_out.as_dict()
+        d["status"] = st
+        return c[:A.n], active[:A.n], d
+
+    def solve_nonneg_noalloc(self, A: Matrix, f, c, active, opts: Optional[Opts] = None,
+                             allow_maxit: bool = False, **kw):
+        """nn_solve_nonneg_noalloc: the same solve with the library's fixed
+        work array (no device allocation inside the call; n <= 262,144).
+        The caller passes c (warm start when opts.c0_mode == 1, overwritten
+        with the solution) and active.  Returns (c, active, stats dict)."""
+        o = opts if opts is not None else default_opts(**kw)
+        st_out = Stats()
+        st = self.lib.nn_solve_nonneg_noalloc(self.handle, A.handle, _ptr(f), ctypes.byref(o),
+                                              _ptr(c), _ptr(active), ctypes.byref(st_out))
+        self._check(st, "nn_solve_nonneg_noalloc",
+                    allow=(NN_OK, NN_EMAXIT) if allow_maxit else (NN_OK,))
         d = st_out.as_dict()
         d["status"] = st
         return c[:A.n], active[:A.n], d
