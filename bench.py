@@ -22,36 +22,75 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_spmv_cube128_traffic.txt")
-# sources of the CG matrix pass (its code, its slice walker, its constants)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1506_08435_amd", "csrc", f)
-                  for f in ("kernels.hip", "rows.hpp", "nnqp_internal.hpp")]
+EXTRAS = ("mixed", "small", "transient", "batch", "serve")
+CSRC = os.path.join(ROOT, "paper_1506_08435_amd", "csrc")
+# sources that decide what a kernel reads and writes: its code, the slice
+# walkers, the constants and the host code that chooses layouts and launches
+KERNEL_SOURCES = {
+    "single": ("kernels.hip", "rows.hpp", "nnqp_internal.hpp", "solver.hip", "api.hip"),
+    "batch": ("batch.hip", "rows.hpp", "nnqp_internal.hpp", "api.hip"),
+}
 
 
-def kernel_hash() -> str:
+def kernel_hash(group: str = "single") -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for f in KERNEL_SOURCES[group]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per launch of the CG matrix pass from the committed rocprofv3
-    counter summary, or None if absent or taken on different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_file(kernel: str, workload: str, precision: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
+
+
+def read_traffic(kernel: str, workload: str, precision: str, group: str = "single"):
+    """HBM bytes per working launch of `kernel` on `workload` in `precision`
+    (fp64 / mixed) from the committed rocprofv3 counter summary
+    profiles/traffic_<kernel>_<workload>_<precision>.txt, or None when no such
+    summary exists or it was taken on other kernel sources."""
+    path = traffic_file(kernel, workload, precision)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_hash(group):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def roofline_of(dom: dict, kernel: str, traffic_bytes, extra=None) -> dict:
+    """Roofline object of the dominant kernel from its HIP-event timing:
+    achieved = algorithmic bytes per launch (the layout the kernel reads) /
+    average launch time; csr_model = the same launches under the paper's CSR
+    byte model (4-byte column indices, unfused vector operands); traffic =
+    counter-measured HBM bytes per launch (null if not measured for this
+    kernel, workload, precision and source)."""
+    cnt = max(dom["count"], 1)
+    avg_s = dom["ms"] / cnt * 1e-3
+    bpl = dom["bytes"] / cnt
+    bcsr = dom.get("bytes_csr", dom["bytes"]) / cnt
+    ach = bpl / avg_s / 1e9 if dom["count"] else 0.0
+    ach_csr = bcsr / avg_s / 1e9 if dom["count"] else 0.0
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic_bytes,
+           "kernel": kernel, "launches": dom["count"], "avg_us": round(avg_s * 1e6, 2),
+           "algorithmic_bytes_per_launch": round(bpl),
+           "csr_model": {"bytes_per_launch": round(bcsr), "achieved": round(ach_csr, 1),
+                         "frac": round(ach_csr / PEAK_HBM_GBS, 4)}}
+    if traffic_bytes and dom["count"]:
+        out["traffic_GBps"] = round(traffic_bytes / avg_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic_bytes / avg_s / 1e9 / PEAK_HBM_GBS, 4)
+        out["traffic_over_algorithmic"] = round(traffic_bytes / bpl, 3)
+    if extra:
+        out.update(extra)
+    return out
 
 
 def cpu_model() -> str:
@@ -144,7 +183,7 @@ def run_small(args):
                         f"D = R(pi/6) diag(1, 1e-3) R^T, f = 1 on [3/8,5/8]^2, KKT tol 1e-8, "
                         f"{args.small_reps} solves",
             "n_gpus": 1, **out}
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def run_hole(args):
@@ -236,7 +275,7 @@ def run_transient(args):
     ctx = nnqp.Context(0)
     K, F, _ = ctx.assemble(p, with_mass=True)
     n = K.n
-    out = {}
+    out, finals = {}, {}
     for prec_name in ("fp64", "mixed"):
         prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
         opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
@@ -244,7 +283,7 @@ def run_transient(args):
         c = torch.zeros(n, dtype=torch.float64, device=ctx.device)
         ctx.step_transient(K, args.dt, F, c, opts=opts)          # warm-up (forms K~)
         c.zero_()
-        ctx.set_profiling(True, None if args.profile_all else ("cg_spmv",))
+        ctx.set_profiling(not args.no_kernel_timing, None if args.profile_all else ("cg_spmv",))
         ctx.kernel_times(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -257,17 +296,16 @@ def run_transient(args):
         kt = ctx.kernel_times(reset=True)
         ctx.set_profiling(False)
         dom = kt["cg_spmv"]
-        avg_ms = dom["ms"] / max(dom["count"], 1)
-        bpl = dom["bytes"] / max(dom["count"], 1)
+        wl = "transient3d_" + "x".join(map(str, args.tdims))
         out[prec_name] = {
             "value": round(n * args.tsteps / wall, 1), "unit": "DOF*steps/s",
             "ms_per_step": round(wall / args.tsteps * 1e3, 3),
             "max_kkt_rel": max(s["kkt_rel"] for s in per_step),
             "outer_its_total": sum(s["outer_its"] for s in per_step),
             "cg_its_total": sum(s["cg_its"] for s in per_step),
-            "cg_spmv_avg_us": round(avg_ms * 1e3, 2),
-            "cg_spmv_frac_of_8TBs": round(bpl / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-            "final_max_c": float(c.max()), "final_active": int(per_step[-1]["n_active"])}
+            "final_max_c": float(c.max()), "final_active": int(per_step[-1]["n_active"]),
+            "roofline": roofline_of(dom, "k_cg_spmv", read_traffic("k_cg_spmv", wl, prec_name))}
+        finals[prec_name] = c.clone()
     line = {"metric": "solved DOF*steps/s, backward Euler, KKT tol 1e-8 per step",
             "workload": f"transient3d_{'x'.join(map(str, args.tdims))}: {n} free DOF, {K.nnz} nnz, "
                         f"D = exp(G) R diag(1,.1,1e-3) R^T (Gaussian random field, seed 1506), "
@@ -275,7 +313,13 @@ def run_transient(args):
             "precond": "Jacobi" if args.precond_degree <= 1 else
                        f"Chebyshev-Jacobi degree {args.precond_degree}",
             "n_gpus": 1, **out}
-    print(json.dumps(line), flush=True)
+    # the mixed-precision end state against the float64 one (both at KKT 1e-8)
+    a, b = finals["mixed"], finals["fp64"]
+    line["mixed_vs_fp64_rel_diff"] = float((a - b).abs().max() / b.abs().max())
+    line["active_nodes_fp64_mixed"] = [out["fp64"]["final_active"], out["mixed"]["final_active"]]
+    line["active_note"] = ("the two end states differ in which degenerate nodes (c = 0 with "
+                           "g = 0 up to the 1e-8 tolerance) sit exactly at zero")
+    return line
 
 
 def run_batch(args):
@@ -299,11 +343,12 @@ def run_batch(args):
         opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
                                  verbose=int(args.verbose))
         cs = [torch.empty(max(K.n, 1), dtype=torch.float64, device=ctx.device) for K in Ks]
-        for _ in range(args.warmup):
+        bsteps = args.batch_steps
+        for _ in range(max(args.warmup, 1)):
             ctx.solve_batch(Ks, Fs, opts=opts, cs=cs)      # also tunes the launch shape
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(bsteps):
             _, _, stats, _ = ctx.solve_batch(Ks, Fs, opts=opts, cs=cs)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -318,21 +363,17 @@ def run_batch(args):
             kt = ctx.kernel_times(reset=True)
             ctx.set_profiling(False)
         dom = kt["cg_spmv"]
-        avg_ms = dom["ms"] / max(dom["count"], 1)
-        bpl = dom["bytes"] / max(dom["count"], 1)
-        achieved = bpl / (avg_ms * 1e-3) / 1e9 if dom["count"] else 0.0
         out[prec_name] = {
-            "value": round(ndof * args.steps / wall, 1), "unit": "DOF/s",
-            "ms_per_step": round(wall / args.steps * 1e3, 3),
+            "value": round(ndof * bsteps / wall, 1), "unit": "DOF/s",
+            "ms_per_step": round(wall / bsteps * 1e3, 3),
             "max_kkt_rel": max(s["kkt_rel"] for s in stats),
             "max_outer_its": max(s["outer_its"] for s in stats),
             "sum_cg_its": sum(s["cg_its"] for s in stats),
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                         "traffic": None, "kernel": "kb_cg_spmv (batched CG matrix pass)",
-                         "launches": dom["count"], "avg_us": round(avg_ms * 1e3, 2),
-                         "algorithmic_bytes_per_launch": round(bpl),
-                         "measured_in": "one extra profiled solve, CG launches one by one"},
+            "roofline": roofline_of(
+                dom, "kb_rows (batched row pass: gradient, Cauchy trial, CG matrix pass or search "
+                     "trial of each member)",
+                read_traffic("kb_rows", f"batch2d_{args.nbatch}", prec_name, group="batch"),
+                {"measured_in": "one extra profiled solve, steps launched one by one"}),
             "kernel_classes": {k: {"count": v["count"],
                                    "avg_us": round(v["ms"] / max(v["count"], 1) * 1e3, 2)}
                                for k, v in kt.items()}}
@@ -340,7 +381,7 @@ def run_batch(args):
             "workload": f"batch2d_{args.nbatch}: {args.nbatch} 2D problems, grid side U{{32..256}}, "
                         f"theta U[0,pi), ratio 10^-U(1,4), f = 1 on a random square; {ndof} free DOF, "
                         f"{nnz} nnz in total; one nn_solve_batch call per step",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, **out}
+            "n_gpus": 1, "steps": args.batch_steps, "warmup": max(args.warmup, 1), **out}
     if not args.no_cpu_baseline:
         import oracle
         S_list = [oracle.assemble(probs[k]) for k in range(args.cpu_members)]
@@ -353,40 +394,56 @@ def run_batch(args):
                                 "cores": oracle.num_threads(), "kind": "oracle",
                                 "sample": f"oracle GPCG, tol 1e-8, on members 0..{args.cpu_members - 1} "
                                           f"of the batch ({nd} DOF): {sec:.2f} s"}
-    print(json.dumps(line), flush=True)
+    return line
 
 
-def run_serve(args):
+def run_serve(args, rates=None):
     """Continuous-batching server on a Poisson stream of transient requests
     (2D/3D 50/50, free DOF log-uniform in [1e3, 1e6], 10 backward-Euler steps
     each, dt = 1e-3, KKT tol 1e-8 per step), FP64 and mixed precision on the
-    same stream; p50/p99 latency (arrival to last step) and DOF*steps/s."""
+    same stream; p50/p99 latency (arrival to last step) and DOF*steps/s, and
+    the mixed end state of every request against its FP64 end state."""
+    import numpy as np
     from paper_1506_08435_amd import nnqp, workloads as W
     from paper_1506_08435_amd.serve import Request, Server
+    rates = args.rates if rates is None else rates
     problems = [W.serve_problem(k, seed=args.serve_seed) for k in range(args.nreq)]
     dofs = [p.n_free for p in problems]
     out = {}
     budget = int(args.hbm_budget_gib * (1 << 30)) if args.hbm_budget_gib > 0 else None
-    for rate in args.rates:
+    for rate in rates:
         arrivals = W.serve_arrivals(args.nreq, rate, seed=args.serve_seed)
         reqs = [Request(k, problems[k], args.serve_steps, float(arrivals[k])) for k in range(args.nreq)]
+        finals = {}
         for prec_name in ("fp64", "mixed"):
             prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
             srv = Server(precision=prec, hbm_budget=budget, tol=1e-8, inner_rtol=args.serve_inner_rtol,
-                         lane_bounds=tuple(args.serve_lanes), solo_lanes=args.serve_solo_lanes)
+                         lane_bounds=tuple(args.serve_lanes), solo_lanes=args.serve_solo_lanes,
+                         keep_states=True, subspace=args.subspace)
             rep = srv.run(reqs)
             sm = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.summary().items()}
             sm["max_kkt_rel"] = max(s["kkt_rel"] for r in rep.results for s in r.step_stats)
             out[f"rate{rate:g}_{prec_name}"] = sm
+            finals[prec_name] = {r.rid: r.c for r in rep.results if r.status == 0}
+        diffs = []
+        for rid, c64 in finals["fp64"].items():
+            cm = finals["mixed"].get(rid)
+            if cm is not None and c64 is not None:
+                diffs.append(float((cm - c64).abs().max() / max(float(c64.abs().max()), 1e-300)))
+        if diffs:
+            out[f"rate{rate:g}_mixed_vs_fp64"] = {
+                "requests": len(diffs), "max_rel_diff": max(diffs),
+                "p99_rel_diff": float(np.percentile(diffs, 99)),
+                "note": "per request: ||c_mixed - c_fp64||_inf / ||c_fp64||_inf of the end "
+                        "states, both at KKT tol 1e-8 per step"}
     line = {"metric": "served transient requests: p50/p99 latency and solved DOF*steps/s",
-            "workload": f"serve: {args.nreq} requests per rate, Poisson arrivals at {args.rates} per s, "
+            "workload": f"serve: {args.nreq} requests per rate, Poisson arrivals at {list(rates)} per s, "
                         f"2D/3D 50/50, free DOF log-uniform in [1e3, 1e6] (here {min(dofs)}..{max(dofs)}, "
                         f"total {sum(dofs)}), {args.serve_steps} backward-Euler steps each, dt = 1e-3, "
                         f"seed {args.serve_seed}; size lanes split at {list(args.serve_lanes)} free DOF, "
                         f"the top {args.serve_solo_lanes} stepped by the single-problem solver",
             "n_gpus": 1, **out}
     if not args.no_cpu_baseline:
-        import numpy as np
         import oracle
         sample = [p for p in problems if p.n_free <= 60000][:args.cpu_members]
         t0 = time.perf_counter()
@@ -403,7 +460,7 @@ def run_serve(args):
                                 "sample": f"oracle assembly + {args.serve_steps} steps of the first "
                                           f"{len(sample)} requests with at most 60000 DOF, one after "
                                           f"another: {sec:.2f} s"}
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def main():
@@ -415,9 +472,9 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=0.5,
                     help="relative tolerance of each inner CG solve (does not change the minimiser)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--subspace", type=int, choices=[0, 1], default=1,
-                    help="TRON's subspace loop (1, the library default) or a Cauchy step every "
-                         "iteration (0); the minimiser is the same")
+    ap.add_argument("--subspace", type=int, choices=[0, 1], default=0,
+                    help="TRON's subspace loop (1) or a Cauchy step every iteration (0, the "
+                         "library default); the minimiser is the same")
     ap.add_argument("--precond-degree", type=int, default=1,
                     help="inner CG preconditioner: 1 = Jacobi, k > 1 = Chebyshev of degree k")
     ap.add_argument("--cpu-n", type=int, default=64, help="cube side of the CPU-baseline sample")
@@ -457,6 +514,14 @@ def main():
     ap.add_argument("--nbatch", type=int, default=512, help="members of the batch workload")
     ap.add_argument("--cpu-members", type=int, default=16,
                     help="batch members the CPU-baseline sample solves")
+    ap.add_argument("--extras", nargs="*", default=list(EXTRAS),
+                    choices=list(EXTRAS),
+                    help="sections the cube workload's line carries besides the FP64 cube "
+                         "(default: all)")
+    ap.add_argument("--no-extras", action="store_true", help="the same as --extras with no name")
+    ap.add_argument("--extra-rates", type=float, nargs="+", default=[500.0],
+                    help="arrival rates of the serve section of the default line")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed calls of the batch workload")
     ap.add_argument("--tdims", type=int, nargs=3, default=[256, 256, 64])
     ap.add_argument("--tsteps", type=int, default=50)
     ap.add_argument("--dt", type=float, default=1e-3)
@@ -466,32 +531,27 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "transient":
-        run_transient(args)
-        return
-    if args.workload == "batch":
-        run_batch(args)
-        return
-    if args.workload == "serve":
-        run_serve(args)
-        return
-    if args.workload == "small":
-        run_small(args)
-        return
-    if args.workload == "hole":
-        run_hole(args)
-        return
-
-    import torch
-    from paper_1506_08435_amd import nnqp, workloads as W
-
     if args.calibrate_copy:
+        # three 512 MiB device-to-device copies: the reference that scales the
+        # HBM counters (FETCH_SIZE, WRITE_SIZE) of a profiled run to bytes
+        import torch
         a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    single = {"transient": run_transient, "batch": run_batch, "serve": run_serve,
+              "small": run_small, "hole": run_hole}
+    if args.workload in single:
+        line = single[args.workload](args)
+        if line is not None:
+            print(json.dumps(line), flush=True)
+        return
+
+    import torch
+    from paper_1506_08435_amd import nnqp, workloads as W
 
     p = W.cube3d(args.n)
     ctx = nnqp.Context(0)
@@ -523,19 +583,13 @@ def main():
     value = n * args.steps / wall
 
     dom = kt["cg_spmv"]
-    avg_ms = dom["ms"] / max(dom["count"], 1)
-    bytes_per_launch = dom["bytes"] / max(dom["count"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if dom["count"] else 0.0
-    traffic = read_traffic()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": "k_cg_spmv (CG matrix pass with fused direction update)",
-                "launches": dom["count"], "avg_us": round(avg_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+    wl = f"cube3d_{args.n}"
+    roofline = roofline_of(dom, "k_cg_spmv (CG matrix pass with fused direction update)",
+                           read_traffic("k_cg_spmv", wl, args.precision))
     if not args.no_triad:
         tri = triad_gbs(torch)
         roofline["achievable_triad_GBps"] = round(tri, 1)
-        roofline["frac_of_achievable"] = round(achieved / tri, 4)
+        roofline["frac_of_achievable"] = round(roofline["achieved"] / tri, 4)
     galerkin = None
     if not args.no_galerkin and prec == nnqp.NN_FP64:
         galerkin = run_galerkin(ctx, K, F, n, stats, args)
@@ -579,9 +633,62 @@ def main():
         out["blmvm"] = blmvm
     if not args.no_blmvm and prec == nnqp.NN_FP64:
         out["tron_levels"] = run_tron_levels(ctx, K, F, args)
+    extras = [] if args.no_extras else args.extras
+    if "mixed" in extras and prec == nnqp.NN_FP64:
+        out["mixed"] = run_cube_mixed(ctx, K, F, c, args)
+    K.free()
+    del ctx
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+    # the other workloads of the metric, each in its own section: the small
+    # 2D solve (latency), the heterogeneous transient run, the 512-member
+    # batch and the served stream (p50/p99), FP64 and mixed precision
+    sub_args = argparse.Namespace(**vars(args))
+    sub_args.no_cpu_baseline = True
+    for key, fn in (("small", run_small), ("transient", run_transient),
+                    ("batch", run_batch), ("serve", run_serve)):
+        if key not in extras:
+            continue
+        t0 = time.perf_counter()
+        sec = fn(sub_args, rates=args.extra_rates) if fn is run_serve else fn(sub_args)
+        sec["section_wall_s"] = round(time.perf_counter() - t0, 1)
+        out[key] = sec
+        print(f"bench: {key} section done in {sec['section_wall_s']} s", file=sys.stderr,
+              flush=True)
     print(json.dumps(out), flush=True)
+
+
+def run_cube_mixed(ctx, K, F, c, args):
+    """The same system in mixed precision (float32 values and CG vectors,
+    float64 residual): DOF/s over `steps` solves, its CG-pass roofline and
+    the end state against the float64 one."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    c64 = c.clone()
+    opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=nnqp.NN_MIXED,
+                             subspace=args.subspace)
+    cm = torch.empty_like(c)
+    ctx.solve_nonneg(K, F, opts=opts, c=cm)              # warm-up (forms the float32 copies)
+    ctx.set_profiling(not args.no_kernel_timing, ("cg_spmv",))
+    ctx.kernel_times(reset=True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, st = ctx.solve_nonneg(K, F, opts=opts, c=cm)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_profiling(False)
+    return {"value": round(K.n * args.steps / wall, 1), "unit": "DOF/s",
+            "ms_per_step": round(wall / args.steps * 1e3, 3),
+            "dtype": "f32 values+CG vectors / f64 residual",
+            "outer_its": stats[-1]["outer_its"], "cg_its": stats[-1]["cg_its"],
+            "kkt_rel": stats[-1]["kkt_rel"],
+            "rel_diff_vs_fp64": float((cm - c64).abs().max() / c64.abs().max()),
+            "roofline": roofline_of(kt["cg_spmv"], "k_cg_spmv (float32 values and vectors)",
+                                    read_traffic("k_cg_spmv", f"cube3d_{args.n}", "mixed"))}
 
 
 def run_galerkin(ctx, K, F, n, stats, args):

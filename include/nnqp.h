@@ -129,10 +129,16 @@ typedef struct {
     int32_t subspace;     /* TRON's subspace loop (Lin & More 1999): 1 = after a projected
                              search that reached a new bound, and unless the CG stopped on
                              the trust-region boundary, the CG and search repeat on the
-                             new face from a fresh gradient before the next Cauchy step;
-                             0 = every iteration starts with a Cauchy step.  Either way
-                             the minimiser is the same.  Default 1.  TRON single-problem
-                             entry points only (the batched ones run 0). */
+                             new face (the variables strictly inside the bounds) from a
+                             fresh gradient before the next Cauchy step,
+                             until the projected gradient has fallen to inner_rtol of its
+                             value at the Cauchy point; 0 = every iteration starts with a
+                             Cauchy step.  Either way
+                             the minimiser is the same.  Default 0: on these problems the
+                             loop's faces (which release no variable until the next Cauchy
+                             step) need many more iterations (658,503-DOF cube: 342 outer
+                             iterations against 63).  TRON single-problem entry points only
+                             (the batched ones run 0). */
 } nn_opts;
 
 /* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */
@@ -414,12 +420,17 @@ nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *
 #define NN_KCLASSES 5
 #define NN_PROF_ALL 0x1f
 nn_status nn_set_profiling(nn_ctx *ctx, int classes);
-/* counts/total_ms/total_bytes: host arrays of NN_KCLASSES entries or NULL.
- * total_bytes is the algorithmic (perfect-cache) byte count of the timed
- * launches.  Launches that found their work already finished (CG iterations
- * enqueued past convergence) are not counted.  reset != 0 clears the totals. */
+/* counts/total_ms/total_bytes/total_bytes_csr: host arrays of NN_KCLASSES
+ * entries or NULL.  total_bytes is the algorithmic (perfect-cache) byte count
+ * of the timed launches for the layout the kernels read (int16 column offsets
+ * and paired copies where they are used); total_bytes_csr counts the same
+ * launches with the paper's CSR byte model (Sec. 4, Table 2: 4-byte column
+ * indices, 8-byte values; the CG matrix pass as a masked SpMV plus a
+ * separate direction update, the CG vector update as its unfused operands).
+ * Launches that found their work already finished (CG iterations enqueued
+ * past convergence) are not counted.  reset != 0 clears the totals. */
 nn_status nn_kernel_times(nn_ctx *ctx, int64_t *counts, double *total_ms, double *total_bytes,
-                          int reset);
+                          double *total_bytes_csr, int reset);
 
 #ifdef __cplusplus
 }

@@ -105,7 +105,7 @@ static hipEvent_t pool_event(nn_ctx *ctx)
     return e;
 }
 
-void prof_begin(nn_ctx *ctx, int cls, double bytes)
+void prof_begin(nn_ctx *ctx, int cls, double bytes, double bytes_csr)
 {
     ctx->prof_open = false;
     if (!ctx->prof || !((ctx->prof_mask >> cls) & 1)) return;
@@ -114,6 +114,7 @@ void prof_begin(nn_ctx *ctx, int cls, double bytes)
     p.a = pool_event(ctx);
     p.b = pool_event(ctx);
     p.bytes = bytes;
+    p.bytes_csr = std::isnan(bytes_csr) ? bytes : bytes_csr;
     p.valid = 1;
     (void)hipEventRecord(p.a, ctx->stream);
     ctx->prof_live.push_back(p);
@@ -127,11 +128,13 @@ void prof_end(nn_ctx *ctx)
     ctx->prof_open = false;
 }
 
-void prof_add(nn_ctx *ctx, int cls, double ms, double bytes)
+void prof_add(nn_ctx *ctx, int cls, double ms, double bytes, double bytes_csr)
 {
+    if (std::isnan(bytes_csr)) bytes_csr = bytes;
     ctx->prof_count[cls]++;
     ctx->prof_ms[cls] += ms;
     ctx->prof_bytes[cls] += bytes > 0 ? bytes : 0.0;
+    ctx->prof_bytes_csr[cls] += bytes_csr > 0 ? bytes_csr : 0.0;
 }
 
 void prof_collect(nn_ctx *ctx)
@@ -145,6 +148,7 @@ void prof_collect(nn_ctx *ctx)
                 ctx->prof_count[p.cls]++;
                 ctx->prof_ms[p.cls] += ms;
                 ctx->prof_bytes[p.cls] += p.bytes > 0 ? p.bytes : 0.0;
+                ctx->prof_bytes_csr[p.cls] += p.bytes_csr > 0 ? p.bytes_csr : 0.0;
             }
         }
         ctx->ev_pool.push_back(p.a);
@@ -379,7 +383,7 @@ nn_status nn_default_opts(nn_opts *o)
     o->method = NN_TRON;
     o->lmm_vectors = 5;
     o->max_lm_its = 20000;
-    o->subspace = 1;
+    o->subspace = 0;
     return NN_OK;
 }
 
@@ -749,7 +753,7 @@ nn_status nn_set_profiling(nn_ctx *ctx, int classes)
 }
 
 nn_status nn_kernel_times(nn_ctx *ctx, int64_t *counts, double *total_ms, double *total_bytes,
-                          int reset)
+                          double *total_bytes_csr, int reset)
 {
     NN_CHECK_CTX(ctx);
     prof_collect(ctx);
@@ -757,10 +761,12 @@ nn_status nn_kernel_times(nn_ctx *ctx, int64_t *counts, double *total_ms, double
         if (counts) counts[k] = ctx->prof_count[k];
         if (total_ms) total_ms[k] = ctx->prof_ms[k];
         if (total_bytes) total_bytes[k] = ctx->prof_bytes[k];
+        if (total_bytes_csr) total_bytes_csr[k] = ctx->prof_bytes_csr[k];
         if (reset) {
             ctx->prof_count[k] = 0;
             ctx->prof_ms[k] = 0.0;
             ctx->prof_bytes[k] = 0.0;
+            ctx->prof_bytes_csr[k] = 0.0;
         }
     }
     return NN_OK;

@@ -1086,6 +1086,25 @@ double row_bytes(const BState &S)
     }
 }
 
+// The same under the paper's CSR model (4-byte column indices; the CG
+// matrix pass as a masked SpMV plus a separate direction update).
+double row_bytes_csr(const BState &S)
+{
+    const double n = S.n, nnz = S.nnz;
+    switch (S.phase) {
+    case PH_GRAD:
+        return 4.0 * (n + 1) + 12.0 * nnz + 32.0 * n;
+    case PH_CAUCHY:
+    case PH_SEARCH:
+        return 4.0 * (n + 1) + (4.0 + S.vb) * nnz + 32.0 * n;
+    case PH_CG:
+        return S.cgdone ? 0.0
+                        : (4.0 + S.vb) * S.nnz_free + (4.0 + 6.0 * S.vb) * S.n_free;
+    default:
+        return 0.0;
+    }
+}
+
 }  // namespace
 
 nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double *const *f,
@@ -1529,9 +1548,12 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         const int gr = grid_for(sh, n_sl);
         if (ctx->prof) {
             // one step; algorithmic bytes of the row pass from the states
-            double brow = 0.0;
+            double brow = 0.0, brow_csr = 0.0;
             for (int p = 0; p < P; p++)
-                if (hs[p].phase != PH_DONE) brow += row_bytes(hs[p]);
+                if (hs[p].phase != PH_DONE) {
+                    brow += row_bytes(hs[p]);
+                    brow_csr += row_bytes_csr(hs[p]);
+                }
             step(st, gr, std::max(n_pr, 1), ev_step.ev.data());
             steps++;
             if (!pull()) {
@@ -1541,7 +1563,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
             float m1 = 0.f, m2 = 0.f;
             if (brow > 0.0 && ((ctx->prof_mask >> KC_CG_SPMV) & 1) &&
                 hipEventElapsedTime(&m1, ev_step.ev[0], ev_step.ev[1]) == hipSuccess)
-                prof_add(ctx, KC_CG_SPMV, m1, brow);
+                prof_add(ctx, KC_CG_SPMV, m1, brow, brow_csr);
             if (((ctx->prof_mask >> KC_CG_UPDATE) & 1) &&
                 hipEventElapsedTime(&m2, ev_step.ev[2], ev_step.ev[3]) == hipSuccess)
                 prof_add(ctx, KC_CG_UPDATE, m2, 0.0);

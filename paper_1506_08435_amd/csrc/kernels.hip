@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
     const double *__restrict__ c, double *__restrict__ g, const double *__restrict__ ks,
     uint8_t *__restrict__ mask, VV *__restrict__ dm, VV *__restrict__ r, VV *__restrict__ z,
     VV *__restrict__ p, VV *__restrict__ q, VV *__restrict__ w, double *partials, DevScalars *S,
-    Box B, int all_free, VV *__restrict__ cres, VV *__restrict__ cdz0, VV *__restrict__ cdz1,
+    Box B, int face, VV *__restrict__ cres, VV *__restrict__ cdz0, VV *__restrict__ cdz1,
     double inv_theta)
 {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -260,7 +260,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(
         const double gi = ks ? g[i] + ks[i] : g[i];
         if (ks) g[i] = gi;
         const double cv = c[i];
-        const bool fr = all_free || !((cv == B.lo && gi >= 0.0) || (cv == B.hi && gi <= 0.0));
+        const bool fr = face == FACE_ALL ? true
+                      : face == FACE_INTERIOR ? (cv != B.lo && cv != B.hi)
+                      : !((cv == B.lo && gi >= 0.0) || (cv == B.hi && gi <= 0.0));
         const VV dmi = fr ? (VV)(1.0 / diag[i]) : VV(0);
         const VV ri = fr ? (VV)(-gi) : VV(0);
         // Jacobi z = dm r, or the first Chebyshev term dm r / theta
@@ -766,7 +768,7 @@ void launch_add(nn_ctx *ctx, int64_t n, double *c, const double *w)
 }
 
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32, Box B, bool all_free,
+                     double *g, const double *ks, bool f32, Box B, int face,
                      const Cheb *ch)
 {
     Part P = make_part(A->n);
@@ -775,12 +777,12 @@ void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const 
     if (f32)
         k_cg_setup<float><<<P.nb, kBlock, 0, ctx->stream>>>(
             P, A->rowptr, diag, c, g, ks, W.mask, W.dm32, W.r32, W.z32, W.p32, W.q32, W.w32,
-            ctx->partials, ctx->scal, B, all_free ? 1 : 0, ch ? W.cres32 : nullptr,
+            ctx->partials, ctx->scal, B, face, ch ? W.cres32 : nullptr,
             ch ? W.cdz32[0] : nullptr, ch ? W.cdz32[1] : nullptr, it);
     else
         k_cg_setup<double><<<P.nb, kBlock, 0, ctx->stream>>>(
             P, A->rowptr, diag, c, g, ks, W.mask, W.dm, W.r, W.z, W.p0, W.q, W.w, ctx->partials,
-            ctx->scal, B, all_free ? 1 : 0, ch ? W.cres : nullptr, ch ? W.cdz[0] : nullptr,
+            ctx->scal, B, face, ch ? W.cres : nullptr, ch ? W.cdz[0] : nullptr,
             ch ? W.cdz[1] : nullptr, it);
 }
 

@@ -124,7 +124,8 @@ struct Dir {
 struct ProfEntry {
     int cls;
     hipEvent_t a, b;
-    double bytes;
+    double bytes;       // algorithmic bytes of the layout the kernel reads
+    double bytes_csr;   // the same launch under the paper's CSR byte model
     int valid;
 };
 
@@ -201,6 +202,7 @@ struct nn_ctx {
     int64_t prof_count[NN_KCLASSES] = {0};
     double prof_ms[NN_KCLASSES] = {0};
     double prof_bytes[NN_KCLASSES] = {0};
+    double prof_bytes_csr[NN_KCLASSES] = {0};
 };
 
 namespace nnqp {
@@ -235,18 +237,26 @@ nn_status read_scalars(nn_ctx *ctx);
 // ops[k] is OP_SUM / OP_MIN / OP_MAX for value k.
 nn_status host_reduce(nn_ctx *ctx, int64_t n, int nv, const int *ops, double *out);
 
-// profiling around launches of a kernel class
-void prof_begin(nn_ctx *ctx, int cls, double bytes);
+// profiling around launches of a kernel class.  bytes: algorithmic bytes of
+// the layout the kernel reads (index width, paired copies); bytes_csr: the
+// same launch under the paper's CSR model (Sec. 4, Table 2: 4-byte column
+// indices, every vector operand of the unfused operations counted), NaN for
+// "the same as bytes"
+void prof_begin(nn_ctx *ctx, int cls, double bytes, double bytes_csr = __builtin_nan(""));
 void prof_end(nn_ctx *ctx);
 void prof_collect(nn_ctx *ctx);
 // add one timed launch of class cls (ms, algorithmic bytes) to the totals
-void prof_add(nn_ctx *ctx, int cls, double ms, double bytes);
+void prof_add(nn_ctx *ctx, int cls, double ms, double bytes, double bytes_csr = __builtin_nan(""));
 
 // ---------------------------------------------------------------- kernel launchers
 // (kernels.hip).  All launch on ctx->stream with the partition of the rows.
 // Kernels marked [host] leave partials for host_reduce; their value lists
 // are given in order.
 enum { KC_CG_SPMV = 0, KC_CG_UPDATE = 1, KC_GRAD = 2, KC_TRIAL = 3, KC_OTHER = 4 };
+// CG faces: the complement of the binding set (the Cauchy point's face), every
+// row (unconstrained solve), the rows strictly inside the bounds (a subspace
+// step: variables at a bound stay there until the next Cauchy step)
+enum { FACE_BINDING = 0, FACE_ALL = 1, FACE_INTERIOR = 2 };
 
 void launch_matvec(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *x, double *y);
 // [host] c = c0v (mode 0) or P(c) (mode 1); |f|^2 sum, max f, #nonfinite f sum, #nonfinite c sum
@@ -265,10 +275,11 @@ void launch_ladder(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double 
 // c = P(c + t d)
 void launch_apply(nn_ctx *ctx, int64_t n, double *c, Dir d, double t, Box B);
 // CG set-up on the face of (c, g + ks) (every row not binding: not at lo with
-// g >= 0, not at hi with g <= 0; every row when all_free); partials of r.z,
+// g >= 0, not at hi with g <= 0: FACE_BINDING; every row: FACE_ALL; every row
+// strictly inside the bounds: FACE_INTERIOR); partials of r.z,
 // r.r, #free, nnz(free) in SLOT_U0; f32 selects the float32 CG vectors
 void launch_cg_setup(nn_ctx *ctx, const nn_matrix *A, const double *diag, const double *c,
-                     double *g, const double *ks, bool f32, Box B, bool all_free,
+                     double *g, const double *ks, bool f32, Box B, int face,
                      const Cheb *ch = nullptr);
 // Chebyshev step `step` (1..degree-1) on the free rows; the last one writes
 // r.z into value 0 of partial slot `slot`

@@ -28,8 +28,12 @@
 //      breakpoint, where the step is again safe.
 //   5. Subspace loop (TRON): when the search stopped on a new face (a free
 //      variable reached its bound) and the CG did not stop on the trust-region
-//      boundary, steps 3-4 repeat from the new point on its face (a fresh
-//      gradient, no new Cauchy step) before the outer iteration ends.
+//      boundary, steps 3-4 repeat from the new point on its face: a fresh
+//      gradient, no new Cauchy step, and the variables at a bound held there
+//      (the CG face is the rows strictly inside the bounds, so it only
+//      shrinks); until one of these fails or the projected gradient has
+//      fallen to inner_rtol of its value at the Cauchy point.  Then the outer
+//      iteration ends.
 //   6. Trust region: the quadratic model is the objective, so the ratio of
 //      actual to predicted reduction is one; the radius (unbounded unless the
 //      caller gives one) grows by 4x whenever the outer iteration's step
@@ -188,6 +192,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     // pass reads them (float32 values, or the paired float64 layout)
     const double ib = ((mixed && A->sl_d16) || VS.v64p) ? 2.0 : 4.0;
     const double spmv_s = 4.0 * (n + 1) + (ib + vb) * A->nnz + 16.0 * n;
+    const double spmv_csr = spmv_s + (4.0 - ib) * A->nnz;   // 4-byte column indices
     Dir dir_g, dir_w;
     dir_g.f64 = W.g;
     if (mixed) dir_w.f32 = W.w32;
@@ -232,6 +237,13 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     bool subspace = false;    // this iteration continues the subspace loop (no Cauchy step)
     int sub_run = 0;          // subspace steps taken in the current outer iteration
     double step_outer = 0.0;  // bound on |c - c_k| over the current outer iteration
+    double pg_cauchy = 0.0;   // |pg| on the face of the outer iteration's Cauchy point
+    // end of an outer iteration: radius update (exact model: ratio one)
+    auto end_outer = [&]() {
+        sub_run = 0;
+        if (tr && step_outer >= 0.99 * delta) delta *= 4.0;
+        step_outer = 0.0;
+    };
 
     static_assert(kLadder == 3, "ladder buffers: ks0, ks1, ks2");
     double *const ladder_ks[kLadder] = {W.ks0, W.ks1, W.ks2};
@@ -242,7 +254,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         // subspace step)
         // the float64 gradient reads the paired copy when the solve has one
         const double grad_b = (VS.v64p ? spmv_s : B.spmv()) + 16.0 * n;
-        prof_begin(ctx, KC_GRAD, grad_b);
+        prof_begin(ctx, KC_GRAD, grad_b, B.spmv() + 16.0 * n);
         launch_grad(ctx, A, vals, VS.v64p, c, f, W.g, box);
         prof_end(ctx);
         S.spmvs++;
@@ -259,10 +271,22 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         if (subspace) {
             static const int kGradOps[5] = {OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM};
             if ((rc = host_reduce(ctx, n, 5, kGradOps, red)) != NN_OK) return rc;
-        } else {
-            prof_begin(ctx, KC_TRIAL, spmv_s + (16.0 + 8.0 * kLadder) * n);
+            // the subspace loop also ends once the projected gradient has
+            // fallen to inner_rtol of its value at the Cauchy point (the
+            // inner tolerance applied to the whole subspace minimisation);
+            // the outer iteration then starts here with its Cauchy step
+            const double pgn = std::sqrt(red[0]);
+            if (red[1] == 0.0 && pgn > tol * normf && pgn <= o->inner_rtol * pg_cauchy) {
+                subspace = false;
+                end_outer();
+            }
+        }
+        if (!subspace) {
+            prof_begin(ctx, KC_TRIAL, spmv_s + (16.0 + 8.0 * kLadder) * n,
+                       spmv_csr + (16.0 + 8.0 * kLadder) * n);
             launch_ladder(ctx, A, VS, c, W.g, lt, ladder_ks, box);
             prof_end(ctx);
+            // (after a subspace exit the gradient partials are read again)
             if ((rc = read_grad_and_ladder(ctx, n, red, lres)) != NN_OK) return rc;
         }
         if (red[1] != 0.0) return finish(fail(ctx, NN_ENONFINITE, "non-finite gradient"));
@@ -296,7 +320,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             double *best_ks = ladder_ks[kMid];
             auto scratch_for = [&](const double *busy) { return busy == W.ks0 ? W.ks1 : W.ks0; };
             auto trial_cauchy = [&](double t, double *ks, double &gs, double &sks, double &ss) -> nn_status {
-                prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
+                prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n, spmv_csr + 16.0 * n);
                 launch_trial(ctx, A, VS, c, dir_g, -t, W.g, nullptr, ks, box);
                 prof_end(ctx);
                 S.spmvs++;
@@ -385,7 +409,8 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         const double delta_rem = delta - step_outer;
         const double delta2 = tr ? std::max(delta_rem, 0.0) * std::max(delta_rem, 0.0) : INFINITY;
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, diag, c, W.g, cg_ks, mixed, box, false, chp);
+        launch_cg_setup(ctx, A, diag, c, W.g, cg_ks, mixed, box,
+                        subspace ? FACE_INTERIOR : FACE_BINDING, chp);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
         for (int st = 1; st <= csteps; st++) launch_cheb(ctx, A, VS, cheb, st, SLOT_U0);
@@ -419,17 +444,28 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             // Chebyshev pass: matrix on the free rows, dz gathered, res and z
             // read and written, dzp, dm, r read, dzn written
             const double b_cheb = n + 4.0 * nf + (ib + vb) * nzf + 8.0 * vb * nf;
+            // the paper's CSR model of the same work: a masked SpMV (4-byte
+            // columns, rowptr, gathered and written vector) plus the direction
+            // update p = z + beta p as its own pass (read r, dinv, p; write p),
+            // and the CG update as its unfused operands (read x, p, r, q, dinv;
+            // write x, r)
+            const double c_spmv = (4.0 + vb) * nzf + (4.0 + 2.0 * vb) * nf + 4.0 * vb * nf;
+            const double c_upd = 7.0 * vb * nf;
             int seen[NN_KCLASSES] = {0};   // launches of each class in this chunk
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
                 P.valid = seen[P.cls]++ < (P.cls == KC_OTHER ? ran * csteps : ran);
                 P.bytes = P.cls == KC_CG_SPMV ? b_spmv : (P.cls == KC_OTHER ? b_cheb : b_upd);
+                P.bytes_csr = P.cls == KC_CG_SPMV ? c_spmv : (P.cls == KC_OTHER ? b_cheb : c_upd);
             }
             S.bytes_moved += ran * (b_spmv + b_upd + csteps * b_cheb);
             S.spmvs += ran * (1 + csteps);
             it_seen = H.it;
         }
         S.cg_its += it_seen;
+        // |pg| on the CG face at the Cauchy point: r.r at the CG set-up, kept
+        // on the device as rtol^2 r.r in the stop threshold
+        if (!subspace && H.done != 2) pg_cauchy = std::sqrt(H.rr_stop) / o->inner_rtol;
         if (H.done == 4) return finish(fail(ctx, NN_ENONFINITE, "non-finite value in CG"));
         if (H.done == 3) return finish(fail(ctx, NN_ENOTSPD, "non-positive curvature in CG"));
         const bool on_boundary = H.done == 2;   // the CG step stopped on the trust region
@@ -448,7 +484,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             double ts = tmax;
             if (bmin < tmax) {
                 for (int k = 0; k < kMaxTrials; k++) {
-                    prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n);
+                    prof_begin(ctx, KC_TRIAL, spmv_s + 16.0 * n, spmv_csr + 16.0 * n);
                     launch_trial(ctx, A, VS, c, dir_w, ts, W.g, W.mask, nullptr, box);
                     prof_end(ctx);
                     S.spmvs++;
@@ -482,17 +518,16 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                          on_boundary ? " (trust-region boundary)" : "");
         if (on_boundary) S.radius_stops++;
         // ---- 5. subspace loop: another CG step on the new face, unless the
-        // step stopped on the trust-region boundary
+        // step stopped on the trust-region boundary (or the projected
+        // gradient has fallen far enough, tested at the top)
         subspace = o->subspace && new_face && !on_boundary && sub_run < kMaxSubspace &&
                    !(tr && step_outer >= 0.99 * delta);
         if (subspace) {
             sub_run++;
             continue;
         }
-        sub_run = 0;
-        // ---- 6. radius update (exact model: ratio one)
-        if (tr && step_outer >= 0.99 * delta) delta *= 4.0;
-        step_outer = 0.0;
+        // ---- 6. radius update
+        end_outer();
     }
     if (result == NN_OK) ctx->err.clear();
     return finish(result);
@@ -569,7 +604,7 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
         S.spmvs++;
         S.bytes_moved += B.spmv() + 16.0 * n;
         prof_begin(ctx, KC_OTHER, 40.0 * n);
-        launch_cg_setup(ctx, A, A->diag, c, W.g, nullptr, false, unbounded, true, chp);
+        launch_cg_setup(ctx, A, A->diag, c, W.g, nullptr, false, unbounded, FACE_ALL, chp);
         prof_end(ctx);
         S.bytes_moved += 88.0 * n;
         for (int st = 1; st <= csteps; st++) launch_cheb(ctx, A, VS, cheb, st, SLOT_U0);
@@ -595,11 +630,13 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
             if ((rc = read_scalars(ctx)) != NN_OK) return rc;
             const int ran = H.it - it_seen;
             const double b_cheb = n + 4.0 * n + 12.0 * A->nnz + 64.0 * n;
+            const double c_spmv = 12.0 * A->nnz + 52.0 * n, c_upd = 56.0 * n;   // CSR model
             int seen[NN_KCLASSES] = {0};
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
                 P.valid = seen[P.cls]++ < (P.cls == KC_OTHER ? ran * csteps : ran);
                 P.bytes = P.cls == KC_CG_SPMV ? b_spmv : (P.cls == KC_OTHER ? b_cheb : b_upd);
+                P.bytes_csr = P.cls == KC_CG_SPMV ? c_spmv : (P.cls == KC_OTHER ? b_cheb : c_upd);
             }
             S.bytes_moved += ran * (b_spmv + b_upd + csteps * b_cheb);
             S.spmvs += ran * (1 + csteps);

@@ -119,7 +119,7 @@ def load_library(path: str = LIB_PATH):
         "nn_step_transient_batch": (i32, [vp, i32, P(vp), dbl, P(vp), P(Opts), P(vp), P(vp),
                                           P(Stats)]),
         "nn_set_profiling": (i32, [vp, ctypes.c_int]),
-        "nn_kernel_times": (i32, [vp, vp, vp, vp, ctypes.c_int]),
+        "nn_kernel_times": (i32, [vp, vp, vp, vp, vp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -433,7 +433,9 @@ class Context:
         counts = np.zeros(NN_KCLASSES, dtype=np.int64)
         ms = np.zeros(NN_KCLASSES)
         by = np.zeros(NN_KCLASSES)
+        bc = np.zeros(NN_KCLASSES)
         self._check(self.lib.nn_kernel_times(self.handle, _ptr(counts), _ptr(ms), _ptr(by),
-                                             int(reset)), "nn_kernel_times")
-        return {name: {"count": int(counts[k]), "ms": float(ms[k]), "bytes": float(by[k])}
+                                             _ptr(bc), int(reset)), "nn_kernel_times")
+        return {name: {"count": int(counts[k]), "ms": float(ms[k]), "bytes": float(by[k]),
+                       "bytes_csr": float(bc[k])}
                 for k, name in enumerate(KCLASS_NAMES)}

@@ -182,7 +182,7 @@ class Server:
                  precision: int = nnqp.NN_FP64, dt: float = 1e-3, tol: float = 1e-8,
                  inner_rtol: float = 0.1, assemble_workers: int = 2, keep_states: bool = False,
                  bounds=(0.0, math.inf), lane_bounds=(30000, 300000), solo_lanes=2,
-                 allocator=None):
+                 allocator=None, subspace: int = 0):
         import torch
         self.torch = torch
         self.device = device
@@ -190,7 +190,8 @@ class Server:
         self.dt = dt
         # bounds c_min <= c <= c_max of every step (Sec. 2.2.2, eq. Eq:non-negative)
         self.opts = nnqp.default_opts(tol=tol, inner_rtol=inner_rtol, precision=precision,
-                                      lower=float(bounds[0]), upper=float(bounds[1]))
+                                      lower=float(bounds[0]), upper=float(bounds[1]),
+                                      subspace=int(subspace))
         free, total = torch.cuda.mem_get_info(device)
         self.budget = int(hbm_budget) if hbm_budget else int(0.75 * free)
         self.workers = assemble_workers
