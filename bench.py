@@ -162,7 +162,8 @@ def run_small(args):
     for prec_name in ("fp64", "mixed"):
         prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
         opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
-                                 subspace=args.subspace)
+                                 subspace=args.subspace,
+                                 engine=args.engine if prec == nnqp.NN_FP64 else min(args.engine, 1))
         c = torch.empty(K.n, dtype=torch.float64, device=ctx.device)
         for _ in range(3):
             ctx.solve_nonneg(K, F, opts=opts, c=c)
@@ -475,6 +476,9 @@ def main():
     ap.add_argument("--subspace", type=int, choices=[0, 1], default=0,
                     help="TRON's subspace loop (1) or a Cauchy step every iteration (0, the "
                          "library default); the minimiser is the same")
+    ap.add_argument("--engine", type=int, choices=[0, 1, 2], default=0,
+                    help="single-problem solves: 0 = by size (one workgroup up to 16,384 rows), "
+                         "1 = multi-block passes, 2 = one workgroup")
     ap.add_argument("--precond-degree", type=int, default=1,
                     help="inner CG preconditioner: 1 = Jacobi, k > 1 = Chebyshev of degree k")
     ap.add_argument("--cpu-n", type=int, default=64, help="cube side of the CPU-baseline sample")

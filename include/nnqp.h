@@ -139,6 +139,14 @@ typedef struct {
                              step) need many more iterations (658,503-DOF cube: 342 outer
                              iterations against 63).  TRON single-problem entry points only
                              (the batched ones run 0). */
+    int32_t engine;       /* how a single-problem TRON solve runs: 0 (default) = by size:
+                             one workgroup in one launch (every pass over the problem by
+                             one 512-thread workgroup, every decision on the device) up
+                             to 4,096 rows when the solve is float64, without a trust
+                             radius, subspace loop or Chebyshev preconditioner, else the
+                             multi-block passes; 1 = always the multi-block passes;
+                             2 = always one workgroup (NN_EINVAL if the options do not
+                             allow it).  The minimiser is the same. */
 } nn_opts;
 
 /* Per-solve report (host struct, filled on return, also on NN_EMAXIT). */

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["api.hip", "assemble.hip", "batch.hip", "blmvm.hip", "kernels.hip", "noalloc.hip",
-           "solver.hip"]
+           "solo.hip", "solver.hip"]
 LIB = os.path.join(HERE, "libnnqp.so")
 ARCH = os.environ.get("NNQP_ARCH", "gfx950")
 

@@ -292,6 +292,7 @@ nn_status nnqp::check_opts(nn_ctx *ctx, const nn_opts *o)
     if (o->precond_degree < 0 || o->precond_degree > 8)
         return fail(ctx, NN_EINVAL, "precond_degree must be in 0..8");
     if (o->subspace != 0 && o->subspace != 1) return fail(ctx, NN_EINVAL, "subspace must be 0 or 1");
+    if (o->engine < 0 || o->engine > 2) return fail(ctx, NN_EINVAL, "engine must be 0, 1 or 2");
     if (o->method == NN_BLMVM) {
         if (o->lmm_vectors < 1 || o->lmm_vectors > 8)
             return fail(ctx, NN_EINVAL, "lmm_vectors must be in 1..8");
@@ -569,6 +570,21 @@ nn_status nn_matvec(nn_ctx *ctx, const nn_matrix *A, int which, const double *x_
 }
 
 
+// NN_OK: run the solve in one workgroup; NN_EMAXIT: run the multi-block
+// passes; NN_EINVAL: engine 2 asked for a solve one workgroup cannot run.
+static nn_status choose_solo(nn_ctx *ctx, const nn_matrix *K, const nn_opts *o)
+{
+    const bool ok = solo_eligible(K, o);
+    if (o->engine == 2) {
+        if (!ok)
+            return fail(ctx, NN_EINVAL,
+                        "engine 2 (one workgroup) runs float64 TRON without a trust radius, "
+                        "subspace loop, Chebyshev preconditioner or trace");
+        return NN_OK;
+    }
+    return (o->engine == 0 && ok && K->n <= kSoloMaxRows) ? NN_OK : NN_EMAXIT;
+}
+
 nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
                           const nn_opts *opts, double *c_dev, uint8_t *active_dev, nn_stats *stats)
 {
@@ -578,6 +594,9 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
     if (st != NN_OK) return st;
     if (opts->method == NN_BLMVM)
         return blmvm_impl(ctx, K, K->val, f_dev, opts, c_dev, active_dev, stats);
+    if ((st = choose_solo(ctx, K, opts)) == NN_OK)
+        return solo_solve_impl(ctx, K, K->val, K->diag, f_dev, opts, c_dev, active_dev, stats);
+    if (st != NN_EMAXIT) return st;   // (NN_EMAXIT: the multi-block passes)
     const float *v32 = nullptr;
     if (opts->precision == NN_MIXED && K->n > 0) {
         if (!K->val32) {
@@ -627,6 +646,9 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     nn_opts o = *opts;
     o.c0_mode = 1;   // warm start from c^(n)
     if (o.method == NN_BLMVM) return blmvm_impl(ctx, K, K->kt, ctx->ws.ft, &o, c_dev, active_dev, stats);
+    if ((st = choose_solo(ctx, K, &o)) == NN_OK)
+        return solo_solve_impl(ctx, K, K->kt, K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev, stats);
+    if (st != NN_EMAXIT) return st;
     return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32p : nullptr,
                       mixed ? nullptr : K->kt64p, K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev,
                       stats);

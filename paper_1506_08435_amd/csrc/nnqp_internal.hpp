@@ -221,6 +221,16 @@ nn_status ensure_workspace(nn_ctx *ctx, int64_t n);
 // Option checks shared by the solve entry points (api.hip).
 nn_status check_opts(nn_ctx *ctx, const nn_opts *o);
 
+// Single-problem solves up to this many rows run in one workgroup and one
+// launch (solo.hip) when the options allow it (nn_opts.engine).
+constexpr int64_t kSoloMaxRows = 4096;
+// whether the solve of A with options o can run in one workgroup
+bool solo_eligible(const nn_matrix *A, const nn_opts *o);
+// the TRON solve of solver.hip in one workgroup (float64 values `vals`)
+nn_status solo_solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const double *diag,
+                          const double *f, const nn_opts *o, double *c, uint8_t *active,
+                          nn_stats *st);
+
 // Rows the fixed work array of nn_solve_nonneg_noalloc holds (noalloc.hip).
 constexpr int64_t kNoAllocMaxRows = 262144;
 // Take the current device's address of that array (once per device; called

@@ -61,7 +61,7 @@ class Opts(ctypes.Structure):
                 ("lower", ctypes.c_double), ("upper", ctypes.c_double),
                 ("method", ctypes.c_int32), ("lmm_vectors", ctypes.c_int32),
                 ("max_lm_its", ctypes.c_int32), ("precond_degree", ctypes.c_int32),
-                ("subspace", ctypes.c_int32)]
+                ("subspace", ctypes.c_int32), ("engine", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -1161,3 +1161,91 @@ def test_subspace_option_validated(ctx):
     with pytest.raises(nnqp.NnError) as ei:
         ctx.solve_nonneg(K, F, subspace=2)
     assert ei.value.status == nnqp.NN_EINVAL
+
+
+# ---------------------------------------------------------------- one-workgroup engine
+ENGINE_CASES = ["square2d_64", "cube3d_21_ragged", "transient_field_20x18x9", "batch_member_0",
+                "batch_member_5"]
+
+
+@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("name", ENGINE_CASES)
+def test_engines_match_oracle(ctx, name, engine):
+    """Both ways a single-problem solve runs (multi-block passes; the whole
+    method in one workgroup and one launch) reach the oracle's minimiser with
+    identical nondegenerate active sets."""
+    p = SOLVE_CASES[name]()
+    K, F, _ = ctx.assemble(p)
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12, inner_rtol=0.1, engine=engine)
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    err = _check_solution(S, _np(c), _np(active), ref.c, strict_expected=name not in NO_STRICT)
+    k = oracle.kkt(S, _np(c))
+    assert k.r <= 1.01e-12 + 4 * ref.floor
+    assert abs(st["kkt_rel"] - k.r) <= 1e-2 * k.r + 1e-15
+    print(f"{name} engine {engine}: err={err:.2e} outer={st['outer_its']} cg={st['cg_its']} "
+          f"{st['seconds'] * 1e3:.2f} ms")
+
+
+def test_one_workgroup_edge_cases(ctx):
+    """One workgroup: a single DOF, f <= 0 (exact zero), a non-finite load,
+    the iteration cap (feasible iterate), a warm start from the solution (no
+    iteration), bitwise reproducibility, bounds on both sides, and transient
+    steps against the oracle."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.square2d(2)                          # one free node
+    K, F, _ = ctx.assemble(p)
+    c, a, st = ctx.solve_nonneg(K, F, tol=1e-12, engine=2)
+    S = oracle.assemble(p)
+    assert abs(_np(c)[0] - oracle.solve(S, tol=1e-14).c[0]) <= 1e-14 * abs(_np(c)[0])
+    p = W.square2d(30, theta=0.4, ratio=1e-2)
+    K, F, _ = ctx.assemble(p)
+    c, a, st = ctx.solve_nonneg(K, -F, tol=1e-12, engine=2)
+    assert torch.count_nonzero(c).item() == 0 and bool(a.all())
+    bad = F.clone()
+    bad[7] = float("nan")
+    with pytest.raises(nnqp.NnError) as ei:
+        ctx.solve_nonneg(K, bad, engine=2)
+    assert ei.value.status == nnqp.NN_ENONFINITE
+    c, _, st = ctx.solve_nonneg(K, F, tol=1e-13, max_outer=2, engine=2, allow_maxit=True)
+    assert st["status"] == nnqp.NN_EMAXIT and st["outer_its"] == 2 and _np(c).min() >= 0.0
+    c1, a1, s1 = ctx.solve_nonneg(K, F, tol=1e-12, engine=2)
+    c2, a2, s2 = ctx.solve_nonneg(K, F, tol=1e-12, engine=2)
+    assert torch.equal(c1, c2) and torch.equal(a1, a2) and s1["cg_its"] == s2["cg_its"]
+    o = nnqp.default_opts(tol=1e-12, c0_mode=1, engine=2)
+    cw = c1.clone()
+    _, _, sw = ctx.solve_nonneg(K, F, opts=o, c=cw)
+    assert sw["outer_its"] == 0 and torch.equal(cw, c1)
+    # both bounds active
+    pb = _capped(W.config_small(), 0.5)
+    lo, hi = pb.bounds
+    Kb, Fb, _ = ctx.assemble(pb)
+    Sb = oracle.assemble(pb)
+    cb, ab, _ = ctx.solve_nonneg(Kb, Fb, tol=1e-12, lower=lo, upper=hi, engine=2)
+    refb = oracle.solve(Sb, tol=1e-13, lo=lo, hi=hi)
+    _check_box(Sb, _np(cb), _np(ab), refb.c, lo, hi, strict_upper=True)
+    # backward-Euler steps
+    q = W.cube3d(10)
+    Kq, Fq, _ = ctx.assemble(q, with_mass=True)
+    Sq = oracle.assemble(q, with_mass=True)
+    cq = torch.zeros(Kq.n, dtype=torch.float64, device=ctx.device)
+    cref = np.zeros(Sq.n)
+    for _ in range(3):
+        cq, aq, _ = ctx.step_transient(Kq, 1e-3, Fq, cq, tol=1e-12, engine=2)
+        r = oracle.transient_step(Sq, 1e-3, cref, tol=1e-13)
+        Kt, ft = oracle.transient_system(Sq, 1e-3, cref)
+        St = oracle.System(n=Sq.n, rowptr=Sq.rowptr, col=Sq.col, K=Kt, M=None, F=ft, dof=Sq.dof)
+        _check_solution(St, _np(cq), _np(aq), r.c)
+        cref = r.c
+
+
+def test_engine_option_validation(ctx):
+    from paper_1506_08435_amd import nnqp
+    K, F, _ = ctx.assemble(W.square2d(12))
+    for kw in ({"engine": 3}, {"engine": 2, "precision": nnqp.NN_MIXED},
+               {"engine": 2, "delta0": 1.0}, {"engine": 2, "subspace": 1},
+               {"engine": 2, "precond_degree": 3}):
+        with pytest.raises(nnqp.NnError) as ei:
+            ctx.solve_nonneg(K, F, **kw)
+        assert ei.value.status == nnqp.NN_EINVAL, kw

@@ -39,7 +39,8 @@ def test_noalloc_matches_solve_twice_and_allocates_nothing(prec):
     for p in (W.cube3d(40), W.config_small()):     # the second call is the smaller system
         K, F, _ = ctx.assemble(p)
         print(f"{prec} {p.name}: n = {K.n}", flush=True)
-        c_ref, a_ref, st_ref = ctx.solve_nonneg(K, F, tol=1e-12, precision=precision)
+        # the multi-block passes, which the no-allocation solve runs at every size
+        c_ref, a_ref, st_ref = ctx.solve_nonneg(K, F, tol=1e-12, precision=precision, engine=1)
         c = torch.full((K.n,), 123.0, dtype=torch.float64, device=ctx.device)
         act = torch.full((K.n,), 7, dtype=torch.uint8, device=ctx.device)
         torch.cuda.synchronize()
@@ -87,6 +88,6 @@ def test_noalloc_limits_and_options():
         assert ei.value.status == nnqp.NN_EINVAL, kw
     # a plain context (hipMalloc) after the hooked ones, same device array
     c2, _, st = ctx.solve_nonneg_noalloc(K, F, c, a, tol=1e-12)
-    c1, _, _ = ctx.solve_nonneg(K, F, tol=1e-12)
+    c1, _, _ = ctx.solve_nonneg(K, F, tol=1e-12, engine=1)
     assert torch.equal(c2, c1)
     ctx.close()
