@@ -280,7 +280,8 @@ def run_transient(args):
     for prec_name in ("fp64", "mixed"):
         prec = nnqp.NN_MIXED if prec_name == "mixed" else nnqp.NN_FP64
         opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=prec,
-                                 precond_degree=args.precond_degree, subspace=args.subspace)
+                                 precond_degree=args.precond_degree, subspace=args.subspace,
+                                 cg_chunk=args.cg_chunk)
         c = torch.zeros(n, dtype=torch.float64, device=ctx.device)
         ctx.step_transient(K, args.dt, F, c, opts=opts)          # warm-up (forms K~)
         c.zero_()
@@ -476,6 +477,8 @@ def main():
     ap.add_argument("--subspace", type=int, choices=[0, 1], default=0,
                     help="TRON's subspace loop (1) or a Cauchy step every iteration (0, the "
                          "library default); the minimiser is the same")
+    ap.add_argument("--cg-chunk", type=int, default=16,
+                    help="CG iterations between convergence reads (0: adaptive first chunk)")
     ap.add_argument("--engine", type=int, choices=[0, 1, 2], default=0,
                     help="single-problem solves: 0 = by size (one workgroup up to 16,384 rows), "
                          "1 = multi-block passes, 2 = one workgroup")
@@ -564,7 +567,7 @@ def main():
     prec = nnqp.NN_MIXED if args.precision == "mixed" else nnqp.NN_FP64
     opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, verbose=int(args.verbose),
                              precision=prec, precond_degree=args.precond_degree,
-                             subspace=args.subspace)
+                             subspace=args.subspace, cg_chunk=args.cg_chunk)
     c = torch.empty(n, dtype=torch.float64, device=ctx.device)
     for _ in range(args.warmup):
         ctx.solve_nonneg(K, F, opts=opts, c=c)
@@ -670,7 +673,7 @@ def run_cube_mixed(ctx, K, F, c, args):
     from paper_1506_08435_amd import nnqp
     c64 = c.clone()
     opts = nnqp.default_opts(tol=1e-8, inner_rtol=args.inner_rtol, precision=nnqp.NN_MIXED,
-                             subspace=args.subspace)
+                             subspace=args.subspace, cg_chunk=args.cg_chunk)
     cm = torch.empty_like(c)
     ctx.solve_nonneg(K, F, opts=opts, c=cm)              # warm-up (forms the float32 copies)
     ctx.set_profiling(not args.no_kernel_timing, ("cg_spmv",))

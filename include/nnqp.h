@@ -108,7 +108,10 @@ typedef struct {
                              radius only ever grows (x4 when a step reaches it).
                              The batched entry points scale the CG step back into
                              the radius instead. */
-    int32_t cg_chunk;     /* CG iterations enqueued between convergence reads; default 16 */
+    int32_t cg_chunk;     /* CG iterations enqueued between convergence reads: k > 0 a fixed
+                             k (default 16); 0 = the previous inner solve's count plus 2
+                             (2..16) first, then 16 at a time.  Iterates do not depend on
+                             it. */
     int32_t verbose;      /* 1: one line per outer iteration on stderr; default 0 */
     double lower;         /* bounds lower <= c <= upper of the constrained solves
                              (Sec. 2.2.2, eq. Eq:non-negative: c_min 1 <= c <= c_max 1).

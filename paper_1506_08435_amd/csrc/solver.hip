@@ -232,7 +232,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     double t_cauchy = 1.0;
     double delta = o->delta0 > 0.0 ? o->delta0 : INFINITY;
     const bool tr = std::isfinite(delta);   // CG truncated at the trust-region boundary
+    // CG iterations enqueued between convergence reads: a fixed chunk, or
+    // (cg_chunk 0) a first chunk of at most 16 sized from the previous inner
+    // solve's count, so a short inner solve enqueues fewer launches that find
+    // it finished (each returns at once, but still costs a few microseconds)
     const int chunk = o->cg_chunk > 0 ? o->cg_chunk : 16;
+    int cg_guess = chunk;   // iterations of the previous inner solve
     nn_status result = NN_EMAXIT;
     bool subspace = false;    // this iteration continues the subspace loop (no Cauchy step)
     int sub_run = 0;          // subspace steps taken in the current outer iteration
@@ -416,9 +421,12 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
         for (int st = 1; st <= csteps; st++) launch_cheb(ctx, A, VS, cheb, st, SLOT_U0);
         int it_seen = 0, j_next = 0;
         H.done = tr && !(delta_rem > 0.0) ? 2 : 0;   // no room left: no CG step
-        for (; !H.done;) {
+        for (int round = 0; !H.done; round++) {
             const size_t mark = ctx->prof_live.size();
-            for (int k = 0; k < chunk; k++, j_next++) {
+            const int this_chunk = o->cg_chunk > 0 || round > 0
+                                       ? chunk
+                                       : std::max(2, std::min(chunk, cg_guess + 2));
+            for (int k = 0; k < this_chunk; k++, j_next++) {
                 prof_begin(ctx, KC_CG_SPMV, -1.0);
                 launch_cg_spmv(ctx, A, VS, j_next, o->max_cg, o->inner_rtol, tr);
                 prof_end(ctx);
@@ -463,6 +471,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             it_seen = H.it;
         }
         S.cg_its += it_seen;
+        if (H.done != 2 || it_seen > 0) cg_guess = it_seen;
         // |pg| on the CG face at the Cauchy point: r.r at the CG set-up, kept
         // on the device as rtol^2 r.r in the stop threshold
         if (!subspace && H.done != 2) pg_cauchy = std::sqrt(H.rr_stop) / o->inner_rtol;
