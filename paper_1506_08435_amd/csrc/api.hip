@@ -171,15 +171,20 @@ nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K, bool f64)
 {
     if (!K->sl_d16 || K->n == 0) return NN_OK;
     const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
-    if (!K->d16p) {
+    if (f64 && !K->d16p) {
         if (dev_malloc(K->al, &K->d16p, sizeof(short) * m) != hipSuccess)
             return fail(ctx, NN_EOOM, "paired offsets allocation");
         launch_pair_d16(ctx, K, K->sl_d16, K->d16p);
     }
-    if (K->val32 && !K->val32p) {
-        if (dev_malloc(K->al, &K->val32p, sizeof(float) * m) != hipSuccess)
-            return fail(ctx, NN_EOOM, "paired float32 allocation");
-        launch_pair_f32(ctx, K, K->val32, K->val32p);
+    if (K->val32 && !K->val32q) {
+        if (!K->d16q) {
+            if (dev_malloc(K->al, &K->d16q, sizeof(short) * m) != hipSuccess)
+                return fail(ctx, NN_EOOM, "quad offsets allocation");
+            launch_quad_d16(ctx, K, K->sl_d16, K->d16q);
+        }
+        if (dev_malloc(K->al, &K->val32q, sizeof(float) * m) != hipSuccess)
+            return fail(ctx, NN_EOOM, "quad float32 allocation");
+        launch_quad_f32(ctx, K, K->val32, K->val32q);
     }
     if (f64 && !K->val64p) {
         if (dev_malloc(K->al, &K->val64p, sizeof(double) * m) != hipSuccess)
@@ -199,10 +204,10 @@ nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, boo
     const int64_t n = K->n;
     if (n == 0) return NN_OK;
     const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
-    const bool want32p = paired && mixed && K->sl_d16;
+    const bool want32q = paired && mixed && K->sl_d16;
     const bool want64p = paired && !mixed && NNQP_PAIR_F64 && K->sl_d16;
     const bool fresh = K->kt && K->kt_dt == dt;
-    if (fresh && (!mixed || K->kt32) && (!want32p || K->kt32p) && (!want64p || K->kt64p))
+    if (fresh && (!mixed || K->kt32) && (!want32q || K->kt32q) && (!want64p || K->kt64p))
         return NN_OK;
     // each buffer is guarded on its own: a call that got one of them and was
     // refused the other leaves the first in place, and a later call takes
@@ -213,15 +218,20 @@ nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, boo
         return fail(ctx, NN_EOOM, "transient diagonal allocation");
     if (mixed && !K->kt32 && dev_malloc(K->al, &K->kt32, sizeof(float) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient float32 allocation");
-    if ((want32p || want64p) && ensure_paired(ctx, K, false) != NN_OK) return NN_EOOM;
-    if (want32p && !K->kt32p && dev_malloc(K->al, &K->kt32p, sizeof(float) * m) != hipSuccess)
+    if (want64p && ensure_paired(ctx, K, false) != NN_OK) return NN_EOOM;
+    if (want32q && !K->d16q) {
+        if (dev_malloc(K->al, &K->d16q, sizeof(short) * m) != hipSuccess)
+            return fail(ctx, NN_EOOM, "quad offsets allocation");
+        launch_quad_d16(ctx, K, K->sl_d16, K->d16q);
+    }
+    if (want32q && !K->kt32q && dev_malloc(K->al, &K->kt32q, sizeof(float) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient float32 allocation");
     if (want64p && !K->kt64p && dev_malloc(K->al, &K->kt64p, sizeof(double) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient paired float64 allocation");
     launch_axpby_vals(ctx, K->nsell, K->mval, dt, K->val, K->kt);
     launch_diag(ctx, K, K->kt, K->kt_diag);
     if (K->kt32) launch_to_f32(ctx, K->nsell, K->kt, K->kt32);
-    if (K->kt32 && K->kt32p) launch_pair_f32(ctx, K, K->kt32, K->kt32p);
+    if (K->kt32 && K->kt32q) launch_quad_f32(ctx, K, K->kt32, K->kt32q);
     if (K->kt64p) launch_pair_f64(ctx, K, K->kt, K->kt64p);
     NN_HIP_TRY(ctx, hipGetLastError());
     K->kt_dt = dt;
@@ -530,8 +540,9 @@ nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes)
     if (precision == NN_MIXED) b += 4.0 * ns + 40.0 * n;    // float32 values and vectors
     // paired copies already made by single-problem solves
     if (A->d16p) b += 2.0 * ns;
-    if (A->val32p) b += 4.0 * ns;
-    if (A->kt32p) b += 4.0 * ns;
+    if (A->d16q) b += 2.0 * ns;
+    if (A->val32q) b += 4.0 * ns;
+    if (A->kt32q) b += 4.0 * ns;
     if (A->val64p) b += 8.0 * ns;
     if (A->kt64p) b += 8.0 * ns;
     *bytes = (size_t)b;
@@ -547,12 +558,13 @@ void nn_matrix_free(nn_ctx *ctx, nn_matrix *A)
         dev_free(A->al, p);
     dev_free(A->al, A->sl_d16);
     dev_free(A->al, A->d16p);
+    dev_free(A->al, A->d16q);
     dev_free(A->al, A->val64p);
     dev_free(A->al, A->kt64p);
     double *dv[] = {A->val, A->mval, A->diag, A->kt, A->kt_diag};
     for (double *p : dv)
         dev_free(A->al, p);
-    float *fv[] = {A->val32, A->kt32, A->val32p, A->kt32p};
+    float *fv[] = {A->val32, A->kt32, A->val32q, A->kt32q};
     for (float *p : fv)
         dev_free(A->al, p);
     delete A;
@@ -610,7 +622,7 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
     // paired copies for the CG and search passes (when the int16 offsets exist)
     const bool pair64 = NNQP_PAIR_F64 && v32 == nullptr;
     if ((v32 || pair64) && (st = ensure_paired(ctx, K, pair64)) != NN_OK) return st;
-    return solve_impl(ctx, K, K->val, v32, v32 ? K->val32p : nullptr, v32 ? nullptr : K->val64p,
+    return solve_impl(ctx, K, K->val, v32, v32 ? K->val32q : nullptr, v32 ? nullptr : K->val64p,
                       K->diag, f_dev, opts, c_dev, active_dev, stats);
 }
 
@@ -649,7 +661,7 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
     if ((st = choose_solo(ctx, K, &o)) == NN_OK)
         return solo_solve_impl(ctx, K, K->kt, K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev, stats);
     if (st != NN_EMAXIT) return st;
-    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32p : nullptr,
+    return solve_impl(ctx, K, K->kt, mixed ? K->kt32 : nullptr, mixed ? K->kt32q : nullptr,
                       mixed ? nullptr : K->kt64p, K->kt_diag, ctx->ws.ft, &o, c_dev, active_dev,
                       stats);
 }

@@ -540,6 +540,28 @@ __global__ __launch_bounds__(kBlock) void k_pair(Part P, const int *__restrict__
     }
 }
 
+// Quad copy of a sliced-ELL array (the layout of nn_matrix::d16q): within
+// slice s of width w, entry k of lane l moves to off + 256 (k / 4) + 4 l + k % 4
+// for k < 4 (w / 4); the next two, if there are two left, to
+// off + 256 (w / 4) + 2 l + (k - 4 (w / 4)); an odd last one stays.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_quad(Part P, const int *__restrict__ so,
+                                                 const T *__restrict__ src, T *__restrict__ dst)
+{
+    const int lane = threadIdx.x & 63, wid = wave_id();
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += P.nb * kWaves) {
+        const int off = so[s], w = (so[s + 1] - off) / kSlice;
+        const int nq = w / 4, np = (w - 4 * nq) / 2;
+        for (int k = 0; k < w; k++) {
+            const int from = off + k * kSlice + lane;
+            int to = from;
+            if (k < 4 * nq) to = off + (k / 4) * 4 * kSlice + 4 * lane + (k & 3);
+            else if (k < 4 * nq + 2 * np) to = off + nq * 4 * kSlice + 2 * lane + (k - 4 * nq);
+            dst[to] = src[from];
+        }
+    }
+}
+
 // float32 copy of a value array (round to nearest)
 __global__ __launch_bounds__(kBlock) void k_to_f32(int64_t m, const double *__restrict__ a,
                                                    float *__restrict__ b)
@@ -679,14 +701,14 @@ void launch_trial(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double *
                   double t, const double *g, const uint8_t *mask, double *ks, Box B)
 {
     Part P = make_part(A->n);
-    if (V.v32p && A->d16p) {
-        const ColsD16P cols{A->d16p};
+    if (V.v32q && A->d16q) {
+        const ColsD16Q cols{A->d16q};
         if (d.f32)
-            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsD16P>), P.nb, P, A->sl_off, cols,
-                          V.v32p, c, d.f32, t, g, mask, ks, ctx->partials, B);
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, float, ColsD16Q>), P.nb, P, A->sl_off, cols,
+                          V.v32q, c, d.f32, t, g, mask, ks, ctx->partials, B);
         else
-            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsD16P>), P.nb, P, A->sl_off, cols,
-                          V.v32p, c, d.f64, t, g, mask, ks, ctx->partials, B);
+            NN_DISPATCH_W(A->wmax, (k_trial<WM, float, double, ColsD16Q>), P.nb, P, A->sl_off, cols,
+                          V.v32q, c, d.f64, t, g, mask, ks, ctx->partials, B);
     } else if (V.v32 && A->sl_d16) {
         const ColsD16 cols{A->sl_d16};
         if (d.f32)
@@ -821,9 +843,9 @@ static void cg_spmv_tr(nn_ctx *ctx, const nn_matrix *A, const Vals &V, int j, in
 {
     Part P = make_part(A->n);
     Workspace &W = ctx->ws;
-    if (V.v32p && A->d16p) {
-        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16P, TR>), P.nb, P, A->sl_off,
-                      ColsD16P{A->d16p}, V.v32p, W.mask, W.z32, W.p32, W.q32, W.w32,
+    if (V.v32q && A->d16q) {
+        NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16Q, TR>), P.nb, P, A->sl_off,
+                      ColsD16Q{A->d16q}, V.v32q, W.mask, W.z32, W.p32, W.q32, W.w32,
                       ctx->partials, ctx->scal, j, max_it, rtol * rtol);
     } else if (V.v32 && A->sl_d16) {
         NN_DISPATCH_W(A->wmax, (k_cg_spmv<WM, float, float, ColsD16, TR>), P.nb, P, A->sl_off,
@@ -882,10 +904,16 @@ void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const dou
         k_breakpoint<double><<<P.nb, kBlock, 0, ctx->stream>>>(P, c, w.f64, g, ctx->partials, B);
 }
 
-void launch_pair_f32(nn_ctx *ctx, const nn_matrix *A, const float *src, float *dst)
+void launch_quad_f32(nn_ctx *ctx, const nn_matrix *A, const float *src, float *dst)
 {
     Part P = make_part(A->n);
-    k_pair<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, src, dst);
+    k_quad<float><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, src, dst);
+}
+
+void launch_quad_d16(nn_ctx *ctx, const nn_matrix *A, const short *src, short *dst)
+{
+    Part P = make_part(A->n);
+    k_quad<short><<<P.nb, kBlock, 0, ctx->stream>>>(P, A->sl_off, src, dst);
 }
 
 void launch_pair_f64(nn_ctx *ctx, const nn_matrix *A, const double *src, double *dst)

@@ -103,7 +103,7 @@ struct LmWork {
 struct Vals {
     const double *v64 = nullptr;
     const float *v32 = nullptr;
-    const float *v32p = nullptr;   // v32 in the paired layout (with A->d16p), or null
+    const float *v32q = nullptr;   // v32 in the quad layout (with A->d16q), or null
     const double *v64p = nullptr;  // v64 in the paired layout (with A->d16p), or null
 };
 
@@ -164,10 +164,15 @@ struct nn_matrix {
     // row sit side by side (one 8- or 16-byte value load and one 4-byte offset
     // load per pair); an odd last column keeps its place.
     short *d16p = nullptr;
-    float *val32p = nullptr;
-    float *kt32p = nullptr;
     double *val64p = nullptr;
     double *kt64p = nullptr;
+    // Quad copies for the float32 CG and search passes (made when sl_d16
+    // exists): entries 4k .. 4k+3 of a row side by side (one 16-byte value
+    // load, one 8-byte offset load), two left-over entries as a pair, an odd
+    // last one in place.
+    short *d16q = nullptr;
+    float *val32q = nullptr;
+    float *kt32q = nullptr;
     double *val = nullptr;     // K values, sliced-ELL order [nsell]
     double *mval = nullptr;    // M values, sliced-ELL order (or null)
     double *diag = nullptr;    // diag(K)
@@ -322,9 +327,11 @@ void launch_breakpoint(nn_ctx *ctx, int64_t n, const double *c, Dir w, const dou
 // b = (float)a
 void launch_to_f32(nn_ctx *ctx, int64_t m, const double *a, float *b);
 // paired copies of a sliced-ELL array of A (layout of nn_matrix::d16p)
-void launch_pair_f32(nn_ctx *ctx, const nn_matrix *A, const float *src, float *dst);
 void launch_pair_d16(nn_ctx *ctx, const nn_matrix *A, const short *src, short *dst);
 void launch_pair_f64(nn_ctx *ctx, const nn_matrix *A, const double *src, double *dst);
+// quad copies (layout of nn_matrix::d16q)
+void launch_quad_f32(nn_ctx *ctx, const nn_matrix *A, const float *src, float *dst);
+void launch_quad_d16(nn_ctx *ctx, const nn_matrix *A, const short *src, short *dst);
 // active = 1 where c == lo, 2 where c == hi, else 0
 void launch_active(nn_ctx *ctx, int64_t n, const double *c, uint8_t *active, Box B);
 // out = m/dt + k
@@ -347,10 +354,10 @@ nn_status assemble_impl(nn_ctx *ctx, const nn_mesh *mesh, const double *D, int64
 
 // ---------------------------------------------------------------- solver (solver.hip)
 // vals: float64 values (gradient, always); vals32: float32 values for the
-// searches and the inner CG (mixed precision) or null; vals32p / vals64p: the
-// same in the paired layout, or null.
+// searches and the inner CG (mixed precision) or null; vals32q: the same in
+// the quad layout, or null; vals64p: vals in the paired layout, or null.
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
-                     const float *vals32p, const double *vals64p, const double *diag,
+                     const float *vals32q, const double *vals64p, const double *diag,
                      const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st);
 
 nn_status finish_matrix(nn_ctx *ctx, nn_matrix *A);

@@ -150,7 +150,7 @@ extern "C" nn_status nn_solve_nonneg_noalloc(nn_ctx *ctx, nn_matrix *K, const do
     const bool prof = ctx->prof;
     ctx->prof = false;
     const nn_status rc =
-        solve_impl(ctx, K, K->val, mixed ? K->val32 : nullptr, mixed ? K->val32p : nullptr,
+        solve_impl(ctx, K, K->val, mixed ? K->val32 : nullptr, mixed ? K->val32q : nullptr,
                    mixed ? nullptr : K->val64p, K->diag, f_dev, opts, c_dev, active_dev, stats);
     ctx->prof = prof;
     std::swap(ctx->scal, scal);

@@ -140,6 +140,11 @@ struct ColsD16P {
     const short *d;
     __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
 };
+// int16 offsets in the quad layout (see nn_matrix::d16q)
+struct ColsD16Q {
+    const short *d;
+    __device__ __forceinline__ int operator()(int e, int row) const { return row + (int)d[e]; }
+};
 
 // Matrix values are read once per pass.  Float64 values are loaded with the
 // non-temporal hint, which keeps the value stream from displacing the
@@ -239,6 +244,83 @@ __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__res
     }
 }
 
+// Quad layout of float32 values (ColsD16Q): the entries 4k .. 4k+3 of the
+// row of lane l sit at off + 256 k + 4 l, so one 16-byte load brings four
+// values and one 8-byte load their four offsets; two entries left over sit
+// as a pair at off + 256 (w / 4) + 2 l, and an odd last one keeps its
+// column-major place.  A 3D row of 15 entries takes five value loads (three
+// quads, a pair, a single) instead of eight in the paired layout: the
+// float32 passes are bound by load instructions more than by bytes.
+template <int WMAX, class VT, class Act, class Pre, class X, class Epi>
+__device__ __forceinline__ void sell_rows_quad(const Part &P, const int *__restrict__ so,
+                                               ColsD16Q sc, const VT *__restrict__ sv, Act active,
+                                               Pre pre, X x, Epi epi)
+{
+    static_assert(sizeof(VT) == 4, "the quad layout holds float32 values");
+    using PV = decltype(pre(0));
+    const int lane = threadIdx.x & 63, wid = wave_id();
+    const int nw = P.nb * kWaves;
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += nw) {
+        const int off = so[s];
+        const int w = (so[s + 1] - off) >> 6;   // uniform in the wave
+        const int nq = w >> 2, rem = w & 3;
+        const int row = s * kSlice + lane;
+        const bool act = row < P.n && active(row);
+        const PV pv = act ? pre(row) : PV();
+        if (__ballot(act) == 0) continue;
+        double acc = 0.0;
+        constexpr int HQ = (WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE) / 4;   // quads per phase
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX / 4; h0 += HQ) {
+            int cc[4 * HQ];
+            float vv[4 * HQ];
+#pragma unroll
+            for (int k = 0; k < HQ; k++) {
+                if (h0 + k < nq) {
+                    const int e = off + (h0 + k) * 4 * kSlice + 4 * lane;
+                    const float4 v = *reinterpret_cast<const float4 *>(sv + e);
+                    const int2 d = *reinterpret_cast<const int2 *>(sc.d + e);
+                    vv[4 * k] = v.x;
+                    vv[4 * k + 1] = v.y;
+                    vv[4 * k + 2] = v.z;
+                    vv[4 * k + 3] = v.w;
+                    cc[4 * k] = row + (int)(short)(d.x & 0xffff);
+                    cc[4 * k + 1] = row + (d.x >> 16);
+                    cc[4 * k + 2] = row + (int)(short)(d.y & 0xffff);
+                    cc[4 * k + 3] = row + (d.y >> 16);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        cc[4 * k + q] = 0;
+                        vv[4 * k + q] = 0.f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4 * HQ; k++)
+                if (h0 + k / 4 < nq) acc += (double)vv[k] * x(cc[k]);
+        }
+        for (int k = WMAX / 4; k < nq; k++) {   // slices wider than the unrolled part
+            const int e = off + k * 4 * kSlice + 4 * lane;
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc += (double)ld_val(sv + e + q) * x(sc(e + q, row));
+        }
+        if (rem >= 2) {
+            const int e = off + nq * 4 * kSlice + 2 * lane;
+            float a, b;
+            ld_pair(sv + e, a, b);
+            const int d2 = *reinterpret_cast<const int *>(sc.d + e);
+            acc += (double)a * x(row + (int)(short)(d2 & 0xffff));
+            acc += (double)b * x(row + (d2 >> 16));
+        }
+        if (rem & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            acc += (double)ld_val(sv + e) * x(sc(e, row));
+        }
+        if (act) epi(row, acc, pv);
+    }
+}
+
 template <int WMAX, class VT, class Cols, class Act, class Pre, class X, class Epi>
 __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__ so, Cols sc,
                                           const VT *__restrict__ sv, Act active, Pre pre, X x,
@@ -246,6 +328,9 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
 {
     if constexpr (std::is_same<Cols, ColsD16P>::value) {
         sell_rows_paired<WMAX>(P, so, sc, sv, active, pre, x, epi);
+        return;
+    } else if constexpr (std::is_same<Cols, ColsD16Q>::value) {
+        sell_rows_quad<WMAX>(P, so, sc, sv, active, pre, x, epi);
         return;
     } else {
     constexpr int NS = NNQP_SLICES_IN_FLIGHT;

@@ -144,7 +144,7 @@ static nn_status read_grad_and_ladder(nn_ctx *ctx, int64_t n, double *grad, doub
 }
 
 nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const float *vals32,
-                     const float *vals32p, const double *vals64p, const double *diag,
+                     const float *vals32q, const double *vals64p, const double *diag,
                      const double *f, const nn_opts *o, double *c, uint8_t *active, nn_stats *st)
 {
     const int64_t n = A->n;
@@ -182,7 +182,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
     Vals VS;
     if (mixed) {
         VS.v32 = vals32;
-        VS.v32p = (vals32p && A->d16p) ? vals32p : nullptr;
+        VS.v32q = (vals32q && A->d16q) ? vals32q : nullptr;
     } else {
         VS.v64 = vals;
         VS.v64p = (vals64p && A->d16p) ? vals64p : nullptr;
