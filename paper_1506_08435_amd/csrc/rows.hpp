@@ -251,6 +251,31 @@ __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__res
 // column-major place.  A 3D row of 15 entries takes five value loads (three
 // quads, a pair, a single) instead of eight in the paired layout: the
 // float32 passes are bound by load instructions more than by bytes.
+// Entries per load phase of the quad walker, and the non-temporal hint on its
+// loads (bit 0: values, bit 1: offsets).  On the 128^3 float32 CG pass (per
+// launch): 8 entries, no hint 49.3 us; 4 entries 50.1 us; 16 entries 71.6 us
+// (80 VGPRs, six waves per SIMD); hint on values 55.7 us, on both 59.1 us.
+#ifndef NNQP_QUAD_PHASE
+#define NNQP_QUAD_PHASE NNQP_LOAD_PHASE
+#endif
+#ifndef NNQP_QUAD_NT
+#define NNQP_QUAD_NT 0
+#endif
+__device__ __forceinline__ float4 ld_quad(const float *p)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 *q = reinterpret_cast<const f4 *>(p);
+    const f4 v = (NNQP_QUAD_NT & 1) ? __builtin_nontemporal_load(q) : *q;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int2 ld_quad_d(const short *p)
+{
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    const i2 *q = reinterpret_cast<const i2 *>(p);
+    const i2 v = (NNQP_QUAD_NT & 2) ? __builtin_nontemporal_load(q) : *q;
+    return make_int2(v.x, v.y);
+}
+
 template <int WMAX, class VT, class Act, class Pre, class X, class Epi>
 __device__ __forceinline__ void sell_rows_quad(const Part &P, const int *__restrict__ so,
                                                ColsD16Q sc, const VT *__restrict__ sv, Act active,
@@ -269,7 +294,7 @@ __device__ __forceinline__ void sell_rows_quad(const Part &P, const int *__restr
         const PV pv = act ? pre(row) : PV();
         if (__ballot(act) == 0) continue;
         double acc = 0.0;
-        constexpr int HQ = (WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE) / 4;   // quads per phase
+        constexpr int HQ = (WMAX < NNQP_QUAD_PHASE ? WMAX : NNQP_QUAD_PHASE) / 4;   // quads per phase
 #pragma unroll
         for (int h0 = 0; h0 < WMAX / 4; h0 += HQ) {
             int cc[4 * HQ];
@@ -278,8 +303,8 @@ __device__ __forceinline__ void sell_rows_quad(const Part &P, const int *__restr
             for (int k = 0; k < HQ; k++) {
                 if (h0 + k < nq) {
                     const int e = off + (h0 + k) * 4 * kSlice + 4 * lane;
-                    const float4 v = *reinterpret_cast<const float4 *>(sv + e);
-                    const int2 d = *reinterpret_cast<const int2 *>(sc.d + e);
+                    const float4 v = ld_quad(sv + e);
+                    const int2 d = ld_quad_d(sc.d + e);
                     vv[4 * k] = v.x;
                     vv[4 * k + 1] = v.y;
                     vv[4 * k + 2] = v.z;
