@@ -111,6 +111,8 @@ def cpu_baseline(n_side: int, threads: int, single_n: int = 32):
     from paper_1506_08435_amd import workloads as W
     if threads > 0:
         oracle.set_num_threads(threads)
+    # a full-size run takes minutes: the oracle reports its own progress
+    oracle.set_progress(30.0 if n_side >= 96 else 0.0)
     p = W.cube3d(n_side)
     S = oracle.assemble(p)
     r = oracle.solve(S, tol=1e-8)
@@ -128,6 +130,35 @@ def cpu_baseline(n_side: int, threads: int, single_n: int = 32):
         out["single_thread"] = {"value": S1.n / r1.seconds, "unit": "DOF/s", "cores": 1,
                                 "sample": f"{single_n}^3 cells ({S1.n} free DOF): {r1.seconds:.2f} s"}
     return out
+
+
+def recorded_cpu_baseline(n_side: int = 128):
+    """The oracle's full-size run on the same host type, as recorded in
+    profiles/oracle_cube3d_<n>.txt by `bench.py --workload cpu --cpu-n <n>`
+    (minutes of CPU time, so it is not repeated inside every bench run), or
+    None when no record exists."""
+    path = os.path.join(ROOT, "profiles", f"oracle_cube3d_{n_side}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        return {"value": float(vals["dof_per_s"]), "unit": "DOF/s", "cores": int(vals["threads"]),
+                "kind": "oracle", "recorded": True, "seconds": float(vals["seconds"]),
+                "sample": f"oracle GPCG + face solve, tol 1e-8, the full {n_side}^3 workload "
+                          f"({vals['free_dof']} free DOF), recorded in profiles/oracle_cube3d_{n_side}.txt"}
+    except (KeyError, ValueError):
+        return None
+
+
+def run_cpu(args):
+    """Only the CPU oracle on the cube workload (no GPU work)."""
+    out = cpu_baseline(args.cpu_n, int(os.environ.get("OMP_NUM_THREADS", "0") or 0), single_n=0)
+    return {"metric": "oracle solved DOF/s on the host cores", "workload": f"cube3d_{args.cpu_n}",
+            "n_gpus": 0, "cpu_baseline": out}
 
 
 def triad_gbs(torch) -> float:
@@ -480,7 +511,7 @@ def main():
     ap.add_argument("--cg-chunk", type=int, default=16,
                     help="CG iterations between convergence reads (0: adaptive first chunk)")
     ap.add_argument("--engine", type=int, choices=[0, 1, 2], default=0,
-                    help="single-problem solves: 0 = by size (one workgroup up to 16,384 rows), "
+                    help="single-problem solves: 0 = by size (one workgroup up to 4,096 rows), "
                          "1 = multi-block passes, 2 = one workgroup")
     ap.add_argument("--precond-degree", type=int, default=1,
                     help="inner CG preconditioner: 1 = Jacobi, k > 1 = Chebyshev of degree k")
@@ -492,7 +523,7 @@ def main():
     ap.add_argument("--verbose", action="store_true", help="per-outer-iteration trace on stderr")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three 512 MiB device-to-device copies first (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["cube", "small", "transient", "batch", "serve", "hole"],
+    ap.add_argument("--workload", choices=["cube", "small", "transient", "batch", "serve", "hole", "cpu"],
                     default="cube")
     ap.add_argument("--hole-k", type=int, default=14,
                     help="cube-with-hole workload: 9k cells per side (k = 14: about 2M DOF)")
@@ -550,7 +581,7 @@ def main():
         del a, b
 
     single = {"transient": run_transient, "batch": run_batch, "serve": run_serve,
-              "small": run_small, "hole": run_hole}
+              "small": run_small, "hole": run_hole, "cpu": run_cpu}
     if args.workload in single:
         line = single[args.workload](args)
         if line is not None:
@@ -647,6 +678,9 @@ def main():
     del ctx
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, int(os.environ.get("OMP_NUM_THREADS", "0") or 0))
+        full = recorded_cpu_baseline(args.n)
+        if full is not None:
+            out["cpu_baseline"]["full_size_recorded"] = full
     # the other workloads of the metric, each in its own section: the small
     # 2D solve (latency), the heterogeneous transient run, the 512-member
     # batch and the served stream (p50/p99), FP64 and mixed precision

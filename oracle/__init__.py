@@ -62,6 +62,7 @@ def _load():
     lib.or_spmv.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, _f64p]
     lib.or_kkt.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, ctypes.c_double,
                            ctypes.c_double, _f64p, _f64p]
+    lib.or_set_progress.argtypes = [ctypes.c_double]
     lib.or_solve.restype = ctypes.c_int
     lib.or_solve.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, ctypes.c_int64, _f64p,
@@ -272,6 +273,11 @@ def num_threads() -> int:
 
 def set_num_threads(t: int) -> None:
     _load().or_set_num_threads(int(t))
+
+
+def set_progress(seconds: float) -> None:
+    """Progress lines on stderr, at most one every `seconds` (0: none)."""
+    _load().or_set_progress(float(seconds))
 
 
 def nondegenerate_masks(c_ref: np.ndarray, g_ref: np.ndarray, F: np.ndarray, rel: float = 1e-8,

@@ -33,8 +33,10 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -45,6 +47,34 @@
 #define OR_ENOMEM 2
 #define OR_EDEGEN 3
 #define OR_ENOCONV 4
+
+/* Progress lines on stderr for long runs: at most one every g_progress
+ * seconds (0: none).  They report, they change nothing. */
+static double g_progress = 0.0;
+static double g_last_report = 0.0;
+
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+static void report(const char *phase, int64_t k, double r)
+{
+    if (!(g_progress > 0.0)) return;
+    const double now = wall_seconds();
+    if (now - g_last_report < g_progress) return;
+    g_last_report = now;
+    fprintf(stderr, "oracle: %s %lld r %.3e\n", phase, (long long)k, r);
+    fflush(stderr);
+}
+
+void or_set_progress(double seconds)
+{
+    g_progress = seconds;
+    g_last_report = wall_seconds();
+}
 
 /* ------------------------------------------------------------------ */
 /* P1 element quantities (Sec. 2.1.3: P^k spaces with k = 1)           */
@@ -505,6 +535,7 @@ static int64_t pcg_face(const qp_t *Q, const uint8_t *mask, const double *b, dou
         if (rn < best * 0.999) { best = rn; since_best = 0; }
         else if (++since_best >= 3) break;
         if (rn <= atol) break;
+        report("face solve iteration", it, rn);
         for (int64_t i = 0; i < n; i++) { z[i] = dinv[i] * r[i]; p[i] = z[i]; }
         double rz = dot(n, r, z);
         for (int64_t j = 0; j < restart && it < maxit; j++, it++) {
@@ -618,6 +649,7 @@ int or_solve(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, c
         st->outer = outer + 1;
         double rel = pg_norm(&Q, c, g) / nf;
         st->r = rel;
+        report("outer iteration", outer, rel);
         /* Near the rounding floor of the residual the iteration stops
          * gaining: once r is below that floor and has not halved for thirty
          * iterations, the face solve and certificate take over (they accept
