@@ -200,7 +200,55 @@ __device__ __forceinline__ void for_bslices(const BDev &B, const int (&ops)[NV],
 // kernels): int32 columns, or int16 offsets from the row (float32 values,
 // when every member has them).  Float64 values load with the non-temporal
 // hint, float32 values normally (as in the single-problem kernels).
-enum { CM_I32 = 0, CM_D16 = 2 };
+enum { CM_I32 = 0, CM_D16 = 2, CM_Q4 = 3 };
+
+// Position of entry k of lane l in a slice of width w of the quad layout
+// (CM_Q4), relative to the slice's first entry: entries 4j .. 4j+3 of a row
+// side by side at 256 j + 4 l, two left over as a pair at 256 (w / 4) + 2 l,
+// an odd last one in its column-major place 64 k + l.  A row of seven
+// entries (2D P1) then takes three value loads and three offset loads
+// instead of seven of each.
+__host__ __device__ __forceinline__ int quad_pos(int k, int l, int w)
+{
+    const int nq = w >> 2, np = (w - 4 * nq) >> 1;
+    if (k < 4 * nq) return 256 * (k >> 2) + 4 * l + (k & 3);
+    if (k < 4 * nq + 2 * np) return 256 * nq + 2 * l + (k - 4 * nq);
+    return 64 * k + l;
+}
+
+// Four (quad) or two (pair) consecutive values of the quad layout, with the
+// same load hint as bld_val.
+__device__ __forceinline__ void bld_quad(const double *p, double (&v)[4])
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 a = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p));
+    const d2 b = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p + 2));
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
+__device__ __forceinline__ void bld_quad(const float *p, float (&v)[4])
+{
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+}
+__device__ __forceinline__ void bld_pair(const double *p, double &a, double &b)
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p));
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void bld_pair(const float *p, float &a, float &b)
+{
+    const float2 v = *reinterpret_cast<const float2 *>(p);
+    a = v.x;
+    b = v.y;
+}
 
 __device__ __forceinline__ double bld_val(const double *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float bld_val(const float *p) { return *p; }
@@ -262,10 +310,63 @@ __device__ __forceinline__ double gsell_row_at(const BDev &B, const VT *__restri
     const int *__restrict__ gc = B.gcol;
     const short *__restrict__ gd = B.gd16;
     auto col = [&](int e) {
-        if (CM == CM_D16) return i + (int)gd[e];
+        if (CM == CM_D16 || CM == CM_Q4) return i + (int)gd[e];
         return gc[e];
     };
     double acc = 0.0;
+    if constexpr (CM == CM_Q4) {
+        // quads in entry order, then the left-over pair, then the odd entry:
+        // the same sum order as the column-major walk
+        const int nq = w >> 2, rem = w & 3;
+        constexpr int HQ = (WMAX < 8 ? WMAX : 8) / 4;   // quads per load phase
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX / 4; h0 += HQ) {
+            int cc[4 * HQ];
+            VT vv[4 * HQ];
+#pragma unroll
+            for (int k = 0; k < HQ; k++) {
+                if (h0 + k < nq) {
+                    const int e = off + (h0 + k) * 4 * kSlice + 4 * lane;
+                    VT q[4];
+                    bld_quad(sv + e, q);
+                    const int2 d = *reinterpret_cast<const int2 *>(gd + e);
+                    cc[4 * k] = i + (int)(short)(d.x & 0xffff);
+                    cc[4 * k + 1] = i + (d.x >> 16);
+                    cc[4 * k + 2] = i + (int)(short)(d.y & 0xffff);
+                    cc[4 * k + 3] = i + (d.y >> 16);
+#pragma unroll
+                    for (int t = 0; t < 4; t++) vv[4 * k + t] = q[t];
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; t++) {
+                        cc[4 * k + t] = 0;
+                        vv[4 * k + t] = VT(0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4 * HQ; k++)
+                if (h0 + k / 4 < nq) acc += (double)vv[k] * x(cc[k]);
+        }
+        for (int k = WMAX / 4; k < nq; k++) {   // slices wider than the unrolled part
+            const int e = off + k * 4 * kSlice + 4 * lane;
+#pragma unroll
+            for (int t = 0; t < 4; t++) acc += (double)bld_val(sv + e + t) * x(col(e + t));
+        }
+        if (rem >= 2) {
+            const int e = off + nq * 4 * kSlice + 2 * lane;
+            VT a, b;
+            bld_pair(sv + e, a, b);
+            const int d2 = *reinterpret_cast<const int *>(gd + e);
+            acc += (double)a * x(i + (int)(short)(d2 & 0xffff));
+            acc += (double)b * x(i + (d2 >> 16));
+        }
+        if (rem & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            acc += (double)bld_val(sv + e) * x(col(e));
+        }
+        return acc;
+    }
     constexpr int H = WMAX < 8 ? WMAX : 8;
 #pragma unroll
     for (int h0 = 0; h0 < WMAX; h0 += H) {
@@ -321,7 +422,8 @@ __global__ void kb_recs(BDev B)
 // Copy the members into the concatenated layout (every slice of the batch):
 // c, f, diagonal and row lengths into the global vectors; slice offsets
 // (ebase[p] + the member's own offset), global columns, int16 offsets and
-// values into the global matrix arrays.  Rows past a member's end get c = 0,
+// values into the global matrix arrays, in the quad layout when int16
+// offsets are made (every member has them), else column-major.  Rows past a member's end get c = 0,
 // f = 0, diagonal 1, length 0; their entries keep their valid columns.
 __global__ void kb_gather(BDev B, const int64_t *__restrict__ ebase, int *__restrict__ gso,
                           int *__restrict__ gcol, short *__restrict__ gd16,
@@ -350,7 +452,8 @@ __global__ void kb_gather(BDev B, const int64_t *__restrict__ ebase, int *__rest
         const double *v64 = B.v64[p];
         const float *v32 = B.v32[p];
         for (int k = 0; k < w; k++) {
-            const int es = src + k * kSlice + lane, ed = dst + k * kSlice + lane;
+            const int es = src + k * kSlice + lane;
+            const int ed = dst + (gd16 ? quad_pos(k, lane, w) : k * kSlice + lane);
             gcol[ed] = sc[es] + r0;
             if (gd16) gd16[ed] = sd[es];
             gv64[ed] = v64[es];
@@ -416,7 +519,7 @@ __global__ void kb_transient_rhs(BDev B, double dt, double *__restrict__ ft)
 }
 
 // g = K c - f over the listed slices (the launch-shape tuner times this pass)
-template <int WMAX>
+template <int WMAX, int CM>
 __global__ void kb_grad(BDev B, double *__restrict__ g)
 {
     const int ops[1] = {OP_SUM};
@@ -424,7 +527,7 @@ __global__ void kb_grad(BDev B, double *__restrict__ g)
                    [&](int, int s, int i, int, bool row, double (&a)[1]) {
                        const double *c = B.cg;
                        const double kc =
-                           gsell_row<WMAX, CM_I32>(B, B.gv64, s, i, [&](int j) { return c[j]; });
+                           gsell_row<WMAX, CM>(B, B.gv64, s, i, [&](int j) { return c[j]; });
                        if (!row) return;
                        g[i] = kc - B.fg[i];
                        a[0] += g[i];
@@ -517,7 +620,7 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
         if (ph == PH_GRAD) {
             a[2] = -INFINITY;
             a[3] = INFINITY;
-            const double kc = gsell_row_at<WMAX, CM_I32>(B, B.gv64, i, off, wsl, [&](int j) { return c[j]; });
+            const double kc = gsell_row_at<WMAX, CM>(B, B.gv64, i, off, wsl, [&](int j) { return c[j]; });
             if (row) {
                 const double gi = kc - B.fg[i];
                 const double cv = c[i];
@@ -656,7 +759,7 @@ __global__ __launch_bounds__(kFinBlock) void kb_step1(BDev B)
     if (ph == PH_GRAD) {
         // gradient, KKT report, convergence test
         S.spmvs++;
-        S.bytes += 4.0 * (n + 1) + 12.0 * nnz + 32.0 * n;
+        S.bytes += 4.0 * (n + 1) + (S.ib + 8.0) * nnz + 32.0 * n;
         if (a[1] != 0.0) {
             S.status = NN_ENONFINITE;
             S.phase = PH_DONE;
@@ -1074,7 +1177,7 @@ double row_bytes(const BState &S)
     const double n = S.n, nnz = S.nnz;
     switch (S.phase) {
     case PH_GRAD:
-        return 4.0 * (n + 1) + 12.0 * nnz + 32.0 * n;
+        return 4.0 * (n + 1) + (S.ib + 8.0) * nnz + 32.0 * n;
     case PH_CAUCHY:
     case PH_SEARCH:
         return 4.0 * (n + 1) + (S.ib + S.vb) * nnz + 32.0 * n;
@@ -1149,7 +1252,13 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     for (int p = 0; p < P; p++)
         if (K[p]->n > 0 && !K[p]->sl_d16) all_d16 = false;
     const double vb = mixed ? 4.0 : 8.0;                // bytes per CG vector entry and per value
-    const double ib = (mixed && all_d16) ? 2.0 : 4.0;   // bytes per column index
+    // Mixed precision reads the concatenated matrix in the quad layout (int16
+    // offsets, four float32 values per load): on the 512-member batch the row
+    // pass takes 67 instead of 107 us.  Float64 keeps int32 columns
+    // column-major: its quad layout (two 16-byte value loads per quad) was no
+    // faster, column-major int16 offsets slower.
+    const bool quad = mixed && all_d16;
+    const double ib = quad ? 2.0 : 4.0;   // bytes per column index
 
     // ---- tables, work vectors, lists, pinned state mirrors
     Arena A(ctx->al);
@@ -1184,7 +1293,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     int64_t *d_ebase = A.d<int64_t>(P);
     double *gv64 = A.d<double>(E);
     float *gv32 = mixed ? A.d<float>(E) : nullptr;
-    short *gd16 = (mixed && all_d16) ? A.d<short>(E) : nullptr;
+    short *gd16 = quad ? A.d<short>(E) : nullptr;
     BVec<double> V64{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     BVec<float> V32{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (mixed) {
@@ -1436,10 +1545,12 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                 if (blk * per_cu > 4096) continue;
                 const Shape cand{blk, per_cu};
                 const int gsz = grid_for(cand, n_sl);
-                NN_BDISPATCH(wmax, (kb_grad<WM>), gsz, blk, st, B, g);   // warm-up
+                if (quad) NN_BDISPATCH(wmax, (kb_grad<WM, CM_Q4>), gsz, blk, st, B, g);   // warm-up
+                else NN_BDISPATCH(wmax, (kb_grad<WM, CM_I32>), gsz, blk, st, B, g);
                 NN_HIP_TRY(ctx, hipEventRecord(t0, st));
                 for (int rep = 0; rep < 3; rep++)
-                    NN_BDISPATCH(wmax, (kb_grad<WM>), gsz, blk, st, B, g);
+                    if (quad) NN_BDISPATCH(wmax, (kb_grad<WM, CM_Q4>), gsz, blk, st, B, g);
+                    else NN_BDISPATCH(wmax, (kb_grad<WM, CM_I32>), gsz, blk, st, B, g);
                 NN_HIP_TRY(ctx, hipEventRecord(t1, st));
                 NN_HIP_TRY(ctx, hipEventSynchronize(t1));
                 float ms = 0.f;
@@ -1466,8 +1577,8 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     // the row and vector passes optionally bracketed by timing events
     auto step = [&](hipStream_t s, int gr, int fg, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[0], s);
-        if (mixed && all_d16)
-            NN_BDISPATCH(wmax, (kb_rows<WM, CM_D16, float, float>), gr, blk, s, B,
+        if (quad)
+            NN_BDISPATCH(wmax, (kb_rows<WM, CM_Q4, float, float>), gr, blk, s, B,
                          (const float *)gv32, V32);
         else if (mixed)
             NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, float, float>), gr, blk, s, B,
