@@ -567,6 +567,38 @@ def test_batch_mixed_precision_matches_oracle(ctx, batch_members):
         print(f"mixed {p.name}: err={err:.2e} refinements={s['refinements']}")
 
 
+def test_batch_mixed_layouts_agree(ctx, batch_members):
+    """Mixed precision reads the batch's concatenated matrix in the quad
+    layout when every member has int16 offsets, else column-major with
+    int32 columns.  Both sum each row in column order, so a member's result
+    is bitwise the same in either; the member whose offsets exceed int16 is
+    checked against the oracle."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    _, Ks, Fs, _ = batch_members
+    cells = (185, 185, 3)
+    f = W.cell_box_indicator(cells, (69, 69, 0), (116, 116, 3))
+    p = W.box_problem("wide3d", cells, 1.0 / 185, W.aniso3d_tensor(), f_elem=f)
+    Kw, Fw, _ = ctx.assemble(p)
+    picks = [0, 3, 12]
+    quad, _, st_q, rc_q = ctx.solve_batch([Ks[k] for k in picks], [Fs[k] for k in picks],
+                                          tol=1e-10, precision=nnqp.NN_MIXED)
+    cm, _, st_c, rc_c = ctx.solve_batch([Ks[k] for k in picks] + [Kw],
+                                        [Fs[k] for k in picks] + [Fw],
+                                        tol=1e-10, precision=nnqp.NN_MIXED)
+    assert rc_q == 0 and rc_c == 0
+    for j, k in enumerate(picks):
+        assert torch.equal(quad[j], cm[j]), k
+        assert st_q[j]["cg_its"] == st_c[j]["cg_its"], k
+    S = oracle.assemble(p)
+    ref = oracle.solve(S, tol=1e-13)
+    c = _np(cm[len(picks)])
+    assert c.min() >= 0.0
+    err = np.abs(c - ref.c).max() / np.abs(ref.c).max()
+    print(f"wide3d in a mixed batch: err vs oracle {err:.2e}")
+    assert err <= MIXED_TOL, err
+
+
 def test_batch_edge_members(ctx, batch_members):
     """Empty batch; a member with no free DOF; a member with f <= 0 (exact
     zero); warm start from the solution (no outer iteration)."""
