@@ -119,7 +119,8 @@ def cpu_baseline(n_side: int, threads: int, single_n: int = 32):
     nthr = oracle.num_threads()
     out = {"value": S.n / r.seconds, "unit": "DOF/s", "cores": nthr, "kind": "oracle",
            "sample": (f"oracle GPCG + face solve, tol 1e-8, on the same workload at {n_side}^3 cells "
-                      f"({S.n} free DOF) instead of 128^3: {r.seconds:.2f} s"),
+                      f"({S.n} free DOF)" + (" instead of 128^3" if n_side != 128 else "")
+                      + f": {r.seconds:.2f} s"),
            "seconds": r.seconds, "cpu_model": cpu_model(),
            "affinity_cores": len(os.sched_getaffinity(0))}
     if single_n > 0:
