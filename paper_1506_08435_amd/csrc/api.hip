@@ -167,15 +167,23 @@ namespace nnqp {
 #define NNQP_PAIR_F64 1   // float64 solves read the paired layout when it exists
 #endif
 
+// The paired int16 offsets (nn_matrix::d16p) that every float64 paired copy
+// is read with.
+static nn_status ensure_d16p(nn_ctx *ctx, nn_matrix *K)
+{
+    if (K->d16p || !K->sl_d16 || K->n == 0) return NN_OK;
+    const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
+    if (dev_malloc(K->al, &K->d16p, sizeof(short) * m) != hipSuccess)
+        return fail(ctx, NN_EOOM, "paired offsets allocation");
+    launch_pair_d16(ctx, K, K->sl_d16, K->d16p);
+    return NN_OK;
+}
+
 nn_status ensure_paired(nn_ctx *ctx, nn_matrix *K, bool f64)
 {
     if (!K->sl_d16 || K->n == 0) return NN_OK;
     const size_t m = (size_t)std::max<int64_t>(K->nsell, 1);
-    if (f64 && !K->d16p) {
-        if (dev_malloc(K->al, &K->d16p, sizeof(short) * m) != hipSuccess)
-            return fail(ctx, NN_EOOM, "paired offsets allocation");
-        launch_pair_d16(ctx, K, K->sl_d16, K->d16p);
-    }
+    if (f64 && ensure_d16p(ctx, K) != NN_OK) return NN_EOOM;
     if (K->val32 && !K->val32q) {
         if (!K->d16q) {
             if (dev_malloc(K->al, &K->d16q, sizeof(short) * m) != hipSuccess)
@@ -218,7 +226,7 @@ nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, boo
         return fail(ctx, NN_EOOM, "transient diagonal allocation");
     if (mixed && !K->kt32 && dev_malloc(K->al, &K->kt32, sizeof(float) * m) != hipSuccess)
         return fail(ctx, NN_EOOM, "transient float32 allocation");
-    if (want64p && ensure_paired(ctx, K, false) != NN_OK) return NN_EOOM;
+    if (want64p && ensure_d16p(ctx, K) != NN_OK) return NN_EOOM;
     if (want32q && !K->d16q) {
         if (dev_malloc(K->al, &K->d16q, sizeof(short) * m) != hipSuccess)
             return fail(ctx, NN_EOOM, "quad offsets allocation");

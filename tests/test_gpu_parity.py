@@ -289,6 +289,27 @@ def test_transient_steps_match_oracle(ctx):
         c_ref = r.c
 
 
+def test_transient_steps_make_the_paired_copies(ctx):
+    """A float64 backward-Euler step reads the paired copy of M/dt + K (int16
+    offset pairs with value pairs), a mixed one the quad copy (int16 offsets
+    with float32 values): the matrix's reported device bytes grow by 10 and
+    then 6 bytes per sliced-ELL entry."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.config_transient3d(20, 18, 9, ell=3.0)
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    b0 = K.bytes(nnqp.NN_FP64)
+    c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    ctx.step_transient(K, 1e-3, F, c, tol=1e-8, engine=1)
+    b1 = K.bytes(nnqp.NN_FP64)
+    c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    ctx.step_transient(K, 1e-3, F, c, tol=1e-8, precision=nnqp.NN_MIXED)
+    b2 = K.bytes(nnqp.NN_FP64)
+    d64, d32 = b1 - b0, b2 - b1
+    assert d64 > 0 and d32 > 0, (b0, b1, b2)
+    assert 3 * d64 == 5 * d32, (d64, d32)
+
+
 # ---------------------------------------------------------------- full size (bench configuration)
 def test_full_size_cube128_certificate(ctx):
     """The 128^3 workload at the metric tolerance, in the launch configuration
