@@ -754,7 +754,10 @@ void launch_ladder(nn_ctx *ctx, const nn_matrix *A, const Vals &V, const double 
         L.t[k] = t[k];
         L.ks[k] = ks[k];
     }
-    if (V.v32 && A->sl_d16)
+    if (V.v32q && A->d16q)
+        NN_DISPATCH_W(A->wmax, (k_ladder<WM, float, ColsD16Q>), P.nb, P, A->sl_off,
+                      ColsD16Q{A->d16q}, V.v32q, c, g, L, B, ctx->partials);
+    else if (V.v32 && A->sl_d16)
         NN_DISPATCH_W(A->wmax, (k_ladder<WM, float, ColsD16>), P.nb, P, A->sl_off,
                       ColsD16{A->sl_d16}, V.v32, c, g, L, B, ctx->partials);
     else if (V.v32)

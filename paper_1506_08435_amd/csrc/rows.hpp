@@ -491,6 +491,96 @@ __device__ __forceinline__ void sell_rows_n_paired(const Part &P, const int *__r
     }
 }
 
+// sell_rows_n on the quad layout (see sell_rows_quad): PHASE / 4 quads per
+// load phase (at least one), entries in the same order, so the sums are the
+// same as on the column-major copy.
+template <int WMAX, int NT, class VT, class Pre, class X, class Epi, int PHASE>
+__device__ __forceinline__ void sell_rows_n_quad(const Part &P, const int *__restrict__ so,
+                                                 ColsD16Q sc, const VT *__restrict__ sv, Pre pre,
+                                                 X x, Epi epi)
+{
+    static_assert(sizeof(VT) == 4, "the quad layout holds float32 values");
+    using PV = decltype(pre(0));
+    const int lane = threadIdx.x & 63, wid = wave_id();
+    const int nw = P.nb * kWaves;
+    for (int s = blockIdx.x * kWaves + wid; s < P.nslices; s += nw) {
+        const int off = so[s];
+        const int w = (so[s + 1] - off) >> 6;
+        const int nq = w >> 2, rem = w & 3;
+        const int row = s * kSlice + lane;
+        const bool act = row < P.n;
+        const PV pv = act ? pre(row) : PV();
+        double acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[t] = 0.0;
+        constexpr int HP = WMAX < PHASE ? WMAX : PHASE;
+        constexpr int HQ = HP / 4 > 0 ? HP / 4 : 1;   // quads per phase
+        double xv[NT];
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX / 4; h0 += HQ) {
+            int cc[4 * HQ];
+            float vv[4 * HQ];
+#pragma unroll
+            for (int k = 0; k < HQ; k++) {
+                if (h0 + k < nq) {
+                    const int e = off + (h0 + k) * 4 * kSlice + 4 * lane;
+                    const float4 v = ld_quad(sv + e);
+                    const int2 d = ld_quad_d(sc.d + e);
+                    vv[4 * k] = v.x;
+                    vv[4 * k + 1] = v.y;
+                    vv[4 * k + 2] = v.z;
+                    vv[4 * k + 3] = v.w;
+                    cc[4 * k] = row + (int)(short)(d.x & 0xffff);
+                    cc[4 * k + 1] = row + (d.x >> 16);
+                    cc[4 * k + 2] = row + (int)(short)(d.y & 0xffff);
+                    cc[4 * k + 3] = row + (d.y >> 16);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        cc[4 * k + q] = 0;
+                        vv[4 * k + q] = 0.f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4 * HQ; k++)
+                if (h0 + k / 4 < nq) {
+                    x(cc[k], xv);
+#pragma unroll
+                    for (int t = 0; t < NT; t++) acc[t] += (double)vv[k] * xv[t];
+                }
+        }
+        for (int k = WMAX / 4; k < nq; k++)   // slices wider than the unrolled part
+            for (int q = 0; q < 4; q++) {
+                const int e = off + k * 4 * kSlice + 4 * lane + q;
+                x(sc(e, row), xv);
+                const double vk = (double)ld_val(sv + e);
+#pragma unroll
+                for (int t = 0; t < NT; t++) acc[t] += vk * xv[t];
+            }
+        if (rem >= 2) {
+            const int e = off + nq * 4 * kSlice + 2 * lane;
+            float a, b;
+            ld_pair(sv + e, a, b);
+            const int d2 = *reinterpret_cast<const int *>(sc.d + e);
+            x(row + (int)(short)(d2 & 0xffff), xv);
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t] += (double)a * xv[t];
+            x(row + (d2 >> 16), xv);
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t] += (double)b * xv[t];
+        }
+        if (rem & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            x(sc(e, row), xv);
+            const double vk = (double)ld_val(sv + e);
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t] += vk * xv[t];
+        }
+        if (act) epi(row, acc, pv);
+    }
+}
+
 template <int WMAX, int NT, class VT, class Cols, class Pre, class X, class Epi,
           int PHASE = NNQP_LOAD_PHASE>
 __device__ __forceinline__ void sell_rows_n(const Part &P, const int *__restrict__ so, Cols sc,
@@ -498,6 +588,9 @@ __device__ __forceinline__ void sell_rows_n(const Part &P, const int *__restrict
 {
     if constexpr (std::is_same<Cols, ColsD16P>::value) {
         sell_rows_n_paired<WMAX, NT, VT, Pre, X, Epi, PHASE>(P, so, sc, sv, pre, x, epi);
+        return;
+    } else if constexpr (std::is_same<Cols, ColsD16Q>::value) {
+        sell_rows_n_quad<WMAX, NT, VT, Pre, X, Epi, PHASE>(P, so, sc, sv, pre, x, epi);
         return;
     } else {
     using PV = decltype(pre(0));
