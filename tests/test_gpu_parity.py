@@ -289,6 +289,42 @@ def test_transient_steps_match_oracle(ctx):
         c_ref = r.c
 
 
+@pytest.mark.parametrize("ny,fits", [(258, True), (259, False)])
+def test_int16_offset_limit(ctx, batch_members, ny, fits):
+    """The widest coupling at the int16 limit: a 128 x ny x 3 Kuhn slab has
+    127 x (ny-1) x 2 free nodes and its widest offset 1 + 127 + 127 (ny-1)
+    is 32,767 for ny = 258 (int16 offsets kept: the paired, quad and batch
+    quad layouts decode the extreme offsets) and 32,894 for ny = 259 (int32
+    columns).  FP64, mixed and a mixed batch against the oracle."""
+    from paper_1506_08435_amd import nnqp
+    cells = (128, ny, 3)
+    f = W.cell_box_indicator(cells, (40, 80, 0), (88, 180, 3))
+    p = W.box_problem(f"slab_{ny}", cells, 1.0 / 128, W.aniso3d_tensor(), f_elem=f)
+    S = oracle.assemble(p)
+    span = int(np.abs(S.col.astype(np.int64) - np.repeat(np.arange(S.n), np.diff(S.rowptr))).max())
+    assert span == 1 + 127 + 127 * (ny - 1)
+    assert (span <= 32767) == fits
+    K, F, _ = ctx.assemble(p)
+    # the library's layout decision, from its reported bytes before any solve
+    b64, bmx = K.bytes(nnqp.NN_FP64), K.bytes(nnqp.NN_MIXED)
+    ns = (bmx - b64 - 40 * K.n) // 4
+    nsl = (K.n + 63) // 64
+    base = 4 * (K.n + 1) + 4 * K.nnz + 4 * (nsl + 1) + 12 * ns + 8 * K.n + 89 * K.n
+    assert b64 - base == (2 * ns if fits else 0), (b64, base, ns)
+    ref = oracle.solve(S, tol=1e-13)
+    assert ref.certified
+    c, active, st = ctx.solve_nonneg(K, F, tol=1e-12)
+    err = _check_solution(S, _np(c), _np(active), ref.c)
+    cm, _, _ = ctx.solve_nonneg(K, F, tol=1e-10, precision=nnqp.NN_MIXED)
+    errm = np.abs(_np(cm) - ref.c).max() / np.abs(ref.c).max()
+    _, Ks, Fs, _ = batch_members
+    cs, _, _, rc = ctx.solve_batch([Ks[0], K], [Fs[0], F], tol=1e-10, precision=nnqp.NN_MIXED)
+    assert rc == 0
+    errb = np.abs(_np(cs[1]) - ref.c).max() / np.abs(ref.c).max()
+    print(f"slab ny={ny}: n={S.n} span={span} err fp64 {err:.2e} mixed {errm:.2e} batch {errb:.2e}")
+    assert errm <= MIXED_TOL and errb <= MIXED_TOL
+
+
 def test_transient_steps_make_the_paired_copies(ctx):
     """A float64 backward-Euler step reads the paired copy of M/dt + K (int16
     offset pairs with value pairs), a mixed one the quad copy (int16 offsets
