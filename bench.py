@@ -239,7 +239,7 @@ def run_hole(args):
     act = torch.empty(n, dtype=torch.uint8, device=ctx.device)
     for _ in range(args.warmup):
         ctx.solve_nonneg(K, F, opts=opts, c=c, active=act)
-    ctx.set_profiling(not args.no_kernel_timing, ("cg_spmv",))
+    ctx.set_profiling(not args.no_kernel_timing, ("cg_spmv",), every=args.time_every)
     ctx.kernel_times(reset=True)
     stats = []
     torch.cuda.synchronize()
@@ -317,7 +317,8 @@ def run_transient(args):
         c = torch.zeros(n, dtype=torch.float64, device=ctx.device)
         ctx.step_transient(K, args.dt, F, c, opts=opts)          # warm-up (forms K~)
         c.zero_()
-        ctx.set_profiling(not args.no_kernel_timing, None if args.profile_all else ("cg_spmv",))
+        ctx.set_profiling(not args.no_kernel_timing, None if args.profile_all else ("cg_spmv",),
+                    every=args.time_every)
         ctx.kernel_times(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -338,7 +339,8 @@ def run_transient(args):
             "outer_its_total": sum(s["outer_its"] for s in per_step),
             "cg_its_total": sum(s["cg_its"] for s in per_step),
             "final_max_c": float(c.max()), "final_active": int(per_step[-1]["n_active"]),
-            "roofline": roofline_of(dom, "k_cg_spmv", read_traffic("k_cg_spmv", wl, prec_name))}
+            "roofline": roofline_of(dom, "k_cg_spmv", read_traffic("k_cg_spmv", wl, prec_name),
+                                    {"timed_one_launch_in": args.time_every})}
         finals[prec_name] = c.clone()
     line = {"metric": "solved DOF*steps/s, backward Euler, KKT tol 1e-8 per step",
             "workload": f"transient3d_{'x'.join(map(str, args.tdims))}: {n} free DOF, {K.nnz} nnz, "
@@ -519,6 +521,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=64, help="cube side of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--time-every", type=int, default=16,
+                    help="inside timed regions, time one CG launch in this many (the passes of a "
+                         "solve have one size; 1: every launch)")
     ap.add_argument("--profile-all", action="store_true",
                     help="time every kernel class inside the timed region (default: the CG matrix pass only)")
     ap.add_argument("--verbose", action="store_true", help="per-outer-iteration trace on stderr")
@@ -605,7 +610,8 @@ def main():
         ctx.solve_nonneg(K, F, opts=opts, c=c)
     # only the dominant kernel is bracketed by events unless asked otherwise:
     # fewer events, less perturbation of the timed solves
-    ctx.set_profiling(not args.no_kernel_timing, None if args.profile_all else ("cg_spmv",))
+    ctx.set_profiling(not args.no_kernel_timing, None if args.profile_all else ("cg_spmv",),
+                    every=args.time_every)
     ctx.kernel_times(reset=True)
     stats = []
     torch.cuda.synchronize()
@@ -624,7 +630,8 @@ def main():
     dom = kt["cg_spmv"]
     wl = f"cube3d_{args.n}"
     roofline = roofline_of(dom, "k_cg_spmv (CG matrix pass with fused direction update)",
-                           read_traffic("k_cg_spmv", wl, args.precision))
+                           read_traffic("k_cg_spmv", wl, args.precision),
+                           {"timed_one_launch_in": args.time_every})
     if not args.no_triad:
         tri = triad_gbs(torch)
         roofline["achievable_triad_GBps"] = round(tri, 1)
@@ -711,7 +718,7 @@ def run_cube_mixed(ctx, K, F, c, args):
                              subspace=args.subspace, cg_chunk=args.cg_chunk)
     cm = torch.empty_like(c)
     ctx.solve_nonneg(K, F, opts=opts, c=cm)              # warm-up (forms the float32 copies)
-    ctx.set_profiling(not args.no_kernel_timing, ("cg_spmv",))
+    ctx.set_profiling(not args.no_kernel_timing, ("cg_spmv",), every=args.time_every)
     ctx.kernel_times(reset=True)
     stats = []
     torch.cuda.synchronize()
@@ -730,7 +737,8 @@ def run_cube_mixed(ctx, K, F, c, args):
             "kkt_rel": stats[-1]["kkt_rel"],
             "rel_diff_vs_fp64": float((cm - c64).abs().max() / c64.abs().max()),
             "roofline": roofline_of(kt["cg_spmv"], "k_cg_spmv (float32 values and vectors)",
-                                    read_traffic("k_cg_spmv", f"cube3d_{args.n}", "mixed"))}
+                                    read_traffic("k_cg_spmv", f"cube3d_{args.n}", "mixed"),
+                                    {"timed_one_launch_in": args.time_every})}
 
 
 def run_galerkin(ctx, K, F, n, stats, args):

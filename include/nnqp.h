@@ -427,12 +427,20 @@ nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *
  * Classes: 0 CG SpMV (fused direction update), 1 CG vector update,
  * 2 gradient SpMV, 3 projected-step SpMV, 4 other.
  * nn_set_profiling: classes = 0 turns profiling off; otherwise bit k of
- * `classes` times class k (NN_PROF_ALL: every class).  Each timed launch is
- * bracketed by two events on the stream, so timing fewer classes perturbs a
- * timed run less. */
+ * `classes` times class k (NN_PROF_ALL: every class).  A timed launch of the
+ * CG classes (0, 1) records its kernel's own begin and end into two events
+ * (hipExtLaunchKernelGGL); a launch of the other classes is bracketed by two
+ * events on the stream.  Timing perturbs a timed run, less so for fewer
+ * classes. */
 #define NN_KCLASSES 5
 #define NN_PROF_ALL 0x1f
 nn_status nn_set_profiling(nn_ctx *ctx, int classes);
+/* Time one launch in `every` (>= 1; default 1: all) of each CG class (0, 1)
+ * while profiling is on; the other classes are always timed in full.  The CG
+ * launches of a solve are passes of the same size, so a systematic sample
+ * gives their average duration at a fraction of the timing overhead.
+ * NN_EINVAL for every < 1. */
+nn_status nn_set_profiling_sample(nn_ctx *ctx, int32_t every);
 /* counts/total_ms/total_bytes/total_bytes_csr: host arrays of NN_KCLASSES
  * entries or NULL.  total_bytes is the algorithmic (perfect-cache) byte count
  * of the timed launches for the layout the kernels read (int16 column offsets

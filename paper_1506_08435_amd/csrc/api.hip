@@ -108,9 +108,13 @@ static hipEvent_t pool_event(nn_ctx *ctx)
 void prof_begin(nn_ctx *ctx, int cls, double bytes, double bytes_csr)
 {
     ctx->prof_open = false;
+    ctx->prof_attach = false;
     if (!ctx->prof || !((ctx->prof_mask >> cls) & 1)) return;
+    const bool cg = cls == KC_CG_SPMV || cls == KC_CG_UPDATE;
+    if (cg && ctx->prof_every > 1 && ctx->prof_calls[cls]++ % ctx->prof_every != 0) return;
     ProfEntry p;
     p.cls = cls;
+    p.seq = ctx->prof_seq;
     p.a = pool_event(ctx);
     p.b = pool_event(ctx);
     p.bytes = bytes;
@@ -119,13 +123,28 @@ void prof_begin(nn_ctx *ctx, int cls, double bytes, double bytes_csr)
     (void)hipEventRecord(p.a, ctx->stream);
     ctx->prof_live.push_back(p);
     ctx->prof_open = true;
+    ctx->prof_attach = cg;
 }
 
 void prof_end(nn_ctx *ctx)
 {
+    ctx->prof_attach = false;
     if (!ctx->prof_open || ctx->prof_live.empty()) return;
     (void)hipEventRecord(ctx->prof_live.back().b, ctx->stream);
     ctx->prof_open = false;
+}
+
+bool prof_kernel_events(nn_ctx *ctx, hipEvent_t *a, hipEvent_t *b)
+{
+    if (!ctx->prof_attach || !ctx->prof_open || ctx->prof_live.empty()) return false;
+    ProfEntry &p = ctx->prof_live.back();
+    p.ka = pool_event(ctx);
+    p.kb = pool_event(ctx);
+    ctx->prof_attach = false;   // one kernel per entry
+    if (!p.ka || !p.kb) return false;
+    *a = p.ka;
+    *b = p.kb;
+    return true;
 }
 
 void prof_add(nn_ctx *ctx, int cls, double ms, double bytes, double bytes_csr)
@@ -144,7 +163,8 @@ void prof_collect(nn_ctx *ctx)
     for (ProfEntry &p : ctx->prof_live) {
         if (p.valid) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            const bool own = p.ka && p.kb;   // the kernel's own begin and end
+            if (hipEventElapsedTime(&ms, own ? p.ka : p.a, own ? p.kb : p.b) == hipSuccess) {
                 ctx->prof_count[p.cls]++;
                 ctx->prof_ms[p.cls] += ms;
                 ctx->prof_bytes[p.cls] += p.bytes > 0 ? p.bytes : 0.0;
@@ -153,6 +173,8 @@ void prof_collect(nn_ctx *ctx)
         }
         ctx->ev_pool.push_back(p.a);
         ctx->ev_pool.push_back(p.b);
+        if (p.ka) ctx->ev_pool.push_back(p.ka);
+        if (p.kb) ctx->ev_pool.push_back(p.kb);
     }
     ctx->prof_live.clear();
 }
@@ -373,6 +395,8 @@ void nn_destroy(nn_ctx *ctx)
     for (ProfEntry &p : ctx->prof_live) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
+        if (p.ka) (void)hipEventDestroy(p.ka);
+        if (p.kb) (void)hipEventDestroy(p.kb);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -791,6 +815,15 @@ nn_status nn_set_profiling(nn_ctx *ctx, int classes)
     NN_CHECK_CTX(ctx);
     ctx->prof = classes != 0;
     ctx->prof_mask = classes & NN_PROF_ALL;
+    return NN_OK;
+}
+
+nn_status nn_set_profiling_sample(nn_ctx *ctx, int32_t every)
+{
+    NN_CHECK_CTX(ctx);
+    if (every < 1) return fail(ctx, NN_EINVAL, "profiling sample interval must be >= 1");
+    ctx->prof_every = every;
+    for (int k = 0; k < NN_KCLASSES; k++) ctx->prof_calls[k] = 0;
     return NN_OK;
 }
 

@@ -1087,6 +1087,30 @@ std::mutex &shape_mutex()
 
 int width_class(int wmax) { return wmax <= 8 ? 8 : (wmax <= 16 ? 16 : 32); }
 
+// The same with the kernel's own begin and end recorded into e0, e1 when
+// they are not null (hipExtLaunchKernelGGL).
+#define NN_BLAUNCH_EV(KERNEL, grid, block, stream, e0, e1, ...)                                 \
+    do {                                                                                        \
+        if (e0)                                                                                 \
+            hipExtLaunchKernelGGL(KERNEL, dim3(grid), dim3(block), 0, stream, e0, e1, 0,         \
+                                  __VA_ARGS__);                                                 \
+        else                                                                                    \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(block), 0, stream, __VA_ARGS__);        \
+    } while (0)
+#define NN_BDISPATCH_EV(wmax, KERNEL, grid, block, stream, e0, e1, ...)                         \
+    do {                                                                                        \
+        if ((wmax) <= 8) {                                                                      \
+            constexpr int WM = 8;                                                               \
+            NN_BLAUNCH_EV(KERNEL, grid, block, stream, e0, e1, __VA_ARGS__);                    \
+        } else if ((wmax) <= 16) {                                                              \
+            constexpr int WM = 16;                                                              \
+            NN_BLAUNCH_EV(KERNEL, grid, block, stream, e0, e1, __VA_ARGS__);                    \
+        } else {                                                                                \
+            constexpr int WM = 32;                                                              \
+            NN_BLAUNCH_EV(KERNEL, grid, block, stream, e0, e1, __VA_ARGS__);                    \
+        }                                                                                       \
+    } while (0)
+
 #define NN_BDISPATCH(wmax, KERNEL, grid, block, stream, ...)                                    \
     do {                                                                                        \
         if ((wmax) <= 8) {                                                                      \
@@ -1575,25 +1599,28 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
 
     // ---- one global step on stream s with grids gr (slices) and fg (members),
     // the row and vector passes optionally bracketed by timing events
+    // (with events, the row and vector passes record their own begin and
+    // end into ev[0..1] and ev[2..3])
     auto step = [&](hipStream_t s, int gr, int fg, hipEvent_t *ev) {
-        if (ev) (void)hipEventRecord(ev[0], s);
+        hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
         if (quad)
-            NN_BDISPATCH(wmax, (kb_rows<WM, CM_Q4, float, float>), gr, blk, s, B,
-                         (const float *)gv32, V32);
+            NN_BDISPATCH_EV(wmax, (kb_rows<WM, CM_Q4, float, float>), gr, blk, s, e0, e1, B,
+                            (const float *)gv32, V32);
         else if (mixed)
-            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, float, float>), gr, blk, s, B,
-                         (const float *)gv32, V32);
+            NN_BDISPATCH_EV(wmax, (kb_rows<WM, CM_I32, float, float>), gr, blk, s, e0, e1, B,
+                            (const float *)gv32, V32);
         else
-            NN_BDISPATCH(wmax, (kb_rows<WM, CM_I32, double, double>), gr, blk, s, B,
-                         (const double *)gv64, V64);
-        if (ev) (void)hipEventRecord(ev[1], s);
+            NN_BDISPATCH_EV(wmax, (kb_rows<WM, CM_I32, double, double>), gr, blk, s, e0, e1, B,
+                            (const double *)gv64, V64);
         hipLaunchKernelGGL(kb_step1, dim3(fg), dim3(kFinBlock), 0, s, B);
-        if (ev) (void)hipEventRecord(ev[2], s);
-        if (mixed)
+        if (ev && mixed)
+            hipExtLaunchKernelGGL((kb_vec<float>), dim3(gr), dim3(blk), 0, s, ev[2], ev[3], 0, B, V32);
+        else if (ev)
+            hipExtLaunchKernelGGL((kb_vec<double>), dim3(gr), dim3(blk), 0, s, ev[2], ev[3], 0, B, V64);
+        else if (mixed)
             hipLaunchKernelGGL((kb_vec<float>), dim3(gr), dim3(blk), 0, s, B, V32);
         else
             hipLaunchKernelGGL((kb_vec<double>), dim3(gr), dim3(blk), 0, s, B, V64);
-        if (ev) (void)hipEventRecord(ev[3], s);
         hipLaunchKernelGGL(kb_step2, dim3(fg), dim3(kFinBlock), 0, s, B);
     };
 

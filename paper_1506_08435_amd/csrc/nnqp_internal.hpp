@@ -1,6 +1,7 @@
 // Internal declarations of the MI355X non-negative QP library (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -123,7 +124,9 @@ struct Dir {
 
 struct ProfEntry {
     int cls;
-    hipEvent_t a, b;
+    hipEvent_t a, b;                 // markers recorded before and after the launch
+    hipEvent_t ka = nullptr, kb = nullptr;   // or the kernel's own begin and end
+    int seq = -1;                    // CG launches: index within their chunk
     double bytes;       // algorithmic bytes of the layout the kernel reads
     double bytes_csr;   // the same launch under the paper's CSR byte model
     int valid;
@@ -202,6 +205,10 @@ struct nn_ctx {
     bool prof = false;
     int prof_mask = 0;         // classes timed while prof is on
     bool prof_open = false;    // a begin event was recorded and awaits its end
+    bool prof_attach = false;  // the next row-kernel launch takes the open entry's kernel events
+    int prof_every = 1;        // time one CG-class launch in prof_every
+    int prof_seq = -1;         // chunk index the next CG-class entry is tagged with
+    int64_t prof_calls[NN_KCLASSES] = {0};   // CG-class launches seen (sampling)
     std::vector<nnqp::ProfEntry> prof_live;
     std::vector<hipEvent_t> ev_pool;
     int64_t prof_count[NN_KCLASSES] = {0};
@@ -260,6 +267,11 @@ nn_status host_reduce(nn_ctx *ctx, int64_t n, int nv, const int *ops, double *ou
 void prof_begin(nn_ctx *ctx, int cls, double bytes, double bytes_csr = __builtin_nan(""));
 void prof_end(nn_ctx *ctx);
 void prof_collect(nn_ctx *ctx);
+// For the CG classes (one kernel per bracket): the open entry's kernel
+// events, which the launch passes to hipExtLaunchKernelGGL so that they
+// record the kernel's own begin and end instead of markers around it.
+// False (a, b untouched) when no such entry is waiting.
+bool prof_kernel_events(nn_ctx *ctx, hipEvent_t *a, hipEvent_t *b);
 // add one timed launch of class cls (ms, algorithmic bytes) to the totals
 void prof_add(nn_ctx *ctx, int cls, double ms, double bytes, double bytes_csr = __builtin_nan(""));
 

@@ -666,17 +666,30 @@ __device__ __forceinline__ double proj_box(double x, Box B)
 // Launch KERNEL (a template over WM, the unrolled slice width; may be a
 // parenthesised template-id) with the instance that covers the widest slice
 // `wmax`; kBlock threads per block on ctx->stream.
+// A launch on the context's stream; while a CG-class profiling entry waits
+// for its kernel, the kernel's own begin and end are recorded into the
+// entry's events (hipExtLaunchKernelGGL) rather than markers around it.
+#define NN_LAUNCH_ROWS(KERNEL, grid, ...)                                                    \
+    do {                                                                                     \
+        hipEvent_t ka_ = nullptr, kb_ = nullptr;                                             \
+        if (ctx->prof_attach && prof_kernel_events(ctx, &ka_, &kb_))                         \
+            hipExtLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, ka_, kb_, \
+                                  0, __VA_ARGS__);                                           \
+        else                                                                                 \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+    } while (0)
+
 #define NN_DISPATCH_W(wmax, KERNEL, grid, ...)                                             \
     do {                                                                                   \
         if ((wmax) <= 8) {                                                                 \
             constexpr int WM = 8;                                                          \
-            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+            NN_LAUNCH_ROWS(KERNEL, grid, __VA_ARGS__);                                     \
         } else if ((wmax) <= 16) {                                                         \
             constexpr int WM = 16;                                                         \
-            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+            NN_LAUNCH_ROWS(KERNEL, grid, __VA_ARGS__);                                     \
         } else {                                                                           \
             constexpr int WM = 32;                                                         \
-            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kBlock), 0, ctx->stream, __VA_ARGS__); \
+            NN_LAUNCH_ROWS(KERNEL, grid, __VA_ARGS__);                                     \
         }                                                                                  \
     } while (0)
 

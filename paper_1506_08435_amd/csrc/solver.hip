@@ -427,6 +427,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                                        ? chunk
                                        : std::max(2, std::min(chunk, cg_guess + 2));
             for (int k = 0; k < this_chunk; k++, j_next++) {
+                ctx->prof_seq = k;
                 prof_begin(ctx, KC_CG_SPMV, -1.0);
                 launch_cg_spmv(ctx, A, VS, j_next, o->max_cg, o->inner_rtol, tr);
                 prof_end(ctx);
@@ -440,6 +441,7 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
                     prof_end(ctx);
                 }
             }
+            ctx->prof_seq = -1;
             if ((rc = read_scalars(ctx)) != NN_OK) return rc;
             const int ran = H.it - it_seen;
             // byte model of the launches that did work; the rest exited at once
@@ -459,10 +461,9 @@ nn_status solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, const 
             // write x, r)
             const double c_spmv = (4.0 + vb) * nzf + (4.0 + 2.0 * vb) * nf + 4.0 * vb * nf;
             const double c_upd = 7.0 * vb * nf;
-            int seen[NN_KCLASSES] = {0};   // launches of each class in this chunk
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
-                P.valid = seen[P.cls]++ < (P.cls == KC_OTHER ? ran * csteps : ran);
+                P.valid = P.seq >= 0 && P.seq < ran;   // the chunk's launches that did work
                 P.bytes = P.cls == KC_CG_SPMV ? b_spmv : (P.cls == KC_OTHER ? b_cheb : b_upd);
                 P.bytes_csr = P.cls == KC_CG_SPMV ? c_spmv : (P.cls == KC_OTHER ? b_cheb : c_upd);
             }
@@ -623,6 +624,7 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
         for (;;) {
             const size_t mark = ctx->prof_live.size();
             for (int k = 0; k < chunk; k++, j_next++) {
+                ctx->prof_seq = k;
                 prof_begin(ctx, KC_CG_SPMV, -1.0);
                 launch_cg_spmv(ctx, A, VS, j_next, budget, rtol);
                 prof_end(ctx);
@@ -636,14 +638,14 @@ nn_status galerkin_impl(nn_ctx *ctx, const nn_matrix *A, const double *f, const 
                     prof_end(ctx);
                 }
             }
+            ctx->prof_seq = -1;
             if ((rc = read_scalars(ctx)) != NN_OK) return rc;
             const int ran = H.it - it_seen;
             const double b_cheb = n + 4.0 * n + 12.0 * A->nnz + 64.0 * n;
             const double c_spmv = 12.0 * A->nnz + 52.0 * n, c_upd = 56.0 * n;   // CSR model
-            int seen[NN_KCLASSES] = {0};
             for (size_t e = mark; e < ctx->prof_live.size(); e++) {
                 ProfEntry &P = ctx->prof_live[e];
-                P.valid = seen[P.cls]++ < (P.cls == KC_OTHER ? ran * csteps : ran);
+                P.valid = P.seq >= 0 && P.seq < ran;   // the chunk's launches that did work
                 P.bytes = P.cls == KC_CG_SPMV ? b_spmv : (P.cls == KC_OTHER ? b_cheb : b_upd);
                 P.bytes_csr = P.cls == KC_CG_SPMV ? c_spmv : (P.cls == KC_OTHER ? b_cheb : c_upd);
             }

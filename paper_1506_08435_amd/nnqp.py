@@ -32,7 +32,7 @@ SYMBOLS = ("nn_create", "nn_create_ex", "nn_destroy", "nn_last_error", "nn_defau
            "nn_matrix_from_csr", "nn_matrix_info", "nn_matrix_export", "nn_matrix_bytes",
            "nn_matrix_free", "nn_matvec", "nn_solve_nonneg", "nn_solve_nonneg_noalloc",
            "nn_solve_galerkin", "nn_step_transient",
-           "nn_solve_batch", "nn_step_transient_batch", "nn_set_profiling", "nn_kernel_times")
+           "nn_solve_batch", "nn_step_transient_batch", "nn_set_profiling", "nn_set_profiling_sample", "nn_kernel_times")
 
 
 # device memory hooks of nn_create_ex: alloc(bytes, user) -> pointer or NULL,
@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH):
         "nn_step_transient_batch": (i32, [vp, i32, P(vp), dbl, P(vp), P(Opts), P(vp), P(vp),
                                           P(Stats)]),
         "nn_set_profiling": (i32, [vp, ctypes.c_int]),
+        "nn_set_profiling_sample": (i32, [vp, i32]),
         "nn_kernel_times": (i32, [vp, vp, vp, vp, vp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -421,12 +422,14 @@ class Context:
                 [st_arr[k].as_dict() for k in range(P)], st)
 
     # ---------------------------------------------------------------- profiling
-    def set_profiling(self, on, classes=None):
+    def set_profiling(self, on, classes=None, every: int = 1):
         """Time kernel launches with HIP events: on=False stops; `classes`
-        (names from KCLASS_NAMES) limits timing to those classes."""
+        (names from KCLASS_NAMES) limits timing to those classes; `every`
+        times one launch in `every` of the CG classes (nn_set_profiling_sample)."""
         mask = 0
         if on:
             mask = NN_PROF_ALL if classes is None else sum(1 << KCLASS_NAMES.index(c) for c in classes)
+        self._check(self.lib.nn_set_profiling_sample(self.handle, int(every)), "nn_set_profiling_sample")
         self._check(self.lib.nn_set_profiling(self.handle, mask), "nn_set_profiling")
 
     def kernel_times(self, reset: bool = False) -> dict:

@@ -325,6 +325,51 @@ def test_int16_offset_limit(ctx, batch_members, ny, fits):
     assert errm <= MIXED_TOL and errb <= MIXED_TOL
 
 
+def test_kernel_timing_leaves_results_unchanged(ctx, batch_members):
+    """With profiling on, the CG kernels record their own begin and end into
+    the context's events: every class reports launches, time and bytes, the
+    CG matrix pass's launches equal the CG iterations, and the results are
+    bitwise those of an unprofiled solve (single problem and batch)."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    p = W.cube3d(21)
+    K, F, _ = ctx.assemble(p)
+    c0, _, st0 = ctx.solve_nonneg(K, F, tol=1e-10, engine=1)
+    ctx.set_profiling(True)
+    ctx.kernel_times(reset=True)
+    c1, _, st1 = ctx.solve_nonneg(K, F, tol=1e-10, engine=1)
+    kt = ctx.kernel_times(reset=True)
+    _, Ks, Fs, _ = batch_members
+    b0, _, _, _ = ctx.solve_batch(Ks[:4], Fs[:4], tol=1e-10)
+    ctx.set_profiling(True)
+    ctx.kernel_times(reset=True)
+    b1, _, _, _ = ctx.solve_batch(Ks[:4], Fs[:4], tol=1e-10)
+    ktb = ctx.kernel_times(reset=True)
+    ctx.set_profiling(False)
+    assert torch.equal(c0, c1) and st0["cg_its"] == st1["cg_its"]
+    assert kt["cg_spmv"]["count"] == st1["cg_its"]
+    for name in ("cg_spmv", "cg_update", "grad", "trial"):
+        assert kt[name]["count"] > 0 and kt[name]["ms"] > 0.0 and kt[name]["bytes"] > 0.0, name
+    per = kt["cg_spmv"]["ms"] / kt["cg_spmv"]["count"]
+    assert 0.0 < per < 1.0, per   # milliseconds per launch of a 9,261-row pass
+    for a, b in zip(b0, b1):
+        assert torch.equal(a, b)
+    assert ktb["cg_spmv"]["count"] > 0 and ktb["cg_spmv"]["ms"] > 0.0
+    # one CG launch in eight timed: a sample of the same launches
+    ctx.set_profiling(True, every=8)
+    ctx.kernel_times(reset=True)
+    c2, _, st2 = ctx.solve_nonneg(K, F, tol=1e-10, engine=1)
+    kt8 = ctx.kernel_times(reset=True)
+    ctx.set_profiling(False)
+    assert torch.equal(c0, c2)
+    assert 0 < kt8["cg_spmv"]["count"] < kt["cg_spmv"]["count"] // 2, (kt8["cg_spmv"], kt["cg_spmv"])
+    assert kt8["grad"]["count"] == kt["grad"]["count"]   # other classes are timed in full
+    with pytest.raises(nnqp.NnError):
+        ctx.set_profiling(True, every=0)
+    print(f"profiled: {kt['cg_spmv']['count']} CG passes, {1e3 * per:.1f} us each; "
+          f"batch row passes {ktb['cg_spmv']['count']}")
+
+
 def test_transient_steps_make_the_paired_copies(ctx):
     """A float64 backward-Euler step reads the paired copy of M/dt + K (int16
     offset pairs with value pairs), a mixed one the quad copy (int16 offsets
