@@ -435,11 +435,12 @@ nn_status nn_step_transient_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *
 #define NN_KCLASSES 5
 #define NN_PROF_ALL 0x1f
 nn_status nn_set_profiling(nn_ctx *ctx, int classes);
-/* Time one launch in `every` (>= 1; default 1: all) of each CG class (0, 1)
- * while profiling is on; the other classes are always timed in full.  The CG
- * launches of a solve are passes of the same size, so a systematic sample
- * gives their average duration at a fraction of the timing overhead.
- * NN_EINVAL for every < 1. */
+/* Time about one launch in `every` (>= 1; default 1: all) of each CG class
+ * (0, 1) while profiling is on, chosen by a hash of the launch count (no
+ * fixed stride that could keep hitting the same place in every chunk of CG
+ * launches); the other classes are always timed in full.  The CG launches of
+ * a solve are passes of the same size, so the sample gives their average
+ * duration at a fraction of the timing overhead.  NN_EINVAL for every < 1. */
 nn_status nn_set_profiling_sample(nn_ctx *ctx, int32_t every);
 /* counts/total_ms/total_bytes/total_bytes_csr: host arrays of NN_KCLASSES
  * entries or NULL.  total_bytes is the algorithmic (perfect-cache) byte count

@@ -111,7 +111,13 @@ void prof_begin(nn_ctx *ctx, int cls, double bytes, double bytes_csr)
     ctx->prof_attach = false;
     if (!ctx->prof || !((ctx->prof_mask >> cls) & 1)) return;
     const bool cg = cls == KC_CG_SPMV || cls == KC_CG_UPDATE;
-    if (cg && ctx->prof_every > 1 && ctx->prof_calls[cls]++ % ctx->prof_every != 0) return;
+    if (cg && ctx->prof_every > 1) {
+        // a pseudo-random one in prof_every: a fixed stride would keep hitting
+        // the same place in every chunk of CG launches (the first launch after
+        // a host read starts on an idle GPU and runs long)
+        const uint32_t h = (uint32_t)ctx->prof_calls[cls]++ * 2654435761u;
+        if ((h >> 16) % (uint32_t)ctx->prof_every != 0) return;
+    }
     ProfEntry p;
     p.cls = cls;
     p.seq = ctx->prof_seq;
