@@ -264,10 +264,11 @@ nn_status nn_matrix_info(const nn_matrix *A, int64_t *n, int64_t *nnz, int *has_
 nn_status nn_matrix_export(nn_ctx *ctx, const nn_matrix *A, int64_t *rowptr, int32_t *col,
                            double *val, double *mval);
 /* Device bytes the matrix and one solve's work vectors occupy for a precision
- * (used to admit requests against an HBM budget), including the paired value
- * and offset copies that single-problem solves have already made (the first
+ * (used to admit requests against an HBM budget), including the value and
+ * offset copies that single-problem solves have already made (the first
  * single-problem solve of a matrix whose column offsets fit int16 adds
- * 10 B per sliced-ELL entry in float64, 6 B in mixed precision). */
+ * 10 B per sliced-ELL entry in float64 (paired layout), 6 B in mixed
+ * precision (quad layout)). */
 nn_status nn_matrix_bytes(const nn_matrix *A, int precision, size_t *bytes);
 void nn_matrix_free(nn_ctx *ctx, nn_matrix *A);
 
@@ -316,9 +317,9 @@ nn_status nn_solve_nonneg(nn_ctx *ctx, nn_matrix *K, const double *f_dev,
  * same TRON solve, with every work buffer (reduction partials, CG scalars,
  * work vectors, face mask) in one fixed device array of the library instead
  * of memory taken through hipMalloc or the context's allocator hooks.  It
- * calls no device allocator and forms no copy of K: the paired and float32
- * copies are used if an earlier nn_solve_nonneg made them (results are then
- * bitwise those of nn_solve_nonneg), else the column-major values.
+ * calls no device allocator and forms no copy of K: the paired, float32 and
+ * quad copies are used if an earlier nn_solve_nonneg made them (results are
+ * then bitwise those of nn_solve_nonneg), else the column-major values.
  *   Limit: n <= 262,144 rows (the array: about 26 MiB of device memory per
  *          GPU, taken when the library is loaded and held until the process
  *          ends); larger n -> NN_EINVAL.

@@ -189,8 +189,9 @@ void prof_collect(nn_ctx *ctx)
 
 namespace nnqp {
 
-// The paired int16 offsets (and, when the float32 values exist, the paired
-// float32 values of K) used by the single-problem float32 passes.
+// Copies of K that the single-problem passes read: with f64, the paired
+// int16 offsets and float64 values; when the float32 values exist, the quad
+// int16 offsets and float32 values.
 #ifndef NNQP_PAIR_F64
 #define NNQP_PAIR_F64 1   // float64 solves read the paired layout when it exists
 #endif

@@ -392,8 +392,9 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                            const nn_opts *o, double *const *c, uint8_t *const *active,
                            nn_stats *stats, double dt);
 // Form (once per dt) the M/dt + K values, their diagonal and, for mixed
-// precision, their float32 copy; with `paired`, also the paired copy the
-// single-problem solver reads at this precision.
+// precision, their float32 copy; with `paired`, also the copy the
+// single-problem solver reads at this precision (paired float64 or quad
+// float32, with their int16 offsets).
 nn_status ensure_transient(nn_ctx *ctx, nn_matrix *K, double dt, bool mixed, bool paired);
 
 }  // namespace nnqp
