@@ -397,10 +397,9 @@ nn_status nn_step_transient(nn_ctx *ctx, nn_matrix *K, double dt, const double *
  * then that call status.  Workspace is allocated for the call and released
  * before return: per row of the batch (rows of 64-row slices) 101 bytes in
  * float64, 77 in mixed precision, plus per stored matrix entry (sliced-ELL,
- * rows padded to the longest row of their slice) 12 bytes in float64, 18 in
+ * rows padded to the longest row of their slice) 14 bytes in float64, 18 in
  * mixed precision (a concatenated copy of every member's matrix; 2 bytes
- * less in mixed precision when a member's columns do not fit int16 offsets
- * from the row).
+ * less when a member's columns do not fit int16 offsets from the row).
  */
 nn_status nn_solve_batch(nn_ctx *ctx, int32_t nprob, nn_matrix *const *K,
                          const double *const *f_dev, const nn_opts *opts, double *const *c_dev,

@@ -200,7 +200,7 @@ __device__ __forceinline__ void for_bslices(const BDev &B, const int (&ops)[NV],
 // kernels): int32 columns, or int16 offsets from the row (float32 values,
 // when every member has them).  Float64 values load with the non-temporal
 // hint, float32 values normally (as in the single-problem kernels).
-enum { CM_I32 = 0, CM_D16 = 2, CM_Q4 = 3 };
+enum { CM_I32 = 0, CM_D16 = 2, CM_Q4 = 3, CM_P2 = 4 };
 
 // Position of entry k of lane l in a slice of width w of the quad layout
 // (CM_Q4), relative to the slice's first entry: entries 4j .. 4j+3 of a row
@@ -213,6 +213,15 @@ __host__ __device__ __forceinline__ int quad_pos(int k, int l, int w)
     const int nq = w >> 2, np = (w - 4 * nq) >> 1;
     if (k < 4 * nq) return 256 * (k >> 2) + 4 * l + (k & 3);
     if (k < 4 * nq + 2 * np) return 256 * nq + 2 * l + (k - 4 * nq);
+    return 64 * k + l;
+}
+
+// The same for the paired layout (CM_P2): entries 2j, 2j+1 of a row side by
+// side at 128 j + 2 l, an odd last one in its column-major place.
+__host__ __device__ __forceinline__ int pair_pos(int k, int l, int w)
+{
+    const int np = w >> 1;
+    if (k < 2 * np) return 128 * (k >> 1) + 2 * l + (k & 1);
     return 64 * k + l;
 }
 
@@ -310,10 +319,46 @@ __device__ __forceinline__ double gsell_row_at(const BDev &B, const VT *__restri
     const int *__restrict__ gc = B.gcol;
     const short *__restrict__ gd = B.gd16;
     auto col = [&](int e) {
-        if (CM == CM_D16 || CM == CM_Q4) return i + (int)gd[e];
+        if (CM == CM_D16 || CM == CM_Q4 || CM == CM_P2) return i + (int)gd[e];
         return gc[e];
     };
     double acc = 0.0;
+    if constexpr (CM == CM_P2) {
+        // pairs in entry order, then the odd entry: the column-major sum order
+        const int np = w >> 1;
+        constexpr int HP = (WMAX < 8 ? WMAX : 8) / 2;   // pairs per load phase
+#pragma unroll
+        for (int h0 = 0; h0 < WMAX / 2; h0 += HP) {
+            int cc[2 * HP];
+            VT vv[2 * HP];
+#pragma unroll
+            for (int k = 0; k < HP; k++) {
+                if (h0 + k < np) {
+                    const int e = off + (h0 + k) * 2 * kSlice + 2 * lane;
+                    bld_pair(sv + e, vv[2 * k], vv[2 * k + 1]);
+                    const int d2 = *reinterpret_cast<const int *>(gd + e);
+                    cc[2 * k] = i + (int)(short)(d2 & 0xffff);
+                    cc[2 * k + 1] = i + (d2 >> 16);
+                } else {
+                    cc[2 * k] = cc[2 * k + 1] = 0;
+                    vv[2 * k] = vv[2 * k + 1] = VT(0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 2 * HP; k++)
+                if (h0 + k / 2 < np) acc += (double)vv[k] * x(cc[k]);
+        }
+        for (int k = WMAX / 2; k < np; k++) {   // slices wider than the unrolled part
+            const int e = off + k * 2 * kSlice + 2 * lane;
+            acc += (double)bld_val(sv + e) * x(col(e));
+            acc += (double)bld_val(sv + e + 1) * x(col(e + 1));
+        }
+        if (w & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            acc += (double)bld_val(sv + e) * x(col(e));
+        }
+        return acc;
+    }
     if constexpr (CM == CM_Q4) {
         // quads in entry order, then the left-over pair, then the odd entry:
         // the same sum order as the column-major walk
@@ -428,7 +473,7 @@ __global__ void kb_recs(BDev B)
 __global__ void kb_gather(BDev B, const int64_t *__restrict__ ebase, int *__restrict__ gso,
                           int *__restrict__ gcol, short *__restrict__ gd16,
                           double *__restrict__ gv64, float *__restrict__ gv32,
-                          double *__restrict__ dg, int *__restrict__ rlen, int copy_f)
+                          double *__restrict__ dg, int *__restrict__ rlen, int copy_f, int layout)
 {
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -453,7 +498,9 @@ __global__ void kb_gather(BDev B, const int64_t *__restrict__ ebase, int *__rest
         const float *v32 = B.v32[p];
         for (int k = 0; k < w; k++) {
             const int es = src + k * kSlice + lane;
-            const int ed = dst + (gd16 ? quad_pos(k, lane, w) : k * kSlice + lane);
+            const int ed = dst + (layout == CM_Q4   ? quad_pos(k, lane, w)
+                                  : layout == CM_P2 ? pair_pos(k, lane, w)
+                                                    : k * kSlice + lane);
             gcol[ed] = sc[es] + r0;
             if (gd16) gd16[ed] = sd[es];
             gv64[ed] = v64[es];
@@ -1089,6 +1136,10 @@ int width_class(int wmax) { return wmax <= 8 ? 8 : (wmax <= 16 ? 16 : 32); }
 
 // The same with the kernel's own begin and end recorded into e0, e1 when
 // they are not null (hipExtLaunchKernelGGL).
+#ifndef NNQP_BATCH_PAIRS
+#define NNQP_BATCH_PAIRS 1   // float64 batches read the concatenated matrix in pairs
+#endif
+
 #define NN_BLAUNCH_EV(KERNEL, grid, block, stream, e0, e1, ...)                                 \
     do {                                                                                        \
         if (e0)                                                                                 \
@@ -1278,11 +1329,14 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     const double vb = mixed ? 4.0 : 8.0;                // bytes per CG vector entry and per value
     // Mixed precision reads the concatenated matrix in the quad layout (int16
     // offsets, four float32 values per load): on the 512-member batch the row
-    // pass takes 67 instead of 107 us.  Float64 keeps int32 columns
-    // column-major: its quad layout (two 16-byte value loads per quad) was no
-    // faster, column-major int16 offsets slower.
+    // pass takes 67 instead of 107 us.  Float64 reads it in pairs (int16
+    // offset pairs, one 16-byte load per value pair): 95-97 instead of
+    // 90-106 us (its quad layout was no faster, column-major int16 offsets
+    // slower).
     const bool quad = mixed && all_d16;
-    const double ib = quad ? 2.0 : 4.0;   // bytes per column index
+    const bool pair = !mixed && all_d16 && NNQP_BATCH_PAIRS;
+    const int layout = quad ? CM_Q4 : (pair ? CM_P2 : CM_I32);
+    const double ib = quad || pair ? 2.0 : 4.0;   // bytes per column index
 
     // ---- tables, work vectors, lists, pinned state mirrors
     Arena A(ctx->al);
@@ -1317,7 +1371,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
     int64_t *d_ebase = A.d<int64_t>(P);
     double *gv64 = A.d<double>(E);
     float *gv32 = mixed ? A.d<float>(E) : nullptr;
-    short *gd16 = quad ? A.d<short>(E) : nullptr;
+    short *gd16 = quad || pair ? A.d<short>(E) : nullptr;
     BVec<double> V64{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     BVec<float> V32{g, ks0, ks1, mask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (mixed) {
@@ -1515,7 +1569,7 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         const int64_t blocks = std::min<int64_t>((S + 3) / 4, (int64_t)num_cu * 8);
         hipLaunchKernelGGL(kb_gather, dim3((int)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, B,
                            (const int64_t *)d_ebase, gso, gcol, gd16, gv64, gv32, dg, rlen,
-                           transient ? 0 : 1);
+                           transient ? 0 : 1, layout);
         layout_ready = true;
         NN_HIP_TRY(ctx, build_recs() ? hipSuccess : hipErrorUnknown);
     }
@@ -1570,10 +1624,12 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
                 const Shape cand{blk, per_cu};
                 const int gsz = grid_for(cand, n_sl);
                 if (quad) NN_BDISPATCH(wmax, (kb_grad<WM, CM_Q4>), gsz, blk, st, B, g);   // warm-up
+                else if (pair) NN_BDISPATCH(wmax, (kb_grad<WM, CM_P2>), gsz, blk, st, B, g);
                 else NN_BDISPATCH(wmax, (kb_grad<WM, CM_I32>), gsz, blk, st, B, g);
                 NN_HIP_TRY(ctx, hipEventRecord(t0, st));
                 for (int rep = 0; rep < 3; rep++)
                     if (quad) NN_BDISPATCH(wmax, (kb_grad<WM, CM_Q4>), gsz, blk, st, B, g);
+                    else if (pair) NN_BDISPATCH(wmax, (kb_grad<WM, CM_P2>), gsz, blk, st, B, g);
                     else NN_BDISPATCH(wmax, (kb_grad<WM, CM_I32>), gsz, blk, st, B, g);
                 NN_HIP_TRY(ctx, hipEventRecord(t1, st));
                 NN_HIP_TRY(ctx, hipEventSynchronize(t1));
@@ -1609,6 +1665,9 @@ nn_status solve_batch_impl(nn_ctx *ctx, int P, nn_matrix *const *K, const double
         else if (mixed)
             NN_BDISPATCH_EV(wmax, (kb_rows<WM, CM_I32, float, float>), gr, blk, s, e0, e1, B,
                             (const float *)gv32, V32);
+        else if (pair)
+            NN_BDISPATCH_EV(wmax, (kb_rows<WM, CM_P2, double, double>), gr, blk, s, e0, e1, B,
+                            (const double *)gv64, V64);
         else
             NN_BDISPATCH_EV(wmax, (kb_rows<WM, CM_I32, double, double>), gr, blk, s, e0, e1, B,
                             (const double *)gv64, V64);

@@ -101,14 +101,14 @@ def batch_workspace_bytes(n: int, dim: int, precision: int) -> int:
     the call: the member's rows in the concatenated work vectors (gradient,
     two search products, mask, start value, load, diagonal, row lengths and
     six CG vectors; whole 64-row slices) and its entries in the concatenated
-    block-diagonal matrix (int32 columns and float64 values; float32 values
-    and int16 offsets too in mixed precision), counted at the longest row of
+    block-diagonal matrix (int32 columns, int16 offsets and float64 values;
+    float32 values too in mixed precision), counted at the longest row of
     a structured P1 pattern (7 in 2D, 15 in 3D) for every row of a slice."""
     rows = 64 * ((n + 63) // 64)
     nsell = (7 if dim == 2 else 15) * rows
     if precision == nnqp.NN_MIXED:
         return int(77.0 * rows + 18.0 * nsell)
-    return int(101.0 * rows + 12.0 * nsell)
+    return int(101.0 * rows + 14.0 * nsell)
 
 
 def estimate_bytes(problem, precision: int, solo: bool = False) -> int:
