@@ -321,8 +321,17 @@ def test_int16_offset_limit(ctx, batch_members, ny, fits):
     cs, _, _, rc = ctx.solve_batch([Ks[0], K], [Fs[0], F], tol=1e-10, precision=nnqp.NN_MIXED)
     assert rc == 0
     errb = np.abs(_np(cs[1]) - ref.c).max() / np.abs(ref.c).max()
-    print(f"slab ny={ny}: n={S.n} span={span} err fp64 {err:.2e} mixed {errm:.2e} batch {errb:.2e}")
-    assert errm <= MIXED_TOL and errb <= MIXED_TOL
+    # float64 batch: paired layout when every member has int16 offsets, else
+    # int32 columns; a member's result is bitwise the same either way
+    import torch
+    c64, _, _, rc64 = ctx.solve_batch([Ks[0], K], [Fs[0], F], tol=1e-12)
+    alone, _, _, rca = ctx.solve_batch([Ks[0]], [Fs[0]], tol=1e-12)
+    assert rc64 == 0 and rca == 0
+    assert torch.equal(c64[0], alone[0])
+    err64b = np.abs(_np(c64[1]) - ref.c).max() / np.abs(ref.c).max()
+    print(f"slab ny={ny}: n={S.n} span={span} err fp64 {err:.2e} mixed {errm:.2e} "
+          f"batch mixed {errb:.2e} batch fp64 {err64b:.2e}")
+    assert errm <= MIXED_TOL and errb <= MIXED_TOL and err64b <= PARITY_TOL
 
 
 def test_kernel_timing_leaves_results_unchanged(ctx, batch_members):
