@@ -22,6 +22,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+
+# The paper's own numbers, as context only (vs_baseline stays null): the
+# single-core CPU times, in seconds, of its cube-with-hole case A3 (2,175,330
+# vertices of unstructured tets, the size class of the 128^3 cube; bounds
+# [0, 1]; TAO/KSP relative tolerance 1e-6), Tables Tab:S5_cube_times_mustang
+# (AMD Opteron 6176, 2.3 GHz) and Tab:S5_cube_times_wolf (Intel Xeon E5-2670,
+# 2.6 GHz), one core each.
+PAPER_A3_SECONDS = {
+    "mustang_1_core": {"galerkin": 121.0, "tron1": 225.0, "tron2": 414.0, "tron3": 599.0,
+                       "blmvm": 1167.0},
+    "wolf_1_core": {"galerkin": 48.0, "tron1": 98.4, "tron2": 129.0, "tron3": 247.0,
+                    "blmvm": 609.0},
+}
+
+
+def paper_context() -> dict:
+    return {"case": "A3: cube with a hole, 2,175,330 vertices (unstructured tets), bounds [0, 1]",
+            "tolerance": "TAO/KSP relative 1e-6", "seconds": PAPER_A3_SECONDS,
+            "note": "single-core CPU times from the paper, context only: other meshes, "
+                    "tolerance and hardware"}
 EXTRAS = ("mixed", "small", "transient", "batch", "serve")
 CSRC = os.path.join(ROOT, "paper_1506_08435_amd", "csrc")
 # sources that decide what a kernel reads and writes: its code, the slice
@@ -296,6 +316,7 @@ def run_hole(args):
     if blmvm is not None:
         line["blmvm"] = blmvm
         line["tron_levels"] = run_tron_levels(ctx, K, F, args, bounds=(0.0, 1.0))
+    line["paper_context"] = paper_context()
     print(json.dumps(line), flush=True)
 
 
@@ -689,6 +710,7 @@ def main():
         full = recorded_cpu_baseline(args.n)
         if full is not None:
             out["cpu_baseline"]["full_size_recorded"] = full
+    out["paper_context"] = paper_context()
     # the other workloads of the metric, each in its own section: the small
     # 2D solve (latency), the heterogeneous transient run, the 512-member
     # batch and the served stream (p50/p99), FP64 and mixed precision

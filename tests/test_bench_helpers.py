@@ -68,6 +68,19 @@ def test_recorded_full_size_oracle_run():
     assert bench.recorded_cpu_baseline(7) is None
 
 
+def test_paper_context_is_the_published_a3_times():
+    ctx = bench.paper_context()
+    s = ctx["seconds"]
+    # Tables Tab:S5_cube_times_mustang / _wolf, case A3: TRON1..3 slow down as
+    # the inner tolerance tightens, and the faster core is faster everywhere
+    for core in ("mustang_1_core", "wolf_1_core"):
+        t = s[core]
+        assert t["galerkin"] < t["tron1"] < t["tron2"] < t["tron3"] < t["blmvm"]
+    for k in s["wolf_1_core"]:
+        assert s["wolf_1_core"][k] < s["mustang_1_core"][k]
+    assert s["mustang_1_core"]["tron1"] == 225.0 and s["wolf_1_core"]["tron1"] == 98.4
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
