@@ -16,7 +16,11 @@ each step a non-negative QP warm-started from the previous one.  The server:
   join at the next tick, finished requests leave and free their memory;
 * routes requests by size to lanes that tick independently on their own
   streams, so small requests are not held by a large one's step; the upper
-  lanes step each of their requests with the single-problem solver.
+  lanes step each of their requests with the single-problem solver;
+* cancels a request at its `cancel_at` time or on `Server.cancel(rid)` from
+  any thread: a waiting request leaves the queue, an admitted one is dropped
+  after its assembly or between ticks, its memory is freed and its budget
+  returned; the steps it finished stay in its result.
 
 Because a batch member's arithmetic does not depend on the other members, a
 request's result is bitwise the same whether it is served alone or in any mix.
@@ -41,6 +45,7 @@ import numpy as np
 from . import nnqp
 
 NN_EBUDGET = nnqp.NN_EBUDGET
+CANCELLED = -1   # Result.status of a request cancelled before its last step
 
 
 @dataclasses.dataclass
@@ -49,6 +54,7 @@ class Request:
     problem: object          # workloads.Problem
     steps: int
     arrival: float           # seconds after the stream starts
+    cancel_at: float = math.inf   # seconds after the stream starts: the client cancels
 
 
 @dataclasses.dataclass
@@ -79,6 +85,7 @@ class Report:
     peak_bytes: int
     budget: int
     lane_ticks: list = dataclasses.field(default_factory=list)   # ticks run by each lane
+    final_bytes: int = 0          # budget still held when the stream ended (0: all returned)
 
     def summary(self) -> dict:
         done = [r for r in self.results if r.status == 0]
@@ -86,6 +93,7 @@ class Report:
         dof_steps = sum(r.n * r.steps for r in done)
         return {"requests": len(self.results), "completed": len(done),
                 "rejected": sum(r.status == NN_EBUDGET for r in self.results),
+                "cancelled": sum(r.status == CANCELLED for r in self.results),
                 "p50_latency_s": float(np.percentile(lat, 50)),
                 "p99_latency_s": float(np.percentile(lat, 99)),
                 "mean_latency_s": float(lat.mean()), "max_latency_s": float(lat.max()),
@@ -207,6 +215,19 @@ class Server:
         # workers): None for hipMalloc, else as nnqp.Context's `allocator`
         self.allocator = allocator
         self._tls = threading.local()
+        self._cancel = set()
+        self._cancel_lock = threading.Lock()
+
+    def cancel(self, rid: int) -> None:
+        """Cancel request `rid` (any thread, also while `run` is serving)."""
+        with self._cancel_lock:
+            self._cancel.add(rid)
+
+    def _cancelled(self, req: Request, now: float) -> bool:
+        if now >= req.cancel_at:
+            return True
+        with self._cancel_lock:
+            return req.rid in self._cancel
 
     # worker-thread assembly on the thread's own context and stream
     def _assemble(self, req: Request):
@@ -272,14 +293,33 @@ class Server:
         batch_sum = sum(L.batch_sum for L in lanes)
         return Report([results[r.rid] for r in reqs], makespan, ticks,
                       batch_sum / max(ticks, 1), len(waited), shared["peak"], self.budget,
-                      [L.ticks for L in lanes])
+                      [L.ticks for L in lanes], shared["used"])
 
     def _lane_loop(self, L: _Lane, results, shared, lock, waited, pool, t0, abort):
         torch = self.torch
+
+        def drop(req):
+            res = results[req.rid]
+            res.status = CANCELLED
+            res.finished = time.perf_counter() - t0
+
         while (L.pending or L.waiting or L.assembling or L.resident) and not abort.is_set():
             now = time.perf_counter() - t0
             while L.pending and L.pending[0].arrival <= now:
                 L.waiting.append(L.pending.popleft())
+            # cancellations: queued requests leave, resident ones free their memory
+            for q in (L.pending, L.waiting):
+                for req in [r for r in q if self._cancelled(r, now)]:
+                    q.remove(req)
+                    drop(req)
+            gone = [s for s in L.resident if self._cancelled(s["req"], now)]
+            for s in gone:
+                drop(s["req"])
+                s["K"].free()
+                with lock:
+                    shared["used"] -= s["bytes"]
+            if gone:
+                L.resident = [s for s in L.resident if not any(s is g for g in gone)]
             # admission: first in, first out within the lane, while the estimate fits
             while L.waiting:
                 req = L.waiting[0]
@@ -303,6 +343,12 @@ class Server:
             for fut in [f for f in L.assembling if f.done()]:
                 req, est = L.assembling.pop(fut)
                 K, F = fut.result()
+                if self._cancelled(req, time.perf_counter() - t0):
+                    drop(req)
+                    K.free()
+                    with lock:
+                        shared["used"] -= est
+                    continue
                 nb = K.bytes(self.precision) + 17 * K.n
                 if L.solo:   # the paired copies and work vectors its steps will add
                     nb = max(nb, est)

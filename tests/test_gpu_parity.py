@@ -379,6 +379,33 @@ def test_kernel_timing_leaves_results_unchanged(ctx, batch_members):
           f"batch row passes {ktb['cg_spmv']['count']}")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_transient_snapshot_and_resume_bitwise(ctx, precision):
+    """A transient run's state is c: copied to host memory after three steps,
+    the run resumed on a fresh context with a freshly assembled matrix gives
+    bitwise the state of the uninterrupted six steps (deterministic assembly
+    and fixed-order reductions)."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    prec = nnqp.NN_MIXED if precision == "mixed" else nnqp.NN_FP64
+    p = W.config_transient3d(20, 18, 9, ell=3.0)
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    c = torch.zeros(K.n, dtype=torch.float64, device=ctx.device)
+    for k in range(6):
+        ctx.step_transient(K, 1e-3, F, c, tol=1e-10, precision=prec)
+        if k == 2:
+            snapshot = c.cpu().numpy().copy()
+    K.free()
+    ctx2 = nnqp.Context(0)
+    K2, F2, _ = ctx2.assemble(p, with_mass=True)
+    c2 = torch.from_numpy(snapshot).to(ctx2.device)
+    for _ in range(3):
+        ctx2.step_transient(K2, 1e-3, F2, c2, tol=1e-10, precision=prec)
+    assert torch.equal(c2, c)
+    K2.free()
+    ctx2.close()
+
+
 def test_transient_steps_make_the_paired_copies(ctx):
     """A float64 backward-Euler step reads the paired copy of M/dt + K (int16
     offset pairs with value pairs), a mixed one the quad copy (int16 offsets

@@ -322,3 +322,42 @@ def test_admission_estimate_bounds_measured_step_memory(prec):
             assert est >= used, (k, solo, used, est)
             K.free()
             ctx.close()
+
+
+@pytest.mark.gpu
+def test_cancelled_requests_leave_and_the_rest_equal_alone():
+    """Request 1 is cancelled before it arrives, request 2 while it is being
+    stepped (it asks for 20,000 steps, seconds of work, and is cancelled 0.3 s
+    after arriving), request 4 by Server.cancel from another thread: each ends
+    with status CANCELLED and fewer steps than asked, the others complete
+    bitwise equal to the request run alone, and every byte of budget is
+    returned."""
+    import threading
+    import torch
+    from paper_1506_08435_amd import nnqp
+    from paper_1506_08435_amd.serve import CANCELLED, Server, solve_alone
+    reqs = _requests(6, steps=3, gap=0.001, seed=11)
+    reqs[1].cancel_at = 0.0
+    reqs[2].steps = 20000
+    reqs[2].cancel_at = reqs[2].arrival + 0.3
+    reqs[4].steps = 20000
+    srv = Server(keep_states=True, tol=1e-10, inner_rtol=0.1)
+    timer = threading.Timer(0.3, srv.cancel, args=(reqs[4].rid,))
+    timer.start()
+    try:
+        rep = srv.run(reqs)
+    finally:
+        timer.cancel()
+    by = {r.rid: r for r in rep.results}
+    for k in (1, 2, 4):
+        assert by[k].status == CANCELLED, (k, by[k].status)
+        assert len(by[k].step_stats) < reqs[k].steps
+    assert len(by[1].step_stats) == 0
+    assert rep.summary()["cancelled"] == 3
+    assert rep.final_bytes == 0
+    ctx = nnqp.Context(0)
+    for k in (0, 3, 5):
+        assert by[k].status == 0
+        c_alone, _ = solve_alone(reqs[k], tol=1e-10, inner_rtol=0.1, ctx=ctx,
+                                 single=srv.is_solo(reqs[k]))
+        assert torch.equal(by[k].c, c_alone), k
