@@ -308,6 +308,152 @@ __device__ __forceinline__ double bsell_row(const BDev &B, const VT *__restrict_
     return acc;
 }
 
+#ifndef NNQP_BATCH_FLAT8
+#define NNQP_BATCH_FLAT8 1   // slices of width <= 8: every load of the row issued before any use
+#endif
+
+// The row sum of gsell_row_at for slices of width w <= 8 (2D P1 rows),
+// written so that no load waits for another: every matrix load of the row is
+// issued under wave-uniform guards that only move raw bits (no column is
+// decoded inside a guard, which would make the compiler wait for that load
+// there), then every gather is issued, then the products are added in entry
+// order.  A slot past the row's entries keeps offset 0 (column i, a valid
+// row) or column i, and value 0, and its product is not added (a select, so
+// a non-finite x_i cannot leak in): the sum is bitwise the one of the
+// guarded walk, entry by entry with fused multiply-adds.  On the 512-member
+// batch the row pass went from 95 to 73 us (float64) and from 76 to 55 us
+// (mixed): the guarded walk waited for every pair's offsets and for every
+// gather in turn.
+template <int CM, class VT, class X>
+__device__ __forceinline__ double gsell_row8(const BDev &B, const VT *__restrict__ sv, int i,
+                                             int off, int w, X x)
+{
+    const int lane = threadIdx.x & 63;
+    const short *__restrict__ gd = B.gd16;
+    double acc = 0.0;
+    if constexpr (CM == CM_Q4) {
+        // quads 0 and 1 (entries 0-7), the pair left over (two entries
+        // after the quads), the odd last entry: the entry order
+        const int nq = w >> 2, rem = w & 3;
+        VT q[2][4];
+        int2 dq[2];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            if (k < nq) {
+                const int e = off + k * 4 * kSlice + 4 * lane;
+                bld_quad(sv + e, q[k]);
+                dq[k] = *reinterpret_cast<const int2 *>(gd + e);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; t++) q[k][t] = VT(0);
+                dq[k] = make_int2(0, 0);
+            }
+        }
+        VT pa = VT(0), pb = VT(0), so = VT(0);
+        int dp = 0, dso = 0;
+        if (rem >= 2) {
+            const int e = off + nq * 4 * kSlice + 2 * lane;
+            bld_pair(sv + e, pa, pb);
+            dp = *reinterpret_cast<const int *>(gd + e);
+        }
+        if (rem & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            so = bld_val(sv + e);
+            dso = gd[e];
+        }
+        double xv[11];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            xv[4 * k] = x(i + (int)(short)(dq[k].x & 0xffff));
+            xv[4 * k + 1] = x(i + (dq[k].x >> 16));
+            xv[4 * k + 2] = x(i + (int)(short)(dq[k].y & 0xffff));
+            xv[4 * k + 3] = x(i + (dq[k].y >> 16));
+        }
+        xv[8] = x(i + (int)(short)(dp & 0xffff));
+        xv[9] = x(i + (dp >> 16));
+        xv[10] = x(i + dso);
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const double y = __builtin_fma((double)q[k][t], xv[4 * k + t], acc);
+                acc = k < nq ? y : acc;
+            }
+        const double y8 = __builtin_fma((double)pa, xv[8], acc);
+        acc = rem >= 2 ? y8 : acc;
+        const double y9 = __builtin_fma((double)pb, xv[9], acc);
+        acc = rem >= 2 ? y9 : acc;
+        const double y10 = __builtin_fma((double)so, xv[10], acc);
+        acc = (rem & 1) ? y10 : acc;
+        return acc;
+    } else if constexpr (CM == CM_P2) {
+        // pairs 0-3 (entries 0-7), the odd last entry
+        const int np = w >> 1;
+        VT v[4][2];
+        int d[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (k < np) {
+                const int e = off + k * 2 * kSlice + 2 * lane;
+                bld_pair(sv + e, v[k][0], v[k][1]);
+                d[k] = *reinterpret_cast<const int *>(gd + e);
+            } else {
+                v[k][0] = v[k][1] = VT(0);
+                d[k] = 0;
+            }
+        }
+        VT so = VT(0);
+        int dso = 0;
+        if (w & 1) {
+            const int e = off + (w - 1) * kSlice + lane;
+            so = bld_val(sv + e);
+            dso = gd[e];
+        }
+        double xv[9];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            xv[2 * k] = x(i + (int)(short)(d[k] & 0xffff));
+            xv[2 * k + 1] = x(i + (d[k] >> 16));
+        }
+        xv[8] = x(i + dso);
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                const double y = __builtin_fma((double)v[k][t], xv[2 * k + t], acc);
+                acc = k < np ? y : acc;
+            }
+        const double y8 = __builtin_fma((double)so, xv[8], acc);
+        acc = (w & 1) ? y8 : acc;
+        return acc;
+    } else {
+        // column-major entries 0-7 (int32 global columns or int16 offsets)
+        const int *__restrict__ gc = B.gcol;
+        VT v[8];
+        int cc[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (k < w) {
+                const int e = off + k * kSlice + lane;
+                v[k] = bld_val(sv + e);
+                cc[k] = CM == CM_D16 ? (int)gd[e] : gc[e];
+            } else {
+                v[k] = VT(0);
+                cc[k] = CM == CM_D16 ? 0 : i;
+            }
+        }
+        double xv[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) xv[k] = x(CM == CM_D16 ? i + cc[k] : cc[k]);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const double y = __builtin_fma((double)v[k], xv[k], acc);
+            acc = k < w ? y : acc;
+        }
+        return acc;
+    }
+}
+
 // Row sums over the concatenated matrix for global row i = s*64 + lane of a
 // slice whose first entry (off) and width (w) are known; global columns
 // (int16 offsets from the row in CM_D16 mode).
@@ -315,6 +461,7 @@ template <int WMAX, int CM, class VT, class X>
 __device__ __forceinline__ double gsell_row_at(const BDev &B, const VT *__restrict__ sv, int i,
                                                int off, int w, X x)
 {
+    if constexpr (WMAX == 8 && NNQP_BATCH_FLAT8) return gsell_row8<CM>(B, sv, i, off, w, x);
     const int lane = threadIdx.x & 63;
     const int *__restrict__ gc = B.gcol;
     const short *__restrict__ gd = B.gd16;
@@ -628,6 +775,9 @@ __global__ __launch_bounds__(kFinBlock) void kb_reduce_init(BDev B)
 
 // ---------------------------------------------------------------- global step
 // Row pass: per listed slice, the matrix pass of the member's phase.
+// (Compiled for eight waves per SIMD, i.e. at most 64 VGPRs, the 512-member
+// batch's pass took 81 instead of 74 us in float64 and 70 instead of 55 us in
+// mixed precision: the compiler then waits for loads earlier.)
 //   GRAD    g = K c - f (float64 values); |pg|^2, #non-finite, ||min(c,g)||_inf,
 //           min c, #(c == 0)
 //   CAUCHY  s = P(c + ttrial g) - c gathered, ks = K s into buffer ksbuf;
@@ -644,17 +794,24 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
     const double *__restrict__ c = B.cg;
     int k = blockIdx.x * wpb + wid;
     // Software pipeline over the wavefront's slices: the record of the slice
-    // after next and the phase of the next one are fetched while this slice
-    // works, so a slice starts with its matrix loads.
+    // after next, and the phase, CG state and free-row mask of the next one,
+    // are fetched while this slice works, so a slice starts with its matrix
+    // loads.  (No pass of this kernel writes them.)
     SRec r1 = k < nlist ? B.srec[k] : SRec{0, 0, 0, 0};
     SRec r2 = k + nw < nlist ? B.srec[k + nw] : SRec{0, 0, 0, 0};
     int ph1 = k < nlist ? B.st[r1.p].phase : PH_DONE;
+    int cd1 = k < nlist ? B.st[r1.p].cgdone : 1;
+    uint8_t m1 = k < nlist ? V.mask[r1.s * kSlice + lane] : 0;
     for (; k < nlist; k += nw) {
         const SRec R = r1;
         const int ph = ph1;
+        const int cgdone = cd1;
+        const bool free_row = m1 != 0;
         if (k + nw < nlist) {
             r1 = r2;
             ph1 = B.st[r1.p].phase;
+            cd1 = B.st[r1.p].cgdone;
+            m1 = V.mask[r1.s * kSlice + lane];
             if (k + 2 * nw < nlist) r2 = B.srec[k + 2 * nw];
         }
         const int s = R.s;
@@ -695,11 +852,11 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
                 a[2] = si * si;
             }
         } else if (ph == PH_CG) {
-            const bool live = S.cgdone == 0 && row && V.mask[i] != 0;
+            const bool live = cgdone == 0 && row && free_row;
             if (__ballot(live) != 0) {
                 const VV *__restrict__ z = V.z;
                 // float64 vectors: the own-row values load before the gathers
-                // (2 % faster on the 512-member batch; 6 % slower with
+                // (2 % faster on the 512-member batch; 5 % slower with
                 // float32 vectors, which load them after)
                 VV pold = VV(0), qold = VV(0), zi = VV(0);
                 if constexpr (sizeof(VV) == 8) {
@@ -726,7 +883,7 @@ __global__ void kb_rows(BDev B, const VT *__restrict__ gvals, BVec<VV> V)
                 }
             }
         } else if (ph == PH_SEARCH) {
-            const bool live = row && V.mask[i] != 0;
+            const bool live = row && free_row;
             if (__ballot(live) != 0) {
                 const double t = S.ts;
                 const VV *__restrict__ w = V.w;
@@ -940,16 +1097,21 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
     const int nw = gridDim.x * wpb;
     const int nlist = B.cnt[0];
     int k = blockIdx.x * wpb + wid;
-    // the same pipeline over the slice records as the row pass
+    // the same pipeline over the slice records as the row pass; the mask of
+    // the next slice is read ahead too (only a set-up writes a mask, and only
+    // its own slice's, which it does not read)
     SRec r1 = k < nlist ? B.srec[k] : SRec{0, 0, 0, 0};
     SRec r2 = k + nw < nlist ? B.srec[k + nw] : SRec{0, 0, 0, 0};
     int op1 = k < nlist ? B.st[r1.p].vop : VO_NONE;
+    uint8_t m1 = k < nlist ? V.mask[r1.s * kSlice + lane] : 0;
     for (; k < nlist; k += nw) {
         const SRec R = r1;
         const int vop = op1;
+        const bool free_row = m1 != 0;
         if (k + nw < nlist) {
             r1 = r2;
             op1 = B.st[r1.p].vop;
+            m1 = V.mask[r1.s * kSlice + lane];
             if (k + 2 * nw < nlist) r2 = B.srec[k + 2 * nw];
         }
         if (vop == VO_NONE) continue;
@@ -986,7 +1148,7 @@ __global__ void kb_vec(BDev B, BVec<VV> V)
                 a[3] = fr ? (double)B.rlen[i] : 0.0;
             }
         } else if (vop == VO_UPDATE) {
-            if (row && V.mask[i]) {
+            if (row && free_row) {
                 const double alpha = S.alpha;
                 const VV ri = (VV)((double)V.r[i] - alpha * (double)V.q[i]);
                 const VV zi = V.dm[i] * ri;

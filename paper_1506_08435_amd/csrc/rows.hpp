@@ -179,19 +179,90 @@ __device__ __forceinline__ void ld_pair(const double *p, double &a, double &b)
 // NS slices in flight at once, issues the slice offsets and the own-row loads
 // of pre() before any gather, and loads entries eight at a time (all eight
 // before their gathers, which keeps the kernels under 64 VGPRs).  Slices wider
-// than WMAX finish in a plain loop.
+// than WMAX finish in a plain loop.  The single-product walks of the paired
+// and quad layouts take slices up to WMAX wide with pair_row_flat and
+// quad_row_flat, which keep every load of a phase in flight together.
 #ifndef NNQP_SLICES_IN_FLIGHT
 #define NNQP_SLICES_IN_FLIGHT 1
 #endif
 #ifndef NNQP_LOAD_PHASE
 #define NNQP_LOAD_PHASE 8
 #endif
+#ifndef NNQP_FLAT_PAIRS
+#define NNQP_FLAT_PAIRS 1   // paired layout: pair_row_flat for slices of width <= WMAX
+#endif
 // Paired layout (ColsD16P): the pair (2k, 2k+1) of the row of lane l sits at
 // off + 128 k + 2 l, so one 8-byte (float32) or 16-byte (float64) load brings
 // both values and one 4-byte load both offsets; an odd last column stays
-// column-major and is loaded after the pairs (loading it with the last pairs
-// holds more registers and, for float64 values, costs a wave per SIMD: the
-// 128^3 CG matrix pass went from 78 to 100 us).
+// column-major and is loaded after the pairs in the guarded walk (loading it
+// with the last pairs there held more registers and, for float64 values,
+// cost a wave per SIMD: the 128^3 CG matrix pass went from 78 to 100 us).
+//
+// The row sum of sell_rows_paired for a slice of width w <= WMAX, written as
+// quad_row_flat (below): HP pairs per phase, the odd last entry in the last
+// phase, loads under guards that only move raw bits, gathers unconditional,
+// products added in entry order with selects.  One pair per phase measured
+// best on the 128^3 float64 CG pass: 70.7-71.7 us, against 74.6-75.9 us for
+// the guarded walk, 73.9-75.4 us with two pairs and 74.8 us with four pairs
+// per phase (65 VGPRs, seven waves per SIMD).
+template <int WMAX, int HP, class VT, class X>
+__device__ __forceinline__ double pair_row_flat(const VT *__restrict__ sv,
+                                                const short *__restrict__ d16, int off, int w,
+                                                int row, X x)
+{
+    const int lane = threadIdx.x & 63;
+    const int np = w >> 1;
+    constexpr int NP = WMAX / 2 > 0 ? WMAX / 2 : 1;   // pairs of the widest slice
+    double acc = 0.0;
+#pragma unroll
+    for (int h0 = 0; h0 < NP; h0 += HP) {
+        const bool last = h0 + HP >= NP;
+        if (!last && h0 >= np) continue;   // wave-uniform
+        VT v[HP][2];
+        int d[HP];
+#pragma unroll
+        for (int k = 0; k < HP; k++) {
+            if (h0 + k < np) {
+                const int e = off + (h0 + k) * 2 * kSlice + 2 * lane;
+                ld_pair(sv + e, v[k][0], v[k][1]);
+                d[k] = *reinterpret_cast<const int *>(d16 + e);
+            } else {
+                v[k][0] = v[k][1] = VT(0);
+                d[k] = 0;
+            }
+        }
+        VT sg = VT(0);
+        int dsg = 0;
+        if (last && (w & 1)) {
+            const int e = off + (w - 1) * kSlice + lane;
+            sg = ld_val(sv + e);
+            dsg = d16[e];
+        }
+        double xv[2 * HP];
+#pragma unroll
+        for (int k = 0; k < HP; k++) {
+            xv[2 * k] = x(row + (int)(short)(d[k] & 0xffff));
+            xv[2 * k + 1] = x(row + (d[k] >> 16));
+        }
+        const double xs = last ? x(row + dsg) : 0.0;
+#pragma unroll
+        for (int k = 0; k < HP; k++)
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                const double y = __builtin_fma((double)v[k][t], xv[2 * k + t], acc);
+                acc = h0 + k < np ? y : acc;
+            }
+        if (last) {
+            const double y = __builtin_fma((double)sg, xs, acc);
+            acc = (w & 1) ? y : acc;
+        }
+    }
+    return acc;
+}
+
+#ifndef NNQP_PAIR_FLAT_PHASE
+#define NNQP_PAIR_FLAT_PHASE 2   // entries per load phase of pair_row_flat
+#endif
 template <int WMAX, class VT, class Act, class Pre, class X, class Epi>
 __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__restrict__ so,
                                                  ColsD16P sc, const VT *__restrict__ sv,
@@ -208,6 +279,12 @@ __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__res
         const bool act = row < P.n && active(row);
         const PV pv = act ? pre(row) : PV();
         if (__ballot(act) == 0) continue;
+        if (NNQP_FLAT_PAIRS && w <= WMAX) {
+            constexpr int HP = (WMAX < NNQP_PAIR_FLAT_PHASE ? WMAX : NNQP_PAIR_FLAT_PHASE) / 2;
+            const double acc = pair_row_flat<WMAX, HP>(sv, sc.d, off, w, row, x);
+            if (act) epi(row, acc, pv);
+            continue;
+        }
         double acc = 0.0;
         constexpr int H = (WMAX < NNQP_LOAD_PHASE ? WMAX : NNQP_LOAD_PHASE) / 2;   // pairs per phase
 #pragma unroll
@@ -251,10 +328,12 @@ __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__res
 // column-major place.  A 3D row of 15 entries takes five value loads (three
 // quads, a pair, a single) instead of eight in the paired layout: the
 // float32 passes are bound by load instructions more than by bytes.
-// Entries per load phase of the quad walker, and the non-temporal hint on its
-// loads (bit 0: values, bit 1: offsets).  On the 128^3 float32 CG pass (per
-// launch): 8 entries, no hint 49.3 us; 4 entries 50.1 us; 16 entries 71.6 us
-// (80 VGPRs, six waves per SIMD); hint on values 55.7 us, on both 59.1 us.
+// Entries per load phase of the guarded quad walker (slices wider than the
+// unrolled part, and the multi-trial passes), and the non-temporal hint on
+// the quad loads (bit 0: values, bit 1: offsets).  Measured on the 128^3
+// float32 CG pass with the guarded walk (per launch): 8 entries, no hint
+// 49.3 us; 4 entries 50.1 us; 16 entries 71.6 us (80 VGPRs, six waves per
+// SIMD); hint on values 55.7 us, on both 59.1 us.
 #ifndef NNQP_QUAD_PHASE
 #define NNQP_QUAD_PHASE NNQP_LOAD_PHASE
 #endif
@@ -276,6 +355,101 @@ __device__ __forceinline__ int2 ld_quad_d(const short *p)
     return make_int2(v.x, v.y);
 }
 
+// The row sum of sell_rows_quad for a slice of width w <= WMAX, phase by
+// phase with no load waiting for another: the quads of a phase (and, in the
+// last phase, the pair and the single left over) are loaded under
+// wave-uniform guards that only move raw bits, so the compiler has no reason
+// to wait for them there; then every gather of the phase is issued, then the
+// products are added in entry order with fused multiply-adds.  A slot past
+// the row's entries keeps offset 0 (column row, a valid index) and value 0,
+// and its product is not added (a select), so the sum is bitwise the one of
+// the guarded walk.  (Decoding the columns inside the guards made every
+// quad and every gather a round trip of its own.)  On the 128^3 float32 CG
+// pass: one quad per phase 39.9-40.1 us (64 VGPRs), two 49.0 us and four
+// 50.1 us (80 VGPRs, six waves per SIMD), the guarded walk 46.5 us.
+#ifndef NNQP_FLAT_ROWS
+#define NNQP_FLAT_ROWS 1
+#endif
+#ifndef NNQP_QUAD_FLAT_PHASE
+#define NNQP_QUAD_FLAT_PHASE 4   // entries per load phase of quad_row_flat
+#endif
+template <int WMAX, int HQ, class X>
+__device__ __forceinline__ double quad_row_flat(const float *__restrict__ sv,
+                                                const short *__restrict__ d16, int off, int w,
+                                                int row, X x)
+{
+    const int lane = threadIdx.x & 63;
+    const int nq = w >> 2, rem = w & 3;
+    constexpr int NQ = WMAX / 4 > 0 ? WMAX / 4 : 1;   // quads of the widest slice
+    double acc = 0.0;
+#pragma unroll
+    for (int h0 = 0; h0 < NQ; h0 += HQ) {
+        const bool last = h0 + HQ >= NQ;
+        if (!last && h0 >= nq) continue;   // wave-uniform
+        float q[HQ][4];
+        int2 dq[HQ];
+#pragma unroll
+        for (int k = 0; k < HQ; k++) {
+            if (h0 + k < nq) {
+                const int e = off + (h0 + k) * 4 * kSlice + 4 * lane;
+                const float4 v = ld_quad(sv + e);
+                dq[k] = ld_quad_d(d16 + e);
+                q[k][0] = v.x;
+                q[k][1] = v.y;
+                q[k][2] = v.z;
+                q[k][3] = v.w;
+            } else {
+                q[k][0] = q[k][1] = q[k][2] = q[k][3] = 0.f;
+                dq[k] = make_int2(0, 0);
+            }
+        }
+        float pa = 0.f, pb = 0.f, sg = 0.f;
+        int dp = 0, dsg = 0;
+        if (last) {
+            if (rem >= 2) {
+                const int e = off + nq * 4 * kSlice + 2 * lane;
+                ld_pair(sv + e, pa, pb);
+                dp = *reinterpret_cast<const int *>(d16 + e);
+            }
+            if (rem & 1) {
+                const int e = off + (w - 1) * kSlice + lane;
+                sg = ld_val(sv + e);
+                dsg = d16[e];
+            }
+        }
+        double xv[4 * HQ];
+#pragma unroll
+        for (int k = 0; k < HQ; k++) {
+            xv[4 * k] = x(row + (int)(short)(dq[k].x & 0xffff));
+            xv[4 * k + 1] = x(row + (dq[k].x >> 16));
+            xv[4 * k + 2] = x(row + (int)(short)(dq[k].y & 0xffff));
+            xv[4 * k + 3] = x(row + (dq[k].y >> 16));
+        }
+        double xp = 0.0, xq = 0.0, xs = 0.0;
+        if (last) {
+            xp = x(row + (int)(short)(dp & 0xffff));
+            xq = x(row + (dp >> 16));
+            xs = x(row + dsg);
+        }
+#pragma unroll
+        for (int k = 0; k < HQ; k++)
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const double y = __builtin_fma((double)q[k][t], xv[4 * k + t], acc);
+                acc = h0 + k < nq ? y : acc;
+            }
+        if (last) {
+            const double y0 = __builtin_fma((double)pa, xp, acc);
+            acc = rem >= 2 ? y0 : acc;
+            const double y1 = __builtin_fma((double)pb, xq, acc);
+            acc = rem >= 2 ? y1 : acc;
+            const double y2 = __builtin_fma((double)sg, xs, acc);
+            acc = (rem & 1) ? y2 : acc;
+        }
+    }
+    return acc;
+}
+
 template <int WMAX, class VT, class Act, class Pre, class X, class Epi>
 __device__ __forceinline__ void sell_rows_quad(const Part &P, const int *__restrict__ so,
                                                ColsD16Q sc, const VT *__restrict__ sv, Act active,
@@ -293,8 +467,14 @@ __device__ __forceinline__ void sell_rows_quad(const Part &P, const int *__restr
         const bool act = row < P.n && active(row);
         const PV pv = act ? pre(row) : PV();
         if (__ballot(act) == 0) continue;
-        double acc = 0.0;
         constexpr int HQ = (WMAX < NNQP_QUAD_PHASE ? WMAX : NNQP_QUAD_PHASE) / 4;   // quads per phase
+        if (NNQP_FLAT_ROWS && w <= WMAX) {
+            constexpr int HF = NNQP_QUAD_FLAT_PHASE / 4 > 0 ? NNQP_QUAD_FLAT_PHASE / 4 : 1;
+            const double acc = quad_row_flat<WMAX, HF>(sv, sc.d, off, w, row, x);
+            if (act) epi(row, acc, pv);
+            continue;
+        }
+        double acc = 0.0;
 #pragma unroll
         for (int h0 = 0; h0 < WMAX / 4; h0 += HQ) {
             int cc[4 * HQ];
