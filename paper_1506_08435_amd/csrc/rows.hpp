@@ -208,7 +208,7 @@ __device__ __forceinline__ void ld_pair(const double *p, double &a, double &b)
 template <int WMAX, int HP, class VT, class X>
 __device__ __forceinline__ double pair_row_flat(const VT *__restrict__ sv,
                                                 const short *__restrict__ d16, int off, int w,
-                                                int row, X x)
+                                                int row, int safe, X x)
 {
     const int lane = threadIdx.x & 63;
     const int np = w >> 1;
@@ -241,10 +241,11 @@ __device__ __forceinline__ double pair_row_flat(const VT *__restrict__ sv,
         double xv[2 * HP];
 #pragma unroll
         for (int k = 0; k < HP; k++) {
-            xv[2 * k] = x(row + (int)(short)(d[k] & 0xffff));
-            xv[2 * k + 1] = x(row + (d[k] >> 16));
+            const bool ok = h0 + k < np;
+            xv[2 * k] = x(ok ? row + (int)(short)(d[k] & 0xffff) : safe);
+            xv[2 * k + 1] = x(ok ? row + (d[k] >> 16) : safe);
         }
-        const double xs = last ? x(row + dsg) : 0.0;
+        const double xs = last ? x((w & 1) ? row + dsg : safe) : 0.0;
 #pragma unroll
         for (int k = 0; k < HP; k++)
 #pragma unroll
@@ -281,7 +282,8 @@ __device__ __forceinline__ void sell_rows_paired(const Part &P, const int *__res
         if (__ballot(act) == 0) continue;
         if (NNQP_FLAT_PAIRS && w <= WMAX) {
             constexpr int HP = (WMAX < NNQP_PAIR_FLAT_PHASE ? WMAX : NNQP_PAIR_FLAT_PHASE) / 2;
-            const double acc = pair_row_flat<WMAX, HP>(sv, sc.d, off, w, row, x);
+            const int safe = row < P.n ? row : P.n - 1;   // an index every vector has
+            const double acc = pair_row_flat<WMAX, HP>(sv, sc.d, off, w, row, safe, x);
             if (act) epi(row, acc, pv);
             continue;
         }
@@ -361,9 +363,10 @@ __device__ __forceinline__ int2 ld_quad_d(const short *p)
 // wave-uniform guards that only move raw bits, so the compiler has no reason
 // to wait for them there; then every gather of the phase is issued, then the
 // products are added in entry order with fused multiply-adds.  A slot past
-// the row's entries keeps offset 0 (column row, a valid index) and value 0,
-// and its product is not added (a select), so the sum is bitwise the one of
-// the guarded walk.  (Decoding the columns inside the guards made every
+// the slice's width gathers x(safe), where safe is the row itself or, for the
+// lanes past the last row, row n - 1 (an index every vector has), and its
+// product is not added (a select), so the sum is bitwise the one of the
+// guarded walk.  (Decoding the columns inside the guards made every
 // quad and every gather a round trip of its own.)  On the 128^3 float32 CG
 // pass: one quad per phase 39.9-40.1 us (64 VGPRs), two 49.0 us and four
 // 50.1 us (80 VGPRs, six waves per SIMD), the guarded walk 46.5 us.
@@ -376,7 +379,7 @@ __device__ __forceinline__ int2 ld_quad_d(const short *p)
 template <int WMAX, int HQ, class X>
 __device__ __forceinline__ double quad_row_flat(const float *__restrict__ sv,
                                                 const short *__restrict__ d16, int off, int w,
-                                                int row, X x)
+                                                int row, int safe, X x)
 {
     const int lane = threadIdx.x & 63;
     const int nq = w >> 2, rem = w & 3;
@@ -420,16 +423,17 @@ __device__ __forceinline__ double quad_row_flat(const float *__restrict__ sv,
         double xv[4 * HQ];
 #pragma unroll
         for (int k = 0; k < HQ; k++) {
-            xv[4 * k] = x(row + (int)(short)(dq[k].x & 0xffff));
-            xv[4 * k + 1] = x(row + (dq[k].x >> 16));
-            xv[4 * k + 2] = x(row + (int)(short)(dq[k].y & 0xffff));
-            xv[4 * k + 3] = x(row + (dq[k].y >> 16));
+            const bool ok = h0 + k < nq;
+            xv[4 * k] = x(ok ? row + (int)(short)(dq[k].x & 0xffff) : safe);
+            xv[4 * k + 1] = x(ok ? row + (dq[k].x >> 16) : safe);
+            xv[4 * k + 2] = x(ok ? row + (int)(short)(dq[k].y & 0xffff) : safe);
+            xv[4 * k + 3] = x(ok ? row + (dq[k].y >> 16) : safe);
         }
         double xp = 0.0, xq = 0.0, xs = 0.0;
         if (last) {
-            xp = x(row + (int)(short)(dp & 0xffff));
-            xq = x(row + (dp >> 16));
-            xs = x(row + dsg);
+            xp = x(rem >= 2 ? row + (int)(short)(dp & 0xffff) : safe);
+            xq = x(rem >= 2 ? row + (dp >> 16) : safe);
+            xs = x((rem & 1) ? row + dsg : safe);
         }
 #pragma unroll
         for (int k = 0; k < HQ; k++)
@@ -470,7 +474,8 @@ __device__ __forceinline__ void sell_rows_quad(const Part &P, const int *__restr
         constexpr int HQ = (WMAX < NNQP_QUAD_PHASE ? WMAX : NNQP_QUAD_PHASE) / 4;   // quads per phase
         if (NNQP_FLAT_ROWS && w <= WMAX) {
             constexpr int HF = NNQP_QUAD_FLAT_PHASE / 4 > 0 ? NNQP_QUAD_FLAT_PHASE / 4 : 1;
-            const double acc = quad_row_flat<WMAX, HF>(sv, sc.d, off, w, row, x);
+            const int safe = row < P.n ? row : P.n - 1;   // an index every vector has
+            const double acc = quad_row_flat<WMAX, HF>(sv, sc.d, off, w, row, safe, x);
             if (act) epi(row, acc, pv);
             continue;
         }
@@ -602,6 +607,151 @@ __device__ __forceinline__ void sell_rows(const Part &P, const int *__restrict__
     }
 }
 
+#ifndef NNQP_FLAT_MULTI
+#define NNQP_FLAT_MULTI 1   // the multi-product walks use the flat row sums below
+#endif
+// pair_row_flat and quad_row_flat for NT products at once: x(j, out) fills
+// NT values per gathered column; acc[t] is the row sum of product t, in the
+// same order and with the same fused multiply-adds as the guarded walks.
+template <int WMAX, int NT, int HP, class VT, class X>
+__device__ __forceinline__ void pair_row_flat_n(const VT *__restrict__ sv,
+                                                const short *__restrict__ d16, int off, int w,
+                                                int row, int safe, X x, double (&acc)[NT])
+{
+    const int lane = threadIdx.x & 63;
+    const int np = w >> 1;
+    constexpr int NP = WMAX / 2 > 0 ? WMAX / 2 : 1;
+#pragma unroll
+    for (int h0 = 0; h0 < NP; h0 += HP) {
+        const bool last = h0 + HP >= NP;
+        if (!last && h0 >= np) continue;   // wave-uniform
+        VT v[HP][2];
+        int d[HP];
+#pragma unroll
+        for (int k = 0; k < HP; k++) {
+            if (h0 + k < np) {
+                const int e = off + (h0 + k) * 2 * kSlice + 2 * lane;
+                ld_pair(sv + e, v[k][0], v[k][1]);
+                d[k] = *reinterpret_cast<const int *>(d16 + e);
+            } else {
+                v[k][0] = v[k][1] = VT(0);
+                d[k] = 0;
+            }
+        }
+        VT sg = VT(0);
+        int dsg = 0;
+        if (last && (w & 1)) {
+            const int e = off + (w - 1) * kSlice + lane;
+            sg = ld_val(sv + e);
+            dsg = d16[e];
+        }
+        double xv[2 * HP][NT];
+#pragma unroll
+        for (int k = 0; k < HP; k++) {
+            const bool ok = h0 + k < np;
+            x(ok ? row + (int)(short)(d[k] & 0xffff) : safe, xv[2 * k]);
+            x(ok ? row + (d[k] >> 16) : safe, xv[2 * k + 1]);
+        }
+        double xs[NT];
+        if (last) x((w & 1) ? row + dsg : safe, xs);
+#pragma unroll
+        for (int k = 0; k < HP; k++)
+#pragma unroll
+            for (int u = 0; u < 2; u++)
+#pragma unroll
+                for (int t = 0; t < NT; t++) {
+                    const double y = __builtin_fma((double)v[k][u], xv[2 * k + u][t], acc[t]);
+                    acc[t] = h0 + k < np ? y : acc[t];
+                }
+        if (last)
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const double y = __builtin_fma((double)sg, xs[t], acc[t]);
+                acc[t] = (w & 1) ? y : acc[t];
+            }
+    }
+}
+
+template <int WMAX, int NT, int HQ, class X>
+__device__ __forceinline__ void quad_row_flat_n(const float *__restrict__ sv,
+                                                const short *__restrict__ d16, int off, int w,
+                                                int row, int safe, X x, double (&acc)[NT])
+{
+    const int lane = threadIdx.x & 63;
+    const int nq = w >> 2, rem = w & 3;
+    constexpr int NQ = WMAX / 4 > 0 ? WMAX / 4 : 1;
+#pragma unroll
+    for (int h0 = 0; h0 < NQ; h0 += HQ) {
+        const bool last = h0 + HQ >= NQ;
+        if (!last && h0 >= nq) continue;   // wave-uniform
+        float q[HQ][4];
+        int2 dq[HQ];
+#pragma unroll
+        for (int k = 0; k < HQ; k++) {
+            if (h0 + k < nq) {
+                const int e = off + (h0 + k) * 4 * kSlice + 4 * lane;
+                const float4 v = ld_quad(sv + e);
+                dq[k] = ld_quad_d(d16 + e);
+                q[k][0] = v.x;
+                q[k][1] = v.y;
+                q[k][2] = v.z;
+                q[k][3] = v.w;
+            } else {
+                q[k][0] = q[k][1] = q[k][2] = q[k][3] = 0.f;
+                dq[k] = make_int2(0, 0);
+            }
+        }
+        float pa = 0.f, pb = 0.f, sg = 0.f;
+        int dp = 0, dsg = 0;
+        if (last) {
+            if (rem >= 2) {
+                const int e = off + nq * 4 * kSlice + 2 * lane;
+                ld_pair(sv + e, pa, pb);
+                dp = *reinterpret_cast<const int *>(d16 + e);
+            }
+            if (rem & 1) {
+                const int e = off + (w - 1) * kSlice + lane;
+                sg = ld_val(sv + e);
+                dsg = d16[e];
+            }
+        }
+        double xv[4 * HQ][NT];
+#pragma unroll
+        for (int k = 0; k < HQ; k++) {
+            const bool ok = h0 + k < nq;
+            x(ok ? row + (int)(short)(dq[k].x & 0xffff) : safe, xv[4 * k]);
+            x(ok ? row + (dq[k].x >> 16) : safe, xv[4 * k + 1]);
+            x(ok ? row + (int)(short)(dq[k].y & 0xffff) : safe, xv[4 * k + 2]);
+            x(ok ? row + (dq[k].y >> 16) : safe, xv[4 * k + 3]);
+        }
+        double xr[3][NT];
+        if (last) {
+            x(rem >= 2 ? row + (int)(short)(dp & 0xffff) : safe, xr[0]);
+            x(rem >= 2 ? row + (dp >> 16) : safe, xr[1]);
+            x((rem & 1) ? row + dsg : safe, xr[2]);
+        }
+#pragma unroll
+        for (int k = 0; k < HQ; k++)
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int t = 0; t < NT; t++) {
+                    const double y = __builtin_fma((double)q[k][u], xv[4 * k + u][t], acc[t]);
+                    acc[t] = h0 + k < nq ? y : acc[t];
+                }
+        if (last)
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const double y0 = __builtin_fma((double)pa, xr[0][t], acc[t]);
+                acc[t] = rem >= 2 ? y0 : acc[t];
+                const double y1 = __builtin_fma((double)pb, xr[1][t], acc[t]);
+                acc[t] = rem >= 2 ? y1 : acc[t];
+                const double y2 = __builtin_fma((double)sg, xr[2][t], acc[t]);
+                acc[t] = (rem & 1) ? y2 : acc[t];
+            }
+    }
+}
+
 // NT products in one pass: like sell_rows, with x(j, out) filling NT values
 // per gathered column and epi(i, acc[NT], pre(i)).  Entries are loaded eight
 // at a time before their gathers; one slice per wavefront in flight.
@@ -625,6 +775,13 @@ __device__ __forceinline__ void sell_rows_n_paired(const Part &P, const int *__r
         double acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; t++) acc[t] = 0.0;
+        if (NNQP_FLAT_MULTI && w <= WMAX) {
+            constexpr int HF = (WMAX < NNQP_PAIR_FLAT_PHASE ? WMAX : NNQP_PAIR_FLAT_PHASE) / 2;
+            const int safe = row < P.n ? row : P.n - 1;
+            pair_row_flat_n<WMAX, NT, HF>(sv, sc.d, off, w, row, safe, x, acc);
+            if (act) epi(row, acc, pv);
+            continue;
+        }
         constexpr int H = (WMAX < PHASE ? WMAX : PHASE) / 2;   // pairs per phase
         double xv[NT];
 #pragma unroll
@@ -693,6 +850,13 @@ __device__ __forceinline__ void sell_rows_n_quad(const Part &P, const int *__res
         double acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; t++) acc[t] = 0.0;
+        if (NNQP_FLAT_MULTI && w <= WMAX) {
+            constexpr int HF = NNQP_QUAD_FLAT_PHASE / 4 > 0 ? NNQP_QUAD_FLAT_PHASE / 4 : 1;
+            const int safe = row < P.n ? row : P.n - 1;
+            quad_row_flat_n<WMAX, NT, HF>(sv, sc.d, off, w, row, safe, x, acc);
+            if (act) epi(row, acc, pv);
+            continue;
+        }
         constexpr int HP = WMAX < PHASE ? WMAX : PHASE;
         constexpr int HQ = HP / 4 > 0 ? HP / 4 : 1;   // quads per phase
         double xv[NT];
