@@ -379,6 +379,43 @@ def test_kernel_timing_leaves_results_unchanged(ctx, batch_members):
           f"batch row passes {ktb['cg_spmv']['count']}")
 
 
+@pytest.mark.parametrize("cells", [20, 15])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_entries_past_the_last_row_are_never_used(ctx, precision, cells):
+    """c, f and the active flags as the first n entries of larger buffers
+    whose tails hold NaN / 0xAB: a solve and a transient step give bitwise
+    the results of exactly sized buffers and leave the tails untouched, so no
+    pass uses a value at, or writes to, an index at or past n.  20^3 cells:
+    6,859 rows (multi-block path, 11 rows in the last slice); 15^3 cells:
+    2,744 rows (the one-workgroup engine, 56 in the last slice)."""
+    import torch
+    from paper_1506_08435_amd import nnqp
+    prec = nnqp.NN_MIXED if precision == "mixed" else nnqp.NN_FP64
+    p = W.cube3d(cells)
+    K, F, _ = ctx.assemble(p, with_mass=True)
+    n = K.n
+    assert n % 64 != 0
+    opts = nnqp.default_opts(tol=1e-10, precision=prec)
+    c_ref, a_ref, st_ref = ctx.solve_nonneg(K, F, opts=opts)
+    tail = 64
+    fb = torch.full((n + tail,), float("nan"), dtype=torch.float64, device=ctx.device)
+    fb[:n] = F[:n]
+    cb = torch.full((n + tail,), float("nan"), dtype=torch.float64, device=ctx.device)
+    ab = torch.full((n + tail,), 0xAB, dtype=torch.uint8, device=ctx.device)
+    c, a, st = ctx.solve_nonneg(K, fb[:n], opts=opts, c=cb[:n], active=ab[:n])
+    assert st["kkt_rel"] <= 1e-10
+    assert torch.equal(c, c_ref) and torch.equal(a, a_ref)
+    assert torch.isnan(cb[n:]).all() and torch.isnan(fb[n:]).all()
+    assert (ab[n:] == 0xAB).all()
+    # one backward-Euler step from that state, both ways
+    c1 = c_ref.clone()
+    ctx.step_transient(K, 1e-3, F, c1, opts=opts)
+    ctx.step_transient(K, 1e-3, fb[:n], cb[:n], opts=opts)
+    assert torch.equal(cb[:n], c1)
+    assert torch.isnan(cb[n:]).all()
+    K.free()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_transient_snapshot_and_resume_bitwise(ctx, precision):
     """A transient run's state is c: copied to host memory after three steps,
