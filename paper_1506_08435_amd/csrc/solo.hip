@@ -67,10 +67,39 @@ constexpr int kSoloWaves = kSoloBlock / 64;
 constexpr int kSoloLdsRows = 4096;
 
 // Reduced values of a pass, the same in every thread: wavefront shuffles,
-// then the wavefronts' totals combined in wavefront order by thread k for
-// value k (a fixed order, so the result is reproducible).
+// then the wavefronts' totals combined in wavefront order (a fixed order, so
+// the result is reproducible).
+#ifndef NNQP_SOLO_ONE_BARRIER
+#define NNQP_SOLO_ONE_BARRIER 1
+#endif
+#if NNQP_SOLO_ONE_BARRIER
+// One barrier per reduction: the totals go to one of two halves of sh,
+// alternating between calls (parity, the same in every thread since every
+// thread makes the same calls), and every thread combines them itself, so a
+// half is written again only two reductions later, after the next barrier.
 template <uint32_t OPS, int NV>
-__device__ __forceinline__ void wg_reduce(double (&a)[NV], double *sh)
+__device__ __forceinline__ void wg_reduce(double (&a)[NV], double *sh, int &parity)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_red<OPS, NV>(a);
+    double *buf = sh + parity * (kSoloWaves * (kMaxRed + 1));
+    parity ^= 1;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; k++) buf[wid * (NV + 1) + k] = a[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        const int op = (int)((OPS >> (2 * k)) & 3u);
+        double v = buf[k];
+#pragma unroll
+        for (int w = 1; w < kSoloWaves; w++) v = red_comb(op, v, buf[w * (NV + 1) + k]);
+        a[k] = v;
+    }
+}
+#else
+template <uint32_t OPS, int NV>
+__device__ __forceinline__ void wg_reduce(double (&a)[NV], double *sh, int &)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     wave_red<OPS, NV>(a);
@@ -91,6 +120,7 @@ __device__ __forceinline__ void wg_reduce(double (&a)[NV], double *sh)
 #pragma unroll
     for (int k = 0; k < NV; k++) a[k] = sh[kSoloWaves * (NV + 1) + k];
 }
+#endif
 
 // Rows of the problem, slice by slice over the workgroup's wavefronts:
 // body(i, act) for row i = 64 s + lane of every slice s of this wavefront.
@@ -236,6 +266,7 @@ __device__ __forceinline__ bool ok_decrease(double gs, double sks)
 template <int WMAX, bool LDSV>
 __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *shbuf, double *lv)
 {
+    int par = 0;   // the half of shbuf the next reduction writes
     const int n = P.n;
     const double dn = n;
     SoloOut S = {};
@@ -264,7 +295,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                 C[i] = proj_box(cv, B);
             }
         }
-        wg_reduce<OPS4(OP_SUM, OP_MAX, OP_SUM, OP_SUM), 4>(a, shbuf);
+        wg_reduce<OPS4(OP_SUM, OP_MAX, OP_SUM, OP_SUM), 4>(a, shbuf, par);
         bytes += 16.0 * dn;
         S.norm_f = sqrt(a[0]);
         if (a[2] != 0.0 || a[3] != 0.0) {
@@ -297,7 +328,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                 a5[3] = fmin(a5[3], cv);
                 a5[4] += (cv == B.lo || cv == B.hi) ? 1.0 : 0.0;
             });
-            wg_reduce<OPS5(OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM), 5>(a5, shbuf);
+            wg_reduce<OPS5(OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM), 5>(a5, shbuf, par);
             S.spmvs++;
             bytes += spmv_b + 16.0 * dn;
             if (a5[1] != 0.0) {
@@ -328,7 +359,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                                   a3[0] += sg.b * sg.a;
                                   a3[1] += sg.a * s;
                               });
-                wg_reduce<OPS2(OP_SUM, OP_SUM), 2>(a3, shbuf);
+                wg_reduce<OPS2(OP_SUM, OP_SUM), 2>(a3, shbuf, par);
                 gs = a3[0];
                 sks = a3[1];
                 S.spmvs++;
@@ -395,7 +426,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                             u[2] += fr ? 1.0 : 0.0;
                             u[3] += fr ? (double)v.len : 0.0;
                         });
-            wg_reduce<0u, 4>(u, shbuf);
+            wg_reduce<0u, 4>(u, shbuf, par);
             bytes += 88.0 * dn;
             double rz = u[0], rr = u[1], rz_prev = 0.0;
             const double nf = u[2], nzf = u[3], rr_stop = O.rtol2 * u[1];
@@ -422,7 +453,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                                   P.q[i] = qi;
                                   pq[0] += pi * qi;
                               });
-                wg_reduce<0u, 1>(pq, shbuf);
+                wg_reduce<0u, 1>(pq, shbuf, par);
                 if (!(pq[0] > 0.0 && isfinite(pq[0]))) {
                     status = isfinite(pq[0]) ? NN_ENOTSPD : NN_ENONFINITE;
                     cg_fail = true;
@@ -445,7 +476,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                                 a2[0] += ri * zi;
                                 a2[1] += ri * ri;
                             });
-                wg_reduce<0u, 2>(a2, shbuf);
+                wg_reduce<0u, 2>(a2, shbuf, par);
                 rz_prev = rz;
                 rz = a2[0];
                 rr = a2[1];
@@ -467,7 +498,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                 b3[1] += G[i] * wi;
                 b3[2] += wi * wi;
             });
-            wg_reduce<OPS3(OP_MIN, OP_SUM, OP_SUM), 3>(b3, shbuf);
+            wg_reduce<OPS3(OP_MIN, OP_SUM, OP_SUM), 3>(b3, shbuf, par);
             bytes += 24.0 * dn;
             const double bmin = b3[0], gw = b3[1], wn = sqrt(b3[2]);
             if (it > 0 && gw < 0.0 && wn > 0.0) {
@@ -485,7 +516,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                                           a3[0] += sg.b * sg.a;
                                           a3[1] += sg.a * s;
                                       });
-                        wg_reduce<OPS2(OP_SUM, OP_SUM), 2>(a3, shbuf);
+                        wg_reduce<OPS2(OP_SUM, OP_SUM), 2>(a3, shbuf, par);
                         S.spmvs++;
                         S.search_trials++;
                         bytes += spmv_b + 16.0 * dn;
@@ -524,7 +555,7 @@ finish:
 template <int WMAX, bool LDSV>
 __global__ __launch_bounds__(kSoloBlock) void k_solo(SoloProb P, SoloOpts O, Box B)
 {
-    __shared__ double shbuf[(kSoloWaves + 1) * (kMaxRed + 1)];
+    __shared__ double shbuf[2 * kSoloWaves * (kMaxRed + 1)];
     if constexpr (LDSV) {
         __shared__ double lv[4 * kSoloLdsRows];
         solo_solve<WMAX, true>(P, O, B, shbuf, lv);
