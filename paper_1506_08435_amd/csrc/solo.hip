@@ -135,29 +135,28 @@ __device__ __forceinline__ void wg_rows(const SoloProb &P, Body body)
 }
 
 // Sliced-ELL product over the workgroup's slices: for each row i with
-// active(i), epi(i, sum over the row's entries of v * x(col), pre(i)).  The
-// passes of a small problem are bound by memory round trips, not bytes, so a
-// wavefront loads the offsets, entries and own-row values of its next slice
-// before it gathers and sums the current one.
+// mask[i] != 0 (every row without a mask), epi(i, sum over the row's entries
+// of v * x(col), pre(i)).  The passes of a small problem are bound by memory
+// round trips, not bytes (see wg_spmv).
 template <int WMAX>
 struct SliceEnt {
-    int off, w;
+    int w;
     int cc[WMAX];
     double vv[WMAX];
 };
 
+// The entries of the slice whose first entry and width are off and w: raw
+// words under wave-uniform guards (nothing here waits for them).
 template <int WMAX>
-__device__ __forceinline__ void load_slice(const SoloProb &P, int s, SliceEnt<WMAX> &e)
+__device__ __forceinline__ void load_slice(const SoloProb &P, int off, int w, SliceEnt<WMAX> &e)
 {
     const int lane = threadIdx.x & 63;
-    const bool has = s < P.nsl;
-    e.off = has ? P.so[s] : 0;
-    e.w = has ? (P.so[s + 1] - e.off) >> 6 : 0;
+    e.w = w;
 #pragma unroll
     for (int k = 0; k < WMAX; k++) {
-        if (k < e.w) {
-            e.cc[k] = P.sc[e.off + k * kSlice + lane];
-            e.vv[k] = P.v[e.off + k * kSlice + lane];
+        if (k < w) {
+            e.cc[k] = P.sc[off + k * kSlice + lane];
+            e.vv[k] = P.v[off + k * kSlice + lane];
         } else {
             e.cc[k] = 0;
             e.vv[k] = 0.0;
@@ -165,42 +164,64 @@ __device__ __forceinline__ void load_slice(const SoloProb &P, int s, SliceEnt<WM
     }
 }
 
-// Slices a wavefront loads ahead of the one it sums (slices up to 8 wide).
-// On the 64^2 square (3,969 rows, float64): one ahead 6.88 ms per solve, two
-// 7.25 ms, three 7.72 ms (more registers to carry, no fewer stalls).
+// First entry and width of slice s (width 0 past the last slice), from two
+// loads that need no guard.
+__device__ __forceinline__ void slice_span(const SoloProb &P, int s, int &off, int &w)
+{
+    const int a = s < P.nsl ? s : P.nsl, b = s + 1 < P.nsl ? s + 1 : P.nsl;
+    off = P.so[a];
+    w = (P.so[b] - off) >> 6;
+}
+
+// Slices a wavefront loads ahead of the one it sums (slices up to 8 wide;
+// wider ones one ahead, their entries take more registers).  On the 64^2
+// square (3,969 rows, float64): one ahead 6.14 ms per solve, two 6.44 ms,
+// three 6.66 ms.
 #ifndef NNQP_SOLO_AHEAD
 #define NNQP_SOLO_AHEAD 1
 #endif
-template <int WMAX, class Act, class Pre, class X, class Epi>
-__device__ __forceinline__ void wg_spmv(const SoloProb &P, Act active, Pre pre, X x, Epi epi)
+
+// mask: the free-row flags (null: every row).  A wavefront loads the slice
+// offsets D + 1 slices ahead and the entries, own-row values and flags of the
+// next D slices before it gathers and sums the current one; the own-row loads
+// take a row every vector has (row 0 past the end) and keep the raw flag, so
+// no load of a later slice is waited for before the current slice's sum.
+template <int WMAX, class Pre, class X, class Epi>
+__device__ __forceinline__ void wg_spmv(const SoloProb &P, const uint8_t *__restrict__ mask,
+                                        Pre pre, X x, Epi epi)
 {
     using PV = decltype(pre(0));
-    // wider slices hold more registers per slice: one ahead (two spill at 32)
     constexpr int D = WMAX <= 8 ? NNQP_SOLO_AHEAD : 1;
     static_assert(D >= 1, "at least the next slice is loaded ahead");
     const int lane = threadIdx.x & 63, wid = wave_id();
-    // the entries, own-row values and row flags of the next D slices are
-    // loaded before the current slice's gathers
-    SliceEnt<WMAX> buf[D + 1];
-    bool act[D + 1];
-    PV pv[D + 1];
-    auto own = [&](int s, bool &a, PV &v) {
+    struct Own {
+        bool in;
+        uint8_t flag;
+        PV pv;
+    };
+    auto own = [&](int s) {
         const int row = s * kSlice + lane;
         const bool in = s < P.nsl && row < P.n;
-        a = in && active(row);
-        v = in ? pre(row) : PV();
+        const int r = in ? row : 0;
+        return Own{in, mask ? mask[r] : (uint8_t)1, pre(r)};
     };
+    SliceEnt<WMAX> ent[D + 1];
+    Own ow[D + 1];
+    int off, w;
 #pragma unroll
     for (int t = 0; t < D; t++) {
-        load_slice<WMAX>(P, wid + t * kSoloWaves, buf[t]);
-        own(wid + t * kSoloWaves, act[t], pv[t]);
+        slice_span(P, wid + t * kSoloWaves, off, w);
+        load_slice<WMAX>(P, off, w, ent[t]);
+        ow[t] = own(wid + t * kSoloWaves);
     }
+    slice_span(P, wid + D * kSoloWaves, off, w);   // the span of the next slice to load
     for (int s = wid; s < P.nsl; s += kSoloWaves) {
-        load_slice<WMAX>(P, s + D * kSoloWaves, buf[D]);
-        own(s + D * kSoloWaves, act[D], pv[D]);
-        const SliceEnt<WMAX> &cur = buf[0];
-        const bool act_c = act[0];
-        const PV pv_c = pv[0];
+        int off2, w2;
+        slice_span(P, s + (D + 1) * kSoloWaves, off2, w2);
+        load_slice<WMAX>(P, off, w, ent[D]);
+        ow[D] = own(s + D * kSoloWaves);
+        const SliceEnt<WMAX> &cur = ent[0];
+        const bool act_c = ow[0].in && ow[0].flag != 0;
         if (__ballot(act_c) != 0) {
             // every gather issued before the first product is added: a slot
             // past the slice's width has column 0 (a valid row) and its
@@ -215,18 +236,23 @@ __device__ __forceinline__ void wg_spmv(const SoloProb &P, Act active, Pre pre, 
                 const double y = __builtin_fma(cur.vv[k], xv[k], acc);
                 acc = k < cur.w ? y : acc;
             }
-            for (int k = WMAX; k < cur.w; k++) {
-                const int e = cur.off + k * kSlice + lane;
-                acc += P.v[e] * x(P.sc[e]);
+            if (cur.w > WMAX) {   // slices wider than the unrolled part
+                int o, ww;
+                slice_span(P, s, o, ww);
+                for (int k = WMAX; k < ww; k++) {
+                    const int e = o + k * kSlice + lane;
+                    acc += P.v[e] * x(P.sc[e]);
+                }
             }
-            if (act_c) epi(s * kSlice + lane, acc, pv_c);
+            if (act_c) epi(s * kSlice + lane, acc, ow[0].pv);
         }
 #pragma unroll
         for (int t = 0; t < D; t++) {
-            buf[t] = buf[t + 1];
-            act[t] = act[t + 1];
-            pv[t] = pv[t + 1];
+            ent[t] = ent[t + 1];
+            ow[t] = ow[t + 1];
         }
+        off = off2;
+        w = w2;
     }
 }
 
@@ -317,7 +343,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
             // ---- 1. gradient g = K c - f and the KKT report
             double a5[5];
             red_init<OPS5(OP_SUM, OP_SUM, OP_MAX, OP_MIN, OP_SUM), 5>(a5);
-            wg_spmv<WMAX>(P, AllRows(), [&](int i) { return Two{C[i], P.f[i]}; },
+            wg_spmv<WMAX>(P, nullptr, [&](int i) { return Two{C[i], P.f[i]}; },
                           [&](int j) { return C[j]; }, [&](int i, double s, Two cf) {
                 const double gi = s - cf.b, cv = cf.a;
                 G[i] = gi;
@@ -353,7 +379,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                     return proj_box(cj - t * G[j], B) - cj;
                 };
                 double a3[2] = {0.0, 0.0};
-                wg_spmv<WMAX>(P, AllRows(), [&](int i) { return Two{sv(i), G[i]}; }, sv,
+                wg_spmv<WMAX>(P, nullptr, [&](int i) { return Two{sv(i), G[i]}; }, sv,
                               [&](int i, double s, Two sg) {
                                   P.ks[buf][i] = s;
                                   a3[0] += sg.b * sg.a;
@@ -444,8 +470,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                 const double beta = j == 0 ? 0.0 : rz / rz_prev;
                 // p <- z + beta p, q <- K z + beta q on the free rows (K p by linearity)
                 double pq[1] = {0.0};
-                wg_spmv<WMAX>(P, [&](int i) { return P.mask[i] != 0; },
-                              [&](int i) { return Three{P.p[i], P.q[i], Z[i]}; },
+                wg_spmv<WMAX>(P, P.mask, [&](int i) { return Three{P.p[i], P.q[i], Z[i]}; },
                               [&](int jj) { return Z[jj]; }, [&](int i, double kz, Three x) {
                                   const double pi = fma(beta, x.a, x.c);
                                   const double qi = fma(beta, x.b, kz);
@@ -510,8 +535,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                             return proj_box(cj + ts * Wv[j], B) - cj;
                         };
                         double a3[2] = {0.0, 0.0};
-                        wg_spmv<WMAX>(P, [&](int i) { return P.mask[i] != 0; },
-                                      [&](int i) { return Two{sv(i), G[i]}; }, sv,
+                        wg_spmv<WMAX>(P, P.mask, [&](int i) { return Two{sv(i), G[i]}; }, sv,
                                       [&](int, double s, Two sg) {
                                           a3[0] += sg.b * sg.a;
                                           a3[1] += sg.a * s;
