@@ -63,8 +63,14 @@ struct SoloOpts {
 // wavefront may hold up to 256 registers and keep many slices in flight.
 constexpr int kSoloBlock = 512;
 constexpr int kSoloWaves = kSoloBlock / 64;
-// problems up to this many rows keep the gathered vectors in LDS (4 x 32 KiB)
+// Vectors in LDS: problems up to kSoloLdsRows rows keep c, g, z and w there
+// (4 x 32 KiB); up to kSoloLdsRows5 rows also q (five vectors of 4,032 rows
+// and the reduction buffer fill the 160 KiB of a CU; on the 64^2 square
+// 6.31 -> 5.98 ms per solve).
 constexpr int kSoloLdsRows = 4096;
+constexpr int kSoloLdsRows5 = 4032;
+// rows per LDS vector of the variant that keeps nv vectors there
+__host__ __device__ constexpr int solo_lds_rows(int nv) { return nv == 5 ? kSoloLdsRows5 : kSoloLdsRows; }
 
 // Reduced values of a pass, the same in every thread: wavefront shuffles,
 // then the wavefronts' totals combined in wavefront order (a fixed order, so
@@ -284,12 +290,13 @@ __device__ __forceinline__ bool ok_decrease(double gs, double sks)
     return gs < 0.0 && gs + 0.5 * sks <= kMu0 * gs;
 }
 
-// The whole solve of one problem by the calling workgroup.  LDSV: the four
-// vectors the passes gather (c, g, the CG vector z and the CG step w) live in
-// the workgroup's LDS `lv` ([4][kSoloLdsRows]) for the whole solve, so a
-// gather costs an LDS access instead of a cache round trip; c is read from
-// and written back to global memory at the start and the end.
-template <int WMAX, bool LDSV>
+// The whole solve of one problem by the calling workgroup.  LDSV = 4: the
+// four vectors the passes gather (c, g, the CG vector z and the CG step w)
+// live in the workgroup's LDS `lv` ([4][kSoloLdsRows]) for the whole solve,
+// so a gather costs an LDS access instead of a cache round trip; c is read
+// from and written back to global memory at the start and the end.  LDSV =
+// 5: q as well ([5][kSoloLdsRows5]).  LDSV = 0: every vector in global memory.
+template <int WMAX, int LDSV>
 __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *shbuf, double *lv)
 {
     int par = 0;   // the half of shbuf the next reduction writes
@@ -299,10 +306,12 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
     int status = NN_EMAXIT;
     double bytes = 0.0;
     const double spmv_b = 4.0 * (dn + 1) + 12.0 * (P.rp[n] - P.rp[0]) + 16.0 * dn;
+    constexpr int LR = solo_lds_rows(LDSV);
     double *const C = LDSV ? lv : P.c;
-    double *const G = LDSV ? lv + kSoloLdsRows : P.g;
-    double *const Z = LDSV ? lv + 2 * kSoloLdsRows : P.z;
-    double *const Wv = LDSV ? lv + 3 * kSoloLdsRows : P.w;
+    double *const G = LDSV ? lv + LR : P.g;
+    double *const Z = LDSV ? lv + 2 * LR : P.z;
+    double *const Wv = LDSV ? lv + 3 * LR : P.w;
+    double *const Q = LDSV == 5 ? lv + 4 * LR : P.q;
 
     // ---- start point and load statistics
     {
@@ -445,7 +454,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                             P.r[i] = ri;
                             Z[i] = zi;
                             P.p[i] = 0.0;
-                            P.q[i] = 0.0;
+                            Q[i] = 0.0;
                             Wv[i] = 0.0;
                             u[0] += ri * zi;
                             u[1] += ri * ri;
@@ -470,12 +479,12 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                 const double beta = j == 0 ? 0.0 : rz / rz_prev;
                 // p <- z + beta p, q <- K z + beta q on the free rows (K p by linearity)
                 double pq[1] = {0.0};
-                wg_spmv<WMAX>(P, P.mask, [&](int i) { return Three{P.p[i], P.q[i], Z[i]}; },
+                wg_spmv<WMAX>(P, P.mask, [&](int i) { return Three{P.p[i], Q[i], Z[i]}; },
                               [&](int jj) { return Z[jj]; }, [&](int i, double kz, Three x) {
                                   const double pi = fma(beta, x.a, x.c);
                                   const double qi = fma(beta, x.b, kz);
                                   P.p[i] = pi;
-                                  P.q[i] = qi;
+                                  Q[i] = qi;
                                   pq[0] += pi * qi;
                               });
                 wg_reduce<0u, 1>(pq, shbuf, par);
@@ -490,7 +499,7 @@ __device__ void solo_solve(const SoloProb &P, const SoloOpts &O, Box B, double *
                     double r, q, dm, p;
                     int m;
                 };
-                wg_rows2<4>(P, [&](int i) { return UV{P.r[i], P.q[i], P.dm[i], P.p[i], P.mask[i]}; },
+                wg_rows2<4>(P, [&](int i) { return UV{P.r[i], Q[i], P.dm[i], P.p[i], P.mask[i]}; },
                             [&](int i, const UV &v) {
                                 if (!v.m) return;
                                 const double ri = v.r - alpha * v.q;
@@ -576,15 +585,15 @@ finish:
     }
 }
 
-template <int WMAX, bool LDSV>
+template <int WMAX, int LDSV>
 __global__ __launch_bounds__(kSoloBlock) void k_solo(SoloProb P, SoloOpts O, Box B)
 {
     __shared__ double shbuf[2 * kSoloWaves * (kMaxRed + 1)];
-    if constexpr (LDSV) {
-        __shared__ double lv[4 * kSoloLdsRows];
-        solo_solve<WMAX, true>(P, O, B, shbuf, lv);
+    if constexpr (LDSV > 0) {
+        __shared__ double lv[LDSV * solo_lds_rows(LDSV)];
+        solo_solve<WMAX, LDSV>(P, O, B, shbuf, lv);
     } else {
-        solo_solve<WMAX, false>(P, O, B, shbuf, nullptr);
+        solo_solve<WMAX, 0>(P, O, B, shbuf, nullptr);
     }
 }
 
@@ -639,15 +648,18 @@ nn_status solo_solve_impl(nn_ctx *ctx, const nn_matrix *A, const double *vals, c
     box.lo = o->lower;
     box.hi = o->upper;
     NN_HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    const bool lds = n <= kSoloLdsRows;
+    const int lds = n <= kSoloLdsRows5 ? 5 : (n <= kSoloLdsRows ? 4 : 0);
 #define NN_SOLO_LAUNCH(WM)                                                                       \
     do {                                                                                         \
-        if (lds)                                                                                 \
-            hipLaunchKernelGGL((k_solo<WM, true>), dim3(1), dim3(kSoloBlock), 0, ctx->stream, P, \
+        if (lds == 5)                                                                            \
+            hipLaunchKernelGGL((k_solo<WM, 5>), dim3(1), dim3(kSoloBlock), 0, ctx->stream, P,    \
+                               O, box);                                                          \
+        else if (lds == 4)                                                                       \
+            hipLaunchKernelGGL((k_solo<WM, 4>), dim3(1), dim3(kSoloBlock), 0, ctx->stream, P,    \
                                O, box);                                                          \
         else                                                                                     \
-            hipLaunchKernelGGL((k_solo<WM, false>), dim3(1), dim3(kSoloBlock), 0, ctx->stream,   \
-                               P, O, box);                                                       \
+            hipLaunchKernelGGL((k_solo<WM, 0>), dim3(1), dim3(kSoloBlock), 0, ctx->stream, P,    \
+                               O, box);                                                          \
     } while (0)
     if (A->wmax <= 8) NN_SOLO_LAUNCH(8);
     else if (A->wmax <= 16) NN_SOLO_LAUNCH(16);

@@ -106,6 +106,7 @@ def test_matvec_matches_oracle(ctx):
 # ---------------------------------------------------------------- QP solves
 SOLVE_CASES = {
     "square2d_64": lambda: W.config_small(),
+    "square2d_65": lambda: W.square2d(65),     # 4,096 rows
     "square2d_45_theta1": lambda: W.square2d(45, theta=1.0, ratio=1e-3),
     "cube3d_16": lambda: W.cube3d(16),
     "cube3d_21_ragged": lambda: W.cube3d(21),
@@ -1371,8 +1372,11 @@ def test_subspace_option_validated(ctx):
 
 
 # ---------------------------------------------------------------- one-workgroup engine
-ENGINE_CASES = ["square2d_64", "cube3d_21_ragged", "transient_field_20x18x9", "batch_member_0",
-                "batch_member_5"]
+# square2d_64 (3,969 rows), square2d_65 (4,096) and cube3d_21 (8,000) take the
+# one-workgroup engine's three ways of holding its vectors (five in LDS, four
+# in LDS, none)
+ENGINE_CASES = ["square2d_64", "square2d_65", "cube3d_21_ragged", "transient_field_20x18x9",
+                "batch_member_0", "batch_member_5"]
 
 
 @pytest.mark.parametrize("engine", [1, 2])
